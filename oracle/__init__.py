@@ -1,0 +1,204 @@
+"""FP64 CPU oracle for "Total variation on a tree" (arXiv 1502.07770).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  It shares no code
+with the GPU library (``paper_1502_07770_amd``) and never imports it; the GPU
+library never imports this package.
+
+The arithmetic lives in ``tv_oracle.c`` (plain C, FP64, optional OpenMP over
+independent chains); this module is a ctypes wrapper that converts numpy
+arrays.  Functions and the passages they follow:
+
+* ``chain_prox``      -- eq. (1D-ROF) solved by the Sec. 4.1 O(n) algorithm
+                         (Algorithm 2 specialised to quadratic unaries).
+* ``chain_dp``        -- the same algorithm for general a_i > 0, b_i and
+                         asymmetric slopes w^-_i <= w^+_i (Sec. 4 / 4.1), with
+                         lambda^+- and breakpoint counters exposed.
+* ``chain_brute``     -- brute force over all edge sign patterns (tiny n).
+* ``chain_adjoint``   -- gradient of <g, x(y, w)> from the run structure of x.
+* ``tv2d``            -- Sec. 5.1 ROF via Lagrangian decomposition and the
+                         accelerated primal-dual iteration eq. (pd), with an
+                         FP64 duality gap.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tv_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class _Counts(ctypes.Structure):
+    _fields_ = [("pushes", ctypes.c_int64), ("pops", ctypes.c_int64),
+                ("max_breakpoints", ctypes.c_int64)]
+
+
+def build(force: bool = True) -> str:
+    """Compile tv_oracle.c into liboracle.so (gcc, -O2, OpenMP, IEEE FP64)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    D = ctypes.c_double
+    lib.orc_chain_dp.argtypes = [I64, P, P, P, P, P, P, P, P, P]
+    lib.orc_chain_dp.restype = ctypes.c_int
+    lib.orc_chain_prox_tv.argtypes = [I64, I64, I64, I64, P, P, D, P, P, ctypes.c_int]
+    lib.orc_chain_prox_tv.restype = ctypes.c_int
+    lib.orc_chain_brute.argtypes = [I64, P, P, P, P, P]
+    lib.orc_chain_brute.restype = ctypes.c_int
+    lib.orc_rof1d_objective.argtypes = [I64, P, P, D, P]
+    lib.orc_rof1d_objective.restype = D
+    lib.orc_chain_adjoint.argtypes = [I64, I64, I64, I64, P, P, P, P, P, ctypes.c_int]
+    lib.orc_chain_adjoint.restype = ctypes.c_int
+    lib.orc_tv2d.argtypes = [I64, I64, P, D, D, I64, D, P, P, P, ctypes.c_int]
+    lib.orc_tv2d.restype = I64
+    lib.orc_rof2d_objective.argtypes = [I64, I64, P, D, P]
+    lib.orc_rof2d_objective.restype = D
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses when ``threads <= 0``."""
+    return int(_load().orc_num_threads())
+
+
+def chain_dp(a, b, wm, wp):
+    """Sec. 4.1 DP on one chain with f_i = a_i x^2/2 - b_i x and pairwise slopes
+    (wm[e], wp[e]) on edge (e, e+1).  Returns (x, lam_lo, lam_hi, counts) with
+    counts = dict(pushes, pops, max_breakpoints)."""
+    a, b = _f64(a), _f64(b)
+    n = a.shape[0]
+    wm = _f64(np.zeros(0) if n == 1 else wm)
+    wp = _f64(np.zeros(0) if n == 1 else wp)
+    assert b.shape == (n,) and wm.shape == (n - 1,) and wp.shape == (n - 1,)
+    x = np.empty(n)
+    llo = np.empty(max(n, 1))
+    lhi = np.empty(max(n, 1))
+    seq = np.empty(4 * n + 9)
+    cnt = _Counts()
+    # pad the edge arrays so the C side may read index n-1 safely
+    wm_p = np.concatenate([wm, [0.0]])
+    wp_p = np.concatenate([wp, [0.0]])
+    rc = _load().orc_chain_dp(n, _ptr(a), _ptr(b), _ptr(wm_p), _ptr(wp_p), _ptr(x),
+                              _ptr(llo), _ptr(lhi), _ptr(seq), ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError("orc_chain_dp failed")
+    return x, llo[: n - 1].copy(), lhi[: n - 1].copy(), dict(
+        pushes=cnt.pushes, pops=cnt.pops, max_breakpoints=cnt.max_breakpoints)
+
+
+def chain_prox(y, w=None, w_scalar: float = 0.0, threads: int = 0, counts: bool = False):
+    """eq. (1D-ROF) for a batch of chains.  ``y`` is (n,) or (C, n); ``w`` is
+    None (use ``w_scalar``) or an array of the same shape as y whose slot i is
+    the weight of edge (i, i+1) (the last slot is ignored).  Returns x (and the
+    per-chain counters when ``counts``)."""
+    y = _f64(y)
+    squeeze = y.ndim == 1
+    y2 = y.reshape(1, -1) if squeeze else y
+    C, n = y2.shape
+    w2 = None
+    if w is not None:
+        w2 = _f64(w).reshape(C, n)
+    x = np.empty_like(y2)
+    cnt = (_Counts * max(C, 1))() if counts else None
+    rc = _load().orc_chain_prox_tv(C, n, 1, n, _ptr(y2), _ptr(w2), float(w_scalar), _ptr(x),
+                                   cnt, int(threads))
+    if rc != 0:
+        raise ValueError("orc_chain_prox_tv: invalid argument (negative or NaN weight?)")
+    out = x.reshape(-1) if squeeze else x
+    if counts:
+        stats = np.array([[c.pushes, c.pops, c.max_breakpoints] for c in cnt[:C]], dtype=np.int64)
+        return out, stats
+    return out
+
+
+def chain_brute(a, b, wm, wp):
+    """Brute-force minimiser of the Sec. 4.1 objective for n <= 12."""
+    a, b = _f64(a), _f64(b)
+    n = a.shape[0]
+    wm_p = np.concatenate([_f64(wm).reshape(-1), [0.0]])
+    wp_p = np.concatenate([_f64(wp).reshape(-1), [0.0]])
+    x = np.empty(n)
+    rc = _load().orc_chain_brute(n, _ptr(a), _ptr(b), _ptr(wm_p), _ptr(wp_p), _ptr(x))
+    if rc != 0:
+        raise ValueError("orc_chain_brute: n must be in [1, 12]")
+    return x
+
+
+def rof1d_objective(y, w, x, w_scalar: float = 0.0) -> float:
+    """Objective of eq. (1D-ROF) for one chain."""
+    y, x = _f64(y), _f64(x)
+    wa = None if w is None else _f64(w)
+    return float(_load().orc_rof1d_objective(y.shape[0], _ptr(y), _ptr(wa), float(w_scalar), _ptr(x)))
+
+
+def chain_adjoint(x, g, scalar_w: bool = False, threads: int = 0):
+    """Gradient of <g, x(y, w)>: returns (dy, dw) where dw has the shape of x
+    (slot i = edge (i, i+1), last slot 0), or a per-chain sum when
+    ``scalar_w``."""
+    x, g = _f64(x), _f64(g)
+    squeeze = x.ndim == 1
+    x2 = x.reshape(1, -1) if squeeze else x
+    g2 = g.reshape(x2.shape)
+    C, n = x2.shape
+    dy = np.empty_like(x2)
+    dw = None if scalar_w else np.empty_like(x2)
+    dws = np.empty(C) if scalar_w else None
+    _load().orc_chain_adjoint(C, n, 1, n, _ptr(x2), _ptr(g2), _ptr(dy), _ptr(dw), _ptr(dws),
+                              int(threads))
+    if squeeze:
+        return dy.reshape(-1), (dws[0] if scalar_w else dw.reshape(-1))
+    return dy, (dws if scalar_w else dw)
+
+
+def tv2d(f, lam: float, tau0: float = 1.0, max_iter: int = 200, gap_tol: float = 0.0,
+         threads: int = 0):
+    """Sec. 5.1 ROF solve.  Returns (x, gap_hist, (P, D, gap_norm), iters)."""
+    f = _f64(f)
+    H, W = f.shape
+    x = np.empty_like(f)
+    hist = np.zeros(max(int(max_iter), 1))
+    out3 = np.zeros(3)
+    k = _load().orc_tv2d(H, W, _ptr(f), float(lam), float(tau0), int(max_iter), float(gap_tol),
+                         _ptr(x), _ptr(hist), _ptr(out3), int(threads))
+    if k < 0:
+        raise ValueError("orc_tv2d: invalid argument")
+    return x, hist[:k].copy(), (float(out3[0]), float(out3[1]), float(out3[2])), int(k)
+
+
+def rof2d_objective(f, lam: float, x) -> float:
+    """Primal ROF objective lam (TV_h + TV_v)(x) + |x - f|^2 / 2."""
+    f, x = _f64(f), _f64(x)
+    H, W = f.shape
+    return float(_load().orc_rof2d_objective(H, W, _ptr(f), float(lam), _ptr(x)))

@@ -1,0 +1,519 @@
+/*
+ * tv_oracle.c -- plain FP64 CPU oracle for "Total variation on a tree"
+ * (Kolmogorov, Pock, Rolinek, arXiv 1502.07770).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or helper
+ * with the GPU library.
+ *
+ * Contents (each function cites the passage it follows):
+ *   orc_chain_dp        -- Sec. 4.1 O(n) chain algorithm (Algorithm 2 specialised
+ *                          to strictly convex quadratic unaries), general a_i > 0
+ *                          and asymmetric pairwise slopes w^-_i <= w^+_i.
+ *   orc_chain_prox_tv   -- the TV-l2 chain prox, eq. (1D-ROF): a_i = 1, b_i = y_i,
+ *                          w^-_i = -w_i, w^+_i = +w_i; batched over strided chains.
+ *   orc_chain_brute     -- brute force over all 3^(n-1) edge sign patterns for
+ *                          tiny chains (n <= 12); independent of the DP.
+ *   orc_tv2d            -- Sec. 5.1 ROF by Lagrangian decomposition, the
+ *                          accelerated primal-dual iteration eq. (pd) with the
+ *                          primal prox on rows and the dual prox (Moreau identity,
+ *                          eq. (prox-tv-conj)) on columns, plus an FP64 duality gap.
+ *   orc_chain_adjoint   -- gradient of <g, x(y,w)> for the chain prox, from the
+ *                          optimality conditions of eq. (1D-ROF) and the clip
+ *                          structure of the backward pass of Algorithm 2.
+ *
+ * Conventions: node indices are 0-based here (the paper's node i is index i-1);
+ * edge e joins nodes e and e+1, so a chain of n nodes has n-1 edge weights.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int64_t pushes;          /* breakpoints added (2 per non-root node)          */
+    int64_t pops;            /* breakpoints removed at either end                */
+    int64_t max_breakpoints; /* largest number t of breakpoints held at once     */
+} orc_counts;
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 4.1: O(n) DP for f_i(x) = a_i x^2 / 2 - b_i x on a chain, pairwise    */
+/* f_e(z) = w^-_e z (z < 0), w^+_e z (z >= 0) on edge (e, e+1).               */
+/* ------------------------------------------------------------------------ */
+/*
+ * The current message (either \hat m_i or m_ij) is the sequence
+ * (s_0, lam_1, s_1, ..., lam_t, s_t) held contiguously in seq[h..e]
+ * (s_p at h + 2p, lam_p at h + 2p - 1).  The true slope of segment p is
+ * s_p + Abar_i with Abar_i = a_1 + ... + a_i (implicit-slope representation),
+ * so adding g_i(z) = a_i z - b_i only advances Abar.  The array has 4n + O(1)
+ * entries and the sequence starts in its middle, growing both ways.
+ *
+ * lam_lo[i], lam_hi[i] receive lambda^-_{i,i+1}, lambda^+_{i,i+1}; x receives
+ * the minimiser.  seq must hold 4n + 9 doubles.  Returns 0, or -1 on n < 1.
+ */
+int orc_chain_dp(int64_t n, const double *a, const double *b,
+                 const double *wm, const double *wp,
+                 double *x, double *lam_lo, double *lam_hi,
+                 double *seq, orc_counts *cnt)
+{
+    if (n < 1) return -1;
+    int64_t h = 2 * n + 4, e = h;  /* sequence = (s_0) only               */
+    double Abar = 0.0;
+    seq[h] = 0.0;                  /* s_0 = -Abar_0 = 0                  */
+    double wm_prev = 0.0, wp_prev = 0.0;
+    if (cnt) { cnt->pushes = 0; cnt->pops = 0; cnt->max_breakpoints = 0; }
+
+    for (int64_t i = 0; i < n; ++i) {
+        const int root = (i == n - 1);
+        /* Algorithm 2, line 0: the root gets a virtual parent edge with
+           w^- = w^+ = 0, so its interval collapses to the zero of \hat m. */
+        const double lo = root ? 0.0 : wm[i];
+        const double hi = root ? 0.0 : wp[i];
+        const double ai = a[i], bi = b[i];
+        Abar += ai;                 /* transformation (a): \hat m_i = m_ki + g_i */
+        const int64_t t = (e - h) / 2;
+        double lm, lp;
+        int64_t ell = 0, r = 1;
+
+        if (t == 0) {
+            /* First node: no incoming message, \hat m_1(z) = a_1 z - b_1. */
+            lm = (lo + bi) / ai;
+            lp = (hi + bi) / ai;
+            ell = 0;
+            r = 1;
+        } else {
+#define LAM(p) seq[h + 2 * (p) - 1]
+#define SLP(p) seq[h + 2 * (p)]
+            /* Left end: largest ell with \hat m_i(lam_ell) < w^-, values by the
+               recursion \hat m(lam_1) = w^-_ki + a_i lam_1 - b_i,
+               \hat m(lam_{p+1}) = \hat m(lam_p) + (s_p + Abar)(lam_{p+1} - lam_p). */
+            double v = wm_prev + ai * LAM(1) - bi;
+            double v_ell = v;
+            if (!(v < lo)) {
+                ell = 0;
+                /* zero on the left end segment (true slope s_0 + Abar = a_i) */
+                lm = LAM(1) - (v - lo) / (SLP(0) + Abar);
+            } else {
+                ell = 1;
+                while (ell < t) {
+                    double vn = v_ell + (SLP(ell) + Abar) * (LAM(ell + 1) - LAM(ell));
+                    if (!(vn < lo)) break;
+                    ++ell;
+                    v_ell = vn;
+                }
+                /* zero on segment ell, which starts at lam_ell */
+                lm = LAM(ell) + (lo - v_ell) / (SLP(ell) + Abar);
+                /* rounding guard: stay inside the bracketing segment */
+                if (lm < LAM(ell)) lm = LAM(ell);
+                if (ell < t && lm > LAM(ell + 1)) lm = LAM(ell + 1);
+            }
+
+            if (root) {
+                x[i] = lm;
+                if (cnt) cnt->pops += ell;
+                break;
+            }
+
+            /* Right end: smallest r >= ell + 1 with \hat m_i(lam_r) > w^+
+               (r = t + 1 if none), values by the recursion from
+               \hat m(lam_t) = w^+_ki + a_i lam_t - b_i downward. */
+            if (ell == t) {
+                /* every old breakpoint left of the zero of w^-: the segment
+                   right of lam^- is the old right end, true slope a_i */
+                r = t + 1;
+                lp = lm + (hi - lo) / (SLP(t) + Abar);
+            } else {
+                double vr = wp_prev + ai * LAM(t) - bi;
+                if (!(vr > hi)) {
+                    r = t + 1;
+                    lp = LAM(t) + (hi - vr) / (SLP(t) + Abar);
+                } else {
+                    r = t;
+                    double v_r = vr;
+                    while (r - 1 >= ell + 1) {
+                        double vp = v_r - (SLP(r - 1) + Abar) * (LAM(r) - LAM(r - 1));
+                        if (!(vp > hi)) break;
+                        --r;
+                        v_r = vp;
+                    }
+                    /* zero on the segment ending at lam_r; its slope is
+                       s_{r-1}, which is s_ell when that segment starts at lam^- */
+                    lp = LAM(r) - (v_r - hi) / (SLP(r - 1) + Abar);
+                    if (lp > LAM(r)) lp = LAM(r);
+                    if (r - 1 >= ell + 1 && lp < LAM(r - 1)) lp = LAM(r - 1);
+                }
+            }
+            if (lp < lm) lp = lm;   /* rounding guard: lam^- <= lam^+ */
+#undef LAM
+#undef SLP
+        }
+
+        if (root) {             /* only reached for n == 1 */
+            x[i] = lm;
+            break;
+        }
+        lam_lo[i] = lm;
+        lam_hi[i] = lp;
+        if (cnt) {
+            cnt->pushes += 2;
+            cnt->pops += ell + (t - r + 1);
+        }
+        /* New sequence (-Abar, lam^-, s_ell, lam_{ell+1}, ..., s_{r-1}, lam^+, -Abar):
+           keep s_ell at h + 2 ell and s_{r-1} at h + 2(r-1); write around them. */
+        {
+            const int64_t h_old = h;
+            seq[h_old + 2 * ell - 1] = lm;
+            seq[h_old + 2 * ell - 2] = -Abar;
+            seq[h_old + 2 * r - 1] = lp;
+            seq[h_old + 2 * r] = -Abar;
+            h = h_old + 2 * ell - 2;
+            e = h_old + 2 * r;
+        }
+        if (cnt) {
+            int64_t tn = (e - h) / 2;
+            if (tn > cnt->max_breakpoints) cnt->max_breakpoints = tn;
+        }
+        wm_prev = lo;
+        wp_prev = hi;
+    }
+
+    /* Backward pass (Algorithm 2, lines 7-9): x_i = clip(x_{i+1}, lam^-_i, lam^+_i). */
+    for (int64_t i = n - 2; i >= 0; --i) {
+        double v = x[i + 1];
+        if (v < lam_lo[i]) v = lam_lo[i];
+        if (v > lam_hi[i]) v = lam_hi[i];
+        x[i] = v;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* eq. (1D-ROF): min_x sum_e w_e |x_{e+1} - x_e| + 1/2 sum_i (x_i - y_i)^2,   */
+/* batched over chains read with arbitrary strides.                          */
+/* ------------------------------------------------------------------------ */
+/*
+ * Chain c, node i lives at y[c * chain_stride + i * elem_stride].  The edge
+ * weight of edge (i, i+1) is w[c * chain_stride + i * elem_stride] when w is
+ * non-NULL (the slot of the last node is ignored), else w_scalar.
+ * counts (optional) receives per-chain counters.  threads <= 0 means all.
+ * Returns 0, or -1 on invalid arguments.
+ */
+int orc_chain_prox_tv(int64_t num_chains, int64_t n, int64_t elem_stride, int64_t chain_stride,
+                      const double *y, const double *w, double w_scalar, double *x,
+                      orc_counts *counts, int threads)
+{
+    if (num_chains < 0 || n < 1) return -1;
+    if (!w && !(w_scalar >= 0.0)) return -1;
+    int bad = 0;
+#ifdef _OPENMP
+    if (threads <= 0) threads = omp_get_max_threads();
+#pragma omp parallel num_threads(threads) reduction(|:bad)
+#endif
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)(4 * n + 9 + 8 * n));
+        double *seq = buf;
+        double *a = buf + 4 * n + 9;
+        double *b = a + n;
+        double *wm = b + n;
+        double *wp = wm + n;
+        double *xc = wp + n;
+        double *llo = xc + n;
+        double *lhi = llo + n;
+        for (int64_t i = 0; i < n; ++i) a[i] = 1.0;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 8)
+#endif
+        for (int64_t c = 0; c < num_chains; ++c) {
+            const double *yc = y + c * chain_stride;
+            for (int64_t i = 0; i < n; ++i) b[i] = yc[i * elem_stride];
+            for (int64_t i = 0; i + 1 < n; ++i) {
+                double we = w ? w[c * chain_stride + i * elem_stride] : w_scalar;
+                if (!(we >= 0.0)) bad = 1;
+                wm[i] = -we;
+                wp[i] = we;
+            }
+            orc_chain_dp(n, a, b, wm, wp, xc, llo, lhi, seq, counts ? counts + c : NULL);
+            double *xo = x + c * chain_stride;
+            for (int64_t i = 0; i < n; ++i) xo[i * elem_stride] = xc[i];
+        }
+        free(buf);
+    }
+    return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Brute force for tiny chains: enumerate every sign pattern of the n-1      */
+/* edges (fused, up, down).  For each, solve the equality-constrained        */
+/* stationarity system (runs of fused nodes share one value), evaluate the  */
+/* TRUE objective at that point, and keep the best.  The optimum's own sign */
+/* pattern reproduces it, and every candidate is a feasible point, so the   */
+/* minimum over candidates is the global minimum of the strictly convex     */
+/* objective of Sec. 4.1 (quadratic unaries, slopes w^- <= w^+).            */
+/* ------------------------------------------------------------------------ */
+static double objective_general(int64_t n, const double *a, const double *b,
+                                const double *wm, const double *wp, const double *x)
+{
+    double f = 0.0;
+    for (int64_t i = 0; i < n; ++i) f += 0.5 * a[i] * x[i] * x[i] - b[i] * x[i];
+    for (int64_t e = 0; e + 1 < n; ++e) {
+        double z = x[e + 1] - x[e];
+        f += (z < 0.0) ? wm[e] * z : wp[e] * z;
+    }
+    return f;
+}
+
+int orc_chain_brute(int64_t n, const double *a, const double *b,
+                    const double *wm, const double *wp, double *x_best)
+{
+    if (n < 1 || n > 12) return -1;
+    int64_t m = n - 1, total = 1;
+    for (int64_t e = 0; e < m; ++e) total *= 3;
+    double best = INFINITY;
+    double x[12];
+    int state[12];
+    for (int64_t code = 0; code < total; ++code) {
+        int64_t c = code;
+        for (int64_t e = 0; e < m; ++e) { state[e] = (int)(c % 3); c /= 3; }
+        /* q_e: the pairwise subgradient used on a non-fused edge
+           (state 1: x_{e+1} > x_e -> w^+_e; state 2: x_{e+1} < x_e -> w^-_e). */
+        int64_t start = 0;
+        while (start < n) {
+            int64_t end = start;
+            while (end < m && state[end] == 0) ++end;   /* run [start..end] */
+            double qin = 0.0, qout = 0.0, sa = 0.0, sb = 0.0;
+            if (start > 0) qin = (state[start - 1] == 1) ? wp[start - 1] : wm[start - 1];
+            if (end < m) qout = (state[end] == 1) ? wp[end] : wm[end];
+            for (int64_t k = start; k <= end; ++k) { sa += a[k]; sb += b[k]; }
+            /* stationarity of the run: sum_k (a_k c - b_k) = qout - qin */
+            double cval = (sb + qout - qin) / sa;
+            for (int64_t k = start; k <= end; ++k) x[k] = cval;
+            start = end + 1;
+        }
+        double f = objective_general(n, a, b, wm, wp, x);
+        if (f < best) {
+            best = f;
+            for (int64_t k = 0; k < n; ++k) x_best[k] = x[k];
+        }
+    }
+    return 0;
+}
+
+/* Objective of eq. (1D-ROF) for one chain (unit stride). */
+double orc_rof1d_objective(int64_t n, const double *y, const double *w, double w_scalar,
+                           const double *x)
+{
+    double f = 0.0;
+    for (int64_t i = 0; i < n; ++i) f += 0.5 * (x[i] - y[i]) * (x[i] - y[i]);
+    for (int64_t e = 0; e + 1 < n; ++e) f += (w ? w[e] : w_scalar) * fabs(x[e + 1] - x[e]);
+    return f;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the chain prox.                                               */
+/* ------------------------------------------------------------------------ */
+/*
+ * On a run R = [s..t] of equal x (maximal, by exact equality of consecutive
+ * values) the optimality conditions of eq. (1D-ROF) give
+ *   x_R = (sum_R y + w_t s_t - w_{s-1} s_{s-1}) / |R|,
+ * where s_e = sign(x_{e+1} - x_e) on the boundary edges (and no term at the
+ * chain ends).  Hence for L = <g, x>:
+ *   dL/dy_i = mean of g over the run containing i,
+ *   dL/dw_e = s_e (mean_g(left run) - mean_g(right run)) on a run boundary e,
+ *   dL/dw_e = 0 inside a run.
+ * dw (length n, slot n-1 unused and set to 0) may be NULL.  With
+ * dw_scalar non-NULL the sum over all edges is written there (scalar w).
+ */
+int orc_chain_adjoint(int64_t num_chains, int64_t n, int64_t elem_stride, int64_t chain_stride,
+                      const double *x, const double *g, double *dy, double *dw,
+                      double *dw_scalar, int threads)
+{
+    if (num_chains < 0 || n < 1) return -1;
+#ifdef _OPENMP
+    if (threads <= 0) threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 8) num_threads(threads)
+#endif
+    for (int64_t c = 0; c < num_chains; ++c) {
+        const double *xc = x + c * chain_stride;
+        const double *gc = g + c * chain_stride;
+        double *dyc = dy + c * chain_stride;
+        double *dwc = dw ? dw + c * chain_stride : NULL;
+        double prev_mean = 0.0, wsum = 0.0;
+        int64_t s = 0;
+        while (s < n) {
+            int64_t t = s;
+            while (t + 1 < n && xc[(t + 1) * elem_stride] == xc[t * elem_stride]) ++t;
+            double sg = 0.0;
+            for (int64_t k = s; k <= t; ++k) sg += gc[k * elem_stride];
+            double mean = sg / (double)(t - s + 1);
+            for (int64_t k = s; k <= t; ++k) {
+                dyc[k * elem_stride] = mean;
+                if (dwc) dwc[k * elem_stride] = 0.0;
+            }
+            if (s > 0) {
+                int64_t eb = s - 1;   /* boundary edge between the runs */
+                double sign = (xc[s * elem_stride] > xc[eb * elem_stride]) ? 1.0 : -1.0;
+                double d = sign * (prev_mean - mean);
+                if (dwc) dwc[eb * elem_stride] = d;
+                wsum += d;
+            }
+            prev_mean = mean;
+            s = t + 1;
+        }
+        if (dw_scalar) dw_scalar[c] = wsum;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 5.1: ROF by Lagrangian decomposition and accelerated primal-dual.   */
+/* ------------------------------------------------------------------------ */
+/*
+ * Image f is H x W, row-major (pixel (r, c) at r * W + c).  Horizontal edges
+ * join (r, c)-(r, c+1) and form the H row chains; vertical edges join
+ * (r, c)-(r+1, c) and form the W column chains; every edge has weight lambda.
+ *
+ * Iteration (eq. (pd), K = identity, G = lambda TV_h + |.-f|^2/2 which is
+ * 1-strongly convex, F = lambda TV_v):
+ *   eta    = y + sigma_k xbar
+ *   y      = eta - prox_{lambda TV_v}(eta)            (column chains; Moreau
+ *            identity, eq. (prox-tv-conj), with TV 1-homogeneous)
+ *   b      = (tau_k f + x - tau_k y) / (1 + tau_k)
+ *   x_new  = prox_{(lambda tau_k/(1+tau_k)) TV_h}(b) (row chains; the primal prox
+ *            rescaled to unit quadratic weight)
+ *   theta  = 1/sqrt(1 + 2 tau_k); tau_{k+1} = theta tau_k; sigma_{k+1} = sigma_k/theta
+ *   xbar   = x_new + theta (x_new - x)
+ * with x^0 = xbar^0 = f, y^0 = 0, sigma_0 = 1/tau_0.
+ *
+ * Duality gap (FP64) after each iteration, at x_new and the dual edge
+ * variables recovered from the two chain solves:
+ *   p_v,e = clip(-sum_{k<=e} y_k, +-lambda) down each column,
+ *   p_h,e = clip(((1+tau)/tau) sum_{k<=e} (x_new_k - b_k), +-lambda) along each row,
+ *   P = lambda TV_h(x) + lambda TV_v(x) + |x - f|^2/2,
+ *   D = |f|^2/2 - |f - D_h^T p_h - D_v^T p_v|^2/2,
+ * (D^T p)_0 = -p_0, (D^T p)_i = p_{i-1} - p_i, (D^T p)_{n-1} = p_{n-2}.
+ * Any |p| <= lambda gives D <= min P (weak duality), so P - D >= 0 bounds the
+ * suboptimality of x.  gap_hist[k] = (P - D) / (H W) after iteration k+1.
+ *
+ * The iteration stops after max_iter iterations, or after the first one whose
+ * normalised gap is <= gap_tol (gap_tol <= 0 disables).  Returns the number
+ * of iterations run, or -1 on bad arguments.  x (H*W) receives the iterate;
+ * out3 (optional) receives {P, D, gap_norm} of the last iteration.
+ */
+static void tv2d_gap(int64_t H, int64_t W, double lambda, double tau, const double *f,
+                     const double *x, const double *bb, const double *y,
+                     double *ph, double *pv, double *out3)
+{
+    /* p_v down each column, p_h along each row */
+    for (int64_t c = 0; c < W; ++c) {
+        double cs = 0.0;
+        for (int64_t r = 0; r + 1 < H; ++r) {
+            cs += y[r * W + c];
+            double p = -cs;
+            if (p > lambda) p = lambda;
+            if (p < -lambda) p = -lambda;
+            pv[r * W + c] = p;
+        }
+    }
+    const double scale = (1.0 + tau) / tau;
+    for (int64_t r = 0; r < H; ++r) {
+        double cs = 0.0;
+        for (int64_t c = 0; c + 1 < W; ++c) {
+            cs += x[r * W + c] - bb[r * W + c];
+            double p = scale * cs;
+            if (p > lambda) p = lambda;
+            if (p < -lambda) p = -lambda;
+            ph[r * W + c] = p;
+        }
+    }
+    double P = 0.0, D = 0.0;
+    for (int64_t r = 0; r < H; ++r) {
+        for (int64_t c = 0; c < W; ++c) {
+            const int64_t k = r * W + c;
+            double xv = x[k], fv = f[k];
+            P += 0.5 * (xv - fv) * (xv - fv);
+            if (c + 1 < W) P += lambda * fabs(x[k + 1] - xv);
+            if (r + 1 < H) P += lambda * fabs(x[k + W] - xv);
+            double z = 0.0;
+            if (c > 0) z += ph[k - 1];
+            if (c + 1 < W) z -= ph[k];
+            if (r > 0) z += pv[k - W];
+            if (r + 1 < H) z -= pv[k];
+            D += 0.5 * fv * fv - 0.5 * (fv - z) * (fv - z);
+        }
+    }
+    out3[0] = P;
+    out3[1] = D;
+    out3[2] = (P - D) / (double)(H * W);
+}
+
+int64_t orc_tv2d(int64_t H, int64_t W, const double *f, double lambda, double tau0,
+                 int64_t max_iter, double gap_tol, double *x, double *gap_hist,
+                 double *out3, int threads)
+{
+    if (H < 1 || W < 1 || !(lambda >= 0.0) || !(tau0 > 0.0) || max_iter < 0) return -1;
+    const int64_t N = H * W;
+    double *y = (double *)calloc((size_t)N, sizeof(double));
+    double *xbar = (double *)malloc(sizeof(double) * (size_t)N);
+    double *eta = (double *)malloc(sizeof(double) * (size_t)N);
+    double *u = (double *)malloc(sizeof(double) * (size_t)N);
+    double *bb = (double *)malloc(sizeof(double) * (size_t)N);
+    double *xn = (double *)malloc(sizeof(double) * (size_t)N);
+    double *ph = (double *)malloc(sizeof(double) * (size_t)N);
+    double *pv = (double *)malloc(sizeof(double) * (size_t)N);
+    memcpy(x, f, sizeof(double) * (size_t)N);
+    memcpy(xbar, f, sizeof(double) * (size_t)N);
+    double tau = tau0, sigma = 1.0 / tau0;
+    double last[3] = {0.0, 0.0, 0.0};
+    int64_t k = 0;
+    for (k = 0; k < max_iter; ++k) {
+        /* dual step on the column chains */
+        for (int64_t i = 0; i < N; ++i) eta[i] = y[i] + sigma * xbar[i];
+        orc_chain_prox_tv(W, H, W, 1, eta, NULL, lambda, u, NULL, threads);
+        for (int64_t i = 0; i < N; ++i) y[i] = eta[i] - u[i];
+        /* primal step on the row chains */
+        for (int64_t i = 0; i < N; ++i) bb[i] = (tau * f[i] + x[i] - tau * y[i]) / (1.0 + tau);
+        orc_chain_prox_tv(H, W, 1, W, bb, NULL, lambda * tau / (1.0 + tau), xn, NULL, threads);
+        /* gap at (x_new, p) */
+        tv2d_gap(H, W, lambda, tau, f, xn, bb, y, ph, pv, last);
+        if (gap_hist) gap_hist[k] = last[2];
+        /* acceleration */
+        const double theta = 1.0 / sqrt(1.0 + 2.0 * tau);
+        for (int64_t i = 0; i < N; ++i) {
+            xbar[i] = xn[i] + theta * (xn[i] - x[i]);
+            x[i] = xn[i];
+        }
+        tau *= theta;
+        sigma /= theta;
+        if (gap_tol > 0.0 && last[2] <= gap_tol) { ++k; break; }
+    }
+    if (out3) { out3[0] = last[0]; out3[1] = last[1]; out3[2] = last[2]; }
+    free(y); free(xbar); free(eta); free(u); free(bb); free(xn); free(ph); free(pv);
+    return k;
+}
+
+/* Primal ROF objective lambda (TV_h + TV_v)(x) + |x - f|^2 / 2. */
+double orc_rof2d_objective(int64_t H, int64_t W, const double *f, double lambda, const double *x)
+{
+    double P = 0.0;
+    for (int64_t r = 0; r < H; ++r)
+        for (int64_t c = 0; c < W; ++c) {
+            const int64_t k = r * W + c;
+            P += 0.5 * (x[k] - f[k]) * (x[k] - f[k]);
+            if (c + 1 < W) P += lambda * fabs(x[k + 1] - x[k]);
+            if (r + 1 < H) P += lambda * fabs(x[k + W] - x[k]);
+        }
+    return P;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,111 @@
+"""Seeded synthetic inputs shared by the GPU path's tests/benchmark and the oracle.
+
+This module holds no arithmetic of the method: it only draws inputs.  All
+randomness comes from ``numpy.random.Generator(PCG64(seed))`` and is returned
+as FP64 arrays; callers cast to the precision they run in.
+
+Workloads (stand-ins for the paper's signals and images, which are not
+available; the noise level sigma = 0.1 and weight 0.1 mirror Sec. 5.1's
+experiments, Figs. 5 and 6):
+
+* ``piecewise_constant``: chains whose clean signal is piecewise constant with
+  segment lengths Geometric(p = 1/seg_mean) on {1, 2, ...} (the last segment
+  truncated), levels U[0, 1], plus N(0, sigma^2) noise.
+* ``shapes_image``: an H x W image of ``n_shapes`` axis-aligned rectangles or
+  disks (probability 1/2 each) painted in order over a zero background, with
+  intensities U[0, 1], plus N(0, sigma^2) noise (no clipping).  Rectangle sides
+  are U[W/20, W/3] x U[H/20, H/3], disk radii U[min(H,W)/40, min(H,W)/6], and
+  centres uniform over the image.
+* ``uneven_batch_specs``: per-image (H, W, lambda, sigma, seed) for a batch of
+  images with H, W uniform on {64, ..., 2048}, lambda U[0.02, 0.3], sigma
+  U[0.05, 0.2].
+* ``edge_weights`` (U[lo, hi]) and ``normal`` (N(0, 1)) helpers.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def generator(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def piecewise_constant(num_chains: int, n: int, seg_mean: float = 20.0, sigma: float = 0.1,
+                       seed: int = 0) -> np.ndarray:
+    """(num_chains, n) FP64 piecewise-constant-plus-noise chains."""
+    g = generator(seed)
+    p = 1.0 / float(seg_mean)
+    k = int(2 * n / seg_mean) + 64
+    lengths = g.geometric(p, size=(num_chains, k))
+    levels = g.uniform(0.0, 1.0, size=(num_chains, k))
+    ends = np.cumsum(lengths, axis=1)
+    short = np.nonzero(ends[:, -1] < n)[0]
+    for c in short:  # essentially never: extend the rare row that falls short
+        while ends[c, -1] < n:
+            extra = g.geometric(p, size=k)
+            lengths[c] = np.concatenate([lengths[c], extra])[-k:]
+            ends[c] = np.cumsum(lengths[c])
+    marks = np.zeros((num_chains, n + 1), dtype=np.int32)
+    rows = np.repeat(np.arange(num_chains), k)
+    e = ends.reshape(-1)
+    keep = e < n
+    marks[rows[keep], e[keep]] = 1
+    seg = np.cumsum(marks[:, :n], axis=1)
+    y = np.take_along_axis(levels, seg, axis=1)
+    y += g.normal(0.0, sigma, size=(num_chains, n))
+    return y
+
+
+def shapes_image(H: int, W: int, n_shapes: int = 30, sigma: float = 0.1, seed: int = 0) -> np.ndarray:
+    """(H, W) FP64 image of random rectangles and disks plus Gaussian noise."""
+    g = generator(seed)
+    img = np.zeros((H, W))
+    m = min(H, W)
+    for _ in range(n_shapes):
+        is_rect = g.random() < 0.5
+        inten = g.uniform(0.0, 1.0)
+        cy = g.uniform(0.0, H)
+        cx = g.uniform(0.0, W)
+        if is_rect:
+            sw = g.uniform(W / 20.0, W / 3.0)
+            sh = g.uniform(H / 20.0, H / 3.0)
+            r0, r1 = int(np.ceil(cy - sh / 2)), int(np.floor(cy + sh / 2))
+            c0, c1 = int(np.ceil(cx - sw / 2)), int(np.floor(cx + sw / 2))
+            r0, c0 = max(r0, 0), max(c0, 0)
+            r1, c1 = min(r1, H - 1), min(c1, W - 1)
+            if r0 <= r1 and c0 <= c1:
+                img[r0:r1 + 1, c0:c1 + 1] = inten
+        else:
+            rad = g.uniform(m / 40.0, m / 6.0)
+            r0, r1 = max(int(np.floor(cy - rad)), 0), min(int(np.ceil(cy + rad)), H - 1)
+            c0, c1 = max(int(np.floor(cx - rad)), 0), min(int(np.ceil(cx + rad)), W - 1)
+            if r0 <= r1 and c0 <= c1:
+                rr = np.arange(r0, r1 + 1)[:, None]
+                cc = np.arange(c0, c1 + 1)[None, :]
+                mask = (rr - cy) ** 2 + (cc - cx) ** 2 <= rad * rad
+                sub = img[r0:r1 + 1, c0:c1 + 1]
+                sub[mask] = inten
+    img += g.normal(0.0, sigma, size=(H, W))
+    return img
+
+
+def uneven_batch_specs(num_images: int = 256, side_lo: int = 64, side_hi: int = 2048,
+                       lam_lo: float = 0.02, lam_hi: float = 0.3,
+                       sigma_lo: float = 0.05, sigma_hi: float = 0.2, seed: int = 0):
+    """List of dicts (H, W, lam, sigma, seed) for a batch of uneven images."""
+    g = generator(seed)
+    Hs = g.integers(side_lo, side_hi + 1, size=num_images)
+    Ws = g.integers(side_lo, side_hi + 1, size=num_images)
+    lams = g.uniform(lam_lo, lam_hi, size=num_images)
+    sigmas = g.uniform(sigma_lo, sigma_hi, size=num_images)
+    seeds = g.integers(0, 2 ** 31 - 1, size=num_images)
+    return [dict(H=int(Hs[i]), W=int(Ws[i]), lam=float(lams[i]), sigma=float(sigmas[i]),
+                 seed=int(seeds[i])) for i in range(num_images)]
+
+
+def edge_weights(shape, lo: float = 0.1, hi: float = 1.0, seed: int = 0) -> np.ndarray:
+    return generator(seed).uniform(lo, hi, size=shape)
+
+
+def normal(shape, seed: int = 0) -> np.ndarray:
+    return generator(seed).normal(0.0, 1.0, size=shape)

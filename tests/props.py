@@ -1,0 +1,92 @@
+"""Properties of the exact solutions that hold at any size (numpy, test-side).
+
+These checks are independent of both the oracle's algorithm and the GPU
+kernels: they restate what the problem statement fixes.
+
+* ``kkt_residual``: optimality conditions of eq. (1D-ROF).  With
+  q_e = sum_{k<=e} (x_k - y_k), x is the minimiser iff |q_e| <= w_e on every
+  edge, q_e = w_e sign(x_{e+1} - x_e) wherever x_{e+1} != x_e, and the total
+  sum q_{n-1} = 0.
+* ``run_structure``: the jump pattern (-1, 0, +1 per edge) of a solution.
+* ``dual_box_solution``: the chain (or 2D) prox via its dual, a box-constrained
+  least-squares problem min |D^T p - y|^2, |p_e| <= w_e, solved by scipy's
+  bounded least squares; x = y - D^T p.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def kkt_residual(y, x, w, jump_tol: float = 0.0):
+    """Return (box_violation, jump_violation, total_sum) for chains along the
+    last axis.  ``w`` is a scalar or has y's shape (last slot ignored)."""
+    y = np.asarray(y, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    n = y.shape[-1]
+    q = np.cumsum(x - y, axis=-1)
+    total = q[..., -1]
+    if n == 1:
+        return 0.0, 0.0, np.abs(total).max()
+    qe = q[..., :-1]
+    we = np.broadcast_to(np.asarray(w, dtype=np.float64), y.shape)[..., :-1]
+    box = np.maximum(np.abs(qe) - we, 0.0).max()
+    d = x[..., 1:] - x[..., :-1]
+    jumps = np.abs(d) > jump_tol
+    s = np.sign(d)
+    jv = np.where(jumps, np.abs(qe - we * s), 0.0).max()
+    return float(box), float(jv), float(np.abs(total).max())
+
+
+def run_structure(x):
+    """-1/0/+1 per edge by exact comparison of consecutive values."""
+    x = np.asarray(x)
+    return np.sign(x[..., 1:] - x[..., :-1]).astype(np.int8)
+
+
+def _diff_matrix(n):
+    D = np.zeros((n - 1, n))
+    D[np.arange(n - 1), np.arange(n - 1)] = -1.0
+    D[np.arange(n - 1), np.arange(1, n)] = 1.0
+    return D
+
+
+def dual_box_solution_1d(y, w):
+    """x = y - D^T p with p = argmin |D^T p - y|^2 s.t. |p_e| <= w_e (BVLS)."""
+    from scipy.optimize import lsq_linear
+    y = np.asarray(y, dtype=np.float64)
+    n = y.shape[0]
+    if n == 1:
+        return y.copy()
+    we = np.broadcast_to(np.asarray(w, dtype=np.float64), (n - 1,))
+    A = _diff_matrix(n).T
+    res = lsq_linear(A, y, bounds=(-we, we), method="bvls", tol=1e-15, max_iter=10000)
+    return y - A @ res.x
+
+
+def dual_box_solution_2d(f, lam):
+    """ROF x = f - D^T p with p = argmin |D^T p - f|^2 s.t. |p| <= lam, where D
+    stacks the horizontal and vertical forward differences (BVLS)."""
+    from scipy.optimize import lsq_linear
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    rows = []
+    for r in range(H):
+        for c in range(W - 1):
+            e = np.zeros(H * W)
+            e[r * W + c] = -1.0
+            e[r * W + c + 1] = 1.0
+            rows.append(e)
+    for r in range(H - 1):
+        for c in range(W):
+            e = np.zeros(H * W)
+            e[r * W + c] = -1.0
+            e[(r + 1) * W + c] = 1.0
+            rows.append(e)
+    if not rows:
+        return f.copy()
+    D = np.array(rows)
+    A = D.T
+    m = D.shape[0]
+    res = lsq_linear(A, f.reshape(-1), bounds=(-lam * np.ones(m), lam * np.ones(m)),
+                     method="bvls", tol=1e-15, max_iter=20000)
+    return (f.reshape(-1) - A @ res.x).reshape(H, W)
