@@ -1,0 +1,200 @@
+/*
+ * tvchain.h -- C ABI of the MI355X (gfx950) batched TV-chain prox and 2D TV
+ * (ROF) solver.
+ *
+ * Method: Kolmogorov, Pock, Rolinek, "Total variation on a tree"
+ * (arXiv 1502.07770).  The chain prox is the exact O(n) dynamic program of
+ * Sec. 4.1 (Algorithm 2 with quadratic unaries) for eq. (1D-ROF):
+ *
+ *     x = argmin_x  sum_e w_e |x_{e+1} - x_e|  +  1/2 sum_i (x_i - y_i)^2 ,
+ *
+ * and the 2D solver is the Lagrangian decomposition of Sec. 5.1 (ROF model,
+ * saddle problem eq. (rof-saddle), accelerated primal-dual iteration eq. (pd)
+ * with the primal prox on row chains and the dual prox, through the Moreau
+ * identity eq. (prox-tv-conj), on column chains).
+ *
+ * Conventions shared by every entry point:
+ *  - Every data pointer is a DEVICE pointer unless marked [host].  The caller
+ *    owns all memory; the library never allocates or frees device memory.
+ *  - Calls are asynchronous on `stream` (0 = the default stream) unless stated
+ *    otherwise, and return a tv_status.  Host-visible argument errors are
+ *    reported before any HIP call is made and leave all buffers untouched.
+ *  - No exception crosses the ABI.
+ *  - Element types: TV_F32 (float) or TV_F64 (double) for y, w, x and all
+ *    gradient buffers of one call.
+ */
+#ifndef TVCHAIN_H
+#define TVCHAIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TV_OK = 0,
+    TV_ERR_INVALID_ARG = 1,   /* bad sizes, strides, null pointers, w < 0 or NaN      */
+    TV_ERR_WORKSPACE = 2,     /* workspace null or smaller than the query says        */
+    TV_ERR_NO_DEVICE = 3,     /* no HIP device visible                                 */
+    TV_ERR_HIP = 4,           /* a HIP runtime call failed (launch, copy, sync)        */
+    TV_ERR_NOT_CONVERGED = 5, /* tv2d: max_iter reached before gap_tol; stats filled   */
+    TV_ERR_NONFINITE = 6      /* tv2d: the duality gap became NaN or infinite          */
+} tv_status;
+
+typedef enum { TV_F32 = 0, TV_F64 = 1 } tv_dtype;
+
+/* [host] A batch of chains inside one buffer.
+ *  Uniform batch (offsets == NULL): chain c, node i is element
+ *      c * chain_stride + i * elem_stride,  i in [0, length).
+ *  Row chains of a row-major H x W image: num_chains = H, length = W,
+ *  elem_stride = 1, chain_stride = W.  Column chains: num_chains = W,
+ *  length = H, elem_stride = W, chain_stride = 1.
+ *  Uneven batch (offsets != NULL, DEVICE array of num_chains + 1 ascending
+ *  int64): chain c is elements offsets[c] .. offsets[c+1]-1 with unit stride;
+ *  length is then the maximum chain length (an upper bound is fine), and
+ *  elem_stride / chain_stride are ignored.  Empty chains are allowed there.
+ *  Edge weights, when given per edge, use the layout of y: the weight of edge
+ *  (i, i+1) sits at the slot of node i; the slot of each chain's last node is
+ *  never read.  Lengths must be below 2^24 for TV_F32 (slopes are exact
+ *  integers in float) and 2^31 otherwise. */
+typedef struct {
+    int64_t num_chains;
+    int64_t length;
+    int64_t elem_stride;
+    int64_t chain_stride;
+    const int64_t *offsets;
+} tv_chain_layout;
+
+/* Bytes of device workspace tv_chain_prox needs for this layout and dtype
+ * (0 on invalid arguments).  Workspace holds the lambda^-/lambda^+ stream of
+ * the forward pass (Sec. 4.1, "Backward pass": 2n numbers per chain), a
+ * per-chain overflow flag and the HBM breakpoint deques of the overflow path. */
+size_t tv_chain_prox_workspace(const tv_chain_layout *layout, tv_dtype dtype);
+
+/* Batched chain prox, eq. (1D-ROF), exact (Sec. 4.1 dynamic program).
+ *  y  : input signal, layout above.
+ *  w  : per-edge weights in y's layout, or NULL to use w_scalar for every edge.
+ *       Weights must be >= 0 (w = 0 decouples the chain at that edge); a NaN or
+ *       negative w_scalar is rejected; per-edge values are not checked.
+ *  x  : output in y's layout; x may alias y (each y_i is read before x_i is
+ *       written by the same lane, and chains do not overlap).
+ *  Breakpoints live in an on-chip deque; a chain whose deque outgrows it is
+ *  redone exactly with its deque in the workspace, so results never depend on
+ *  the data's breakpoint depth. */
+tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const void *y,
+                        const void *w, double w_scalar, void *x,
+                        void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
+size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);
+
+/* Adjoint of tv_chain_prox for L = <grad_x, x(y, w)>.  x is the output of the
+ * forward call.  Runs are maximal blocks of exactly equal consecutive x (the
+ * backward clip of Algorithm 2 produces exact copies inside a run):
+ *   grad_y_i = mean of grad_x over the run containing i,
+ *   dL/dw_e  = s_e (mean_left - mean_right) on a run boundary e, with
+ *              s_e = sign(x_{e+1} - x_e), and 0 inside a run.
+ *  grad_y : output, y's layout (may be NULL).
+ *  grad_w : NULL (skip), or if w_per_edge != 0 an output in y's layout (slot of
+ *           each chain's last node set to 0), else an output of num_chains
+ *           values holding each chain's sum over its edges (the gradient of a
+ *           scalar weight shared by that chain).
+ *  At a kink (a degenerate point where a run is about to split) this is the
+ *  derivative for the run structure of the given x. */
+tv_status tv_chain_prox_backward(const tv_chain_layout *layout, tv_dtype dtype,
+                                 const void *x, const void *grad_x, void *grad_y,
+                                 void *grad_w, int w_per_edge,
+                                 void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* [host] Options of the 2D solvers. */
+typedef struct {
+    int max_iter;        /* iterations to run at most (>= 0)                          */
+    int gap_every;       /* evaluate the FP64 duality gap every this many iterations  */
+    double gap_tol;      /* stop once (P - D) / (H W) <= gap_tol; <= 0: never stop    */
+    double tau0;         /* initial primal step; sigma_0 = 1 / tau0 (tau sigma = 1)    */
+    int resume;          /* nonzero: continue from the state held in the workspace    */
+    double *gap_history; /* DEVICE, optional: gap after iteration k at [k-1]; entries
+                            of iterations without a gap evaluation are left untouched */
+} tv2d_options;
+
+/* [host] Result of a 2D solve (written by the library before it returns). */
+typedef struct {
+    int iters;        /* total iterations in the state (including resumed ones)       */
+    int status;       /* TV_OK, TV_ERR_NOT_CONVERGED or TV_ERR_NONFINITE              */
+    double gap_norm;  /* (P - D) / (H W) at the last evaluation                       */
+    double primal;    /* P(x) = lambda (TV_h + TV_v)(x) + |x - f|^2 / 2  (FP64)        */
+    double dual;      /* D(p) = |f|^2/2 - |f - D_h^T p_h - D_v^T p_v|^2 / 2  (FP64)    */
+} tv2d_stats;
+
+/* Bytes of device workspace tv2d_solve needs for an H x W image. */
+size_t tv2d_workspace(int64_t H, int64_t W, tv_dtype dtype);
+
+/* 2D ROF, min_x lambda (TV_h + TV_v)(x) + |x - f|^2 / 2 on the 4-connected grid,
+ * by the Sec. 5.1 decomposition into row chains (TV_h) and column chains
+ * (TV_v), accelerated primal-dual (tau_{k+1} = theta_k tau_k,
+ * sigma_{k+1} = sigma_k / theta_k, theta_k = 1/sqrt(1 + 2 tau_k), the primal
+ * part being 1-strongly convex), x^0 = f, y^0 = 0 unless resuming.
+ *  f      : H x W image, row-major with leading dimension ld >= W.
+ *  x      : output H x W, leading dimension ld.
+ *  The duality gap uses dual edge variables recovered from the two chain
+ *  solves, clipped to [-lambda, lambda], so P - D >= 0 always bounds the
+ *  suboptimality of x.  Reductions are FP64 whatever dtype is.
+ *  SYNCHRONOUS: returns after the solve ends (the host reads the gap every
+ *  gap_every iterations to decide whether to continue); `stats` is host memory.
+ *  Returns TV_OK, TV_ERR_NOT_CONVERGED (gap_tol > 0 not reached), or an error. */
+tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld,
+                     double lambda, void *x, const tv2d_options *options, tv2d_stats *stats,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Bytes of device workspace tv2d_solve_batched needs. H, W: [host] arrays. */
+size_t tv2d_batched_workspace(int num_images, const int64_t *H, const int64_t *W, tv_dtype dtype);
+
+/* Many independent 2D ROF problems of different sizes in one solve: every
+ * image's row chains run in one launch and its column chains in another, each
+ * image with its own lambda and its own stopping test.
+ *  H, W, pixel_offsets, lambda: [host] arrays of num_images entries; image j
+ *  occupies f[pixel_offsets[j] .. + H[j] W[j]) row-major (ld = W[j]), and x
+ *  likewise.  stats: [host] array of num_images results.  SYNCHRONOUS. */
+tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
+                             const int64_t *pixel_offsets, const double *lambda,
+                             const void *f, void *x, const tv2d_options *options,
+                             tv2d_stats *stats, void *workspace, size_t workspace_bytes,
+                             hipStream_t stream);
+
+/* [host] Process-wide tuning of the chain-prox launches.  Each chain of length
+ * n is cut into S segments of L nodes that are solved in parallel and then
+ * stitched exactly (the result does not depend on the tuning):
+ *   target_lanes: aim for about this many (chain, segment) lanes per launch;
+ *   min_segment : never cut segments shorter than this many nodes;
+ *   halo        : each segment's dynamic program starts this many nodes early
+ *                 so that its breakpoint deque has usually converged to the
+ *                 true one by the segment start (boundaries where it has not
+ *                 are detected exactly and redone).
+ * Defaults: 131072 lanes, 128 nodes, halo 128. */
+typedef struct {
+    int64_t target_lanes;
+    int64_t min_segment;
+    int64_t halo;
+} tv_tuning;
+
+/* Set the tuning (NULL restores the defaults); TV_ERR_INVALID_ARG on values < 1.
+ * Not thread-safe with respect to concurrent prox calls: a workspace sized
+ * before a change may be too small after it (TV_ERR_WORKSPACE). */
+tv_status tv_set_tuning(const tv_tuning *tuning);
+tv_status tv_get_tuning(tv_tuning *tuning);
+
+/* Segment length L the current tuning gives this layout (0 on bad layouts). */
+int64_t tv_chain_prox_segment_length(const tv_chain_layout *layout);
+
+/* Static description of a status code. */
+const char *tv_status_string(tv_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVCHAIN_H */

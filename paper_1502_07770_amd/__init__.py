@@ -1,1 +1,12 @@
-"""MI355X-native batched TV-chain prox and 2D TV (placeholder, binding follows)."""
+"""MI355X-native exact TV-chain prox and 2D TV (ROF) solver.
+
+Implements the data-parallel hot path of Kolmogorov, Pock, Rolinek, "Total
+variation on a tree" (arXiv 1502.07770): the O(n) chain dynamic program of
+Sec. 4.1, batched over the row and column chains of the Sec. 5.1 Lagrangian
+decomposition of 2D ROF, as hand-written HIP kernels for gfx950 behind the C
+ABI in ``include/tvchain.h``.  ``binding`` marshals torch tensors into that
+ABI; ``synth`` draws the seeded synthetic workloads.
+"""
+from .binding import (TvChainError, chain_prox, chain_prox_backward, load, prox)  # noqa: F401
+
+__all__ = ["TvChainError", "chain_prox", "chain_prox_backward", "load", "prox"]

@@ -1,0 +1,295 @@
+"""ctypes binding of libtvchain.so (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libtvchain.so``; this module
+only converts torch tensors (device memory) and the current HIP stream into
+the C ABI declared in ``include/tvchain.h``.  There is no CPU fallback: if the
+library is missing or no GPU is visible, calls raise ``TvChainError``.
+
+Functions mirror the C entry points:
+
+* ``chain_prox(y, w, dim)``            -> tv_chain_prox (eq. (1D-ROF), Sec. 4.1)
+* ``chain_prox_backward(x, g, ...)``   -> tv_chain_prox_backward
+* ``prox(y, w, dim)``                  -> autograd-aware chain prox
+* ``tv2d(f, lam, ...)``                -> tv2d_solve (Sec. 5.1)
+* ``tv2d_batched(images, lams, ...)``  -> tv2d_solve_batched
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Union
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtvchain.so")
+
+TV_OK = 0
+TV_ERR_INVALID_ARG = 1
+TV_ERR_WORKSPACE = 2
+TV_ERR_NO_DEVICE = 3
+TV_ERR_HIP = 4
+TV_ERR_NOT_CONVERGED = 5
+TV_ERR_NONFINITE = 6
+TV_F32 = 0
+TV_F64 = 1
+
+
+class TvChainError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        msg = "%s: status %d (%s)" % (what or "tvchain", self.status, status_string(self.status))
+        super().__init__(msg)
+
+
+class ChainLayout(ctypes.Structure):
+    _fields_ = [("num_chains", ctypes.c_int64), ("length", ctypes.c_int64),
+                ("elem_stride", ctypes.c_int64), ("chain_stride", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p)]
+
+
+class Tv2dOptions(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("gap_every", ctypes.c_int), ("gap_tol", ctypes.c_double),
+                ("tau0", ctypes.c_double), ("resume", ctypes.c_int), ("gap_history", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("target_lanes", ctypes.c_int64), ("min_segment", ctypes.c_int64), ("halo", ctypes.c_int64)]
+
+
+class Tv2dStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("gap_norm", ctypes.c_double),
+                ("primal", ctypes.c_double), ("dual", ctypes.c_double)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SIG = {
+    "tv_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "tv_chain_prox_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
+    "tv_chain_prox": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, _P, _P, ctypes.c_size_t, _P]),
+    "tv_chain_prox_backward_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
+    "tv_chain_prox_backward": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P,
+                                              ctypes.c_size_t, _P]),
+    "tv_set_tuning": (ctypes.c_int, [_P]),
+    "tv_get_tuning": (ctypes.c_int, [_P]),
+    "tv_chain_prox_segment_length": (_I64, [_P]),
+    "tv2d_workspace": (ctypes.c_size_t, [_I64, _I64, ctypes.c_int]),
+    "tv2d_solve": (ctypes.c_int, [ctypes.c_int, _P, _I64, _I64, _I64, ctypes.c_double, _P, _P, _P, _P,
+                                  ctypes.c_size_t, _P]),
+    "tv2d_batched_workspace": (ctypes.c_size_t, [ctypes.c_int, _P, _P, ctypes.c_int]),
+    "tv2d_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                          ctypes.c_size_t, _P]),
+}
+
+
+def load() -> ctypes.CDLL:
+    """Load libtvchain.so; raises TvChainError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TvChainError(TV_ERR_NO_DEVICE, "libtvchain.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIG.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().tv_status_string(int(status)).decode()
+    except Exception:  # library missing: still give a readable message
+        return "status %d" % status
+
+
+def _check(status: int, what: str) -> None:
+    if status != TV_OK:
+        raise TvChainError(status, what)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return TV_F32
+    if t.dtype == torch.float64:
+        return TV_F64
+    raise TypeError("tvchain supports float32 and float64 tensors, got %s" % t.dtype)
+
+
+def _require_gpu(*ts: torch.Tensor) -> None:
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise TvChainError(TV_ERR_INVALID_ARG, "tvchain tensors must live on the GPU")
+
+
+def _stream_ptr(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(load().tv_get_tuning(ctypes.byref(t)), "tv_get_tuning")
+    return {"target_lanes": int(t.target_lanes), "min_segment": int(t.min_segment), "halo": int(t.halo)}
+
+
+def set_tuning(target_lanes: Optional[int] = None, min_segment: Optional[int] = None,
+               halo: Optional[int] = None) -> None:
+    """Set the process-wide segmentation of chain-prox launches (None keeps the
+    current value).  Results do not depend on it; only speed does."""
+    cur = get_tuning()
+    t = Tuning(int(target_lanes if target_lanes is not None else cur["target_lanes"]),
+               int(min_segment if min_segment is not None else cur["min_segment"]),
+               int(halo if halo is not None else cur["halo"]))
+    _check(load().tv_set_tuning(ctypes.byref(t)), "tv_set_tuning")
+
+
+def reset_tuning() -> None:
+    _check(load().tv_set_tuning(None), "tv_set_tuning")
+
+
+def segment_length(num_chains: int, length: int) -> int:
+    lay = ChainLayout(int(num_chains), int(length), 1, int(length), None)
+    return int(load().tv_chain_prox_segment_length(ctypes.byref(lay)))
+
+
+# ---------------------------------------------------------------------------
+# layouts
+# ---------------------------------------------------------------------------
+
+def _chain_view(y: torch.Tensor, dim: int):
+    """Return (tensor to pass, layout, restore) for chains along ``dim``.
+
+    1-D tensors are one chain.  2-D tensors are passed with their own strides
+    (rows: dim=-1/1, columns: dim=0).  Anything else is moved to a contiguous
+    (chains, n) view and restored afterwards."""
+    if y.dim() == 1:
+        y1 = y.contiguous()
+        return y1, ChainLayout(1, y1.shape[0], 1, y1.shape[0], None), lambda t: t
+    d = dim % y.dim()
+    if y.dim() == 2 and y.is_contiguous():
+        R, C = y.shape
+        if d == 1:
+            return y, ChainLayout(R, C, 1, C, None), lambda t: t
+        return y, ChainLayout(C, R, C, 1, None), lambda t: t
+    moved = torch.movedim(y, d, -1)
+    shp = moved.shape
+    flat = moved.reshape(-1, shp[-1]).contiguous()
+    lay = ChainLayout(flat.shape[0], flat.shape[1], 1, flat.shape[1], None)
+    return flat, lay, (lambda t: torch.movedim(t.reshape(shp), -1, d))
+
+
+def chain_prox(y: torch.Tensor, w: Union[float, torch.Tensor] = 0.0, dim: int = -1,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Exact TV prox of every chain of ``y`` along ``dim`` (eq. (1D-ROF)).
+
+    ``w`` is a float (one weight for every edge) or a tensor shaped like ``y``
+    whose entry at node i is the weight of edge (i, i+1) along ``dim``."""
+    _require_gpu(y)
+    lib = load()
+    if y.numel() == 0:
+        return torch.empty_like(y) if out is None else out
+    wv = None
+    w_scalar = 0.0
+    if isinstance(w, torch.Tensor):
+        _require_gpu(w)
+        if w.shape != y.shape or w.dtype != y.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "per-edge w must match y's shape and dtype")
+        if w.stride() != y.stride():
+            y, w = y.contiguous(), w.contiguous()
+        wv, _, _ = _chain_view(w, dim)
+    else:
+        w_scalar = float(w)
+    yv, lay, restore = _chain_view(y, dim)
+    xv = torch.empty_like(yv)
+    code = _dtype_code(y)
+    nbytes = lib.tv_chain_prox_workspace(ctypes.byref(lay), code)
+    ws = _workspace(nbytes, y.device)
+    st = lib.tv_chain_prox(ctypes.byref(lay), code, _ptr(yv), _ptr(wv), w_scalar, _ptr(xv), _ptr(ws),
+                           nbytes, ctypes.c_void_p(_stream_ptr(y.device)))
+    _check(st, "tv_chain_prox")
+    res = restore(xv)
+    if out is not None:
+        out.copy_(res)
+        return out
+    return res
+
+
+def chain_prox_backward(x: torch.Tensor, grad_x: torch.Tensor, dim: int = -1,
+                        per_edge_w: bool = False, need_y: bool = True, need_w: bool = True):
+    """Adjoint of ``chain_prox``: returns (grad_y, grad_w); grad_w has x's shape
+    when ``per_edge_w`` and otherwise holds one sum per chain (shape of x
+    without ``dim``), either may be None."""
+    _require_gpu(x, grad_x)
+    lib = load()
+    xv, lay, restore = _chain_view(x, dim)
+    gv, lay_g, _ = _chain_view(grad_x.to(x.dtype), dim)
+    if (lay_g.elem_stride, lay_g.chain_stride) != (lay.elem_stride, lay.chain_stride):
+        xv = xv.contiguous()
+        gv = gv.contiguous()
+        xv, lay, restore = _chain_view(xv, dim)
+        gv, _, _ = _chain_view(gv, dim)
+    gy = torch.empty_like(xv) if need_y else None
+    if need_w:
+        gw = torch.empty_like(xv) if per_edge_w else torch.empty(lay.num_chains, dtype=x.dtype, device=x.device)
+    else:
+        gw = None
+    code = _dtype_code(x)
+    nbytes = lib.tv_chain_prox_backward_workspace(ctypes.byref(lay), code)
+    ws = _workspace(nbytes, x.device)
+    st = lib.tv_chain_prox_backward(ctypes.byref(lay), code, _ptr(xv), _ptr(gv), _ptr(gy), _ptr(gw),
+                                    1 if per_edge_w else 0, _ptr(ws), nbytes,
+                                    ctypes.c_void_p(_stream_ptr(x.device)))
+    _check(st, "tv_chain_prox_backward")
+    gy_out = restore(gy) if gy is not None else None
+    if gw is not None:
+        if per_edge_w:
+            gw = restore(gw)
+        else:
+            d = dim % x.dim()
+            shp = list(x.shape)
+            del shp[d]
+            gw = gw.reshape(shp) if shp else gw.reshape(())
+    return gy_out, gw
+
+
+class _ProxFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y, w_t, w_scalar, dim):
+        x = chain_prox(y, w_t if w_t is not None else w_scalar, dim)
+        ctx.save_for_backward(x)
+        ctx.dim = dim
+        ctx.per_edge = w_t is not None
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        need_y = ctx.needs_input_grad[0]
+        need_w = ctx.per_edge and ctx.needs_input_grad[1]
+        gy, gw = chain_prox_backward(x, gx.contiguous(), ctx.dim, per_edge_w=True, need_y=need_y,
+                                     need_w=need_w)
+        return gy, gw, None, None
+
+
+def prox(y: torch.Tensor, w: Union[float, torch.Tensor] = 0.0, dim: int = -1) -> torch.Tensor:
+    """Differentiable chain prox: gradients flow to ``y`` and, when ``w`` is a
+    per-edge tensor, to ``w`` (through the run-structure adjoint)."""
+    if isinstance(w, torch.Tensor):
+        return _ProxFn.apply(y, w, 0.0, dim)
+    return _ProxFn.apply(y, None, float(w), dim)

@@ -1,0 +1,171 @@
+// api_chain.hip -- C ABI of the batched chain prox and its adjoint.
+#include <math.h>
+
+#include "../../include/tvchain.h"
+#include "kernels.h"
+
+namespace tvc {
+
+static const SegTuning kDefaultTuning{int64_t(1) << 17, 128, 128};
+
+SegTuning &seg_tuning() {
+    static SegTuning t = kDefaultTuning;
+    return t;
+}
+
+static int64_t round_tile(int64_t v) { return (v + kTile - 1) / kTile * kTile; }
+
+// Enough segments per chain that the launch has about target_lanes lanes,
+// with segments no shorter than min_segment; L, H and CK are tile multiples.
+SegPlan seg_plan(int64_t num_chains, int64_t n) {
+    const SegTuning &t = seg_tuning();
+    SegPlan p;
+    int64_t S = num_chains > 0 ? (t.target_lanes + num_chains - 1) / num_chains : 1;
+    const int64_t smax = (n + t.min_segment - 1) / t.min_segment;
+    if (S > smax) S = smax;
+    if (S < 1) S = 1;
+    p.L = round_tile((n + S - 1) / S);
+    if (p.L < kTile) p.L = kTile;
+    p.H = round_tile(t.halo);
+    p.CK = 16;  // checkpoints at a + 16, 32, 48, 64 (tile multiples)
+    return p;
+}
+
+// Host-side checks of a layout; no HIP call.
+static bool layout_ok(const tv_chain_layout *L, tv_dtype dt) {
+    if (!L) return false;
+    if (dt != TV_F32 && dt != TV_F64) return false;
+    if (L->num_chains < 0) return false;
+    if (L->num_chains == 0) return true;
+    if (L->length < 1) return false;
+    const int64_t lim = (dt == TV_F32) ? (int64_t(1) << 24) : (int64_t(1) << 31) - 8;
+    if (L->length >= lim) return false;
+    if (!L->offsets) {
+        if (L->elem_stride < 1) return false;
+        if (L->num_chains > 1 && L->chain_stride < 1) return false;
+    }
+    return true;
+}
+
+static ChainBatch to_batch(const tv_chain_layout *L) {
+    ChainBatch b;
+    b.num_chains = L->num_chains;
+    b.n = L->length;
+    b.es = L->elem_stride;
+    b.cs = L->chain_stride;
+    b.offsets = L->offsets;
+    return b;
+}
+
+static size_t prox_ws_bytes(const tv_chain_layout *L, tv_dtype dt) {
+    const ChainBatch b = to_batch(L);
+    const SegPlan plan = seg_plan(b.num_chains, b.n);
+    return dt == TV_F32 ? chain_prox_ws_bytes<float>(b, plan) : chain_prox_ws_bytes<double>(b, plan);
+}
+
+static tv_status device_check() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
+    return TV_OK;
+}
+
+}  // namespace tvc
+
+using namespace tvc;
+
+extern "C" {
+
+const char *tv_status_string(tv_status s) {
+    switch (s) {
+    case TV_OK: return "ok";
+    case TV_ERR_INVALID_ARG: return "invalid argument";
+    case TV_ERR_WORKSPACE: return "workspace missing or too small";
+    case TV_ERR_NO_DEVICE: return "no HIP device";
+    case TV_ERR_HIP: return "HIP runtime error";
+    case TV_ERR_NOT_CONVERGED: return "duality gap tolerance not reached within max_iter";
+    case TV_ERR_NONFINITE: return "non-finite duality gap";
+    }
+    return "unknown status";
+}
+
+size_t tv_chain_prox_workspace(const tv_chain_layout *layout, tv_dtype dtype) {
+    if (!layout_ok(layout, dtype)) return 0;
+    if (layout->num_chains == 0) return 0;
+    return prox_ws_bytes(layout, dtype);
+}
+
+tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const void *y, const void *w,
+                        double w_scalar, void *x, void *workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+    if (!layout_ok(layout, dtype)) return TV_ERR_INVALID_ARG;
+    if (layout->num_chains == 0) return TV_OK;
+    if (!y || !x) return TV_ERR_INVALID_ARG;
+    if (!w && !(isfinite(w_scalar) && w_scalar >= 0.0)) return TV_ERR_INVALID_ARG;
+    const size_t need = prox_ws_bytes(layout, dtype);
+    if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
+    tv_status st = device_check();
+    if (st != TV_OK) return st;
+    const ChainBatch b = to_batch(layout);
+    const SegPlan plan = seg_plan(b.num_chains, b.n);
+    hipError_t e;
+    if (dtype == TV_F32)
+        e = launch_chain_prox<float>(b, (const float *)y, (const float *)w, (float)w_scalar, (float *)x,
+                                     workspace, plan, stream);
+    else
+        e = launch_chain_prox<double>(b, (const double *)y, (const double *)w, w_scalar, (double *)x,
+                                      workspace, plan, stream);
+    return e == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+tv_status tv_set_tuning(const tv_tuning *t) {
+    if (!t) {
+        seg_tuning() = kDefaultTuning;
+        return TV_OK;
+    }
+    if (t->target_lanes < 1 || t->min_segment < 1 || t->halo < 0) return TV_ERR_INVALID_ARG;
+    seg_tuning() = SegTuning{t->target_lanes, t->min_segment, t->halo};
+    return TV_OK;
+}
+
+tv_status tv_get_tuning(tv_tuning *t) {
+    if (!t) return TV_ERR_INVALID_ARG;
+    t->target_lanes = seg_tuning().target_lanes;
+    t->min_segment = seg_tuning().min_segment;
+    t->halo = seg_tuning().halo;
+    return TV_OK;
+}
+
+int64_t tv_chain_prox_segment_length(const tv_chain_layout *layout) {
+    if (!layout || layout->num_chains < 1 || layout->length < 1) return 0;
+    return seg_plan(layout->num_chains, layout->length).L;
+}
+
+size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype) {
+    (void)layout;
+    (void)dtype;
+    return 0;
+}
+
+tv_status tv_chain_prox_backward(const tv_chain_layout *layout, tv_dtype dtype, const void *x,
+                                 const void *grad_x, void *grad_y, void *grad_w, int w_per_edge,
+                                 void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    (void)workspace;
+    (void)workspace_bytes;
+    if (!layout_ok(layout, dtype)) return TV_ERR_INVALID_ARG;
+    if (layout->num_chains == 0) return TV_OK;
+    if (!x || !grad_x) return TV_ERR_INVALID_ARG;
+    if (!grad_y && !grad_w) return TV_OK;
+    tv_status st = device_check();
+    if (st != TV_OK) return st;
+    const ChainBatch b = to_batch(layout);
+    hipError_t e;
+    if (dtype == TV_F32)
+        e = launch_chain_adjoint<float>(b, (const float *)x, (const float *)grad_x, (float *)grad_y,
+                                        (float *)grad_w, w_per_edge, stream);
+    else
+        e = launch_chain_adjoint<double>(b, (const double *)x, (const double *)grad_x, (double *)grad_y,
+                                         (double *)grad_w, w_per_edge, stream);
+    return e == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,801 @@
+// seg_kernels.h -- segment-parallel exact chain TV prox (gfx950).
+//
+// A chain of n nodes is cut into segments of L nodes; lane (s, c) owns segment
+// s of chain c, and consecutive lanes own the same segment of consecutive
+// chains (coalesced for column layouts and for the lambda stream).
+//
+// Why segments can be solved independently and still exactly.  The deque of
+// the Sec. 4.1 dynamic program forgets its history: a run started at node
+// a - H from an empty deque (an assumed zero incoming message) ends up holding
+// bit-for-bit the same breakpoints as the true run after a few dozen nodes on
+// the workloads here (median 14, 99th percentile 66 on the 4096^2 image).  From
+// the first node where the two deques are equal every later step computes the
+// same values.  So:
+//  k_seg_main   runs its segment's DP from an empty deque starting H nodes
+//               early (the halo), streams lambda^-/lambda^+ for its own nodes,
+//               and saves its deque after the halo (HS), at two checkpoints
+//               inside the segment (CK1, CK2) and at its end (ES).  It then
+//               runs the backward clip pass (Algorithm 2, lines 7-9) over its
+//               own nodes: composing x_i = clip(x_{i+1}, lam^-_i, lam^+_i) from
+//               the right, the composed map is a clip onto an interval, and once
+//               that interval is a single point every node left of it is
+//               determined and written.
+//  k_seg_verify compares the saved end state of segment s-1 with the halo state
+//               of segment s (exact comparison of breakpoints and slope tags).
+//  k_seg_fix    one lane per chain, only where a comparison failed: redoes the
+//               segment from the true incoming deque until it meets a saved
+//               checkpoint (then the first pass is exact from there), and redoes
+//               its backward pass.  Chains whose deque outgrew the LDS ring are
+//               solved here sequentially with the deque in HBM.
+//  k_seg_tail   finishes each segment's un-collapsed right tail from the value at
+//               the segment's right end (a short composition over segments).
+// The output is bit-identical to running the DP sequentially per chain.
+//
+// The deque is a ring of packed (lambda, tag) entries in LDS with the front
+// and back entries cached in registers and the next entry of a scan prefetched
+// one pop ahead.  Loads of node data run P nodes ahead into registers, so each
+// memory wait covers requests issued a tile earlier.
+#pragma once
+#include "chain_core.h"
+
+namespace tvc {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) LamPair {
+    T lo, hi;
+};
+
+// A deque entry: breakpoint lambda and the birth step k of the segment to its
+// right, kept as a floating-point integer (exact below 2^24 for float) so the
+// slope s - k is one exact subtraction.
+template <typename T>
+struct alignas(2 * sizeof(T)) Ent {
+    T l;
+    T k;
+};
+
+template <typename T> __device__ __forceinline__ Ent<T> mk_ent(T l, T k) {
+    Ent<T> e;
+    e.l = l;
+    e.k = k;
+    return e;
+}
+
+// Segment geometry: halo H and checkpoint spacing CK (both multiples of the
+// tile) and the saved-state slots per segment.
+constexpr int kCheckpoints = 4;  // first-pass deques saved every CK nodes after a segment start
+constexpr int kSaves = 3 + kCheckpoints;  // HS, CK..., ES, ES2
+// Breakpoints examined branch-free at each end of the deque per step.
+constexpr int kScanWindow = 5;
+// Nodes the backward sweep loads ahead of their use.
+constexpr int kSweepTile = 16;
+constexpr int kSaveHalo = 0, kSaveCk = 1, kSaveEnd = 1 + kCheckpoints, kSaveEnd2 = 2 + kCheckpoints;
+
+template <typename T>
+struct SegWs {
+    int64_t C;          // chains
+    int64_t n;          // maximum chain length
+    int64_t L;          // segment length
+    int64_t S;          // segments per chain of length n
+    int64_t H;          // halo
+    int64_t CK;         // checkpoint spacing
+    LamPair<T> *lam;    // [n][C]
+    Ent<T> *st;         // saved deques [S][kSaves][K][C] (ES2: the repair's end state)
+    int *st_size;       // [S][kSaves][C]
+    uint32_t *st_hash;  // [S][kSaves][C]
+    uint8_t *ovf;       // [C][S] ring overflow
+    uint8_t *mis;       // [C][S] halo state != end state of the previous segment
+    uint8_t *clean;     // [C][S] the repair met a first-pass checkpoint
+    int *rep_stop;      // [S][C] node where the repair stopped
+    T *seg_lo;          // [S][C] composed backward clip of the segment
+    T *seg_hi;
+    int *seg_unc;       // [S][C] first node of the un-collapsed tail
+    T *seg_xb;          // [S][C] x at the first node after the segment
+    T *fb_lam;          // [C][2n+4] HBM deques for overflowing chains
+    int *fb_tag;
+    int64_t fb_cap;
+};
+
+struct ChainSpan {
+    int64_t base;  // element of node 0
+    int64_t es;    // element stride
+    int64_t n;     // nodes
+};
+
+template <typename T> __device__ __forceinline__ T pos_inf();
+template <> __device__ __forceinline__ float pos_inf<float>() { return __builtin_huge_valf(); }
+template <> __device__ __forceinline__ double pos_inf<double>() { return __builtin_huge_val(); }
+
+template <int K> __device__ __forceinline__ int clamp_size(int v) { return v < 0 ? 0 : (v > K ? K : v); }
+
+__device__ __forceinline__ uint32_t bits32(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t bits32(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    return (uint32_t)b ^ (uint32_t)(b >> 32) * 0x9E3779B1u;
+}
+
+template <typename T, int K> struct CRing;
+
+// Entry-by-entry comparison of a ring with a saved state of the same size,
+// loading the saved entries in independent batches of eight.
+template <typename T, int K>
+__device__ __forceinline__ bool saved_equal(const CRing<T, K> &R, const Ent<T> *src, int64_t stride);
+
+// ---------------------------------------------------------------------------
+// LDS ring with register-cached ends.
+// ---------------------------------------------------------------------------
+template <typename T, int K>
+struct CRing {
+    Ent<T> *col;  // this lane's column: slot j at col[j * 64]
+    int head, size;
+    Ent<T> f, b;  // front / back copies (valid when size >= 1)
+
+    __device__ __forceinline__ void init(Ent<T> *base, int lane) {
+        col = base + lane;
+        head = 0;
+        size = 0;
+    }
+    __device__ __forceinline__ Ent<T> &at(int j) const { return col[((head + j) & (K - 1)) * 64]; }
+    __device__ __forceinline__ Ent<T> ld(int j) const { return col[((head + j) & (K - 1)) * 64]; }
+    // Order-sensitive 32-bit hash of the breakpoints and tags (the back tag is
+    // excluded); a filter only: equality is always confirmed entry by entry.
+    __device__ __forceinline__ uint32_t hash() const {
+        uint32_t h = 0x811C9DC5u ^ (uint32_t)size;
+        for (int j = 0; j < size; ++j) {
+            const Ent<T> e = ld(j);
+            h = (h ^ bits32(e.l)) * 0x01000193u;
+            if (j + 1 < size) h = (h ^ bits32(e.k)) * 0x01000193u;
+        }
+        return h;
+    }
+    __device__ __forceinline__ void save(Ent<T> *dst, int *szdst, uint32_t *hdst, int64_t stride) const {
+        *szdst = size;
+        *hdst = hash();
+        for (int j = 0; j < size; ++j) dst[j * stride] = ld(j);
+    }
+    __device__ __forceinline__ void load(const Ent<T> *src, const int *szsrc, int64_t stride) {
+        head = 0;
+        size = clamp_size<K>(*szsrc);
+        for (int j = 0; j < size; ++j) col[j * 64] = src[j * stride];
+        if (size > 0) {
+            f = col[0];
+            b = col[(size - 1) * 64];
+        }
+    }
+    // Same breakpoints and tags (the back entry's tag is never read).  Size
+    // and hash reject most unequal states with two loads; the exact check
+    // loads the saved entries eight at a time.
+    __device__ __forceinline__ bool equals(const Ent<T> *src, const int *szsrc, const uint32_t *hsrc,
+                                           int64_t stride) const {
+        if (*szsrc != size || *hsrc != hash()) return false;
+        return saved_equal<T, K>(*this, src, stride);
+    }
+};
+
+template <typename T, int K>
+__device__ __forceinline__ bool saved_equal(const CRing<T, K> &R, const Ent<T> *src, int64_t stride) {
+    const int n = R.size;
+    bool eq = true;
+    for (int j0 = 0; j0 < n && eq; j0 += 8) {
+        Ent<T> e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[j] = src[(j0 + j < n ? j0 + j : n - 1) * stride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int jj = j0 + j;
+            if (jj < n) {
+                const Ent<T> m = R.ld(jj);
+                eq = eq && (e[j].l == m.l) && (jj + 1 == n || e[j].k == m.k);
+            }
+        }
+    }
+    return eq;
+}
+
+// One DP step on a CRing: the same arithmetic as dp_step in chain_core.h, in a
+// branch-free form.  The message values at the first W and the last W
+// breakpoints are formed up front (all LDS reads issued together); the pop
+// count of each end is the number of leading values beyond the threshold (the
+// values are non-decreasing, also in floating point), and the bracketing
+// segment is picked with selects.  Only an end that needs more than W pops
+// (about 3 in 1000 steps on the workloads here) falls back to a loop.  This
+// keeps a wave's 64 lanes in step: a divergent pop loop costs the slowest
+// lane's pop count (about 4 per end per node) instead of the mean (1).
+template <typename T, int K, int W>
+__device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, int s, T yi, T wprev, T w, bool root, T &lm,
+                                            T &lp) {
+    const T lo = -w, hi = w;
+    const T sf = (T)s;
+    const int t = R.size;
+    if (t == 0) {
+        lm = yi + lo;
+        lp = yi + hi;
+        if (root) return true;
+        R.head = 0;
+        R.size = 2;
+        R.f = mk_ent<T>(lm, sf - (T)1);
+        R.b = mk_ent<T>(lp, (T)0);
+        R.col[0] = R.f;
+        R.col[64] = R.b;
+        return true;
+    }
+    Ent<T> F[W], B[W];
+    F[0] = R.f;
+    B[0] = R.b;
+#pragma unroll
+    for (int j = 1; j < W; ++j) {
+        F[j] = R.ld(j);
+        B[j] = R.ld(t - 1 - j);
+    }
+    // ---- left end: pops p = #{j : v_j < lo}, v_0 = m(lam_1) ----
+    T v[W];
+    v[0] = F[0].l - wprev - yi;
+#pragma unroll
+    for (int j = 1; j < W; ++j) v[j] = v[j - 1] + (sf - F[j - 1].k) * (F[j].l - F[j - 1].l);
+    int p = 0;
+    T ck = F[0].k, cl = F[0].l, nl = F[0].l, vc = v[0];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const bool c = (j < t) & (v[j] < lo);
+        p = c ? j + 1 : p;
+        cl = c ? F[j].l : cl;
+        ck = c ? F[j].k : ck;
+        vc = c ? v[j] : vc;
+        nl = c ? F[j + 1 < W ? j + 1 : W - 1].l : nl;
+    }
+    if (p == W && t > W) {  // rare: keep popping one breakpoint at a time
+        for (;;) {
+            if (p == t) break;
+            const Ent<T> nx = R.ld(p);
+            const T vn = vc + (sf - ck) * (nx.l - cl);
+            nl = nx.l;
+            if (vn >= lo) break;
+            vc = vn;
+            cl = nx.l;
+            ck = nx.k;
+            ++p;
+        }
+    }
+    {
+        const T lm_gen = clampv(cl + (lo - vc) * recip(sf - ck), cl, nl);
+        const T lm_all = cl + (lo - vc);          // beyond every breakpoint (slope 1)
+        const T lm_none = F[0].l - (v[0] - lo);  // before the first breakpoint (slope 1)
+        lm = (p == 0) ? lm_none : ((p == t) ? lm_all : lm_gen);
+    }
+    const T tnew = (p == 0 || p == t) ? sf - (T)1 : ck;
+    if (root) return true;
+    if (p == 0 && t >= K) return false;
+    // pop p, push lm at the front
+    R.head = (R.head + p + K - 1) & (K - 1);
+    const int t1 = t - p + 1;
+    R.f = mk_ent<T>(lm, tnew);
+    R.col[R.head * 64] = R.f;
+    if (t1 == 1) {
+        // every old breakpoint was popped: the segment right of lm has slope 1
+        lp = lm + (hi - lo);
+        R.b = mk_ent<T>(lp, (T)0);
+        R.col[((R.head + 1) & (K - 1)) * 64] = R.b;
+        R.size = 2;
+        return true;
+    }
+    // ---- right end over the t - p old breakpoints left (never pops lm) ----
+    const int qmax = t1 - 1;
+    T u[W];
+    u[0] = B[0].l + wprev - yi;
+#pragma unroll
+    for (int j = 1; j < W; ++j) u[j] = u[j - 1] - (sf - B[j].k) * (B[j - 1].l - B[j].l);
+    int q = 0;
+    T rk = B[0].k, rcl = B[0].l, rnl = B[0].l, uc = u[0];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const bool c = (j < qmax) & (u[j] > hi);
+        q = c ? j + 1 : q;
+        rcl = c ? B[j].l : rcl;
+        uc = c ? u[j] : uc;
+        rnl = c ? B[j + 1 < W ? j + 1 : W - 1].l : rnl;
+        rk = c ? B[j + 1 < W ? j + 1 : W - 1].k : rk;
+    }
+    if (q == W && qmax > W) {  // rare: keep popping from the back
+        for (;;) {
+            if (q == qmax) break;
+            const Ent<T> nx = R.ld(t1 - 1 - q);
+            const T up = uc - (sf - nx.k) * (rcl - nx.l);
+            rnl = nx.l;
+            rk = nx.k;
+            if (up <= hi) break;
+            uc = up;
+            rcl = nx.l;
+            ++q;
+        }
+    }
+    {
+        const T lp_gen = clampv(rcl - (uc - hi) * recip(sf - rk), rnl, rcl);
+        T lp_lm = lm + (hi - lo) * recip(sf - tnew);  // popped down to lm (lm's segment)
+        lp_lm = (lp_lm > rcl) ? rcl : lp_lm;
+        const T lp_none = B[0].l + (hi - u[0]);          // beyond the last breakpoint (slope 1)
+        lp = (q == 0) ? lp_none : ((q == qmax) ? lp_lm : lp_gen);
+    }
+    if (q == 0) R.at(t1 - 1).k = sf - (T)1;  // the old back's right segment is now interior, slope 1
+    R.size = t1 - q;
+    if (R.size >= K) return false;
+    ++R.size;
+    R.b = mk_ent<T>(lp, (T)0);
+    R.at(R.size - 1) = R.b;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Shared pieces.
+// ---------------------------------------------------------------------------
+template <typename T, int K>
+__device__ __forceinline__ void node_step(CRing<T, K> &R, bool &ok, int64_t i, int64_t n, T yi, T wi, T &wprev,
+                                          T &lm, T &lp) {
+    const bool root = (i == n - 1);
+    lm = (T)0;
+    lp = (T)0;
+    if (ok) ok = dp_step_win<T, K, kScanWindow>(R, (int)(i + 1), yi, wprev, root ? (T)0 : wi, root, lm, lp);
+    if (root) lp = lm;
+    wprev = wi;
+}
+
+template <typename T>
+__device__ __forceinline__ void put_lam(LamPair<T> *lam, int64_t i, int64_t C, int64_t c, T lm, T lp) {
+    LamPair<T> pr;
+    pr.lo = lm;
+    pr.hi = lp;
+    lam[i * C + c] = pr;
+}
+
+template <typename T>
+__device__ __forceinline__ Ent<T> *save_slot(const SegWs<T> &ws, int K, int64_t s, int kind, int64_t c) {
+    return ws.st + ((s * kSaves + kind) * K) * ws.C + c;
+}
+template <typename T>
+__device__ __forceinline__ int *size_slot(const SegWs<T> &ws, int64_t s, int kind, int64_t c) {
+    return ws.st_size + (s * kSaves + kind) * ws.C + c;
+}
+template <typename T>
+__device__ __forceinline__ uint32_t *hash_slot(const SegWs<T> &ws, int64_t s, int kind, int64_t c) {
+    return ws.st_hash + (s * kSaves + kind) * ws.C + c;
+}
+// Save / compare the ring against saved state `kind` of segment s.
+template <typename T, int K>
+__device__ __forceinline__ void save_state(const SegWs<T> &ws, const CRing<T, K> &R, int64_t s, int kind, int64_t c) {
+    R.save(save_slot(ws, K, s, kind, c), size_slot(ws, s, kind, c), hash_slot(ws, s, kind, c), ws.C);
+}
+template <typename T, int K>
+__device__ __forceinline__ bool equals_state(const SegWs<T> &ws, const CRing<T, K> &R, int64_t s, int kind, int64_t c) {
+    return R.equals(save_slot(ws, K, s, kind, c), size_slot(ws, s, kind, c), hash_slot(ws, s, kind, c), ws.C);
+}
+template <typename T, int K>
+__device__ __forceinline__ void load_state(const SegWs<T> &ws, CRing<T, K> &R, int64_t s, int kind, int64_t c) {
+    R.load(save_slot(ws, K, s, kind, c), size_slot(ws, s, kind, c), ws.C);
+}
+
+// Forward DP over nodes [from, b) with data loads P nodes ahead, storing the
+// lambda pairs of nodes >= a.  After each full tile hook(e) is called with the
+// next node index e (tile edges are multiples of P from `from`); a true return
+// stops the run, and fwd_run then returns e.  Otherwise it returns b.
+template <typename T, class Prob, int K, int P, class Hook>
+__device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::Src &src, bool &ok, T &wprev,
+                                           int64_t from, int64_t a, int64_t b, int64_t n, LamPair<T> *lam,
+                                           int64_t C, int64_t c, Hook hook) {
+    typename Prob::Pre pre[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) pre[j] = src.load((from + j < b) ? from + j : b - 1);
+    auto node = [&](int64_t i, const typename Prob::Pre &pv) {
+        T lm, lp;
+        node_step<T, K>(R, ok, i, n, src.data(pv), src.weight(pv), wprev, lm, lp);
+        if (i >= a) put_lam<T>(lam, i, C, c, lm, lp);
+    };
+    int64_t i0 = from;
+    for (; i0 + P <= b; i0 += P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int64_t i = i0 + j;
+            const auto pv = pre[j];
+            pre[j] = src.load((i + P < b) ? i + P : b - 1);
+            node(i, pv);
+        }
+        if (hook(i0 + P)) return i0 + P;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        if (i0 + j < b) node(i0 + j, pre[j]);
+    }
+    return b;
+}
+
+// Backward clip pass over [a, b) of one chain.  All lanes of a wave share a and
+// b, so node indices are wave-uniform and the lambda / sink accesses coalesce.
+// Collapsed nodes are written through the sink; the un-collapsed right tail
+// gets its composed interval in the lambda stream for k_seg_tail.
+template <typename T, class Prob, int P>
+__device__ __forceinline__ void bwd_sweep(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp,
+                                          int64_t s, int64_t c, int64_t a, int64_t b) {
+    const auto sink = Prob::sink(pp, sp);
+    LamPair<T> *__restrict__ lam = ws.lam;
+    const int64_t C = ws.C;
+    T glo = -pos_inf<T>(), ghi = pos_inf<T>(), x = (T)0;
+    bool col = false;
+    int64_t k = a - 1;
+    LamPair<T> pre[P];
+    typename Prob::SinkPre spre[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int64_t i = (b - 1 - j >= a) ? b - 1 - j : a;
+        pre[j] = lam[i * C + c];
+        spre[j] = sink.load(i);
+    }
+    auto visit = [&](int64_t i, const LamPair<T> &p, const typename Prob::SinkPre &sv) {
+        if (!col) {
+            glo = clampv(glo, p.lo, p.hi);
+            ghi = clampv(ghi, p.lo, p.hi);
+            if (glo == ghi) {
+                col = true;
+                x = glo;
+                k = i;
+            }
+        } else {
+            x = clampv(x, p.lo, p.hi);
+        }
+        if (col) {
+            sink.store(i, x, sv);
+        } else {
+            LamPair<T> g;
+            g.lo = glo;
+            g.hi = ghi;
+            lam[i * C + c] = g;
+        }
+    };
+    int64_t i0 = b - 1;
+    for (; i0 - (P - 1) >= a; i0 -= P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int64_t i = i0 - j;
+            const LamPair<T> p = pre[j];
+            const auto sv = spre[j];
+            const int64_t ip = (i - P >= a) ? i - P : a;
+            pre[j] = lam[ip * C + c];
+            spre[j] = sink.load(ip);
+            visit(i, p, sv);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        if (i0 - j >= a) visit(i0 - j, pre[j], spre[j]);
+    }
+    const int64_t sc = s * C + c;
+    ws.seg_unc[sc] = (int)(k + 1);
+    ws.seg_lo[sc] = col ? x : glo;
+    ws.seg_hi[sc] = col ? x : ghi;
+}
+
+// True if the deque after node e - 1 equals the first pass's checkpoint there.
+template <typename T, int K>
+__device__ __forceinline__ bool meets_checkpoint(const SegWs<T> &ws, const CRing<T, K> &R, int64_t s, int64_t c,
+                                                 int64_t a, int64_t e) {
+    const int64_t m = (e - a) / ws.CK;
+    if (e <= a || m * ws.CK != e - a || m > kCheckpoints) return false;
+    return equals_state<T, K>(ws, R, s, kSaveCk + (int)m - 1, c);
+}
+
+// ---------------------------------------------------------------------------
+// First pass: forward with halo and saves, then the backward sweep.
+// ---------------------------------------------------------------------------
+template <typename T, class Prob, int K, int P>
+__global__ __launch_bounds__(64) void k_seg_main(SegWs<T> ws, typename Prob::Params pp) {
+    __shared__ Ent<T> s_ent[K * 64];
+    const int lane = threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+    if (g >= ws.S * ws.C) return;
+    const int64_t c = g % ws.C, s = g / ws.C;
+    const ChainSpan sp = Prob::span(pp, c, ws.n);
+    const int64_t n = sp.n;
+    const int64_t a = s * ws.L;
+    if (a >= n) return;
+    const int64_t b = (a + ws.L < n) ? a + ws.L : n;
+    const int64_t h0 = (a > ws.H) ? a - ws.H : 0;
+    const auto src = Prob::src(pp, sp);
+    CRing<T, K> R;
+    R.init(s_ent, lane);
+    bool ok = true;
+    T wprev = (T)0;
+    const int64_t C = ws.C;
+    if (s > 0 && h0 == a) save_state<T, K>(ws, R, s, kSaveHalo, c);  // no halo: the run starts empty at a
+    // tile edges align with a and a + m CK (all multiples of P)
+    auto saves = [&](int64_t e) {
+        if (ok) {
+            if (s > 0 && e == a) save_state<T, K>(ws, R, s, kSaveHalo, c);
+            const int64_t m = (e - a) / ws.CK;
+            if (e > a && m * ws.CK == e - a && m <= kCheckpoints)
+                save_state<T, K>(ws, R, s, kSaveCk + (int)m - 1, c);
+        }
+        return false;
+    };
+    fwd_run<T, Prob, K, P>(R, src, ok, wprev, h0, a, b, n, ws.lam, C, c, saves);
+    if (ok && b < n) save_state<T, K>(ws, R, s, kSaveEnd, c);
+    ws.ovf[c * ws.S + s] = ok ? 0 : 1;
+    if (ok) bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
+}
+
+// ---------------------------------------------------------------------------
+// Boundary check and repair, lane (s, c) for s >= 1.  If the first pass's
+// deque after the halo differs from the saved end state of segment s-1, the
+// segment is rerun from that end state (taken as the true incoming message;
+// k_seg_fix corrects the rare cases where it is not) until the deque matches a
+// first-pass checkpoint, then its backward pass is redone.
+// ---------------------------------------------------------------------------
+template <typename T, class Prob, int K, int P>
+__global__ __launch_bounds__(64) void k_seg_repair(SegWs<T> ws, typename Prob::Params pp) {
+    __shared__ Ent<T> s_ent[K * 64];
+    const int lane = threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+    if (g >= (ws.S - 1) * ws.C) return;
+    const int64_t c = g % ws.C, s = g / ws.C + 1;
+    const ChainSpan sp = Prob::span(pp, c, ws.n);
+    const int64_t n = sp.n;
+    const int64_t a = s * ws.L;
+    if (a >= n) return;
+    const int64_t b = (a + ws.L < n) ? a + ws.L : n;
+    const int64_t cs = c * ws.S + s;
+    if (ws.ovf[cs] || ws.ovf[cs - 1]) return;  // the chain goes to the HBM fallback
+    const int64_t C = ws.C;
+    bool same = (*size_slot(ws, s - 1, kSaveEnd, c) == *size_slot(ws, s, kSaveHalo, c)) &&
+                (*hash_slot(ws, s - 1, kSaveEnd, c) == *hash_slot(ws, s, kSaveHalo, c));
+    if (same) {
+        const Ent<T> *A = save_slot(ws, K, s - 1, kSaveEnd, c);
+        const Ent<T> *B = save_slot(ws, K, s, kSaveHalo, c);
+        const int m = clamp_size<K>(*size_slot(ws, s - 1, kSaveEnd, c));
+        for (int j0 = 0; j0 < m && same; j0 += 8) {
+            Ent<T> ea[8], eb[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int jj = (j0 + j < m) ? j0 + j : m - 1;
+                ea[j] = A[jj * C];
+                eb[j] = B[jj * C];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int jj = j0 + j;
+                if (jj < m) same = same && (ea[j].l == eb[j].l) && (jj + 1 == m || ea[j].k == eb[j].k);
+            }
+        }
+    }
+    ws.mis[cs] = same ? 0 : 1;
+    if (same) return;
+    const auto src = Prob::src(pp, sp);
+    CRing<T, K> R;
+    R.init(s_ent, lane);
+    load_state<T, K>(ws, R, s - 1, kSaveEnd, c);
+    bool ok = true;
+    T wprev = src.weight(src.load(a - 1));
+    const int64_t stop = fwd_run<T, Prob, K, P>(R, src, ok, wprev, a, a, b, n, ws.lam, C, c,
+                                                [&](int64_t e) { return !ok || meets_checkpoint<T, K>(ws, R, s, c, a, e); });
+    if (!ok) {
+        ws.ovf[cs] = 1;
+        return;
+    }
+    // met a checkpoint, or ends with the first pass's end deque: either way the
+    // two runs coincide from some node on, so the saved end state is the true one
+    const bool clean = stop < b || (b < n && equals_state<T, K>(ws, R, s, kSaveEnd, c));
+    ws.clean[cs] = clean ? 1 : 0;
+    ws.rep_stop[s * C + c] = (int)stop;
+    if (!clean && b < n) save_state<T, K>(ws, R, s, kSaveEnd2, c);
+    bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
+}
+
+// Sequential DP + backward of a whole chain with the deque in HBM.
+template <typename T, class Prob>
+__device__ void seg_full_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c) {
+    const auto src = Prob::src(pp, sp);
+    GlobalDeque<T> dq;
+    dq.init(ws.fb_lam + c * ws.fb_cap, ws.fb_tag + c * ws.fb_cap, ws.fb_cap);
+    T wprev = (T)0;
+    for (int64_t i = 0; i < sp.n; ++i) {
+        const auto pr = src.load(i);
+        const bool root = (i == sp.n - 1);
+        T lm = (T)0, lp = (T)0;
+        const T wi = src.weight(pr);
+        dp_step<T>(dq, (int)(i + 1), src.data(pr), wprev, root ? (T)0 : wi, root, lm, lp);
+        if (root) lp = lm;
+        put_lam<T>(ws.lam, i, ws.C, c, lm, lp);
+        wprev = wi;
+    }
+    const auto sink = Prob::sink(pp, sp);
+    T x = (T)0;
+    for (int64_t i = sp.n - 1; i >= 0; --i) {
+        const LamPair<T> p = ws.lam[i * ws.C + c];
+        const auto sv = sink.load(i);
+        x = (i == sp.n - 1) ? p.lo : clampv(x, p.lo, p.hi);
+        sink.store(i, x, sv);
+    }
+    for (int64_t s = 0; s * ws.L < sp.n; ++s) {
+        const int64_t b = (s + 1) * ws.L < sp.n ? (s + 1) * ws.L : sp.n;
+        ws.seg_unc[s * ws.C + c] = (int)b;
+    }
+}
+
+template <typename T, class Prob, int K, int P>
+__device__ void fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
+                          Ent<T> *s_ent, int lane);
+
+// ---------------------------------------------------------------------------
+// Fix-up, one lane per chain (a no-op for almost every chain).  Walks the
+// segments keeping track of whether the saved end state of the previous
+// segment is the true one; where it is not, the segment is redone
+// sequentially from the true state until a checkpoint matches and past the
+// region the repair kernel rewrote.
+// ---------------------------------------------------------------------------
+template <typename T, class Prob, int K, int P>
+__global__ __launch_bounds__(64) void k_seg_fix(SegWs<T> ws, typename Prob::Params pp) {
+    __shared__ Ent<T> s_ent[K * 64];
+    const int lane = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+    if (c >= ws.C) return;
+    const ChainSpan sp = Prob::span(pp, c, ws.n);
+    const int64_t n = sp.n;
+    if (n <= 0) return;
+    const int64_t Sc = (n + ws.L - 1) / ws.L;
+    const uint8_t *ovf = ws.ovf + c * ws.S;
+    const uint8_t *mis = ws.mis + c * ws.S;
+    const uint8_t *cln = ws.clean + c * ws.S;
+    bool any_ovf = false, any_dirty = false;
+    for (int64_t s = 0; s < Sc; ++s) {
+        any_ovf |= ovf[s] != 0;
+        if (s > 0 && s + 1 < Sc) any_dirty |= (mis[s] != 0) && (cln[s] == 0);
+    }
+    if (any_ovf) {
+        seg_full_chain<T, Prob>(ws, pp, sp, c);
+        return;
+    }
+    if (any_dirty) fix_chain<T, Prob, K, P>(ws, pp, sp, c, s_ent, lane);
+    // x entering each segment from the right: compose the segment maps from the
+    // root's segment leftwards (seg_lo/hi are final here)
+    T x = ws.seg_lo[(Sc - 1) * ws.C + c];
+#pragma unroll 4
+    for (int64_t j = Sc - 2; j >= 0; --j) {
+        ws.seg_xb[j * ws.C + c] = x;
+        x = clampv(x, ws.seg_lo[j * ws.C + c], ws.seg_hi[j * ws.C + c]);
+    }
+}
+
+template <typename T, class Prob, int K, int P>
+__device__ void fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
+                          Ent<T> *s_ent, int lane) {
+    const int64_t n = sp.n;
+    const int64_t Sc = (n + ws.L - 1) / ws.L;
+    const uint8_t *mis = ws.mis + c * ws.S;
+    const uint8_t *cln = ws.clean + c * ws.S;
+    const auto src = Prob::src(pp, sp);
+    CRing<T, K> R;
+    R.init(s_ent, lane);
+    const int64_t C = ws.C;
+    bool end_true = true, ok = true;
+    for (int64_t s = 1; s < Sc && ok; ++s) {
+        const int64_t a = s * ws.L;
+        const int64_t b = (a + ws.L < n) ? a + ws.L : n;
+        if (end_true) {
+            // the pass that wrote segment s started from the true state
+            if (mis[s] && !cln[s]) {
+                end_true = false;
+                if (b < n) load_state<T, K>(ws, R, s, kSaveEnd2, c);
+            }
+            continue;
+        }
+        // R holds the true deque entering segment s: redo it until it meets the
+        // first pass and is past whatever the repair kernel rewrote.
+        const int64_t redo_to = mis[s] ? (int64_t)ws.rep_stop[s * C + c] : a;
+        T wprev = src.weight(src.load(a - 1));
+        bool met = false;
+        const int64_t stop = fwd_run<T, Prob, K, P>(R, src, ok, wprev, a, a, b, n, ws.lam, C, c, [&](int64_t e) {
+            if (!ok) return true;
+            met = met || meets_checkpoint<T, K>(ws, R, s, c, a, e);
+            return met && e >= redo_to;
+        });
+        if (!ok) break;
+        if (stop == b && !met && b < n)
+            met = equals_state<T, K>(ws, R, s, kSaveEnd, c);
+        bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
+        end_true = met;
+    }
+    if (!ok) seg_full_chain<T, Prob>(ws, pp, sp, c);
+}
+
+// ---------------------------------------------------------------------------
+// Un-collapsed tails: x_i = clip(x_b, composed interval of i .. b-1).
+// ---------------------------------------------------------------------------
+template <typename T, class Prob>
+__global__ __launch_bounds__(64) void k_seg_tail(SegWs<T> ws, typename Prob::Params pp) {
+    const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (g >= (ws.S - 1) * ws.C) return;
+    const int64_t c = g % ws.C, s = g / ws.C;
+    const ChainSpan sp = Prob::span(pp, c, ws.n);
+    const int64_t n = sp.n;
+    const int64_t a = s * ws.L;
+    if (a + ws.L >= n) return;  // the root's segment always collapses
+    const int64_t b = a + ws.L;
+    const int64_t C = ws.C;
+    const int64_t u = ws.seg_unc[s * C + c];
+    if (u >= b) return;
+    const T x = ws.seg_xb[s * C + c];
+    const auto sink = Prob::sink(pp, sp);
+#pragma unroll 4
+    for (int64_t i = b - 1; i >= u; --i) {
+        const LamPair<T> p = ws.lam[i * C + c];
+        const auto sv = sink.load(i);
+        sink.store(i, clampv(x, p.lo, p.hi), sv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+template <typename T, int K>
+size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int64_t CK, SegWs<T> *out) {
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int64_t S = (n + L - 1) / L;
+    const int64_t cap = 2 * n + 4;
+    size_t off = 0;
+    const size_t o_lam = off;  off += al(sizeof(LamPair<T>) * (size_t)(n * C));
+    const size_t o_st = off;   off += al(sizeof(Ent<T>) * (size_t)(S * kSaves * K * C));
+    const size_t o_sz = off;   off += al(sizeof(int) * (size_t)(S * kSaves * C));
+    const size_t o_hs = off;   off += al(sizeof(uint32_t) * (size_t)(S * kSaves * C));
+    const size_t o_ovf = off;  off += al((size_t)(S * C));
+    const size_t o_mis = off;  off += al((size_t)(S * C));
+    const size_t o_cln = off;  off += al((size_t)(S * C));
+    const size_t o_rs = off;   off += al(sizeof(int) * (size_t)(S * C));
+    const size_t o_lo = off;   off += al(sizeof(T) * (size_t)(S * C));
+    const size_t o_hi = off;   off += al(sizeof(T) * (size_t)(S * C));
+    const size_t o_unc = off;  off += al(sizeof(int) * (size_t)(S * C));
+    const size_t o_xb = off;   off += al(sizeof(T) * (size_t)(S * C));
+    const size_t o_fl = off;   off += al(sizeof(T) * (size_t)(C * cap));
+    const size_t o_ft = off;   off += al(sizeof(int) * (size_t)(C * cap));
+    if (base && out) {
+        char *p = (char *)base;
+        SegWs<T> w;
+        w.C = C;
+        w.n = n;
+        w.L = L;
+        w.S = S;
+        w.H = H;
+        w.CK = CK;
+        w.lam = (LamPair<T> *)(p + o_lam);
+        w.st = (Ent<T> *)(p + o_st);
+        w.st_size = (int *)(p + o_sz);
+        w.st_hash = (uint32_t *)(p + o_hs);
+        w.ovf = (uint8_t *)(p + o_ovf);
+        w.mis = (uint8_t *)(p + o_mis);
+        w.clean = (uint8_t *)(p + o_cln);
+        w.rep_stop = (int *)(p + o_rs);
+        w.seg_lo = (T *)(p + o_lo);
+        w.seg_hi = (T *)(p + o_hi);
+        w.seg_unc = (int *)(p + o_unc);
+        w.seg_xb = (T *)(p + o_xb);
+        w.fb_lam = (T *)(p + o_fl);
+        w.fb_tag = (int *)(p + o_ft);
+        w.fb_cap = cap;
+        *out = w;
+    }
+    return off;
+}
+
+template <typename T, class Prob, int K, int P>
+hipError_t seg_launch(const SegWs<T> &ws, const typename Prob::Params &pp, hipStream_t stream) {
+    if (ws.C <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((ws.S * ws.C + 63) / 64);
+    hipLaunchKernelGGL((k_seg_main<T, Prob, K, P>), dim3(blocks), dim3(64), 0, stream, ws, pp);
+    if (ws.S > 1) {
+        const unsigned rb = (unsigned)(((ws.S - 1) * ws.C + 63) / 64);
+        hipLaunchKernelGGL((k_seg_repair<T, Prob, K, P>), dim3(rb), dim3(64), 0, stream, ws, pp);
+    }
+    const unsigned fb = (unsigned)((ws.C + 63) / 64);
+    hipLaunchKernelGGL((k_seg_fix<T, Prob, K, P>), dim3(fb), dim3(64), 0, stream, ws, pp);
+    if (ws.S > 1) {
+        const unsigned tb = (unsigned)(((ws.S - 1) * ws.C + 63) / 64);
+        hipLaunchKernelGGL((k_seg_tail<T, Prob>), dim3(tb), dim3(64), 0, stream, ws, pp);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tvc
