@@ -7,6 +7,7 @@ decomposition of 2D ROF, as hand-written HIP kernels for gfx950 behind the C
 ABI in ``include/tvchain.h``.  ``binding`` marshals torch tensors into that
 ABI; ``synth`` draws the seeded synthetic workloads.
 """
-from .binding import (TvChainError, chain_prox, chain_prox_backward, load, prox)  # noqa: F401
+from .binding import (Tv2dSolver, TvChainError, chain_prox, chain_prox_backward, load, prox,  # noqa: F401
+                      tv2d)
 
-__all__ = ["TvChainError", "chain_prox", "chain_prox_backward", "load", "prox"]
+__all__ = ["Tv2dSolver", "TvChainError", "chain_prox", "chain_prox_backward", "load", "prox", "tv2d"]

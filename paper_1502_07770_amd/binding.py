@@ -293,3 +293,66 @@ def prox(y: torch.Tensor, w: Union[float, torch.Tensor] = 0.0, dim: int = -1) ->
     if isinstance(w, torch.Tensor):
         return _ProxFn.apply(y, w, 0.0, dim)
     return _ProxFn.apply(y, None, float(w), dim)
+
+
+# ---------------------------------------------------------------------------
+# 2D ROF (tv2d_solve)
+# ---------------------------------------------------------------------------
+
+class Tv2dSolver:
+    """Owns the device workspace of one H x W problem so that solves can be
+    resumed (the workspace holds x, y, xbar and the schedule position)."""
+
+    def __init__(self, H: int, W: int, dtype=torch.float32, device="cuda"):
+        self.H, self.W = int(H), int(W)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.code = _dtype_code(torch.empty(0, dtype=dtype))
+        lib = load()
+        self.nbytes = int(lib.tv2d_workspace(self.H, self.W, self.code))
+        if self.nbytes == 0:
+            raise TvChainError(TV_ERR_INVALID_ARG, "tv2d_workspace")
+        self.ws = _workspace(self.nbytes, self.device)
+
+    def solve(self, f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10,
+              gap_tol: float = 0.0, tau0: float = 1.0, resume: bool = False,
+              gap_history: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
+        """Run the Sec. 5.1 decomposition.  Returns (x, stats dict).  With
+        gap_tol > 0 a solve that stops at max_iter above the tolerance raises
+        nothing: stats['status'] says TV_ERR_NOT_CONVERGED."""
+        _require_gpu(f)
+        if f.shape != (self.H, self.W) or f.dtype != self.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "f must be (%d, %d) %s" % (self.H, self.W, self.dtype))
+        if f.stride(1) != 1:
+            f = f.contiguous()
+        ld = f.stride(0)
+        x = out if out is not None else torch.empty((self.H, self.W), dtype=self.dtype, device=f.device)
+        if x.stride(1) != 1 or x.stride(0) != ld:
+            x = torch.empty_strided((self.H, self.W), (ld, 1), dtype=self.dtype, device=f.device)
+        hist_ptr = None
+        if gap_history is not None:
+            if gap_history.dtype != torch.float64 or not gap_history.is_cuda:
+                raise TvChainError(TV_ERR_INVALID_ARG, "gap_history must be a float64 GPU tensor")
+            hist_ptr = gap_history.data_ptr()
+        opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 1 if resume else 0, hist_ptr)
+        stats = Tv2dStats()
+        st = load().tv2d_solve(self.code, _ptr(f), self.H, self.W, ld, float(lam), _ptr(x), ctypes.byref(opt),
+                               ctypes.byref(stats), _ptr(self.ws), self.nbytes,
+                               ctypes.c_void_p(_stream_ptr(f.device)))
+        if st not in (TV_OK, TV_ERR_NOT_CONVERGED):
+            raise TvChainError(st, "tv2d_solve")
+        info = {"iters": stats.iters, "status": stats.status, "gap_norm": stats.gap_norm,
+                "primal": stats.primal, "dual": stats.dual}
+        if out is not None and x is not out:
+            out.copy_(x)
+            x = out
+        return x, info
+
+
+def tv2d(f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10, gap_tol: float = 0.0,
+         tau0: float = 1.0, gap_history: Optional[torch.Tensor] = None):
+    """2D ROF min_x lam (TV_h + TV_v)(x) + |x - f|^2 / 2 by the row/column chain
+    decomposition (Sec. 5.1).  Returns (x, stats)."""
+    s = Tv2dSolver(f.shape[0], f.shape[1], f.dtype, f.device)
+    return s.solve(f, lam, max_iter=max_iter, gap_every=gap_every, gap_tol=gap_tol, tau0=tau0,
+                   gap_history=gap_history)

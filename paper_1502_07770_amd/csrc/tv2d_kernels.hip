@@ -1,0 +1,514 @@
+// tv2d_kernels.hip -- 2D ROF by Lagrangian decomposition into row and column
+// chains (Sec. 5.1 of Kolmogorov, Pock, Rolinek, "Total variation on a tree").
+//
+//   min_x lambda (TV_h + TV_v)(x) + |x - f|^2 / 2,
+//   saddle problem  min_x max_y <x, y> + lambda TV_h(x) + |x - f|^2/2 - (lambda TV_v)^*(y)
+//   (eq. (rof-saddle)), solved by the accelerated primal-dual iteration eq. (pd):
+//     column step: eta = y + sigma_k xbar;  y' = eta - prox_{lambda TV_v}(eta)
+//                  (the dual prox through the Moreau identity, eq. (prox-tv-conj);
+//                  the scale sigma drops out because TV is positively 1-homogeneous)
+//     row step:    b = (tau_k f + x - tau_k y') / (1 + tau_k)
+//                  x' = prox_{(lambda tau_k / (1 + tau_k)) TV_h}(b)
+//                  (the primal prox with its quadratic weight 1 + 1/tau_k scaled to 1)
+//                  xbar' = x' + theta_k (x' - x)
+//   with theta_k = 1/sqrt(1 + 2 tau_k), tau_{k+1} = theta_k tau_k,
+//   sigma_k = 1 / tau_k (G is 1-strongly convex, tau sigma = 1).
+// Both steps are chain problems of eq. (1D-ROF) solved by the segmented exact
+// DP (seg_kernels.h); the elementwise work is fused into the chain kernels'
+// loads (data) and stores (epilogue).  x and y are double-buffered because the
+// chain kernels re-read their inputs (halo and repair passes) after other
+// segments have started writing outputs.
+//
+// Duality gap (FP64, every gap_every iterations).  Dual edge variables come
+// from the two chain solves: down each column p_v,e = -sum_{k<=e} y'_k and
+// along each row p_h,e = ((1 + tau)/tau) sum_{k<=e} (x'_k - b_k), both clipped
+// to [-lambda, lambda] and rounded toward zero when stored in the iterate
+// precision, so they are always feasible.  Then
+//   P = lambda TV_h(x') + lambda TV_v(x') + |x' - f|^2 / 2,
+//   D = |f|^2/2 - |f - D_h^T p_h - D_v^T p_v|^2 / 2,
+// and P - D >= P(x') - min P >= 0 (weak duality).  The sums use a fixed block
+// partition and tree reductions, so they are deterministic.
+#include <math.h>
+
+#include "../../include/tvchain.h"
+#include "kernels.h"
+#include "seg_kernels.h"
+
+namespace tvc {
+
+// b_i of the row step; shared by the row chain source and the gap kernel so
+// both see bit-identical values.
+template <typename T>
+__device__ __forceinline__ T row_data(T f, T x, T y, T tau, T inv1p) {
+    return (tau * f + x - tau * y) * inv1p;
+}
+
+// Column step: chains are the W columns of the dense H x W state (es = W).
+template <typename T>
+struct ColProb {
+    struct Params {
+        const T *y_old;
+        const T *xbar;
+        T *y_new;
+        T sigma;
+        T lam;
+        int64_t W;
+    };
+    struct Pre {
+        T y, xb;
+    };
+    struct SinkPre {
+        T y, xb;
+    };
+    struct Src {
+        const T *__restrict__ y;
+        const T *__restrict__ xb;
+        T sigma, lam;
+        int64_t c, W;
+        __device__ __forceinline__ Pre load(int64_t i) const {
+            Pre p;
+            p.y = y[i * W + c];
+            p.xb = xb[i * W + c];
+            return p;
+        }
+        __device__ __forceinline__ T data(const Pre &p) const { return p.y + sigma * p.xb; }
+        __device__ __forceinline__ T weight(const Pre &) const { return lam; }
+    };
+    struct Sink {
+        const T *__restrict__ y;
+        const T *__restrict__ xb;
+        T *__restrict__ yn;
+        T sigma;
+        int64_t c, W;
+        __device__ __forceinline__ SinkPre load(int64_t i) const {
+            SinkPre p;
+            p.y = y[i * W + c];
+            p.xb = xb[i * W + c];
+            return p;
+        }
+        __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
+            yn[i * W + c] = (p.y + sigma * p.xb) - u;
+        }
+    };
+    static __device__ __forceinline__ ChainSpan span(const Params &, int64_t c, int64_t nmax) {
+        return ChainSpan{c, 0, nmax};
+    }
+    static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
+        return Src{p.y_old, p.xbar, p.sigma, p.lam, sp.base, p.W};
+    }
+    static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
+        return Sink{p.y_old, p.xbar, p.y_new, p.sigma, sp.base, p.W};
+    }
+};
+
+// Row step: chains are the H rows (es = 1); f has its own leading dimension.
+template <typename T>
+struct RowProb {
+    struct Params {
+        const T *f;
+        int64_t ldf;
+        const T *x_old;
+        const T *y;
+        T *x_new;
+        T *xbar;
+        T tau, inv1p, theta, wrow;
+        int64_t W;
+    };
+    struct Pre {
+        T f, x, y;
+    };
+    struct SinkPre {
+        T x;
+    };
+    struct Src {
+        const T *__restrict__ f;
+        const T *__restrict__ x;
+        const T *__restrict__ y;
+        T tau, inv1p, w;
+        int64_t r, ldf, W;
+        __device__ __forceinline__ Pre load(int64_t i) const {
+            Pre p;
+            p.f = f[r * ldf + i];
+            p.x = x[r * W + i];
+            p.y = y[r * W + i];
+            return p;
+        }
+        __device__ __forceinline__ T data(const Pre &p) const { return row_data(p.f, p.x, p.y, tau, inv1p); }
+        __device__ __forceinline__ T weight(const Pre &) const { return w; }
+    };
+    struct Sink {
+        const T *__restrict__ x;
+        T *__restrict__ xn;
+        T *__restrict__ xb;
+        T theta;
+        int64_t r, W;
+        __device__ __forceinline__ SinkPre load(int64_t i) const { return SinkPre{x[r * W + i]}; }
+        __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
+            xn[r * W + i] = u;
+            xb[r * W + i] = u + theta * (u - p.x);
+        }
+    };
+    static __device__ __forceinline__ ChainSpan span(const Params &, int64_t r, int64_t nmax) {
+        return ChainSpan{r, 1, nmax};
+    }
+    static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
+        return Src{p.f, p.x_old, p.y, p.tau, p.inv1p, p.wrow, sp.base, p.ldf, p.W};
+    }
+    static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
+        return Sink{p.x_old, p.x_new, p.xbar, p.theta, sp.base, p.W};
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Gap kernels.
+// ---------------------------------------------------------------------------
+// Store a clipped dual value in precision T, rounded toward zero so that the
+// stored value still satisfies |p| <= lambda.
+template <typename T> __device__ __forceinline__ T store_feasible(double p);
+template <> __device__ __forceinline__ double store_feasible<double>(double p) { return p; }
+template <> __device__ __forceinline__ float store_feasible<float>(double p) { return __double2float_rz(p); }
+
+__device__ __forceinline__ double clipd(double v, double lam) { return v < -lam ? -lam : (v > lam ? lam : v); }
+
+// p_v down every column: p_v[r][c] = clip(-sum_{k<=r} y[k][c]), as a
+// two-phase segmented scan over row blocks of kGapRows rows; lanes are
+// consecutive columns, so every load is coalesced.
+constexpr int kGapRows = 64;
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_gap_colsum(const T *__restrict__ y, double *__restrict__ colpart, int64_t H,
+                                                   int64_t W) {
+    const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int64_t nseg = (H + kGapRows - 1) / kGapRows;
+    if (g >= nseg * W) return;
+    const int64_t c = g % W, sg = g / W;
+    const int64_t r0 = sg * kGapRows, r1 = (r0 + kGapRows < H) ? r0 + kGapRows : H;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int64_t r = r0; r < r1; ++r) acc += (double)y[r * W + c];
+    colpart[sg * W + c] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_gap_pv(const T *__restrict__ y, const double *__restrict__ colpart,
+                                               T *__restrict__ pv, int64_t H, int64_t W, double lam) {
+    const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int64_t nseg = (H + kGapRows - 1) / kGapRows;
+    if (g >= nseg * W) return;
+    const int64_t c = g % W, sg = g / W;
+    double cs = 0.0;
+    for (int64_t j = 0; j < sg; ++j) cs += colpart[j * W + c];
+    const int64_t r0 = sg * kGapRows, r1 = (r0 + kGapRows < H) ? r0 + kGapRows : H;
+#pragma unroll 8
+    for (int64_t r = r0; r < r1; ++r) {
+        cs += (double)y[r * W + c];
+        pv[r * W + c] = store_feasible<T>(clipd(-cs, lam));
+    }
+}
+
+// One wave per row, 64 columns per pass: the row's residual x' - b is
+// prefix-summed across the wave (FP64 shuffles) into p_h; every pixel adds its
+// primal terms and its dual term 1/2 f^2 - 1/2 (f - z)^2 with
+// z = (D_h^T p_h + D_v^T p_v) at that pixel.  Per-row sums go to part.
+constexpr int kGapBlock = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kGapBlock) void k_gap_rows(const T *__restrict__ f, int64_t ldf, const T *__restrict__ xn,
+                                                        const T *__restrict__ xo, const T *__restrict__ y,
+                                                        const T *__restrict__ pv, int64_t H, int64_t W, double lam,
+                                                        T tau, T inv1p, double pscale, double *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (kGapBlock / 64) + (threadIdx.x >> 6);
+    if (r >= H) return;  // whole waves exit together: no block barrier below
+    double P = 0.0, D = 0.0, carry = 0.0, ph_last = 0.0;
+    for (int64_t c0 = 0; c0 < W; c0 += 64) {
+        const int64_t c = c0 + lane;
+        const bool in = c < W;
+        const int64_t k = r * W + c;
+        T fv = 0, xv = 0, xo_v = 0, yv = 0, xr = 0, xd_ = 0, pvu = 0, pvd = 0;
+        if (in) {
+            fv = f[r * ldf + c];
+            xv = xn[k];
+            xo_v = xo[k];
+            yv = y[k];
+            if (c + 1 < W) xr = xn[k + 1];
+            if (r + 1 < H) {
+                xd_ = xn[k + W];
+                pvd = pv[k];
+            }
+            if (r > 0) pvu = pv[k - W];
+        }
+        const T b = row_data<T>(fv, xo_v, yv, tau, inv1p);
+        double res = (in && c + 1 < W) ? (double)xv - (double)b : 0.0;
+        // inclusive prefix over the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double t = __shfl_up(res, off, 64);
+            if (lane >= off) res += t;
+        }
+        const double cs = carry + res;
+        const double ph = (in && c + 1 < W) ? (double)store_feasible<T>(clipd(pscale * cs, lam)) : 0.0;
+        double ph_left = __shfl_up(ph, 1, 64);
+        if (lane == 0) ph_left = ph_last;
+        if (in) {
+            double z = ph_left - ph;
+            if (r > 0) z += (double)pvu;
+            if (r + 1 < H) z -= (double)pvd;
+            const double fd = (double)fv, xd = (double)xv;
+            P += 0.5 * (xd - fd) * (xd - fd);
+            if (c + 1 < W) P += lam * fabs((double)xr - xd);
+            if (r + 1 < H) P += lam * fabs((double)xd_ - xd);
+            D += 0.5 * fd * fd - 0.5 * (fd - z) * (fd - z);
+        }
+        carry = __shfl(cs, 63, 64);
+        ph_last = __shfl(ph, 63, 64);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        P += __shfl_down(P, off, 64);
+        D += __shfl_down(D, off, 64);
+    }
+    if (lane == 0) {
+        part[2 * r] = P;
+        part[2 * r + 1] = D;
+    }
+}
+
+// Final reduction (one block): out = {P, D, (P - D) / (H W)}; also the gap
+// history slot of this iteration.
+__global__ __launch_bounds__(kGapBlock) void k_gap_final(const double *__restrict__ part, int nparts, double HW,
+                                                         double *__restrict__ out, double *__restrict__ hist,
+                                                         int64_t hist_idx) {
+    __shared__ double sP[kGapBlock], sD[kGapBlock];
+    double P = 0.0, D = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kGapBlock) {
+        P += part[2 * i];
+        D += part[2 * i + 1];
+    }
+    sP[threadIdx.x] = P;
+    sD[threadIdx.x] = D;
+    __syncthreads();
+    for (int st = kGapBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sP[threadIdx.x] += sP[threadIdx.x + st];
+            sD[threadIdx.x] += sD[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double g = (sP[0] - sD[0]) / HW;
+        out[0] = sP[0];
+        out[1] = sD[0];
+        out[2] = g;
+        if (hist) hist[hist_idx] = g;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T *__restrict__ dst, int64_t n, T v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
+// Copy between a dense H x W buffer and a strided one (leading dimension ld).
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy2d(const T *__restrict__ src, int64_t lds, T *__restrict__ dst,
+                                                int64_t ldd, int64_t H, int64_t W) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= H * W) return;
+    const int64_t r = i / W, c = i % W;
+    dst[r * ldd + c] = src[r * lds + c];
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+struct Tv2dHeader {  // device-resident solver state header
+    int64_t iters;
+    int64_t cur;     // which x / y buffer holds the current iterate
+    double tau;
+    double pad;
+    double gap[3];   // P, D, gap_norm of the last evaluation
+};
+
+template <typename T>
+struct Tv2dWs {
+    Tv2dHeader *hdr;
+    T *x[2], *y[2], *xbar, *pv;
+    double *part;
+    double *colpart;
+    void *seg;       // chain-prox workspace, shared by the row and column launches
+    size_t seg_bytes;
+};
+
+template <typename T>
+static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out) {
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t N = (size_t)(H * W);
+    const SegPlan pr = seg_plan(H, W), pc = seg_plan(W, H);
+    const size_t sr = seg_ws_layout<T, kRingSlots>(nullptr, H, W, pr.L, pr.H, pr.CK, nullptr);
+    const size_t scol = seg_ws_layout<T, kRingSlots>(nullptr, W, H, pc.L, pc.H, pc.CK, nullptr);
+    const size_t nparts = (size_t)H;
+    const size_t ncol = (size_t)(((H + kGapRows - 1) / kGapRows) * W);
+    size_t off = 0;
+    const size_t o_hdr = off; off += al(sizeof(Tv2dHeader));
+    const size_t o_x0 = off;  off += al(sizeof(T) * N);
+    const size_t o_x1 = off;  off += al(sizeof(T) * N);
+    const size_t o_y0 = off;  off += al(sizeof(T) * N);
+    const size_t o_y1 = off;  off += al(sizeof(T) * N);
+    const size_t o_xb = off;  off += al(sizeof(T) * N);
+    const size_t o_pv = off;  off += al(sizeof(T) * N);
+    const size_t o_pt = off;  off += al(sizeof(double) * 2 * nparts);
+    const size_t o_cp = off;  off += al(sizeof(double) * ncol);
+    const size_t o_sg = off;  off += al(sr > scol ? sr : scol);
+    if (base && out) {
+        char *p = (char *)base;
+        out->hdr = (Tv2dHeader *)(p + o_hdr);
+        out->x[0] = (T *)(p + o_x0);
+        out->x[1] = (T *)(p + o_x1);
+        out->y[0] = (T *)(p + o_y0);
+        out->y[1] = (T *)(p + o_y1);
+        out->xbar = (T *)(p + o_xb);
+        out->pv = (T *)(p + o_pv);
+        out->part = (double *)(p + o_pt);
+        out->colpart = (double *)(p + o_cp);
+        out->seg = (void *)(p + o_sg);
+        out->seg_bytes = sr > scol ? sr : scol;
+    }
+    return off;
+}
+
+template <typename T>
+static hipError_t tv2d_iteration(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
+                                 int cur, double tau, bool gap, int64_t k, double *hist, hipStream_t st) {
+    const double theta = 1.0 / sqrt(1.0 + 2.0 * tau);
+    const double sigma = 1.0 / tau;
+    const int nxt = cur ^ 1;
+    // column step: y[nxt] = eta - prox(eta), eta = y[cur] + sigma xbar
+    {
+        const SegPlan pc = seg_plan(W, H);
+        SegWs<T> sw;
+        seg_ws_layout<T, kRingSlots>(ws.seg, W, H, pc.L, pc.H, pc.CK, &sw);
+        typename ColProb<T>::Params pp{ws.y[cur], ws.xbar, ws.y[nxt], (T)sigma, (T)lam, W};
+        hipError_t e = seg_launch<T, ColProb<T>, kRingSlots, kTile>(sw, pp, st);
+        if (e != hipSuccess) return e;
+    }
+    // row step: x[nxt] = prox(b), xbar = x[nxt] + theta (x[nxt] - x[cur])
+    const double inv1p = 1.0 / (1.0 + tau);
+    {
+        const SegPlan pr = seg_plan(H, W);
+        SegWs<T> sw;
+        seg_ws_layout<T, kRingSlots>(ws.seg, H, W, pr.L, pr.H, pr.CK, &sw);
+        typename RowProb<T>::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, (T)tau, (T)inv1p,
+                                       (T)theta, (T)(lam * tau * inv1p), W};
+        hipError_t e = seg_launch<T, RowProb<T>, kRingSlots, kTile>(sw, pp, st);
+        if (e != hipSuccess) return e;
+    }
+    if (gap) {
+        const int64_t nseg = (H + kGapRows - 1) / kGapRows;
+        const unsigned cb = (unsigned)((nseg * W + 63) / 64);
+        hipLaunchKernelGGL((k_gap_colsum<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, H, W);
+        hipLaunchKernelGGL((k_gap_pv<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, ws.pv, H, W, lam);
+        const unsigned rb = (unsigned)((H + kGapBlock / 64 - 1) / (kGapBlock / 64));
+        hipLaunchKernelGGL((k_gap_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, f, ldf, ws.x[nxt], ws.x[cur],
+                           ws.y[nxt], ws.pv, H, W, lam, (T)tau, (T)inv1p, (1.0 + tau) / tau, ws.part);
+        hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(kGapBlock), 0, st, ws.part, (int)H, (double)(H * W),
+                           &ws.hdr->gap[0], hist, k);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static tv_status tv2d_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, double lam, T *x,
+                              const tv2d_options *opt, tv2d_stats *stats, void *workspace, hipStream_t st) {
+    Tv2dWs<T> ws;
+    tv2d_layout<T>(workspace, H, W, &ws);
+    Tv2dHeader h{};
+    if (opt->resume) {
+        if (hipMemcpyAsync(&h, ws.hdr, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return TV_ERR_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
+    } else {
+        // x^0 = xbar^0 = f, y^0 = 0
+        const unsigned nb = (unsigned)((H * W + 255) / 256);
+        hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
+        hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
+        hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
+        h.iters = 0;
+        h.cur = 0;
+        h.tau = opt->tau0;
+        h.gap[0] = h.gap[1] = h.gap[2] = NAN;
+    }
+    const int every = opt->gap_every > 0 ? opt->gap_every : 1;
+    int status = TV_OK;
+    int done = 0;
+    double g3[3] = {h.gap[0], h.gap[1], h.gap[2]};
+    bool have_gap = !opt->resume ? false : !isnan(h.gap[2]);
+    while (done < opt->max_iter) {
+        const int chunk = (opt->max_iter - done < every) ? opt->max_iter - done : every;
+        for (int j = 0; j < chunk; ++j) {
+            const bool gap = (j == chunk - 1);
+            hipError_t e = tv2d_iteration<T>(ws, f, ld, H, W, lam, (int)h.cur, h.tau, gap, h.iters,
+                                             opt->gap_history, st);
+            if (e != hipSuccess) return TV_ERR_HIP;
+            const double theta = 1.0 / sqrt(1.0 + 2.0 * h.tau);
+            h.tau *= theta;
+            h.cur ^= 1;
+            ++h.iters;
+        }
+        done += chunk;
+        if (hipMemcpyAsync(g3, ws.hdr->gap, sizeof(g3), hipMemcpyDeviceToHost, st) != hipSuccess) return TV_ERR_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
+        have_gap = true;
+        if (!isfinite(g3[2])) {
+            status = TV_ERR_NONFINITE;
+            break;
+        }
+        if (opt->gap_tol > 0.0 && g3[2] <= opt->gap_tol) break;
+    }
+    if (status == TV_OK && opt->gap_tol > 0.0 && !(have_gap && g3[2] <= opt->gap_tol)) status = TV_ERR_NOT_CONVERGED;
+    h.gap[0] = g3[0];
+    h.gap[1] = g3[1];
+    h.gap[2] = g3[2];
+    if (hipMemcpyAsync(ws.hdr, &h, sizeof(h), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
+    const unsigned nb = (unsigned)((H * W + 255) / 256);
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, ws.x[h.cur], W, x, ld, H, W);
+    if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
+    if (stats) {
+        stats->iters = (int)h.iters;
+        stats->status = status;
+        stats->primal = g3[0];
+        stats->dual = g3[1];
+        stats->gap_norm = g3[2];
+    }
+    return (tv_status)status;
+}
+
+}  // namespace tvc
+
+using namespace tvc;
+
+extern "C" {
+
+size_t tv2d_workspace(int64_t H, int64_t W, tv_dtype dtype) {
+    if (H < 1 || W < 1 || (dtype != TV_F32 && dtype != TV_F64)) return 0;
+    return dtype == TV_F32 ? tv2d_layout<float>(nullptr, H, W, nullptr) : tv2d_layout<double>(nullptr, H, W, nullptr);
+}
+
+tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, void *x,
+                     const tv2d_options *options, tv2d_stats *stats, void *workspace, size_t workspace_bytes,
+                     hipStream_t stream) {
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (!f || !x || !options || H < 1 || W < 1 || ld < W) return TV_ERR_INVALID_ARG;
+    if (!(isfinite(lambda) && lambda >= 0.0)) return TV_ERR_INVALID_ARG;
+    if (options->max_iter < 0 || !(options->tau0 > 0.0) || !isfinite(options->tau0)) return TV_ERR_INVALID_ARG;
+    const int64_t lim = (dtype == TV_F32) ? (int64_t(1) << 24) : (int64_t(1) << 31) - 8;
+    if (H >= lim || W >= lim) return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < tv2d_workspace(H, W, dtype)) return TV_ERR_WORKSPACE;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
+    if (dtype == TV_F32)
+        return tv2d_solve_t<float>((const float *)f, H, W, ld, lambda, (float *)x, options, stats, workspace, stream);
+    return tv2d_solve_t<double>((const double *)f, H, W, ld, lambda, (double *)x, options, stats, workspace, stream);
+}
+
+}  // extern "C"
