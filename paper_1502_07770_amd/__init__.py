@@ -8,6 +8,7 @@ ABI in ``include/tvchain.h``.  ``binding`` marshals torch tensors into that
 ABI; ``synth`` draws the seeded synthetic workloads.
 """
 from .binding import (Tv2dSolver, TvChainError, chain_prox, chain_prox_backward, load, prox,  # noqa: F401
-                      tv2d)
+                      tv2d, tv2d_batched)
 
-__all__ = ["Tv2dSolver", "TvChainError", "chain_prox", "chain_prox_backward", "load", "prox", "tv2d"]
+__all__ = ["Tv2dSolver", "TvChainError", "chain_prox", "chain_prox_backward", "load", "prox", "tv2d",
+           "tv2d_batched"]

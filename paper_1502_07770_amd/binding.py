@@ -356,3 +356,47 @@ def tv2d(f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10, 
     s = Tv2dSolver(f.shape[0], f.shape[1], f.dtype, f.device)
     return s.solve(f, lam, max_iter=max_iter, gap_every=gap_every, gap_tol=gap_tol, tau0=tau0,
                    gap_history=gap_history)
+
+
+def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol: float = 0.0,
+                 tau0: float = 1.0, packed: Optional[torch.Tensor] = None):
+    """Solve many 2D ROF problems of different sizes in one call
+    (tv2d_solve_batched).  ``images`` is a list of (H_j, W_j) GPU tensors of one
+    dtype (or a list of shapes when ``packed`` holds them back to back);
+    ``lams`` the per-image weights.  Each image stops at its own gap_tol.
+    Returns (list of x_j views into one packed output, list of stats dicts)."""
+    if packed is None:
+        _require_gpu(*images)
+        dtype = images[0].dtype
+        shapes = [tuple(im.shape) for im in images]
+        packed = torch.cat([im.reshape(-1) for im in images]).contiguous()
+    else:
+        _require_gpu(packed)
+        dtype = packed.dtype
+        shapes = [tuple(s) for s in images]
+    n = len(shapes)
+    Hs = (ctypes.c_int64 * n)(*[s[0] for s in shapes])
+    Ws = (ctypes.c_int64 * n)(*[s[1] for s in shapes])
+    offs, o = [], 0
+    for s in shapes:
+        offs.append(o)
+        o += s[0] * s[1]
+    Os = (ctypes.c_int64 * n)(*offs)
+    Ls = (ctypes.c_double * n)(*[float(v) for v in lams])
+    code = _dtype_code(packed)
+    lib = load()
+    nbytes = int(lib.tv2d_batched_workspace(n, Hs, Ws, code))
+    if nbytes == 0:
+        raise TvChainError(TV_ERR_INVALID_ARG, "tv2d_batched_workspace")
+    ws = _workspace(nbytes, packed.device)
+    x = torch.empty_like(packed)
+    opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 0, None)
+    stats = (Tv2dStats * n)()
+    st = lib.tv2d_solve_batched(code, n, Hs, Ws, Os, Ls, _ptr(packed), _ptr(x), ctypes.byref(opt), stats, _ptr(ws),
+                                nbytes, ctypes.c_void_p(_stream_ptr(packed.device)))
+    if st not in (TV_OK, TV_ERR_NOT_CONVERGED):
+        raise TvChainError(st, "tv2d_solve_batched")
+    outs = [x[offs[j]:offs[j] + shapes[j][0] * shapes[j][1]].view(shapes[j]) for j in range(n)]
+    infos = [{"iters": s.iters, "status": s.status, "gap_norm": s.gap_norm, "primal": s.primal, "dual": s.dual}
+             for s in stats]
+    return outs, infos

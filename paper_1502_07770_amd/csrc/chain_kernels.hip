@@ -47,6 +47,7 @@ struct PlainProb {
     };
     static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t c, int64_t nmax) {
         ChainSpan sp;
+        sp.aux = 0;
         if (p.offsets) {
             const int64_t o0 = p.offsets[c], len = p.offsets[c + 1] - o0;
             sp.base = o0;

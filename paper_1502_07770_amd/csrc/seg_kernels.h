@@ -69,6 +69,8 @@ constexpr int kSaves = 3 + kCheckpoints;  // HS, CK..., ES, ES2
 constexpr int kScanWindow = 5;
 // Nodes the backward sweep loads ahead of their use.
 constexpr int kSweepTile = 16;
+// Lanes (each with a 2n + 4 entry HBM deque) for chains that overflow the ring.
+constexpr int64_t kOverflowLanes = 1024;
 constexpr int kSaveHalo = 0, kSaveCk = 1, kSaveEnd = 1 + kCheckpoints, kSaveEnd2 = 2 + kCheckpoints;
 
 template <typename T>
@@ -91,15 +93,19 @@ struct SegWs {
     T *seg_hi;
     int *seg_unc;       // [S][C] first node of the un-collapsed tail
     T *seg_xb;          // [S][C] x at the first node after the segment
-    T *fb_lam;          // [C][2n+4] HBM deques for overflowing chains
+    int *ovf_count;     // chains appended to ovf_list (zeroed by k_seg_main)
+    int *ovf_list;      // [C] chains whose deque outgrew the LDS ring
+    T *fb_lam;          // [fb_lanes][2n+4] HBM deques of the overflow kernel
     int *fb_tag;
     int64_t fb_cap;
+    int64_t fb_lanes;
 };
 
 struct ChainSpan {
     int64_t base;  // element of node 0
     int64_t es;    // element stride
     int64_t n;     // nodes
+    int64_t aux;   // problem-specific tag (e.g. the image of a batched chain)
 };
 
 template <typename T> __device__ __forceinline__ T pos_inf();
@@ -488,6 +494,7 @@ __global__ __launch_bounds__(64) void k_seg_main(SegWs<T> ws, typename Prob::Par
     __shared__ Ent<T> s_ent[K * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+    if (g == 0) *ws.ovf_count = 0;  // consumed by k_seg_fix / k_seg_ovf after this kernel
     if (g >= ws.S * ws.C) return;
     const int64_t c = g % ws.C, s = g / ws.C;
     const ChainSpan sp = Prob::span(pp, c, ws.n);
@@ -587,10 +594,11 @@ __global__ __launch_bounds__(64) void k_seg_repair(SegWs<T> ws, typename Prob::P
 
 // Sequential DP + backward of a whole chain with the deque in HBM.
 template <typename T, class Prob>
-__device__ void seg_full_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c) {
+__device__ void seg_full_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
+                               int64_t slot) {
     const auto src = Prob::src(pp, sp);
     GlobalDeque<T> dq;
-    dq.init(ws.fb_lam + c * ws.fb_cap, ws.fb_tag + c * ws.fb_cap, ws.fb_cap);
+    dq.init(ws.fb_lam + slot * ws.fb_cap, ws.fb_tag + slot * ws.fb_cap, ws.fb_cap);
     T wprev = (T)0;
     for (int64_t i = 0; i < sp.n; ++i) {
         const auto pr = src.load(i);
@@ -617,7 +625,7 @@ __device__ void seg_full_chain(const SegWs<T> &ws, const typename Prob::Params &
 }
 
 template <typename T, class Prob, int K, int P>
-__device__ void fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
+__device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
                           Ent<T> *s_ent, int lane);
 
 // ---------------------------------------------------------------------------
@@ -645,11 +653,10 @@ __global__ __launch_bounds__(64) void k_seg_fix(SegWs<T> ws, typename Prob::Para
         any_ovf |= ovf[s] != 0;
         if (s > 0 && s + 1 < Sc) any_dirty |= (mis[s] != 0) && (cln[s] == 0);
     }
-    if (any_ovf) {
-        seg_full_chain<T, Prob>(ws, pp, sp, c);
+    if (any_ovf || (any_dirty && !fix_chain<T, Prob, K, P>(ws, pp, sp, c, s_ent, lane))) {
+        ws.ovf_list[atomicAdd(ws.ovf_count, 1)] = (int)c;  // solved by k_seg_ovf
         return;
     }
-    if (any_dirty) fix_chain<T, Prob, K, P>(ws, pp, sp, c, s_ent, lane);
     // x entering each segment from the right: compose the segment maps from the
     // root's segment leftwards (seg_lo/hi are final here)
     T x = ws.seg_lo[(Sc - 1) * ws.C + c];
@@ -660,8 +667,10 @@ __global__ __launch_bounds__(64) void k_seg_fix(SegWs<T> ws, typename Prob::Para
     }
 }
 
+// Returns false if the true deque outgrew the ring (the chain then goes to
+// the HBM overflow kernel).
 template <typename T, class Prob, int K, int P>
-__device__ void fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
+__device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
                           Ent<T> *s_ent, int lane) {
     const int64_t n = sp.n;
     const int64_t Sc = (n + ws.L - 1) / ws.L;
@@ -699,7 +708,21 @@ __device__ void fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, c
         bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
         end_true = met;
     }
-    if (!ok) seg_full_chain<T, Prob>(ws, pp, sp, c);
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Overflowed chains, solved sequentially with the deque in HBM by a bounded
+// pool of lanes (lane l owns deque storage l).
+// ---------------------------------------------------------------------------
+template <typename T, class Prob>
+__global__ __launch_bounds__(64) void k_seg_ovf(SegWs<T> ws, typename Prob::Params pp) {
+    const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int64_t cnt = *ws.ovf_count;
+    for (int64_t j = l; j < cnt; j += ws.fb_lanes) {
+        const int64_t c = ws.ovf_list[j];
+        seg_full_chain<T, Prob>(ws, pp, Prob::span(pp, c, ws.n), c, l);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -749,8 +772,11 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
     const size_t o_hi = off;   off += al(sizeof(T) * (size_t)(S * C));
     const size_t o_unc = off;  off += al(sizeof(int) * (size_t)(S * C));
     const size_t o_xb = off;   off += al(sizeof(T) * (size_t)(S * C));
-    const size_t o_fl = off;   off += al(sizeof(T) * (size_t)(C * cap));
-    const size_t o_ft = off;   off += al(sizeof(int) * (size_t)(C * cap));
+    const int64_t fbl = (C < kOverflowLanes ? (C + 63) / 64 * 64 : kOverflowLanes);
+    const size_t o_oc = off;   off += al(sizeof(int));
+    const size_t o_ol = off;   off += al(sizeof(int) * (size_t)C);
+    const size_t o_fl = off;   off += al(sizeof(T) * (size_t)(fbl * cap));
+    const size_t o_ft = off;   off += al(sizeof(int) * (size_t)(fbl * cap));
     if (base && out) {
         char *p = (char *)base;
         SegWs<T> w;
@@ -772,9 +798,12 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
         w.seg_hi = (T *)(p + o_hi);
         w.seg_unc = (int *)(p + o_unc);
         w.seg_xb = (T *)(p + o_xb);
+        w.ovf_count = (int *)(p + o_oc);
+        w.ovf_list = (int *)(p + o_ol);
         w.fb_lam = (T *)(p + o_fl);
         w.fb_tag = (int *)(p + o_ft);
         w.fb_cap = cap;
+        w.fb_lanes = fbl;
         *out = w;
     }
     return off;
@@ -791,6 +820,7 @@ hipError_t seg_launch(const SegWs<T> &ws, const typename Prob::Params &pp, hipSt
     }
     const unsigned fb = (unsigned)((ws.C + 63) / 64);
     hipLaunchKernelGGL((k_seg_fix<T, Prob, K, P>), dim3(fb), dim3(64), 0, stream, ws, pp);
+    hipLaunchKernelGGL((k_seg_ovf<T, Prob>), dim3((unsigned)(ws.fb_lanes / 64)), dim3(64), 0, stream, ws, pp);
     if (ws.S > 1) {
         const unsigned tb = (unsigned)(((ws.S - 1) * ws.C + 63) / 64);
         hipLaunchKernelGGL((k_seg_tail<T, Prob>), dim3(tb), dim3(64), 0, stream, ws, pp);

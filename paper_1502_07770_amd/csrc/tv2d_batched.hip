@@ -1,0 +1,535 @@
+// tv2d_batched.hip -- many independent 2D ROF problems of different sizes in
+// one solve (the Sec. 5.1 row/column decomposition of every image at once).
+//
+// Every image's column chains run in one segmented chain launch and every
+// image's row chains in another.  Chains are listed longest first, so the 64
+// lanes of a wave hold chains of (nearly) equal length; the chains of one image
+// stay adjacent (its columns stay coalesced).  All images share the iteration
+// counter and step schedule (tau_k, sigma_k = 1/tau_k, theta_k); each has its
+// own lambda and its own FP64 duality gap, and an image whose gap reaches the
+// tolerance is frozen on the device: its chains and gap terms are skipped from
+// then on and its iterate stays in the buffer it was in.
+#include <math.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "../../include/tvchain.h"
+#include "kernels.h"
+#include "seg_kernels.h"
+#include "tv2d_common.h"
+
+namespace tvc {
+
+struct BChain {
+    int64_t base;  // pixel of node 0 (packed image storage)
+    int32_t n;     // nodes
+    int32_t es;    // element stride (1 for rows, W_j for columns)
+    int32_t img;
+    int32_t pad;
+};
+
+template <typename T>
+struct BColProb {
+    struct Params {
+        const BChain *desc;
+        const T *y_old;
+        const T *xbar;
+        T *y_new;
+        T sigma;
+        const double *lam;
+        const int *active;
+    };
+    struct Pre {
+        T y, xb;
+    };
+    struct SinkPre {
+        T y, xb;
+    };
+    struct Src {
+        const T *__restrict__ y;
+        const T *__restrict__ xb;
+        T sigma, lam;
+        int64_t base, es;
+        __device__ __forceinline__ Pre load(int64_t i) const {
+            Pre p;
+            p.y = y[base + i * es];
+            p.xb = xb[base + i * es];
+            return p;
+        }
+        __device__ __forceinline__ T data(const Pre &p) const { return p.y + sigma * p.xb; }
+        __device__ __forceinline__ T weight(const Pre &) const { return lam; }
+    };
+    struct Sink {
+        const T *__restrict__ y;
+        const T *__restrict__ xb;
+        T *__restrict__ yn;
+        T sigma;
+        int64_t base, es;
+        __device__ __forceinline__ SinkPre load(int64_t i) const {
+            SinkPre p;
+            p.y = y[base + i * es];
+            p.xb = xb[base + i * es];
+            return p;
+        }
+        __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
+            yn[base + i * es] = (p.y + sigma * p.xb) - u;
+        }
+    };
+    static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t c, int64_t) {
+        const BChain d = p.desc[c];
+        return ChainSpan{d.base, d.es, p.active[d.img] ? (int64_t)d.n : 0, d.img};
+    }
+    static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
+        return Src{p.y_old, p.xbar, p.sigma, (T)p.lam[sp.aux], sp.base, sp.es};
+    }
+    static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
+        return Sink{p.y_old, p.xbar, p.y_new, p.sigma, sp.base, sp.es};
+    }
+};
+
+template <typename T>
+struct BRowProb {
+    struct Params {
+        const BChain *desc;
+        const T *f;
+        const T *x_old;
+        const T *y;
+        T *x_new;
+        T *xbar;
+        T tau, inv1p, theta;
+        double tau_d, inv1p_d;
+        const double *lam;
+        const int *active;
+    };
+    struct Pre {
+        T f, x, y;
+    };
+    struct SinkPre {
+        T x;
+    };
+    struct Src {
+        const T *__restrict__ f;
+        const T *__restrict__ x;
+        const T *__restrict__ y;
+        T tau, inv1p, w;
+        int64_t base;
+        __device__ __forceinline__ Pre load(int64_t i) const {
+            Pre p;
+            p.f = f[base + i];
+            p.x = x[base + i];
+            p.y = y[base + i];
+            return p;
+        }
+        __device__ __forceinline__ T data(const Pre &p) const { return row_data(p.f, p.x, p.y, tau, inv1p); }
+        __device__ __forceinline__ T weight(const Pre &) const { return w; }
+    };
+    struct Sink {
+        const T *__restrict__ x;
+        T *__restrict__ xn;
+        T *__restrict__ xb;
+        T theta;
+        int64_t base;
+        __device__ __forceinline__ SinkPre load(int64_t i) const { return SinkPre{x[base + i]}; }
+        __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
+            xn[base + i] = u;
+            xb[base + i] = u + theta * (u - p.x);
+        }
+    };
+    static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t c, int64_t) {
+        const BChain d = p.desc[c];
+        return ChainSpan{d.base, 1, p.active[d.img] ? (int64_t)d.n : 0, d.img};
+    }
+    static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
+        return Src{p.f, p.x_old, p.y, p.tau, p.inv1p, (T)(p.lam[sp.aux] * p.tau_d * p.inv1p_d), sp.base};
+    }
+    static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
+        return Sink{p.x_old, p.x_new, p.xbar, p.theta, sp.base};
+    }
+};
+
+// Per-image geometry on the device.
+struct BImg {
+    int64_t off;       // first pixel
+    int64_t H, W;
+    int64_t row0;      // first row in the global row list
+};
+
+// p_v down every column of every active image (lane = column chain).
+template <typename T>
+__global__ __launch_bounds__(64) void k_bgap_pv(const BChain *__restrict__ cols, int64_t ncols,
+                                                const T *__restrict__ y, T *__restrict__ pv,
+                                                const double *__restrict__ lam, const int *__restrict__ active) {
+    const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (c >= ncols) return;
+    const BChain d = cols[c];
+    if (!active[d.img]) return;
+    const double lm = lam[d.img];
+    double cs = 0.0;
+#pragma unroll 8
+    for (int64_t r = 0; r + 1 < d.n; ++r) {
+        const int64_t k = d.base + r * d.es;
+        cs += (double)y[k];
+        pv[k] = store_feasible<T>(clipd(-cs, lm));
+    }
+}
+
+// One wave per row of every active image; as k_gap_rows of the single-image
+// solver, with the image's own geometry and lambda.
+template <typename T>
+__global__ __launch_bounds__(kGapBlock) void k_bgap_rows(const BImg *__restrict__ imgs, const int *__restrict__ rowimg,
+                                                         int64_t nrows, const T *__restrict__ f,
+                                                         const T *__restrict__ xn, const T *__restrict__ xo,
+                                                         const T *__restrict__ y, const T *__restrict__ pv,
+                                                         const double *__restrict__ lamv, const int *__restrict__ active,
+                                                         T tau, T inv1p, double pscale, double *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * (kGapBlock / 64) + (threadIdx.x >> 6);
+    if (t >= nrows) return;
+    const int j = rowimg[t];
+    if (!active[j]) return;
+    const BImg im = imgs[j];
+    const int64_t r = t - im.row0, H = im.H, W = im.W;
+    const double lam = lamv[j];
+    const T *fr = f + im.off, *xnr = xn + im.off, *xor_ = xo + im.off, *yr = y + im.off, *pvr = pv + im.off;
+    double P = 0.0, D = 0.0, carry = 0.0, ph_last = 0.0;
+    for (int64_t c0 = 0; c0 < W; c0 += 64) {
+        const int64_t c = c0 + lane;
+        const bool in = c < W;
+        const int64_t k = r * W + c;
+        T fv = 0, xv = 0, xo_v = 0, yv = 0, xr = 0, xd_ = 0, pvu = 0, pvd = 0;
+        if (in) {
+            fv = fr[k];
+            xv = xnr[k];
+            xo_v = xor_[k];
+            yv = yr[k];
+            if (c + 1 < W) xr = xnr[k + 1];
+            if (r + 1 < H) {
+                xd_ = xnr[k + W];
+                pvd = pvr[k];
+            }
+            if (r > 0) pvu = pvr[k - W];
+        }
+        const T b = row_data<T>(fv, xo_v, yv, tau, inv1p);
+        double res = (in && c + 1 < W) ? (double)xv - (double)b : 0.0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double tt = __shfl_up(res, off, 64);
+            if (lane >= off) res += tt;
+        }
+        const double cs = carry + res;
+        const double ph = (in && c + 1 < W) ? (double)store_feasible<T>(clipd(pscale * cs, lam)) : 0.0;
+        double ph_left = __shfl_up(ph, 1, 64);
+        if (lane == 0) ph_left = ph_last;
+        if (in) {
+            double z = ph_left - ph;
+            if (r > 0) z += (double)pvu;
+            if (r + 1 < H) z -= (double)pvd;
+            const double fd = (double)fv, xd = (double)xv;
+            P += 0.5 * (xd - fd) * (xd - fd);
+            if (c + 1 < W) P += lam * fabs((double)xr - xd);
+            if (r + 1 < H) P += lam * fabs((double)xd_ - xd);
+            D += 0.5 * fd * fd - 0.5 * (fd - z) * (fd - z);
+        }
+        carry = __shfl(cs, 63, 64);
+        ph_last = __shfl(ph, 63, 64);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        P += __shfl_down(P, off, 64);
+        D += __shfl_down(D, off, 64);
+    }
+    if (lane == 0) {
+        part[2 * t] = P;
+        part[2 * t + 1] = D;
+    }
+}
+
+// One block per image: reduce the image's rows, record the gap, freeze the
+// image once it is at the tolerance (its iterate is in buffer `nxt`).
+__global__ __launch_bounds__(kGapBlock) void k_bgap_final(const BImg *__restrict__ imgs, const double *__restrict__ part,
+                                                          int *__restrict__ active, int *__restrict__ buf,
+                                                          int *__restrict__ iters, double *__restrict__ gap3,
+                                                          double tol, int nxt, int iter_after) {
+    const int j = blockIdx.x;
+    if (!active[j]) return;  // uniform per block
+    const BImg im = imgs[j];
+    __shared__ double sP[kGapBlock], sD[kGapBlock];
+    double P = 0.0, D = 0.0;
+    for (int64_t r = threadIdx.x; r < im.H; r += kGapBlock) {
+        P += part[2 * (im.row0 + r)];
+        D += part[2 * (im.row0 + r) + 1];
+    }
+    sP[threadIdx.x] = P;
+    sD[threadIdx.x] = D;
+    __syncthreads();
+    for (int st = kGapBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sP[threadIdx.x] += sP[threadIdx.x + st];
+            sD[threadIdx.x] += sD[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double g = (sP[0] - sD[0]) / (double)(im.H * im.W);
+        gap3[3 * j] = sP[0];
+        gap3[3 * j + 1] = sD[0];
+        gap3[3 * j + 2] = g;
+        iters[j] = iter_after;
+        if (tol > 0.0 && g <= tol) {
+            active[j] = 0;
+            buf[j] = nxt;
+        }
+    }
+}
+
+// Copy each image's iterate (buffer buf[j], or `cur` if still active) out.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bcopy_out(const BImg *__restrict__ imgs, int nimg, const int *__restrict__ active,
+                                                   const int *__restrict__ buf, int cur, const T *__restrict__ x0,
+                                                   const T *__restrict__ x1, T *__restrict__ out, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    int lo = 0, hi = nimg - 1;  // image containing pixel i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (imgs[mid].off <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const int b = active[lo] ? cur : buf[lo];
+    out[i] = b ? x1[i] : x0[i];
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+struct BGeom {
+    int nimg;
+    int64_t total, nrows, ncols, maxH, maxW;
+};
+
+static bool batched_geom(int num_images, const int64_t *H, const int64_t *W, BGeom *g) {
+    if (num_images < 1 || !H || !W) return false;
+    g->nimg = num_images;
+    g->total = g->nrows = g->ncols = g->maxH = g->maxW = 0;
+    for (int j = 0; j < num_images; ++j) {
+        if (H[j] < 1 || W[j] < 1) return false;
+        g->total += H[j] * W[j];
+        g->nrows += H[j];
+        g->ncols += W[j];
+        g->maxH = H[j] > g->maxH ? H[j] : g->maxH;
+        g->maxW = W[j] > g->maxW ? W[j] : g->maxW;
+    }
+    return true;
+}
+
+template <typename T>
+struct BWs {
+    BImg *imgs;
+    BChain *rows, *cols;
+    int *rowimg, *active, *buf, *iters;
+    double *lam, *gap3, *part;
+    T *x[2], *y[2], *xbar, *pv;
+    void *seg;
+};
+
+template <typename T>
+static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const SegPlan pr = seg_plan(g.nrows, g.maxW), pc = seg_plan(g.ncols, g.maxH);
+    const size_t sr = seg_ws_layout<T, kRingSlots>(nullptr, g.nrows, g.maxW, pr.L, pr.H, pr.CK, nullptr);
+    const size_t scol = seg_ws_layout<T, kRingSlots>(nullptr, g.ncols, g.maxH, pc.L, pc.H, pc.CK, nullptr);
+    const size_t N = (size_t)g.total;
+    size_t off = 0;
+    const size_t o_im = off;  off += al(sizeof(BImg) * g.nimg);
+    const size_t o_rw = off;  off += al(sizeof(BChain) * (size_t)g.nrows);
+    const size_t o_cl = off;  off += al(sizeof(BChain) * (size_t)g.ncols);
+    const size_t o_ri = off;  off += al(sizeof(int) * (size_t)g.nrows);
+    const size_t o_ac = off;  off += al(sizeof(int) * g.nimg);
+    const size_t o_bf = off;  off += al(sizeof(int) * g.nimg);
+    const size_t o_it = off;  off += al(sizeof(int) * g.nimg);
+    const size_t o_lm = off;  off += al(sizeof(double) * g.nimg);
+    const size_t o_g3 = off;  off += al(sizeof(double) * 3 * g.nimg);
+    const size_t o_pt = off;  off += al(sizeof(double) * 2 * (size_t)g.nrows);
+    const size_t o_x0 = off;  off += al(sizeof(T) * N);
+    const size_t o_x1 = off;  off += al(sizeof(T) * N);
+    const size_t o_y0 = off;  off += al(sizeof(T) * N);
+    const size_t o_y1 = off;  off += al(sizeof(T) * N);
+    const size_t o_xb = off;  off += al(sizeof(T) * N);
+    const size_t o_pv = off;  off += al(sizeof(T) * N);
+    const size_t o_sg = off;  off += al(sr > scol ? sr : scol);
+    if (base && out) {
+        char *p = (char *)base;
+        out->imgs = (BImg *)(p + o_im);
+        out->rows = (BChain *)(p + o_rw);
+        out->cols = (BChain *)(p + o_cl);
+        out->rowimg = (int *)(p + o_ri);
+        out->active = (int *)(p + o_ac);
+        out->buf = (int *)(p + o_bf);
+        out->iters = (int *)(p + o_it);
+        out->lam = (double *)(p + o_lm);
+        out->gap3 = (double *)(p + o_g3);
+        out->part = (double *)(p + o_pt);
+        out->x[0] = (T *)(p + o_x0);
+        out->x[1] = (T *)(p + o_x1);
+        out->y[0] = (T *)(p + o_y0);
+        out->y[1] = (T *)(p + o_y1);
+        out->xbar = (T *)(p + o_xb);
+        out->pv = (T *)(p + o_pv);
+        out->seg = (void *)(p + o_sg);
+    }
+    return off;
+}
+
+template <typename T>
+static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
+                                 const double *lam, const T *f, T *x, const tv2d_options *opt, tv2d_stats *stats,
+                                 void *workspace, hipStream_t st) {
+    BWs<T> ws;
+    batched_layout<T>(workspace, g, &ws);
+    // geometry and chain lists (longest chains first; stable, so an image's
+    // chains stay adjacent and in order)
+    std::vector<BImg> imgs(g.nimg);
+    std::vector<int> rowimg((size_t)g.nrows);
+    std::vector<BChain> rows, cols;
+    rows.reserve((size_t)g.nrows);
+    cols.reserve((size_t)g.ncols);
+    int64_t r0 = 0;
+    for (int j = 0; j < g.nimg; ++j) {
+        imgs[j] = BImg{pix[j], H[j], W[j], r0};
+        for (int64_t r = 0; r < H[j]; ++r) {
+            rowimg[(size_t)(r0 + r)] = j;
+            rows.push_back(BChain{pix[j] + r * W[j], (int32_t)W[j], 1, j, 0});
+        }
+        for (int64_t c = 0; c < W[j]; ++c) cols.push_back(BChain{pix[j] + c, (int32_t)H[j], (int32_t)W[j], j, 0});
+        r0 += H[j];
+    }
+    auto longer = [](const BChain &a, const BChain &b) { return a.n > b.n; };
+    std::stable_sort(rows.begin(), rows.end(), longer);
+    std::stable_sort(cols.begin(), cols.end(), longer);
+    std::vector<int> ones(g.nimg, 1), zeros(g.nimg, 0);
+    hipError_t e = hipSuccess;
+    e = e ? e : hipMemcpyAsync(ws.imgs, imgs.data(), sizeof(BImg) * g.nimg, hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(ws.rows, rows.data(), sizeof(BChain) * rows.size(), hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(ws.cols, cols.data(), sizeof(BChain) * cols.size(), hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(ws.rowimg, rowimg.data(), sizeof(int) * rowimg.size(), hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(ws.lam, lam, sizeof(double) * g.nimg, hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(ws.active, ones.data(), sizeof(int) * g.nimg, hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(ws.buf, zeros.data(), sizeof(int) * g.nimg, hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(ws.iters, zeros.data(), sizeof(int) * g.nimg, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return TV_ERR_HIP;
+    // x^0 = xbar^0 = f, y^0 = 0 (packed storage, same offsets as f)
+    const unsigned nb = (unsigned)((g.total + 255) / 256);
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, g.total, ws.x[0], g.total, (int64_t)1, g.total);
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, g.total, ws.xbar, g.total, (int64_t)1, g.total);
+    hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], g.total, (T)0);
+    std::vector<double> gap3(3 * (size_t)g.nimg, NAN);
+    std::vector<int> active(g.nimg, 1), iters(g.nimg, 0);
+    const int every = opt->gap_every > 0 ? opt->gap_every : 1;
+    double tau = opt->tau0;
+    int cur = 0, k = 0;
+    int n_active = g.nimg;
+    const SegPlan pr = seg_plan(g.nrows, g.maxW), pc = seg_plan(g.ncols, g.maxH);
+    while (k < opt->max_iter && n_active > 0) {
+        const int chunk = (opt->max_iter - k < every) ? opt->max_iter - k : every;
+        for (int jj = 0; jj < chunk; ++jj, ++k) {
+            const double theta = 1.0 / sqrt(1.0 + 2.0 * tau), sigma = 1.0 / tau, inv1p = 1.0 / (1.0 + tau);
+            const int nxt = cur ^ 1;
+            SegWs<T> sw;
+            seg_ws_layout<T, kRingSlots>(ws.seg, g.ncols, g.maxH, pc.L, pc.H, pc.CK, &sw);
+            typename BColProb<T>::Params cp{ws.cols, ws.y[cur], ws.xbar, ws.y[nxt], (T)sigma, ws.lam, ws.active};
+            if (seg_launch<T, BColProb<T>, kRingSlots, kTile>(sw, cp, st) != hipSuccess) return TV_ERR_HIP;
+            seg_ws_layout<T, kRingSlots>(ws.seg, g.nrows, g.maxW, pr.L, pr.H, pr.CK, &sw);
+            typename BRowProb<T>::Params rp{ws.rows, f, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, (T)tau, (T)inv1p,
+                                            (T)theta, tau, inv1p, ws.lam, ws.active};
+            if (seg_launch<T, BRowProb<T>, kRingSlots, kTile>(sw, rp, st) != hipSuccess) return TV_ERR_HIP;
+            if (jj == chunk - 1) {
+                const unsigned cb = (unsigned)((g.ncols + 63) / 64);
+                hipLaunchKernelGGL((k_bgap_pv<T>), dim3(cb), dim3(64), 0, st, ws.cols, g.ncols, ws.y[nxt], ws.pv,
+                                   ws.lam, ws.active);
+                const unsigned rb = (unsigned)((g.nrows + kGapBlock / 64 - 1) / (kGapBlock / 64));
+                hipLaunchKernelGGL((k_bgap_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, ws.imgs, ws.rowimg, g.nrows, f,
+                                   ws.x[nxt], ws.x[cur], ws.y[nxt], ws.pv, ws.lam, ws.active, (T)tau, (T)inv1p,
+                                   (1.0 + tau) / tau, ws.part);
+                hipLaunchKernelGGL(k_bgap_final, dim3(g.nimg), dim3(kGapBlock), 0, st, ws.imgs, ws.part, ws.active,
+                                   ws.buf, ws.iters, ws.gap3, opt->gap_tol, nxt, k + 1);
+            }
+            if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
+            tau *= theta;
+            cur = nxt;
+        }
+        if (hipMemcpyAsync(active.data(), ws.active, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st) != hipSuccess)
+            return TV_ERR_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
+        n_active = 0;
+        for (int j = 0; j < g.nimg; ++j) n_active += active[j];
+    }
+    hipLaunchKernelGGL((k_bcopy_out<T>), dim3(nb), dim3(256), 0, st, ws.imgs, g.nimg, ws.active, ws.buf, cur, ws.x[0],
+                       ws.x[1], x, g.total);
+    e = hipMemcpyAsync(gap3.data(), ws.gap3, sizeof(double) * 3 * g.nimg, hipMemcpyDeviceToHost, st);
+    e = e ? e : hipMemcpyAsync(iters.data(), ws.iters, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st);
+    e = e ? e : hipMemcpyAsync(active.data(), ws.active, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st);
+    e = e ? e : hipStreamSynchronize(st);
+    if (e != hipSuccess) return TV_ERR_HIP;
+    tv_status worst = TV_OK;
+    for (int j = 0; j < g.nimg; ++j) {
+        int s = TV_OK;
+        if (!isfinite(gap3[3 * j + 2])) s = TV_ERR_NONFINITE;
+        else if (opt->gap_tol > 0.0 && active[j]) s = TV_ERR_NOT_CONVERGED;
+        if (stats) {
+            stats[j].iters = iters[j];
+            stats[j].status = s;
+            stats[j].primal = gap3[3 * j];
+            stats[j].dual = gap3[3 * j + 1];
+            stats[j].gap_norm = gap3[3 * j + 2];
+        }
+        if (s == TV_ERR_NONFINITE) worst = TV_ERR_NONFINITE;
+        else if (s == TV_ERR_NOT_CONVERGED && worst == TV_OK) worst = TV_ERR_NOT_CONVERGED;
+    }
+    return worst;
+}
+
+}  // namespace tvc
+
+using namespace tvc;
+
+extern "C" {
+
+size_t tv2d_batched_workspace(int num_images, const int64_t *H, const int64_t *W, tv_dtype dtype) {
+    BGeom g;
+    if ((dtype != TV_F32 && dtype != TV_F64) || !batched_geom(num_images, H, W, &g)) return 0;
+    return dtype == TV_F32 ? batched_layout<float>(nullptr, g, nullptr) : batched_layout<double>(nullptr, g, nullptr);
+}
+
+tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
+                             const int64_t *pixel_offsets, const double *lambda, const void *f, void *x,
+                             const tv2d_options *options, tv2d_stats *stats, void *workspace, size_t workspace_bytes,
+                             hipStream_t stream) {
+    BGeom g;
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (!batched_geom(num_images, H, W, &g) || !pixel_offsets || !lambda || !f || !x || !options)
+        return TV_ERR_INVALID_ARG;
+    if (options->max_iter < 0 || !(options->tau0 > 0.0) || !isfinite(options->tau0) || options->resume)
+        return TV_ERR_INVALID_ARG;
+    const int64_t lim = (dtype == TV_F32) ? (int64_t(1) << 24) : (int64_t(1) << 31) - 8;
+    if (g.maxH >= lim || g.maxW >= lim || g.nrows >= (int64_t(1) << 31) || g.ncols >= (int64_t(1) << 31))
+        return TV_ERR_INVALID_ARG;
+    // images must be packed back to back in order
+    int64_t expect = 0;
+    for (int j = 0; j < num_images; ++j) {
+        if (pixel_offsets[j] != expect) return TV_ERR_INVALID_ARG;
+        if (!(isfinite(lambda[j]) && lambda[j] >= 0.0)) return TV_ERR_INVALID_ARG;
+        expect += H[j] * W[j];
+    }
+    if (!workspace || workspace_bytes < tv2d_batched_workspace(num_images, H, W, dtype)) return TV_ERR_WORKSPACE;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
+    if (dtype == TV_F32)
+        return batched_solve_t<float>(g, H, W, pixel_offsets, lambda, (const float *)f, (float *)x, options, stats,
+                                      workspace, stream);
+    return batched_solve_t<double>(g, H, W, pixel_offsets, lambda, (const double *)f, (double *)x, options, stats,
+                                   workspace, stream);
+}
+
+}  // extern "C"

@@ -33,15 +33,9 @@
 #include "../../include/tvchain.h"
 #include "kernels.h"
 #include "seg_kernels.h"
+#include "tv2d_common.h"
 
 namespace tvc {
-
-// b_i of the row step; shared by the row chain source and the gap kernel so
-// both see bit-identical values.
-template <typename T>
-__device__ __forceinline__ T row_data(T f, T x, T y, T tau, T inv1p) {
-    return (tau * f + x - tau * y) * inv1p;
-}
 
 // Column step: chains are the W columns of the dense H x W state (es = W).
 template <typename T>
@@ -91,7 +85,7 @@ struct ColProb {
         }
     };
     static __device__ __forceinline__ ChainSpan span(const Params &, int64_t c, int64_t nmax) {
-        return ChainSpan{c, 0, nmax};
+        return ChainSpan{c, 0, nmax, 0};
     }
     static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
         return Src{p.y_old, p.xbar, p.sigma, p.lam, sp.base, p.W};
@@ -149,7 +143,7 @@ struct RowProb {
         }
     };
     static __device__ __forceinline__ ChainSpan span(const Params &, int64_t r, int64_t nmax) {
-        return ChainSpan{r, 1, nmax};
+        return ChainSpan{r, 1, nmax, 0};
     }
     static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
         return Src{p.f, p.x_old, p.y, p.tau, p.inv1p, p.wrow, sp.base, p.ldf, p.W};
@@ -162,14 +156,6 @@ struct RowProb {
 // ---------------------------------------------------------------------------
 // Gap kernels.
 // ---------------------------------------------------------------------------
-// Store a clipped dual value in precision T, rounded toward zero so that the
-// stored value still satisfies |p| <= lambda.
-template <typename T> __device__ __forceinline__ T store_feasible(double p);
-template <> __device__ __forceinline__ double store_feasible<double>(double p) { return p; }
-template <> __device__ __forceinline__ float store_feasible<float>(double p) { return __double2float_rz(p); }
-
-__device__ __forceinline__ double clipd(double v, double lam) { return v < -lam ? -lam : (v > lam ? lam : v); }
-
 // p_v down every column: p_v[r][c] = clip(-sum_{k<=r} y[k][c]), as a
 // two-phase segmented scan over row blocks of kGapRows rows; lanes are
 // consecutive columns, so every load is coalesced.
@@ -210,7 +196,6 @@ __global__ __launch_bounds__(64) void k_gap_pv(const T *__restrict__ y, const do
 // prefix-summed across the wave (FP64 shuffles) into p_h; every pixel adds its
 // primal terms and its dual term 1/2 f^2 - 1/2 (f - z)^2 with
 // z = (D_h^T p_h + D_v^T p_v) at that pixel.  Per-row sums go to part.
-constexpr int kGapBlock = 256;
 
 template <typename T>
 __global__ __launch_bounds__(kGapBlock) void k_gap_rows(const T *__restrict__ f, int64_t ldf, const T *__restrict__ xn,
@@ -302,22 +287,6 @@ __global__ __launch_bounds__(kGapBlock) void k_gap_final(const double *__restric
         out[2] = g;
         if (hist) hist[hist_idx] = g;
     }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_fill(T *__restrict__ dst, int64_t n, T v) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) dst[i] = v;
-}
-
-// Copy between a dense H x W buffer and a strided one (leading dimension ld).
-template <typename T>
-__global__ __launch_bounds__(256) void k_copy2d(const T *__restrict__ src, int64_t lds, T *__restrict__ dst,
-                                                int64_t ldd, int64_t H, int64_t W) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= H * W) return;
-    const int64_t r = i / W, c = i % W;
-    dst[r * ldd + c] = src[r * lds + c];
 }
 
 // ---------------------------------------------------------------------------

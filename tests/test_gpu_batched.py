@@ -1,0 +1,66 @@
+"""GPU tests of the batched uneven 2D solver (tv2d_solve_batched).
+
+Each image of a batch follows exactly the single-image iteration (same
+schedule, same per-pixel arithmetic; chain results do not depend on how the
+chains are segmented or ordered), so batched and single-image results must be
+bit-identical, also when images stop at their own duality-gap tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1502_07770_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(num, lo, hi, seed):
+    specs = synth.uneven_batch_specs(num, side_lo=lo, side_hi=hi, seed=seed)
+    imgs = [synth.shapes_image(s["H"], s["W"], sigma=s["sigma"], seed=s["seed"]) for s in specs]
+    return specs, imgs
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_equals_single_fixed_iterations(dtype):
+    specs, imgs = _batch(12, 1, 160, seed=1)
+    ts = [torch.tensor(im, dtype=dtype, device="cuda") for im in imgs]
+    lams = [s["lam"] for s in specs]
+    xs, infos = binding.tv2d_batched(ts, lams, max_iter=30, gap_every=10)
+    for t, lam, xb, ib in zip(ts, lams, xs, infos):
+        x1, i1 = binding.tv2d(t, lam, max_iter=30, gap_every=10)
+        assert torch.equal(xb, x1)
+        assert ib["iters"] == 30 and ib["gap_norm"] == i1["gap_norm"]
+
+
+def test_batched_fp64_matches_oracle():
+    specs, imgs = _batch(6, 8, 90, seed=2)
+    ts = [torch.tensor(im, dtype=torch.float64, device="cuda") for im in imgs]
+    xs, infos = binding.tv2d_batched(ts, [s["lam"] for s in specs], max_iter=40, gap_every=40)
+    for im, s, xb, ib in zip(imgs, specs, xs, infos):
+        xo, ho, (Po, Do, go), _ = oracle.tv2d(im, s["lam"], max_iter=40)
+        assert np.abs(xb.cpu().numpy() - xo).max() <= 1e-9 * max(np.ptp(im), 1e-12)
+        assert abs(ib["gap_norm"] - go) <= 1e-6 * abs(go) + 1e-14
+
+
+def test_batched_per_image_stopping():
+    specs, imgs = _batch(10, 32, 200, seed=3)
+    ts = [torch.tensor(im, dtype=torch.float32, device="cuda") for im in imgs]
+    lams = [s["lam"] for s in specs]
+    xs, infos = binding.tv2d_batched(ts, lams, max_iter=500, gap_every=5, gap_tol=1e-4)
+    iters = [i["iters"] for i in infos]
+    assert len(set(iters)) > 1                                   # images stop at different times
+    for t, lam, xb, ib in zip(ts, lams, xs, infos):
+        assert ib["status"] == binding.TV_OK and ib["gap_norm"] <= 1e-4
+        x1, i1 = binding.tv2d(t, lam, max_iter=500, gap_every=5, gap_tol=1e-4)
+        assert i1["iters"] == ib["iters"]
+        assert torch.equal(xb, x1)
+
+
+def test_batched_not_converged_and_rejections():
+    specs, imgs = _batch(3, 16, 40, seed=4)
+    ts = [torch.tensor(im, dtype=torch.float32, device="cuda") for im in imgs]
+    xs, infos = binding.tv2d_batched(ts, [0.1] * 3, max_iter=2, gap_every=1, gap_tol=1e-12)
+    assert all(i["status"] == binding.TV_ERR_NOT_CONVERGED for i in infos)
+    with pytest.raises(binding.TvChainError):
+        binding.tv2d_batched(ts, [0.1, -1.0, 0.1], max_iter=2)
