@@ -1,26 +1,33 @@
 #!/usr/bin/env python3
-"""Benchmark of the batched exact TV-chain prox on one MI355X.
+"""Benchmark of the batched exact TV-chain prox (and the 2D ROF solvers) on one MI355X.
 
-Workload (one "step"): the 4096 x 4096 FP32 shapes-plus-noise image
+Headline workload (one "step"): the 4096 x 4096 FP32 shapes-plus-noise image
 (30 rectangles/disks, intensities U[0,1], noise sigma 0.1, seed 3); the exact
 chain prox (w = 0.1) of all 4096 row chains and all 4096 column chains of
 length 4096, i.e. 33,554,432 chain nodes.  Inputs are resident in HBM before
-timing starts.  The reported value is Gelem/s = nodes / time.
+timing starts.  value = Gelem/s = nodes / time.
 
-Also reported on the same JSON line:
-  roofline     -- the chain-prox launch's algorithmic bytes (8 B/node: y read,
-                  x written) over its own event-timed duration, against the
-                  8 TB/s HBM peak; traffic from committed rocprofv3 counters when
-                  they match the current kernel source, else null.
+Also on the same JSON line:
+  roofline     -- one tv_chain_prox call (its kernels: k_seg_main, k_seg_repair,
+                  k_seg_fix, k_seg_ovf, k_seg_tail) timed with HIP events;
+                  algorithmic bytes 8 B/node (y read, x written) / duration vs the
+                  8 TB/s HBM peak; traffic from the committed rocprofv3
+                  FETCH_SIZE/WRITE_SIZE summary when it was taken on the current
+                  kernel sources, else null.
   cpu_baseline -- the FP64 C oracle on the host cores, same workload.
-  extras       -- 2D ROF time-to-gap (FP32 vs FP64) and the adjoint, when built.
+  extras       -- 2D ROF time-to-gap 1e-4 in FP32 vs FP64 (512^2 and 4096^2),
+                  200 iterations at 512^2, forward+backward of 65,536 chains of
+                  1,024 with per-edge weights, and a batch of 256 uneven images.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+       python bench.py --rocprof-summary DIR   (print a summary of rocprofv3 output)
+       python bench.py --copy-calibration      (a plain copy of known size, for counters)
 """
 from __future__ import annotations
 
 import argparse
 import ctypes
+import glob
 import hashlib
 import json
 import os
@@ -36,7 +43,8 @@ HBM_PEAK_GBS = 8000.0
 SIDE = 4096
 W_CHAIN = 0.1
 SEED = 3
-KERNEL_SOURCES = ["paper_1502_07770_amd/csrc/chain_core.h", "paper_1502_07770_amd/csrc/chain_kernels.hip"]
+KERNEL_SOURCES = ["paper_1502_07770_amd/csrc/chain_core.h", "paper_1502_07770_amd/csrc/seg_kernels.h",
+                  "paper_1502_07770_amd/csrc/chain_kernels.hip", "paper_1502_07770_amd/csrc/api_chain.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chain_prox_4096_traffic.json")
 
 
@@ -53,8 +61,8 @@ def log(*a):
 
 
 def committed_traffic():
-    """HBM bytes per launch from the committed rocprofv3 FETCH/WRITE counter
-    summary, only if it was taken on the current kernel source."""
+    """HBM bytes per tv_chain_prox call (4096x4096 rows or columns) from the
+    committed counter summary, only if taken on the current kernel sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -63,6 +71,23 @@ def committed_traffic():
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+class Timer:
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def __call__(self, fn, reps):
+        torch = self.torch
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(self.stream)
+        for _ in range(reps):
+            fn()
+        b.record(self.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
 
 
 def bench_chain(steps: int, warmup: int):
@@ -115,11 +140,11 @@ def bench_chain(steps: int, warmup: int):
     col_ms = [b.elapsed_time(c) for _, b, c in ev]
     nodes = 2 * SIDE * SIDE
     ms_step = total_ms / steps
-    gelem = nodes / (ms_step * 1e-3) / 1e9
-    # sanity: finite output
     assert torch.isfinite(xr).all() and torch.isfinite(xc).all()
-    return dict(ms_per_step=ms_step, gelem=gelem, row_ms=float(np.mean(row_ms)), col_ms=float(np.mean(col_ms)),
-                row_ms_min=float(np.min(row_ms)), col_ms_min=float(np.min(col_ms)), nodes=nodes, img=img)
+    return dict(ms_per_step=ms_step, gelem=nodes / (ms_step * 1e-3) / 1e9, row_ms=float(np.mean(row_ms)),
+                col_ms=float(np.mean(col_ms)), nodes=nodes, img=img,
+                segment_length=int(lib.tv_chain_prox_segment_length(ctypes.byref(rows))),
+                tuning=binding.get_tuning())
 
 
 def cpu_baseline(img):
@@ -136,9 +161,132 @@ def cpu_baseline(img):
         times.append(time.perf_counter() - t)
     dt = float(np.median(times))
     nodes = 2 * y.size
-    return {"value": nodes / dt / 1e9, "unit": "Gelem/s", "cores": threads, "kind": "oracle",
+    return {"value": round(nodes / dt / 1e9, 4), "unit": "Gelem/s", "cores": threads, "kind": "oracle",
             "sample": "full workload: 4096 row + 4096 column chains of 4096 (FP64 C oracle, OpenMP over "
-                      "chains), median of 3 runs of %.2f s" % dt}
+                      "chains), median of 3 runs of %.3f s" % dt}
+
+
+def bench_tv2d(side: int, seed: int, iters_fixed: int | None, tol: float, max_iter: int):
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    img = synth.shapes_image(side, side, seed=seed)
+    out = {"image": "%dx%d shapes+noise sigma 0.1, lambda 0.1" % (side, side)}
+    for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        f = torch.tensor(img, dtype=dt, device="cuda")
+        s = binding.Tv2dSolver(side, side, dt)
+        s.solve(f, 0.1, max_iter=2, gap_every=1)  # warm-up
+        torch.cuda.synchronize()
+        r = {}
+        if iters_fixed:
+            t = time.perf_counter()
+            _, info = s.solve(f, 0.1, max_iter=iters_fixed, gap_every=10)
+            r["ms_%d_iters" % iters_fixed] = round((time.perf_counter() - t) * 1e3, 3)
+            r["gap_after_%d" % iters_fixed] = info["gap_norm"]
+        t = time.perf_counter()
+        _, info = s.solve(f, 0.1, max_iter=max_iter, gap_every=5, gap_tol=tol)
+        r["time_to_gap_ms"] = round((time.perf_counter() - t) * 1e3, 3)
+        r["iters_to_gap"] = info["iters"]
+        r["gap"] = info["gap_norm"]
+        r["reached"] = info["status"] == binding.TV_OK
+        out[name] = r
+    return out
+
+
+def bench_adjoint(steps: int):
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    C, n = 65536, 1024
+    y = torch.tensor(synth.piecewise_constant(C, n, seed=5), dtype=torch.float32, device="cuda")
+    w = torch.tensor(synth.edge_weights((C, n), seed=6), dtype=torch.float32, device="cuda")
+    g = torch.tensor(synth.normal((C, n), seed=7), dtype=torch.float32, device="cuda")
+    tm = Timer(torch, torch.cuda.current_stream())
+    fwd = lambda: binding.chain_prox(y, w, dim=-1)  # noqa: E731
+    x = fwd()
+    bwd = lambda: binding.chain_prox_backward(x, g, dim=-1, per_edge_w=True)  # noqa: E731
+    fwd(); bwd()
+    f_ms = tm(fwd, steps)
+    b_ms = tm(bwd, steps)
+    nodes = C * n
+    return {"workload": "65536 chains x 1024, per-edge w ~ U[0.1,1], FP32",
+            "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3),
+            "fwd_gelem_s": round(nodes / f_ms / 1e6, 2), "bwd_gelem_s": round(nodes / b_ms / 1e6, 2),
+            "fwd_bwd_gelem_s": round(nodes / (f_ms + b_ms) / 1e6, 2),
+            "fwd_hbm_frac": round(nodes * 12 / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bwd_hbm_frac": round(nodes * 16 / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def bench_batched():
+    import numpy as np
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    t = time.perf_counter()
+    specs = synth.uneven_batch_specs(256, seed=11)
+    packed = np.concatenate([synth.shapes_image(s["H"], s["W"], sigma=s["sigma"], seed=s["seed"]).ravel()
+                             .astype(np.float32) for s in specs])
+    gen_s = time.perf_counter() - t
+    f = torch.from_numpy(packed).cuda()
+    shapes = [(s["H"], s["W"]) for s in specs]
+    lams = [s["lam"] for s in specs]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    xs, infos = binding.tv2d_batched(shapes, lams, max_iter=2000, gap_every=10, gap_tol=1e-4, packed=f)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    iters = [i["iters"] for i in infos]
+    return {"workload": "256 images, H,W ~ U{64..2048}, lambda ~ U[0.02,0.3], sigma ~ U[0.05,0.2], FP32",
+            "pixels": int(packed.size), "time_to_gap_ms": round(dt * 1e3, 1),
+            "all_reached": all(i["status"] == binding.TV_OK for i in infos),
+            "iters_min": min(iters), "iters_max": max(iters), "generate_s": round(gen_s, 1)}
+
+
+def rocprof_summary(d):
+    """Print per-kernel call counts and average durations from rocprofv3 output
+    (kernel_stats CSV or the results database) and, if counter CSVs are present,
+    per-dispatch FETCH_SIZE / WRITE_SIZE."""
+    import csv
+    import sqlite3
+    stats = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
+    if stats:
+        with open(stats[0]) as fh:
+            rows = list(csv.DictReader(fh))
+        print("kernel stats (%s):" % os.path.relpath(stats[0], d))
+        for r in rows[:15]:
+            print("  %-60s calls=%-6s avg_us=%.1f" % (r["Name"].split("(")[0][:60], r["Calls"],
+                                                       float(r["AverageNs"]) / 1e3))
+    dbs = sorted(glob.glob(os.path.join(d, "**", "*results.db"), recursive=True))
+    if dbs and not stats:
+        con = sqlite3.connect(dbs[0])
+        print("kernel stats (%s):" % os.path.relpath(dbs[0], d))
+        call_us = 0.0
+        for name, calls, total, avg in con.execute(
+                "select name, total_calls, total_duration, average from top_kernels limit 15"):
+            short = name.split("(")[0].replace("void ", "")
+            print("  %-60s calls=%-6d total_us=%-10.1f avg_us=%.1f" % (short[:60], calls, total, avg))
+            if short.startswith("tvc::k_seg_"):
+                call_us += avg
+        if call_us:
+            print("  tv_chain_prox call (sum of the k_seg_* averages): %.1f us" % call_us)
+    for cnt in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(cnt) as fh:
+            rows = list(csv.DictReader(fh))
+        agg = {}
+        for r in rows:
+            key = (r["Kernel_Name"].split("(")[0][:60], r["Counter_Name"])
+            agg.setdefault(key, []).append(float(r["Counter_Value"]))
+        print("counters (%s):" % os.path.relpath(cnt, d))
+        for (k, c), v in sorted(agg.items()):
+            print("  %-60s %-12s dispatches=%-4d mean=%.1f" % (k, c, len(v), sum(v) / len(v)))
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB (reads 1 GiB, writes 1 GiB)."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4}))
 
 
 def main():
@@ -148,16 +296,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--rocprof-summary", metavar="DIR")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.rocprof_summary:
+        rocprof_summary(args.rocprof_summary)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the chains of this workload are independent and this "
-              "build runs on a single MI355X (run with --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU only: this build runs on a single MI355X and the chains of the "
+              "workload are independent (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
     from paper_1502_07770_amd import binding
     if not os.path.exists(binding.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     log("bench: chain prox 4096x4096 rows+cols, steps=%d warmup=%d" % (args.steps, args.warmup))
     r = bench_chain(args.steps, args.warmup)
@@ -165,7 +321,7 @@ def main():
         r["ms_per_step"], r["gelem"], r["row_ms"], r["col_ms"]))
     launch_nodes = SIDE * SIDE
     alg_bytes = 8.0 * launch_nodes
-    dom_ms = max(r["row_ms"], r["col_ms"])
+    dom_ms = 0.5 * (r["row_ms"] + r["col_ms"])  # average tv_chain_prox call (rows and columns alternate)
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     traffic = committed_traffic()
     out = {
@@ -187,6 +343,8 @@ def main():
             "nodes_per_step": r["nodes"],
             "row_launch_ms": round(r["row_ms"], 4),
             "col_launch_ms": round(r["col_ms"], 4),
+            "segment_length": r["segment_length"],
+            "tuning": r["tuning"],
         },
         "hbm_pct": round(100.0 * r["gelem"] * 8.0 / HBM_PEAK_GBS, 2),
         "roofline": {
@@ -196,14 +354,28 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_chain_prox_lds (+ overflow fallback launch), %s chains" % (
-                "row" if r["row_ms"] >= r["col_ms"] else "column"),
+            "kernel": "one tv_chain_prox call (k_seg_main, k_seg_repair, k_seg_fix, k_seg_ovf, k_seg_tail), "
+                      "averaged over the row and column calls",
             "alg_bytes_per_launch": alg_bytes,
         },
     }
     if not args.no_cpu:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(r["img"])
+    if not args.no_extras:
+        extras = {}
+        try:
+            log("bench: 2D 512x512")
+            extras["tv2d_512"] = bench_tv2d(512, 11, 200, 1e-4, 2000)
+            log("bench: 2D 4096x4096")
+            extras["tv2d_4096"] = bench_tv2d(4096, SEED, None, 1e-4, 500)
+            log("bench: adjoint 65536x1024")
+            extras["adjoint"] = bench_adjoint(5)
+            log("bench: batched 256 images")
+            extras["batched"] = bench_batched()
+        except Exception as e:  # report what finished
+            extras["error"] = repr(e)
+        out["extras"] = extras
     print(json.dumps(out), flush=True)
 
 
