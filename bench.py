@@ -278,6 +278,43 @@ def rocprof_summary(d):
             print("  %-60s %-12s dispatches=%-4d mean=%.1f" % (k, c, len(v), sum(v) / len(v)))
 
 
+def _counter_means(d, counter):
+    import csv
+    out = {}
+    for cnt in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(cnt) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    out.setdefault(r["Kernel_Name"].split("(")[0].replace("void ", ""), []).append(
+                        float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in out.items()}
+
+
+def traffic_from_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """HBM bytes of one tv_chain_prox call from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch, averaged over the row and column calls), each scaled by what the
+    counter reads for a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB)."""
+    gib = float(1 << 30)
+    cf = _counter_means(copy_fetch_dir, "FETCH_SIZE")
+    cw = _counter_means(copy_write_dir, "WRITE_SIZE")
+    copy_k = [k for k in cf if "copyBuffer" in k][0]
+    f_scale = gib / (cf[copy_k] * 1024.0)
+    w_scale = gib / (cw[copy_k] * 1024.0)
+    fe = {k: v for k, v in _counter_means(fetch_dir, "FETCH_SIZE").items() if k.startswith("tvc::k_seg_")}
+    wr = {k: v for k, v in _counter_means(write_dir, "WRITE_SIZE").items() if k.startswith("tvc::k_seg_")}
+    fetch_b = sum(fe.values()) * 1024.0 * f_scale
+    write_b = sum(wr.values()) * 1024.0 * w_scale
+    rec = {"workload": "tv_chain_prox, 4096 chains of 4096 (rows or columns), FP32, w = 0.1",
+           "kernel_source_hash": kernel_source_hash(),
+           "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+           "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
+           "bytes_per_launch": round(fetch_b + write_b),
+           "alg_bytes_per_launch": 8 * SIDE * SIDE,
+           "per_kernel_fetch_kib": {k: round(v, 1) for k, v in fe.items()},
+           "per_kernel_write_kib": {k: round(v, 1) for k, v in wr.items()}}
+    return rec
+
+
 def copy_calibration():
     """A plain device-to-device copy of 1 GiB (reads 1 GiB, writes 1 GiB)."""
     import torch
@@ -298,7 +335,15 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--rocprof-summary", metavar="DIR")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="rocprofv3 --pmc output folders; writes the traffic record read by the roofline")
     args = ap.parse_args()
+    if args.traffic_from:
+        rec = traffic_from_counters(*args.traffic_from)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec, indent=1))
+        return
     if args.rocprof_summary:
         rocprof_summary(args.rocprof_summary)
         return
