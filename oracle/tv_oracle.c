@@ -69,7 +69,7 @@ int orc_chain_dp(int64_t n, const double *a, const double *b,
 
     for (int64_t i = 0; i < n; ++i) {
         const int root = (i == n - 1);
-        /* Algorithm 2, line 0: the root gets a virtual parent edge with
+        /* Algorithm 2 gives the root a virtual parent edge with
            w^- = w^+ = 0, so its interval collapses to the zero of \hat m. */
         const double lo = root ? 0.0 : wm[i];
         const double hi = root ? 0.0 : wp[i];
@@ -181,7 +181,7 @@ int orc_chain_dp(int64_t n, const double *a, const double *b,
         wp_prev = hi;
     }
 
-    /* Backward pass (Algorithm 2, lines 7-9): x_i = clip(x_{i+1}, lam^-_i, lam^+_i). */
+    /* Backward pass of Algorithm 2: x_i = clip(x_{i+1}, lam^-_i, lam^+_i). */
     for (int64_t i = n - 2; i >= 0; --i) {
         double v = x[i + 1];
         if (v < lam_lo[i]) v = lam_lo[i];

@@ -267,7 +267,7 @@ __device__ __forceinline__ bool run_chain(DQ &dq, int64_t n, Src &src, Sink &sin
         }
         wprev = wi;
     }
-    // Backward pass (Algorithm 2, lines 7-9): x_i = clip(x_{i+1}, lam^-_i, lam^+_i).
+    // Backward pass of Algorithm 2: x_i = clip(x_{i+1}, lam^-_i, lam^+_i).
     T x = xroot;
     sink.emit(n - 1, x);
     int64_t i = n - 2;

@@ -15,7 +15,7 @@
 //               early (the halo), streams lambda^-/lambda^+ for its own nodes,
 //               and saves its deque after the halo (HS), at two checkpoints
 //               inside the segment (CK1, CK2) and at its end (ES).  It then
-//               runs the backward clip pass (Algorithm 2, lines 7-9) over its
+//               runs the backward clip pass of Algorithm 2 over its
 //               own nodes: composing x_i = clip(x_{i+1}, lam^-_i, lam^+_i) from
 //               the right, the composed map is a clip onto an interval, and once
 //               that interval is a single point every node left of it is
