@@ -31,9 +31,11 @@ template <typename T> __device__ __forceinline__ T recip(T v);
 template <> __device__ __forceinline__ float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double recip<double>(double v) { return 1.0 / v; }
 
-template <typename T> __device__ __forceinline__ T clampv(T v, T lo, T hi) {
-    return v < lo ? lo : (v > hi ? hi : v);
-}
+// Clip of v to [lo, hi] for lo <= hi (every call site guarantees the order:
+// brackets of sorted breakpoints, and lambda^- <= lambda^+).  FP32 uses the
+// median-of-three instruction (one VALU op, no NaN canonicalisation).
+__device__ __forceinline__ float clampv(float v, float lo, float hi) { return __builtin_amdgcn_fmed3f(v, lo, hi); }
+__device__ __forceinline__ double clampv(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Per-lane ring of K entries in LDS.  lam/tag point at this lane's column:
 // slot j lives at lam[j * LANES].

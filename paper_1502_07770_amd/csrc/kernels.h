@@ -9,7 +9,10 @@ namespace tvc {
 // Breakpoint slots of the per-lane LDS ring.  The deepest deque seen on the
 // piecewise-constant / shapes workloads is ~15 breakpoints; chains that go
 // deeper are solved with their deque in HBM.
-constexpr int kRingSlots = 32;
+#ifndef TVC_RING_SLOTS
+#define TVC_RING_SLOTS 16
+#endif
+constexpr int kRingSlots = TVC_RING_SLOTS;
 // Nodes per register tile: loads run this many nodes ahead of their use.
 constexpr int kTile = 8;
 

@@ -66,7 +66,10 @@ template <typename T> __device__ __forceinline__ Ent<T> mk_ent(T l, T k) {
 constexpr int kCheckpoints = 4;  // first-pass deques saved every CK nodes after a segment start
 constexpr int kSaves = 3 + kCheckpoints;  // HS, CK..., ES, ES2
 // Breakpoints examined branch-free at each end of the deque per step.
-constexpr int kScanWindow = 5;
+#ifndef TVC_SCAN_WINDOW
+#define TVC_SCAN_WINDOW 5
+#endif
+constexpr int kScanWindow = TVC_SCAN_WINDOW;
 // Nodes the backward sweep loads ahead of their use.
 constexpr int kSweepTile = 16;
 // Lanes (each with a 2n + 4 entry HBM deque) for chains that overflow the ring.
@@ -128,11 +131,17 @@ template <typename T, int K>
 __device__ __forceinline__ bool saved_equal(const CRing<T, K> &R, const Ent<T> *src, int64_t stride);
 
 // ---------------------------------------------------------------------------
-// LDS ring with register-cached ends.
+// LDS ring of K entries per lane with register-cached ends.  Every entry is
+// stored twice, at slot m and at slot m + K, so the first W and the last W
+// entries of the deque lie at fixed offsets from one base address each: the
+// hot step needs no per-read index arithmetic and never wraps.  Slots are
+// lane-interleaved (slot m of lane l at m * 64 + l), so the 64 lanes of a
+// wave hit distinct banks.
 // ---------------------------------------------------------------------------
 template <typename T, int K>
 struct CRing {
-    Ent<T> *col;  // this lane's column: slot j at col[j * 64]
+    static_assert((K & (K - 1)) == 0, "ring size must be a power of two");
+    Ent<T> *col;  // this lane's column: slot m at col[m * 64], its copy at col[(m + K) * 64]
     int head, size;
     Ent<T> f, b;  // front / back copies (valid when size >= 1)
 
@@ -141,8 +150,12 @@ struct CRing {
         head = 0;
         size = 0;
     }
-    __device__ __forceinline__ Ent<T> &at(int j) const { return col[((head + j) & (K - 1)) * 64]; }
     __device__ __forceinline__ Ent<T> ld(int j) const { return col[((head + j) & (K - 1)) * 64]; }
+    __device__ __forceinline__ void put_slot(int m, const Ent<T> &e) const {
+        col[m * 64] = e;
+        col[(m + K) * 64] = e;
+    }
+    __device__ __forceinline__ void set(int j, const Ent<T> &e) const { put_slot((head + j) & (K - 1), e); }
     // Order-sensitive 32-bit hash of the breakpoints and tags (the back tag is
     // excluded); a filter only: equality is always confirmed entry by entry.
     __device__ __forceinline__ uint32_t hash() const {
@@ -162,10 +175,10 @@ struct CRing {
     __device__ __forceinline__ void load(const Ent<T> *src, const int *szsrc, int64_t stride) {
         head = 0;
         size = clamp_size<K>(*szsrc);
-        for (int j = 0; j < size; ++j) col[j * 64] = src[j * stride];
+        for (int j = 0; j < size; ++j) put_slot(j, src[j * stride]);
         if (size > 0) {
-            f = col[0];
-            b = col[(size - 1) * 64];
+            f = src[0];
+            b = src[(size - 1) * stride];
         }
     }
     // Same breakpoints and tags (the back entry's tag is never read).  Size
@@ -198,63 +211,53 @@ __device__ __forceinline__ bool saved_equal(const CRing<T, K> &R, const Ent<T> *
     return eq;
 }
 
-// One DP step on a CRing: the same arithmetic as dp_step in chain_core.h, in a
-// branch-free form.  The message values at the first W and the last W
-// breakpoints are formed up front (all LDS reads issued together); the pop
-// count of each end is the number of leading values beyond the threshold (the
-// values are non-decreasing, also in floating point), and the bracketing
-// segment is picked with selects.  Only an end that needs more than W pops
-// (about 3 in 1000 steps on the workloads here) falls back to a loop.  This
-// keeps a wave's 64 lanes in step: a divergent pop loop costs the slowest
-// lane's pop count (about 4 per end per node) instead of the mean (1).
+// One DP step (Sec. 4.1 with a_i = 1) on a CRing, branch-free except for the
+// rare long scans.  s = i + 1 is the number of unaries added so far, so the
+// true slope of a segment with birth tag k is s - k; the segments beyond
+// either end have slope 1.  The message values at the first W and the last W
+// breakpoints are formed up front; the pop count of each end is the number of
+// leading values beyond the threshold (non-decreasing, also in floating
+// point), and the bracketing segment is picked with selects.  An end needing
+// more than W pops falls back to a loop.  An empty deque (the first node of a
+// run) is handled by selects on the same path; its LDS reads are in bounds and
+// their values unused.  The root step is the same step with w = 0 (its deque
+// update is never used).  Returns false if the deque would outgrow the ring;
+// the ring then keeps running on clamped sizes and the caller discards it.
 template <typename T, int K, int W>
-__device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, int s, T yi, T wprev, T w, bool root, T &lm,
-                                            T &lp) {
+__device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, T sf, T yi, T wprev, T w, T &lm, T &lp) {
+    static_assert(W >= 2 && W <= K, "scan window");
     const T lo = -w, hi = w;
-    const T sf = (T)s;
     const int t = R.size;
-    if (t == 0) {
-        lm = yi + lo;
-        lp = yi + hi;
-        if (root) return true;
-        R.head = 0;
-        R.size = 2;
-        R.f = mk_ent<T>(lm, sf - (T)1);
-        R.b = mk_ent<T>(lp, (T)0);
-        R.col[0] = R.f;
-        R.col[64] = R.b;
-        return true;
-    }
+    const int h = R.head;
+    const Ent<T> *fp = R.col + h * 64;                          // logical 0 .. W-1
+    const Ent<T> *bp = R.col + ((h + t - W) & (K - 1)) * 64;    // logical t-W .. t-1
     Ent<T> F[W], B[W];
     F[0] = R.f;
     B[0] = R.b;
 #pragma unroll
     for (int j = 1; j < W; ++j) {
-        F[j] = R.ld(j);
-        B[j] = R.ld(t - 1 - j);
+        F[j] = fp[j * 64];
+        B[j] = bp[(W - 1 - j) * 64];
     }
-    // ---- left end: pops p = #{j : v_j < lo}, v_0 = m(lam_1) ----
+    // ---- left end: pops p = #{j < t : v_j < lo}, v_0 = message at lam_1 ----
     T v[W];
     v[0] = F[0].l - wprev - yi;
 #pragma unroll
     for (int j = 1; j < W; ++j) v[j] = v[j - 1] + (sf - F[j - 1].k) * (F[j].l - F[j - 1].l);
     int p = 0;
-    T ck = F[0].k, cl = F[0].l, nl = F[0].l, vc = v[0];
+    T vc = v[0];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         const bool c = (j < t) & (v[j] < lo);
         p = c ? j + 1 : p;
-        cl = c ? F[j].l : cl;
-        ck = c ? F[j].k : ck;
         vc = c ? v[j] : vc;
-        nl = c ? F[j + 1 < W ? j + 1 : W - 1].l : nl;
     }
     if (p == W && t > W) {  // rare: keep popping one breakpoint at a time
+        T cl = F[W - 1].l, ck = F[W - 1].k;
         for (;;) {
             if (p == t) break;
             const Ent<T> nx = R.ld(p);
             const T vn = vc + (sf - ck) * (nx.l - cl);
-            nl = nx.l;
             if (vn >= lo) break;
             vc = vn;
             cl = nx.l;
@@ -262,72 +265,79 @@ __device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, int s, T yi, T wprev
             ++p;
         }
     }
+    // the bracket [lam_p, lam_{p+1}] (logical p - 1 and p) is re-read from the
+    // ring rather than selected from the window: two loads instead of 3W selects
+    const Ent<T> *pb = R.col + ((h + p - 1) & (K - 1)) * 64;
+    const Ent<T> ea = pb[0], eb = pb[64];
+    const T cl = ea.l, ck = ea.k, nl = eb.l;
+    const bool empty = (t == 0);
+    const T rl = recip(sf - ck);
     {
-        const T lm_gen = clampv(cl + (lo - vc) * recip(sf - ck), cl, nl);
+        const T lm_gen = clampv(cl + (lo - vc) * rl, cl, nl);
         const T lm_all = cl + (lo - vc);          // beyond every breakpoint (slope 1)
         const T lm_none = F[0].l - (v[0] - lo);  // before the first breakpoint (slope 1)
         lm = (p == 0) ? lm_none : ((p == t) ? lm_all : lm_gen);
+        lm = empty ? yi + lo : lm;
     }
     const T tnew = (p == 0 || p == t) ? sf - (T)1 : ck;
-    if (root) return true;
-    if (p == 0 && t >= K) return false;
     // pop p, push lm at the front
-    R.head = (R.head + p + K - 1) & (K - 1);
+    const int h1 = (h + p - 1) & (K - 1);
     const int t1 = t - p + 1;
-    R.f = mk_ent<T>(lm, tnew);
-    R.col[R.head * 64] = R.f;
-    if (t1 == 1) {
-        // every old breakpoint was popped: the segment right of lm has slope 1
-        lp = lm + (hi - lo);
-        R.b = mk_ent<T>(lp, (T)0);
-        R.col[((R.head + 1) & (K - 1)) * 64] = R.b;
-        R.size = 2;
-        return true;
-    }
-    // ---- right end over the t - p old breakpoints left (never pops lm) ----
+    const Ent<T> fnew = mk_ent<T>(lm, tnew);
+    R.put_slot(h1, fnew);
+    // ---- right end over the qmax = t - p old breakpoints left (never pops lm) ----
     const int qmax = t1 - 1;
     T u[W];
     u[0] = B[0].l + wprev - yi;
 #pragma unroll
     for (int j = 1; j < W; ++j) u[j] = u[j - 1] - (sf - B[j].k) * (B[j - 1].l - B[j].l);
     int q = 0;
-    T rk = B[0].k, rcl = B[0].l, rnl = B[0].l, uc = u[0];
+    T uc = u[0];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         const bool c = (j < qmax) & (u[j] > hi);
         q = c ? j + 1 : q;
-        rcl = c ? B[j].l : rcl;
         uc = c ? u[j] : uc;
-        rnl = c ? B[j + 1 < W ? j + 1 : W - 1].l : rnl;
-        rk = c ? B[j + 1 < W ? j + 1 : W - 1].k : rk;
     }
     if (q == W && qmax > W) {  // rare: keep popping from the back
+        T rcl = B[W - 1].l;
         for (;;) {
             if (q == qmax) break;
-            const Ent<T> nx = R.ld(t1 - 1 - q);
+            const Ent<T> nx = R.ld(t - 1 - q);
             const T up = uc - (sf - nx.k) * (rcl - nx.l);
-            rnl = nx.l;
-            rk = nx.k;
             if (up <= hi) break;
             uc = up;
             rcl = nx.l;
             ++q;
         }
     }
+    // bracket: logical t - 1 - q (left end, its tag) and t - q (right end);
+    // only read where q < qmax, i.e. never the slot the front push just wrote
+    const Ent<T> *qb = R.col + ((h + t - 1 - q) & (K - 1)) * 64;
+    const Ent<T> ra = qb[0], rb = qb[64];
+    const T rnl = ra.l, rk = ra.k, rcl = rb.l;
     {
         const T lp_gen = clampv(rcl - (uc - hi) * recip(sf - rk), rnl, rcl);
-        T lp_lm = lm + (hi - lo) * recip(sf - tnew);  // popped down to lm (lm's segment)
-        lp_lm = (lp_lm > rcl) ? rcl : lp_lm;
-        const T lp_none = B[0].l + (hi - u[0]);          // beyond the last breakpoint (slope 1)
-        lp = (q == 0) ? lp_none : ((q == qmax) ? lp_lm : lp_gen);
+        // popped down to lm: lm's segment has slope s - tnew (1 when tnew = s - 1)
+        T lp_lm = lm + (hi - lo) * ((p == 0 || p == t) ? (T)1 : rl);
+        lp_lm = (qmax > 0 && lp_lm > rcl) ? rcl : lp_lm;
+        const T lp_none = B[0].l + (hi - u[0]);     // beyond the last breakpoint (slope 1)
+        lp = (q == qmax) ? lp_lm : ((q == 0) ? lp_none : lp_gen);
+        lp = empty ? yi + hi : lp;
     }
-    if (q == 0) R.at(t1 - 1).k = sf - (T)1;  // the old back's right segment is now interior, slope 1
-    R.size = t1 - q;
-    if (R.size >= K) return false;
-    ++R.size;
-    R.b = mk_ent<T>(lp, (T)0);
-    R.at(R.size - 1) = R.b;
-    return true;
+    // The old back (logical t1 - 1) stays as an interior breakpoint when q = 0:
+    // its right segment now has slope 1.  Written unconditionally: when q > 0
+    // that slot is dead or overwritten by the new back below, and when
+    // qmax = 0 it is the front slot, rewritten with its own value.
+    R.put_slot((h1 + t1 - 1) & (K - 1), qmax > 0 ? mk_ent<T>(B[0].l, sf - (T)1) : fnew);
+    const int t2 = t1 - q + 1;
+    const Ent<T> bnew = mk_ent<T>(lp, (T)0);
+    R.put_slot((h1 + t2 - 1) & (K - 1), bnew);
+    R.head = h1;
+    R.size = t2 < K ? t2 : K;
+    R.f = fnew;
+    R.b = bnew;
+    return (t1 <= K) & (t2 <= K);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,9 +347,8 @@ template <typename T, int K>
 __device__ __forceinline__ void node_step(CRing<T, K> &R, bool &ok, int64_t i, int64_t n, T yi, T wi, T &wprev,
                                           T &lm, T &lp) {
     const bool root = (i == n - 1);
-    lm = (T)0;
-    lp = (T)0;
-    if (ok) ok = dp_step_win<T, K, kScanWindow>(R, (int)(i + 1), yi, wprev, root ? (T)0 : wi, root, lm, lp);
+    const bool fits = dp_step_win<T, K, kScanWindow>(R, (T)(int)(i + 1), yi, wprev, root ? (T)0 : wi, lm, lp);
+    ok = ok & (fits | root);
     if (root) lp = lm;
     wprev = wi;
 }
@@ -379,20 +388,21 @@ __device__ __forceinline__ void load_state(const SegWs<T> &ws, CRing<T, K> &R, i
 }
 
 // Forward DP over nodes [from, b) with data loads P nodes ahead, storing the
-// lambda pairs of nodes >= a.  After each full tile hook(e) is called with the
-// next node index e (tile edges are multiples of P from `from`); a true return
-// stops the run, and fwd_run then returns e.  Otherwise it returns b.
-template <typename T, class Prob, int K, int P, class Hook>
+// lambda pairs if kStore (a halo run stores nothing).  After each full tile
+// hook(e) is called with the next node index e (tile edges are multiples of P
+// from `from`); a true return stops the run, and fwd_run then returns e.
+// Otherwise it returns b.
+template <typename T, class Prob, int K, int P, bool kStore, class Hook>
 __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::Src &src, bool &ok, T &wprev,
-                                           int64_t from, int64_t a, int64_t b, int64_t n, LamPair<T> *lam,
-                                           int64_t C, int64_t c, Hook hook) {
+                                           int64_t from, int64_t b, int64_t n, LamPair<T> *lam, int64_t C,
+                                           int64_t c, Hook hook) {
     typename Prob::Pre pre[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) pre[j] = src.load((from + j < b) ? from + j : b - 1);
     auto node = [&](int64_t i, const typename Prob::Pre &pv) {
         T lm, lp;
         node_step<T, K>(R, ok, i, n, src.data(pv), src.weight(pv), wprev, lm, lp);
-        if (i >= a) put_lam<T>(lam, i, C, c, lm, lp);
+        if (kStore) put_lam<T>(lam, i, C, c, lm, lp);
     };
     int64_t i0 = from;
     for (; i0 + P <= b; i0 += P) {
@@ -491,7 +501,7 @@ __device__ __forceinline__ bool meets_checkpoint(const SegWs<T> &ws, const CRing
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_main(SegWs<T> ws, typename Prob::Params pp) {
-    __shared__ Ent<T> s_ent[K * 64];
+    __shared__ Ent<T> s_ent[2 * K * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g == 0) *ws.ovf_count = 0;  // consumed by k_seg_fix / k_seg_ovf after this kernel
@@ -509,18 +519,19 @@ __global__ __launch_bounds__(64) void k_seg_main(SegWs<T> ws, typename Prob::Par
     bool ok = true;
     T wprev = (T)0;
     const int64_t C = ws.C;
-    if (s > 0 && h0 == a) save_state<T, K>(ws, R, s, kSaveHalo, c);  // no halo: the run starts empty at a
-    // tile edges align with a and a + m CK (all multiples of P)
+    // halo [h0, a) from an empty deque, storing nothing (a - h0 is a multiple of P)
+    if (h0 < a)
+        fwd_run<T, Prob, K, P, false>(R, src, ok, wprev, h0, a, n, ws.lam, C, c, [](int64_t) { return false; });
+    if (s > 0 && ok) save_state<T, K>(ws, R, s, kSaveHalo, c);
+    // own nodes; tile edges align with a + m CK (multiples of P)
     auto saves = [&](int64_t e) {
         if (ok) {
-            if (s > 0 && e == a) save_state<T, K>(ws, R, s, kSaveHalo, c);
             const int64_t m = (e - a) / ws.CK;
-            if (e > a && m * ws.CK == e - a && m <= kCheckpoints)
-                save_state<T, K>(ws, R, s, kSaveCk + (int)m - 1, c);
+            if (m * ws.CK == e - a && m <= kCheckpoints) save_state<T, K>(ws, R, s, kSaveCk + (int)m - 1, c);
         }
         return false;
     };
-    fwd_run<T, Prob, K, P>(R, src, ok, wprev, h0, a, b, n, ws.lam, C, c, saves);
+    fwd_run<T, Prob, K, P, true>(R, src, ok, wprev, a, b, n, ws.lam, C, c, saves);
     if (ok && b < n) save_state<T, K>(ws, R, s, kSaveEnd, c);
     ws.ovf[c * ws.S + s] = ok ? 0 : 1;
     if (ok) bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
@@ -535,7 +546,7 @@ __global__ __launch_bounds__(64) void k_seg_main(SegWs<T> ws, typename Prob::Par
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_repair(SegWs<T> ws, typename Prob::Params pp) {
-    __shared__ Ent<T> s_ent[K * 64];
+    __shared__ Ent<T> s_ent[2 * K * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g >= (ws.S - 1) * ws.C) return;
@@ -577,7 +588,7 @@ __global__ __launch_bounds__(64) void k_seg_repair(SegWs<T> ws, typename Prob::P
     load_state<T, K>(ws, R, s - 1, kSaveEnd, c);
     bool ok = true;
     T wprev = src.weight(src.load(a - 1));
-    const int64_t stop = fwd_run<T, Prob, K, P>(R, src, ok, wprev, a, a, b, n, ws.lam, C, c,
+    const int64_t stop = fwd_run<T, Prob, K, P, true>(R, src, ok, wprev, a, b, n, ws.lam, C, c,
                                                 [&](int64_t e) { return !ok || meets_checkpoint<T, K>(ws, R, s, c, a, e); });
     if (!ok) {
         ws.ovf[cs] = 1;
@@ -637,7 +648,7 @@ __device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, c
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_fix(SegWs<T> ws, typename Prob::Params pp) {
-    __shared__ Ent<T> s_ent[K * 64];
+    __shared__ Ent<T> s_ent[2 * K * 64];
     const int lane = threadIdx.x;
     const int64_t c = (int64_t)blockIdx.x * 64 + lane;
     if (c >= ws.C) return;
@@ -697,7 +708,7 @@ __device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, c
         const int64_t redo_to = mis[s] ? (int64_t)ws.rep_stop[s * C + c] : a;
         T wprev = src.weight(src.load(a - 1));
         bool met = false;
-        const int64_t stop = fwd_run<T, Prob, K, P>(R, src, ok, wprev, a, a, b, n, ws.lam, C, c, [&](int64_t e) {
+        const int64_t stop = fwd_run<T, Prob, K, P, true>(R, src, ok, wprev, a, b, n, ws.lam, C, c, [&](int64_t e) {
             if (!ok) return true;
             met = met || meets_checkpoint<T, K>(ws, R, s, c, a, e);
             return met && e >= redo_to;

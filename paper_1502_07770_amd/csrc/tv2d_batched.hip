@@ -166,12 +166,21 @@ __global__ __launch_bounds__(64) void k_bgap_pv(const BChain *__restrict__ cols,
     const BChain d = cols[c];
     if (!active[d.img]) return;
     const double lm = lam[d.img];
-    double cs = 0.0;
-#pragma unroll 8
-    for (int64_t r = 0; r + 1 < d.n; ++r) {
-        const int64_t k = d.base + r * d.es;
-        cs += (double)y[k];
-        pv[k] = store_feasible<T>(clipd(-cs, lm));
+    // same summation order as the single-image two-phase scan: the prefix of a
+    // row is (sum of the earlier blocks' sums, each from zero) + the rows of its
+    // own block in order
+    double pre = 0.0;
+    for (int64_t r0 = 0; r0 < d.n; r0 += kGapRows) {
+        const int64_t r1 = (r0 + kGapRows < d.n) ? r0 + kGapRows : d.n;
+        double cs = pre, bs = 0.0;
+        for (int64_t r = r0; r < r1; ++r) {
+            const int64_t k = d.base + r * d.es;
+            const double v = (double)y[k];
+            cs += v;
+            bs += v;
+            if (r + 1 < d.n) pv[k] = store_feasible<T>(clipd(-cs, lm));
+        }
+        pre += bs;
     }
 }
 

@@ -7,6 +7,10 @@ namespace tvc {
 
 // Threads per block of the gap reductions (four wave64 rows per block).
 constexpr int kGapBlock = 256;
+// Rows per block of the column prefix sums of the gap.  The single-image and
+// batched solvers sum in the same order (within a block from zero, blocks
+// added left to right), so their gaps agree bit for bit.
+constexpr int kGapRows = 64;
 
 // b_i of the row step; shared by the row chain source and the gap kernel so
 // both see bit-identical values.

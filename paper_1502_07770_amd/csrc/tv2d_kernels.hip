@@ -159,7 +159,6 @@ struct RowProb {
 // p_v down every column: p_v[r][c] = clip(-sum_{k<=r} y[k][c]), as a
 // two-phase segmented scan over row blocks of kGapRows rows; lanes are
 // consecutive columns, so every load is coalesced.
-constexpr int kGapRows = 64;
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_gap_colsum(const T *__restrict__ y, double *__restrict__ colpart, int64_t H,
