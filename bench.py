@@ -45,7 +45,7 @@ W_CHAIN = 0.1
 SEED = 3
 KERNEL_SOURCES = ["paper_1502_07770_amd/csrc/chain_core.h", "paper_1502_07770_amd/csrc/seg_kernels.h",
                   "paper_1502_07770_amd/csrc/chain_kernels.hip", "paper_1502_07770_amd/csrc/api_chain.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chain_prox_4096_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chain_prox_4096_rows_cols_traffic.json")
 
 
 def kernel_source_hash() -> str:
@@ -61,8 +61,8 @@ def log(*a):
 
 
 def committed_traffic():
-    """HBM bytes per tv_chain_prox call (4096x4096 rows or columns) from the
-    committed counter summary, only if taken on the current kernel sources."""
+    """HBM bytes per bench step launch from the committed counter summary, only
+    if taken on the current kernel sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -91,6 +91,8 @@ class Timer:
 
 
 def bench_chain(steps: int, warmup: int):
+    """The headline step: rows and columns of the image in ONE tv_chain_prox_multi
+    launch.  Also times the two batches as separate tv_chain_prox calls."""
     import numpy as np
     import torch
     from paper_1502_07770_amd import binding, synth
@@ -103,47 +105,55 @@ def bench_chain(steps: int, warmup: int):
     xc = torch.empty_like(y)
     rows = binding.ChainLayout(SIDE, SIDE, 1, SIDE, None)
     cols = binding.ChainLayout(SIDE, SIDE, SIDE, 1, None)
-    nb_r = lib.tv_chain_prox_workspace(ctypes.byref(rows), binding.TV_F32)
-    nb_c = lib.tv_chain_prox_workspace(ctypes.byref(cols), binding.TV_F32)
-    ws_r = torch.empty(nb_r, dtype=torch.uint8, device=dev)
-    ws_c = torch.empty(nb_c, dtype=torch.uint8, device=dev)
+    lays = (binding.ChainLayout * 2)(rows, cols)
+    yp = (ctypes.c_void_p * 2)(y.data_ptr(), y.data_ptr())
+    xp = (ctypes.c_void_p * 2)(xr.data_ptr(), xc.data_ptr())
+    wsc = (ctypes.c_double * 2)(W_CHAIN, W_CHAIN)
+    nb = lib.tv_chain_prox_multi_workspace(2, lays, binding.TV_F32)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
     sp = ctypes.c_void_p(stream.cuda_stream)
-    yp = ctypes.c_void_p(y.data_ptr())
 
-    def call(lay, out, ws, nb):
-        st = lib.tv_chain_prox(ctypes.byref(lay), binding.TV_F32, yp, None, W_CHAIN,
-                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nb, sp)
+    def step():
+        st = lib.tv_chain_prox_multi(2, lays, binding.TV_F32, yp, None, wsc, xp, ctypes.c_void_p(ws.data_ptr()),
+                                     nb, sp)
         if st != 0:
-            raise binding.TvChainError(st, "tv_chain_prox")
+            raise binding.TvChainError(st, "tv_chain_prox_multi")
 
     for _ in range(warmup):
-        call(rows, xr, ws_r, nb_r)
-        call(cols, xc, ws_c, nb_c)
+        step()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
-    for a, b, c in ev:
+    for a, b in ev:
         a.record(stream)
-        call(rows, xr, ws_r, nb_r)
+        step()
         b.record(stream)
-        call(cols, xc, ws_c, nb_c)
-        c.record(stream)
     t1.record(stream)
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
-    row_ms = [a.elapsed_time(b) for a, b, _ in ev]
-    col_ms = [b.elapsed_time(c) for _, b, c in ev]
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    assert torch.isfinite(xr).all() and torch.isfinite(xc).all()
+    # the same work as two separate calls (context)
+    sep = []
+    for lay in (rows, cols):
+        nbs = lib.tv_chain_prox_workspace(ctypes.byref(lay), binding.TV_F32)
+        wss = torch.empty(nbs, dtype=torch.uint8, device=dev)
+        out = torch.empty_like(y)
+        call = lambda: lib.tv_chain_prox(ctypes.byref(lay), binding.TV_F32, ctypes.c_void_p(y.data_ptr()),  # noqa
+                                         None, W_CHAIN, ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(wss.data_ptr()), nbs, sp)
+        call()
+        sep.append(Timer(torch, stream)(call, max(3, steps // 2)))
     nodes = 2 * SIDE * SIDE
     ms_step = total_ms / steps
-    assert torch.isfinite(xr).all() and torch.isfinite(xc).all()
-    return dict(ms_per_step=ms_step, gelem=nodes / (ms_step * 1e-3) / 1e9, row_ms=float(np.mean(row_ms)),
-                col_ms=float(np.mean(col_ms)), nodes=nodes, img=img,
-                segment_length=int(lib.tv_chain_prox_segment_length(ctypes.byref(rows))),
+    return dict(ms_per_step=ms_step, gelem=nodes / (ms_step * 1e-3) / 1e9, launch_ms=float(np.mean(launch_ms)),
+                separate_ms=sep, nodes=nodes, img=img,
+                segment_length=int(lib.tv_chain_prox_segment_length(ctypes.byref(
+                    binding.ChainLayout(2 * SIDE, SIDE, 1, SIDE, None)))),
                 tuning=binding.get_tuning())
 
 
@@ -257,15 +267,16 @@ def rocprof_summary(d):
     if dbs and not stats:
         con = sqlite3.connect(dbs[0])
         print("kernel stats (%s):" % os.path.relpath(dbs[0], d))
-        call_us = 0.0
+        call_us = {}
         for name, calls, total, avg in con.execute(
-                "select name, total_calls, total_duration, average from top_kernels limit 15"):
+                "select name, total_calls, total_duration, average from top_kernels limit 25"):
             short = name.split("(")[0].replace("void ", "")
             print("  %-60s calls=%-6d total_us=%-10.1f avg_us=%.1f" % (short[:60], calls, total, avg))
             if short.startswith("tvc::k_seg_"):
-                call_us += avg
-        if call_us:
-            print("  tv_chain_prox call (sum of the k_seg_* averages): %.1f us" % call_us)
+                prob = short.split(",")[1].strip().split("<")[0] if "," in short else short
+                call_us[prob] = call_us.get(prob, 0.0) + avg
+        for prob, us in sorted(call_us.items()):
+            print("  one launch with %s (sum of the k_seg_* averages): %.1f us" % (prob, us))
     for cnt in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
         with open(cnt) as fh:
             rows = list(csv.DictReader(fh))
@@ -291,8 +302,9 @@ def _counter_means(d, counter):
 
 
 def traffic_from_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
-    """HBM bytes of one tv_chain_prox call from FETCH_SIZE / WRITE_SIZE (KiB per
-    dispatch, averaged over the row and column calls), each scaled by what the
+    """HBM bytes of one tv_chain_prox_multi launch (the bench step) from
+    FETCH_SIZE / WRITE_SIZE (KiB per dispatch, averaged over the steps of the
+    run; the separate-call timing dispatches are excluded), each scaled by what the
     counter reads for a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB)."""
     gib = float(1 << 30)
     cf = _counter_means(copy_fetch_dir, "FETCH_SIZE")
@@ -300,16 +312,17 @@ def traffic_from_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     copy_k = [k for k in cf if "copyBuffer" in k][0]
     f_scale = gib / (cf[copy_k] * 1024.0)
     w_scale = gib / (cw[copy_k] * 1024.0)
-    fe = {k: v for k, v in _counter_means(fetch_dir, "FETCH_SIZE").items() if k.startswith("tvc::k_seg_")}
-    wr = {k: v for k, v in _counter_means(write_dir, "WRITE_SIZE").items() if k.startswith("tvc::k_seg_")}
+    step = lambda k: k.startswith("tvc::k_seg_") and "MultiProb" in k  # noqa: E731
+    fe = {k: v for k, v in _counter_means(fetch_dir, "FETCH_SIZE").items() if step(k)}
+    wr = {k: v for k, v in _counter_means(write_dir, "WRITE_SIZE").items() if step(k)}
     fetch_b = sum(fe.values()) * 1024.0 * f_scale
     write_b = sum(wr.values()) * 1024.0 * w_scale
-    rec = {"workload": "tv_chain_prox, 4096 chains of 4096 (rows or columns), FP32, w = 0.1",
+    rec = {"workload": "tv_chain_prox_multi, 4096 row + 4096 column chains of 4096 in one launch, FP32, w = 0.1",
            "kernel_source_hash": kernel_source_hash(),
            "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
            "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
            "bytes_per_launch": round(fetch_b + write_b),
-           "alg_bytes_per_launch": 8 * SIDE * SIDE,
+           "alg_bytes_per_launch": 8 * 2 * SIDE * SIDE,
            "per_kernel_fetch_kib": {k: round(v, 1) for k, v in fe.items()},
            "per_kernel_write_kib": {k: round(v, 1) for k, v in wr.items()}}
     return rec
@@ -362,12 +375,10 @@ def main():
 
     log("bench: chain prox 4096x4096 rows+cols, steps=%d warmup=%d" % (args.steps, args.warmup))
     r = bench_chain(args.steps, args.warmup)
-    log("bench: %.3f ms/step, %.1f Gelem/s (rows %.3f ms, cols %.3f ms)" % (
-        r["ms_per_step"], r["gelem"], r["row_ms"], r["col_ms"]))
-    launch_nodes = SIDE * SIDE
-    alg_bytes = 8.0 * launch_nodes
-    dom_ms = 0.5 * (r["row_ms"] + r["col_ms"])  # average tv_chain_prox call (rows and columns alternate)
-    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    log("bench: %.3f ms/step, %.1f Gelem/s (one launch %.3f ms; separate row / column calls %.3f / %.3f ms)" % (
+        r["ms_per_step"], r["gelem"], r["launch_ms"], r["separate_ms"][0], r["separate_ms"][1]))
+    alg_bytes = 8.0 * r["nodes"]
+    achieved = alg_bytes / (r["launch_ms"] * 1e-3) / 1e9
     traffic = committed_traffic()
     out = {
         "metric": METRIC,
@@ -384,10 +395,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "exact TV chain prox of all 4096 row and 4096 column chains (length 4096) of a "
-                        "4096x4096 FP32 shapes+noise image (sigma 0.1, seed 3), w = 0.1",
+                        "4096x4096 FP32 shapes+noise image (sigma 0.1, seed 3), w = 0.1, in one launch",
             "nodes_per_step": r["nodes"],
-            "row_launch_ms": round(r["row_ms"], 4),
-            "col_launch_ms": round(r["col_ms"], 4),
+            "launch_ms": round(r["launch_ms"], 4),
+            "separate_row_col_calls_ms": [round(v, 4) for v in r["separate_ms"]],
             "segment_length": r["segment_length"],
             "tuning": r["tuning"],
         },
@@ -399,8 +410,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "one tv_chain_prox call (k_seg_main, k_seg_repair, k_seg_fix, k_seg_ovf, k_seg_tail), "
-                      "averaged over the row and column calls",
+            "kernel": "one tv_chain_prox_multi launch over rows + columns (k_seg_main, k_seg_repair, k_seg_fix, "
+                      "k_seg_ovf, k_seg_tail)",
             "alg_bytes_per_launch": alg_bytes,
         },
     }

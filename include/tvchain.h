@@ -80,14 +80,34 @@ size_t tv_chain_prox_workspace(const tv_chain_layout *layout, tv_dtype dtype);
  *  w  : per-edge weights in y's layout, or NULL to use w_scalar for every edge.
  *       Weights must be >= 0 (w = 0 decouples the chain at that edge); a NaN or
  *       negative w_scalar is rejected; per-edge values are not checked.
- *  x  : output in y's layout; x may alias y (each y_i is read before x_i is
- *       written by the same lane, and chains do not overlap).
+ *  x  : output in y's layout.  Its address range must not overlap y's or w's
+ *       (segments of a chain run in parallel and re-read their input after
+ *       neighbouring segments have written their output); an overlap that the
+ *       host can see (equal pointers, or intersecting ranges of a uniform
+ *       layout) is rejected with TV_ERR_INVALID_ARG.
  *  Breakpoints live in an on-chip deque; a chain whose deque outgrows it is
  *  redone exactly with its deque in the workspace, so results never depend on
  *  the data's breakpoint depth. */
 tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const void *y,
                         const void *w, double w_scalar, void *x,
                         void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Several uniform batches of chains solved in ONE launch (e.g. the row and
+ * the column chains of an image, or chains of different lengths), each as by
+ * tv_chain_prox: batch b is layouts[b] (offsets must be NULL) over y[b] with
+ * per-edge weights w[b], or with w_scalar[b] if w is NULL, into x[b].
+ *  num_batches : 1 .. TV_MAX_CHAIN_BATCHES.
+ *  y, w, x, w_scalar : [host] arrays of num_batches entries (y, w, x hold
+ *       DEVICE pointers).  Inputs may be shared between batches; no x[b] may
+ *       overlap any y, w or other x (checked as in tv_chain_prox).
+ * The chains of all batches share one segmentation (the longest length sets
+ * it), which gives a launch enough lanes where a single batch would not.
+ * Results are bit-identical to separate tv_chain_prox calls. */
+#define TV_MAX_CHAIN_BATCHES 8
+size_t tv_chain_prox_multi_workspace(int num_batches, const tv_chain_layout *layouts, tv_dtype dtype);
+tv_status tv_chain_prox_multi(int num_batches, const tv_chain_layout *layouts, tv_dtype dtype,
+                              const void *const *y, const void *const *w, const double *w_scalar,
+                              void *const *x, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
 size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);

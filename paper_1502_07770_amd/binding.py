@@ -8,6 +8,7 @@ library is missing or no GPU is visible, calls raise ``TvChainError``.
 Functions mirror the C entry points:
 
 * ``chain_prox(y, w, dim)``            -> tv_chain_prox (eq. (1D-ROF), Sec. 4.1)
+* ``chain_prox_multi(items, w)``      -> tv_chain_prox_multi (several batches, one launch)
 * ``chain_prox_backward(x, g, ...)``   -> tv_chain_prox_backward
 * ``prox(y, w, dim)``                  -> autograd-aware chain prox
 * ``tv2d(f, lam, ...)``                -> tv2d_solve (Sec. 5.1)
@@ -74,6 +75,9 @@ _SIG = {
     "tv_chain_prox_backward_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "tv_chain_prox_backward": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P,
                                               ctypes.c_size_t, _P]),
+    "tv_chain_prox_multi_workspace": (ctypes.c_size_t, [ctypes.c_int, _P, ctypes.c_int]),
+    "tv_chain_prox_multi": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                           _P]),
     "tv_set_tuning": (ctypes.c_int, [_P]),
     "tv_get_tuning": (ctypes.c_int, [_P]),
     "tv_chain_prox_segment_length": (_I64, [_P]),
@@ -228,6 +232,39 @@ def chain_prox(y: torch.Tensor, w: Union[float, torch.Tensor] = 0.0, dim: int = 
         out.copy_(res)
         return out
     return res
+
+
+MAX_CHAIN_BATCHES = 8
+
+
+def chain_prox_multi(items, w: Union[float, list] = 0.0) -> list:
+    """Exact TV prox of several batches of chains in one launch
+    (tv_chain_prox_multi).  ``items`` is a list of ``(y, dim)`` pairs (one
+    dtype, one device); ``w`` is one scalar weight for every batch or a list
+    with one per batch.  Returns the outputs in the order of ``items``;
+    they are bit-identical to separate ``chain_prox`` calls."""
+    if not 1 <= len(items) <= MAX_CHAIN_BATCHES:
+        raise TvChainError(TV_ERR_INVALID_ARG, "chain_prox_multi takes 1..%d batches" % MAX_CHAIN_BATCHES)
+    lib = load()
+    ys = [y for y, _ in items]
+    _require_gpu(*ys)
+    dev, code = ys[0].device, _dtype_code(ys[0])
+    if any(y.device != dev or _dtype_code(y) != code for y in ys):
+        raise TvChainError(TV_ERR_INVALID_ARG, "chain_prox_multi batches must share dtype and device")
+    wl = list(w) if isinstance(w, (list, tuple)) else [float(w)] * len(items)
+    views = [_chain_view(y, d) for y, d in items]
+    xs = [torch.empty_like(v) for v, _, _ in views]
+    nb = len(items)
+    lays = (ChainLayout * nb)(*[lay for _, lay, _ in views])
+    yp = (ctypes.c_void_p * nb)(*[v.data_ptr() for v, _, _ in views])
+    xp = (ctypes.c_void_p * nb)(*[x.data_ptr() for x in xs])
+    wsc = (ctypes.c_double * nb)(*[float(v) for v in wl])
+    nbytes = lib.tv_chain_prox_multi_workspace(nb, lays, code)
+    ws = _workspace(nbytes, dev)
+    st = lib.tv_chain_prox_multi(nb, lays, code, yp, None, wsc, xp, _ptr(ws), nbytes,
+                                 ctypes.c_void_p(_stream_ptr(dev)))
+    _check(st, "tv_chain_prox_multi")
+    return [restore(x) for x, (_, _, restore) in zip(xs, views)]
 
 
 def chain_prox_backward(x: torch.Tensor, grad_x: torch.Tensor, dim: int = -1,

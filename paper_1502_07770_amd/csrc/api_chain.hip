@@ -57,6 +57,34 @@ static ChainBatch to_batch(const tv_chain_layout *L) {
     return b;
 }
 
+// Byte range [lo, hi) touched by a uniform layout's elements starting at p
+// (CSR layouts: only the base pointer is known on the host).
+static void layout_span(const tv_chain_layout *L, tv_dtype dt, const void *p, uintptr_t *lo, uintptr_t *hi) {
+    const size_t es = dt == TV_F32 ? 4 : 8;
+    const uintptr_t b = (uintptr_t)p;
+    *lo = b;
+    if (L->offsets || L->num_chains < 1) {
+        *hi = b + es;
+        return;
+    }
+    const int64_t last = (L->num_chains - 1) * (L->num_chains > 1 ? L->chain_stride : 0) +
+                         (L->length - 1) * L->elem_stride;
+    *hi = b + (uintptr_t)(last + 1) * es;
+}
+
+// True if the output may overlap an input: segments of one chain run in
+// parallel and re-read their input after neighbouring segments have written
+// their output, so x must not share memory with y (or w).
+static bool overlaps(const tv_chain_layout *Lx, const void *x, const tv_chain_layout *Ly, const void *y,
+                     tv_dtype dt) {
+    if (!x || !y) return false;
+    if (x == y) return true;
+    uintptr_t a0, a1, b0, b1;
+    layout_span(Lx, dt, x, &a0, &a1);
+    layout_span(Ly, dt, y, &b0, &b1);
+    return a0 < b1 && b0 < a1;
+}
+
 static size_t prox_ws_bytes(const tv_chain_layout *L, tv_dtype dt) {
     const ChainBatch b = to_batch(L);
     const SegPlan plan = seg_plan(b.num_chains, b.n);
@@ -101,6 +129,7 @@ tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const voi
     if (layout->num_chains == 0) return TV_OK;
     if (!y || !x) return TV_ERR_INVALID_ARG;
     if (!w && !(isfinite(w_scalar) && w_scalar >= 0.0)) return TV_ERR_INVALID_ARG;
+    if (overlaps(layout, x, layout, y, dtype) || overlaps(layout, x, layout, w, dtype)) return TV_ERR_INVALID_ARG;
     const size_t need = prox_ws_bytes(layout, dtype);
     if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
     tv_status st = device_check();
@@ -114,6 +143,62 @@ tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const voi
     else
         e = launch_chain_prox<double>(b, (const double *)y, (const double *)w, w_scalar, (double *)x,
                                       workspace, plan, stream);
+    return e == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+static_assert(kMaxChainBatches == TV_MAX_CHAIN_BATCHES, "batch limit of the ABI");
+
+static bool multi_ok(int nb, const tv_chain_layout *layouts, tv_dtype dtype, int64_t *C, int64_t *n) {
+    if (nb < 1 || nb > kMaxChainBatches || !layouts) return false;
+    *C = 0;
+    *n = 0;
+    for (int b = 0; b < nb; ++b) {
+        if (!layout_ok(&layouts[b], dtype) || layouts[b].offsets) return false;
+        *C += layouts[b].num_chains;
+        if (layouts[b].num_chains > 0 && layouts[b].length > *n) *n = layouts[b].length;
+    }
+    return true;
+}
+
+size_t tv_chain_prox_multi_workspace(int num_batches, const tv_chain_layout *layouts, tv_dtype dtype) {
+    int64_t C, n;
+    if (!multi_ok(num_batches, layouts, dtype, &C, &n) || C == 0) return 0;
+    const SegPlan plan = seg_plan(C, n);
+    ChainBatch all{C, n, 1, n, nullptr};
+    return dtype == TV_F32 ? chain_prox_ws_bytes<float>(all, plan) : chain_prox_ws_bytes<double>(all, plan);
+}
+
+tv_status tv_chain_prox_multi(int num_batches, const tv_chain_layout *layouts, tv_dtype dtype,
+                              const void *const *y, const void *const *w, const double *w_scalar,
+                              void *const *x, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    int64_t C, n;
+    if (!multi_ok(num_batches, layouts, dtype, &C, &n)) return TV_ERR_INVALID_ARG;
+    if (C == 0) return TV_OK;
+    if (!y || !x || (!w && !w_scalar)) return TV_ERR_INVALID_ARG;
+    ChainBatch bs[kMaxChainBatches];
+    for (int b = 0; b < num_batches; ++b) {
+        if (layouts[b].num_chains > 0 && (!y[b] || !x[b] || (w && !w[b]))) return TV_ERR_INVALID_ARG;
+        if (!w && !(isfinite(w_scalar[b]) && w_scalar[b] >= 0.0)) return TV_ERR_INVALID_ARG;
+        for (int o = 0; o < num_batches; ++o) {
+            if (overlaps(&layouts[b], x[b], &layouts[o], y[o], dtype)) return TV_ERR_INVALID_ARG;
+            if (w && overlaps(&layouts[b], x[b], &layouts[o], w[o], dtype)) return TV_ERR_INVALID_ARG;
+            if (o != b && overlaps(&layouts[b], x[b], &layouts[o], x[o], dtype)) return TV_ERR_INVALID_ARG;
+        }
+        bs[b] = to_batch(&layouts[b]);
+    }
+    const SegPlan plan = seg_plan(C, n);
+    ChainBatch all{C, n, 1, n, nullptr};
+    const size_t need = dtype == TV_F32 ? chain_prox_ws_bytes<float>(all, plan) : chain_prox_ws_bytes<double>(all, plan);
+    if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
+    tv_status st = device_check();
+    if (st != TV_OK) return st;
+    hipError_t e;
+    if (dtype == TV_F32)
+        e = launch_chain_prox_multi<float>(num_batches, bs, (const float *const *)y, (const float *const *)w,
+                                           w_scalar, (float *const *)x, workspace, plan, stream);
+    else
+        e = launch_chain_prox_multi<double>(num_batches, bs, (const double *const *)y, (const double *const *)w,
+                                            w_scalar, (double *const *)x, workspace, plan, stream);
     return e == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
 

@@ -69,6 +69,63 @@ struct PlainProb {
 };
 
 // ---------------------------------------------------------------------------
+// Several batches of chains in one launch (e.g. the row and the column chains
+// of an image).  Global chain c belongs to the last batch b with c0[b] <= c;
+// each batch has its own buffers, strides, length and scalar weight.  The
+// per-node work is PlainProb's: only the lane's setup picks its batch.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatches = kMaxChainBatches;
+
+template <typename T, bool EDGE_W>
+struct MultiProb {
+    using Base = PlainProb<T, EDGE_W>;
+    struct Params {
+        int nb;
+        int64_t c0[kMaxBatches];  // first global chain of each batch
+        const T *y[kMaxBatches];
+        const T *w[kMaxBatches];
+        T *x[kMaxBatches];
+        T ws[kMaxBatches];
+        int64_t n[kMaxBatches], es[kMaxBatches], cs[kMaxBatches];
+    };
+    using Pre = typename Base::Pre;
+    using SinkPre = typename Base::SinkPre;
+    using Src = typename Base::Src;
+    using Sink = typename Base::Sink;
+    // value of arr[b] for a per-lane b, without dynamic indexing of the kernel
+    // arguments (selects over the batches)
+    template <typename V>
+    static __device__ __forceinline__ V pick(const V (&arr)[kMaxBatches], int b) {
+        V v = arr[0];
+#pragma unroll
+        for (int j = 1; j < kMaxBatches; ++j) v = (b == j) ? arr[j] : v;
+        return v;
+    }
+    static __device__ __forceinline__ int batch_of(const Params &p, int64_t c) {
+        int b = 0;
+#pragma unroll
+        for (int j = 1; j < kMaxBatches; ++j) b += (j < p.nb && c >= p.c0[j]) ? 1 : 0;
+        return b;
+    }
+    static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t c, int64_t) {
+        const int b = batch_of(p, c);
+        ChainSpan sp;
+        sp.aux = b;
+        sp.base = (c - pick(p.c0, b)) * pick(p.cs, b);
+        sp.es = pick(p.es, b);
+        sp.n = pick(p.n, b);
+        return sp;
+    }
+    static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
+        const int b = (int)sp.aux;
+        return Src{pick(p.y, b), pick(p.w, b), pick(p.ws, b), sp.base, sp.es};
+    }
+    static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
+        return Sink{pick(p.x, (int)sp.aux), sp.base, sp.es};
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Adjoint.  Pass 1 (left to right): run sums of g in FP64; at the end of each
 // run its mean goes to grad_y at the run's last node, and the boundary edge
 // that closed the previous run gets s_e (mean_prev - mean) in grad_w; edges
@@ -152,6 +209,46 @@ hipError_t launch_chain_prox(const ChainBatch &b, const T *y, const T *w, T w_sc
 }
 
 template <typename T>
+hipError_t launch_chain_prox_multi(int nb, const ChainBatch *bs, const T *const *y, const T *const *w,
+                                   const double *w_scalar, T *const *x, void *workspace, const SegPlan &plan,
+                                   hipStream_t stream) {
+    int64_t C = 0, n = 0;
+    for (int b = 0; b < nb; ++b) {
+        C += bs[b].num_chains;
+        n = bs[b].n > n ? bs[b].n : n;
+    }
+    if (C <= 0) return hipSuccess;
+    SegWs<T> ws;
+    seg_ws_layout<T, kRingSlots>(workspace, C, n, plan.L, plan.H, plan.CK, &ws);
+    auto fill = [&](auto &pp) {
+        pp.nb = nb;
+        int64_t c0 = 0;
+        for (int b = 0; b < kMaxBatches; ++b) {
+            const bool on = b < nb;
+            pp.c0[b] = on ? c0 : C;
+            pp.y[b] = on ? y[b] : nullptr;
+            pp.w[b] = (on && w) ? w[b] : nullptr;
+            pp.x[b] = on ? x[b] : nullptr;
+            pp.ws[b] = on && !w ? (T)w_scalar[b] : (T)0;
+            pp.n[b] = on ? bs[b].n : 0;
+            pp.es[b] = on ? bs[b].es : 1;
+            pp.cs[b] = on ? bs[b].cs : 0;
+            if (on) c0 += bs[b].num_chains;
+        }
+    };
+    if (w) {
+        using Prob = MultiProb<T, true>;
+        typename Prob::Params pp;
+        fill(pp);
+        return seg_launch<T, Prob, kRingSlots, kTile>(ws, pp, stream);
+    }
+    using Prob = MultiProb<T, false>;
+    typename Prob::Params pp;
+    fill(pp);
+    return seg_launch<T, Prob, kRingSlots, kTile>(ws, pp, stream);
+}
+
+template <typename T>
 size_t chain_prox_ws_bytes(const ChainBatch &b, const SegPlan &plan) {
     return seg_ws_layout<T, kRingSlots>(nullptr, b.num_chains, b.n, plan.L, plan.H, plan.CK, nullptr);
 }
@@ -170,6 +267,12 @@ template hipError_t launch_chain_prox<float>(const ChainBatch &, const float *, 
                                              float *, void *, const SegPlan &, hipStream_t);
 template hipError_t launch_chain_prox<double>(const ChainBatch &, const double *, const double *, double,
                                               double *, void *, const SegPlan &, hipStream_t);
+template hipError_t launch_chain_prox_multi<float>(int, const ChainBatch *, const float *const *,
+                                                   const float *const *, const double *, float *const *, void *,
+                                                   const SegPlan &, hipStream_t);
+template hipError_t launch_chain_prox_multi<double>(int, const ChainBatch *, const double *const *,
+                                                    const double *const *, const double *, double *const *, void *,
+                                                    const SegPlan &, hipStream_t);
 template size_t chain_prox_ws_bytes<float>(const ChainBatch &, const SegPlan &);
 template size_t chain_prox_ws_bytes<double>(const ChainBatch &, const SegPlan &);
 template hipError_t launch_chain_adjoint<float>(const ChainBatch &, const float *, const float *,

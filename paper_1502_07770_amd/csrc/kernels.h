@@ -47,6 +47,13 @@ template <typename T>
 hipError_t launch_chain_prox(const ChainBatch &b, const T *y, const T *w, T w_scalar, T *x, void *workspace,
                              const SegPlan &plan, hipStream_t stream);
 
+// Up to kMaxChainBatches uniform batches in one launch (see tv_chain_prox_multi).
+constexpr int kMaxChainBatches = 8;
+template <typename T>
+hipError_t launch_chain_prox_multi(int nb, const ChainBatch *bs, const T *const *y, const T *const *w,
+                                   const double *w_scalar, T *const *x, void *workspace, const SegPlan &plan,
+                                   hipStream_t stream);
+
 template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,
                                 int w_per_edge, hipStream_t stream);

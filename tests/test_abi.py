@@ -1,0 +1,107 @@
+"""Host-side checks of the C ABI (no GPU): the built library exports every
+function that include/tvchain.h declares, and argument errors are reported
+before any HIP call (so they are testable on a machine without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1502_07770_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tvchain.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(tv\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libtvchain.so not built")
+    return binding.load()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("tv_chain_prox", "tv_chain_prox_backward", "tv_chain_prox_multi", "tv2d_solve",
+              "tv2d_solve_batched", "tv_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if getattr(lib, n, None) is None]
+    assert not missing, missing
+    # the binding describes every declared function
+    assert set(_declared()) <= set(binding._SIG)
+
+
+def test_status_strings(lib):
+    for code in range(7):
+        assert lib.tv_status_string(code)
+    assert lib.tv_status_string(99) == b"unknown status"
+
+
+def test_tuning_round_trip_and_rejections(lib):
+    saved = binding.get_tuning()
+    try:
+        binding.set_tuning(target_lanes=4096, min_segment=32, halo=40)
+        assert binding.get_tuning() == {"target_lanes": 4096, "min_segment": 32, "halo": 40}
+        bad = binding.Tuning(0, 1, 0)
+        assert lib.tv_set_tuning(ctypes.byref(bad)) == binding.TV_ERR_INVALID_ARG
+        assert lib.tv_get_tuning(None) == binding.TV_ERR_INVALID_ARG
+    finally:
+        binding.set_tuning(**saved)
+
+
+def _lay(C, n, es, cs):
+    return binding.ChainLayout(C, n, es, cs, None)
+
+
+def test_workspace_queries(lib):
+    rows = _lay(64, 1000, 1, 1000)
+    assert lib.tv_chain_prox_workspace(ctypes.byref(rows), binding.TV_F32) > 0
+    assert lib.tv_chain_prox_workspace(ctypes.byref(rows), 7) == 0          # bad dtype
+    assert lib.tv_chain_prox_workspace(ctypes.byref(_lay(4, 0, 1, 1)), binding.TV_F32) == 0
+    assert lib.tv_chain_prox_workspace(ctypes.byref(_lay(4, 1 << 24, 1, 1 << 24)), binding.TV_F32) == 0
+    assert lib.tv2d_workspace(64, 48, binding.TV_F32) > 0
+    assert lib.tv2d_workspace(0, 48, binding.TV_F32) == 0
+    lays = (binding.ChainLayout * 2)(_lay(64, 100, 1, 100), _lay(100, 64, 100, 1))
+    assert lib.tv_chain_prox_multi_workspace(2, lays, binding.TV_F32) > 0
+    assert lib.tv_chain_prox_multi_workspace(0, lays, binding.TV_F32) == 0
+    assert lib.tv_chain_prox_multi_workspace(9, lays, binding.TV_F32) == 0
+
+
+def test_argument_errors_before_any_hip_call(lib):
+    rows = _lay(8, 100, 1, 100)
+    P = ctypes.c_void_p
+    buf, out, ws = P(0x10000000), P(0x20000000), P(0x30000000)
+    call = lib.tv_chain_prox
+    # negative / NaN weight, null pointers
+    assert call(ctypes.byref(rows), 0, buf, None, -1.0, out, ws, 1 << 30, None) == binding.TV_ERR_INVALID_ARG
+    assert call(ctypes.byref(rows), 0, buf, None, float("nan"), out, ws, 1 << 30, None) == binding.TV_ERR_INVALID_ARG
+    assert call(ctypes.byref(rows), 0, None, None, 0.1, out, ws, 1 << 30, None) == binding.TV_ERR_INVALID_ARG
+    # x aliasing y (or overlapping its range) is rejected
+    assert call(ctypes.byref(rows), 0, buf, None, 0.1, buf, ws, 1 << 30, None) == binding.TV_ERR_INVALID_ARG
+    assert call(ctypes.byref(rows), 0, buf, None, 0.1, P(0x10000000 + 4 * 799), ws, 1 << 30,
+                None) == binding.TV_ERR_INVALID_ARG
+    # workspace missing or short
+    assert call(ctypes.byref(rows), 0, buf, None, 0.1, out, None, 0, None) == binding.TV_ERR_WORKSPACE
+    need = lib.tv_chain_prox_workspace(ctypes.byref(rows), 0)
+    assert call(ctypes.byref(rows), 0, buf, None, 0.1, out, ws, need - 1, None) == binding.TV_ERR_WORKSPACE
+    # multi: overlapping outputs, bad batch counts, NaN weight
+    lays = (binding.ChainLayout * 2)(rows, rows)
+    ys = (P * 2)(buf, buf)
+    same = (P * 2)(out, out)
+    wsc = (ctypes.c_double * 2)(0.1, 0.1)
+    m = lib.tv_chain_prox_multi
+    assert m(2, lays, 0, ys, None, wsc, same, ws, 1 << 30, None) == binding.TV_ERR_INVALID_ARG
+    assert m(0, lays, 0, ys, None, wsc, same, ws, 1 << 30, None) == binding.TV_ERR_INVALID_ARG
+    xs = (P * 2)(out, P(0x40000000))
+    bad = (ctypes.c_double * 2)(0.1, float("nan"))
+    assert m(2, lays, 0, ys, None, bad, xs, ws, 1 << 30, None) == binding.TV_ERR_INVALID_ARG
+    assert m(2, lays, 0, ys, None, wsc, xs, None, 0, None) == binding.TV_ERR_WORKSPACE

@@ -250,3 +250,34 @@ def test_segmented_uneven_lengths(tuning):
         tuning(target_lanes=1 << 30, min_segment=8)
         got = _solve(y, 0.3, torch.float32)
         assert np.array_equal(got, ref), n
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_multi_batch_launch_equals_separate_calls(dtype):
+    """Rows and columns of an image (and a third batch of other length and
+    weight) in one tv_chain_prox_multi launch: bit-identical to separate calls."""
+    img = _dev(synth.shapes_image(700, 900, seed=41), dtype)
+    other = _dev(synth.piecewise_constant(300, 2500, seed=42), dtype)
+    xs = binding.chain_prox_multi([(img, -1), (img, 0), (other, -1)], w=[0.1, 0.1, 0.45])
+    assert torch.equal(xs[0], binding.chain_prox(img, 0.1, dim=-1))
+    assert torch.equal(xs[1], binding.chain_prox(img, 0.1, dim=0))
+    assert torch.equal(xs[2], binding.chain_prox(other, 0.45, dim=-1))
+    ov = other.double().cpu().numpy()
+    _check_rows(ov, xs[2].double().cpu().numpy(), oracle.chain_prox(ov, w_scalar=0.45), TOL[dtype])
+
+
+def test_multi_batch_full_size_rows_and_columns_fp32():
+    """The 4096 x 4096 rows + columns step as one launch, against separate calls
+    and the oracle on sampled chains."""
+    img = synth.shapes_image(4096, 4096, seed=3)
+    t = _dev(img, torch.float32)
+    xr, xc = binding.chain_prox_multi([(t, -1), (t, 0)], w=0.1)
+    assert torch.equal(xr, binding.chain_prox(t, 0.1, dim=-1))
+    assert torch.equal(xc, binding.chain_prox(t, 0.1, dim=0))
+    yv = t.double().cpu().numpy()
+    rows = np.random.default_rng(5).choice(4096, size=48, replace=False)
+    _check_rows(yv[rows], xr.double().cpu().numpy()[rows], oracle.chain_prox(yv[rows], w_scalar=0.1),
+                TOL[torch.float32])
+    cols = np.ascontiguousarray(yv[:, rows].T)
+    _check_rows(cols, xc.double().cpu().numpy()[:, rows].T, oracle.chain_prox(cols, w_scalar=0.1),
+                TOL[torch.float32])
