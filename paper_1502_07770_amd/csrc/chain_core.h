@@ -31,6 +31,25 @@ template <typename T> __device__ __forceinline__ T recip(T v);
 template <> __device__ __forceinline__ float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double recip<double>(double v) { return 1.0 / v; }
 
+// Four consecutive elements from a 16-byte aligned address (two 16-byte loads
+// for double).
+__device__ __forceinline__ void vload4(const float *p, float (&o)[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void vload4(const double *p, double (&o)[4]) {
+    const double2 a = *reinterpret_cast<const double2 *>(p), b = *reinterpret_cast<const double2 *>(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+__device__ __forceinline__ void vstore4(float *p, const float (&v)[4]) {
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void vstore4(double *p, const double (&v)[4]) {
+    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+}
+template <typename T> __device__ __forceinline__ bool aligned16(const T *p) { return ((uintptr_t)p & 15) == 0; }
+
 // Clip of v to [lo, hi] for lo <= hi (every call site guarantees the order:
 // brackets of sorted breakpoints, and lambda^- <= lambda^+).  FP32 uses the
 // median-of-three instruction (one VALU op, no NaN canonicalisation).

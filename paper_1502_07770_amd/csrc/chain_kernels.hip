@@ -30,11 +30,26 @@ struct PlainProb {
         const T *__restrict__ w;
         T ws;
         int64_t base, es;
+        bool vec;  // unit stride and 16-byte aligned: load4 may be used
+        __device__ __forceinline__ Src(const T *y_, const T *w_, T ws_, int64_t base_, int64_t es_)
+            : y(y_), w(w_), ws(ws_), base(base_), es(es_),
+              vec(es_ == 1 && aligned16(y_ + base_) && (!EDGE_W || aligned16(w_ + base_))) {}
         __device__ __forceinline__ Pre load(int64_t i) const {
             Pre p;
             p.y = y[base + i * es];
             p.w = EDGE_W ? w[base + i * es] : ws;
             return p;
+        }
+        // nodes i .. i+3 (i a multiple of 4, vec set)
+        __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
+            T a[4], c[4];
+            vload4(y + base + i, a);
+            if (EDGE_W) vload4(w + base + i, c);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                o[k].y = a[k];
+                o[k].w = EDGE_W ? c[k] : ws;
+            }
         }
         __device__ __forceinline__ T data(const Pre &p) const { return p.y; }
         __device__ __forceinline__ T weight(const Pre &p) const { return p.w; }
@@ -42,8 +57,15 @@ struct PlainProb {
     struct Sink {
         T *__restrict__ x;
         int64_t base, es;
+        bool vec;  // unit stride and 16-byte aligned: load4 / store4 may be used
+        __device__ __forceinline__ Sink(T *x_, int64_t base_, int64_t es_)
+            : x(x_), base(base_), es(es_), vec(es_ == 1 && aligned16(x_ + base_)) {}
         __device__ __forceinline__ SinkPre load(int64_t) const { return SinkPre{}; }
+        __device__ __forceinline__ void load4(int64_t, SinkPre *) const {}
         __device__ __forceinline__ void store(int64_t i, T v, const SinkPre &) const { x[base + i * es] = v; }
+        __device__ __forceinline__ void store4(int64_t i, const T (&v)[4], const SinkPre (&)[4]) const {
+            vstore4(x + base + i, v);
+        }
     };
     static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t c, int64_t nmax) {
         ChainSpan sp;

@@ -396,6 +396,7 @@ template <typename T, class Prob, int K, int P, bool kStore, class Hook>
 __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::Src &src, bool &ok, T &wprev,
                                            int64_t from, int64_t b, int64_t n, LamPair<T> *lam, int64_t C,
                                            int64_t c, Hook hook) {
+    static_assert(P % 4 == 0, "tiles hold whole groups of four nodes");
     typename Prob::Pre pre[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) pre[j] = src.load((from + j < b) ? from + j : b - 1);
@@ -410,7 +411,19 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::
         for (int j = 0; j < P; ++j) {
             const int64_t i = i0 + j;
             const auto pv = pre[j];
-            pre[j] = src.load((i + P < b) ? i + P : b - 1);
+            if (!src.vec) {
+                pre[j] = src.load((i + P < b) ? i + P : b - 1);
+            } else if ((j & 3) == 3) {
+                // unit-stride chains (rows): refill the four slots just consumed
+                // with one 16-byte load per stream (node indices are multiples of 4)
+                const int64_t q = i + P - 3;
+                if (q + 3 < b) {
+                    src.load4(q, &pre[j - 3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) pre[j - 3 + k] = src.load((q + k < b) ? q + k : b - 1);
+                }
+            }
             node(i, pv);
         }
         if (hook(i0 + P)) return i0 + P;
@@ -425,25 +438,47 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::
 // Backward clip pass over [a, b) of one chain.  All lanes of a wave share a and
 // b, so node indices are wave-uniform and the lambda / sink accesses coalesce.
 // Collapsed nodes are written through the sink; the un-collapsed right tail
-// gets its composed interval in the lambda stream for k_seg_tail.
-template <typename T, class Prob, int P>
-__device__ __forceinline__ void bwd_sweep(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp,
-                                          int64_t s, int64_t c, int64_t a, int64_t b) {
-    const auto sink = Prob::sink(pp, sp);
+// gets its composed interval in the lambda stream for k_seg_tail.  With kVec
+// (unit-stride, 16-byte aligned sink and b a multiple of 4) the sink is read
+// and written four nodes at a time: node groups [4m, 4m + 3] are visited from
+// the top, buffered, and stored with one 16-byte access per stream when the
+// whole group has collapsed (the group holding the collapse point falls back
+// to single stores).
+template <typename T, class Prob, int P, bool kVec>
+__device__ __forceinline__ void bwd_sweep_run(const SegWs<T> &ws, const typename Prob::Sink &sink, int64_t s,
+                                              int64_t c, int64_t a, int64_t b) {
+    static_assert(P % 4 == 0, "tiles hold whole groups of four nodes");
+    using SP = typename Prob::SinkPre;
     LamPair<T> *__restrict__ lam = ws.lam;
     const int64_t C = ws.C;
     T glo = -pos_inf<T>(), ghi = pos_inf<T>(), x = (T)0;
     bool col = false;
     int64_t k = a - 1;
     LamPair<T> pre[P];
-    typename Prob::SinkPre spre[P];
+    SP spre[P];
+    // slot j holds node i0 - j of the current tile (i0 = b - 1 - tile * P)
+    auto refill_sink = [&](int jhi, int64_t q) {  // nodes q .. q+3 into slots jhi, jhi-1, jhi-2, jhi-3
+        if (q >= a) {
+            SP t4[4];
+            sink.load4(q, t4);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) spre[jhi - m] = t4[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) spre[jhi - m] = sink.load((q + m >= a) ? q + m : a);
+        }
+    };
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const int64_t i = (b - 1 - j >= a) ? b - 1 - j : a;
         pre[j] = lam[i * C + c];
-        spre[j] = sink.load(i);
+        if (!kVec) spre[j] = sink.load(i);
+        else if ((j & 3) == 3) refill_sink(j, b - 1 - j);
     }
-    auto visit = [&](int64_t i, const LamPair<T> &p, const typename Prob::SinkPre &sv) {
+    T gx[4];
+    SP gs[4];
+    bool gc[4];
+    auto visit = [&](int64_t i, int jj, const LamPair<T> &p, const SP &sv) {
         if (!col) {
             glo = clampv(glo, p.lo, p.hi);
             ghi = clampv(ghi, p.lo, p.hi);
@@ -456,12 +491,28 @@ __device__ __forceinline__ void bwd_sweep(const SegWs<T> &ws, const typename Pro
             x = clampv(x, p.lo, p.hi);
         }
         if (col) {
-            sink.store(i, x, sv);
+            if (kVec) {
+                gx[3 - jj] = x;
+                gs[3 - jj] = sv;
+                gc[3 - jj] = true;
+            } else {
+                sink.store(i, x, sv);
+            }
         } else {
             LamPair<T> g;
             g.lo = glo;
             g.hi = ghi;
             lam[i * C + c] = g;
+            if (kVec) gc[3 - jj] = false;
+        }
+        if (kVec && jj == 3) {  // i = 4m: the group is complete
+            if (gc[0] & gc[1] & gc[2] & gc[3]) {
+                sink.store4(i, gx, gs);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    if (gc[m]) sink.store(i + m, gx[m], gs[m]);
+            }
         }
     };
     int64_t i0 = b - 1;
@@ -470,21 +521,32 @@ __device__ __forceinline__ void bwd_sweep(const SegWs<T> &ws, const typename Pro
         for (int j = 0; j < P; ++j) {
             const int64_t i = i0 - j;
             const LamPair<T> p = pre[j];
-            const auto sv = spre[j];
+            const SP sv = spre[j];
             const int64_t ip = (i - P >= a) ? i - P : a;
             pre[j] = lam[ip * C + c];
-            spre[j] = sink.load(ip);
-            visit(i, p, sv);
+            if (!kVec) spre[j] = sink.load(ip);
+            else if ((j & 3) == 3) refill_sink(j, i - P);
+            visit(i, j & 3, p, sv);
         }
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-        if (i0 - j >= a) visit(i0 - j, pre[j], spre[j]);
+        if (i0 - j >= a) visit(i0 - j, j & 3, pre[j], spre[j]);
     }
     const int64_t sc = s * C + c;
     ws.seg_unc[sc] = (int)(k + 1);
     ws.seg_lo[sc] = col ? x : glo;
     ws.seg_hi[sc] = col ? x : ghi;
+}
+
+template <typename T, class Prob, int P>
+__device__ __forceinline__ void bwd_sweep(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp,
+                                          int64_t s, int64_t c, int64_t a, int64_t b) {
+    const auto sink = Prob::sink(pp, sp);
+    if (sink.vec && (b & 3) == 0)
+        bwd_sweep_run<T, Prob, P, true>(ws, sink, s, c, a, b);
+    else
+        bwd_sweep_run<T, Prob, P, false>(ws, sink, s, c, a, b);
 }
 
 // True if the deque after node e - 1 equals the first pass's checkpoint there.

@@ -60,6 +60,10 @@ struct BColProb {
         }
         __device__ __forceinline__ T data(const Pre &p) const { return p.y + sigma * p.xb; }
         __device__ __forceinline__ T weight(const Pre &) const { return lam; }
+        static constexpr bool vec = false;  // lanes of a wave already read consecutive columns
+        __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
+            for (int k = 0; k < 4; ++k) o[k] = load(i + k);
+        }
     };
     struct Sink {
         const T *__restrict__ y;
@@ -75,6 +79,13 @@ struct BColProb {
         }
         __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
             yn[base + i * es] = (p.y + sigma * p.xb) - u;
+        }
+        static constexpr bool vec = false;
+        __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const {
+            for (int k = 0; k < 4; ++k) o[k] = load(i + k);
+        }
+        __device__ __forceinline__ void store4(int64_t i, const T (&u)[4], const SinkPre (&p)[4]) const {
+            for (int k = 0; k < 4; ++k) store(i + k, u[k], p[k]);
         }
     };
     static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t c, int64_t) {
@@ -115,12 +126,28 @@ struct BRowProb {
         const T *__restrict__ y;
         T tau, inv1p, w;
         int64_t base;
+        bool vec;  // the row's three streams are 16-byte aligned: load4 may be used
+        __device__ __forceinline__ Src(const T *f_, const T *x_, const T *y_, T tau_, T inv1p_, T w_, int64_t base_)
+            : f(f_), x(x_), y(y_), tau(tau_), inv1p(inv1p_), w(w_), base(base_),
+              vec(aligned16(f_ + base_) && aligned16(x_ + base_) && aligned16(y_ + base_)) {}
         __device__ __forceinline__ Pre load(int64_t i) const {
             Pre p;
             p.f = f[base + i];
             p.x = x[base + i];
             p.y = y[base + i];
             return p;
+        }
+        __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
+            T a[4], b[4], c[4];
+            vload4(f + base + i, a);
+            vload4(x + base + i, b);
+            vload4(y + base + i, c);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                o[k].f = a[k];
+                o[k].x = b[k];
+                o[k].y = c[k];
+            }
         }
         __device__ __forceinline__ T data(const Pre &p) const { return row_data(p.f, p.x, p.y, tau, inv1p); }
         __device__ __forceinline__ T weight(const Pre &) const { return w; }
@@ -131,10 +158,25 @@ struct BRowProb {
         T *__restrict__ xb;
         T theta;
         int64_t base;
+        bool vec;  // the row's streams are 16-byte aligned: load4 / store4 may be used
+        __device__ __forceinline__ Sink(const T *x_, T *xn_, T *xb_, T theta_, int64_t base_)
+            : x(x_), xn(xn_), xb(xb_), theta(theta_), base(base_),
+              vec(aligned16(x_ + base_) && aligned16(xn_ + base_) && aligned16(xb_ + base_)) {}
         __device__ __forceinline__ SinkPre load(int64_t i) const { return SinkPre{x[base + i]}; }
+        __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const {
+            T v[4];
+            vload4(x + base + i, v);
+            for (int k = 0; k < 4; ++k) o[k].x = v[k];
+        }
         __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
             xn[base + i] = u;
             xb[base + i] = u + theta * (u - p.x);
+        }
+        __device__ __forceinline__ void store4(int64_t i, const T (&u)[4], const SinkPre (&p)[4]) const {
+            T b[4];
+            for (int k = 0; k < 4; ++k) b[k] = u[k] + theta * (u[k] - p[k].x);
+            vstore4(xn + base + i, u);
+            vstore4(xb + base + i, b);
         }
     };
     static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t c, int64_t) {

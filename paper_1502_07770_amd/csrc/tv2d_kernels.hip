@@ -67,6 +67,10 @@ struct ColProb {
         }
         __device__ __forceinline__ T data(const Pre &p) const { return p.y + sigma * p.xb; }
         __device__ __forceinline__ T weight(const Pre &) const { return lam; }
+        static constexpr bool vec = false;  // lanes of a wave already read consecutive columns
+        __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
+            for (int k = 0; k < 4; ++k) o[k] = load(i + k);
+        }
     };
     struct Sink {
         const T *__restrict__ y;
@@ -82,6 +86,13 @@ struct ColProb {
         }
         __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
             yn[i * W + c] = (p.y + sigma * p.xb) - u;
+        }
+        static constexpr bool vec = false;
+        __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const {
+            for (int k = 0; k < 4; ++k) o[k] = load(i + k);
+        }
+        __device__ __forceinline__ void store4(int64_t i, const T (&u)[4], const SinkPre (&p)[4]) const {
+            for (int k = 0; k < 4; ++k) store(i + k, u[k], p[k]);
         }
     };
     static __device__ __forceinline__ ChainSpan span(const Params &, int64_t c, int64_t nmax) {
@@ -120,12 +131,29 @@ struct RowProb {
         const T *__restrict__ y;
         T tau, inv1p, w;
         int64_t r, ldf, W;
+        bool vec;  // the row's three streams are 16-byte aligned: load4 may be used
+        __device__ __forceinline__ Src(const T *f_, const T *x_, const T *y_, T tau_, T inv1p_, T w_, int64_t r_,
+                                       int64_t ldf_, int64_t W_)
+            : f(f_), x(x_), y(y_), tau(tau_), inv1p(inv1p_), w(w_), r(r_), ldf(ldf_), W(W_),
+              vec(aligned16(f_ + r_ * ldf_) && aligned16(x_ + r_ * W_) && aligned16(y_ + r_ * W_)) {}
         __device__ __forceinline__ Pre load(int64_t i) const {
             Pre p;
             p.f = f[r * ldf + i];
             p.x = x[r * W + i];
             p.y = y[r * W + i];
             return p;
+        }
+        __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
+            T a[4], b[4], c[4];
+            vload4(f + r * ldf + i, a);
+            vload4(x + r * W + i, b);
+            vload4(y + r * W + i, c);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                o[k].f = a[k];
+                o[k].x = b[k];
+                o[k].y = c[k];
+            }
         }
         __device__ __forceinline__ T data(const Pre &p) const { return row_data(p.f, p.x, p.y, tau, inv1p); }
         __device__ __forceinline__ T weight(const Pre &) const { return w; }
@@ -136,10 +164,25 @@ struct RowProb {
         T *__restrict__ xb;
         T theta;
         int64_t r, W;
+        bool vec;  // the row's streams are 16-byte aligned: load4 / store4 may be used
+        __device__ __forceinline__ Sink(const T *x_, T *xn_, T *xb_, T theta_, int64_t r_, int64_t W_)
+            : x(x_), xn(xn_), xb(xb_), theta(theta_), r(r_), W(W_),
+              vec(aligned16(x_ + r_ * W_) && aligned16(xn_ + r_ * W_) && aligned16(xb_ + r_ * W_)) {}
         __device__ __forceinline__ SinkPre load(int64_t i) const { return SinkPre{x[r * W + i]}; }
+        __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const {
+            T v[4];
+            vload4(x + r * W + i, v);
+            for (int k = 0; k < 4; ++k) o[k].x = v[k];
+        }
         __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
             xn[r * W + i] = u;
             xb[r * W + i] = u + theta * (u - p.x);
+        }
+        __device__ __forceinline__ void store4(int64_t i, const T (&u)[4], const SinkPre (&p)[4]) const {
+            T b[4];
+            for (int k = 0; k < 4; ++k) b[k] = u[k] + theta * (u[k] - p[k].x);
+            vstore4(xn + r * W + i, u);
+            vstore4(xb + r * W + i, b);
         }
     };
     static __device__ __forceinline__ ChainSpan span(const Params &, int64_t r, int64_t nmax) {
