@@ -212,6 +212,298 @@ __global__ __launch_bounds__(64) void k_chain_adjoint(ChainBatch b, const T *__r
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint for unit-stride chains (rows, CSR): one wave per chain.  The chain
+// is processed in chunks of 64 * kAdjV nodes held in registers, lane l owning
+// the kAdjV consecutive nodes [c0 + l kAdjV, c0 + (l + 1) kAdjV), so every
+// load and store of the wave covers contiguous memory.  Per chunk:
+//  - run ends: node i ends a run if i = n - 1 or x_i != x_{i+1};
+//  - a segmented prefix sum (FP64) and count of g over the runs, lane-local
+//    then across the wave, gives each run's total at its end, hence its mean;
+//  - a reverse segmented scan hands every node the mean of its run (the first
+//    run end at or after it);
+//  - grad_y = run mean; grad_w = s_e (mean_left - mean_right) on run
+//    boundaries e (s_e the sign of x_{e+1} - x_e), 0 inside runs.
+// A run still open at the end of a chunk carries its sum, count and start
+// into the next chunk; when it closes, its nodes in earlier chunks and the
+// boundary edge before it are written then.  Every output element is
+// written once.
+// ---------------------------------------------------------------------------
+constexpr int kAdjV = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_chain_adjoint_rows(ChainBatch b, const T *__restrict__ x,
+                                                           const T *__restrict__ g, T *__restrict__ gy,
+                                                           T *__restrict__ gw, int w_per_edge) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= b.num_chains) return;  // whole waves
+    const ChainSpan a = PlainProb<T, false>::span(
+        typename PlainProb<T, false>::Params{nullptr, nullptr, (T)0, nullptr, 1, b.cs, b.offsets}, c, b.n);
+    const int64_t n = a.n;
+    if (n <= 0) {
+        if (gw && !w_per_edge && lane == 0) gw[c] = (T)0;
+        return;
+    }
+    const T *__restrict__ xr = x + a.base;
+    const T *__restrict__ gr = g + a.base;
+    T *__restrict__ yr = gy ? gy + a.base : nullptr;
+    T *__restrict__ wr = (gw && w_per_edge) ? gw + a.base : nullptr;
+    const bool vec = aligned16(xr) && aligned16(gr) && (!yr || aligned16(yr)) && (!wr || aligned16(wr));
+    constexpr int64_t CH = 64 * kAdjV;
+    // run open at the start of the chunk (identical in every lane)
+    double o_sum = 0.0;
+    int64_t o_cnt = 0, o_start = 0;
+    // boundary edge whose right-hand run is the open run
+    int64_t p_edge = -1;
+    double p_mean = 0.0, p_sgn = 0.0;
+    double wsum = 0.0;  // this lane's part of the scalar-weight gradient
+    for (int64_t c0 = 0; c0 < n; c0 += CH) {
+        const int64_t i0 = c0 + lane * kAdjV;
+        T xv[kAdjV], gv[kAdjV];
+        const bool full = i0 + kAdjV <= n;
+        if (vec && full) {
+#pragma unroll
+            for (int q = 0; q < kAdjV; q += 4) {
+                T t[4], u[4];
+                vload4(xr + i0 + q, t);
+                vload4(gr + i0 + q, u);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    xv[q + m] = t[m];
+                    gv[q + m] = u[m];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kAdjV; ++k) {
+                const int64_t i = i0 + k;
+                xv[k] = i < n ? xr[i] : (T)0;
+                gv[k] = i < n ? gr[i] : (T)0;
+            }
+        }
+        T xnext_lane = __shfl_down(xv[0], 1, 64);
+        if (lane == 63) xnext_lane = (c0 + CH < n) ? xr[c0 + CH] : (T)0;
+        bool end[kAdjV];
+        T xn[kAdjV];
+#pragma unroll
+        for (int k = 0; k < kAdjV; ++k) {
+            const int64_t i = i0 + k;
+            xn[k] = (k + 1 < kAdjV) ? xv[k + 1] : xnext_lane;
+            end[k] = (i < n) && (i + 1 == n || xv[k] != xn[k]);
+        }
+        // lane-local segmented prefix sums and counts (reset after each end)
+        double ps[kAdjV];
+        int pc[kAdjV];
+        double acc = 0.0;
+        int cnt = 0;
+        bool has_end = false;
+#pragma unroll
+        for (int k = 0; k < kAdjV; ++k) {
+            if (i0 + k < n) {
+                acc += (double)gv[k];
+                ++cnt;
+            }
+            ps[k] = acc;
+            pc[k] = cnt;
+            if (end[k]) {
+                acc = 0.0;
+                cnt = 0;
+                has_end = true;
+            }
+        }
+        // across the wave: carry into each lane = sum / count since the last end
+        // in an earlier lane (or the chunk's open run)
+        double cs = acc;
+        int cc = cnt;
+        bool cf = has_end;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double s2 = __shfl_up(cs, off, 64);
+            const int c2 = __shfl_up(cc, off, 64);
+            const int f2 = __shfl_up((int)cf, off, 64);
+            if (lane >= off && !cf) {
+                cs = s2 + cs;
+                cc = c2 + cc;
+                cf = f2 != 0;
+            }
+        }
+        double ex_s = __shfl_up(cs, 1, 64);
+        int64_t ex_c = __shfl_up(cc, 1, 64);
+        bool ex_f = __shfl_up((int)cf, 1, 64) != 0;
+        if (lane == 0) {
+            ex_s = 0.0;
+            ex_c = 0;
+            ex_f = false;
+        }
+        if (!ex_f) {
+            ex_s = o_sum + ex_s;
+            ex_c += o_cnt;
+        }
+        // run means at run ends
+        double mean[kAdjV];
+        bool first = true;
+#pragma unroll
+        for (int k = 0; k < kAdjV; ++k) {
+            const double tot = first ? ex_s + ps[k] : ps[k];
+            const int64_t tc = first ? ex_c + pc[k] : pc[k];
+            mean[k] = end[k] ? tot / (double)tc : 0.0;
+            if (end[k]) first = false;
+        }
+        // reverse: the first end at or after each node
+        double val[kAdjV];
+        bool known[kAdjV];
+        {
+            double cur = 0.0;
+            bool kn = false;
+#pragma unroll
+            for (int k = kAdjV - 1; k >= 0; --k) {
+                if (end[k]) {
+                    cur = mean[k];
+                    kn = true;
+                }
+                val[k] = cur;
+                known[k] = kn;
+            }
+        }
+        double rv = val[0];  // the lane's first-end mean
+        bool rf = known[0];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double v2 = __shfl_down(rv, off, 64);
+            const int f2 = __shfl_down((int)rf, off, 64);
+            if (lane + off < 64 && !rf) {
+                rv = v2;
+                rf = f2 != 0;
+            }
+        }
+        const double chunk_first_mean = __shfl(rv, 0, 64);  // mean of the chunk's first run end
+        const bool chunk_has_end = __shfl((int)rf, 0, 64) != 0;
+        double nx_v = __shfl_down(rv, 1, 64);
+        bool nx_f = __shfl_down((int)rf, 1, 64) != 0;
+        if (lane == 63) nx_f = false;
+#pragma unroll
+        for (int k = 0; k < kAdjV; ++k) {
+            if (!known[k] && nx_f) {
+                val[k] = nx_v;
+                known[k] = true;
+            }
+        }
+        // the run open before this chunk closes at the chunk's first end
+        if ((o_cnt > 0 || p_edge >= 0) && chunk_has_end) {
+            const T m = (T)chunk_first_mean;
+            if (yr)
+                for (int64_t i = o_start + lane; i < c0; i += 64) yr[i] = m;
+            if (p_edge >= 0 && lane == 0) {
+                const double d = p_sgn * (p_mean - chunk_first_mean);
+                if (wr) wr[p_edge] = (T)d;
+                wsum += d;
+            }
+            o_cnt = 0;
+            p_edge = -1;
+        }
+        // grad_y of nodes whose run closes in this chunk
+        if (yr) {
+            bool all = full && vec;
+#pragma unroll
+            for (int k = 0; k < kAdjV; ++k) all = all && known[k];
+            if (all) {
+#pragma unroll
+                for (int q = 0; q < kAdjV; q += 4) {
+                    const T t[4] = {(T)val[q], (T)val[q + 1], (T)val[q + 2], (T)val[q + 3]};
+                    vstore4(yr + i0 + q, t);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kAdjV; ++k)
+                    if (i0 + k < n && known[k]) yr[i0 + k] = (T)val[k];
+            }
+        }
+        // grad_w: the mean right of a boundary is the next node's value
+        const double v0_next = __shfl_down(val[0], 1, 64);
+        const bool k0_next = __shfl_down((int)known[0], 1, 64) != 0;
+        double dw[kAdjV];
+        bool dw_ok[kAdjV];
+        int64_t pend_i = -1;
+        double pend_m = 0.0, pend_s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kAdjV; ++k) {
+            const int64_t i = i0 + k;
+            double vr;
+            bool kr;
+            if (k + 1 < kAdjV) {
+                vr = val[k + 1];
+                kr = known[k + 1];
+            } else {
+                vr = v0_next;
+                kr = (lane < 63) && k0_next;
+            }
+            dw[k] = 0.0;
+            dw_ok[k] = i < n;
+            if (i < n && end[k] && i + 1 < n) {
+                const double sg = (xn[k] > xv[k]) ? 1.0 : -1.0;
+                if (kr) {
+                    dw[k] = sg * (mean[k] - vr);
+                } else {  // the right-hand run is still open
+                    dw_ok[k] = false;
+                    pend_i = i;
+                    pend_m = mean[k];
+                    pend_s = sg;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kAdjV; ++k)
+            if (dw_ok[k]) wsum += dw[k];
+        if (wr) {
+            bool all = full && vec;
+#pragma unroll
+            for (int k = 0; k < kAdjV; ++k) all = all && dw_ok[k];
+            if (all) {
+#pragma unroll
+                for (int q = 0; q < kAdjV; q += 4) {
+                    const T t[4] = {(T)dw[q], (T)dw[q + 1], (T)dw[q + 2], (T)dw[q + 3]};
+                    vstore4(wr + i0 + q, t);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kAdjV; ++k)
+                    if (dw_ok[k]) wr[i0 + k] = (T)dw[k];
+            }
+        }
+        // carry: the run open at the end of the chunk (never the chain's last run)
+        const int64_t c1 = (c0 + CH < n) ? c0 + CH : n;
+        if (c1 < n) {
+            const double t_s = __shfl(cs, 63, 64);
+            const int64_t t_c = __shfl(cc, 63, 64);
+            const bool t_f = __shfl((int)cf, 63, 64) != 0;
+            if (t_f) {  // the open run started in this chunk
+                o_sum = t_s;
+                o_cnt = t_c;
+                o_start = c1 - t_c;
+                // its left boundary edge, if it is pending, lives in some lane
+                const unsigned long long bal = __ballot(pend_i >= 0);
+                if (bal) {
+                    const int src = 63 - __clzll(bal);  // the last lane with a pending edge
+                    p_edge = __shfl(pend_i, src, 64);
+                    p_mean = __shfl(pend_m, src, 64);
+                    p_sgn = __shfl(pend_s, src, 64);
+                }
+            } else {  // no end in the whole chunk: the open run grows (or starts at c0)
+                if (o_cnt == 0) o_start = c0;
+                o_sum = o_sum + t_s;
+                o_cnt += t_c;
+            }
+        }
+    }
+    if (gw && !w_per_edge) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, 64);
+        if (lane == 0) gw[c] = (T)wsum;
+    }
+    if (wr && lane == 0) wr[n - 1] = (T)0;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -279,6 +571,13 @@ template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,
                                 int w_per_edge, hipStream_t stream) {
     if (b.num_chains <= 0) return hipSuccess;
+    if (b.offsets || b.es == 1) {  // unit-stride chains: one wave per chain, contiguous accesses
+        const unsigned blocks = (unsigned)((b.num_chains + 3) / 4);
+        hipLaunchKernelGGL((k_chain_adjoint_rows<T>), dim3(blocks), dim3(256), 0, stream, b, x, g, gy, gw,
+                           w_per_edge);
+        return hipGetLastError();
+    }
+    // strided chains (columns): one lane per chain, lanes read consecutive chains
     const unsigned blocks = (unsigned)((b.num_chains + 63) / 64);
     hipLaunchKernelGGL((k_chain_adjoint<T>), dim3(blocks), dim3(64), 0, stream, b, x, g, gy, gw,
                        w_per_edge);

@@ -143,3 +143,81 @@ def test_column_layout_backward():
     dyo, dwo = oracle.chain_adjoint(xo, g)
     assert np.abs(dy.cpu().numpy().T - dyo).max() < 1e-12
     assert np.abs(dw.cpu().numpy().T[:, :-1] - dwo[:, :-1]).max() < 1e-12
+
+
+def _designed_runs(n, seed):
+    """Chains whose run structure is set by hand: ends exactly at the 1024-node
+    chunk edges, one run over the whole chain, ends next to chunk edges, long
+    random runs, short random runs and all-singleton runs."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    def from_bounds(bounds):
+        x = np.zeros(n)
+        level = 0.0
+        prev = 0
+        for bnd in list(bounds) + [n]:
+            level += rng.choice([-1.0, 1.0]) * rng.uniform(0.1, 1.0)
+            x[prev:bnd] = level
+            prev = bnd
+        return x
+    rows.append(from_bounds(range(1024, n, 1024)))
+    rows.append(np.full(n, 0.7))
+    rows.append(from_bounds(sorted({1023, 1025, 2047, 2049, 3071})))
+    long_runs = np.cumsum(rng.geometric(1 / 300, size=64))
+    rows.append(from_bounds(long_runs[long_runs < n]))
+    rows.append(from_bounds(np.unique(rng.integers(1, n, size=n // 5))))
+    rows.append(rng.normal(size=n))
+    rows.append(from_bounds([1]))
+    rows.append(from_bounds([n - 1]))
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-6)])
+@pytest.mark.parametrize("n", [4100, 1024, 2048, 37])
+def test_rows_adjoint_across_chunks(dtype, tol, n):
+    """Unit-stride adjoint (wave per chain, 1024-node chunks): runs crossing,
+    ending at and spanning chunk edges, against the oracle's formulas."""
+    x = _designed_runs(n, seed=n)
+    g = synth.normal(x.shape, seed=n + 1)
+    xt, gt = _dev(x, dtype), _dev(g, dtype)
+    dy, dw = binding.chain_prox_backward(xt, gt, dim=-1, per_edge_w=True)
+    _, dws = binding.chain_prox_backward(xt, gt, dim=-1, per_edge_w=False, need_y=False)
+    xv, gv = xt.double().cpu().numpy(), gt.double().cpu().numpy()
+    dyo, dwo = oracle.chain_adjoint(xv, gv)
+    _, dwso = oracle.chain_adjoint(xv, gv, scalar_w=True)
+    scale = max(1.0, np.abs(dyo).max())
+    assert np.abs(dy.double().cpu().numpy() - dyo).max() <= tol * scale
+    assert np.abs(dw.double().cpu().numpy()[:, :-1] - dwo[:, :-1]).max() <= tol * scale
+    assert (dw.double().cpu().numpy()[:, -1] == 0).all()
+    assert np.abs(dws.double().cpu().numpy() - dwso).max() <= tol * max(1.0, np.abs(dwso).max()) * 10
+
+
+def test_rows_adjoint_csr_chains():
+    """Uneven chains given by CSR offsets go through the unit-stride adjoint."""
+    import ctypes
+    rng = np.random.default_rng(3)
+    lens = [1, 2, 1023, 1024, 1025, 3000, 0, 77]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    xs = [np.repeat(rng.normal(size=max(1, L // 50 + 1)), 50)[:L] for L in lens]
+    x = np.concatenate(xs)
+    g = rng.normal(size=x.size)
+    xt, gt = _dev(x, torch.float64), _dev(g, torch.float64)
+    dy = torch.empty_like(xt)
+    dw = torch.empty_like(xt)
+    ot = torch.tensor(offs, device="cuda")
+    lib = binding.load()
+    lay = binding.ChainLayout(len(lens), max(lens), 1, 1, ctypes.c_void_p(ot.data_ptr()))
+    st = lib.tv_chain_prox_backward(ctypes.byref(lay), binding.TV_F64, ctypes.c_void_p(xt.data_ptr()),
+                                    ctypes.c_void_p(gt.data_ptr()), ctypes.c_void_p(dy.data_ptr()),
+                                    ctypes.c_void_p(dw.data_ptr()), 1, None, 0,
+                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    torch.cuda.synchronize()
+    dyv, dwv = dy.cpu().numpy(), dw.cpu().numpy()
+    for c, L in enumerate(lens):
+        if L == 0:
+            continue
+        sl = slice(offs[c], offs[c + 1])
+        dyo, dwo = oracle.chain_adjoint(x[sl][None], g[sl][None])
+        assert np.abs(dyv[sl] - dyo[0]).max() < 1e-12
+        assert np.abs(dwv[sl][:-1] - dwo[0][:-1]).max(initial=0.0) < 1e-12
