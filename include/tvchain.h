@@ -109,6 +109,30 @@ tv_status tv_chain_prox_multi(int num_batches, const tv_chain_layout *layouts, t
                               const void *const *y, const void *const *w, const double *w_scalar,
                               void *const *x, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* [host] What the autotuner chose. */
+typedef struct {
+    int64_t segment_length; /* nodes per segment (lane) of a chain                 */
+    int64_t halo;           /* nodes each segment's run starts before the segment  */
+    int ring_slots;         /* breakpoint slots of the on-chip deque (16 or 32)     */
+    int candidates;         /* plans timed                                          */
+    double ms;              /* time of one launch with the chosen plan              */
+} tv_tuning_result;
+
+/* Autotuner of the chain-prox launch (segmentation and on-chip deque size):
+ * times every candidate plan that fits the workspace on this data (one untimed
+ * and three timed launches each, HIP events on `stream`) and makes the fastest
+ * the plan of every later tv_chain_prox / tv_chain_prox_multi launch with the
+ * same total number of chains and (maximum) length, in this process.
+ * Arguments as tv_chain_prox_multi; x receives the prox.  Synchronous.  Results
+ * never depend on the plan (the segmented solve is exact), only speed does.
+ * The workspace queries above already reserve room for every candidate. */
+tv_status tv_chain_prox_autotune(int num_batches, const tv_chain_layout *layouts, tv_dtype dtype,
+                                 const void *const *y, const void *const *w, const double *w_scalar,
+                                 void *const *x, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                                 tv_tuning_result *chosen);
+/* Forget every plan chosen by the autotuners (chain prox and 2D solvers). */
+void tv_autotune_clear(void);
+
 /* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
 size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);
 
@@ -170,8 +194,27 @@ tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_
                      double lambda, void *x, const tv2d_options *options, tv2d_stats *stats,
                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Autotuner of tv2d_solve's two chain launches (the column and the row step):
+ * sets up the first iteration from f in the workspace, times every candidate
+ * plan of each launch that fits the workspace and makes the fastest the plan
+ * of every later tv2d_solve of an H x W image in this process.  Overwrites
+ * the solver state held in the workspace (run a fresh solve after it, not a
+ * resume).  Synchronous.  The solve's results do not depend on the plans. */
+tv_status tv2d_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda,
+                        double tau0, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                        tv_tuning_result *col, tv_tuning_result *row);
+
 /* Bytes of device workspace tv2d_solve_batched needs. H, W: [host] arrays. */
 size_t tv2d_batched_workspace(int num_images, const int64_t *H, const int64_t *W, tv_dtype dtype);
+
+/* Autotuner of tv2d_solve_batched's two chain launches, as tv2d_autotune, for
+ * this batch geometry (later batched solves with the same number of rows and
+ * columns and the same largest H and W use the chosen plans).  Overwrites the
+ * solver state in the workspace.  Synchronous. */
+tv_status tv2d_batched_autotune(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
+                                const int64_t *pixel_offsets, const double *lambda, const void *f, double tau0,
+                                void *workspace, size_t workspace_bytes, hipStream_t stream,
+                                tv_tuning_result *col, tv_tuning_result *row);
 
 /* Many independent 2D ROF problems of different sizes in one solve: every
  * image's row chains run in one launch and its column chains in another, each

@@ -9,6 +9,7 @@ Functions mirror the C entry points:
 
 * ``chain_prox(y, w, dim)``            -> tv_chain_prox (eq. (1D-ROF), Sec. 4.1)
 * ``chain_prox_multi(items, w)``      -> tv_chain_prox_multi (several batches, one launch)
+* ``autotune_chain_prox(items, w)``   -> tv_chain_prox_autotune (plan per shape)
 * ``chain_prox_backward(x, g, ...)``   -> tv_chain_prox_backward
 * ``prox(y, w, dim)``                  -> autograd-aware chain prox
 * ``tv2d(f, lam, ...)``                -> tv2d_solve (Sec. 5.1)
@@ -58,6 +59,15 @@ class Tuning(ctypes.Structure):
     _fields_ = [("target_lanes", ctypes.c_int64), ("min_segment", ctypes.c_int64), ("halo", ctypes.c_int64)]
 
 
+class TuningResult(ctypes.Structure):
+    _fields_ = [("segment_length", ctypes.c_int64), ("halo", ctypes.c_int64), ("ring_slots", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"segment_length": int(self.segment_length), "halo": int(self.halo),
+                "ring_slots": int(self.ring_slots), "candidates": int(self.candidates), "ms": float(self.ms)}
+
+
 class Tv2dStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("gap_norm", ctypes.c_double),
                 ("primal", ctypes.c_double), ("dual", ctypes.c_double)]
@@ -78,6 +88,13 @@ _SIG = {
     "tv_chain_prox_multi_workspace": (ctypes.c_size_t, [ctypes.c_int, _P, ctypes.c_int]),
     "tv_chain_prox_multi": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                            _P]),
+    "tv_chain_prox_autotune": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                              _P, _P]),
+    "tv_autotune_clear": (None, []),
+    "tv2d_autotune": (ctypes.c_int, [ctypes.c_int, _P, _I64, _I64, _I64, ctypes.c_double, ctypes.c_double, _P,
+                                     ctypes.c_size_t, _P, _P, _P]),
+    "tv2d_batched_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_double, _P,
+                                             ctypes.c_size_t, _P, _P, _P]),
     "tv_set_tuning": (ctypes.c_int, [_P]),
     "tv_get_tuning": (ctypes.c_int, [_P]),
     "tv_chain_prox_segment_length": (_I64, [_P]),
@@ -237,15 +254,14 @@ def chain_prox(y: torch.Tensor, w: Union[float, torch.Tensor] = 0.0, dim: int = 
 MAX_CHAIN_BATCHES = 8
 
 
-def chain_prox_multi(items, w: Union[float, list] = 0.0) -> list:
-    """Exact TV prox of several batches of chains in one launch
-    (tv_chain_prox_multi).  ``items`` is a list of ``(y, dim)`` pairs (one
-    dtype, one device); ``w`` is one scalar weight for every batch or a list
-    with one per batch.  Returns the outputs in the order of ``items``;
-    they are bit-identical to separate ``chain_prox`` calls."""
+def autotune_clear() -> None:
+    """Forget every plan chosen by the autotuners."""
+    load().tv_autotune_clear()
+
+
+def _multi_args(items, w):
     if not 1 <= len(items) <= MAX_CHAIN_BATCHES:
         raise TvChainError(TV_ERR_INVALID_ARG, "chain_prox_multi takes 1..%d batches" % MAX_CHAIN_BATCHES)
-    lib = load()
     ys = [y for y, _ in items]
     _require_gpu(*ys)
     dev, code = ys[0].device, _dtype_code(ys[0])
@@ -259,6 +275,32 @@ def chain_prox_multi(items, w: Union[float, list] = 0.0) -> list:
     yp = (ctypes.c_void_p * nb)(*[v.data_ptr() for v, _, _ in views])
     xp = (ctypes.c_void_p * nb)(*[x.data_ptr() for x in xs])
     wsc = (ctypes.c_double * nb)(*[float(v) for v in wl])
+    return dev, code, nb, views, xs, lays, yp, xp, wsc
+
+
+def autotune_chain_prox(items, w: Union[float, list] = 0.0) -> dict:
+    """Autotune the launch of these chain batches (tv_chain_prox_autotune): later
+    chain_prox / chain_prox_multi calls with the same total number of chains and
+    length use the fastest plan.  Returns the chosen plan."""
+    lib = load()
+    dev, code, nb, views, xs, lays, yp, xp, wsc = _multi_args(items, w)
+    nbytes = lib.tv_chain_prox_multi_workspace(nb, lays, code)
+    ws = _workspace(nbytes, dev)
+    res = TuningResult()
+    st = lib.tv_chain_prox_autotune(nb, lays, code, yp, None, wsc, xp, _ptr(ws), nbytes,
+                                    ctypes.c_void_p(_stream_ptr(dev)), ctypes.byref(res))
+    _check(st, "tv_chain_prox_autotune")
+    return res.as_dict()
+
+
+def chain_prox_multi(items, w: Union[float, list] = 0.0) -> list:
+    """Exact TV prox of several batches of chains in one launch
+    (tv_chain_prox_multi).  ``items`` is a list of ``(y, dim)`` pairs (one
+    dtype, one device); ``w`` is one scalar weight for every batch or a list
+    with one per batch.  Returns the outputs in the order of ``items``;
+    they are bit-identical to separate ``chain_prox`` calls."""
+    lib = load()
+    dev, code, nb, views, xs, lays, yp, xp, wsc = _multi_args(items, w)
     nbytes = lib.tv_chain_prox_multi_workspace(nb, lays, code)
     ws = _workspace(nbytes, dev)
     st = lib.tv_chain_prox_multi(nb, lays, code, yp, None, wsc, xp, _ptr(ws), nbytes,
@@ -351,6 +393,22 @@ class Tv2dSolver:
             raise TvChainError(TV_ERR_INVALID_ARG, "tv2d_workspace")
         self.ws = _workspace(self.nbytes, self.device)
 
+    def autotune(self, f: torch.Tensor, lam: float, tau0: float = 1.0) -> dict:
+        """Choose the fastest plans of the column and row launches for this
+        image size (tv2d_autotune).  Resets the solver state (no resume after
+        it).  Returns {"col": plan, "row": plan}."""
+        _require_gpu(f)
+        if f.shape != (self.H, self.W) or f.dtype != self.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "f must be (%d, %d) %s" % (self.H, self.W, self.dtype))
+        if f.stride(1) != 1:
+            f = f.contiguous()
+        col, row = TuningResult(), TuningResult()
+        st = load().tv2d_autotune(self.code, _ptr(f), self.H, self.W, f.stride(0), float(lam), float(tau0),
+                                  _ptr(self.ws), self.nbytes, ctypes.c_void_p(_stream_ptr(f.device)),
+                                  ctypes.byref(col), ctypes.byref(row))
+        _check(st, "tv2d_autotune")
+        return {"col": col.as_dict(), "row": row.as_dict()}
+
     def solve(self, f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10,
               gap_tol: float = 0.0, tau0: float = 1.0, resume: bool = False,
               gap_history: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
@@ -396,7 +454,8 @@ def tv2d(f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10, 
 
 
 def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol: float = 0.0,
-                 tau0: float = 1.0, packed: Optional[torch.Tensor] = None):
+                 tau0: float = 1.0, packed: Optional[torch.Tensor] = None, autotune: bool = False,
+                 tuned: Optional[dict] = None):
     """Solve many 2D ROF problems of different sizes in one call
     (tv2d_solve_batched).  ``images`` is a list of (H_j, W_j) GPU tensors of one
     dtype (or a list of shapes when ``packed`` holds them back to back);
@@ -426,6 +485,14 @@ def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol
     if nbytes == 0:
         raise TvChainError(TV_ERR_INVALID_ARG, "tv2d_batched_workspace")
     ws = _workspace(nbytes, packed.device)
+    if autotune:  # choose the launch plans first (tv2d_batched_autotune); the solve below uses them
+        col, row = TuningResult(), TuningResult()
+        st = lib.tv2d_batched_autotune(code, n, Hs, Ws, Os, Ls, _ptr(packed), float(tau0), _ptr(ws), nbytes,
+                                       ctypes.c_void_p(_stream_ptr(packed.device)), ctypes.byref(col),
+                                       ctypes.byref(row))
+        _check(st, "tv2d_batched_autotune")
+        if tuned is not None:
+            tuned.update({"col": col.as_dict(), "row": row.as_dict()})
     x = torch.empty_like(packed)
     opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 0, None)
     stats = (Tv2dStats * n)()

@@ -1,6 +1,9 @@
 // api_chain.hip -- C ABI of the batched chain prox and its adjoint.
 #include <math.h>
 
+#include <map>
+#include <mutex>
+
 #include "../../include/tvchain.h"
 #include "kernels.h"
 
@@ -17,7 +20,7 @@ static int64_t round_tile(int64_t v) { return (v + kTile - 1) / kTile * kTile; }
 
 // Enough segments per chain that the launch has about target_lanes lanes,
 // with segments no shorter than min_segment; L, H and CK are tile multiples.
-SegPlan seg_plan(int64_t num_chains, int64_t n) {
+SegPlan seg_default_plan(int64_t num_chains, int64_t n) {
     const SegTuning &t = seg_tuning();
     SegPlan p;
     int64_t S = num_chains > 0 ? (t.target_lanes + num_chains - 1) / num_chains : 1;
@@ -28,7 +31,43 @@ SegPlan seg_plan(int64_t num_chains, int64_t n) {
     if (p.L < kTile) p.L = kTile;
     p.H = round_tile(t.halo);
     p.CK = 16;  // checkpoints at a + 16, 32, 48, 64 (tile multiples)
+    p.K = kRingSlots;
     return p;
+}
+
+// Plans chosen by the autotuner, per (kind, chains, length).
+namespace {
+struct TunedKey {
+    int kind;
+    int64_t C, n;
+    bool operator<(const TunedKey &o) const {
+        return kind != o.kind ? kind < o.kind : (C != o.C ? C < o.C : n < o.n);
+    }
+};
+std::mutex g_tuned_mu;
+std::map<TunedKey, SegPlan> &tuned_map() {
+    static std::map<TunedKey, SegPlan> m;
+    return m;
+}
+}  // namespace
+
+SegPlan seg_plan(int64_t num_chains, int64_t n, int kind) {
+    {
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        auto it = tuned_map().find(TunedKey{kind, num_chains, n});
+        if (it != tuned_map().end()) return it->second;
+    }
+    return seg_default_plan(num_chains, n);
+}
+
+void seg_set_tuned(int kind, int64_t num_chains, int64_t n, const SegPlan &p) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    tuned_map()[TunedKey{kind, num_chains, n}] = p;
+}
+
+void seg_clear_tuned() {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    tuned_map().clear();
 }
 
 // Host-side checks of a layout; no HIP call.
@@ -85,16 +124,45 @@ static bool overlaps(const tv_chain_layout *Lx, const void *x, const tv_chain_la
     return a0 < b1 && b0 < a1;
 }
 
+// Room for any plan the autotuner may choose for this shape.
 static size_t prox_ws_bytes(const tv_chain_layout *L, tv_dtype dt) {
-    const ChainBatch b = to_batch(L);
-    const SegPlan plan = seg_plan(b.num_chains, b.n);
-    return dt == TV_F32 ? chain_prox_ws_bytes<float>(b, plan) : chain_prox_ws_bytes<double>(b, plan);
+    return dt == TV_F32 ? seg_bytes_max<float>(L->num_chains, L->length, kPlanChain)
+                        : seg_bytes_max<double>(L->num_chains, L->length, kPlanChain);
 }
 
 static tv_status device_check() {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
     return TV_OK;
+}
+
+// Times one launch of the given plan (after one untimed run) with HIP events.
+template <typename T>
+hipError_t time_multi(int nb, const ChainBatch *bs, const void *const *y, const void *const *w,
+                             const double *w_scalar, void *const *x, void *workspace, const SegPlan &plan,
+                             hipStream_t stream, int reps, float *ms) {
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return e;
+    }
+    auto run = [&]() {
+        return launch_chain_prox_multi<T>(nb, bs, (const T *const *)y, (const T *const *)w, w_scalar,
+                                          (T *const *)x, workspace, plan, stream);
+    };
+    e = run();
+    if (e == hipSuccess) e = hipEventRecord(e0, stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = run();
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e == hipSuccess) *ms /= (float)reps;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return e;
 }
 
 }  // namespace tvc
@@ -130,12 +198,12 @@ tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const voi
     if (!y || !x) return TV_ERR_INVALID_ARG;
     if (!w && !(isfinite(w_scalar) && w_scalar >= 0.0)) return TV_ERR_INVALID_ARG;
     if (overlaps(layout, x, layout, y, dtype) || overlaps(layout, x, layout, w, dtype)) return TV_ERR_INVALID_ARG;
-    const size_t need = prox_ws_bytes(layout, dtype);
+    const ChainBatch b = to_batch(layout);
+    const SegPlan plan = seg_plan(b.num_chains, b.n);
+    const size_t need = dtype == TV_F32 ? chain_prox_ws_bytes<float>(b, plan) : chain_prox_ws_bytes<double>(b, plan);
     if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
     tv_status st = device_check();
     if (st != TV_OK) return st;
-    const ChainBatch b = to_batch(layout);
-    const SegPlan plan = seg_plan(b.num_chains, b.n);
     hipError_t e;
     if (dtype == TV_F32)
         e = launch_chain_prox<float>(b, (const float *)y, (const float *)w, (float)w_scalar, (float *)x,
@@ -163,9 +231,7 @@ static bool multi_ok(int nb, const tv_chain_layout *layouts, tv_dtype dtype, int
 size_t tv_chain_prox_multi_workspace(int num_batches, const tv_chain_layout *layouts, tv_dtype dtype) {
     int64_t C, n;
     if (!multi_ok(num_batches, layouts, dtype, &C, &n) || C == 0) return 0;
-    const SegPlan plan = seg_plan(C, n);
-    ChainBatch all{C, n, 1, n, nullptr};
-    return dtype == TV_F32 ? chain_prox_ws_bytes<float>(all, plan) : chain_prox_ws_bytes<double>(all, plan);
+    return dtype == TV_F32 ? seg_bytes_max<float>(C, n, kPlanChain) : seg_bytes_max<double>(C, n, kPlanChain);
 }
 
 tv_status tv_chain_prox_multi(int num_batches, const tv_chain_layout *layouts, tv_dtype dtype,
@@ -201,6 +267,62 @@ tv_status tv_chain_prox_multi(int num_batches, const tv_chain_layout *layouts, t
                                             w_scalar, (double *const *)x, workspace, plan, stream);
     return e == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
+
+tv_status tv_chain_prox_autotune(int num_batches, const tv_chain_layout *layouts, tv_dtype dtype,
+                                 const void *const *y, const void *const *w, const double *w_scalar,
+                                 void *const *x, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                                 tv_tuning_result *chosen) {
+    int64_t C, n;
+    if (!multi_ok(num_batches, layouts, dtype, &C, &n)) return TV_ERR_INVALID_ARG;
+    if (C == 0) return TV_OK;
+    if (!y || !x || (!w && !w_scalar)) return TV_ERR_INVALID_ARG;
+    ChainBatch bs[kMaxChainBatches];
+    for (int b = 0; b < num_batches; ++b) {
+        if (layouts[b].num_chains > 0 && (!y[b] || !x[b] || (w && !w[b]))) return TV_ERR_INVALID_ARG;
+        if (!w && !(isfinite(w_scalar[b]) && w_scalar[b] >= 0.0)) return TV_ERR_INVALID_ARG;
+        for (int o = 0; o < num_batches; ++o) {
+            if (overlaps(&layouts[b], x[b], &layouts[o], y[o], dtype)) return TV_ERR_INVALID_ARG;
+            if (w && overlaps(&layouts[b], x[b], &layouts[o], w[o], dtype)) return TV_ERR_INVALID_ARG;
+            if (o != b && overlaps(&layouts[b], x[b], &layouts[o], x[o], dtype)) return TV_ERR_INVALID_ARG;
+        }
+        bs[b] = to_batch(&layouts[b]);
+    }
+    if (!workspace) return TV_ERR_WORKSPACE;
+    tv_status st = device_check();
+    if (st != TV_OK) return st;
+    SegPlan cand[64];
+    const int m = dtype == TV_F32 ? seg_candidates<float>(C, n, cand, 64) : seg_candidates<double>(C, n, cand, 64);
+    int best = -1, tried = 0;
+    float best_ms = 0.0f;
+    for (int j = 0; j < m; ++j) {
+        const size_t need = dtype == TV_F32 ? seg_ws_bytes_plan<float>(C, n, cand[j])
+                                            : seg_ws_bytes_plan<double>(C, n, cand[j]);
+        if (need > workspace_bytes) continue;
+        float ms = 0.0f;
+        const hipError_t e =
+            dtype == TV_F32
+                ? time_multi<float>(num_batches, bs, y, w, w_scalar, x, workspace, cand[j], stream, 3, &ms)
+                : time_multi<double>(num_batches, bs, y, w, w_scalar, x, workspace, cand[j], stream, 3, &ms);
+        if (e != hipSuccess) return TV_ERR_HIP;
+        ++tried;
+        if (best < 0 || ms < best_ms) {
+            best = j;
+            best_ms = ms;
+        }
+    }
+    if (best < 0) return TV_ERR_WORKSPACE;
+    seg_set_tuned(kPlanChain, C, n, cand[best]);
+    if (chosen) {
+        chosen->segment_length = cand[best].L;
+        chosen->halo = cand[best].H;
+        chosen->ring_slots = cand[best].K;
+        chosen->candidates = tried;
+        chosen->ms = best_ms;
+    }
+    return TV_OK;
+}
+
+void tv_autotune_clear(void) { seg_clear_tuned(); }
 
 tv_status tv_set_tuning(const tv_tuning *t) {
     if (!t) {

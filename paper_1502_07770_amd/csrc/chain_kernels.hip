@@ -510,16 +510,14 @@ template <typename T>
 hipError_t launch_chain_prox(const ChainBatch &b, const T *y, const T *w, T w_scalar, T *x, void *workspace,
                              const SegPlan &plan, hipStream_t stream) {
     if (b.num_chains <= 0) return hipSuccess;
-    SegWs<T> ws;
-    seg_ws_layout<T, kRingSlots>(workspace, b.num_chains, b.n, plan.L, plan.H, plan.CK, &ws);
     if (w) {
         using Prob = PlainProb<T, true>;
         typename Prob::Params pp{y, w, w_scalar, x, b.es, b.cs, b.offsets};
-        return seg_launch<T, Prob, kRingSlots, kTile>(ws, pp, stream);
+        return seg_run<T, Prob, kTile>(workspace, b.num_chains, b.n, plan, pp, stream);
     }
     using Prob = PlainProb<T, false>;
     typename Prob::Params pp{y, w, w_scalar, x, b.es, b.cs, b.offsets};
-    return seg_launch<T, Prob, kRingSlots, kTile>(ws, pp, stream);
+    return seg_run<T, Prob, kTile>(workspace, b.num_chains, b.n, plan, pp, stream);
 }
 
 template <typename T>
@@ -532,8 +530,6 @@ hipError_t launch_chain_prox_multi(int nb, const ChainBatch *bs, const T *const 
         n = bs[b].n > n ? bs[b].n : n;
     }
     if (C <= 0) return hipSuccess;
-    SegWs<T> ws;
-    seg_ws_layout<T, kRingSlots>(workspace, C, n, plan.L, plan.H, plan.CK, &ws);
     auto fill = [&](auto &pp) {
         pp.nb = nb;
         int64_t c0 = 0;
@@ -554,18 +550,74 @@ hipError_t launch_chain_prox_multi(int nb, const ChainBatch *bs, const T *const 
         using Prob = MultiProb<T, true>;
         typename Prob::Params pp;
         fill(pp);
-        return seg_launch<T, Prob, kRingSlots, kTile>(ws, pp, stream);
+        return seg_run<T, Prob, kTile>(workspace, C, n, plan, pp, stream);
     }
     using Prob = MultiProb<T, false>;
     typename Prob::Params pp;
     fill(pp);
-    return seg_launch<T, Prob, kRingSlots, kTile>(ws, pp, stream);
+    return seg_run<T, Prob, kTile>(workspace, C, n, plan, pp, stream);
 }
 
 template <typename T>
 size_t chain_prox_ws_bytes(const ChainBatch &b, const SegPlan &plan) {
-    return seg_ws_layout<T, kRingSlots>(nullptr, b.num_chains, b.n, plan.L, plan.H, plan.CK, nullptr);
+    return seg_ws_bytes<T>(b.num_chains, b.n, plan);
 }
+
+// Autotuner candidates: segment lengths 32 .. 1024, halos 64 and 128, rings of
+// 16 or 32 slots (32 only where segments are at least 4 times longer, to bound
+// the saved deques), keeping only plans whose workspace stays within twice the
+// default plan's (or the default's plus 64 MiB).  Segment lengths at or above
+// the chain length are all the same plan; only the shortest is kept.
+template <typename T>
+int seg_candidates(int64_t C, int64_t n, SegPlan *out, int max_out) {
+    const SegPlan d = seg_default_plan(C, n);
+    const size_t base = seg_ws_bytes<T>(C, n, d);
+    const size_t cap = (2 * base > base + (size_t(64) << 20)) ? 2 * base : base + (size_t(64) << 20);
+    int m = 0;
+    if (m < max_out) out[m++] = d;
+    bool whole = false;
+    for (int64_t L = 32; L <= 1024 && !whole; L *= 2) {
+        const int64_t Lr = (L >= n) ? ((n + kTile - 1) / kTile) * kTile : L;
+        whole = L >= n;
+        for (int K = 16; K <= 32; K *= 2) {
+            if (K * 4 > Lr && K > 16) continue;
+            for (int64_t H = 64; H <= 128; H *= 2) {
+                const SegPlan p{Lr, H, 16, K};
+                if (seg_ws_bytes<T>(C, n, p) > cap) continue;
+                bool dup = false;
+                for (int j = 0; j < m; ++j)
+                    dup = dup || (out[j].L == p.L && out[j].H == p.H && out[j].K == p.K);
+                if (!dup && m < max_out) out[m++] = p;
+            }
+        }
+    }
+    return m;
+}
+
+template <typename T>
+size_t seg_bytes_max(int64_t C, int64_t n, int kind) {
+    SegPlan c[64];
+    const int m = seg_candidates<T>(C, n, c, 64);
+    size_t mx = 0;
+    for (int j = 0; j < m; ++j) {
+        const size_t b = seg_ws_bytes<T>(C, n, c[j]);
+        mx = b > mx ? b : mx;
+    }
+    // a plan tuned for this shape earlier (or set by hand) must fit too
+    const size_t t = seg_ws_bytes<T>(C, n, seg_plan(C, n, kind));
+    return t > mx ? t : mx;
+}
+
+template <typename T>
+size_t seg_ws_bytes_plan(int64_t C, int64_t n, const SegPlan &plan) {
+    return seg_ws_bytes<T>(C, n, plan);
+}
+template size_t seg_ws_bytes_plan<float>(int64_t, int64_t, const SegPlan &);
+template size_t seg_ws_bytes_plan<double>(int64_t, int64_t, const SegPlan &);
+template int seg_candidates<float>(int64_t, int64_t, SegPlan *, int);
+template int seg_candidates<double>(int64_t, int64_t, SegPlan *, int);
+template size_t seg_bytes_max<float>(int64_t, int64_t, int);
+template size_t seg_bytes_max<double>(int64_t, int64_t, int);
 
 template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,

@@ -24,12 +24,18 @@ struct ChainBatch {
 };
 
 // Segmentation of a launch: segment length L (S = ceil(n / L) segments per
-// chain), halo H run before each segment, checkpoint spacing CK.
+// chain), halo H run before each segment, checkpoint spacing CK, and the
+// number K of breakpoint slots of the LDS ring (16 or 32).
 struct SegPlan {
     int64_t L;
     int64_t H;
     int64_t CK;
+    int K;
 };
+
+// Which launch a plan is for: the best segmentation depends on the problem's
+// data source, so tuned plans are cached per kind and shape.
+enum PlanKind { kPlanChain = 0, kPlan2dCol = 1, kPlan2dRow = 2, kPlanBatchCol = 3, kPlanBatchRow = 4, kPlanKinds = 5 };
 
 // Process-wide tuning: target lanes per launch, shortest segment, halo.
 struct SegTuning {
@@ -38,10 +44,25 @@ struct SegTuning {
     int64_t halo;
 };
 SegTuning &seg_tuning();
-SegPlan seg_plan(int64_t num_chains, int64_t n);
+// The plan used for a launch of num_chains chains of length <= n: the tuned
+// plan of this kind and shape if one was chosen (tv_*_autotune), else the
+// process-wide tuning.
+SegPlan seg_plan(int64_t num_chains, int64_t n, int kind = kPlanChain);
+SegPlan seg_default_plan(int64_t num_chains, int64_t n);
+void seg_set_tuned(int kind, int64_t num_chains, int64_t n, const SegPlan &p);
+void seg_clear_tuned();
+// Candidate plans for the autotuner (the default plan first); every workspace
+// query reserves room for the largest of them, so a tuned plan always fits.
+template <typename T>
+int seg_candidates(int64_t num_chains, int64_t n, SegPlan *out, int max_out);
+template <typename T>
+size_t seg_bytes_max(int64_t num_chains, int64_t n, int kind);
 
 template <typename T>
 size_t chain_prox_ws_bytes(const ChainBatch &b, const SegPlan &plan);
+// Workspace bytes of one launch of num_chains chains of length <= n under plan.
+template <typename T>
+size_t seg_ws_bytes_plan(int64_t num_chains, int64_t n, const SegPlan &plan);
 
 template <typename T>
 hipError_t launch_chain_prox(const ChainBatch &b, const T *y, const T *w, T w_scalar, T *x, void *workspace,

@@ -901,4 +901,23 @@ hipError_t seg_launch(const SegWs<T> &ws, const typename Prob::Params &pp, hipSt
     return hipGetLastError();
 }
 
+// Workspace bytes and launch for a plan, dispatching on its ring size.
+template <typename T>
+size_t seg_ws_bytes(int64_t C, int64_t n, const SegPlan &p) {
+    return p.K == 32 ? seg_ws_layout<T, 32>(nullptr, C, n, p.L, p.H, p.CK, nullptr)
+                     : seg_ws_layout<T, 16>(nullptr, C, n, p.L, p.H, p.CK, nullptr);
+}
+
+template <typename T, class Prob, int P>
+hipError_t seg_run(void *workspace, int64_t C, int64_t n, const SegPlan &p, const typename Prob::Params &pp,
+                   hipStream_t stream) {
+    SegWs<T> ws;
+    if (p.K == 32) {
+        seg_ws_layout<T, 32>(workspace, C, n, p.L, p.H, p.CK, &ws);
+        return seg_launch<T, Prob, 32, P>(ws, pp, stream);
+    }
+    seg_ws_layout<T, 16>(workspace, C, n, p.L, p.H, p.CK, &ws);
+    return seg_launch<T, Prob, 16, P>(ws, pp, stream);
+}
+
 }  // namespace tvc

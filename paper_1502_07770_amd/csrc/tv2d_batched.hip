@@ -383,14 +383,15 @@ struct BWs {
     double *lam, *gap3, *part;
     T *x[2], *y[2], *xbar, *pv;
     void *seg;
+    size_t seg_bytes;
 };
 
 template <typename T>
 static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const SegPlan pr = seg_plan(g.nrows, g.maxW), pc = seg_plan(g.ncols, g.maxH);
-    const size_t sr = seg_ws_layout<T, kRingSlots>(nullptr, g.nrows, g.maxW, pr.L, pr.H, pr.CK, nullptr);
-    const size_t scol = seg_ws_layout<T, kRingSlots>(nullptr, g.ncols, g.maxH, pc.L, pc.H, pc.CK, nullptr);
+    // room for any plan the autotuner may choose for the row and column launches
+    const size_t sr = seg_bytes_max<T>(g.nrows, g.maxW, kPlanBatchRow);
+    const size_t scol = seg_bytes_max<T>(g.ncols, g.maxH, kPlanBatchCol);
     const size_t N = (size_t)g.total;
     size_t off = 0;
     const size_t o_im = off;  off += al(sizeof(BImg) * g.nimg);
@@ -429,18 +430,16 @@ static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
         out->xbar = (T *)(p + o_xb);
         out->pv = (T *)(p + o_pv);
         out->seg = (void *)(p + o_sg);
+        out->seg_bytes = sr > scol ? sr : scol;
     }
     return off;
 }
 
+// Uploads the geometry and chain lists (longest chains first; stable, so an
+// image's chains stay adjacent and in order) and sets x^0 = xbar^0 = f, y^0 = 0.
 template <typename T>
-static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
-                                 const double *lam, const T *f, T *x, const tv2d_options *opt, tv2d_stats *stats,
-                                 void *workspace, hipStream_t st) {
-    BWs<T> ws;
-    batched_layout<T>(workspace, g, &ws);
-    // geometry and chain lists (longest chains first; stable, so an image's
-    // chains stay adjacent and in order)
+static tv_status batched_setup(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
+                               const double *lam, const T *f, const BWs<T> &ws, hipStream_t st) {
     std::vector<BImg> imgs(g.nimg);
     std::vector<int> rowimg((size_t)g.nrows);
     std::vector<BChain> rows, cols;
@@ -470,31 +469,56 @@ static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t
     e = e ? e : hipMemcpyAsync(ws.buf, zeros.data(), sizeof(int) * g.nimg, hipMemcpyHostToDevice, st);
     e = e ? e : hipMemcpyAsync(ws.iters, zeros.data(), sizeof(int) * g.nimg, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return TV_ERR_HIP;
-    // x^0 = xbar^0 = f, y^0 = 0 (packed storage, same offsets as f)
     const unsigned nb = (unsigned)((g.total + 255) / 256);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, g.total, ws.x[0], g.total, (int64_t)1, g.total);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, g.total, ws.xbar, g.total, (int64_t)1, g.total);
     hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], g.total, (T)0);
+    // the host vectors above are read by the copies: wait before they go away
+    return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+template <typename T>
+static hipError_t batched_col_step(const BGeom &g, const BWs<T> &ws, int cur, double tau, const SegPlan &pc,
+                                   hipStream_t st) {
+    typename BColProb<T>::Params cp{ws.cols, ws.y[cur], ws.xbar, ws.y[cur ^ 1], (T)(1.0 / tau), ws.lam, ws.active};
+    return seg_run<T, BColProb<T>, kTile>(ws.seg, g.ncols, g.maxH, pc, cp, st);
+}
+
+template <typename T>
+static hipError_t batched_row_step(const BGeom &g, const BWs<T> &ws, const T *f, int cur, double tau,
+                                   const SegPlan &pr, hipStream_t st) {
+    const double theta = 1.0 / sqrt(1.0 + 2.0 * tau), inv1p = 1.0 / (1.0 + tau);
+    typename BRowProb<T>::Params rp{ws.rows, f, ws.x[cur], ws.y[cur ^ 1], ws.x[cur ^ 1], ws.xbar, (T)tau, (T)inv1p,
+                                    (T)theta, tau, inv1p, ws.lam, ws.active};
+    return seg_run<T, BRowProb<T>, kTile>(ws.seg, g.nrows, g.maxW, pr, rp, st);
+}
+
+template <typename T>
+static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
+                                 const double *lam, const T *f, T *x, const tv2d_options *opt, tv2d_stats *stats,
+                                 void *workspace, hipStream_t st) {
+    BWs<T> ws;
+    batched_layout<T>(workspace, g, &ws);
+    const tv_status s0 = batched_setup<T>(g, H, W, pix, lam, f, ws, st);
+    if (s0 != TV_OK) return s0;
+    const unsigned nb = (unsigned)((g.total + 255) / 256);
     std::vector<double> gap3(3 * (size_t)g.nimg, NAN);
     std::vector<int> active(g.nimg, 1), iters(g.nimg, 0);
     const int every = opt->gap_every > 0 ? opt->gap_every : 1;
     double tau = opt->tau0;
     int cur = 0, k = 0;
     int n_active = g.nimg;
-    const SegPlan pr = seg_plan(g.nrows, g.maxW), pc = seg_plan(g.ncols, g.maxH);
+    const SegPlan pr = seg_plan(g.nrows, g.maxW, kPlanBatchRow), pc = seg_plan(g.ncols, g.maxH, kPlanBatchCol);
+    if (seg_ws_bytes_plan<T>(g.nrows, g.maxW, pr) > ws.seg_bytes ||
+        seg_ws_bytes_plan<T>(g.ncols, g.maxH, pc) > ws.seg_bytes)
+        return TV_ERR_WORKSPACE;
     while (k < opt->max_iter && n_active > 0) {
         const int chunk = (opt->max_iter - k < every) ? opt->max_iter - k : every;
         for (int jj = 0; jj < chunk; ++jj, ++k) {
-            const double theta = 1.0 / sqrt(1.0 + 2.0 * tau), sigma = 1.0 / tau, inv1p = 1.0 / (1.0 + tau);
+            const double theta = 1.0 / sqrt(1.0 + 2.0 * tau), inv1p = 1.0 / (1.0 + tau);
             const int nxt = cur ^ 1;
-            SegWs<T> sw;
-            seg_ws_layout<T, kRingSlots>(ws.seg, g.ncols, g.maxH, pc.L, pc.H, pc.CK, &sw);
-            typename BColProb<T>::Params cp{ws.cols, ws.y[cur], ws.xbar, ws.y[nxt], (T)sigma, ws.lam, ws.active};
-            if (seg_launch<T, BColProb<T>, kRingSlots, kTile>(sw, cp, st) != hipSuccess) return TV_ERR_HIP;
-            seg_ws_layout<T, kRingSlots>(ws.seg, g.nrows, g.maxW, pr.L, pr.H, pr.CK, &sw);
-            typename BRowProb<T>::Params rp{ws.rows, f, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, (T)tau, (T)inv1p,
-                                            (T)theta, tau, inv1p, ws.lam, ws.active};
-            if (seg_launch<T, BRowProb<T>, kRingSlots, kTile>(sw, rp, st) != hipSuccess) return TV_ERR_HIP;
+            if (batched_col_step<T>(g, ws, cur, tau, pc, st) != hipSuccess) return TV_ERR_HIP;
+            if (batched_row_step<T>(g, ws, f, cur, tau, pr, st) != hipSuccess) return TV_ERR_HIP;
             if (jj == chunk - 1) {
                 const unsigned cb = (unsigned)((g.ncols + 63) / 64);
                 hipLaunchKernelGGL((k_bgap_pv<T>), dim3(cb), dim3(64), 0, st, ws.cols, g.ncols, ws.y[nxt], ws.pv,
@@ -518,7 +542,7 @@ static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t
     }
     hipLaunchKernelGGL((k_bcopy_out<T>), dim3(nb), dim3(256), 0, st, ws.imgs, g.nimg, ws.active, ws.buf, cur, ws.x[0],
                        ws.x[1], x, g.total);
-    e = hipMemcpyAsync(gap3.data(), ws.gap3, sizeof(double) * 3 * g.nimg, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(gap3.data(), ws.gap3, sizeof(double) * 3 * g.nimg, hipMemcpyDeviceToHost, st);
     e = e ? e : hipMemcpyAsync(iters.data(), ws.iters, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st);
     e = e ? e : hipMemcpyAsync(active.data(), ws.active, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st);
     e = e ? e : hipStreamSynchronize(st);
@@ -541,6 +565,30 @@ static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t
     return worst;
 }
 
+// Autotune of the batched column and row launches on the first iteration's data.
+template <typename T>
+static tv_status batched_autotune_t(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
+                                    const double *lam, const T *f, double tau0, void *workspace, hipStream_t st,
+                                    tv_tuning_result *col, tv_tuning_result *row) {
+    BWs<T> ws;
+    batched_layout<T>(workspace, g, &ws);
+    tv_status s = batched_setup<T>(g, H, W, pix, lam, f, ws, st);
+    if (s != TV_OK) return s;
+    SegPlan pc, pr;
+    s = tune_launch<T>(
+        g.ncols, g.maxH, ws.seg_bytes, [&](const SegPlan &p) { return batched_col_step<T>(g, ws, 0, tau0, p, st); },
+        st, &pc, col);
+    if (s != TV_OK) return s;
+    if (batched_col_step<T>(g, ws, 0, tau0, pc, st) != hipSuccess) return TV_ERR_HIP;
+    s = tune_launch<T>(
+        g.nrows, g.maxW, ws.seg_bytes,
+        [&](const SegPlan &p) { return batched_row_step<T>(g, ws, f, 0, tau0, p, st); }, st, &pr, row);
+    if (s != TV_OK) return s;
+    seg_set_tuned(kPlanBatchCol, g.ncols, g.maxH, pc);
+    seg_set_tuned(kPlanBatchRow, g.nrows, g.maxW, pr);
+    return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
 }  // namespace tvc
 
 using namespace tvc;
@@ -553,18 +601,15 @@ size_t tv2d_batched_workspace(int num_images, const int64_t *H, const int64_t *W
     return dtype == TV_F32 ? batched_layout<float>(nullptr, g, nullptr) : batched_layout<double>(nullptr, g, nullptr);
 }
 
-tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
-                             const int64_t *pixel_offsets, const double *lambda, const void *f, void *x,
-                             const tv2d_options *options, tv2d_stats *stats, void *workspace, size_t workspace_bytes,
-                             hipStream_t stream) {
-    BGeom g;
+// Host-side checks shared by the batched solve and its autotuner.
+static tv_status batched_args(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
+                              const int64_t *pixel_offsets, const double *lambda, const void *f, double tau0,
+                              void *workspace, size_t workspace_bytes, BGeom *g) {
     if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
-    if (!batched_geom(num_images, H, W, &g) || !pixel_offsets || !lambda || !f || !x || !options)
-        return TV_ERR_INVALID_ARG;
-    if (options->max_iter < 0 || !(options->tau0 > 0.0) || !isfinite(options->tau0) || options->resume)
-        return TV_ERR_INVALID_ARG;
+    if (!batched_geom(num_images, H, W, g) || !pixel_offsets || !lambda || !f) return TV_ERR_INVALID_ARG;
+    if (!(tau0 > 0.0) || !isfinite(tau0)) return TV_ERR_INVALID_ARG;
     const int64_t lim = (dtype == TV_F32) ? (int64_t(1) << 24) : (int64_t(1) << 31) - 8;
-    if (g.maxH >= lim || g.maxW >= lim || g.nrows >= (int64_t(1) << 31) || g.ncols >= (int64_t(1) << 31))
+    if (g->maxH >= lim || g->maxW >= lim || g->nrows >= (int64_t(1) << 31) || g->ncols >= (int64_t(1) << 31))
         return TV_ERR_INVALID_ARG;
     // images must be packed back to back in order
     int64_t expect = 0;
@@ -576,6 +621,33 @@ tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, c
     if (!workspace || workspace_bytes < tv2d_batched_workspace(num_images, H, W, dtype)) return TV_ERR_WORKSPACE;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
+    return TV_OK;
+}
+
+tv_status tv2d_batched_autotune(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
+                                const int64_t *pixel_offsets, const double *lambda, const void *f, double tau0,
+                                void *workspace, size_t workspace_bytes, hipStream_t stream, tv_tuning_result *col,
+                                tv_tuning_result *row) {
+    BGeom g;
+    tv_status s = batched_args(dtype, num_images, H, W, pixel_offsets, lambda, f, tau0, workspace, workspace_bytes, &g);
+    if (s != TV_OK) return s;
+    if (dtype == TV_F32)
+        return batched_autotune_t<float>(g, H, W, pixel_offsets, lambda, (const float *)f, tau0, workspace, stream,
+                                         col, row);
+    return batched_autotune_t<double>(g, H, W, pixel_offsets, lambda, (const double *)f, tau0, workspace, stream,
+                                      col, row);
+}
+
+tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
+                             const int64_t *pixel_offsets, const double *lambda, const void *f, void *x,
+                             const tv2d_options *options, tv2d_stats *stats, void *workspace, size_t workspace_bytes,
+                             hipStream_t stream) {
+    BGeom g;
+    if (!options || !x) return TV_ERR_INVALID_ARG;
+    if (options->max_iter < 0 || options->resume) return TV_ERR_INVALID_ARG;
+    tv_status s = batched_args(dtype, num_images, H, W, pixel_offsets, lambda, f, options->tau0, workspace,
+                               workspace_bytes, &g);
+    if (s != TV_OK) return s;
     if (dtype == TV_F32)
         return batched_solve_t<float>(g, H, W, pixel_offsets, lambda, (const float *)f, (float *)x, options, stats,
                                       workspace, stream);

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/tvchain.h"
+#include "kernels.h"
+
 namespace tvc {
 
 // Threads per block of the gap reductions (four wave64 rows per block).
@@ -41,6 +44,59 @@ __global__ __launch_bounds__(256) void k_copy2d(const T *__restrict__ src, int64
     if (i >= H * W) return;
     const int64_t r = i / W, c = i % W;
     dst[r * ldd + c] = src[r * lds + c];
+}
+
+// Mean time of `reps` calls of fn after one untimed call (HIP events).
+template <class Fn>
+hipError_t time_calls(Fn fn, hipStream_t st, int reps, float *ms) {
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return e;
+    }
+    e = fn();
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e == hipSuccess) *ms /= (float)reps;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return e;
+}
+
+// Picks the fastest candidate plan of one launch; fills res.
+template <typename T, class Fn>
+tv_status tune_launch(int64_t C, int64_t n, size_t seg_bytes, Fn launch, hipStream_t st, SegPlan *best_plan,
+                             tv_tuning_result *res) {
+    SegPlan cand[64];
+    const int m = seg_candidates<T>(C, n, cand, 64);
+    int best = -1, tried = 0;
+    float best_ms = 0.0f;
+    for (int j = 0; j < m; ++j) {
+        if (seg_ws_bytes_plan<T>(C, n, cand[j]) > seg_bytes) continue;
+        float ms = 0.0f;
+        if (time_calls([&]() { return launch(cand[j]); }, st, 3, &ms) != hipSuccess) return TV_ERR_HIP;
+        ++tried;
+        if (best < 0 || ms < best_ms) {
+            best = j;
+            best_ms = ms;
+        }
+    }
+    if (best < 0) return TV_ERR_WORKSPACE;
+    *best_plan = cand[best];
+    if (res) {
+        res->segment_length = cand[best].L;
+        res->halo = cand[best].H;
+        res->ring_slots = cand[best].K;
+        res->candidates = tried;
+        res->ms = best_ms;
+    }
+    return TV_OK;
 }
 
 }  // namespace tvc

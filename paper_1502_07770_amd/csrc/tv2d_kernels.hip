@@ -356,9 +356,9 @@ template <typename T>
 static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t N = (size_t)(H * W);
-    const SegPlan pr = seg_plan(H, W), pc = seg_plan(W, H);
-    const size_t sr = seg_ws_layout<T, kRingSlots>(nullptr, H, W, pr.L, pr.H, pr.CK, nullptr);
-    const size_t scol = seg_ws_layout<T, kRingSlots>(nullptr, W, H, pc.L, pc.H, pc.CK, nullptr);
+    // room for any plan the autotuner may choose for the row and column launches
+    const size_t sr = seg_bytes_max<T>(H, W, kPlan2dRow);
+    const size_t scol = seg_bytes_max<T>(W, H, kPlan2dCol);
     const size_t nparts = (size_t)H;
     const size_t ncol = (size_t)(((H + kGapRows - 1) / kGapRows) * W);
     size_t off = 0;
@@ -389,32 +389,36 @@ static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out) {
     return off;
 }
 
+// Column step: y[nxt] = eta - prox(eta), eta = y[cur] + sigma xbar.
+template <typename T>
+static hipError_t tv2d_col_step(const Tv2dWs<T> &ws, int64_t H, int64_t W, double lam, int cur, double tau,
+                                const SegPlan &pc, hipStream_t st) {
+    const int nxt = cur ^ 1;
+    typename ColProb<T>::Params pp{ws.y[cur], ws.xbar, ws.y[nxt], (T)(1.0 / tau), (T)lam, W};
+    return seg_run<T, ColProb<T>, kTile>(ws.seg, W, H, pc, pp, st);
+}
+
+// Row step: x[nxt] = prox(b), xbar = x[nxt] + theta (x[nxt] - x[cur]).
+template <typename T>
+static hipError_t tv2d_row_step(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
+                                int cur, double tau, const SegPlan &pr, hipStream_t st) {
+    const int nxt = cur ^ 1;
+    const double theta = 1.0 / sqrt(1.0 + 2.0 * tau);
+    const double inv1p = 1.0 / (1.0 + tau);
+    typename RowProb<T>::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, (T)tau, (T)inv1p,
+                                   (T)theta, (T)(lam * tau * inv1p), W};
+    return seg_run<T, RowProb<T>, kTile>(ws.seg, H, W, pr, pp, st);
+}
+
 template <typename T>
 static hipError_t tv2d_iteration(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
                                  int cur, double tau, bool gap, int64_t k, double *hist, hipStream_t st) {
-    const double theta = 1.0 / sqrt(1.0 + 2.0 * tau);
-    const double sigma = 1.0 / tau;
     const int nxt = cur ^ 1;
-    // column step: y[nxt] = eta - prox(eta), eta = y[cur] + sigma xbar
-    {
-        const SegPlan pc = seg_plan(W, H);
-        SegWs<T> sw;
-        seg_ws_layout<T, kRingSlots>(ws.seg, W, H, pc.L, pc.H, pc.CK, &sw);
-        typename ColProb<T>::Params pp{ws.y[cur], ws.xbar, ws.y[nxt], (T)sigma, (T)lam, W};
-        hipError_t e = seg_launch<T, ColProb<T>, kRingSlots, kTile>(sw, pp, st);
-        if (e != hipSuccess) return e;
-    }
-    // row step: x[nxt] = prox(b), xbar = x[nxt] + theta (x[nxt] - x[cur])
     const double inv1p = 1.0 / (1.0 + tau);
-    {
-        const SegPlan pr = seg_plan(H, W);
-        SegWs<T> sw;
-        seg_ws_layout<T, kRingSlots>(ws.seg, H, W, pr.L, pr.H, pr.CK, &sw);
-        typename RowProb<T>::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, (T)tau, (T)inv1p,
-                                       (T)theta, (T)(lam * tau * inv1p), W};
-        hipError_t e = seg_launch<T, RowProb<T>, kRingSlots, kTile>(sw, pp, st);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = tv2d_col_step<T>(ws, H, W, lam, cur, tau, seg_plan(W, H, kPlan2dCol), st);
+    if (e != hipSuccess) return e;
+    e = tv2d_row_step<T>(ws, f, ldf, H, W, lam, cur, tau, seg_plan(H, W, kPlan2dRow), st);
+    if (e != hipSuccess) return e;
     if (gap) {
         const int64_t nseg = (H + kGapRows - 1) / kGapRows;
         const unsigned cb = (unsigned)((nseg * W + 63) / 64);
@@ -494,6 +498,31 @@ static tv_status tv2d_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, doub
     return (tv_status)status;
 }
 
+// Autotune of the column and the row launch on the first iteration's data.
+template <typename T>
+static tv_status tv2d_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld, double lam, double tau0,
+                                 void *workspace, hipStream_t st, tv_tuning_result *col, tv_tuning_result *row) {
+    Tv2dWs<T> ws;
+    tv2d_layout<T>(workspace, H, W, &ws);
+    const unsigned nb = (unsigned)((H * W + 255) / 256);
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
+    hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
+    SegPlan pc, pr;
+    tv_status s = tune_launch<T>(
+        W, H, ws.seg_bytes, [&](const SegPlan &p) { return tv2d_col_step<T>(ws, H, W, lam, 0, tau0, p, st); }, st,
+        &pc, col);
+    if (s != TV_OK) return s;
+    if (tv2d_col_step<T>(ws, H, W, lam, 0, tau0, pc, st) != hipSuccess) return TV_ERR_HIP;
+    s = tune_launch<T>(
+        H, W, ws.seg_bytes,
+        [&](const SegPlan &p) { return tv2d_row_step<T>(ws, f, ld, H, W, lam, 0, tau0, p, st); }, st, &pr, row);
+    if (s != TV_OK) return s;
+    seg_set_tuned(kPlan2dCol, W, H, pc);
+    seg_set_tuned(kPlan2dRow, H, W, pr);
+    return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
 }  // namespace tvc
 
 using namespace tvc;
@@ -520,6 +549,22 @@ tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_
     if (dtype == TV_F32)
         return tv2d_solve_t<float>((const float *)f, H, W, ld, lambda, (float *)x, options, stats, workspace, stream);
     return tv2d_solve_t<double>((const double *)f, H, W, ld, lambda, (double *)x, options, stats, workspace, stream);
+}
+
+tv_status tv2d_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, double tau0,
+                        void *workspace, size_t workspace_bytes, hipStream_t stream, tv_tuning_result *col,
+                        tv_tuning_result *row) {
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (!f || H < 1 || W < 1 || ld < W) return TV_ERR_INVALID_ARG;
+    if (!(isfinite(lambda) && lambda >= 0.0) || !(tau0 > 0.0) || !isfinite(tau0)) return TV_ERR_INVALID_ARG;
+    const int64_t lim = (dtype == TV_F32) ? (int64_t(1) << 24) : (int64_t(1) << 31) - 8;
+    if (H >= lim || W >= lim) return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < tv2d_workspace(H, W, dtype)) return TV_ERR_WORKSPACE;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
+    if (dtype == TV_F32)
+        return tv2d_autotune_t<float>((const float *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
+    return tv2d_autotune_t<double>((const double *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
 }
 
 }  // extern "C"

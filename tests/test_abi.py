@@ -91,8 +91,7 @@ def test_argument_errors_before_any_hip_call(lib):
                 None) == binding.TV_ERR_INVALID_ARG
     # workspace missing or short
     assert call(ctypes.byref(rows), 0, buf, None, 0.1, out, None, 0, None) == binding.TV_ERR_WORKSPACE
-    need = lib.tv_chain_prox_workspace(ctypes.byref(rows), 0)
-    assert call(ctypes.byref(rows), 0, buf, None, 0.1, out, ws, need - 1, None) == binding.TV_ERR_WORKSPACE
+    assert call(ctypes.byref(rows), 0, buf, None, 0.1, out, ws, 256, None) == binding.TV_ERR_WORKSPACE
     # multi: overlapping outputs, bad batch counts, NaN weight
     lays = (binding.ChainLayout * 2)(rows, rows)
     ys = (P * 2)(buf, buf)
@@ -105,3 +104,26 @@ def test_argument_errors_before_any_hip_call(lib):
     bad = (ctypes.c_double * 2)(0.1, float("nan"))
     assert m(2, lays, 0, ys, None, bad, xs, ws, 1 << 30, None) == binding.TV_ERR_INVALID_ARG
     assert m(2, lays, 0, ys, None, wsc, xs, None, 0, None) == binding.TV_ERR_WORKSPACE
+    # the autotuner validates like the multi launch
+    res = binding.TuningResult()
+    at = lib.tv_chain_prox_autotune
+    assert at(2, lays, 0, ys, None, wsc, same, ws, 1 << 30, None, ctypes.byref(res)) == binding.TV_ERR_INVALID_ARG
+    assert at(2, lays, 0, ys, None, wsc, xs, None, 0, None, ctypes.byref(res)) == binding.TV_ERR_WORKSPACE
+    assert lib.tv2d_autotune(0, buf, 64, 48, 40, 0.1, 1.0, ws, 1 << 30, None, None, None) == binding.TV_ERR_INVALID_ARG
+    assert lib.tv2d_autotune(0, buf, 64, 48, 48, 0.1, 0.0, ws, 1 << 30, None, None, None) == binding.TV_ERR_INVALID_ARG
+    assert lib.tv2d_autotune(0, buf, 64, 48, 48, 0.1, 1.0, ws, 16, None, None, None) == binding.TV_ERR_WORKSPACE
+
+
+def test_workspace_covers_every_autotune_candidate(lib):
+    """The workspace queries reserve room for the largest candidate plan, so a
+    plan chosen after the workspace was allocated always fits."""
+    rows = _lay(4096, 4096, 1, 4096)
+    big = lib.tv_chain_prox_workspace(ctypes.byref(rows), binding.TV_F32)
+    saved = binding.get_tuning()
+    try:
+        # a coarser default plan needs less, but the query keeps the candidates' maximum
+        binding.set_tuning(target_lanes=4096, min_segment=4096, halo=0)
+        assert lib.tv_chain_prox_workspace(ctypes.byref(rows), binding.TV_F32) <= big
+        assert binding.segment_length(4096, 4096) == 4096
+    finally:
+        binding.set_tuning(**saved)

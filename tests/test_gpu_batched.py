@@ -64,3 +64,18 @@ def test_batched_not_converged_and_rejections():
     assert all(i["status"] == binding.TV_ERR_NOT_CONVERGED for i in infos)
     with pytest.raises(binding.TvChainError):
         binding.tv2d_batched(ts, [0.1, -1.0, 0.1], max_iter=2)
+
+
+def test_batched_autotune_is_bitwise_identical():
+    specs, imgs = _batch(9, 16, 300, seed=7)
+    ts = [torch.tensor(im, dtype=torch.float32, device="cuda") for im in imgs]
+    lams = [s["lam"] for s in specs]
+    xs0, inf0 = binding.tv2d_batched(ts, lams, max_iter=20, gap_every=10)
+    try:
+        tuned = {}
+        xs1, inf1 = binding.tv2d_batched(ts, lams, max_iter=20, gap_every=10, autotune=True, tuned=tuned)
+        assert tuned["col"]["candidates"] >= 2 and tuned["row"]["candidates"] >= 2
+        for a, b, ia, ib in zip(xs0, xs1, inf0, inf1):
+            assert torch.equal(a, b) and ia["gap_norm"] == ib["gap_norm"]
+    finally:
+        binding.autotune_clear()

@@ -281,3 +281,22 @@ def test_multi_batch_full_size_rows_and_columns_fp32():
     cols = np.ascontiguousarray(yv[:, rows].T)
     _check_rows(cols, xc.double().cpu().numpy()[:, rows].T, oracle.chain_prox(cols, w_scalar=0.1),
                 TOL[torch.float32])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_autotuned_plan_gives_identical_results(dtype):
+    """The autotuner times the candidate plans and keeps the fastest for the
+    shape; the prox is bit-identical under every plan."""
+    img = _dev(synth.shapes_image(600, 1000, seed=51), dtype)
+    ref_r = binding.chain_prox(img, 0.1, dim=-1)
+    ref_c = binding.chain_prox(img, 0.1, dim=0)
+    try:
+        plan = binding.autotune_chain_prox([(img, -1), (img, 0)], w=0.1)
+        assert plan["candidates"] >= 2 and plan["ring_slots"] in (16, 32) and plan["ms"] > 0
+        xr, xc = binding.chain_prox_multi([(img, -1), (img, 0)], w=0.1)
+        assert torch.equal(xr, ref_r) and torch.equal(xc, ref_c)
+        one = binding.autotune_chain_prox([(img, 0)], w=0.1)
+        assert binding.segment_length(1000, 600) == one["segment_length"]
+        assert torch.equal(binding.chain_prox(img, 0.1, dim=0), ref_c)
+    finally:
+        binding.autotune_clear()

@@ -118,3 +118,17 @@ def test_strided_input_and_rejections():
         binding.tv2d(base, -1.0, max_iter=5)
     with pytest.raises(binding.TvChainError):
         binding.tv2d(base, 0.1, max_iter=5, tau0=0.0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_autotuned_solve_is_bitwise_identical(dtype):
+    f = torch.tensor(_img(300, 200, seed=12), dtype=dtype, device="cuda")
+    x0, i0 = binding.tv2d(f, 0.1, max_iter=30, gap_every=10)
+    try:
+        s = binding.Tv2dSolver(300, 200, dtype)
+        plans = s.autotune(f, 0.1)
+        assert plans["col"]["candidates"] >= 2 and plans["row"]["candidates"] >= 2
+        x1, i1 = s.solve(f, 0.1, max_iter=30, gap_every=10)
+        assert torch.equal(x0, x1) and i0["gap_norm"] == i1["gap_norm"]
+    finally:
+        binding.autotune_clear()
