@@ -120,6 +120,13 @@ def bench_chain(steps: int, warmup: int):
         if st != 0:
             raise binding.TvChainError(st, "tv_chain_prox_multi")
 
+    # setup (not timed): the autotuner picks the launch plan for this shape
+    res = binding.TuningResult()
+    st = lib.tv_chain_prox_autotune(2, lays, binding.TV_F32, yp, None, wsc, xp, ctypes.c_void_p(ws.data_ptr()), nb,
+                                    sp, ctypes.byref(res))
+    if st != 0:
+        raise binding.TvChainError(st, "tv_chain_prox_autotune")
+    plan = res.as_dict()
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -151,10 +158,7 @@ def bench_chain(steps: int, warmup: int):
     nodes = 2 * SIDE * SIDE
     ms_step = total_ms / steps
     return dict(ms_per_step=ms_step, gelem=nodes / (ms_step * 1e-3) / 1e9, launch_ms=float(np.mean(launch_ms)),
-                separate_ms=sep, nodes=nodes, img=img,
-                segment_length=int(lib.tv_chain_prox_segment_length(ctypes.byref(
-                    binding.ChainLayout(2 * SIDE, SIDE, 1, SIDE, None)))),
-                tuning=binding.get_tuning())
+                separate_ms=sep, nodes=nodes, img=img, plan=plan)
 
 
 def cpu_baseline(img):
@@ -184,9 +188,9 @@ def bench_tv2d(side: int, seed: int, iters_fixed: int | None, tol: float, max_it
     for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
         f = torch.tensor(img, dtype=dt, device="cuda")
         s = binding.Tv2dSolver(side, side, dt)
+        r = {"plans": s.autotune(f, 0.1)}  # setup, not timed
         s.solve(f, 0.1, max_iter=2, gap_every=1)  # warm-up
         torch.cuda.synchronize()
-        r = {}
         if iters_fixed:
             t = time.perf_counter()
             _, info = s.solve(f, 0.1, max_iter=iters_fixed, gap_every=10)
@@ -210,6 +214,7 @@ def bench_adjoint(steps: int):
     w = torch.tensor(synth.edge_weights((C, n), seed=6), dtype=torch.float32, device="cuda")
     g = torch.tensor(synth.normal((C, n), seed=7), dtype=torch.float32, device="cuda")
     tm = Timer(torch, torch.cuda.current_stream())
+    plan = binding.autotune_chain_prox([(y, -1)], w=0.55)  # setup, not timed (scalar w of the same scale)
     fwd = lambda: binding.chain_prox(y, w, dim=-1)  # noqa: E731
     x = fwd()
     bwd = lambda: binding.chain_prox_backward(x, g, dim=-1, per_edge_w=True)  # noqa: E731
@@ -217,7 +222,7 @@ def bench_adjoint(steps: int):
     f_ms = tm(fwd, steps)
     b_ms = tm(bwd, steps)
     nodes = C * n
-    return {"workload": "65536 chains x 1024, per-edge w ~ U[0.1,1], FP32",
+    return {"workload": "65536 chains x 1024, per-edge w ~ U[0.1,1], FP32", "plan": plan,
             "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3),
             "fwd_gelem_s": round(nodes / f_ms / 1e6, 2), "bwd_gelem_s": round(nodes / b_ms / 1e6, 2),
             "fwd_bwd_gelem_s": round(nodes / (f_ms + b_ms) / 1e6, 2),
@@ -237,6 +242,8 @@ def bench_batched():
     f = torch.from_numpy(packed).cuda()
     shapes = [(s["H"], s["W"]) for s in specs]
     lams = [s["lam"] for s in specs]
+    tuned = {}
+    binding.tv2d_batched(shapes, lams, max_iter=1, gap_every=1, packed=f, autotune=True, tuned=tuned)  # setup
     torch.cuda.synchronize()
     t = time.perf_counter()
     xs, infos = binding.tv2d_batched(shapes, lams, max_iter=2000, gap_every=10, gap_tol=1e-4, packed=f)
@@ -246,7 +253,7 @@ def bench_batched():
     return {"workload": "256 images, H,W ~ U{64..2048}, lambda ~ U[0.02,0.3], sigma ~ U[0.05,0.2], FP32",
             "pixels": int(packed.size), "time_to_gap_ms": round(dt * 1e3, 1),
             "all_reached": all(i["status"] == binding.TV_OK for i in infos),
-            "iters_min": min(iters), "iters_max": max(iters), "generate_s": round(gen_s, 1)}
+            "iters_min": min(iters), "iters_max": max(iters), "generate_s": round(gen_s, 1), "plans": tuned}
 
 
 def rocprof_summary(d):
@@ -399,8 +406,7 @@ def main():
             "nodes_per_step": r["nodes"],
             "launch_ms": round(r["launch_ms"], 4),
             "separate_row_col_calls_ms": [round(v, 4) for v in r["separate_ms"]],
-            "segment_length": r["segment_length"],
-            "tuning": r["tuning"],
+            "autotuned_plan": r["plan"],
         },
         "hbm_pct": round(100.0 * r["gelem"] * 8.0 / HBM_PEAK_GBS, 2),
         "roofline": {

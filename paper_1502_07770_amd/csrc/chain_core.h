@@ -31,24 +31,31 @@ template <typename T> __device__ __forceinline__ T recip(T v);
 template <> __device__ __forceinline__ float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double recip<double>(double v) { return 1.0 / v; }
 
-// Four consecutive elements from a 16-byte aligned address (two 16-byte loads
-// for double).
+// Four consecutive elements as one 16-byte access (two for double).  Only the
+// element alignment is assumed: gfx950 runs in unaligned-access mode, and the
+// compiler emits dwordx4 accesses for these copies at any 4-byte alignment.
 __device__ __forceinline__ void vload4(const float *p, float (&o)[4]) {
-    const float4 v = *reinterpret_cast<const float4 *>(p);
+    float4 v;
+    __builtin_memcpy(&v, __builtin_assume_aligned(p, 4), 16);
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
 __device__ __forceinline__ void vload4(const double *p, double (&o)[4]) {
-    const double2 a = *reinterpret_cast<const double2 *>(p), b = *reinterpret_cast<const double2 *>(p + 2);
+    double2 a, b;
+    __builtin_memcpy(&a, __builtin_assume_aligned(p, 8), 16);
+    __builtin_memcpy(&b, __builtin_assume_aligned(p + 2, 8), 16);
     o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
 __device__ __forceinline__ void vstore4(float *p, const float (&v)[4]) {
-    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    const float4 t = make_float4(v[0], v[1], v[2], v[3]);
+    __builtin_memcpy(__builtin_assume_aligned(p, 4), &t, 16);
 }
 __device__ __forceinline__ void vstore4(double *p, const double (&v)[4]) {
-    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
-    *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+    const double2 a = make_double2(v[0], v[1]), b = make_double2(v[2], v[3]);
+    __builtin_memcpy(__builtin_assume_aligned(p, 8), &a, 16);
+    __builtin_memcpy(__builtin_assume_aligned(p + 2, 8), &b, 16);
 }
-template <typename T> __device__ __forceinline__ bool aligned16(const T *p) { return ((uintptr_t)p & 15) == 0; }
+// Element alignment (what the 16-byte accesses above need).
+template <typename T> __device__ __forceinline__ bool elem_aligned(const T *p) { return ((uintptr_t)p % sizeof(T)) == 0; }
 
 // Clip of v to [lo, hi] for lo <= hi (every call site guarantees the order:
 // brackets of sorted breakpoints, and lambda^- <= lambda^+).  FP32 uses the

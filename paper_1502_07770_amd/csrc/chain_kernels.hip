@@ -30,10 +30,10 @@ struct PlainProb {
         const T *__restrict__ w;
         T ws;
         int64_t base, es;
-        bool vec;  // unit stride and 16-byte aligned: load4 may be used
+        bool vec;  // unit stride and element-aligned: load4 may be used
         __device__ __forceinline__ Src(const T *y_, const T *w_, T ws_, int64_t base_, int64_t es_)
             : y(y_), w(w_), ws(ws_), base(base_), es(es_),
-              vec(es_ == 1 && aligned16(y_ + base_) && (!EDGE_W || aligned16(w_ + base_))) {}
+              vec(es_ == 1 && elem_aligned(y_ + base_) && (!EDGE_W || elem_aligned(w_ + base_))) {}
         __device__ __forceinline__ Pre load(int64_t i) const {
             Pre p;
             p.y = y[base + i * es];
@@ -57,9 +57,9 @@ struct PlainProb {
     struct Sink {
         T *__restrict__ x;
         int64_t base, es;
-        bool vec;  // unit stride and 16-byte aligned: load4 / store4 may be used
+        bool vec;  // unit stride and element-aligned: load4 / store4 may be used
         __device__ __forceinline__ Sink(T *x_, int64_t base_, int64_t es_)
-            : x(x_), base(base_), es(es_), vec(es_ == 1 && aligned16(x_ + base_)) {}
+            : x(x_), base(base_), es(es_), vec(es_ == 1 && elem_aligned(x_ + base_)) {}
         __device__ __forceinline__ SinkPre load(int64_t) const { return SinkPre{}; }
         __device__ __forceinline__ void load4(int64_t, SinkPre *) const {}
         __device__ __forceinline__ void store(int64_t i, T v, const SinkPre &) const { x[base + i * es] = v; }
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_chain_adjoint_rows(ChainBatch b, const 
     const T *__restrict__ gr = g + a.base;
     T *__restrict__ yr = gy ? gy + a.base : nullptr;
     T *__restrict__ wr = (gw && w_per_edge) ? gw + a.base : nullptr;
-    const bool vec = aligned16(xr) && aligned16(gr) && (!yr || aligned16(yr)) && (!wr || aligned16(wr));
+    const bool vec = elem_aligned(xr) && elem_aligned(gr) && (!yr || elem_aligned(yr)) && (!wr || elem_aligned(wr));
     constexpr int64_t CH = 64 * kAdjV;
     // run open at the start of the chunk (identical in every lane)
     double o_sum = 0.0;

@@ -439,7 +439,7 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::
 // b, so node indices are wave-uniform and the lambda / sink accesses coalesce.
 // Collapsed nodes are written through the sink; the un-collapsed right tail
 // gets its composed interval in the lambda stream for k_seg_tail.  With kVec
-// (unit-stride, 16-byte aligned sink and b a multiple of 4) the sink is read
+// (unit-stride, element-aligned sink and b a multiple of 4) the sink is read
 // and written four nodes at a time: node groups [4m, 4m + 3] are visited from
 // the top, buffered, and stored with one 16-byte access per stream when the
 // whole group has collapsed (the group holding the collapse point falls back

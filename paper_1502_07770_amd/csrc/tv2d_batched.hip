@@ -126,10 +126,10 @@ struct BRowProb {
         const T *__restrict__ y;
         T tau, inv1p, w;
         int64_t base;
-        bool vec;  // the row's three streams are 16-byte aligned: load4 may be used
+        bool vec;  // the row's three streams are element-aligned: load4 may be used
         __device__ __forceinline__ Src(const T *f_, const T *x_, const T *y_, T tau_, T inv1p_, T w_, int64_t base_)
             : f(f_), x(x_), y(y_), tau(tau_), inv1p(inv1p_), w(w_), base(base_),
-              vec(aligned16(f_ + base_) && aligned16(x_ + base_) && aligned16(y_ + base_)) {}
+              vec(elem_aligned(f_ + base_) && elem_aligned(x_ + base_) && elem_aligned(y_ + base_)) {}
         __device__ __forceinline__ Pre load(int64_t i) const {
             Pre p;
             p.f = f[base + i];
@@ -158,10 +158,10 @@ struct BRowProb {
         T *__restrict__ xb;
         T theta;
         int64_t base;
-        bool vec;  // the row's streams are 16-byte aligned: load4 / store4 may be used
+        bool vec;  // the row's streams are element-aligned: load4 / store4 may be used
         __device__ __forceinline__ Sink(const T *x_, T *xn_, T *xb_, T theta_, int64_t base_)
             : x(x_), xn(xn_), xb(xb_), theta(theta_), base(base_),
-              vec(aligned16(x_ + base_) && aligned16(xn_ + base_) && aligned16(xb_ + base_)) {}
+              vec(elem_aligned(x_ + base_) && elem_aligned(xn_ + base_) && elem_aligned(xb_ + base_)) {}
         __device__ __forceinline__ SinkPre load(int64_t i) const { return SinkPre{x[base + i]}; }
         __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const {
             T v[4];

@@ -131,11 +131,11 @@ struct RowProb {
         const T *__restrict__ y;
         T tau, inv1p, w;
         int64_t r, ldf, W;
-        bool vec;  // the row's three streams are 16-byte aligned: load4 may be used
+        bool vec;  // the row's three streams are element-aligned: load4 may be used
         __device__ __forceinline__ Src(const T *f_, const T *x_, const T *y_, T tau_, T inv1p_, T w_, int64_t r_,
                                        int64_t ldf_, int64_t W_)
             : f(f_), x(x_), y(y_), tau(tau_), inv1p(inv1p_), w(w_), r(r_), ldf(ldf_), W(W_),
-              vec(aligned16(f_ + r_ * ldf_) && aligned16(x_ + r_ * W_) && aligned16(y_ + r_ * W_)) {}
+              vec(elem_aligned(f_ + r_ * ldf_) && elem_aligned(x_ + r_ * W_) && elem_aligned(y_ + r_ * W_)) {}
         __device__ __forceinline__ Pre load(int64_t i) const {
             Pre p;
             p.f = f[r * ldf + i];
@@ -164,10 +164,10 @@ struct RowProb {
         T *__restrict__ xb;
         T theta;
         int64_t r, W;
-        bool vec;  // the row's streams are 16-byte aligned: load4 / store4 may be used
+        bool vec;  // the row's streams are element-aligned: load4 / store4 may be used
         __device__ __forceinline__ Sink(const T *x_, T *xn_, T *xb_, T theta_, int64_t r_, int64_t W_)
             : x(x_), xn(xn_), xb(xb_), theta(theta_), r(r_), W(W_),
-              vec(aligned16(x_ + r_ * W_) && aligned16(xn_ + r_ * W_) && aligned16(xb_ + r_ * W_)) {}
+              vec(elem_aligned(x_ + r_ * W_) && elem_aligned(xn_ + r_ * W_) && elem_aligned(xb_ + r_ * W_)) {}
         __device__ __forceinline__ SinkPre load(int64_t i) const { return SinkPre{x[r * W + i]}; }
         __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const {
             T v[4];
