@@ -90,7 +90,7 @@ class Timer:
         return a.elapsed_time(b) / reps
 
 
-def bench_chain(steps: int, warmup: int):
+def bench_chain(steps: int, warmup: int, autotune: bool = True):
     """The headline step: rows and columns of the image in ONE tv_chain_prox_multi
     launch.  Also times the two batches as separate tv_chain_prox calls."""
     import numpy as np
@@ -121,12 +121,18 @@ def bench_chain(steps: int, warmup: int):
             raise binding.TvChainError(st, "tv_chain_prox_multi")
 
     # setup (not timed): the autotuner picks the launch plan for this shape
-    res = binding.TuningResult()
-    st = lib.tv_chain_prox_autotune(2, lays, binding.TV_F32, yp, None, wsc, xp, ctypes.c_void_p(ws.data_ptr()), nb,
-                                    sp, ctypes.byref(res))
-    if st != 0:
-        raise binding.TvChainError(st, "tv_chain_prox_autotune")
-    plan = res.as_dict()
+    plan = None
+    if autotune:
+        res = binding.TuningResult()
+        st = lib.tv_chain_prox_autotune(2, lays, binding.TV_F32, yp, None, wsc, xp, ctypes.c_void_p(ws.data_ptr()),
+                                        nb, sp, ctypes.byref(res))
+        if st != 0:
+            raise binding.TvChainError(st, "tv_chain_prox_autotune")
+        plan = res.as_dict()
+    else:
+        plan = {"segment_length": int(lib.tv_chain_prox_segment_length(ctypes.byref(
+            binding.ChainLayout(2 * SIDE, SIDE, 1, SIDE, None)))), "halo": binding.get_tuning()["halo"],
+                "ring_slots": 16, "candidates": 0, "ms": None}
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -353,6 +359,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -381,7 +389,7 @@ def main():
         return
 
     log("bench: chain prox 4096x4096 rows+cols, steps=%d warmup=%d" % (args.steps, args.warmup))
-    r = bench_chain(args.steps, args.warmup)
+    r = bench_chain(args.steps, args.warmup, autotune=not args.no_autotune)
     log("bench: %.3f ms/step, %.1f Gelem/s (one launch %.3f ms; separate row / column calls %.3f / %.3f ms)" % (
         r["ms_per_step"], r["gelem"], r["launch_ms"], r["separate_ms"][0], r["separate_ms"][1]))
     alg_bytes = 8.0 * r["nodes"]
