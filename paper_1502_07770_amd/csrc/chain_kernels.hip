@@ -34,10 +34,14 @@ struct PlainProb {
         __device__ __forceinline__ Src(const T *y_, const T *w_, T ws_, int64_t base_, int64_t es_)
             : y(y_), w(w_), ws(ws_), base(base_), es(es_),
               vec(es_ == 1 && elem_aligned(y_ + base_) && (!EDGE_W || elem_aligned(w_ + base_))) {}
-        __device__ __forceinline__ Pre load(int64_t i) const {
+        __device__ __forceinline__ Pre load(int64_t i) const { return load_off(base + i * es); }
+        // element offset of node i, and the offset step between nodes
+        __device__ __forceinline__ int64_t off(int64_t i) const { return base + i * es; }
+        __device__ __forceinline__ int64_t step() const { return es; }
+        __device__ __forceinline__ Pre load_off(int64_t o) const {
             Pre p;
-            p.y = y[base + i * es];
-            p.w = EDGE_W ? w[base + i * es] : ws;
+            p.y = y[o];
+            p.w = EDGE_W ? w[o] : ws;
             return p;
         }
         // nodes i .. i+3 (i a multiple of 4, vec set)

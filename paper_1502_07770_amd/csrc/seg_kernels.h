@@ -400,12 +400,39 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::
     typename Prob::Pre pre[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) pre[j] = src.load((from + j < b) ? from + j : b - 1);
+    LamPair<T> *lq = lam + from * C + c;  // lambda pair of the next node (running pointer)
     auto node = [&](int64_t i, const typename Prob::Pre &pv) {
         T lm, lp;
         node_step<T, K>(R, ok, i, n, src.data(pv), src.weight(pv), wprev, lm, lp);
-        if (kStore) put_lam<T>(lam, i, C, c, lm, lp);
+        if (kStore) {
+            LamPair<T> pr;
+            pr.lo = lm;
+            pr.hi = lp;
+            *lq = pr;
+            lq += C;
+        }
     };
     int64_t i0 = from;
+    // tiles whose prefetch stays inside [from, b): no clamping, running offsets
+    for (; i0 + 2 * P <= b; i0 += P) {
+        int64_t o = src.off(i0 + P);
+        const int64_t st = src.step();
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const auto pv = pre[j];
+            if (!src.vec) {
+                pre[j] = src.load_off(o);
+                o += st;
+            } else if ((j & 3) == 3) {
+                // unit-stride chains (rows): refill the four slots just consumed
+                // with one 16-byte load per stream (node indices are multiples of 4)
+                src.load4(i0 + j + P - 3, &pre[j - 3]);
+            }
+            node(i0 + j, pv);
+        }
+        if (hook(i0 + P)) return i0 + P;
+    }
+    // the last full tile (its prefetch is clamped to the run's last node)
     for (; i0 + P <= b; i0 += P) {
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -414,8 +441,6 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::
             if (!src.vec) {
                 pre[j] = src.load((i + P < b) ? i + P : b - 1);
             } else if ((j & 3) == 3) {
-                // unit-stride chains (rows): refill the four slots just consumed
-                // with one 16-byte load per stream (node indices are multiples of 4)
                 const int64_t q = i + P - 3;
                 if (q + 3 < b) {
                     src.load4(q, &pre[j - 3]);

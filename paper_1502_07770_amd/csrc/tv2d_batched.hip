@@ -52,10 +52,13 @@ struct BColProb {
         const T *__restrict__ xb;
         T sigma, lam;
         int64_t base, es;
-        __device__ __forceinline__ Pre load(int64_t i) const {
+        __device__ __forceinline__ Pre load(int64_t i) const { return load_off(base + i * es); }
+        __device__ __forceinline__ int64_t off(int64_t i) const { return base + i * es; }
+        __device__ __forceinline__ int64_t step() const { return es; }
+        __device__ __forceinline__ Pre load_off(int64_t o) const {
             Pre p;
-            p.y = y[base + i * es];
-            p.xb = xb[base + i * es];
+            p.y = y[o];
+            p.xb = xb[o];
             return p;
         }
         __device__ __forceinline__ T data(const Pre &p) const { return p.y + sigma * p.xb; }
@@ -137,6 +140,9 @@ struct BRowProb {
             p.y = y[base + i];
             return p;
         }
+        __device__ __forceinline__ int64_t off(int64_t i) const { return i; }
+        __device__ __forceinline__ int64_t step() const { return 1; }
+        __device__ __forceinline__ Pre load_off(int64_t o) const { return load(o); }
         __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
             T a[4], b[4], c[4];
             vload4(f + base + i, a);

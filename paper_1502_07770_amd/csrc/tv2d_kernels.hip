@@ -59,10 +59,13 @@ struct ColProb {
         const T *__restrict__ xb;
         T sigma, lam;
         int64_t c, W;
-        __device__ __forceinline__ Pre load(int64_t i) const {
+        __device__ __forceinline__ Pre load(int64_t i) const { return load_off(i * W + c); }
+        __device__ __forceinline__ int64_t off(int64_t i) const { return i * W + c; }
+        __device__ __forceinline__ int64_t step() const { return W; }
+        __device__ __forceinline__ Pre load_off(int64_t o) const {
             Pre p;
-            p.y = y[i * W + c];
-            p.xb = xb[i * W + c];
+            p.y = y[o];
+            p.xb = xb[o];
             return p;
         }
         __device__ __forceinline__ T data(const Pre &p) const { return p.y + sigma * p.xb; }
@@ -143,6 +146,9 @@ struct RowProb {
             p.y = y[r * W + i];
             return p;
         }
+        __device__ __forceinline__ int64_t off(int64_t i) const { return i; }
+        __device__ __forceinline__ int64_t step() const { return 1; }
+        __device__ __forceinline__ Pre load_off(int64_t o) const { return load(o); }
         __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
             T a[4], b[4], c[4];
             vload4(f + r * ldf + i, a);
