@@ -79,3 +79,28 @@ def test_batched_autotune_is_bitwise_identical():
             assert torch.equal(a, b) and ia["gap_norm"] == ib["gap_norm"]
     finally:
         binding.autotune_clear()
+
+
+def test_full_size_batch_of_256_against_oracle():
+    """The bench's batch (256 images, sides U{64..2048}, per-image lambda and
+    noise) solved to gap 1e-4 per image in FP32 with autotuned launches; the
+    smallest, the largest and a middle image are checked against the FP64
+    oracle run for the same number of iterations (1e-4 x range)."""
+    specs = synth.uneven_batch_specs(256, seed=11)
+    imgs = [synth.shapes_image(s["H"], s["W"], sigma=s["sigma"], seed=s["seed"]) for s in specs]
+    packed = torch.tensor(np.concatenate([im.ravel() for im in imgs]), dtype=torch.float32, device="cuda")
+    shapes = [(s["H"], s["W"]) for s in specs]
+    lams = [s["lam"] for s in specs]
+    try:
+        xs, infos = binding.tv2d_batched(shapes, lams, max_iter=2000, gap_every=10, gap_tol=1e-4, packed=packed,
+                                         autotune=True)
+    finally:
+        binding.autotune_clear()
+    assert all(i["status"] == binding.TV_OK and i["gap_norm"] <= 1e-4 for i in infos)
+    sizes = [h * w for h, w in shapes]
+    order = np.argsort(sizes)
+    for j in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        fv = np.float32(imgs[j]).astype(np.float64)
+        xo, _, (_, _, go), k = oracle.tv2d(fv, lams[j], max_iter=infos[j]["iters"])
+        assert np.abs(xs[j].double().cpu().numpy() - xo).max() <= 1e-4 * np.ptp(fv), j
+        assert abs(infos[j]["gap_norm"] - go) <= 1e-6

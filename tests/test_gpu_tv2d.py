@@ -132,3 +132,24 @@ def test_autotuned_solve_is_bitwise_identical(dtype):
         assert torch.equal(x0, x1) and i0["gap_norm"] == i1["gap_norm"]
     finally:
         binding.autotune_clear()
+
+
+def test_full_size_4096_fp32_to_gap_against_oracle():
+    """The 4096 x 4096 2D solve in the configuration the bench times (autotuned
+    plans, FP32 iterates, FP64 gap every 5 iterations, stop at gap 1e-4): the
+    iterate at the stopping iteration matches the FP64 oracle run for the same
+    number of iterations to 1e-4 x range, and both gaps are below the tolerance."""
+    img = _img(4096, 4096, seed=3)
+    f = torch.tensor(img, dtype=torch.float32, device="cuda")
+    try:
+        s = binding.Tv2dSolver(4096, 4096, torch.float32)
+        s.autotune(f, 0.1)
+        x, info = s.solve(f, 0.1, max_iter=500, gap_every=5, gap_tol=1e-4)
+    finally:
+        binding.autotune_clear()
+    assert info["status"] == binding.TV_OK and info["gap_norm"] <= 1e-4
+    fv = f.double().cpu().numpy()
+    xo, ho, (Po, Do, go), k = oracle.tv2d(fv, 0.1, max_iter=info["iters"])
+    assert k == info["iters"] and go <= 1e-4
+    assert np.abs(x.double().cpu().numpy() - xo).max() <= 1e-4 * np.ptp(fv)
+    assert abs(info["gap_norm"] - go) <= 1e-6
