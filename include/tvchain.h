@@ -163,6 +163,9 @@ typedef struct {
     int resume;          /* nonzero: continue from the state held in the workspace    */
     double *gap_history; /* DEVICE, optional: gap after iteration k at [k-1]; entries
                             of iterations without a gap evaluation are left untouched */
+    int use_graph;       /* nonzero: capture a chunk of gap_every (<= 64) iterations
+                            in a HIP graph once and replay it for every full chunk
+                            (same kernels and results; fewer launches from the host) */
 } tv2d_options;
 
 /* [host] Result of a 2D solve (written by the library before it returns). */

@@ -52,7 +52,8 @@ class ChainLayout(ctypes.Structure):
 
 class Tv2dOptions(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("gap_every", ctypes.c_int), ("gap_tol", ctypes.c_double),
-                ("tau0", ctypes.c_double), ("resume", ctypes.c_int), ("gap_history", ctypes.c_void_p)]
+                ("tau0", ctypes.c_double), ("resume", ctypes.c_int), ("gap_history", ctypes.c_void_p),
+                ("use_graph", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -411,7 +412,8 @@ class Tv2dSolver:
 
     def solve(self, f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10,
               gap_tol: float = 0.0, tau0: float = 1.0, resume: bool = False,
-              gap_history: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
+              gap_history: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+              use_graph: bool = False):
         """Run the Sec. 5.1 decomposition.  Returns (x, stats dict).  With
         gap_tol > 0 a solve that stops at max_iter above the tolerance raises
         nothing: stats['status'] says TV_ERR_NOT_CONVERGED."""
@@ -429,7 +431,8 @@ class Tv2dSolver:
             if gap_history.dtype != torch.float64 or not gap_history.is_cuda:
                 raise TvChainError(TV_ERR_INVALID_ARG, "gap_history must be a float64 GPU tensor")
             hist_ptr = gap_history.data_ptr()
-        opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 1 if resume else 0, hist_ptr)
+        opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 1 if resume else 0, hist_ptr,
+                          1 if use_graph else 0)
         stats = Tv2dStats()
         st = load().tv2d_solve(self.code, _ptr(f), self.H, self.W, ld, float(lam), _ptr(x), ctypes.byref(opt),
                                ctypes.byref(stats), _ptr(self.ws), self.nbytes,
@@ -445,17 +448,17 @@ class Tv2dSolver:
 
 
 def tv2d(f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10, gap_tol: float = 0.0,
-         tau0: float = 1.0, gap_history: Optional[torch.Tensor] = None):
+         tau0: float = 1.0, gap_history: Optional[torch.Tensor] = None, use_graph: bool = False):
     """2D ROF min_x lam (TV_h + TV_v)(x) + |x - f|^2 / 2 by the row/column chain
     decomposition (Sec. 5.1).  Returns (x, stats)."""
     s = Tv2dSolver(f.shape[0], f.shape[1], f.dtype, f.device)
     return s.solve(f, lam, max_iter=max_iter, gap_every=gap_every, gap_tol=gap_tol, tau0=tau0,
-                   gap_history=gap_history)
+                   gap_history=gap_history, use_graph=use_graph)
 
 
 def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol: float = 0.0,
                  tau0: float = 1.0, packed: Optional[torch.Tensor] = None, autotune: bool = False,
-                 tuned: Optional[dict] = None):
+                 tuned: Optional[dict] = None, use_graph: bool = False):
     """Solve many 2D ROF problems of different sizes in one call
     (tv2d_solve_batched).  ``images`` is a list of (H_j, W_j) GPU tensors of one
     dtype (or a list of shapes when ``packed`` holds them back to back);
@@ -494,7 +497,7 @@ def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol
         if tuned is not None:
             tuned.update({"col": col.as_dict(), "row": row.as_dict()})
     x = torch.empty_like(packed)
-    opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 0, None)
+    opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 0, None, 1 if use_graph else 0)
     stats = (Tv2dStats * n)()
     st = lib.tv2d_solve_batched(code, n, Hs, Ws, Os, Ls, _ptr(packed), _ptr(x), ctypes.byref(opt), stats, _ptr(ws),
                                 nbytes, ctypes.c_void_p(_stream_ptr(packed.device)))

@@ -37,7 +37,7 @@ struct BColProb {
         const T *y_old;
         const T *xbar;
         T *y_new;
-        T sigma;
+        const IterSched *sc;
         const double *lam;
         const int *active;
     };
@@ -96,10 +96,10 @@ struct BColProb {
         return ChainSpan{d.base, d.es, p.active[d.img] ? (int64_t)d.n : 0, d.img};
     }
     static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
-        return Src{p.y_old, p.xbar, p.sigma, (T)p.lam[sp.aux], sp.base, sp.es};
+        return Src{p.y_old, p.xbar, (T)p.sc->sigma, (T)p.lam[sp.aux], sp.base, sp.es};
     }
     static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
-        return Sink{p.y_old, p.xbar, p.y_new, p.sigma, sp.base, sp.es};
+        return Sink{p.y_old, p.xbar, p.y_new, (T)p.sc->sigma, sp.base, sp.es};
     }
 };
 
@@ -112,8 +112,7 @@ struct BRowProb {
         const T *y;
         T *x_new;
         T *xbar;
-        T tau, inv1p, theta;
-        double tau_d, inv1p_d;
+        const IterSched *sc;
         const double *lam;
         const int *active;
     };
@@ -190,10 +189,11 @@ struct BRowProb {
         return ChainSpan{d.base, 1, p.active[d.img] ? (int64_t)d.n : 0, d.img};
     }
     static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
-        return Src{p.f, p.x_old, p.y, p.tau, p.inv1p, (T)(p.lam[sp.aux] * p.tau_d * p.inv1p_d), sp.base};
+        const IterSched sc = *p.sc;
+        return Src{p.f, p.x_old, p.y, (T)sc.tau, (T)sc.inv1p, (T)(p.lam[sp.aux] * sc.tau * sc.inv1p), sp.base};
     }
     static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
-        return Sink{p.x_old, p.x_new, p.xbar, p.theta, sp.base};
+        return Sink{p.x_old, p.x_new, p.xbar, (T)p.sc->theta, sp.base};
     }
 };
 
@@ -240,7 +240,9 @@ __global__ __launch_bounds__(kGapBlock) void k_bgap_rows(const BImg *__restrict_
                                                          const T *__restrict__ xn, const T *__restrict__ xo,
                                                          const T *__restrict__ y, const T *__restrict__ pv,
                                                          const double *__restrict__ lamv, const int *__restrict__ active,
-                                                         T tau, T inv1p, double pscale, double *__restrict__ part) {
+                                                         const IterSched *__restrict__ sc, double *__restrict__ part) {
+    const T tau = (T)sc->tau, inv1p = (T)sc->inv1p;
+    const double pscale = sc->pscale;
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * (kGapBlock / 64) + (threadIdx.x >> 6);
     if (t >= nrows) return;
@@ -308,7 +310,8 @@ __global__ __launch_bounds__(kGapBlock) void k_bgap_rows(const BImg *__restrict_
 __global__ __launch_bounds__(kGapBlock) void k_bgap_final(const BImg *__restrict__ imgs, const double *__restrict__ part,
                                                           int *__restrict__ active, int *__restrict__ buf,
                                                           int *__restrict__ iters, double *__restrict__ gap3,
-                                                          double tol, int nxt, int iter_after) {
+                                                          double tol, int nxt, const IterSched *__restrict__ sc) {
+    const int iter_after = (int)sc->iter_after;
     const int j = blockIdx.x;
     if (!active[j]) return;  // uniform per block
     const BImg im = imgs[j];
@@ -388,6 +391,7 @@ struct BWs {
     int *rowimg, *active, *buf, *iters;
     double *lam, *gap3, *part;
     T *x[2], *y[2], *xbar, *pv;
+    IterSched *sched;  // [kSchedCap] per-iteration scalars of the current chunk
     void *seg;
     size_t seg_bytes;
 };
@@ -416,6 +420,7 @@ static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
     const size_t o_y1 = off;  off += al(sizeof(T) * N);
     const size_t o_xb = off;  off += al(sizeof(T) * N);
     const size_t o_pv = off;  off += al(sizeof(T) * N);
+    const size_t o_sc = off;  off += al(sizeof(IterSched) * kSchedCap);
     const size_t o_sg = off;  off += al(sr > scol ? sr : scol);
     if (base && out) {
         char *p = (char *)base;
@@ -435,6 +440,7 @@ static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
         out->y[1] = (T *)(p + o_y1);
         out->xbar = (T *)(p + o_xb);
         out->pv = (T *)(p + o_pv);
+        out->sched = (IterSched *)(p + o_sc);
         out->seg = (void *)(p + o_sg);
         out->seg_bytes = sr > scol ? sr : scol;
     }
@@ -484,20 +490,51 @@ static tv_status batched_setup(const BGeom &g, const int64_t *H, const int64_t *
 }
 
 template <typename T>
-static hipError_t batched_col_step(const BGeom &g, const BWs<T> &ws, int cur, double tau, const SegPlan &pc,
+static hipError_t batched_col_step(const BGeom &g, const BWs<T> &ws, int cur, const IterSched *sc, const SegPlan &pc,
                                    hipStream_t st) {
-    typename BColProb<T>::Params cp{ws.cols, ws.y[cur], ws.xbar, ws.y[cur ^ 1], (T)(1.0 / tau), ws.lam, ws.active};
+    typename BColProb<T>::Params cp{ws.cols, ws.y[cur], ws.xbar, ws.y[cur ^ 1], sc, ws.lam, ws.active};
     return seg_run<T, BColProb<T>, kTile>(ws.seg, g.ncols, g.maxH, pc, cp, st);
 }
 
 template <typename T>
-static hipError_t batched_row_step(const BGeom &g, const BWs<T> &ws, const T *f, int cur, double tau,
+static hipError_t batched_row_step(const BGeom &g, const BWs<T> &ws, const T *f, int cur, const IterSched *sc,
                                    const SegPlan &pr, hipStream_t st) {
-    const double theta = 1.0 / sqrt(1.0 + 2.0 * tau), inv1p = 1.0 / (1.0 + tau);
-    typename BRowProb<T>::Params rp{ws.rows, f, ws.x[cur], ws.y[cur ^ 1], ws.x[cur ^ 1], ws.xbar, (T)tau, (T)inv1p,
-                                    (T)theta, tau, inv1p, ws.lam, ws.active};
+    typename BRowProb<T>::Params rp{ws.rows, f, ws.x[cur], ws.y[cur ^ 1], ws.x[cur ^ 1], ws.xbar, sc, ws.lam,
+                                    ws.active};
     return seg_run<T, BRowProb<T>, kTile>(ws.seg, g.nrows, g.maxW, pr, rp, st);
 }
+
+// Issues `count` iterations starting at parity cur0; iteration j reads its
+// scalars from ws.sched[j]; the last one is followed by the gap evaluation and
+// the per-image stopping test.  The same sequence is launched directly or
+// captured into a HIP graph and replayed.
+template <typename T>
+static hipError_t batched_iters(const BGeom &g, const BWs<T> &ws, const T *f, int cur0, int count, double gap_tol,
+                                const SegPlan &pc, const SegPlan &pr, hipStream_t st) {
+    int cur = cur0;
+    for (int j = 0; j < count; ++j) {
+        const int nxt = cur ^ 1;
+        const IterSched *sc = ws.sched + j;
+        hipError_t e = batched_col_step<T>(g, ws, cur, sc, pc, st);
+        if (e == hipSuccess) e = batched_row_step<T>(g, ws, f, cur, sc, pr, st);
+        if (e != hipSuccess) return e;
+        if (j == count - 1) {
+            const unsigned cb = (unsigned)((g.ncols + 63) / 64);
+            hipLaunchKernelGGL((k_bgap_pv<T>), dim3(cb), dim3(64), 0, st, ws.cols, g.ncols, ws.y[nxt], ws.pv, ws.lam,
+                               ws.active);
+            const unsigned rb = (unsigned)((g.nrows + kGapBlock / 64 - 1) / (kGapBlock / 64));
+            hipLaunchKernelGGL((k_bgap_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, ws.imgs, ws.rowimg, g.nrows, f,
+                               ws.x[nxt], ws.x[cur], ws.y[nxt], ws.pv, ws.lam, ws.active, sc, ws.part);
+            hipLaunchKernelGGL(k_bgap_final, dim3(g.nimg), dim3(kGapBlock), 0, st, ws.imgs, ws.part, ws.active,
+                               ws.buf, ws.iters, ws.gap3, gap_tol, nxt, sc);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        cur = nxt;
+    }
+    return hipSuccess;
+}
+
 
 template <typename T>
 static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
@@ -518,27 +555,43 @@ static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t
     if (seg_ws_bytes_plan<T>(g.nrows, g.maxW, pr) > ws.seg_bytes ||
         seg_ws_bytes_plan<T>(g.ncols, g.maxH, pc) > ws.seg_bytes)
         return TV_ERR_WORKSPACE;
+    ChunkGraphs graphs;
+    std::vector<IterSched> sched(kSchedCap);
     while (k < opt->max_iter && n_active > 0) {
         const int chunk = (opt->max_iter - k < every) ? opt->max_iter - k : every;
-        for (int jj = 0; jj < chunk; ++jj, ++k) {
-            const double theta = 1.0 / sqrt(1.0 + 2.0 * tau), inv1p = 1.0 / (1.0 + tau);
-            const int nxt = cur ^ 1;
-            if (batched_col_step<T>(g, ws, cur, tau, pc, st) != hipSuccess) return TV_ERR_HIP;
-            if (batched_row_step<T>(g, ws, f, cur, tau, pr, st) != hipSuccess) return TV_ERR_HIP;
-            if (jj == chunk - 1) {
-                const unsigned cb = (unsigned)((g.ncols + 63) / 64);
-                hipLaunchKernelGGL((k_bgap_pv<T>), dim3(cb), dim3(64), 0, st, ws.cols, g.ncols, ws.y[nxt], ws.pv,
-                                   ws.lam, ws.active);
-                const unsigned rb = (unsigned)((g.nrows + kGapBlock / 64 - 1) / (kGapBlock / 64));
-                hipLaunchKernelGGL((k_bgap_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, ws.imgs, ws.rowimg, g.nrows, f,
-                                   ws.x[nxt], ws.x[cur], ws.y[nxt], ws.pv, ws.lam, ws.active, (T)tau, (T)inv1p,
-                                   (1.0 + tau) / tau, ws.part);
-                hipLaunchKernelGGL(k_bgap_final, dim3(g.nimg), dim3(kGapBlock), 0, st, ws.imgs, ws.part, ws.active,
-                                   ws.buf, ws.iters, ws.gap3, opt->gap_tol, nxt, k + 1);
+        // upload the chunk's schedule in pieces of at most kSchedCap iterations;
+        // the gap follows the chunk's last iteration
+        for (int done = 0; done < chunk;) {
+            const int piece = (chunk - done < kSchedCap) ? chunk - done : kSchedCap;
+            for (int j = 0; j < piece; ++j) {
+                sched[j] = make_sched(tau, k + j);
+                tau *= sched[j].theta;
             }
-            if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
-            tau *= theta;
-            cur = nxt;
+            if (hipMemcpyAsync(ws.sched, sched.data(), sizeof(IterSched) * piece, hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                return TV_ERR_HIP;
+            const bool last = done + piece == chunk;
+            const double tol = opt->gap_tol;
+            auto issue = [&](hipStream_t s2) { return batched_iters<T>(g, ws, f, cur, piece, tol, pc, pr, s2); };
+            hipGraphExec_t ge = nullptr;
+            if (opt->use_graph && last && piece == every && done == 0) ge = graphs.get(cur, issue);
+            if (ge) {
+                if (hipGraphLaunch(ge, st) != hipSuccess) return TV_ERR_HIP;
+            } else if (last) {
+                if (batched_iters<T>(g, ws, f, cur, piece, tol, pc, pr, st) != hipSuccess) return TV_ERR_HIP;
+            } else {
+                // a piece without the gap: iterations only
+                for (int j = 0; j < piece; ++j) {
+                    if (batched_col_step<T>(g, ws, (cur + j) & 1, ws.sched + j, pc, st) != hipSuccess ||
+                        batched_row_step<T>(g, ws, f, (cur + j) & 1, ws.sched + j, pr, st) != hipSuccess)
+                        return TV_ERR_HIP;
+                }
+            }
+            // the host schedule buffer is reused by the next piece: wait for the upload
+            if (!last && hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
+            cur = (cur + piece) & 1;
+            k += piece;
+            done += piece;
         }
         if (hipMemcpyAsync(active.data(), ws.active, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st) != hipSuccess)
             return TV_ERR_HIP;
@@ -580,15 +633,17 @@ static tv_status batched_autotune_t(const BGeom &g, const int64_t *H, const int6
     batched_layout<T>(workspace, g, &ws);
     tv_status s = batched_setup<T>(g, H, W, pix, lam, f, ws, st);
     if (s != TV_OK) return s;
+    const IterSched sc0 = make_sched(tau0, 0);
+    if (hipMemcpyAsync(ws.sched, &sc0, sizeof(sc0), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
     SegPlan pc, pr;
     s = tune_launch<T>(
-        g.ncols, g.maxH, ws.seg_bytes, [&](const SegPlan &p) { return batched_col_step<T>(g, ws, 0, tau0, p, st); },
-        st, &pc, col);
+        g.ncols, g.maxH, ws.seg_bytes,
+        [&](const SegPlan &p) { return batched_col_step<T>(g, ws, 0, ws.sched, p, st); }, st, &pc, col);
     if (s != TV_OK) return s;
-    if (batched_col_step<T>(g, ws, 0, tau0, pc, st) != hipSuccess) return TV_ERR_HIP;
+    if (batched_col_step<T>(g, ws, 0, ws.sched, pc, st) != hipSuccess) return TV_ERR_HIP;
     s = tune_launch<T>(
         g.nrows, g.maxW, ws.seg_bytes,
-        [&](const SegPlan &p) { return batched_row_step<T>(g, ws, f, 0, tau0, p, st); }, st, &pr, row);
+        [&](const SegPlan &p) { return batched_row_step<T>(g, ws, f, 0, ws.sched, p, st); }, st, &pr, row);
     if (s != TV_OK) return s;
     seg_set_tuned(kPlanBatchCol, g.ncols, g.maxH, pc);
     seg_set_tuned(kPlanBatchRow, g.nrows, g.maxW, pr);

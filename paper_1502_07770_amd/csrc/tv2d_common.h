@@ -1,6 +1,7 @@
 // tv2d_common.h -- pieces shared by the single-image and batched 2D solvers.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 #include "../../include/tvchain.h"
@@ -14,6 +15,31 @@ constexpr int kGapBlock = 256;
 // batched solvers sum in the same order (within a block from zero, blocks
 // added left to right), so their gaps agree bit for bit.
 constexpr int kGapRows = 64;
+
+// Per-iteration scalars of the accelerated schedule, computed on the host in
+// FP64 and read by the kernels from device memory, so that a chunk of
+// iterations can be captured once in a HIP graph and replayed.
+struct IterSched {
+    double tau;     // tau_k
+    double sigma;   // 1 / tau_k
+    double theta;   // 1 / sqrt(1 + 2 tau_k)
+    double inv1p;   // 1 / (1 + tau_k)
+    double pscale;  // (1 + tau_k) / tau_k
+    int64_t iter_after;  // k + 1
+};
+// Iterations whose schedule one upload holds (and the longest captured chunk).
+constexpr int kSchedCap = 64;
+
+__host__ __forceinline__ IterSched make_sched(double tau, int64_t k) {
+    IterSched s;
+    s.tau = tau;
+    s.sigma = 1.0 / tau;
+    s.theta = 1.0 / sqrt(1.0 + 2.0 * tau);
+    s.inv1p = 1.0 / (1.0 + tau);
+    s.pscale = (1.0 + tau) / tau;
+    s.iter_after = k + 1;
+    return s;
+}
 
 // b_i of the row step; shared by the row chain source and the gap kernel so
 // both see bit-identical values.
@@ -98,5 +124,41 @@ tv_status tune_launch(int64_t C, int64_t n, size_t seg_bytes, Fn launch, hipStre
     }
     return TV_OK;
 }
+
+// Graphs of full chunks, one per starting parity, captured on a private
+// stream on first use and replayed on the caller's stream.
+struct ChunkGraphs {
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool failed = false;
+    ~ChunkGraphs() {
+        for (auto &x : exec)
+            if (x) hipGraphExecDestroy(x);
+        if (cap) hipStreamDestroy(cap);
+    }
+    template <class Fn>
+    hipGraphExec_t get(int parity, Fn issue) {
+        if (failed) return nullptr;
+        if (exec[parity]) return exec[parity];
+        if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+            failed = true;
+            return nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            failed = true;
+            return nullptr;
+        }
+        const hipError_t e = issue(cap);
+        const hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e != hipSuccess || e2 != hipSuccess || !graph ||
+            hipGraphInstantiate(&exec[parity], graph, nullptr, nullptr, 0) != hipSuccess) {
+            exec[parity] = nullptr;
+            failed = true;
+        }
+        if (graph) hipGraphDestroy(graph);
+        return exec[parity];
+    }
+};
 
 }  // namespace tvc

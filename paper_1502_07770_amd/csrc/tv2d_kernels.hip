@@ -30,6 +30,8 @@
 // partition and tree reductions, so they are deterministic.
 #include <math.h>
 
+#include <vector>
+
 #include "../../include/tvchain.h"
 #include "kernels.h"
 #include "seg_kernels.h"
@@ -44,7 +46,7 @@ struct ColProb {
         const T *y_old;
         const T *xbar;
         T *y_new;
-        T sigma;
+        const IterSched *sc;
         T lam;
         int64_t W;
     };
@@ -102,10 +104,10 @@ struct ColProb {
         return ChainSpan{c, 0, nmax, 0};
     }
     static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
-        return Src{p.y_old, p.xbar, p.sigma, p.lam, sp.base, p.W};
+        return Src{p.y_old, p.xbar, (T)p.sc->sigma, p.lam, sp.base, p.W};
     }
     static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
-        return Sink{p.y_old, p.xbar, p.y_new, p.sigma, sp.base, p.W};
+        return Sink{p.y_old, p.xbar, p.y_new, (T)p.sc->sigma, sp.base, p.W};
     }
 };
 
@@ -119,7 +121,8 @@ struct RowProb {
         const T *y;
         T *x_new;
         T *xbar;
-        T tau, inv1p, theta, wrow;
+        const IterSched *sc;
+        double lam;
         int64_t W;
     };
     struct Pre {
@@ -195,10 +198,11 @@ struct RowProb {
         return ChainSpan{r, 1, nmax, 0};
     }
     static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
-        return Src{p.f, p.x_old, p.y, p.tau, p.inv1p, p.wrow, sp.base, p.ldf, p.W};
+        const IterSched sc = *p.sc;
+        return Src{p.f, p.x_old, p.y, (T)sc.tau, (T)sc.inv1p, (T)(p.lam * sc.tau * sc.inv1p), sp.base, p.ldf, p.W};
     }
     static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
-        return Sink{p.x_old, p.x_new, p.xbar, p.theta, sp.base, p.W};
+        return Sink{p.x_old, p.x_new, p.xbar, (T)p.sc->theta, sp.base, p.W};
     }
 };
 
@@ -249,7 +253,9 @@ template <typename T>
 __global__ __launch_bounds__(kGapBlock) void k_gap_rows(const T *__restrict__ f, int64_t ldf, const T *__restrict__ xn,
                                                         const T *__restrict__ xo, const T *__restrict__ y,
                                                         const T *__restrict__ pv, int64_t H, int64_t W, double lam,
-                                                        T tau, T inv1p, double pscale, double *__restrict__ part) {
+                                                        const IterSched *__restrict__ sc, double *__restrict__ part) {
+    const T tau = (T)sc->tau, inv1p = (T)sc->inv1p;
+    const double pscale = sc->pscale;
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * (kGapBlock / 64) + (threadIdx.x >> 6);
     if (r >= H) return;  // whole waves exit together: no block barrier below
@@ -311,7 +317,8 @@ __global__ __launch_bounds__(kGapBlock) void k_gap_rows(const T *__restrict__ f,
 // history slot of this iteration.
 __global__ __launch_bounds__(kGapBlock) void k_gap_final(const double *__restrict__ part, int nparts, double HW,
                                                          double *__restrict__ out, double *__restrict__ hist,
-                                                         int64_t hist_idx) {
+                                                         const IterSched *__restrict__ sc) {
+    const int64_t hist_idx = sc->iter_after - 1;
     __shared__ double sP[kGapBlock], sD[kGapBlock];
     double P = 0.0, D = 0.0;
     for (int i = threadIdx.x; i < nparts; i += kGapBlock) {
@@ -352,6 +359,7 @@ template <typename T>
 struct Tv2dWs {
     Tv2dHeader *hdr;
     T *x[2], *y[2], *xbar, *pv;
+    IterSched *sched;  // [kSchedCap] per-iteration scalars of the current chunk
     double *part;
     double *colpart;
     void *seg;       // chain-prox workspace, shared by the row and column launches
@@ -375,6 +383,7 @@ static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out) {
     const size_t o_y1 = off;  off += al(sizeof(T) * N);
     const size_t o_xb = off;  off += al(sizeof(T) * N);
     const size_t o_pv = off;  off += al(sizeof(T) * N);
+    const size_t o_sc = off;  off += al(sizeof(IterSched) * kSchedCap);
     const size_t o_pt = off;  off += al(sizeof(double) * 2 * nparts);
     const size_t o_cp = off;  off += al(sizeof(double) * ncol);
     const size_t o_sg = off;  off += al(sr > scol ? sr : scol);
@@ -387,6 +396,7 @@ static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out) {
         out->y[1] = (T *)(p + o_y1);
         out->xbar = (T *)(p + o_xb);
         out->pv = (T *)(p + o_pv);
+        out->sched = (IterSched *)(p + o_sc);
         out->part = (double *)(p + o_pt);
         out->colpart = (double *)(p + o_cp);
         out->seg = (void *)(p + o_sg);
@@ -397,46 +407,51 @@ static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out) {
 
 // Column step: y[nxt] = eta - prox(eta), eta = y[cur] + sigma xbar.
 template <typename T>
-static hipError_t tv2d_col_step(const Tv2dWs<T> &ws, int64_t H, int64_t W, double lam, int cur, double tau,
+static hipError_t tv2d_col_step(const Tv2dWs<T> &ws, int64_t H, int64_t W, double lam, int cur, const IterSched *sc,
                                 const SegPlan &pc, hipStream_t st) {
     const int nxt = cur ^ 1;
-    typename ColProb<T>::Params pp{ws.y[cur], ws.xbar, ws.y[nxt], (T)(1.0 / tau), (T)lam, W};
+    typename ColProb<T>::Params pp{ws.y[cur], ws.xbar, ws.y[nxt], sc, (T)lam, W};
     return seg_run<T, ColProb<T>, kTile>(ws.seg, W, H, pc, pp, st);
 }
 
 // Row step: x[nxt] = prox(b), xbar = x[nxt] + theta (x[nxt] - x[cur]).
 template <typename T>
 static hipError_t tv2d_row_step(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
-                                int cur, double tau, const SegPlan &pr, hipStream_t st) {
+                                int cur, const IterSched *sc, const SegPlan &pr, hipStream_t st) {
     const int nxt = cur ^ 1;
-    const double theta = 1.0 / sqrt(1.0 + 2.0 * tau);
-    const double inv1p = 1.0 / (1.0 + tau);
-    typename RowProb<T>::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, (T)tau, (T)inv1p,
-                                   (T)theta, (T)(lam * tau * inv1p), W};
+    typename RowProb<T>::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, sc, lam, W};
     return seg_run<T, RowProb<T>, kTile>(ws.seg, H, W, pr, pp, st);
 }
 
+// `count` iterations from parity cur0, iteration j reading ws.sched[j]; the gap
+// after the last one.  Launched directly or captured into a HIP graph.
 template <typename T>
-static hipError_t tv2d_iteration(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
-                                 int cur, double tau, bool gap, int64_t k, double *hist, hipStream_t st) {
-    const int nxt = cur ^ 1;
-    const double inv1p = 1.0 / (1.0 + tau);
-    hipError_t e = tv2d_col_step<T>(ws, H, W, lam, cur, tau, seg_plan(W, H, kPlan2dCol), st);
-    if (e != hipSuccess) return e;
-    e = tv2d_row_step<T>(ws, f, ldf, H, W, lam, cur, tau, seg_plan(H, W, kPlan2dRow), st);
-    if (e != hipSuccess) return e;
-    if (gap) {
-        const int64_t nseg = (H + kGapRows - 1) / kGapRows;
-        const unsigned cb = (unsigned)((nseg * W + 63) / 64);
-        hipLaunchKernelGGL((k_gap_colsum<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, H, W);
-        hipLaunchKernelGGL((k_gap_pv<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, ws.pv, H, W, lam);
-        const unsigned rb = (unsigned)((H + kGapBlock / 64 - 1) / (kGapBlock / 64));
-        hipLaunchKernelGGL((k_gap_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, f, ldf, ws.x[nxt], ws.x[cur],
-                           ws.y[nxt], ws.pv, H, W, lam, (T)tau, (T)inv1p, (1.0 + tau) / tau, ws.part);
-        hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(kGapBlock), 0, st, ws.part, (int)H, (double)(H * W),
-                           &ws.hdr->gap[0], hist, k);
+static hipError_t tv2d_iters(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
+                             int cur0, int count, bool gap, double *hist, const SegPlan &pc, const SegPlan &pr,
+                             hipStream_t st) {
+    int cur = cur0;
+    for (int j = 0; j < count; ++j) {
+        const int nxt = cur ^ 1;
+        const IterSched *sc = ws.sched + j;
+        hipError_t e = tv2d_col_step<T>(ws, H, W, lam, cur, sc, pc, st);
+        if (e == hipSuccess) e = tv2d_row_step<T>(ws, f, ldf, H, W, lam, cur, sc, pr, st);
+        if (e != hipSuccess) return e;
+        if (gap && j == count - 1) {
+            const int64_t nseg = (H + kGapRows - 1) / kGapRows;
+            const unsigned cb = (unsigned)((nseg * W + 63) / 64);
+            hipLaunchKernelGGL((k_gap_colsum<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, H, W);
+            hipLaunchKernelGGL((k_gap_pv<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, ws.pv, H, W, lam);
+            const unsigned rb = (unsigned)((H + kGapBlock / 64 - 1) / (kGapBlock / 64));
+            hipLaunchKernelGGL((k_gap_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, f, ldf, ws.x[nxt], ws.x[cur],
+                               ws.y[nxt], ws.pv, H, W, lam, sc, ws.part);
+            hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(kGapBlock), 0, st, ws.part, (int)H, (double)(H * W),
+                               &ws.hdr->gap[0], hist, sc);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        cur = nxt;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 template <typename T>
@@ -464,17 +479,40 @@ static tv_status tv2d_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, doub
     int done = 0;
     double g3[3] = {h.gap[0], h.gap[1], h.gap[2]};
     bool have_gap = !opt->resume ? false : !isnan(h.gap[2]);
+    const SegPlan pc = seg_plan(W, H, kPlan2dCol), pr = seg_plan(H, W, kPlan2dRow);
+    if (seg_ws_bytes_plan<T>(W, H, pc) > ws.seg_bytes || seg_ws_bytes_plan<T>(H, W, pr) > ws.seg_bytes)
+        return TV_ERR_WORKSPACE;
+    ChunkGraphs graphs;
+    std::vector<IterSched> sched(kSchedCap);
     while (done < opt->max_iter) {
         const int chunk = (opt->max_iter - done < every) ? opt->max_iter - done : every;
-        for (int j = 0; j < chunk; ++j) {
-            const bool gap = (j == chunk - 1);
-            hipError_t e = tv2d_iteration<T>(ws, f, ld, H, W, lam, (int)h.cur, h.tau, gap, h.iters,
-                                             opt->gap_history, st);
-            if (e != hipSuccess) return TV_ERR_HIP;
-            const double theta = 1.0 / sqrt(1.0 + 2.0 * h.tau);
-            h.tau *= theta;
-            h.cur ^= 1;
-            ++h.iters;
+        for (int part = 0; part < chunk;) {
+            const int piece = (chunk - part < kSchedCap) ? chunk - part : kSchedCap;
+            for (int j = 0; j < piece; ++j) {
+                sched[j] = make_sched(h.tau, h.iters + j);
+                h.tau *= sched[j].theta;
+            }
+            if (hipMemcpyAsync(ws.sched, sched.data(), sizeof(IterSched) * piece, hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                return TV_ERR_HIP;
+            const bool last = part + piece == chunk;
+            const int cur = (int)h.cur;
+            auto issue = [&](hipStream_t s2) {
+                return tv2d_iters<T>(ws, f, ld, H, W, lam, cur, piece, true, opt->gap_history, pc, pr, s2);
+            };
+            hipGraphExec_t ge = nullptr;
+            if (opt->use_graph && last && piece == every && part == 0) ge = graphs.get(cur, issue);
+            if (ge) {
+                if (hipGraphLaunch(ge, st) != hipSuccess) return TV_ERR_HIP;
+            } else if (tv2d_iters<T>(ws, f, ld, H, W, lam, cur, piece, last, opt->gap_history, pc, pr, st) !=
+                       hipSuccess) {
+                return TV_ERR_HIP;
+            }
+            // the host schedule buffer is reused by the next piece: wait for the upload
+            if (!last && hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
+            h.cur = (h.cur + piece) & 1;
+            h.iters += piece;
+            part += piece;
         }
         done += chunk;
         if (hipMemcpyAsync(g3, ws.hdr->gap, sizeof(g3), hipMemcpyDeviceToHost, st) != hipSuccess) return TV_ERR_HIP;
@@ -514,15 +552,17 @@ static tv_status tv2d_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld, d
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
     hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
+    const IterSched sc0 = make_sched(tau0, 0);
+    if (hipMemcpyAsync(ws.sched, &sc0, sizeof(sc0), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
     SegPlan pc, pr;
     tv_status s = tune_launch<T>(
-        W, H, ws.seg_bytes, [&](const SegPlan &p) { return tv2d_col_step<T>(ws, H, W, lam, 0, tau0, p, st); }, st,
-        &pc, col);
+        W, H, ws.seg_bytes, [&](const SegPlan &p) { return tv2d_col_step<T>(ws, H, W, lam, 0, ws.sched, p, st); },
+        st, &pc, col);
     if (s != TV_OK) return s;
-    if (tv2d_col_step<T>(ws, H, W, lam, 0, tau0, pc, st) != hipSuccess) return TV_ERR_HIP;
+    if (tv2d_col_step<T>(ws, H, W, lam, 0, ws.sched, pc, st) != hipSuccess) return TV_ERR_HIP;
     s = tune_launch<T>(
         H, W, ws.seg_bytes,
-        [&](const SegPlan &p) { return tv2d_row_step<T>(ws, f, ld, H, W, lam, 0, tau0, p, st); }, st, &pr, row);
+        [&](const SegPlan &p) { return tv2d_row_step<T>(ws, f, ld, H, W, lam, 0, ws.sched, p, st); }, st, &pr, row);
     if (s != TV_OK) return s;
     seg_set_tuned(kPlan2dCol, W, H, pc);
     seg_set_tuned(kPlan2dRow, H, W, pr);

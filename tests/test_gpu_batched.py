@@ -104,3 +104,14 @@ def test_full_size_batch_of_256_against_oracle():
         xo, _, (_, _, go), k = oracle.tv2d(fv, lams[j], max_iter=infos[j]["iters"])
         assert np.abs(xs[j].double().cpu().numpy() - xo).max() <= 1e-4 * np.ptp(fv), j
         assert abs(infos[j]["gap_norm"] - go) <= 1e-6
+
+
+def test_batched_graph_replays_match_direct_launches():
+    specs, imgs = _batch(10, 24, 180, seed=9)
+    ts = [torch.tensor(im, dtype=torch.float32, device="cuda") for im in imgs]
+    lams = [s["lam"] for s in specs]
+    xs0, inf0 = binding.tv2d_batched(ts, lams, max_iter=300, gap_every=5, gap_tol=1e-4)
+    xs1, inf1 = binding.tv2d_batched(ts, lams, max_iter=300, gap_every=5, gap_tol=1e-4, use_graph=True)
+    assert len({i["iters"] for i in inf0}) > 1          # images stop in different replays
+    for a, b, ia, ib in zip(xs0, xs1, inf0, inf1):
+        assert torch.equal(a, b) and ia["iters"] == ib["iters"] and ia["gap_norm"] == ib["gap_norm"]

@@ -153,3 +153,22 @@ def test_full_size_4096_fp32_to_gap_against_oracle():
     assert k == info["iters"] and go <= 1e-4
     assert np.abs(x.double().cpu().numpy() - xo).max() <= 1e-4 * np.ptp(fv)
     assert abs(info["gap_norm"] - go) <= 1e-6
+
+
+@pytest.mark.parametrize("every,iters", [(5, 23), (4, 40)])
+def test_graph_replays_match_direct_launches(every, iters):
+    """Chunks of gap_every iterations captured once per starting parity and
+    replayed (odd chunks alternate parity; a final partial chunk runs
+    directly): every gap and the final iterate equal the direct launches'."""
+    f = torch.tensor(_img(160, 120, seed=14), dtype=torch.float32, device="cuda")
+    h0 = torch.full((iters,), float("nan"), dtype=torch.float64, device="cuda")
+    h1 = torch.full((iters,), float("nan"), dtype=torch.float64, device="cuda")
+    x0, i0 = binding.tv2d(f, 0.12, max_iter=iters, gap_every=every, gap_history=h0)
+    x1, i1 = binding.tv2d(f, 0.12, max_iter=iters, gap_every=every, gap_history=h1, use_graph=True)
+    assert torch.equal(x0, x1)
+    assert torch.equal(h0.isnan(), h1.isnan()) and torch.equal(h0[~h0.isnan()], h1[~h1.isnan()])
+    assert i0["iters"] == i1["iters"] == iters and i0["gap_norm"] == i1["gap_norm"]
+    # stopping at the tolerance inside the graph path
+    x2, i2 = binding.tv2d(f, 0.12, max_iter=500, gap_every=every, gap_tol=2e-4, use_graph=True)
+    x3, i3 = binding.tv2d(f, 0.12, max_iter=500, gap_every=every, gap_tol=2e-4)
+    assert i2["iters"] == i3["iters"] and torch.equal(x2, x3)
