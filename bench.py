@@ -198,9 +198,13 @@ def bench_tv2d(side: int, seed: int, iters_fixed: int | None, tol: float, max_it
         s.solve(f, 0.1, max_iter=2, gap_every=1)  # warm-up
         torch.cuda.synchronize()
         if iters_fixed:
-            t = time.perf_counter()
-            _, info = s.solve(f, 0.1, max_iter=iters_fixed, gap_every=10)
-            r["ms_%d_iters" % iters_fixed] = round((time.perf_counter() - t) * 1e3, 3)
+            for graph in (False, True):
+                s.solve(f, 0.1, max_iter=20, gap_every=10, use_graph=graph)  # warm-up (graph capture)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, info = s.solve(f, 0.1, max_iter=iters_fixed, gap_every=10, use_graph=graph)
+                key = "ms_%d_iters%s" % (iters_fixed, "_graph" if graph else "")
+                r[key] = round((time.perf_counter() - t) * 1e3, 3)
             r["gap_after_%d" % iters_fixed] = info["gap_norm"]
         t = time.perf_counter()
         _, info = s.solve(f, 0.1, max_iter=max_iter, gap_every=5, gap_tol=tol)
@@ -255,9 +259,14 @@ def bench_batched():
     xs, infos = binding.tv2d_batched(shapes, lams, max_iter=2000, gap_every=10, gap_tol=1e-4, packed=f)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
+    t = time.perf_counter()
+    binding.tv2d_batched(shapes, lams, max_iter=2000, gap_every=10, gap_tol=1e-4, packed=f, use_graph=True)
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - t
     iters = [i["iters"] for i in infos]
     return {"workload": "256 images, H,W ~ U{64..2048}, lambda ~ U[0.02,0.3], sigma ~ U[0.05,0.2], FP32",
             "pixels": int(packed.size), "time_to_gap_ms": round(dt * 1e3, 1),
+            "time_to_gap_ms_graph": round(dt_graph * 1e3, 1),
             "all_reached": all(i["status"] == binding.TV_OK for i in infos),
             "iters_min": min(iters), "iters_max": max(iters), "generate_s": round(gen_s, 1), "plans": tuned}
 
