@@ -49,10 +49,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "chain_prox_4096_rows_cols_traffic
 
 
 def kernel_source_hash() -> str:
+    """Hash of the chain-prox kernel sources with comments and whitespace
+    removed: a counter record stays valid across comment edits only."""
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

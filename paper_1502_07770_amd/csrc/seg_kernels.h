@@ -12,29 +12,34 @@
 // the first node where the two deques are equal every later step computes the
 // same values.  So:
 //  k_seg_main   runs its segment's DP from an empty deque starting H nodes
-//               early (the halo), streams lambda^-/lambda^+ for its own nodes,
-//               and saves its deque after the halo (HS), at two checkpoints
-//               inside the segment (CK1, CK2) and at its end (ES).  It then
-//               runs the backward clip pass of Algorithm 2 over its
-//               own nodes: composing x_i = clip(x_{i+1}, lam^-_i, lam^+_i) from
-//               the right, the composed map is a clip onto an interval, and once
-//               that interval is a single point every node left of it is
-//               determined and written.
-//  k_seg_verify compares the saved end state of segment s-1 with the halo state
-//               of segment s (exact comparison of breakpoints and slope tags).
-//  k_seg_fix    one lane per chain, only where a comparison failed: redoes the
-//               segment from the true incoming deque until it meets a saved
-//               checkpoint (then the first pass is exact from there), and redoes
-//               its backward pass.  Chains whose deque outgrew the LDS ring are
-//               solved here sequentially with the deque in HBM.
+//               early (the halo, which stores nothing), streams lambda^-/
+//               lambda^+ for its own nodes, and saves its deque after the halo
+//               (HS), at 4 checkpoints every CK nodes inside the segment and at
+//               its end (ES).  It then runs the backward clip pass of
+//               Algorithm 2 over its own nodes: composing x_i = clip(x_{i+1},
+//               lam^-_i, lam^+_i) from the right, the composed map is a clip onto
+//               an interval, and once that interval is a single point every node
+//               left of it is determined and written.
+//  k_seg_repair compares the saved end state of segment s-1 with the halo state
+//               of segment s (hash, then exact comparison of breakpoints and
+//               tags); where they differ it reruns the segment from that end
+//               state until the deque meets a first-pass checkpoint (or the
+//               segment end) and redoes the backward pass.
+//  k_seg_fix    one lane per chain: redoes, sequentially, the rare segments
+//               whose repair started from a state that was not yet the true one;
+//               then composes the value entering each segment from the root.
+//               Chains whose deque outgrew the ring go to k_seg_ovf.
+//  k_seg_ovf    a pool of lanes solves the overflowed chains with the deque in
+//               HBM.
 //  k_seg_tail   finishes each segment's un-collapsed right tail from the value at
-//               the segment's right end (a short composition over segments).
+//               the segment's right end.
 // The output is bit-identical to running the DP sequentially per chain.
 //
-// The deque is a ring of packed (lambda, tag) entries in LDS with the front
-// and back entries cached in registers and the next entry of a scan prefetched
-// one pop ahead.  Loads of node data run P nodes ahead into registers, so each
-// memory wait covers requests issued a tile earlier.
+// The deque is a ring of packed (lambda, tag) entries in LDS, stored twice so
+// the entries next to either end lie at fixed offsets from one address, with
+// the front and back entries cached in registers.  Loads of node data run P
+// nodes ahead into registers (four per 16-byte load on unit-stride chains), so
+// each memory wait covers requests issued a tile earlier.
 #pragma once
 #include "chain_core.h"
 
