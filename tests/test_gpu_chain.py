@@ -300,3 +300,28 @@ def test_autotuned_plan_gives_identical_results(dtype):
         assert torch.equal(binding.chain_prox(img, 0.1, dim=0), ref_c)
     finally:
         binding.autotune_clear()
+
+
+def test_maximum_length_fp32_chain():
+    """The longest FP32 chain the ABI accepts (2^24 - 1 nodes, slopes still exact
+    integers in float), against the oracle; and a length of 2^24 is rejected."""
+    n = (1 << 24) - 1
+    y = synth.piecewise_constant(1, n, seed=61)[0]
+    t = _dev(y, torch.float32)
+    x = binding.chain_prox(t, 0.3, dim=-1)
+    yv = t.double().cpu().numpy()
+    xo = oracle.chain_prox(yv[None], w_scalar=0.3)[0]
+    assert np.abs(x.double().cpu().numpy() - xo).max() <= TOL[torch.float32] * np.ptp(yv)
+    with pytest.raises(binding.TvChainError):
+        binding.chain_prox(torch.zeros(1 << 24, dtype=torch.float32, device="cuda"), 0.3, dim=-1)
+
+
+def test_many_tiny_chains_and_single_node_chains():
+    """A million chains of 1, 2 and 3 nodes (closed forms of the prox)."""
+    rng = np.random.default_rng(62)
+    for n in (1, 2, 3):
+        y = rng.normal(size=(1 << 20, n))
+        x = binding.chain_prox(_dev(y, torch.float64), 0.25, dim=-1).cpu().numpy()
+        assert np.abs(x - oracle.chain_prox(y, w_scalar=0.25)).max() < 1e-12
+        if n == 1:
+            assert np.array_equal(x, y)
