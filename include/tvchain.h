@@ -245,9 +245,11 @@ typedef struct {
     int64_t target_lanes;
     int64_t min_segment;
     int64_t halo;
+    int64_t ring_slots;  /* breakpoint slots of the on-chip deque: 16 or 32 */
 } tv_tuning;
 
-/* Set the tuning (NULL restores the defaults); TV_ERR_INVALID_ARG on values < 1.
+/* Set the tuning (NULL restores the defaults); TV_ERR_INVALID_ARG on values < 1
+ * or a ring size other than 16 or 32.
  * Not thread-safe with respect to concurrent prox calls: a workspace sized
  * before a change may be too small after it (TV_ERR_WORKSPACE). */
 tv_status tv_set_tuning(const tv_tuning *tuning);

@@ -57,7 +57,8 @@ class Tv2dOptions(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("target_lanes", ctypes.c_int64), ("min_segment", ctypes.c_int64), ("halo", ctypes.c_int64)]
+    _fields_ = [("target_lanes", ctypes.c_int64), ("min_segment", ctypes.c_int64), ("halo", ctypes.c_int64),
+                ("ring_slots", ctypes.c_int64)]
 
 
 class TuningResult(ctypes.Structure):
@@ -167,17 +168,19 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 def get_tuning() -> dict:
     t = Tuning()
     _check(load().tv_get_tuning(ctypes.byref(t)), "tv_get_tuning")
-    return {"target_lanes": int(t.target_lanes), "min_segment": int(t.min_segment), "halo": int(t.halo)}
+    return {"target_lanes": int(t.target_lanes), "min_segment": int(t.min_segment), "halo": int(t.halo),
+            "ring_slots": int(t.ring_slots)}
 
 
 def set_tuning(target_lanes: Optional[int] = None, min_segment: Optional[int] = None,
-               halo: Optional[int] = None) -> None:
+               halo: Optional[int] = None, ring_slots: Optional[int] = None) -> None:
     """Set the process-wide segmentation of chain-prox launches (None keeps the
     current value).  Results do not depend on it; only speed does."""
     cur = get_tuning()
     t = Tuning(int(target_lanes if target_lanes is not None else cur["target_lanes"]),
                int(min_segment if min_segment is not None else cur["min_segment"]),
-               int(halo if halo is not None else cur["halo"]))
+               int(halo if halo is not None else cur["halo"]),
+               int(ring_slots if ring_slots is not None else cur["ring_slots"]))
     _check(load().tv_set_tuning(ctypes.byref(t)), "tv_set_tuning")
 
 

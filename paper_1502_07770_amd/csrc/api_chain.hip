@@ -9,7 +9,7 @@
 
 namespace tvc {
 
-static const SegTuning kDefaultTuning{int64_t(1) << 17, 128, 128};
+static const SegTuning kDefaultTuning{int64_t(1) << 17, 128, 128, kRingSlots};
 
 SegTuning &seg_tuning() {
     static SegTuning t = kDefaultTuning;
@@ -31,7 +31,7 @@ SegPlan seg_default_plan(int64_t num_chains, int64_t n) {
     if (p.L < kTile) p.L = kTile;
     p.H = round_tile(t.halo);
     p.CK = 16;  // checkpoints at a + 16, 32, 48, 64 (tile multiples)
-    p.K = kRingSlots;
+    p.K = (int)t.ring_slots;
     return p;
 }
 
@@ -330,7 +330,8 @@ tv_status tv_set_tuning(const tv_tuning *t) {
         return TV_OK;
     }
     if (t->target_lanes < 1 || t->min_segment < 1 || t->halo < 0) return TV_ERR_INVALID_ARG;
-    seg_tuning() = SegTuning{t->target_lanes, t->min_segment, t->halo};
+    if (t->ring_slots != 16 && t->ring_slots != 32) return TV_ERR_INVALID_ARG;
+    seg_tuning() = SegTuning{t->target_lanes, t->min_segment, t->halo, t->ring_slots};
     return TV_OK;
 }
 
@@ -339,6 +340,7 @@ tv_status tv_get_tuning(tv_tuning *t) {
     t->target_lanes = seg_tuning().target_lanes;
     t->min_segment = seg_tuning().min_segment;
     t->halo = seg_tuning().halo;
+    t->ring_slots = seg_tuning().ring_slots;
     return TV_OK;
 }
 

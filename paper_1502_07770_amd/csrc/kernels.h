@@ -42,6 +42,7 @@ struct SegTuning {
     int64_t target_lanes;
     int64_t min_segment;
     int64_t halo;
+    int64_t ring_slots;
 };
 SegTuning &seg_tuning();
 // The plan used for a launch of num_chains chains of length <= n: the tuned

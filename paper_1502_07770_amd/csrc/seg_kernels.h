@@ -79,6 +79,8 @@ constexpr int kScanWindow = TVC_SCAN_WINDOW;
 constexpr int kSweepTile = 16;
 // Lanes (each with a 2n + 4 entry HBM deque) for chains that overflow the ring.
 constexpr int64_t kOverflowLanes = 1024;
+// Nodes per register tile of the overflow kernel's forward runs.
+constexpr int kTileOvf = 8;
 constexpr int kSaveHalo = 0, kSaveCk = 1, kSaveEnd = 1 + kCheckpoints, kSaveEnd2 = 2 + kCheckpoints;
 
 template <typename T>
@@ -695,6 +697,24 @@ __global__ __launch_bounds__(64) void k_seg_repair(SegWs<T> ws, typename Prob::P
     bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
 }
 
+// Backward clip of a whole chain from its lambda stream (after a sequential
+// forward pass); marks every segment's tail as done for k_seg_tail.
+template <typename T, class Prob>
+__device__ void full_backward(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c) {
+    const auto sink = Prob::sink(pp, sp);
+    T x = (T)0;
+    for (int64_t i = sp.n - 1; i >= 0; --i) {
+        const LamPair<T> p = ws.lam[i * ws.C + c];
+        const auto sv = sink.load(i);
+        x = (i == sp.n - 1) ? p.lo : clampv(x, p.lo, p.hi);
+        sink.store(i, x, sv);
+    }
+    for (int64_t s = 0; s * ws.L < sp.n; ++s) {
+        const int64_t b = (s + 1) * ws.L < sp.n ? (s + 1) * ws.L : sp.n;
+        ws.seg_unc[s * ws.C + c] = (int)b;
+    }
+}
+
 // Sequential DP + backward of a whole chain with the deque in HBM.
 template <typename T, class Prob>
 __device__ void seg_full_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
@@ -713,18 +733,7 @@ __device__ void seg_full_chain(const SegWs<T> &ws, const typename Prob::Params &
         put_lam<T>(ws.lam, i, ws.C, c, lm, lp);
         wprev = wi;
     }
-    const auto sink = Prob::sink(pp, sp);
-    T x = (T)0;
-    for (int64_t i = sp.n - 1; i >= 0; --i) {
-        const LamPair<T> p = ws.lam[i * ws.C + c];
-        const auto sv = sink.load(i);
-        x = (i == sp.n - 1) ? p.lo : clampv(x, p.lo, p.hi);
-        sink.store(i, x, sv);
-    }
-    for (int64_t s = 0; s * ws.L < sp.n; ++s) {
-        const int64_t b = (s + 1) * ws.L < sp.n ? (s + 1) * ws.L : sp.n;
-        ws.seg_unc[s * ws.C + c] = (int)b;
-    }
+    full_backward<T, Prob>(ws, pp, sp, c);
 }
 
 template <typename T, class Prob, int K, int P>
@@ -815,16 +824,37 @@ __device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, c
 }
 
 // ---------------------------------------------------------------------------
-// Overflowed chains, solved sequentially with the deque in HBM by a bounded
-// pool of lanes (lane l owns deque storage l).
+// Overflowed chains, solved sequentially by a bounded pool of lanes: first with
+// a 64 KiB per-wave LDS ring (64 slots for float, 32 for double), and only if
+// the deque outgrows that too, with the deque in HBM (lane l owns deque
+// storage l).  Both paths compute the same bits as the segmented one.
 // ---------------------------------------------------------------------------
+template <typename T> struct OvfRing {
+    static constexpr int K = sizeof(T) == 4 ? 64 : 32;
+};
+
 template <typename T, class Prob>
 __global__ __launch_bounds__(64) void k_seg_ovf(SegWs<T> ws, typename Prob::Params pp) {
-    const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    constexpr int KB = OvfRing<T>::K;
+    __shared__ Ent<T> s_big[2 * KB * 64];
+    const int lane = threadIdx.x;
+    const int64_t l = (int64_t)blockIdx.x * 64 + lane;
     const int64_t cnt = *ws.ovf_count;
     for (int64_t j = l; j < cnt; j += ws.fb_lanes) {
         const int64_t c = ws.ovf_list[j];
-        seg_full_chain<T, Prob>(ws, pp, Prob::span(pp, c, ws.n), c, l);
+        const ChainSpan sp = Prob::span(pp, c, ws.n);
+        if (sp.n <= 0) continue;
+        const auto src = Prob::src(pp, sp);
+        CRing<T, KB> R;
+        R.init(s_big, lane);
+        bool ok = true;
+        T wprev = (T)0;
+        fwd_run<T, Prob, KB, kTileOvf, true>(R, src, ok, wprev, 0, sp.n, sp.n, ws.lam, ws.C, c,
+                                             [](int64_t) { return false; });
+        if (ok)
+            full_backward<T, Prob>(ws, pp, sp, c);
+        else
+            seg_full_chain<T, Prob>(ws, pp, sp, c, l);
     }
 }
 

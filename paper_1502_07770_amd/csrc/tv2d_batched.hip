@@ -633,8 +633,20 @@ static tv_status batched_autotune_t(const BGeom &g, const int64_t *H, const int6
     batched_layout<T>(workspace, g, &ws);
     tv_status s = batched_setup<T>(g, H, W, pix, lam, f, ws, st);
     if (s != TV_OK) return s;
-    const IterSched sc0 = make_sched(tau0, 0);
-    if (hipMemcpyAsync(ws.sched, &sc0, sizeof(sc0), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
+    // a few iterations first, so the plans are timed on deques as deep as the
+    // solve's later iterations build (no image converges: tolerance 0)
+    IterSched sc[kTuneWarm + 1];
+    double tau = tau0;
+    for (int j = 0; j <= kTuneWarm; ++j) {
+        sc[j] = make_sched(tau, j);
+        tau *= sc[j].theta;
+    }
+    if (hipMemcpyAsync(ws.sched, sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
+    if (batched_iters<T>(g, ws, f, 0, kTuneWarm, 0.0, seg_plan(g.ncols, g.maxH, kPlanBatchCol),
+                         seg_plan(g.nrows, g.maxW, kPlanBatchRow), st) != hipSuccess)
+        return TV_ERR_HIP;
+    if (hipMemcpyAsync(ws.sched, &sc[kTuneWarm], sizeof(IterSched), hipMemcpyHostToDevice, st) != hipSuccess)
+        return TV_ERR_HIP;
     SegPlan pc, pr;
     s = tune_launch<T>(
         g.ncols, g.maxH, ws.seg_bytes,

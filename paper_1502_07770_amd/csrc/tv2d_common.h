@@ -29,6 +29,9 @@ struct IterSched {
 };
 // Iterations whose schedule one upload holds (and the longest captured chunk).
 constexpr int kSchedCap = 64;
+// Iterations the autotuners run before timing candidate plans (even, so the
+// state is back in the buffers of parity 0).
+constexpr int kTuneWarm = 8;
 
 __host__ __forceinline__ IterSched make_sched(double tau, int64_t k) {
     IterSched s;

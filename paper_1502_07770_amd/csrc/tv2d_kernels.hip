@@ -552,8 +552,22 @@ static tv_status tv2d_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld, d
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
     hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
-    const IterSched sc0 = make_sched(tau0, 0);
-    if (hipMemcpyAsync(ws.sched, &sc0, sizeof(sc0), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
+    // Run a few iterations first: the deques of the column and row chains
+    // deepen as the dual variable builds up, and a plan timed on the first
+    // iteration's data alone would pick a ring that overflows later on.
+    IterSched sc[kTuneWarm + 1];
+    double tau = tau0;
+    for (int j = 0; j <= kTuneWarm; ++j) {
+        sc[j] = make_sched(tau, j);
+        tau *= sc[j].theta;
+    }
+    if (hipMemcpyAsync(ws.sched, sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
+    if (tv2d_iters<T>(ws, f, ld, H, W, lam, 0, kTuneWarm, false, nullptr, seg_plan(W, H, kPlan2dCol),
+                      seg_plan(H, W, kPlan2dRow), st) != hipSuccess)
+        return TV_ERR_HIP;
+    // the timed steps read iteration kTuneWarm's scalars from the first slot
+    if (hipMemcpyAsync(ws.sched, &sc[kTuneWarm], sizeof(IterSched), hipMemcpyHostToDevice, st) != hipSuccess)
+        return TV_ERR_HIP;
     SegPlan pc, pr;
     tv_status s = tune_launch<T>(
         W, H, ws.seg_bytes, [&](const SegPlan &p) { return tv2d_col_step<T>(ws, H, W, lam, 0, ws.sched, p, st); },

@@ -49,9 +49,11 @@ def test_status_strings(lib):
 def test_tuning_round_trip_and_rejections(lib):
     saved = binding.get_tuning()
     try:
-        binding.set_tuning(target_lanes=4096, min_segment=32, halo=40)
-        assert binding.get_tuning() == {"target_lanes": 4096, "min_segment": 32, "halo": 40}
-        bad = binding.Tuning(0, 1, 0)
+        binding.set_tuning(target_lanes=4096, min_segment=32, halo=40, ring_slots=32)
+        assert binding.get_tuning() == {"target_lanes": 4096, "min_segment": 32, "halo": 40, "ring_slots": 32}
+        bad = binding.Tuning(0, 1, 0, 16)
+        assert lib.tv_set_tuning(ctypes.byref(bad)) == binding.TV_ERR_INVALID_ARG
+        bad = binding.Tuning(4096, 1, 0, 24)
         assert lib.tv_set_tuning(ctypes.byref(bad)) == binding.TV_ERR_INVALID_ARG
         assert lib.tv_get_tuning(None) == binding.TV_ERR_INVALID_ARG
     finally:

@@ -107,6 +107,32 @@ def test_deep_deque_takes_exact_fallback(dtype):
     assert err.max() <= TOL[dtype], err.max()
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_overflow_tiers_match_the_ring_path(tuning, dtype):
+    """Deques of depth 17..112: with a 16-slot ring they overflow into the
+    large-ring sequential pass (up to 64 slots for float, 32 for double) or,
+    deeper still, into the HBM deque; with a 32-slot ring the shallower ones
+    stay on the segmented path.  Every route gives the same bits."""
+    n = 1024
+    rows, ws = [], []
+    for k, wv in enumerate((1.0, 3.0, 5.0, 10.0, 50.0)):
+        for j in range(3):
+            rows.append(np.sqrt(np.arange(n) + 7 * k + j))
+            ws.append(wv)
+    y = np.array(rows)
+    w = np.repeat(np.array(ws)[:, None], n, axis=1)
+    _, st = oracle.chain_prox(y, w=w, counts=True)
+    assert st[:, 2].min() > 16 and st[:, 2].max() > 64
+    tuning(target_lanes=1 << 30, min_segment=128, ring_slots=16)
+    a = _solve(y, w, dtype)
+    tuning(target_lanes=1 << 30, min_segment=128, ring_slots=32)
+    b = _solve(y, w, dtype)
+    assert np.array_equal(a, b)
+    yv = _dev(y, dtype).cpu().double().numpy()
+    wv = _dev(w, dtype).cpu().double().numpy()
+    _check_rows(yv, a.astype(np.float64), oracle.chain_prox(yv, w=wv), TOL[dtype])
+
+
 def test_in_place_and_strided_dims():
     y = synth.piecewise_constant(8, 4, seed=7).reshape(2, 4, 4)
     t = _dev(y, torch.float64)
