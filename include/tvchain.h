@@ -130,8 +130,50 @@ tv_status tv_chain_prox_autotune(int num_batches, const tv_chain_layout *layouts
                                  const void *const *y, const void *const *w, const double *w_scalar,
                                  void *const *x, void *workspace, size_t workspace_bytes, hipStream_t stream,
                                  tv_tuning_result *chosen);
-/* Forget every plan chosen by the autotuners (chain prox and 2D solvers). */
+/* Forget every plan chosen by the autotuners (chain prox, chain DP and 2D
+ * solvers). */
 void tv_autotune_clear(void);
+
+/* ---- General quadratic unaries and asymmetric weights (Sec. 4.1 in full) ----
+ * The chain problem of Sec. 4.1 with strictly convex quadratic unaries and
+ * piecewise-linear pairwise terms (the setting of Sec. 4, first paragraph):
+ *
+ *     x = argmin_x  sum_i ( a_i x_i^2 / 2 - b_i x_i )  +  sum_e f_e(x_{e+1} - x_e),
+ *     f_e(z) = wm_e z  for z < 0,   f_e(z) = wp_e z  for z >= 0,
+ *
+ * with a_i > 0 and wm_e <= wp_e (f_e convex).  wm = -w, wp = w, a = 1, b = y is
+ * eq. (1D-ROF); a_i = c_i, b_i = c_i y_i is a prox with per-node data weights.
+ * The DP runs with real-valued slopes Abar_s - Abar_k (Abar = running sum of a,
+ * formed once per node in FP64 by a prefix pass): slopes are no longer exact
+ * integers, and each is rounded once to the working precision.
+ *  layout : as for tv_chain_prox (uniform or CSR offsets); lengths below 2^24
+ *           (TV_F32) or 2^31 (TV_F64).
+ *  a      : per-node a_i > 0 in the layout, or NULL for a_i = 1.  Values are not
+ *           checked: a_i <= 0, or a_i too small to change the FP64 running sum,
+ *           gives unspecified (possibly non-finite) output, never an invalid
+ *           memory access.
+ *  b      : per-node b_i.
+ *  wm, wp : per-edge wm_e <= wp_e in the layout (slot of node i = edge (i, i+1);
+ *           each chain's last slot is never read).  wm_e > wp_e gives
+ *           unspecified output.
+ *  x      : output in the layout; must not overlap a, b, wm or wp (rejected with
+ *           TV_ERR_INVALID_ARG where the host can see it, as in tv_chain_prox).
+ * Workspace holds the FP64 prefix sums (8 bytes per node), the lambda stream and
+ * the saved deques; chains whose deque outgrows the on-chip ring are redone
+ * exactly with their deque in the workspace.  The segmented solve is
+ * bit-identical to a sequential one, for every plan. */
+size_t tv_chain_dp_workspace(const tv_chain_layout *layout, tv_dtype dtype);
+tv_status tv_chain_dp(const tv_chain_layout *layout, tv_dtype dtype, const void *a, const void *b,
+                      const void *wm, const void *wp, void *x,
+                      void *workspace, size_t workspace_bytes, hipStream_t stream);
+/* Autotuner of tv_chain_dp launches, as tv_chain_prox_autotune: times every
+ * candidate plan that fits the workspace on this data, keeps the fastest for
+ * later tv_chain_dp calls of the same shape in this process; x receives the
+ * solution.  Synchronous. */
+tv_status tv_chain_dp_autotune(const tv_chain_layout *layout, tv_dtype dtype, const void *a, const void *b,
+                               const void *wm, const void *wp, void *x,
+                               void *workspace, size_t workspace_bytes, hipStream_t stream,
+                               tv_tuning_result *chosen);
 
 /* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
 size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);

@@ -93,6 +93,9 @@ _SIG = {
     "tv_chain_prox_autotune": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                               _P, _P]),
     "tv_autotune_clear": (None, []),
+    "tv_chain_dp_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
+    "tv_chain_dp": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "tv_chain_dp_autotune": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
     "tv2d_autotune": (ctypes.c_int, [ctypes.c_int, _P, _I64, _I64, _I64, ctypes.c_double, ctypes.c_double, _P,
                                      ctypes.c_size_t, _P, _P, _P]),
     "tv2d_batched_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_double, _P,
@@ -253,6 +256,53 @@ def chain_prox(y: torch.Tensor, w: Union[float, torch.Tensor] = 0.0, dim: int = 
         out.copy_(res)
         return out
     return res
+
+
+def chain_dp(b: torch.Tensor, wm: torch.Tensor, wp: torch.Tensor, a: Optional[torch.Tensor] = None,
+             dim: int = -1, out: Optional[torch.Tensor] = None, autotune: bool = False):
+    """Sec. 4.1 chain DP with general quadratic unaries and asymmetric weights
+    (tv_chain_dp): per chain along ``dim``, the minimiser of
+    sum_i a_i x_i^2 / 2 - b_i x_i + sum_e f_e(x_{e+1} - x_e) with
+    f_e(z) = wm_e z (z < 0), wp_e z (z >= 0).  ``wm``, ``wp`` (and ``a``, None
+    meaning all ones) are shaped like ``b``; entry i along ``dim`` belongs to
+    edge (i, i+1).  With ``autotune`` the call times the candidate plans and
+    returns (x, chosen plan)."""
+    _require_gpu(b, wm, wp, *([a] if a is not None else []))
+    lib = load()
+    for t in (wm, wp) + ((a,) if a is not None else ()):
+        if t.shape != b.shape or t.dtype != b.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "a, wm and wp must match b's shape and dtype")
+    if b.numel() == 0:
+        x = torch.empty_like(b) if out is None else out
+        return (x, None) if autotune else x
+    ts = [b, wm, wp] + ([a] if a is not None else [])
+    if any(t.stride() != b.stride() for t in ts):
+        ts = [t.contiguous() for t in ts]
+    views = [_chain_view(t, dim) for t in ts]
+    bv, lay, restore = views[0]
+    wmv, wpv = views[1][0], views[2][0]
+    av = views[3][0] if a is not None else None
+    xv = torch.empty_like(bv)
+    code = _dtype_code(b)
+    nbytes = lib.tv_chain_dp_workspace(ctypes.byref(lay), code)
+    ws = _workspace(nbytes, b.device)
+    stream = ctypes.c_void_p(_stream_ptr(b.device))
+    chosen = None
+    if autotune:
+        res = TuningResult()
+        st = lib.tv_chain_dp_autotune(ctypes.byref(lay), code, _ptr(av), _ptr(bv), _ptr(wmv), _ptr(wpv),
+                                      _ptr(xv), _ptr(ws), nbytes, stream, ctypes.byref(res))
+        _check(st, "tv_chain_dp_autotune")
+        chosen = res.as_dict()
+    else:
+        st = lib.tv_chain_dp(ctypes.byref(lay), code, _ptr(av), _ptr(bv), _ptr(wmv), _ptr(wpv), _ptr(xv),
+                             _ptr(ws), nbytes, stream)
+        _check(st, "tv_chain_dp")
+    res_x = restore(xv)
+    if out is not None:
+        out.copy_(res_x)
+        res_x = out
+    return (res_x, chosen) if autotune else res_x
 
 
 MAX_CHAIN_BATCHES = 8

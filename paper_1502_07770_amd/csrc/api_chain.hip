@@ -6,6 +6,7 @@
 
 #include "../../include/tvchain.h"
 #include "kernels.h"
+#include "tv2d_common.h"
 
 namespace tvc {
 
@@ -212,6 +213,95 @@ tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const voi
         e = launch_chain_prox<double>(b, (const double *)y, (const double *)w, w_scalar, (double *)x,
                                       workspace, plan, stream);
     return e == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+// ---- general unaries and asymmetric weights ----
+
+static size_t dp_ws_bytes(const tv_chain_layout *L, tv_dtype dt) {
+    const int64_t C = L->num_chains, n = L->length;
+    return dt == TV_F32 ? chain_dp_ws_bytes<float>(C, n, seg_bytes_max<float, double>(C, n, kPlanDp))
+                        : chain_dp_ws_bytes<double>(C, n, seg_bytes_max<double, double>(C, n, kPlanDp));
+}
+
+static size_t dp_ws_bytes_plan(const tv_chain_layout *L, tv_dtype dt, const SegPlan &p) {
+    const int64_t C = L->num_chains, n = L->length;
+    return dt == TV_F32 ? chain_dp_ws_bytes<float>(C, n, seg_ws_bytes_plan<float, double>(C, n, p))
+                        : chain_dp_ws_bytes<double>(C, n, seg_ws_bytes_plan<double, double>(C, n, p));
+}
+
+static tv_status dp_args(const tv_chain_layout *L, tv_dtype dt, const void *a, const void *b, const void *wm,
+                         const void *wp, void *x) {
+    if (!layout_ok(L, dt)) return TV_ERR_INVALID_ARG;
+    if (L->num_chains == 0) return TV_OK;
+    if (!b || !wm || !wp || !x) return TV_ERR_INVALID_ARG;
+    if (overlaps(L, x, L, a, dt) || overlaps(L, x, L, b, dt) || overlaps(L, x, L, wm, dt) ||
+        overlaps(L, x, L, wp, dt))
+        return TV_ERR_INVALID_ARG;
+    return TV_OK;
+}
+
+static hipError_t dp_launch(const tv_chain_layout *L, tv_dtype dt, const void *a, const void *b, const void *wm,
+                            const void *wp, void *x, void *ws, const SegPlan &plan, hipStream_t st) {
+    const ChainBatch bt = to_batch(L);
+    if (dt == TV_F32)
+        return launch_chain_dp<float>(bt, (const float *)a, (const float *)b, (const float *)wm, (const float *)wp,
+                                      (float *)x, ws, plan, st);
+    return launch_chain_dp<double>(bt, (const double *)a, (const double *)b, (const double *)wm,
+                                   (const double *)wp, (double *)x, ws, plan, st);
+}
+
+size_t tv_chain_dp_workspace(const tv_chain_layout *layout, tv_dtype dtype) {
+    if (!layout_ok(layout, dtype) || layout->num_chains == 0) return 0;
+    return dp_ws_bytes(layout, dtype);
+}
+
+tv_status tv_chain_dp(const tv_chain_layout *layout, tv_dtype dtype, const void *a, const void *b, const void *wm,
+                      const void *wp, void *x, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    tv_status st = dp_args(layout, dtype, a, b, wm, wp, x);
+    if (st != TV_OK || layout->num_chains == 0) return st;
+    const SegPlan plan = seg_plan(layout->num_chains, layout->length, kPlanDp);
+    if (!workspace || workspace_bytes < dp_ws_bytes_plan(layout, dtype, plan)) return TV_ERR_WORKSPACE;
+    st = device_check();
+    if (st != TV_OK) return st;
+    return dp_launch(layout, dtype, a, b, wm, wp, x, workspace, plan, stream) == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+tv_status tv_chain_dp_autotune(const tv_chain_layout *layout, tv_dtype dtype, const void *a, const void *b,
+                               const void *wm, const void *wp, void *x, void *workspace, size_t workspace_bytes,
+                               hipStream_t stream, tv_tuning_result *chosen) {
+    tv_status st = dp_args(layout, dtype, a, b, wm, wp, x);
+    if (st != TV_OK || layout->num_chains == 0) return st;
+    if (!workspace) return TV_ERR_WORKSPACE;
+    st = device_check();
+    if (st != TV_OK) return st;
+    const int64_t C = layout->num_chains, n = layout->length;
+    SegPlan cand[64];
+    const int m = dtype == TV_F32 ? seg_candidates<float, double>(C, n, cand, 64)
+                                  : seg_candidates<double, double>(C, n, cand, 64);
+    int best = -1, tried = 0;
+    float best_ms = 0.0f;
+    for (int j = 0; j < m; ++j) {
+        if (dp_ws_bytes_plan(layout, dtype, cand[j]) > workspace_bytes) continue;
+        float ms = 0.0f;
+        if (time_calls([&]() { return dp_launch(layout, dtype, a, b, wm, wp, x, workspace, cand[j], stream); },
+                       stream, 3, &ms) != hipSuccess)
+            return TV_ERR_HIP;
+        ++tried;
+        if (best < 0 || ms < best_ms) {
+            best = j;
+            best_ms = ms;
+        }
+    }
+    if (best < 0) return TV_ERR_WORKSPACE;
+    seg_set_tuned(kPlanDp, C, n, cand[best]);
+    if (chosen) {
+        chosen->segment_length = cand[best].L;
+        chosen->halo = cand[best].H;
+        chosen->ring_slots = cand[best].K;
+        chosen->candidates = tried;
+        chosen->ms = best_ms;
+    }
+    return TV_OK;
 }
 
 static_assert(kMaxChainBatches == TV_MAX_CHAIN_BATCHES, "batch limit of the ABI");

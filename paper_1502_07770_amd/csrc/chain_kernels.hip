@@ -13,6 +13,8 @@ namespace tvc {
 // ---------------------------------------------------------------------------
 template <typename T, bool EDGE_W>
 struct PlainProb {
+    using Tag = T;  // a_i = 1: integer tags in the working precision
+    static constexpr bool kGen = false;
     struct Params {
         const T *y;
         const T *w;
@@ -104,6 +106,8 @@ constexpr int kMaxBatches = kMaxChainBatches;
 
 template <typename T, bool EDGE_W>
 struct MultiProb {
+    using Tag = T;  // a_i = 1: integer tags in the working precision
+    static constexpr bool kGen = false;
     using Base = PlainProb<T, EDGE_W>;
     struct Params {
         int nb;
@@ -572,10 +576,10 @@ size_t chain_prox_ws_bytes(const ChainBatch &b, const SegPlan &plan) {
 // the saved deques), keeping only plans whose workspace stays within twice the
 // default plan's (or the default's plus 64 MiB).  Segment lengths at or above
 // the chain length are all the same plan; only the shortest is kept.
-template <typename T>
+template <typename T, typename G>
 int seg_candidates(int64_t C, int64_t n, SegPlan *out, int max_out) {
     const SegPlan d = seg_default_plan(C, n);
-    const size_t base = seg_ws_bytes<T>(C, n, d);
+    const size_t base = seg_ws_bytes<T, G>(C, n, d);
     const size_t cap = (2 * base > base + (size_t(64) << 20)) ? 2 * base : base + (size_t(64) << 20);
     int m = 0;
     if (m < max_out) out[m++] = d;
@@ -587,7 +591,7 @@ int seg_candidates(int64_t C, int64_t n, SegPlan *out, int max_out) {
             if (K * 4 > Lr && K > 16) continue;
             for (int64_t H = 64; H <= 128; H *= 2) {
                 const SegPlan p{Lr, H, 16, K};
-                if (seg_ws_bytes<T>(C, n, p) > cap) continue;
+                if (seg_ws_bytes<T, G>(C, n, p) > cap) continue;
                 bool dup = false;
                 for (int j = 0; j < m; ++j)
                     dup = dup || (out[j].L == p.L && out[j].H == p.H && out[j].K == p.K);
@@ -598,30 +602,33 @@ int seg_candidates(int64_t C, int64_t n, SegPlan *out, int max_out) {
     return m;
 }
 
-template <typename T>
+template <typename T, typename G>
 size_t seg_bytes_max(int64_t C, int64_t n, int kind) {
     SegPlan c[64];
-    const int m = seg_candidates<T>(C, n, c, 64);
+    const int m = seg_candidates<T, G>(C, n, c, 64);
     size_t mx = 0;
     for (int j = 0; j < m; ++j) {
-        const size_t b = seg_ws_bytes<T>(C, n, c[j]);
+        const size_t b = seg_ws_bytes<T, G>(C, n, c[j]);
         mx = b > mx ? b : mx;
     }
     // a plan tuned for this shape earlier (or set by hand) must fit too
-    const size_t t = seg_ws_bytes<T>(C, n, seg_plan(C, n, kind));
+    const size_t t = seg_ws_bytes<T, G>(C, n, seg_plan(C, n, kind));
     return t > mx ? t : mx;
 }
 
-template <typename T>
+template <typename T, typename G>
 size_t seg_ws_bytes_plan(int64_t C, int64_t n, const SegPlan &plan) {
-    return seg_ws_bytes<T>(C, n, plan);
+    return seg_ws_bytes<T, G>(C, n, plan);
 }
-template size_t seg_ws_bytes_plan<float>(int64_t, int64_t, const SegPlan &);
-template size_t seg_ws_bytes_plan<double>(int64_t, int64_t, const SegPlan &);
-template int seg_candidates<float>(int64_t, int64_t, SegPlan *, int);
-template int seg_candidates<double>(int64_t, int64_t, SegPlan *, int);
-template size_t seg_bytes_max<float>(int64_t, int64_t, int);
-template size_t seg_bytes_max<double>(int64_t, int64_t, int);
+template size_t seg_ws_bytes_plan<float, float>(int64_t, int64_t, const SegPlan &);
+template size_t seg_ws_bytes_plan<double, double>(int64_t, int64_t, const SegPlan &);
+template size_t seg_ws_bytes_plan<float, double>(int64_t, int64_t, const SegPlan &);
+template int seg_candidates<float, float>(int64_t, int64_t, SegPlan *, int);
+template int seg_candidates<double, double>(int64_t, int64_t, SegPlan *, int);
+template int seg_candidates<float, double>(int64_t, int64_t, SegPlan *, int);
+template size_t seg_bytes_max<float, float>(int64_t, int64_t, int);
+template size_t seg_bytes_max<double, double>(int64_t, int64_t, int);
+template size_t seg_bytes_max<float, double>(int64_t, int64_t, int);
 
 template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,

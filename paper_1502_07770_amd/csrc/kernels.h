@@ -35,7 +35,15 @@ struct SegPlan {
 
 // Which launch a plan is for: the best segmentation depends on the problem's
 // data source, so tuned plans are cached per kind and shape.
-enum PlanKind { kPlanChain = 0, kPlan2dCol = 1, kPlan2dRow = 2, kPlanBatchCol = 3, kPlanBatchRow = 4, kPlanKinds = 5 };
+enum PlanKind {
+    kPlanChain = 0,
+    kPlan2dCol = 1,
+    kPlan2dRow = 2,
+    kPlanBatchCol = 3,
+    kPlanBatchRow = 4,
+    kPlanDp = 5,
+    kPlanKinds = 6
+};
 
 // Process-wide tuning: target lanes per launch, shortest segment, halo.
 struct SegTuning {
@@ -54,15 +62,16 @@ void seg_set_tuned(int kind, int64_t num_chains, int64_t n, const SegPlan &p);
 void seg_clear_tuned();
 // Candidate plans for the autotuner (the default plan first); every workspace
 // query reserves room for the largest of them, so a tuned plan always fits.
-template <typename T>
+// G is the tag type of the deque entries (T when a_i = 1, FP64 otherwise).
+template <typename T, typename G = T>
 int seg_candidates(int64_t num_chains, int64_t n, SegPlan *out, int max_out);
-template <typename T>
+template <typename T, typename G = T>
 size_t seg_bytes_max(int64_t num_chains, int64_t n, int kind);
 
 template <typename T>
 size_t chain_prox_ws_bytes(const ChainBatch &b, const SegPlan &plan);
 // Workspace bytes of one launch of num_chains chains of length <= n under plan.
-template <typename T>
+template <typename T, typename G = T>
 size_t seg_ws_bytes_plan(int64_t num_chains, int64_t n, const SegPlan &plan);
 
 template <typename T>
@@ -75,6 +84,14 @@ template <typename T>
 hipError_t launch_chain_prox_multi(int nb, const ChainBatch *bs, const T *const *y, const T *const *w,
                                    const double *w_scalar, T *const *x, void *workspace, const SegPlan &plan,
                                    hipStream_t stream);
+
+// General unaries and asymmetric weights (see tv_chain_dp): workspace bytes
+// with seg_bytes for the segmented kernels, and the launch.
+template <typename T>
+size_t chain_dp_ws_bytes(int64_t num_chains, int64_t n, size_t seg_bytes);
+template <typename T>
+hipError_t launch_chain_dp(const ChainBatch &b, const T *a, const T *bv, const T *wm, const T *wp, T *x,
+                           void *workspace, const SegPlan &plan, hipStream_t stream);
 
 template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,

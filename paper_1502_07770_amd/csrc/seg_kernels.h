@@ -50,17 +50,18 @@ struct alignas(2 * sizeof(T)) LamPair {
     T lo, hi;
 };
 
-// A deque entry: breakpoint lambda and the birth step k of the segment to its
-// right, kept as a floating-point integer (exact below 2^24 for float) so the
-// slope s - k is one exact subtraction.
-template <typename T>
-struct alignas(2 * sizeof(T)) Ent {
+// A deque entry: breakpoint lambda and the tag k of the segment to its right.
+// With a_i = 1 the tag is the birth step, kept as a floating-point integer in
+// the working precision (exact below 2^24 for float) so the slope s - k is one
+// exact subtraction; with general a_i it is the FP64 prefix sum Abar_k.
+template <typename T, typename G = T>
+struct alignas(2 * sizeof(G)) Ent {
     T l;
-    T k;
+    G k;
 };
 
-template <typename T> __device__ __forceinline__ Ent<T> mk_ent(T l, T k) {
-    Ent<T> e;
+template <typename T, typename G> __device__ __forceinline__ Ent<T, G> mk_ent(T l, G k) {
+    Ent<T, G> e;
     e.l = l;
     e.k = k;
     return e;
@@ -83,7 +84,7 @@ constexpr int64_t kOverflowLanes = 1024;
 constexpr int kTileOvf = 8;
 constexpr int kSaveHalo = 0, kSaveCk = 1, kSaveEnd = 1 + kCheckpoints, kSaveEnd2 = 2 + kCheckpoints;
 
-template <typename T>
+template <typename T, typename G = T>
 struct SegWs {
     int64_t C;          // chains
     int64_t n;          // maximum chain length
@@ -92,7 +93,7 @@ struct SegWs {
     int64_t H;          // halo
     int64_t CK;         // checkpoint spacing
     LamPair<T> *lam;    // [n][C]
-    Ent<T> *st;         // saved deques [S][kSaves][K][C] (ES2: the repair's end state)
+    Ent<T, G> *st;      // saved deques [S][kSaves][K][C] (ES2: the repair's end state)
     int *st_size;       // [S][kSaves][C]
     uint32_t *st_hash;  // [S][kSaves][C]
     uint8_t *ovf;       // [C][S] ring overflow
@@ -106,7 +107,7 @@ struct SegWs {
     int *ovf_count;     // chains appended to ovf_list (zeroed by k_seg_main)
     int *ovf_list;      // [C] chains whose deque outgrew the LDS ring
     T *fb_lam;          // [fb_lanes][2n+4] HBM deques of the overflow kernel
-    int *fb_tag;
+    G *fb_tag;
     int64_t fb_cap;
     int64_t fb_lanes;
 };
@@ -130,12 +131,12 @@ __device__ __forceinline__ uint32_t bits32(double v) {
     return (uint32_t)b ^ (uint32_t)(b >> 32) * 0x9E3779B1u;
 }
 
-template <typename T, int K> struct CRing;
+template <typename T, int K, typename G = T> struct CRing;
 
 // Entry-by-entry comparison of a ring with a saved state of the same size,
 // loading the saved entries in independent batches of eight.
-template <typename T, int K>
-__device__ __forceinline__ bool saved_equal(const CRing<T, K> &R, const Ent<T> *src, int64_t stride);
+template <typename T, int K, typename G>
+__device__ __forceinline__ bool saved_equal(const CRing<T, K, G> &R, const Ent<T, G> *src, int64_t stride);
 
 // ---------------------------------------------------------------------------
 // LDS ring of K entries per lane with register-cached ends.  Every entry is
@@ -145,41 +146,42 @@ __device__ __forceinline__ bool saved_equal(const CRing<T, K> &R, const Ent<T> *
 // lane-interleaved (slot m of lane l at m * 64 + l), so the 64 lanes of a
 // wave hit distinct banks.
 // ---------------------------------------------------------------------------
-template <typename T, int K>
+template <typename T, int K, typename G>
 struct CRing {
     static_assert((K & (K - 1)) == 0, "ring size must be a power of two");
-    Ent<T> *col;  // this lane's column: slot m at col[m * 64], its copy at col[(m + K) * 64]
+    using E = Ent<T, G>;
+    E *col;  // this lane's column: slot m at col[m * 64], its copy at col[(m + K) * 64]
     int head, size;
-    Ent<T> f, b;  // front / back copies (valid when size >= 1)
+    E f, b;  // front / back copies (valid when size >= 1)
 
-    __device__ __forceinline__ void init(Ent<T> *base, int lane) {
+    __device__ __forceinline__ void init(E *base, int lane) {
         col = base + lane;
         head = 0;
         size = 0;
     }
-    __device__ __forceinline__ Ent<T> ld(int j) const { return col[((head + j) & (K - 1)) * 64]; }
-    __device__ __forceinline__ void put_slot(int m, const Ent<T> &e) const {
+    __device__ __forceinline__ E ld(int j) const { return col[((head + j) & (K - 1)) * 64]; }
+    __device__ __forceinline__ void put_slot(int m, const E &e) const {
         col[m * 64] = e;
         col[(m + K) * 64] = e;
     }
-    __device__ __forceinline__ void set(int j, const Ent<T> &e) const { put_slot((head + j) & (K - 1), e); }
+    __device__ __forceinline__ void set(int j, const E &e) const { put_slot((head + j) & (K - 1), e); }
     // Order-sensitive 32-bit hash of the breakpoints and tags (the back tag is
     // excluded); a filter only: equality is always confirmed entry by entry.
     __device__ __forceinline__ uint32_t hash() const {
         uint32_t h = 0x811C9DC5u ^ (uint32_t)size;
         for (int j = 0; j < size; ++j) {
-            const Ent<T> e = ld(j);
+            const E e = ld(j);
             h = (h ^ bits32(e.l)) * 0x01000193u;
             if (j + 1 < size) h = (h ^ bits32(e.k)) * 0x01000193u;
         }
         return h;
     }
-    __device__ __forceinline__ void save(Ent<T> *dst, int *szdst, uint32_t *hdst, int64_t stride) const {
+    __device__ __forceinline__ void save(E *dst, int *szdst, uint32_t *hdst, int64_t stride) const {
         *szdst = size;
         *hdst = hash();
         for (int j = 0; j < size; ++j) dst[j * stride] = ld(j);
     }
-    __device__ __forceinline__ void load(const Ent<T> *src, const int *szsrc, int64_t stride) {
+    __device__ __forceinline__ void load(const E *src, const int *szsrc, int64_t stride) {
         head = 0;
         size = clamp_size<K>(*szsrc);
         for (int j = 0; j < size; ++j) put_slot(j, src[j * stride]);
@@ -191,26 +193,26 @@ struct CRing {
     // Same breakpoints and tags (the back entry's tag is never read).  Size
     // and hash reject most unequal states with two loads; the exact check
     // loads the saved entries eight at a time.
-    __device__ __forceinline__ bool equals(const Ent<T> *src, const int *szsrc, const uint32_t *hsrc,
+    __device__ __forceinline__ bool equals(const E *src, const int *szsrc, const uint32_t *hsrc,
                                            int64_t stride) const {
         if (*szsrc != size || *hsrc != hash()) return false;
-        return saved_equal<T, K>(*this, src, stride);
+        return saved_equal<T, K, G>(*this, src, stride);
     }
 };
 
-template <typename T, int K>
-__device__ __forceinline__ bool saved_equal(const CRing<T, K> &R, const Ent<T> *src, int64_t stride) {
+template <typename T, int K, typename G>
+__device__ __forceinline__ bool saved_equal(const CRing<T, K, G> &R, const Ent<T, G> *src, int64_t stride) {
     const int n = R.size;
     bool eq = true;
     for (int j0 = 0; j0 < n && eq; j0 += 8) {
-        Ent<T> e[8];
+        Ent<T, G> e[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) e[j] = src[(j0 + j < n ? j0 + j : n - 1) * stride];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int jj = j0 + j;
             if (jj < n) {
-                const Ent<T> m = R.ld(jj);
+                const Ent<T, G> m = R.ld(jj);
                 eq = eq && (e[j].l == m.l) && (jj + 1 == n || e[j].k == m.k);
             }
         }
@@ -218,27 +220,33 @@ __device__ __forceinline__ bool saved_equal(const CRing<T, K> &R, const Ent<T> *
     return eq;
 }
 
-// One DP step (Sec. 4.1 with a_i = 1) on a CRing, branch-free except for the
-// rare long scans.  s = i + 1 is the number of unaries added so far, so the
-// true slope of a segment with birth tag k is s - k; the segments beyond
-// either end have slope 1.  The message values at the first W and the last W
+// One DP step (Sec. 4.1) on a CRing, branch-free except for the rare long
+// scans.  With a_i = 1 (kGen false) sf = s = i + 1 is the number of unaries
+// added so far and the true slope of a segment with birth tag k is s - k; in
+// general it is Abar_s - Abar_k, and the segments beyond either end have slope
+// a_s (1 when a_i = 1).  The message values at the first W and the last W
 // breakpoints are formed up front; the pop count of each end is the number of
 // leading values beyond the threshold (non-decreasing, also in floating
 // point), and the bracketing segment is picked with selects.  An end needing
 // more than W pops falls back to a loop.  An empty deque (the first node of a
 // run) is handled by selects on the same path; its LDS reads are in bounds and
-// their values unused.  The root step is the same step with w = 0 (its deque
-// update is never used).  Returns false if the deque would outgrow the ring;
-// the ring then keeps running on clamped sizes and the caller discards it.
-template <typename T, int K, int W>
-__device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, T sf, T yi, T wprev, T w, T &lm, T &lp) {
+// their values unused.  The root step is the same step with a zero leaving
+// edge (its deque update is never used).  Returns false if the deque would
+// outgrow the ring; the ring then keeps running on clamped sizes and the
+// caller discards it.
+template <typename T, typename G, int K, int W, bool kGen>
+__device__ __forceinline__ bool dp_step_win(CRing<T, K, G> &R, const StepIn<T, G> &in, T &lm, T &lp) {
     static_assert(W >= 2 && W <= K, "scan window");
-    const T lo = -w, hi = w;
+    using E = Ent<T, G>;
+    const T lo = in.lo, hi = in.hi, yi = in.yi;
+    const G sf = in.sf;
+    const EndSlope<T, G, kGen> es(sf, in.sprev);
+    const G tend = kGen ? in.sprev : (G)(sf - (G)1);  // tag of a segment that was a flat end
     const int t = R.size;
     const int h = R.head;
-    const Ent<T> *fp = R.col + h * 64;                          // logical 0 .. W-1
-    const Ent<T> *bp = R.col + ((h + t - W) & (K - 1)) * 64;    // logical t-W .. t-1
-    Ent<T> F[W], B[W];
+    const E *fp = R.col + h * 64;                          // logical 0 .. W-1
+    const E *bp = R.col + ((h + t - W) & (K - 1)) * 64;    // logical t-W .. t-1
+    E F[W], B[W];
     F[0] = R.f;
     B[0] = R.b;
 #pragma unroll
@@ -248,9 +256,9 @@ __device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, T sf, T yi, T wprev,
     }
     // ---- left end: pops p = #{j < t : v_j < lo}, v_0 = message at lam_1 ----
     T v[W];
-    v[0] = F[0].l - wprev - yi;
+    v[0] = es.mul(F[0].l) + in.lop - yi;
 #pragma unroll
-    for (int j = 1; j < W; ++j) v[j] = v[j - 1] + (sf - F[j - 1].k) * (F[j].l - F[j - 1].l);
+    for (int j = 1; j < W; ++j) v[j] = v[j - 1] + slope_of<T, G>(sf, F[j - 1].k) * (F[j].l - F[j - 1].l);
     int p = 0;
     T vc = v[0];
 #pragma unroll
@@ -260,11 +268,12 @@ __device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, T sf, T yi, T wprev,
         vc = c ? v[j] : vc;
     }
     if (p == W && t > W) {  // rare: keep popping one breakpoint at a time
-        T cl = F[W - 1].l, ck = F[W - 1].k;
+        T cl = F[W - 1].l;
+        G ck = F[W - 1].k;
         for (;;) {
             if (p == t) break;
-            const Ent<T> nx = R.ld(p);
-            const T vn = vc + (sf - ck) * (nx.l - cl);
+            const E nx = R.ld(p);
+            const T vn = vc + slope_of<T, G>(sf, ck) * (nx.l - cl);
             if (vn >= lo) break;
             vc = vn;
             cl = nx.l;
@@ -274,30 +283,32 @@ __device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, T sf, T yi, T wprev,
     }
     // the bracket [lam_p, lam_{p+1}] (logical p - 1 and p) is re-read from the
     // ring rather than selected from the window: two loads instead of 3W selects
-    const Ent<T> *pb = R.col + ((h + p - 1) & (K - 1)) * 64;
-    const Ent<T> ea = pb[0], eb = pb[64];
-    const T cl = ea.l, ck = ea.k, nl = eb.l;
+    const E *pb = R.col + ((h + p - 1) & (K - 1)) * 64;
+    const E ea = pb[0], eb = pb[64];
+    const T cl = ea.l, nl = eb.l;
+    const G ck = ea.k;
     const bool empty = (t == 0);
-    const T rl = recip(sf - ck);
+    const T rl = recip(slope_of<T, G>(sf, ck));
     {
         const T lm_gen = clampv(cl + (lo - vc) * rl, cl, nl);
-        const T lm_all = cl + (lo - vc);          // beyond every breakpoint (slope 1)
-        const T lm_none = F[0].l - (v[0] - lo);  // before the first breakpoint (slope 1)
+        const T lm_all = cl + es.div(lo - vc);          // beyond every breakpoint (end slope)
+        const T lm_none = F[0].l - es.div(v[0] - lo);  // before the first breakpoint (end slope)
         lm = (p == 0) ? lm_none : ((p == t) ? lm_all : lm_gen);
-        lm = empty ? yi + lo : lm;
+        lm = empty ? es.div(yi + lo) : lm;
     }
-    const T tnew = (p == 0 || p == t) ? sf - (T)1 : ck;
+    const bool end_seg = (p == 0 || p == t);
+    const G tnew = end_seg ? tend : ck;
     // pop p, push lm at the front
     const int h1 = (h + p - 1) & (K - 1);
     const int t1 = t - p + 1;
-    const Ent<T> fnew = mk_ent<T>(lm, tnew);
+    const E fnew = mk_ent<T, G>(lm, tnew);
     R.put_slot(h1, fnew);
     // ---- right end over the qmax = t - p old breakpoints left (never pops lm) ----
     const int qmax = t1 - 1;
     T u[W];
-    u[0] = B[0].l + wprev - yi;
+    u[0] = es.mul(B[0].l) + in.hip - yi;
 #pragma unroll
-    for (int j = 1; j < W; ++j) u[j] = u[j - 1] - (sf - B[j].k) * (B[j - 1].l - B[j].l);
+    for (int j = 1; j < W; ++j) u[j] = u[j - 1] - slope_of<T, G>(sf, B[j].k) * (B[j - 1].l - B[j].l);
     int q = 0;
     T uc = u[0];
 #pragma unroll
@@ -310,8 +321,8 @@ __device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, T sf, T yi, T wprev,
         T rcl = B[W - 1].l;
         for (;;) {
             if (q == qmax) break;
-            const Ent<T> nx = R.ld(t - 1 - q);
-            const T up = uc - (sf - nx.k) * (rcl - nx.l);
+            const E nx = R.ld(t - 1 - q);
+            const T up = uc - slope_of<T, G>(sf, nx.k) * (rcl - nx.l);
             if (up <= hi) break;
             uc = up;
             rcl = nx.l;
@@ -320,25 +331,27 @@ __device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, T sf, T yi, T wprev,
     }
     // bracket: logical t - 1 - q (left end, its tag) and t - q (right end);
     // only read where q < qmax, i.e. never the slot the front push just wrote
-    const Ent<T> *qb = R.col + ((h + t - 1 - q) & (K - 1)) * 64;
-    const Ent<T> ra = qb[0], rb = qb[64];
-    const T rnl = ra.l, rk = ra.k, rcl = rb.l;
+    const E *qb = R.col + ((h + t - 1 - q) & (K - 1)) * 64;
+    const E ra = qb[0], rb = qb[64];
+    const T rnl = ra.l, rcl = rb.l;
+    const G rk = ra.k;
     {
-        const T lp_gen = clampv(rcl - (uc - hi) * recip(sf - rk), rnl, rcl);
-        // popped down to lm: lm's segment has slope s - tnew (1 when tnew = s - 1)
-        T lp_lm = lm + (hi - lo) * ((p == 0 || p == t) ? (T)1 : rl);
+        const T lp_gen = clampv(rcl - (uc - hi) * recip(slope_of<T, G>(sf, rk)), rnl, rcl);
+        // popped down to lm: lm's segment has the end slope when tnew = tend
+        T lp_lm = lm + (hi - lo) * (end_seg ? es.ra : rl);
         lp_lm = (qmax > 0 && lp_lm > rcl) ? rcl : lp_lm;
-        const T lp_none = B[0].l + (hi - u[0]);     // beyond the last breakpoint (slope 1)
+        const T lp_none = B[0].l + es.div(hi - u[0]);  // beyond the last breakpoint (end slope)
         lp = (q == qmax) ? lp_lm : ((q == 0) ? lp_none : lp_gen);
-        lp = empty ? yi + hi : lp;
+        lp = empty ? es.div(yi + hi) : lp;
     }
     // The old back (logical t1 - 1) stays as an interior breakpoint when q = 0:
-    // its right segment now has slope 1.  Written unconditionally: when q > 0
-    // that slot is dead or overwritten by the new back below, and when
-    // qmax = 0 it is the front slot, rewritten with its own value.
-    R.put_slot((h1 + t1 - 1) & (K - 1), qmax > 0 ? mk_ent<T>(B[0].l, sf - (T)1) : fnew);
+    // its right segment is the flat right end, tag tend.  Written
+    // unconditionally: when q > 0 that slot is dead or overwritten by the new
+    // back below, and when qmax = 0 it is the front slot, rewritten with its own
+    // value.
+    R.put_slot((h1 + t1 - 1) & (K - 1), qmax > 0 ? mk_ent<T, G>(B[0].l, tend) : fnew);
     const int t2 = t1 - q + 1;
-    const Ent<T> bnew = mk_ent<T>(lp, (T)0);
+    const E bnew = mk_ent<T, G>(lp, (G)0);
     R.put_slot((h1 + t2 - 1) & (K - 1), bnew);
     R.head = h1;
     R.size = t2 < K ? t2 : K;
@@ -350,14 +363,87 @@ __device__ __forceinline__ bool dp_step_win(CRing<T, K> &R, T sf, T yi, T wprev,
 // ---------------------------------------------------------------------------
 // Shared pieces.
 // ---------------------------------------------------------------------------
-template <typename T, int K>
-__device__ __forceinline__ void node_step(CRing<T, K> &R, bool &ok, int64_t i, int64_t n, T yi, T wi, T &wprev,
-                                          T &lm, T &lp) {
+// A problem policy (Prob) supplies its node records (Pre) through Src, and
+// declares its model: Tag = the tag type, kGen = general a_i and asymmetric
+// weights.  With kGen false Src provides data (b_i = y_i) and weight (w_i of
+// the leaving edge, w^- = -w_i, w^+ = w_i); with kGen true it provides data,
+// prefix (Abar_i, FP64), wlo / whi (w^-, w^+ of the leaving edge).
+//
+// What a step needs from the node before it.
+template <typename T, typename G, bool kGen> struct Carry;
+template <typename T, typename G> struct Carry<T, G, false> {
+    T wprev;
+};
+template <typename T, typename G> struct Carry<T, G, true> {
+    G sprev;
+    T lop, hip;
+};
+template <typename T, class Prob> using CarryOf = Carry<T, typename Prob::Tag, Prob::kGen>;
+template <typename T, class Prob> using WsOf = SegWs<T, typename Prob::Tag>;
+template <typename T, class Prob> using EntOf = Ent<T, typename Prob::Tag>;
+
+// The carry of a run that starts at node i (node i - 1's leaving edge and
+// prefix; zeros at the first node).
+template <typename T, class Prob>
+__device__ __forceinline__ CarryOf<T, Prob> carry_before(const typename Prob::Src &src, int64_t i) {
+    CarryOf<T, Prob> cy;
+    if constexpr (Prob::kGen) {
+        cy.sprev = 0;
+        cy.lop = (T)0;
+        cy.hip = (T)0;
+        if (i > 0) {
+            const auto pv = src.load(i - 1);
+            cy.sprev = src.prefix(pv);
+            cy.lop = src.wlo(pv);
+            cy.hip = src.whi(pv);
+        }
+    } else {
+        cy.wprev = (i > 0) ? src.weight(src.load(i - 1)) : (T)0;
+    }
+    return cy;
+}
+
+// Inputs of the step at node i (root: zero leaving edge); advances the carry.
+template <typename T, class Prob>
+__device__ __forceinline__ StepIn<T, typename Prob::Tag> step_in(const typename Prob::Src &src,
+                                                                 const typename Prob::Pre &pv, int64_t i, bool root,
+                                                                 CarryOf<T, Prob> &cy) {
+    StepIn<T, typename Prob::Tag> in;
+    in.yi = src.data(pv);
+    if constexpr (Prob::kGen) {
+        const T wl = src.wlo(pv), wh = src.whi(pv);
+        in.sf = src.prefix(pv);
+        in.sprev = cy.sprev;
+        in.lop = cy.lop;
+        in.hip = cy.hip;
+        in.lo = root ? (T)0 : wl;
+        in.hi = root ? (T)0 : wh;
+        cy.sprev = in.sf;
+        cy.lop = wl;
+        cy.hip = wh;
+    } else {
+        const T wi = src.weight(pv);
+        const T w = root ? (T)0 : wi;
+        in.sf = (T)(int)(i + 1);
+        in.sprev = in.sf - (T)1;
+        in.lop = -cy.wprev;
+        in.hip = cy.wprev;
+        in.lo = -w;
+        in.hi = w;
+        cy.wprev = wi;
+    }
+    return in;
+}
+
+template <typename T, class Prob, int K>
+__device__ __forceinline__ void node_step(CRing<T, K, typename Prob::Tag> &R, bool &ok, int64_t i, int64_t n,
+                                          const typename Prob::Src &src, const typename Prob::Pre &pv,
+                                          CarryOf<T, Prob> &cy, T &lm, T &lp) {
     const bool root = (i == n - 1);
-    const bool fits = dp_step_win<T, K, kScanWindow>(R, (T)(int)(i + 1), yi, wprev, root ? (T)0 : wi, lm, lp);
+    const auto in = step_in<T, Prob>(src, pv, i, root, cy);
+    const bool fits = dp_step_win<T, typename Prob::Tag, K, kScanWindow, Prob::kGen>(R, in, lm, lp);
     ok = ok & (fits | root);
     if (root) lp = lm;
-    wprev = wi;
 }
 
 template <typename T>
@@ -368,29 +454,32 @@ __device__ __forceinline__ void put_lam(LamPair<T> *lam, int64_t i, int64_t C, i
     lam[i * C + c] = pr;
 }
 
-template <typename T>
-__device__ __forceinline__ Ent<T> *save_slot(const SegWs<T> &ws, int K, int64_t s, int kind, int64_t c) {
+template <typename T, typename G>
+__device__ __forceinline__ Ent<T, G> *save_slot(const SegWs<T, G> &ws, int K, int64_t s, int kind, int64_t c) {
     return ws.st + ((s * kSaves + kind) * K) * ws.C + c;
 }
-template <typename T>
-__device__ __forceinline__ int *size_slot(const SegWs<T> &ws, int64_t s, int kind, int64_t c) {
+template <typename T, typename G>
+__device__ __forceinline__ int *size_slot(const SegWs<T, G> &ws, int64_t s, int kind, int64_t c) {
     return ws.st_size + (s * kSaves + kind) * ws.C + c;
 }
-template <typename T>
-__device__ __forceinline__ uint32_t *hash_slot(const SegWs<T> &ws, int64_t s, int kind, int64_t c) {
+template <typename T, typename G>
+__device__ __forceinline__ uint32_t *hash_slot(const SegWs<T, G> &ws, int64_t s, int kind, int64_t c) {
     return ws.st_hash + (s * kSaves + kind) * ws.C + c;
 }
 // Save / compare the ring against saved state `kind` of segment s.
-template <typename T, int K>
-__device__ __forceinline__ void save_state(const SegWs<T> &ws, const CRing<T, K> &R, int64_t s, int kind, int64_t c) {
+template <typename T, int K, typename G>
+__device__ __forceinline__ void save_state(const SegWs<T, G> &ws, const CRing<T, K, G> &R, int64_t s, int kind,
+                                           int64_t c) {
     R.save(save_slot(ws, K, s, kind, c), size_slot(ws, s, kind, c), hash_slot(ws, s, kind, c), ws.C);
 }
-template <typename T, int K>
-__device__ __forceinline__ bool equals_state(const SegWs<T> &ws, const CRing<T, K> &R, int64_t s, int kind, int64_t c) {
+template <typename T, int K, typename G>
+__device__ __forceinline__ bool equals_state(const SegWs<T, G> &ws, const CRing<T, K, G> &R, int64_t s, int kind,
+                                             int64_t c) {
     return R.equals(save_slot(ws, K, s, kind, c), size_slot(ws, s, kind, c), hash_slot(ws, s, kind, c), ws.C);
 }
-template <typename T, int K>
-__device__ __forceinline__ void load_state(const SegWs<T> &ws, CRing<T, K> &R, int64_t s, int kind, int64_t c) {
+template <typename T, int K, typename G>
+__device__ __forceinline__ void load_state(const SegWs<T, G> &ws, CRing<T, K, G> &R, int64_t s, int kind,
+                                           int64_t c) {
     R.load(save_slot(ws, K, s, kind, c), size_slot(ws, s, kind, c), ws.C);
 }
 
@@ -400,9 +489,9 @@ __device__ __forceinline__ void load_state(const SegWs<T> &ws, CRing<T, K> &R, i
 // from `from`); a true return stops the run, and fwd_run then returns e.
 // Otherwise it returns b.
 template <typename T, class Prob, int K, int P, bool kStore, class Hook>
-__device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::Src &src, bool &ok, T &wprev,
-                                           int64_t from, int64_t b, int64_t n, LamPair<T> *lam, int64_t C,
-                                           int64_t c, Hook hook) {
+__device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, const typename Prob::Src &src,
+                                           bool &ok, CarryOf<T, Prob> &cy, int64_t from, int64_t b, int64_t n,
+                                           LamPair<T> *lam, int64_t C, int64_t c, Hook hook) {
     static_assert(P % 4 == 0, "tiles hold whole groups of four nodes");
     typename Prob::Pre pre[P];
 #pragma unroll
@@ -410,7 +499,7 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::
     LamPair<T> *lq = lam + from * C + c;  // lambda pair of the next node (running pointer)
     auto node = [&](int64_t i, const typename Prob::Pre &pv) {
         T lm, lp;
-        node_step<T, K>(R, ok, i, n, src.data(pv), src.weight(pv), wprev, lm, lp);
+        node_step<T, Prob, K>(R, ok, i, n, src, pv, cy, lm, lp);
         if (kStore) {
             LamPair<T> pr;
             pr.lo = lm;
@@ -477,7 +566,7 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K> &R, const typename Prob::
 // whole group has collapsed (the group holding the collapse point falls back
 // to single stores).
 template <typename T, class Prob, int P, bool kVec>
-__device__ __forceinline__ void bwd_sweep_run(const SegWs<T> &ws, const typename Prob::Sink &sink, int64_t s,
+__device__ __forceinline__ void bwd_sweep_run(const WsOf<T, Prob> &ws, const typename Prob::Sink &sink, int64_t s,
                                               int64_t c, int64_t a, int64_t b) {
     static_assert(P % 4 == 0, "tiles hold whole groups of four nodes");
     using SP = typename Prob::SinkPre;
@@ -572,7 +661,7 @@ __device__ __forceinline__ void bwd_sweep_run(const SegWs<T> &ws, const typename
 }
 
 template <typename T, class Prob, int P>
-__device__ __forceinline__ void bwd_sweep(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp,
+__device__ __forceinline__ void bwd_sweep(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, const ChainSpan &sp,
                                           int64_t s, int64_t c, int64_t a, int64_t b) {
     const auto sink = Prob::sink(pp, sp);
     if (sink.vec && (b & 3) == 0)
@@ -582,20 +671,20 @@ __device__ __forceinline__ void bwd_sweep(const SegWs<T> &ws, const typename Pro
 }
 
 // True if the deque after node e - 1 equals the first pass's checkpoint there.
-template <typename T, int K>
-__device__ __forceinline__ bool meets_checkpoint(const SegWs<T> &ws, const CRing<T, K> &R, int64_t s, int64_t c,
+template <typename T, int K, typename G>
+__device__ __forceinline__ bool meets_checkpoint(const SegWs<T, G> &ws, const CRing<T, K, G> &R, int64_t s, int64_t c,
                                                  int64_t a, int64_t e) {
     const int64_t m = (e - a) / ws.CK;
     if (e <= a || m * ws.CK != e - a || m > kCheckpoints) return false;
-    return equals_state<T, K>(ws, R, s, kSaveCk + (int)m - 1, c);
+    return equals_state<T, K, G>(ws, R, s, kSaveCk + (int)m - 1, c);
 }
 
 // ---------------------------------------------------------------------------
 // First pass: forward with halo and saves, then the backward sweep.
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
-__global__ __launch_bounds__(64) void k_seg_main(SegWs<T> ws, typename Prob::Params pp) {
-    __shared__ Ent<T> s_ent[2 * K * 64];
+__global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob::Params pp) {
+    __shared__ EntOf<T, Prob> s_ent[2 * K * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g == 0) *ws.ovf_count = 0;  // consumed by k_seg_fix / k_seg_ovf after this kernel
@@ -608,25 +697,25 @@ __global__ __launch_bounds__(64) void k_seg_main(SegWs<T> ws, typename Prob::Par
     const int64_t b = (a + ws.L < n) ? a + ws.L : n;
     const int64_t h0 = (a > ws.H) ? a - ws.H : 0;
     const auto src = Prob::src(pp, sp);
-    CRing<T, K> R;
+    CRing<T, K, typename Prob::Tag> R;
     R.init(s_ent, lane);
     bool ok = true;
-    T wprev = (T)0;
+    auto cy = carry_before<T, Prob>(src, h0);
     const int64_t C = ws.C;
     // halo [h0, a) from an empty deque, storing nothing (a - h0 is a multiple of P)
     if (h0 < a)
-        fwd_run<T, Prob, K, P, false>(R, src, ok, wprev, h0, a, n, ws.lam, C, c, [](int64_t) { return false; });
-    if (s > 0 && ok) save_state<T, K>(ws, R, s, kSaveHalo, c);
+        fwd_run<T, Prob, K, P, false>(R, src, ok, cy, h0, a, n, ws.lam, C, c, [](int64_t) { return false; });
+    if (s > 0 && ok) save_state(ws, R, s, kSaveHalo, c);
     // own nodes; tile edges align with a + m CK (multiples of P)
     auto saves = [&](int64_t e) {
         if (ok) {
             const int64_t m = (e - a) / ws.CK;
-            if (m * ws.CK == e - a && m <= kCheckpoints) save_state<T, K>(ws, R, s, kSaveCk + (int)m - 1, c);
+            if (m * ws.CK == e - a && m <= kCheckpoints) save_state(ws, R, s, kSaveCk + (int)m - 1, c);
         }
         return false;
     };
-    fwd_run<T, Prob, K, P, true>(R, src, ok, wprev, a, b, n, ws.lam, C, c, saves);
-    if (ok && b < n) save_state<T, K>(ws, R, s, kSaveEnd, c);
+    fwd_run<T, Prob, K, P, true>(R, src, ok, cy, a, b, n, ws.lam, C, c, saves);
+    if (ok && b < n) save_state(ws, R, s, kSaveEnd, c);
     ws.ovf[c * ws.S + s] = ok ? 0 : 1;
     if (ok) bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
 }
@@ -639,8 +728,8 @@ __global__ __launch_bounds__(64) void k_seg_main(SegWs<T> ws, typename Prob::Par
 // first-pass checkpoint, then its backward pass is redone.
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
-__global__ __launch_bounds__(64) void k_seg_repair(SegWs<T> ws, typename Prob::Params pp) {
-    __shared__ Ent<T> s_ent[2 * K * 64];
+__global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Prob::Params pp) {
+    __shared__ EntOf<T, Prob> s_ent[2 * K * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g >= (ws.S - 1) * ws.C) return;
@@ -656,11 +745,11 @@ __global__ __launch_bounds__(64) void k_seg_repair(SegWs<T> ws, typename Prob::P
     bool same = (*size_slot(ws, s - 1, kSaveEnd, c) == *size_slot(ws, s, kSaveHalo, c)) &&
                 (*hash_slot(ws, s - 1, kSaveEnd, c) == *hash_slot(ws, s, kSaveHalo, c));
     if (same) {
-        const Ent<T> *A = save_slot(ws, K, s - 1, kSaveEnd, c);
-        const Ent<T> *B = save_slot(ws, K, s, kSaveHalo, c);
+        const EntOf<T, Prob> *A = save_slot(ws, K, s - 1, kSaveEnd, c);
+        const EntOf<T, Prob> *B = save_slot(ws, K, s, kSaveHalo, c);
         const int m = clamp_size<K>(*size_slot(ws, s - 1, kSaveEnd, c));
         for (int j0 = 0; j0 < m && same; j0 += 8) {
-            Ent<T> ea[8], eb[8];
+            EntOf<T, Prob> ea[8], eb[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int jj = (j0 + j < m) ? j0 + j : m - 1;
@@ -677,30 +766,30 @@ __global__ __launch_bounds__(64) void k_seg_repair(SegWs<T> ws, typename Prob::P
     ws.mis[cs] = same ? 0 : 1;
     if (same) return;
     const auto src = Prob::src(pp, sp);
-    CRing<T, K> R;
+    CRing<T, K, typename Prob::Tag> R;
     R.init(s_ent, lane);
-    load_state<T, K>(ws, R, s - 1, kSaveEnd, c);
+    load_state(ws, R, s - 1, kSaveEnd, c);
     bool ok = true;
-    T wprev = src.weight(src.load(a - 1));
-    const int64_t stop = fwd_run<T, Prob, K, P, true>(R, src, ok, wprev, a, b, n, ws.lam, C, c,
-                                                [&](int64_t e) { return !ok || meets_checkpoint<T, K>(ws, R, s, c, a, e); });
+    auto cy = carry_before<T, Prob>(src, a);
+    const int64_t stop = fwd_run<T, Prob, K, P, true>(R, src, ok, cy, a, b, n, ws.lam, C, c,
+                                                [&](int64_t e) { return !ok || meets_checkpoint(ws, R, s, c, a, e); });
     if (!ok) {
         ws.ovf[cs] = 1;
         return;
     }
     // met a checkpoint, or ends with the first pass's end deque: either way the
     // two runs coincide from some node on, so the saved end state is the true one
-    const bool clean = stop < b || (b < n && equals_state<T, K>(ws, R, s, kSaveEnd, c));
+    const bool clean = stop < b || (b < n && equals_state(ws, R, s, kSaveEnd, c));
     ws.clean[cs] = clean ? 1 : 0;
     ws.rep_stop[s * C + c] = (int)stop;
-    if (!clean && b < n) save_state<T, K>(ws, R, s, kSaveEnd2, c);
+    if (!clean && b < n) save_state(ws, R, s, kSaveEnd2, c);
     bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
 }
 
 // Backward clip of a whole chain from its lambda stream (after a sequential
 // forward pass); marks every segment's tail as done for k_seg_tail.
 template <typename T, class Prob>
-__device__ void full_backward(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c) {
+__device__ void full_backward(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c) {
     const auto sink = Prob::sink(pp, sp);
     T x = (T)0;
     for (int64_t i = sp.n - 1; i >= 0; --i) {
@@ -717,28 +806,28 @@ __device__ void full_backward(const SegWs<T> &ws, const typename Prob::Params &p
 
 // Sequential DP + backward of a whole chain with the deque in HBM.
 template <typename T, class Prob>
-__device__ void seg_full_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
-                               int64_t slot) {
+__device__ void seg_full_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, const ChainSpan &sp,
+                               int64_t c, int64_t slot) {
+    using G = typename Prob::Tag;
     const auto src = Prob::src(pp, sp);
-    GlobalDeque<T> dq;
+    GlobalDeque<T, G> dq;
     dq.init(ws.fb_lam + slot * ws.fb_cap, ws.fb_tag + slot * ws.fb_cap, ws.fb_cap);
-    T wprev = (T)0;
+    auto cy = carry_before<T, Prob>(src, 0);
     for (int64_t i = 0; i < sp.n; ++i) {
         const auto pr = src.load(i);
         const bool root = (i == sp.n - 1);
         T lm = (T)0, lp = (T)0;
-        const T wi = src.weight(pr);
-        dp_step<T>(dq, (int)(i + 1), src.data(pr), wprev, root ? (T)0 : wi, root, lm, lp);
+        const auto in = step_in<T, Prob>(src, pr, i, root, cy);
+        dp_step<T, G, Prob::kGen>(dq, in, root, lm, lp);
         if (root) lp = lm;
         put_lam<T>(ws.lam, i, ws.C, c, lm, lp);
-        wprev = wi;
     }
     full_backward<T, Prob>(ws, pp, sp, c);
 }
 
 template <typename T, class Prob, int K, int P>
-__device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
-                          Ent<T> *s_ent, int lane);
+__device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
+                          EntOf<T, Prob> *s_ent, int lane);
 
 // ---------------------------------------------------------------------------
 // Fix-up, one lane per chain (a no-op for almost every chain).  Walks the
@@ -748,8 +837,8 @@ __device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, c
 // region the repair kernel rewrote.
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
-__global__ __launch_bounds__(64) void k_seg_fix(SegWs<T> ws, typename Prob::Params pp) {
-    __shared__ Ent<T> s_ent[2 * K * 64];
+__global__ __launch_bounds__(64) void k_seg_fix(WsOf<T, Prob> ws, typename Prob::Params pp) {
+    __shared__ EntOf<T, Prob> s_ent[2 * K * 64];
     const int lane = threadIdx.x;
     const int64_t c = (int64_t)blockIdx.x * 64 + lane;
     if (c >= ws.C) return;
@@ -782,14 +871,14 @@ __global__ __launch_bounds__(64) void k_seg_fix(SegWs<T> ws, typename Prob::Para
 // Returns false if the true deque outgrew the ring (the chain then goes to
 // the HBM overflow kernel).
 template <typename T, class Prob, int K, int P>
-__device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
-                          Ent<T> *s_ent, int lane) {
+__device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, const ChainSpan &sp, int64_t c,
+                          EntOf<T, Prob> *s_ent, int lane) {
     const int64_t n = sp.n;
     const int64_t Sc = (n + ws.L - 1) / ws.L;
     const uint8_t *mis = ws.mis + c * ws.S;
     const uint8_t *cln = ws.clean + c * ws.S;
     const auto src = Prob::src(pp, sp);
-    CRing<T, K> R;
+    CRing<T, K, typename Prob::Tag> R;
     R.init(s_ent, lane);
     const int64_t C = ws.C;
     bool end_true = true, ok = true;
@@ -800,23 +889,23 @@ __device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, c
             // the pass that wrote segment s started from the true state
             if (mis[s] && !cln[s]) {
                 end_true = false;
-                if (b < n) load_state<T, K>(ws, R, s, kSaveEnd2, c);
+                if (b < n) load_state(ws, R, s, kSaveEnd2, c);
             }
             continue;
         }
         // R holds the true deque entering segment s: redo it until it meets the
         // first pass and is past whatever the repair kernel rewrote.
         const int64_t redo_to = mis[s] ? (int64_t)ws.rep_stop[s * C + c] : a;
-        T wprev = src.weight(src.load(a - 1));
+        auto cy = carry_before<T, Prob>(src, a);
         bool met = false;
-        const int64_t stop = fwd_run<T, Prob, K, P, true>(R, src, ok, wprev, a, b, n, ws.lam, C, c, [&](int64_t e) {
+        const int64_t stop = fwd_run<T, Prob, K, P, true>(R, src, ok, cy, a, b, n, ws.lam, C, c, [&](int64_t e) {
             if (!ok) return true;
-            met = met || meets_checkpoint<T, K>(ws, R, s, c, a, e);
+            met = met || meets_checkpoint(ws, R, s, c, a, e);
             return met && e >= redo_to;
         });
         if (!ok) break;
         if (stop == b && !met && b < n)
-            met = equals_state<T, K>(ws, R, s, kSaveEnd, c);
+            met = equals_state(ws, R, s, kSaveEnd, c);
         bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
         end_true = met;
     }
@@ -825,18 +914,18 @@ __device__ bool fix_chain(const SegWs<T> &ws, const typename Prob::Params &pp, c
 
 // ---------------------------------------------------------------------------
 // Overflowed chains, solved sequentially by a bounded pool of lanes: first with
-// a 64 KiB per-wave LDS ring (64 slots for float, 32 for double), and only if
-// the deque outgrows that too, with the deque in HBM (lane l owns deque
-// storage l).  Both paths compute the same bits as the segmented one.
+// a 64 KiB per-wave LDS ring (64 slots of 8-byte entries, 32 of 16-byte ones),
+// and only if the deque outgrows that too, with the deque in HBM (lane l owns
+// deque storage l).  Both paths compute the same bits as the segmented one.
 // ---------------------------------------------------------------------------
-template <typename T> struct OvfRing {
-    static constexpr int K = sizeof(T) == 4 ? 64 : 32;
+template <class E> struct OvfRing {
+    static constexpr int K = 65536 / (2 * 64 * (int)sizeof(E));
 };
 
 template <typename T, class Prob>
-__global__ __launch_bounds__(64) void k_seg_ovf(SegWs<T> ws, typename Prob::Params pp) {
-    constexpr int KB = OvfRing<T>::K;
-    __shared__ Ent<T> s_big[2 * KB * 64];
+__global__ __launch_bounds__(64) void k_seg_ovf(WsOf<T, Prob> ws, typename Prob::Params pp) {
+    constexpr int KB = OvfRing<EntOf<T, Prob>>::K;
+    __shared__ EntOf<T, Prob> s_big[2 * KB * 64];
     const int lane = threadIdx.x;
     const int64_t l = (int64_t)blockIdx.x * 64 + lane;
     const int64_t cnt = *ws.ovf_count;
@@ -845,11 +934,11 @@ __global__ __launch_bounds__(64) void k_seg_ovf(SegWs<T> ws, typename Prob::Para
         const ChainSpan sp = Prob::span(pp, c, ws.n);
         if (sp.n <= 0) continue;
         const auto src = Prob::src(pp, sp);
-        CRing<T, KB> R;
+        CRing<T, KB, typename Prob::Tag> R;
         R.init(s_big, lane);
         bool ok = true;
-        T wprev = (T)0;
-        fwd_run<T, Prob, KB, kTileOvf, true>(R, src, ok, wprev, 0, sp.n, sp.n, ws.lam, ws.C, c,
+        auto cy = carry_before<T, Prob>(src, 0);
+        fwd_run<T, Prob, KB, kTileOvf, true>(R, src, ok, cy, 0, sp.n, sp.n, ws.lam, ws.C, c,
                                              [](int64_t) { return false; });
         if (ok)
             full_backward<T, Prob>(ws, pp, sp, c);
@@ -862,7 +951,7 @@ __global__ __launch_bounds__(64) void k_seg_ovf(SegWs<T> ws, typename Prob::Para
 // Un-collapsed tails: x_i = clip(x_b, composed interval of i .. b-1).
 // ---------------------------------------------------------------------------
 template <typename T, class Prob>
-__global__ __launch_bounds__(64) void k_seg_tail(SegWs<T> ws, typename Prob::Params pp) {
+__global__ __launch_bounds__(64) void k_seg_tail(WsOf<T, Prob> ws, typename Prob::Params pp) {
     const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (g >= (ws.S - 1) * ws.C) return;
     const int64_t c = g % ws.C, s = g / ws.C;
@@ -887,14 +976,14 @@ __global__ __launch_bounds__(64) void k_seg_tail(SegWs<T> ws, typename Prob::Par
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-template <typename T, int K>
-size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int64_t CK, SegWs<T> *out) {
+template <typename T, int K, typename G = T>
+size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int64_t CK, SegWs<T, G> *out) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const int64_t S = (n + L - 1) / L;
     const int64_t cap = 2 * n + 4;
     size_t off = 0;
     const size_t o_lam = off;  off += al(sizeof(LamPair<T>) * (size_t)(n * C));
-    const size_t o_st = off;   off += al(sizeof(Ent<T>) * (size_t)(S * kSaves * K * C));
+    const size_t o_st = off;   off += al(sizeof(Ent<T, G>) * (size_t)(S * kSaves * K * C));
     const size_t o_sz = off;   off += al(sizeof(int) * (size_t)(S * kSaves * C));
     const size_t o_hs = off;   off += al(sizeof(uint32_t) * (size_t)(S * kSaves * C));
     const size_t o_ovf = off;  off += al((size_t)(S * C));
@@ -909,10 +998,10 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
     const size_t o_oc = off;   off += al(sizeof(int));
     const size_t o_ol = off;   off += al(sizeof(int) * (size_t)C);
     const size_t o_fl = off;   off += al(sizeof(T) * (size_t)(fbl * cap));
-    const size_t o_ft = off;   off += al(sizeof(int) * (size_t)(fbl * cap));
+    const size_t o_ft = off;   off += al(sizeof(G) * (size_t)(fbl * cap));
     if (base && out) {
         char *p = (char *)base;
-        SegWs<T> w;
+        SegWs<T, G> w;
         w.C = C;
         w.n = n;
         w.L = L;
@@ -920,7 +1009,7 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
         w.H = H;
         w.CK = CK;
         w.lam = (LamPair<T> *)(p + o_lam);
-        w.st = (Ent<T> *)(p + o_st);
+        w.st = (Ent<T, G> *)(p + o_st);
         w.st_size = (int *)(p + o_sz);
         w.st_hash = (uint32_t *)(p + o_hs);
         w.ovf = (uint8_t *)(p + o_ovf);
@@ -934,7 +1023,7 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
         w.ovf_count = (int *)(p + o_oc);
         w.ovf_list = (int *)(p + o_ol);
         w.fb_lam = (T *)(p + o_fl);
-        w.fb_tag = (int *)(p + o_ft);
+        w.fb_tag = (G *)(p + o_ft);
         w.fb_cap = cap;
         w.fb_lanes = fbl;
         *out = w;
@@ -943,7 +1032,7 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
 }
 
 template <typename T, class Prob, int K, int P>
-hipError_t seg_launch(const SegWs<T> &ws, const typename Prob::Params &pp, hipStream_t stream) {
+hipError_t seg_launch(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, hipStream_t stream) {
     if (ws.C <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((ws.S * ws.C + 63) / 64);
     hipLaunchKernelGGL((k_seg_main<T, Prob, K, P>), dim3(blocks), dim3(64), 0, stream, ws, pp);
@@ -962,16 +1051,16 @@ hipError_t seg_launch(const SegWs<T> &ws, const typename Prob::Params &pp, hipSt
 }
 
 // Workspace bytes and launch for a plan, dispatching on its ring size.
-template <typename T>
+template <typename T, typename G = T>
 size_t seg_ws_bytes(int64_t C, int64_t n, const SegPlan &p) {
-    return p.K == 32 ? seg_ws_layout<T, 32>(nullptr, C, n, p.L, p.H, p.CK, nullptr)
-                     : seg_ws_layout<T, 16>(nullptr, C, n, p.L, p.H, p.CK, nullptr);
+    return p.K == 32 ? seg_ws_layout<T, 32, G>(nullptr, C, n, p.L, p.H, p.CK, nullptr)
+                     : seg_ws_layout<T, 16, G>(nullptr, C, n, p.L, p.H, p.CK, nullptr);
 }
 
 template <typename T, class Prob, int P>
 hipError_t seg_run(void *workspace, int64_t C, int64_t n, const SegPlan &p, const typename Prob::Params &pp,
                    hipStream_t stream) {
-    SegWs<T> ws;
+    WsOf<T, Prob> ws;
     if (p.K == 32) {
         seg_ws_layout<T, 32>(workspace, C, n, p.L, p.H, p.CK, &ws);
         return seg_launch<T, Prob, 32, P>(ws, pp, stream);

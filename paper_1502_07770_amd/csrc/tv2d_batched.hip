@@ -32,6 +32,8 @@ struct BChain {
 
 template <typename T>
 struct BColProb {
+    using Tag = T;  // a_i = 1: integer tags in the working precision
+    static constexpr bool kGen = false;
     struct Params {
         const BChain *desc;
         const T *y_old;
@@ -105,6 +107,8 @@ struct BColProb {
 
 template <typename T>
 struct BRowProb {
+    using Tag = T;  // a_i = 1: integer tags in the working precision
+    static constexpr bool kGen = false;
     struct Params {
         const BChain *desc;
         const T *f;

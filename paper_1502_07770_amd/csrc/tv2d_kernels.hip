@@ -42,6 +42,8 @@ namespace tvc {
 // Column step: chains are the W columns of the dense H x W state (es = W).
 template <typename T>
 struct ColProb {
+    using Tag = T;  // a_i = 1: integer tags in the working precision
+    static constexpr bool kGen = false;
     struct Params {
         const T *y_old;
         const T *xbar;
@@ -114,6 +116,8 @@ struct ColProb {
 // Row step: chains are the H rows (es = 1); f has its own leading dimension.
 template <typename T>
 struct RowProb {
+    using Tag = T;  // a_i = 1: integer tags in the working precision
+    static constexpr bool kGen = false;
     struct Params {
         const T *f;
         int64_t ldf;

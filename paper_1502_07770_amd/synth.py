@@ -19,6 +19,10 @@ experiments, Figs. 5 and 6):
 * ``uneven_batch_specs``: per-image (H, W, lambda, sigma, seed) for a batch of
   images with H, W uniform on {64, ..., 2048}, lambda U[0.02, 0.3], sigma
   U[0.05, 0.2].
+* ``general_chain_problem``: inputs of the general chain DP (quadratic unaries
+  a_i x^2 / 2 - b_i x, edge slopes w^- <= w^+) on an H x W image: data weights
+  a ~ U[0.5, 2], b = a f with f the shapes image, w^- = -w u and w^+ = w v with
+  u, v ~ U[0.5, 1.5] per edge (asymmetric TV of weight about w).
 * ``edge_weights`` (U[lo, hi]) and ``normal`` (N(0, 1)) helpers.
 """
 from __future__ import annotations
@@ -109,3 +113,14 @@ def edge_weights(shape, lo: float = 0.1, hi: float = 1.0, seed: int = 0) -> np.n
 
 def normal(shape, seed: int = 0) -> np.ndarray:
     return generator(seed).normal(0.0, 1.0, size=shape)
+
+
+def general_chain_problem(H: int, W: int, w: float = 0.1, seed: int = 0):
+    """(a, b, wm, wp), each H x W, for the general chain DP over the rows or the
+    columns of a shapes image (see the module docstring)."""
+    f = shapes_image(H, W, seed=seed)
+    g = generator(seed + 7919)
+    a = g.uniform(0.5, 2.0, size=(H, W))
+    wm = -w * g.uniform(0.5, 1.5, size=(H, W))
+    wp = w * g.uniform(0.5, 1.5, size=(H, W))
+    return a, a * f, wm, wp

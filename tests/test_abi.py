@@ -116,6 +116,34 @@ def test_argument_errors_before_any_hip_call(lib):
     assert lib.tv2d_autotune(0, buf, 64, 48, 48, 0.1, 1.0, ws, 16, None, None, None) == binding.TV_ERR_WORKSPACE
 
 
+def test_chain_dp_argument_errors_and_workspace(lib):
+    """tv_chain_dp: host-visible argument errors come back before any HIP call."""
+    P = ctypes.c_void_p
+    rows = _lay(8, 100, 1, 100)
+    a, b, wm, wp, x, ws = (P(0x10000000 * k) for k in range(1, 7))
+    assert lib.tv_chain_dp_workspace(ctypes.byref(rows), binding.TV_F32) > \
+        lib.tv_chain_prox_workspace(ctypes.byref(rows), binding.TV_F32)  # + FP64 prefix sums
+    assert lib.tv_chain_dp_workspace(ctypes.byref(rows), 5) == 0
+    assert lib.tv_chain_dp_workspace(ctypes.byref(_lay(4, 1 << 24, 1, 1 << 24)), binding.TV_F32) == 0
+    dp = lib.tv_chain_dp
+    big = 1 << 30
+    assert dp(ctypes.byref(rows), 0, a, None, wm, wp, x, ws, big, None) == binding.TV_ERR_INVALID_ARG  # no b
+    assert dp(ctypes.byref(rows), 0, a, b, None, wp, x, ws, big, None) == binding.TV_ERR_INVALID_ARG  # no wm
+    assert dp(ctypes.byref(rows), 0, a, b, wm, None, x, ws, big, None) == binding.TV_ERR_INVALID_ARG  # no wp
+    assert dp(ctypes.byref(rows), 0, a, b, wm, wp, None, ws, big, None) == binding.TV_ERR_INVALID_ARG  # no x
+    for alias in (a, b, wm, wp):  # x overlapping any input
+        assert dp(ctypes.byref(rows), 0, a, b, wm, wp, alias, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    assert dp(ctypes.byref(rows), 0, a, b, wm, wp, P(0x20000000 + 4 * 799), ws, big,
+              None) == binding.TV_ERR_INVALID_ARG
+    assert dp(ctypes.byref(rows), 0, None, b, wm, wp, x, None, 0, None) == binding.TV_ERR_WORKSPACE
+    assert dp(ctypes.byref(rows), 0, None, b, wm, wp, x, ws, 256, None) == binding.TV_ERR_WORKSPACE
+    assert dp(ctypes.byref(_lay(0, 100, 1, 100)), 0, None, None, None, None, None, None, 0, None) == binding.TV_OK
+    res = binding.TuningResult()
+    at = lib.tv_chain_dp_autotune
+    assert at(ctypes.byref(rows), 0, a, b, wm, wp, b, ws, big, None, ctypes.byref(res)) == binding.TV_ERR_INVALID_ARG
+    assert at(ctypes.byref(rows), 0, a, b, wm, wp, x, None, 0, None, ctypes.byref(res)) == binding.TV_ERR_WORKSPACE
+
+
 def test_workspace_covers_every_autotune_candidate(lib):
     """The workspace queries reserve room for the largest candidate plan, so a
     plan chosen after the workspace was allocated always fits."""
