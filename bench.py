@@ -8,8 +8,8 @@ length 4096, i.e. 33,554,432 chain nodes.  Inputs are resident in HBM before
 timing starts.  value = Gelem/s = nodes / time.
 
 Also on the same JSON line:
-  roofline     -- one tv_chain_prox call (its kernels: k_seg_main, k_seg_repair,
-                  k_seg_fix, k_seg_ovf, k_seg_tail) timed with HIP events;
+  roofline     -- one tv_chain_prox_multi launch (its kernels: k_seg_main,
+                  k_seg_repair, k_seg_fix, k_seg_ovf, k_seg_tail) timed with HIP events;
                   algorithmic bytes 8 B/node (y read, x written) / duration vs the
                   8 TB/s HBM peak; traffic from the committed rocprofv3
                   FETCH_SIZE/WRITE_SIZE summary when it was taken on the current
@@ -17,9 +17,11 @@ Also on the same JSON line:
   cpu_baseline -- the FP64 C oracle on the host cores, same workload.
   extras       -- 2D ROF time-to-gap 1e-4 in FP32 vs FP64 (512^2 and 4096^2),
                   200 iterations at 512^2, forward+backward of 65,536 chains of
-                  1,024 with per-edge weights, and a batch of 256 uneven images.
+                  1,024 with per-edge weights, the general chain DP (data weights,
+                  asymmetric edge slopes) on the 4096^2 rows and columns, and a
+                  batch of 256 uneven images.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras | --extras LIST]
        python bench.py --rocprof-summary DIR   (print a summary of rocprofv3 output)
        python bench.py --copy-calibration      (a plain copy of known size, for counters)
 """
@@ -246,6 +248,34 @@ def bench_adjoint(steps: int):
             "bwd_hbm_frac": round(nodes * 16 / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def bench_general_dp(steps: int, autotune: bool = True):
+    """The general chain DP (tv_chain_dp: data weights a_i, asymmetric edge
+    slopes) over all row and all column chains of a 4096 x 4096 image, FP32;
+    rows and columns are separate calls (each autotuned just before it is
+    timed: both have the same chain count and length, so they share a plan
+    key).  Algorithmic bytes: a, b, w^-, w^+ read and x written, 20 B/node."""
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    a, b, wm, wp = (torch.tensor(v, dtype=torch.float32, device="cuda")
+                    for v in synth.general_chain_problem(SIDE, SIDE, seed=SEED))
+    tm = Timer(torch, torch.cuda.current_stream())
+    out = {"workload": "4096 row + 4096 column chains of 4096, a ~ U[0.5,2], b = a f (shapes image), "
+                       "w- = -0.1 U[0.5,1.5], w+ = 0.1 U[0.5,1.5], FP32"}
+    for name, dim in (("rows", -1), ("cols", 0)):
+        plan = None
+        if autotune:
+            _, plan = binding.chain_dp(b, wm, wp, a=a, dim=dim, autotune=True)  # setup, not timed
+        else:
+            binding.chain_dp(b, wm, wp, a=a, dim=dim)
+        ms = tm(lambda: binding.chain_dp(b, wm, wp, a=a, dim=dim), steps)  # noqa: B023
+        out[name] = {"plan": plan, "ms": round(ms, 4)}
+    tot = out["rows"]["ms"] + out["cols"]["ms"]
+    nodes = 2 * SIDE * SIDE
+    out["gelem_s"] = round(nodes / tot / 1e6, 2)
+    out["hbm_frac"] = round(nodes * 20 / (tot * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
 def bench_batched():
     import numpy as np
     import torch
@@ -303,8 +333,10 @@ def rocprof_summary(d):
             if short.startswith("tvc::k_seg_"):
                 prob = short.split(",")[1].strip().split("<")[0] if "," in short else short
                 call_us[prob] = call_us.get(prob, 0.0) + avg
+            elif short.startswith("tvc::k_prefix_"):  # the general DP's prefix pass
+                call_us["tvc::GenProb"] = call_us.get("tvc::GenProb", 0.0) + avg
         for prob, us in sorted(call_us.items()):
-            print("  one launch with %s (sum of the k_seg_* averages): %.1f us" % (prob, us))
+            print("  one launch with %s (sum of the k_seg_* (and k_prefix_*) averages): %.1f us" % (prob, us))
     for cnt in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
         with open(cnt) as fh:
             rows = list(csv.DictReader(fh))
@@ -374,6 +406,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -449,15 +483,18 @@ def main():
         out["cpu_baseline"] = cpu_baseline(r["img"])
     if not args.no_extras:
         extras = {}
+        runs = [("tv2d_512", "2D 512x512", lambda: bench_tv2d(512, 11, 200, 1e-4, 2000)),
+                ("tv2d_4096", "2D 4096x4096", lambda: bench_tv2d(4096, SEED, None, 1e-4, 500)),
+                ("adjoint", "adjoint 65536x1024", lambda: bench_adjoint(5)),
+                ("general_dp", "general chain DP 4096x4096 rows, cols",
+                 lambda: bench_general_dp(10, autotune=not args.no_autotune)),
+                ("batched", "batched 256 images", bench_batched)]
+        pick = None if args.extras == "all" else set(args.extras.split(","))
         try:
-            log("bench: 2D 512x512")
-            extras["tv2d_512"] = bench_tv2d(512, 11, 200, 1e-4, 2000)
-            log("bench: 2D 4096x4096")
-            extras["tv2d_4096"] = bench_tv2d(4096, SEED, None, 1e-4, 500)
-            log("bench: adjoint 65536x1024")
-            extras["adjoint"] = bench_adjoint(5)
-            log("bench: batched 256 images")
-            extras["batched"] = bench_batched()
+            for key, what, fn in runs:
+                if pick is None or key in pick:
+                    log("bench: " + what)
+                    extras[key] = fn()
         except Exception as e:  # report what finished
             extras["error"] = repr(e)
         out["extras"] = extras

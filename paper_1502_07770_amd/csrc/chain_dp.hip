@@ -4,78 +4,103 @@
 // on the segmented kernels of seg_kernels.h.
 //
 // The slopes of the message are the sums Abar_s - Abar_k of the a_i between
-// two steps.  A prefix pass writes Abar_i = a_0 + ... + a_i in FP64, node-major
-// [i][chain], in a fixed summation order (blocks of kPrefixBlock nodes from
-// zero, block totals added left to right), and the DP reads it: every run over
-// a node (halo, segment, repair, fix-up, overflow) sees the same bits, so the
-// segmented output is bit-identical to the sequential one as for a_i = 1.
+// two steps, formed from FP64 prefix sums Abar_i that every run over a node
+// (halo, segment, repair, fix-up, overflow) must reproduce bit for bit.  A
+// prefix pass stores one FP64 anchor per group of kAnchor nodes, the sum of a
+// before the group (blocks of kPrefixBlock nodes summed from zero, block
+// totals added left to right); inside a group Abar_i is the anchor plus the
+// group's a_j up to i, added left to right in FP64.  Runs start at multiples
+// of the tile (a multiple of kAnchor), and a run starting elsewhere rebuilds
+// Abar_{i-1} the same way, so the segmented output stays bit-identical to the
+// sequential one, as for a_i = 1.
 #include "kernels.h"
 #include "seg_kernels.h"
 
 namespace tvc {
 
-// Nodes per block of the prefix pass.
+// Nodes per anchor and per block of the prefix pass.
+constexpr int64_t kAnchor = 8;
 constexpr int64_t kPrefixBlock = 256;
+static_assert(kPrefixBlock % kAnchor == 0, "blocks hold whole anchor groups");
+static_assert(kTile % kAnchor == 0, "runs start on anchor groups");
+constexpr int kAnchorShift = 3;
+static_assert((int64_t(1) << kAnchorShift) == kAnchor, "anchor groups are a power of two");
 
 template <typename T>
 struct GenProb {
     using Tag = double;  // FP64 prefix sums
     static constexpr bool kGen = true;
     struct Params {
-        const T *b, *wm, *wp;
-        const double *abar;  // [n][C]
+        const T *a, *b, *wm, *wp;  // a may be null (a_i = 1)
+        const double *anchor;      // [ceil(n / kAnchor)][C]
         T *x;
         int64_t es, cs, C;
         const int64_t *offsets;
     };
     struct Pre {
-        double s;
-        T b, wm, wp;
+        double s;  // anchor of the node's group
+        T a, b, wm, wp;
     };
     struct SinkPre {};
     // Node offsets here are node indices: the element offset (base + i es) and
-    // the prefix offset (i C + c) both follow from it.
+    // the anchor offset ((i / kAnchor) C + c) both follow from it.
     struct Src {
+        const T *__restrict__ a;
         const T *__restrict__ b;
         const T *__restrict__ wm;
         const T *__restrict__ wp;
-        const double *__restrict__ abar;
+        const double *__restrict__ anchor;
         int64_t base, es, C, c;
         bool vec;  // unit stride and element-aligned: load4 may be used
         __device__ __forceinline__ Src(const Params &p, int64_t base_, int64_t es_, int64_t c_)
-            : b(p.b), wm(p.wm), wp(p.wp), abar(p.abar), base(base_), es(es_), C(p.C), c(c_),
-              vec(es_ == 1 && elem_aligned(p.b + base_) && elem_aligned(p.wm + base_) &&
-                  elem_aligned(p.wp + base_)) {}
+            : a(p.a), b(p.b), wm(p.wm), wp(p.wp), anchor(p.anchor), base(base_), es(es_), C(p.C), c(c_),
+              vec(es_ == 1 && (!p.a || elem_aligned(p.a + base_)) && elem_aligned(p.b + base_) &&
+                  elem_aligned(p.wm + base_) && elem_aligned(p.wp + base_)) {}
+        __device__ __forceinline__ T av(int64_t o) const { return a ? a[o] : (T)1; }
         __device__ __forceinline__ Pre load(int64_t i) const { return load_off(i); }
         __device__ __forceinline__ int64_t off(int64_t i) const { return i; }
         __device__ __forceinline__ int64_t step() const { return 1; }
         __device__ __forceinline__ Pre load_off(int64_t i) const {
             const int64_t o = base + i * es;
             Pre p;
-            p.s = abar[i * C + c];
+            p.s = anchor[(i >> kAnchorShift) * C + c];
+            p.a = av(o);
             p.b = b[o];
             p.wm = wm[o];
             p.wp = wp[o];
             return p;
         }
-        // nodes i .. i+3 (i a multiple of 4, vec set)
+        // nodes i .. i+3 (i a multiple of 4, vec set): one anchor group
         __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
-            T vb[4], vm[4], vp[4];
+            T va[4] = {(T)1, (T)1, (T)1, (T)1}, vb[4], vm[4], vp[4];
+            if (a) vload4(a + base + i, va);
             vload4(b + base + i, vb);
             vload4(wm + base + i, vm);
             vload4(wp + base + i, vp);
+            const double s = anchor[(i >> kAnchorShift) * C + c];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                o[k].s = abar[(i + k) * C + c];
+                o[k].s = s;
+                o[k].a = va[k];
                 o[k].b = vb[k];
                 o[k].wm = vm[k];
                 o[k].wp = vp[k];
             }
         }
         __device__ __forceinline__ T data(const Pre &p) const { return p.b; }
-        __device__ __forceinline__ double prefix(const Pre &p) const { return p.s; }
         __device__ __forceinline__ T wlo(const Pre &p) const { return p.wm; }
         __device__ __forceinline__ T whi(const Pre &p) const { return p.wp; }
+        // Abar_i from Abar_{i-1} (or, at a group start, from the anchor)
+        __device__ __forceinline__ double prefix(const Pre &p, int64_t i, double sprev) const {
+            return ((i & (kAnchor - 1)) == 0 ? p.s : sprev) + (double)p.a;
+        }
+        // Abar_{i-1} for a run starting at node i > 0, summed as prefix() sums it
+        __device__ __forceinline__ double prefix_before(int64_t i) const {
+            const int64_t g = (i - 1) >> kAnchorShift;
+            double s = anchor[g * C + c];
+            for (int64_t j = g * kAnchor; j < i; ++j) s += (double)av(base + j * es);
+            return s;
+        }
     };
     struct Sink {
         T *__restrict__ x;
@@ -114,13 +139,14 @@ struct GenProb {
 };
 
 // ---------------------------------------------------------------------------
-// Prefix pass.  Lane (block j, chain c): the FP64 sum of a over the block
-// (pass 1); one lane per chain turns the block sums into block starts (pass 2);
-// lane (j, c) writes the running sums of its block from its start (pass 3).
+// Prefix pass.  Lane (block j, chain c) sums a over the block in FP64 from
+// zero, writing the sum before each of its anchor groups (pass 1) and the
+// block total; one lane per chain turns the block totals into block starts
+// (pass 2); every anchor then gets its block's start added (pass 3).
 // a == nullptr stands for a_i = 1.
 // ---------------------------------------------------------------------------
 struct PrefixGeom {
-    int64_t C, n, nblk, es, cs;
+    int64_t C, n, ngrp, nblk, es, cs;
     const int64_t *offsets;
 };
 
@@ -138,39 +164,41 @@ __device__ __forceinline__ void chain_extent(const PrefixGeom &g, int64_t c, int
     }
 }
 
-template <typename T, bool kWrite>
-__device__ __forceinline__ double block_scan(const PrefixGeom &g, const T *__restrict__ a, int64_t c, int64_t j,
-                                             double acc, double *__restrict__ abar) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_anchor_blocks(PrefixGeom g, const T *__restrict__ a,
+                                                       double *__restrict__ anchor, double *__restrict__ part) {
+    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (l >= g.nblk * g.C) return;
+    const int64_t c = l % g.C, j = l / g.C;
     int64_t base, es, len;
     chain_extent(g, c, &base, &es, &len);
     const int64_t i0 = j * kPrefixBlock;
     const int64_t i1 = (i0 + kPrefixBlock < len) ? i0 + kPrefixBlock : len;
-    constexpr int U = 8;
-    int64_t i = i0;
-    for (; i + U <= i1; i += U) {
-        double v[U];
+    const bool vec = a && es == 1 && elem_aligned(a + base);
+    double acc = 0.0;
+    for (int64_t i = i0; i < i1; i += kAnchor) {
+        anchor[(i / kAnchor) * g.C + c] = acc;
+        if (i + kAnchor <= i1) {
+            T v[kAnchor];
+            if (vec) {
 #pragma unroll
-        for (int k = 0; k < U; ++k) v[k] = a ? (double)a[base + (i + k) * es] : 1.0;
+                for (int k = 0; k < kAnchor; k += 4) {
+                    T q[4];
+                    vload4(a + base + i + k, q);
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            acc += v[k];
-            if (kWrite) abar[(i + k) * g.C + c] = acc;
+                    for (int m = 0; m < 4; ++m) v[k + m] = q[m];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kAnchor; ++k) v[k] = a ? a[base + (i + k) * es] : (T)1;
+            }
+#pragma unroll
+            for (int k = 0; k < kAnchor; ++k) acc += (double)v[k];
+        } else {
+            for (int64_t k = i; k < i1; ++k) acc += a ? (double)a[base + k * es] : 1.0;
         }
     }
-    for (; i < i1; ++i) {
-        acc += a ? (double)a[base + i * es] : 1.0;
-        if (kWrite) abar[i * g.C + c] = acc;
-    }
-    return acc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_prefix_blocks(PrefixGeom g, const T *__restrict__ a,
-                                                       double *__restrict__ part) {
-    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (l >= g.nblk * g.C) return;
-    const int64_t c = l % g.C, j = l / g.C;
-    part[j * g.C + c] = block_scan<T, false>(g, a, c, j, 0.0, nullptr);
+    part[j * g.C + c] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_prefix_starts(PrefixGeom g, double *__restrict__ part) {
@@ -184,22 +212,21 @@ __global__ __launch_bounds__(256) void k_prefix_starts(PrefixGeom g, double *__r
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_prefix_write(PrefixGeom g, const T *__restrict__ a,
-                                                      const double *__restrict__ part, double *__restrict__ abar) {
+__global__ __launch_bounds__(256) void k_anchor_add(PrefixGeom g, const double *__restrict__ part,
+                                                    double *__restrict__ anchor) {
     const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (l >= g.nblk * g.C) return;
-    const int64_t c = l % g.C, j = l / g.C;
-    block_scan<T, true>(g, a, c, j, part[j * g.C + c], abar);
+    if (l >= g.ngrp * g.C) return;
+    const int64_t c = l % g.C, q = l / g.C;
+    anchor[l] += part[(q / (kPrefixBlock / kAnchor)) * g.C + c];
 }
 
-// Workspace: [prefix sums n x C doubles][block sums nblk x C doubles][segments].
+// Workspace: [anchors ngrp x C doubles][block sums nblk x C doubles][segments].
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 template <typename T>
 size_t chain_dp_ws_bytes(int64_t C, int64_t n, size_t seg_bytes) {
-    const int64_t nblk = (n + kPrefixBlock - 1) / kPrefixBlock;
-    return al256(sizeof(double) * (size_t)(n * C)) + al256(sizeof(double) * (size_t)(nblk * C)) + seg_bytes;
+    const int64_t ngrp = (n + kAnchor - 1) / kAnchor, nblk = (n + kPrefixBlock - 1) / kPrefixBlock;
+    return al256(sizeof(double) * (size_t)(ngrp * C)) + al256(sizeof(double) * (size_t)(nblk * C)) + seg_bytes;
 }
 
 template <typename T>
@@ -207,18 +234,19 @@ hipError_t launch_chain_dp(const ChainBatch &bt, const T *a, const T *b, const T
                            void *workspace, const SegPlan &plan, hipStream_t stream) {
     const int64_t C = bt.num_chains, n = bt.n;
     if (C <= 0) return hipSuccess;
-    const int64_t nblk = (n + kPrefixBlock - 1) / kPrefixBlock;
+    const int64_t ngrp = (n + kAnchor - 1) / kAnchor, nblk = (n + kPrefixBlock - 1) / kPrefixBlock;
     char *p = (char *)workspace;
-    double *abar = (double *)p;
-    p += al256(sizeof(double) * (size_t)(n * C));
+    double *anchor = (double *)p;
+    p += al256(sizeof(double) * (size_t)(ngrp * C));
     double *part = (double *)p;
     p += al256(sizeof(double) * (size_t)(nblk * C));
-    const PrefixGeom g{C, n, nblk, bt.es, bt.cs, bt.offsets};
-    const unsigned pb = (unsigned)((nblk * C + 255) / 256);
-    hipLaunchKernelGGL((k_prefix_blocks<T>), dim3(pb), dim3(256), 0, stream, g, a, part);
+    const PrefixGeom g{C, n, ngrp, nblk, bt.es, bt.cs, bt.offsets};
+    hipLaunchKernelGGL((k_anchor_blocks<T>), dim3((unsigned)((nblk * C + 255) / 256)), dim3(256), 0, stream, g, a,
+                       anchor, part);
     hipLaunchKernelGGL(k_prefix_starts, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, stream, g, part);
-    hipLaunchKernelGGL((k_prefix_write<T>), dim3(pb), dim3(256), 0, stream, g, a, part, abar);
-    typename GenProb<T>::Params pp{b, wm, wp, abar, x, bt.es, bt.cs, C, bt.offsets};
+    hipLaunchKernelGGL(k_anchor_add, dim3((unsigned)((ngrp * C + 255) / 256)), dim3(256), 0, stream, g, part,
+                       anchor);
+    typename GenProb<T>::Params pp{a, b, wm, wp, anchor, x, bt.es, bt.cs, C, bt.offsets};
     return seg_run<T, GenProb<T>, kTile>(p, C, n, plan, pp, stream);
 }
 

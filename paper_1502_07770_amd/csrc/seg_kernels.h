@@ -35,9 +35,10 @@
 //               the segment's right end.
 // The output is bit-identical to running the DP sequentially per chain.
 //
-// The deque is a ring of packed (lambda, tag) entries in LDS, stored twice so
-// the entries next to either end lie at fixed offsets from one address, with
-// the front and back entries cached in registers.  Loads of node data run P
+// The deque is a ring of packed (lambda, tag) entries in LDS whose first W
+// slots are also stored past its end, so the entries next to either end lie at
+// fixed offsets from one address, with the front and back entries cached in
+// registers.  Loads of node data run P
 // nodes ahead into registers (four per 16-byte load on unit-stride chains), so
 // each memory wait covers requests issued a tile earlier.
 #pragma once
@@ -139,18 +140,22 @@ template <typename T, int K, typename G>
 __device__ __forceinline__ bool saved_equal(const CRing<T, K, G> &R, const Ent<T, G> *src, int64_t stride);
 
 // ---------------------------------------------------------------------------
-// LDS ring of K entries per lane with register-cached ends.  Every entry is
-// stored twice, at slot m and at slot m + K, so the first W and the last W
-// entries of the deque lie at fixed offsets from one base address each: the
-// hot step needs no per-read index arithmetic and never wraps.  Slots are
-// lane-interleaved (slot m of lane l at m * 64 + l), so the 64 lanes of a
-// wave hit distinct banks.
+// LDS ring of K entries per lane with register-cached ends.  The first W
+// slots are stored twice, at slot m and at slot m + K, so the first W and the
+// last W entries of the deque lie at fixed offsets from one base address each
+// (a window starting at slot m < K reads slots m .. m + W - 2 < K + W - 1): the
+// hot step needs no per-read index arithmetic and never wraps, and a lane
+// needs K + W slots rather than 2K.  Slots are lane-interleaved (slot m of lane
+// l at m * 64 + l), so the 64 lanes of a wave hit distinct banks.
 // ---------------------------------------------------------------------------
 template <typename T, int K, typename G>
 struct CRing {
     static_assert((K & (K - 1)) == 0, "ring size must be a power of two");
+    static_assert(kScanWindow <= K, "the copied slots are ring slots");
+    // slot rows of the per-wave LDS array (64 entries each)
+    static constexpr int kRows = K + kScanWindow;
     using E = Ent<T, G>;
-    E *col;  // this lane's column: slot m at col[m * 64], its copy at col[(m + K) * 64]
+    E *col;  // this lane's column: slot m at col[m * 64], the copy of m < W at col[(m + K) * 64]
     int head, size;
     E f, b;  // front / back copies (valid when size >= 1)
 
@@ -162,7 +167,7 @@ struct CRing {
     __device__ __forceinline__ E ld(int j) const { return col[((head + j) & (K - 1)) * 64]; }
     __device__ __forceinline__ void put_slot(int m, const E &e) const {
         col[m * 64] = e;
-        col[(m + K) * 64] = e;
+        col[(m < kScanWindow ? m + K : m) * 64] = e;  // slots past W: the same slot again
     }
     __device__ __forceinline__ void set(int j, const E &e) const { put_slot((head + j) & (K - 1), e); }
     // Order-sensitive 32-bit hash of the breakpoints and tags (the back tag is
@@ -367,7 +372,8 @@ __device__ __forceinline__ bool dp_step_win(CRing<T, K, G> &R, const StepIn<T, G
 // declares its model: Tag = the tag type, kGen = general a_i and asymmetric
 // weights.  With kGen false Src provides data (b_i = y_i) and weight (w_i of
 // the leaving edge, w^- = -w_i, w^+ = w_i); with kGen true it provides data,
-// prefix (Abar_i, FP64), wlo / whi (w^-, w^+ of the leaving edge).
+// wlo / whi (w^-, w^+ of the leaving edge), prefix(pv, i, Abar_{i-1}) = Abar_i
+// and prefix_before(i) = Abar_{i-1} (FP64; equal bits on every run).
 //
 // What a step needs from the node before it.
 template <typename T, typename G, bool kGen> struct Carry;
@@ -393,7 +399,7 @@ __device__ __forceinline__ CarryOf<T, Prob> carry_before(const typename Prob::Sr
         cy.hip = (T)0;
         if (i > 0) {
             const auto pv = src.load(i - 1);
-            cy.sprev = src.prefix(pv);
+            cy.sprev = src.prefix_before(i);
             cy.lop = src.wlo(pv);
             cy.hip = src.whi(pv);
         }
@@ -412,7 +418,7 @@ __device__ __forceinline__ StepIn<T, typename Prob::Tag> step_in(const typename 
     in.yi = src.data(pv);
     if constexpr (Prob::kGen) {
         const T wl = src.wlo(pv), wh = src.whi(pv);
-        in.sf = src.prefix(pv);
+        in.sf = src.prefix(pv, i, cy.sprev);
         in.sprev = cy.sprev;
         in.lop = cy.lop;
         in.hip = cy.hip;
@@ -684,7 +690,7 @@ __device__ __forceinline__ bool meets_checkpoint(const SegWs<T, G> &ws, const CR
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob::Params pp) {
-    __shared__ EntOf<T, Prob> s_ent[2 * K * 64];
+    __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g == 0) *ws.ovf_count = 0;  // consumed by k_seg_fix / k_seg_ovf after this kernel
@@ -729,7 +735,7 @@ __global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Prob::Params pp) {
-    __shared__ EntOf<T, Prob> s_ent[2 * K * 64];
+    __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g >= (ws.S - 1) * ws.C) return;
@@ -838,7 +844,7 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
 // ---------------------------------------------------------------------------
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_fix(WsOf<T, Prob> ws, typename Prob::Params pp) {
-    __shared__ EntOf<T, Prob> s_ent[2 * K * 64];
+    __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
     const int lane = threadIdx.x;
     const int64_t c = (int64_t)blockIdx.x * 64 + lane;
     if (c >= ws.C) return;
@@ -919,13 +925,14 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
 // deque storage l).  Both paths compute the same bits as the segmented one.
 // ---------------------------------------------------------------------------
 template <class E> struct OvfRing {
-    static constexpr int K = 65536 / (2 * 64 * (int)sizeof(E));
+    static constexpr int fit(int k) { return (k + kScanWindow) * 64 * (int)sizeof(E) <= 65536 ? k : fit(k / 2); }
+    static constexpr int K = fit(256);
 };
 
 template <typename T, class Prob>
 __global__ __launch_bounds__(64) void k_seg_ovf(WsOf<T, Prob> ws, typename Prob::Params pp) {
     constexpr int KB = OvfRing<EntOf<T, Prob>>::K;
-    __shared__ EntOf<T, Prob> s_big[2 * KB * 64];
+    __shared__ EntOf<T, Prob> s_big[CRing<T, KB, typename Prob::Tag>::kRows * 64];
     const int lane = threadIdx.x;
     const int64_t l = (int64_t)blockIdx.x * 64 + lane;
     const int64_t cnt = *ws.ovf_count;
