@@ -74,6 +74,14 @@ def _load():
     lib.orc_tv2d.restype = I64
     lib.orc_rof2d_objective.argtypes = [I64, I64, P, D, P]
     lib.orc_rof2d_objective.restype = D
+    lib.orc_chain_pq.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_chain_pq.restype = ctypes.c_int
+    lib.orc_chain_pq_brute.argtypes = [I64, P, P, P, P, P, P, P]
+    lib.orc_chain_pq_brute.restype = ctypes.c_int
+    lib.orc_pq_objective.argtypes = [I64, P, P, P, P, P, P, P]
+    lib.orc_pq_objective.restype = D
+    lib.orc_chain_prox_l1.argtypes = [I64, I64, I64, I64, P, P, P, D, P, D, P, P, ctypes.c_int]
+    lib.orc_chain_prox_l1.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -139,6 +147,76 @@ def chain_prox(y, w=None, w_scalar: float = 0.0, threads: int = 0, counts: bool 
     out = x.reshape(-1) if squeeze else x
     if counts:
         stats = np.array([[c.pushes, c.pops, c.max_breakpoints] for c in cnt[:C]], dtype=np.int64)
+        return out, stats
+    return out
+
+
+def chain_pq(a, b, c, d, wm, wp):
+    """Sec. 4.2 DP on one chain with piecewise-quadratic unaries
+    f_i = a_i x^2/2 - b_i x + c_i |x - d_i| and edge slopes (wm[e], wp[e]) on
+    edge (e, e+1).  Returns (x, lam_lo, lam_hi, counts)."""
+    a, b, c, d = _f64(a), _f64(b), _f64(c), _f64(d)
+    n = a.shape[0]
+    assert b.shape == c.shape == d.shape == (n,)
+    wm_p = np.concatenate([_f64(wm).reshape(-1)[: max(n - 1, 0)], [0.0]])
+    wp_p = np.concatenate([_f64(wp).reshape(-1)[: max(n - 1, 0)], [0.0]])
+    x = np.empty(n)
+    llo = np.empty(max(n, 1))
+    lhi = np.empty(max(n, 1))
+    buf = np.empty(3 * (3 * n + 4))
+    cnt = _Counts()
+    rc = _load().orc_chain_pq(n, _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(wm_p), _ptr(wp_p), _ptr(x),
+                              _ptr(llo), _ptr(lhi), _ptr(buf), ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError("orc_chain_pq failed")
+    return x, llo[: n - 1].copy(), lhi[: n - 1].copy(), dict(
+        pushes=cnt.pushes, pops=cnt.pops, max_breakpoints=cnt.max_breakpoints)
+
+
+def chain_pq_brute(a, b, c, d, wm, wp):
+    """Brute-force minimiser of the Sec. 4.2 chain objective for n <= 6."""
+    a, b, c, d = _f64(a), _f64(b), _f64(c), _f64(d)
+    n = a.shape[0]
+    wm_p = np.concatenate([_f64(wm).reshape(-1)[: max(n - 1, 0)], [0.0]])
+    wp_p = np.concatenate([_f64(wp).reshape(-1)[: max(n - 1, 0)], [0.0]])
+    x = np.empty(n)
+    rc = _load().orc_chain_pq_brute(n, _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(wm_p), _ptr(wp_p), _ptr(x))
+    if rc != 0:
+        raise ValueError("orc_chain_pq_brute: n must be in [1, 6]")
+    return x
+
+
+def pq_objective(a, b, c, d, wm, wp, x) -> float:
+    """Objective of the Sec. 4.2 chain problem at x."""
+    a, b, c, d, x = _f64(a), _f64(b), _f64(c), _f64(d), _f64(x)
+    n = a.shape[0]
+    wm_p = np.concatenate([_f64(wm).reshape(-1)[: max(n - 1, 0)], [0.0]])
+    wp_p = np.concatenate([_f64(wp).reshape(-1)[: max(n - 1, 0)], [0.0]])
+    return float(_load().orc_pq_objective(n, _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(wm_p), _ptr(wp_p),
+                                          _ptr(x)))
+
+
+def chain_prox_l1(y, d, w=None, w_scalar: float = 0.0, c=None, c_scalar: float = 1.0, threads: int = 0,
+                  counts: bool = False):
+    """TV-l1 chain prox for a batch of chains (rows of y): argmin sum w|dx| +
+    sum (x - y)^2/2 + sum c |x - d|.  w, c: arrays shaped like y (slot i of w =
+    edge (i, i+1), the last slot ignored) or None for the scalars."""
+    y = _f64(y)
+    squeeze = y.ndim == 1
+    y2 = y.reshape(1, -1) if squeeze else y
+    C, n = y2.shape
+    d2 = _f64(d).reshape(C, n)
+    w2 = None if w is None else _f64(w).reshape(C, n)
+    c2 = None if c is None else _f64(c).reshape(C, n)
+    x = np.empty_like(y2)
+    cnt = (_Counts * max(C, 1))() if counts else None
+    rc = _load().orc_chain_prox_l1(C, n, 1, n, _ptr(y2), _ptr(d2), _ptr(w2), float(w_scalar), _ptr(c2),
+                                   float(c_scalar), _ptr(x), cnt, int(threads))
+    if rc != 0:
+        raise ValueError("orc_chain_prox_l1: invalid argument")
+    out = x.reshape(-1) if squeeze else x
+    if counts:
+        stats = np.array([[q.pushes, q.pops, q.max_breakpoints] for q in cnt[:C]], dtype=np.int64)
         return out, stats
     return out
 

@@ -22,6 +22,15 @@
  *   orc_chain_adjoint   -- gradient of <g, x(y,w)> for the chain prox, from the
  *                          optimality conditions of eq. (1D-ROF) and the clip
  *                          structure of the backward pass of Algorithm 2.
+ *   orc_chain_pq        -- Sec. 4.2, piecewise-quadratic unaries
+ *                          a_i x^2/2 - b_i x + c_i |x - d_i| on a chain (the
+ *                          unaries of the TV-l1 primal prox, eq. (prox-pq)), with
+ *                          the breakpoint multiset kept as a sorted array.
+ *   orc_chain_pq_brute  -- brute force for the same objective on tiny chains
+ *                          (n <= 6): every edge and node state, independent of
+ *                          the DP.
+ *   orc_chain_prox_l1   -- the TV-l1 chain prox x = argmin sum w|dx| + sum
+ *                          (x - y)^2/2 + sum c |x - d|, batched over chains.
  *
  * Conventions: node indices are 0-based here (the paper's node i is index i-1);
  * edge e joins nodes e and e+1, so a chain of n nodes has n-1 edge weights.
@@ -516,4 +525,304 @@ int orc_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 4.2: piecewise-quadratic unaries on a chain.                         */
+/*   f_i(x) = a_i x^2 / 2 - b_i x + c_i |x - d_i|   (a_i > 0, c_i >= 0)       */
+/*   f_e(z) = w^-_e z (z < 0), w^+_e z (z >= 0), z = x_{e+1} - x_e.           */
+/* The derivative h of the current message is non-decreasing and piecewise   */
+/* linear with jumps; it is kept as its left end (al, bl) (h(z) = al z + bl  */
+/* as z -> -inf), its right end (ar, br), and the multiset S of breakpoints  */
+/* (lam, da, db) sorted by lam: right of lam the linear piece changes by     */
+/* (da, db).  h is left-continuous: h(z) uses the breakpoints with lam < z.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double *lam, *da, *db;
+    int64_t t;
+} pq_set;
+
+static void pq_insert(pq_set *S, int64_t pos, double lam, double da, double db)
+{
+    memmove(S->lam + pos + 1, S->lam + pos, sizeof(double) * (size_t)(S->t - pos));
+    memmove(S->da + pos + 1, S->da + pos, sizeof(double) * (size_t)(S->t - pos));
+    memmove(S->db + pos + 1, S->db + pos, sizeof(double) * (size_t)(S->t - pos));
+    S->lam[pos] = lam;
+    S->da[pos] = da;
+    S->db[pos] = db;
+    S->t++;
+}
+
+static void pq_erase_front(pq_set *S, int64_t k)
+{
+    if (k <= 0) return;
+    memmove(S->lam, S->lam + k, sizeof(double) * (size_t)(S->t - k));
+    memmove(S->da, S->da + k, sizeof(double) * (size_t)(S->t - k));
+    memmove(S->db, S->db + k, sizeof(double) * (size_t)(S->t - k));
+    S->t -= k;
+}
+
+/* The point where h crosses level v from below: the z with h(z) <= v <= h(z+)
+   (unique: every linear piece between the ends has slope > 0).  Scans from
+   the left; returns the number of breakpoints passed (they lie left of the
+   crossing), the linear piece (pa, pb) in force just left of the crossing,
+   and in *jump whether the crossing is the jump of breakpoint `passed`. */
+static double pq_cross_left(const pq_set *S, double al, double bl, double v, int64_t *passed,
+                            double *pa, double *pb, int *jump)
+{
+    double A = al, B = bl;
+    int64_t j = 0;
+    double z;
+    *jump = 0;
+    for (;;) {
+        if (j == S->t) { z = (v - B) / A; break; }
+        const double l = S->lam[j];
+        const double vl = A * l + B;            /* h just left of lam_j */
+        if (vl >= v) {                           /* inside the piece left of lam_j */
+            z = (v - B) / A;
+            if (z > l) z = l;
+            if (j > 0 && z < S->lam[j - 1]) z = S->lam[j - 1];
+            break;
+        }
+        const double vr = vl + S->da[j] * l + S->db[j];   /* h just right of lam_j */
+        if (vr >= v) { z = l; *jump = 1; break; }  /* the jump at lam_j crosses v */
+        A += S->da[j];
+        B += S->db[j];
+        ++j;
+    }
+    *passed = j;
+    *pa = A;
+    *pb = B;
+    return z;
+}
+
+/* Mirror image from the right: the z with h(z) <= v <= h(z+), scanning from
+   the right end (ar, br); returns the breakpoints passed (right of z), the
+   piece just right of the crossing, and whether it is the jump of breakpoint
+   t - 1 - passed. */
+static double pq_cross_right(const pq_set *S, double ar, double br, double v, int64_t *passed,
+                             double *pa, double *pb, int *jump)
+{
+    double A = ar, B = br;
+    int64_t j = S->t - 1, k = 0;
+    double z;
+    *jump = 0;
+    for (;;) {
+        if (j < 0) { z = (v - B) / A; break; }
+        const double l = S->lam[j];
+        const double vr = A * l + B;            /* h just right of lam_j */
+        if (vr <= v) {                           /* inside the piece right of lam_j */
+            z = (v - B) / A;
+            if (z < l) z = l;
+            if (j + 1 < S->t && z > S->lam[j + 1]) z = S->lam[j + 1];
+            break;
+        }
+        const double vl = vr - (S->da[j] * l + S->db[j]);  /* h just left of lam_j */
+        if (vl <= v) { z = l; *jump = 1; break; }
+        A -= S->da[j];
+        B -= S->db[j];
+        --j;
+        ++k;
+    }
+    *passed = k;
+    *pa = A;
+    *pb = B;
+    return z;
+}
+
+/* lam_lo / lam_hi receive lambda^-_{i,i+1} / lambda^+_{i,i+1}; x the
+   minimiser; buf holds 3 (3n + 4) doubles.  Returns 0, or -1 on n < 1. */
+int orc_chain_pq(int64_t n, const double *a, const double *b, const double *c, const double *d,
+                 const double *wm, const double *wp, double *x, double *lam_lo, double *lam_hi,
+                 double *buf, orc_counts *cnt)
+{
+    if (n < 1) return -1;
+    const int64_t cap = 3 * n + 4;
+    pq_set S = {buf, buf + cap, buf + 2 * cap, 0};
+    double al = 0.0, bl = 0.0, ar = 0.0, br = 0.0;  /* the zero message into node 0 */
+    if (cnt) { cnt->pushes = 0; cnt->pops = 0; cnt->max_breakpoints = 0; }
+    for (int64_t i = 0; i < n; ++i) {
+        /* transformation (a): add g_i = a_i z - b_i + c_i sign(z - d_i) */
+        al += a[i];
+        bl += -b[i] - c[i];
+        ar += a[i];
+        br += -b[i] + c[i];
+        if (c[i] > 0.0) {
+            int64_t pos = S.t;  /* after every breakpoint with lam <= d_i */
+            int64_t lo_i = 0, hi_i = S.t;
+            while (lo_i < hi_i) {
+                const int64_t mid = (lo_i + hi_i) / 2;
+                if (S.lam[mid] <= d[i]) lo_i = mid + 1; else hi_i = mid;
+            }
+            pos = lo_i;
+            pq_insert(&S, pos, d[i], 0.0, 2.0 * c[i]);
+            if (cnt) cnt->pushes++;
+        }
+        if (i == n - 1) {  /* root: the zero of h */
+            int64_t k;
+            double pa, pb;
+            int jump;
+            x[i] = pq_cross_left(&S, al, bl, 0.0, &k, &pa, &pb, &jump);
+            break;
+        }
+        /* transformation (b): clip to [w^-_i, w^+_i].  Left: h becomes flat at
+           lo left of lm.  Where lm is the jump of a breakpoint, that
+           breakpoint's increment is updated (merged with the new one), so
+           every breakpoint keeps a non-negative jump in value. */
+        const double lo = wm[i], hi = wp[i];
+        int64_t k;
+        double pa, pb;
+        int jump;
+        const double lm = pq_cross_left(&S, al, bl, lo, &k, &pa, &pb, &jump);
+        double nda = pa, ndb = pb - lo;
+        if (jump) {
+            nda += S.da[k];
+            ndb += S.db[k];
+        }
+        pq_erase_front(&S, k + jump);
+        if (cnt) cnt->pops += k;
+        pq_insert(&S, 0, lm, nda, ndb);
+        al = 0.0;
+        bl = lo;
+        /* right: flat at hi right of lp */
+        const double lp = pq_cross_right(&S, ar, br, hi, &k, &pa, &pb, &jump);
+        nda = -pa;
+        ndb = hi - pb;
+        if (jump) {
+            nda += S.da[S.t - 1 - k];
+            ndb += S.db[S.t - 1 - k];
+        }
+        S.t -= k + jump;
+        pq_insert(&S, S.t, lp, nda, ndb);
+        ar = 0.0;
+        br = hi;
+        lam_lo[i] = lm;
+        lam_hi[i] = lp < lm ? lm : lp;
+        if (cnt) {
+            cnt->pushes += 2;
+            cnt->pops += k;
+            if (S.t > cnt->max_breakpoints) cnt->max_breakpoints = S.t;
+        }
+    }
+    /* backward pass of Algorithm 2 */
+    for (int64_t i = n - 2; i >= 0; --i) {
+        double v = x[i + 1];
+        if (v < lam_lo[i]) v = lam_lo[i];
+        if (v > lam_hi[i]) v = lam_hi[i];
+        x[i] = v;
+    }
+    return 0;
+}
+
+double orc_pq_objective(int64_t n, const double *a, const double *b, const double *c, const double *d,
+                        const double *wm, const double *wp, const double *x)
+{
+    double f = 0.0;
+    for (int64_t i = 0; i < n; ++i) f += 0.5 * a[i] * x[i] * x[i] - b[i] * x[i] + c[i] * fabs(x[i] - d[i]);
+    for (int64_t e = 0; e + 1 < n; ++e) {
+        const double z = x[e + 1] - x[e];
+        f += (z < 0.0) ? wm[e] * z : wp[e] * z;
+    }
+    return f;
+}
+
+/* Brute force over every edge state (fused / up / down) and node state
+   (below d_i / at d_i / above d_i) for n <= 6.  For each pattern the runs of
+   fused nodes take one value: d of the first node of the run that is "at d",
+   else the stationary point sum(b - c s - q_in + q_out) / sum(a) of the run
+   (s = -1 below, +1 above; q the edge slopes entering / leaving the run).
+   Every candidate is a feasible point and the optimum's own pattern
+   reproduces it, so the best true objective over all candidates is the
+   minimum. */
+int orc_chain_pq_brute(int64_t n, const double *a, const double *b, const double *c, const double *d,
+                       const double *wm, const double *wp, double *x_best)
+{
+    if (n < 1 || n > 6) return -1;
+    const int64_t m = n - 1;
+    int64_t ne = 1, nn = 1;
+    for (int64_t e = 0; e < m; ++e) ne *= 3;
+    for (int64_t i = 0; i < n; ++i) nn *= 3;
+    double best = INFINITY, xc[6];
+    int es[6], ns[6];
+    for (int64_t ce = 0; ce < ne; ++ce) {
+        int64_t t = ce;
+        for (int64_t e = 0; e < m; ++e) { es[e] = (int)(t % 3); t /= 3; }
+        for (int64_t cn = 0; cn < nn; ++cn) {
+            int64_t u = cn;
+            for (int64_t i = 0; i < n; ++i) { ns[i] = (int)(u % 3); u /= 3; }
+            int64_t start = 0;
+            while (start < n) {
+                int64_t end = start;
+                while (end < m && es[end] == 0) ++end;   /* run [start..end] */
+                double qin = 0.0, qout = 0.0;
+                if (start > 0) qin = (es[start - 1] == 1) ? wp[start - 1] : wm[start - 1];
+                if (end < m) qout = (es[end] == 1) ? wp[end] : wm[end];
+                double A = 0.0, B = 0.0, val = NAN;
+                for (int64_t i = start; i <= end; ++i) {
+                    if (ns[i] == 1 && isnan(val)) val = d[i];
+                    A += a[i];
+                    B += b[i] - c[i] * (ns[i] == 0 ? -1.0 : 1.0);
+                }
+                if (isnan(val)) val = (B - qin + qout) / A;
+                for (int64_t i = start; i <= end; ++i) xc[i] = val;
+                start = end + 1;
+            }
+            const double f = orc_pq_objective(n, a, b, c, d, wm, wp, xc);
+            if (f < best) {
+                best = f;
+                for (int64_t i = 0; i < n; ++i) x_best[i] = xc[i];
+            }
+        }
+    }
+    return 0;
+}
+
+/* TV-l1 chain prox x = argmin sum_e w_e |x_{e+1} - x_e| + sum_i (x_i - y_i)^2 / 2
+   + sum_i c_i |x_i - d_i| (orc_chain_pq with a = 1, b = y, w^- = -w, w^+ = w),
+   batched over strided chains.  w and c are per-node arrays in y's layout or
+   NULL (use w_scalar / c_scalar).  Returns 0, or -1 on a bad argument. */
+int orc_chain_prox_l1(int64_t num_chains, int64_t n, int64_t elem_stride, int64_t chain_stride,
+                      const double *y, const double *d, const double *w, double w_scalar,
+                      const double *c, double c_scalar, double *x, orc_counts *counts, int threads)
+{
+    if (n < 1 || num_chains < 0) return -1;
+    if (!w && !(w_scalar >= 0.0)) return -1;
+    if (!c && !(c_scalar >= 0.0)) return -1;
+    int bad = 0;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel
+#endif
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)(9 * n + 12 + 10 * n));
+        if (!buf) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            bad = 1;
+        } else {
+            double *a = buf + 9 * n + 12, *b = a + n, *cc = b + n, *dd = cc + n, *wm = dd + n, *wp = wm + n;
+            double *xc = wp + n, *llo = xc + n, *lhi = llo + n;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+            for (int64_t ch = 0; ch < num_chains; ++ch) {
+                const int64_t base = ch * chain_stride;
+                for (int64_t i = 0; i < n; ++i) {
+                    const int64_t o = base + i * elem_stride;
+                    a[i] = 1.0;
+                    b[i] = y[o];
+                    dd[i] = d[o];
+                    cc[i] = c ? c[o] : c_scalar;
+                    const double we = (i + 1 < n) ? (w ? w[o] : w_scalar) : 0.0;
+                    wm[i] = -we;
+                    wp[i] = we;
+                }
+                orc_chain_pq(n, a, b, cc, dd, wm, wp, xc, llo, lhi, buf, counts ? counts + ch : NULL);
+                for (int64_t i = 0; i < n; ++i) x[base + i * elem_stride] = xc[i];
+            }
+            free(buf);
+        }
+    }
+    return bad ? -1 : 0;
 }

@@ -11,6 +11,11 @@ kernels: they restate what the problem statement fixes.
 * ``dual_box_solution``: the chain (or 2D) prox via its dual, a box-constrained
   least-squares problem min |D^T p - y|^2, |p_e| <= w_e, solved by scipy's
   bounded least squares; x = y - D^T p.
+* ``kkt_pq``: optimality certificate for the chain with unaries
+  a_i x^2/2 - b_i x + c_i |x - d_i| and edge slopes w^-_e <= w^+_e: the edge
+  subgradients q_e must satisfy q_e = q_{e-1} + a_i x_i - b_i + c_i u_i with
+  u_i in the subdifferential of |x_i - d_i| and q_e in that of the edge term,
+  and q_{n-1} = 0; the feasible q_e form an interval, propagated node by node.
 """
 from __future__ import annotations
 
@@ -90,3 +95,37 @@ def dual_box_solution_2d(f, lam):
     res = lsq_linear(A, f.reshape(-1), bounds=(-lam * np.ones(m), lam * np.ones(m)),
                      method="bvls", tol=1e-15, max_iter=20000)
     return (f.reshape(-1) - A @ res.x).reshape(H, W)
+
+
+def kkt_pq(a, b, c, d, wm, wp, x, tol: float):
+    """Largest violation of the optimality conditions of one chain (see the
+    module docstring).  Values within ``tol`` of a kink (x_i = d_i, or
+    x_{e+1} = x_e) count as on it; a return value near 0 certifies x."""
+    a, b, c, d, x = (np.asarray(v, dtype=np.float64) for v in (a, b, c, d, x))
+    wm = np.asarray(wm, dtype=np.float64)
+    wp = np.asarray(wp, dtype=np.float64)
+    n = x.shape[0]
+    lo = hi = 0.0
+    worst = 0.0
+    for i in range(n):
+        r = a[i] * x[i] - b[i]
+        if abs(x[i] - d[i]) <= tol:
+            ul, uh = -1.0, 1.0
+        else:
+            ul = uh = float(np.sign(x[i] - d[i]))
+        ql, qh = lo + r + c[i] * ul, hi + r + c[i] * uh
+        if i == n - 1:
+            el = eh = 0.0
+        else:
+            z = x[i + 1] - x[i]
+            if z > tol:
+                el = eh = wp[i]
+            elif z < -tol:
+                el = eh = wm[i]
+            else:
+                el, eh = wm[i], wp[i]
+        lo, hi = max(ql, el), min(qh, eh)
+        if lo > hi:  # empty: record the gap and continue from its midpoint
+            worst = max(worst, lo - hi)
+            lo = hi = 0.5 * (lo + hi)
+    return worst
