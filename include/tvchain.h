@@ -175,6 +175,29 @@ tv_status tv_chain_dp_autotune(const tv_chain_layout *layout, tv_dtype dtype, co
                                void *workspace, size_t workspace_bytes, hipStream_t stream,
                                tv_tuning_result *chosen);
 
+/* ---- TV-l1 chain prox (Sec. 4.2, piecewise-quadratic unaries) ----
+ *
+ *     x = argmin_x  sum_e w_e |x_{e+1} - x_e| + sum_i (x_i - y_i)^2 / 2 + sum_i c_i |x_i - d_i| ,
+ *
+ * the chain subproblem of the TV-l1 primal prox eq. (prox-pq) with its
+ * quadratic weight normalised to 1 (prox_{tau (w TV + |. - f|)}(xi) is this with
+ * y = xi, d = f, c = tau, w = tau w).  Exact: the Sec. 4.2 message passing with
+ * the breakpoint multiset of the message derivative (position, slope tag, jump)
+ * kept sorted per chain in on-chip memory, one chain per lane; chains whose set
+ * outgrows it are redone with the set in the workspace.  Slopes are integers,
+ * so lengths must be below 2^24 for TV_F32.
+ *  y, d  : per-node inputs in the layout (uniform or CSR offsets).
+ *  w     : per-edge weights in the layout (slot of node i = edge (i, i+1)), or
+ *          NULL to use w_scalar (>= 0, finite, else TV_ERR_INVALID_ARG).
+ *  c     : per-node data weights c_i >= 0 in the layout, or NULL to use c_scalar
+ *          (>= 0, finite).  Per-node values of w and c are not checked.
+ *  x     : output in the layout; must not overlap y, d, w or c (rejected where
+ *          the host can see it). */
+size_t tv_chain_prox_l1_workspace(const tv_chain_layout *layout, tv_dtype dtype);
+tv_status tv_chain_prox_l1(const tv_chain_layout *layout, tv_dtype dtype, const void *y, const void *d,
+                           const void *w, double w_scalar, const void *c, double c_scalar, void *x,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
 size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);
 

@@ -93,6 +93,9 @@ _SIG = {
     "tv_chain_prox_autotune": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                               _P, _P]),
     "tv_autotune_clear": (None, []),
+    "tv_chain_prox_l1_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
+    "tv_chain_prox_l1": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, ctypes.c_double, _P,
+                                        _P, ctypes.c_size_t, _P]),
     "tv_chain_dp_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "tv_chain_dp": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "tv_chain_dp_autotune": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
@@ -303,6 +306,46 @@ def chain_dp(b: torch.Tensor, wm: torch.Tensor, wp: torch.Tensor, a: Optional[to
         out.copy_(res_x)
         res_x = out
     return (res_x, chosen) if autotune else res_x
+
+
+def chain_prox_l1(y: torch.Tensor, d: torch.Tensor, w: Union[float, torch.Tensor] = 0.0,
+                  c: Union[float, torch.Tensor] = 1.0, dim: int = -1,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """TV-l1 chain prox (tv_chain_prox_l1) of every chain along ``dim``:
+    argmin sum w|x_{i+1} - x_i| + sum (x - y)^2/2 + sum c|x - d|.  ``w`` and
+    ``c`` are floats or tensors shaped like ``y`` (w at node i is the weight of
+    edge (i, i+1))."""
+    _require_gpu(y, d)
+    lib = load()
+    if y.numel() == 0:
+        return torch.empty_like(y) if out is None else out
+    ts = [y, d] + [t for t in (w, c) if isinstance(t, torch.Tensor)]
+    for t in ts:
+        _require_gpu(t)
+        if t.shape != y.shape or t.dtype != y.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "d, w and c must match y's shape and dtype")
+    if any(t.stride() != y.stride() for t in ts):
+        y, d = y.contiguous(), d.contiguous()
+        w = w.contiguous() if isinstance(w, torch.Tensor) else w
+        c = c.contiguous() if isinstance(c, torch.Tensor) else c
+    yv, lay, restore = _chain_view(y, dim)
+    dv = _chain_view(d, dim)[0]
+    wv = _chain_view(w, dim)[0] if isinstance(w, torch.Tensor) else None
+    cv = _chain_view(c, dim)[0] if isinstance(c, torch.Tensor) else None
+    ws_ = 0.0 if wv is not None else float(w)
+    cs_ = 0.0 if cv is not None else float(c)
+    xv = torch.empty_like(yv)
+    code = _dtype_code(y)
+    nbytes = lib.tv_chain_prox_l1_workspace(ctypes.byref(lay), code)
+    ws = _workspace(nbytes, y.device)
+    st = lib.tv_chain_prox_l1(ctypes.byref(lay), code, _ptr(yv), _ptr(dv), _ptr(wv), ws_, _ptr(cv), cs_, _ptr(xv),
+                              _ptr(ws), nbytes, ctypes.c_void_p(_stream_ptr(y.device)))
+    _check(st, "tv_chain_prox_l1")
+    res = restore(xv)
+    if out is not None:
+        out.copy_(res)
+        return out
+    return res
 
 
 MAX_CHAIN_BATCHES = 8

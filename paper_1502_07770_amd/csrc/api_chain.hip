@@ -304,6 +304,39 @@ tv_status tv_chain_dp_autotune(const tv_chain_layout *layout, tv_dtype dtype, co
     return TV_OK;
 }
 
+// ---- TV-l1 chain prox ----
+
+size_t tv_chain_prox_l1_workspace(const tv_chain_layout *layout, tv_dtype dtype) {
+    if (!layout_ok(layout, dtype) || layout->num_chains == 0) return 0;
+    return dtype == TV_F32 ? chain_l1_ws_bytes<float>(layout->num_chains, layout->length)
+                           : chain_l1_ws_bytes<double>(layout->num_chains, layout->length);
+}
+
+tv_status tv_chain_prox_l1(const tv_chain_layout *layout, tv_dtype dtype, const void *y, const void *d,
+                           const void *w, double w_scalar, const void *c, double c_scalar, void *x,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!layout_ok(layout, dtype)) return TV_ERR_INVALID_ARG;
+    if (layout->num_chains == 0) return TV_OK;
+    if (!y || !d || !x) return TV_ERR_INVALID_ARG;
+    if (!w && !(isfinite(w_scalar) && w_scalar >= 0.0)) return TV_ERR_INVALID_ARG;
+    if (!c && !(isfinite(c_scalar) && c_scalar >= 0.0)) return TV_ERR_INVALID_ARG;
+    if (overlaps(layout, x, layout, y, dtype) || overlaps(layout, x, layout, d, dtype) ||
+        overlaps(layout, x, layout, w, dtype) || overlaps(layout, x, layout, c, dtype))
+        return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < tv_chain_prox_l1_workspace(layout, dtype)) return TV_ERR_WORKSPACE;
+    tv_status st = device_check();
+    if (st != TV_OK) return st;
+    const ChainBatch b = to_batch(layout);
+    hipError_t e;
+    if (dtype == TV_F32)
+        e = launch_chain_l1<float>(b, (const float *)y, (const float *)d, (const float *)w, (float)w_scalar,
+                                   (const float *)c, (float)c_scalar, (float *)x, workspace, stream);
+    else
+        e = launch_chain_l1<double>(b, (const double *)y, (const double *)d, (const double *)w, w_scalar,
+                                    (const double *)c, c_scalar, (double *)x, workspace, stream);
+    return e == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
 static_assert(kMaxChainBatches == TV_MAX_CHAIN_BATCHES, "batch limit of the ABI");
 
 static bool multi_ok(int nb, const tv_chain_layout *layouts, tv_dtype dtype, int64_t *C, int64_t *n) {

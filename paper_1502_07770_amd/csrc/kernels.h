@@ -93,6 +93,13 @@ template <typename T>
 hipError_t launch_chain_dp(const ChainBatch &b, const T *a, const T *bv, const T *wm, const T *wp, T *x,
                            void *workspace, const SegPlan &plan, hipStream_t stream);
 
+// TV-l1 chain prox (see tv_chain_prox_l1): workspace bytes and the launch.
+template <typename T>
+size_t chain_l1_ws_bytes(int64_t num_chains, int64_t n);
+template <typename T>
+hipError_t launch_chain_l1(const ChainBatch &b, const T *y, const T *d, const T *w, T w_scalar, const T *c,
+                           T c_scalar, T *x, void *workspace, hipStream_t stream);
+
 template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,
                                 int w_per_edge, hipStream_t stream);

@@ -23,6 +23,9 @@ experiments, Figs. 5 and 6):
   a_i x^2 / 2 - b_i x, edge slopes w^- <= w^+) on an H x W image: data weights
   a ~ U[0.5, 2], b = a f with f the shapes image, w^- = -w u and w^+ = w v with
   u, v ~ U[0.5, 1.5] per edge (asymmetric TV of weight about w).
+* ``salt_pepper_chains``: piecewise-constant chains (levels U[0, 1], no
+  Gaussian noise) with a fraction of the samples (25%) replaced by 0 or 1 with
+  probability 1/2 each -- impulse noise, the TV-l1 model's setting (Sec. 5.2).
 * ``edge_weights`` (U[lo, hi]) and ``normal`` (N(0, 1)) helpers.
 """
 from __future__ import annotations
@@ -124,3 +127,12 @@ def general_chain_problem(H: int, W: int, w: float = 0.1, seed: int = 0):
     wm = -w * g.uniform(0.5, 1.5, size=(H, W))
     wp = w * g.uniform(0.5, 1.5, size=(H, W))
     return a, a * f, wm, wp
+
+
+def salt_pepper_chains(num_chains: int, n: int, frac: float = 0.25, seed: int = 0) -> np.ndarray:
+    """Piecewise-constant chains with salt & pepper noise (see the module docstring)."""
+    f = piecewise_constant(num_chains, n, sigma=0.0, seed=seed)
+    g = generator(seed + 104729)
+    m = g.random(f.shape) < frac
+    f[m] = g.integers(0, 2, int(m.sum())).astype(np.float64)
+    return f

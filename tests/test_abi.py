@@ -144,6 +144,26 @@ def test_chain_dp_argument_errors_and_workspace(lib):
     assert at(ctypes.byref(rows), 0, a, b, wm, wp, x, None, 0, None, ctypes.byref(res)) == binding.TV_ERR_WORKSPACE
 
 
+def test_chain_prox_l1_argument_errors(lib):
+    """tv_chain_prox_l1: host-visible argument errors before any HIP call."""
+    P = ctypes.c_void_p
+    rows = _lay(8, 100, 1, 100)
+    y, d, w, c, x, ws = (P(0x10000000 * k) for k in range(1, 7))
+    assert lib.tv_chain_prox_l1_workspace(ctypes.byref(rows), binding.TV_F32) > 0
+    assert lib.tv_chain_prox_l1_workspace(ctypes.byref(rows), 3) == 0
+    f = lib.tv_chain_prox_l1
+    big = 1 << 30
+    assert f(ctypes.byref(rows), 0, None, d, None, 0.1, None, 1.0, x, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    assert f(ctypes.byref(rows), 0, y, None, None, 0.1, None, 1.0, x, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    assert f(ctypes.byref(rows), 0, y, d, None, -0.1, None, 1.0, x, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    assert f(ctypes.byref(rows), 0, y, d, None, 0.1, None, float("inf"), x, ws, big,
+             None) == binding.TV_ERR_INVALID_ARG
+    for alias in (y, d, w, c):
+        assert f(ctypes.byref(rows), 0, y, d, w, 0.1, c, 1.0, alias, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    assert f(ctypes.byref(rows), 0, y, d, w, 0.1, c, 1.0, x, None, 0, None) == binding.TV_ERR_WORKSPACE
+    assert f(ctypes.byref(rows), 0, y, d, w, 0.1, c, 1.0, x, ws, 64, None) == binding.TV_ERR_WORKSPACE
+
+
 def test_workspace_covers_every_autotune_candidate(lib):
     """The workspace queries reserve room for the largest candidate plan, so a
     plan chosen after the workspace was allocated always fits."""
