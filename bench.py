@@ -18,8 +18,9 @@ Also on the same JSON line:
   extras       -- 2D ROF time-to-gap 1e-4 in FP32 vs FP64 (512^2 and 4096^2),
                   200 iterations at 512^2, forward+backward of 65,536 chains of
                   1,024 with per-edge weights, the general chain DP (data weights,
-                  asymmetric edge slopes) on the 4096^2 rows and columns, and a
-                  batch of 256 uneven images.
+                  asymmetric edge slopes) on the 4096^2 rows and columns, the
+                  TV-l1 chain prox of 65,536 salt & pepper chains, and a batch of
+                  256 uneven images.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras | --extras LIST]
        python bench.py --rocprof-summary DIR   (print a summary of rocprofv3 output)
@@ -276,6 +277,30 @@ def bench_general_dp(steps: int, autotune: bool = True):
     return out
 
 
+def bench_l1(steps: int, autotune: bool = True):
+    """TV-l1 chain prox (tv_chain_prox_l1) of 65,536 salt & pepper chains of
+    1,024 (25% impulses), y = d = f, w = 0.55, c = 1, FP32, as row chains
+    (unit stride) and as column chains (the same data transposed).
+    Algorithmic bytes: y and d read, x written, 12 B/node."""
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    f = torch.tensor(synth.salt_pepper_chains(65536, 1024, seed=12), dtype=torch.float32, device="cuda")
+    ft = f.t().contiguous()
+    tm = Timer(torch, torch.cuda.current_stream())
+    out = {"workload": "65536 chains x 1024, piecewise-constant + 25% salt & pepper, y = d, w = 0.55, c = 1, FP32"}
+    nodes = f.numel()
+    for name, t, dim in (("rows", f, -1), ("cols", ft, 0)):
+        plan = None
+        if autotune:  # setup, not timed; rows and columns share a plan key, so each is tuned just before it
+            _, plan = binding.chain_prox_l1(t, t, 0.55, 1.0, dim=dim, autotune=True)
+        else:
+            binding.chain_prox_l1(t, t, 0.55, 1.0, dim=dim)
+        ms = tm(lambda: binding.chain_prox_l1(t, t, 0.55, 1.0, dim=dim), steps)  # noqa: B023
+        out[name] = {"plan": plan, "ms": round(ms, 4), "gelem_s": round(nodes / ms / 1e6, 2),
+                     "hbm_frac": round(nodes * 12 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def bench_batched():
     import numpy as np
     import torch
@@ -407,7 +432,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,batched")
+                    help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -488,6 +513,7 @@ def main():
                 ("adjoint", "adjoint 65536x1024", lambda: bench_adjoint(5)),
                 ("general_dp", "general chain DP 4096x4096 rows, cols",
                  lambda: bench_general_dp(10, autotune=not args.no_autotune)),
+                ("tv_l1", "TV-l1 chain prox 65536x1024", lambda: bench_l1(10, autotune=not args.no_autotune)),
                 ("batched", "batched 256 images", bench_batched)]
         pick = None if args.extras == "all" else set(args.extras.split(","))
         try:

@@ -183,9 +183,13 @@ tv_status tv_chain_dp_autotune(const tv_chain_layout *layout, tv_dtype dtype, co
  * quadratic weight normalised to 1 (prox_{tau (w TV + |. - f|)}(xi) is this with
  * y = xi, d = f, c = tau, w = tau w).  Exact: the Sec. 4.2 message passing with
  * the breakpoint multiset of the message derivative (position, slope tag, jump)
- * kept sorted per chain in on-chip memory, one chain per lane; chains whose set
- * outgrows it are redone with the set in the workspace.  Slopes are integers,
- * so lengths must be below 2^24 for TV_F32.
+ * kept sorted in on-chip memory; chains are cut into segments solved in
+ * parallel from a halo, as for tv_chain_prox, and sets that outgrow the
+ * on-chip ring are redone with the set in the workspace.  The sets carry
+ * rounding drift (their jump remainders are re-derived at every crossing), so
+ * segment boundaries accept sets that agree to 3e-5 (FP32) or 1e-12 (FP64) of
+ * the data scale: results agree with a sequential solve to that level, not bit
+ * for bit.  Slopes are integers, so lengths must be below 2^24 for TV_F32.
  *  y, d  : per-node inputs in the layout (uniform or CSR offsets).
  *  w     : per-edge weights in the layout (slot of node i = edge (i, i+1)), or
  *          NULL to use w_scalar (>= 0, finite, else TV_ERR_INVALID_ARG).
@@ -197,6 +201,14 @@ size_t tv_chain_prox_l1_workspace(const tv_chain_layout *layout, tv_dtype dtype)
 tv_status tv_chain_prox_l1(const tv_chain_layout *layout, tv_dtype dtype, const void *y, const void *d,
                            const void *w, double w_scalar, const void *c, double c_scalar, void *x,
                            void *workspace, size_t workspace_bytes, hipStream_t stream);
+/* Autotuner of tv_chain_prox_l1 launches, as tv_chain_prox_autotune: times
+ * every candidate plan that fits the workspace on this data and keeps the
+ * fastest for later calls of the same shape in this process; x receives the
+ * prox.  Synchronous. */
+tv_status tv_chain_prox_l1_autotune(const tv_chain_layout *layout, tv_dtype dtype, const void *y, const void *d,
+                                    const void *w, double w_scalar, const void *c, double c_scalar, void *x,
+                                    void *workspace, size_t workspace_bytes, hipStream_t stream,
+                                    tv_tuning_result *chosen);
 
 /* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
 size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);

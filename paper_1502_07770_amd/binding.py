@@ -96,6 +96,8 @@ _SIG = {
     "tv_chain_prox_l1_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "tv_chain_prox_l1": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, ctypes.c_double, _P,
                                         _P, ctypes.c_size_t, _P]),
+    "tv_chain_prox_l1_autotune": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P,
+                                                 ctypes.c_double, _P, _P, ctypes.c_size_t, _P, _P]),
     "tv_chain_dp_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "tv_chain_dp": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "tv_chain_dp_autotune": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
@@ -310,11 +312,12 @@ def chain_dp(b: torch.Tensor, wm: torch.Tensor, wp: torch.Tensor, a: Optional[to
 
 def chain_prox_l1(y: torch.Tensor, d: torch.Tensor, w: Union[float, torch.Tensor] = 0.0,
                   c: Union[float, torch.Tensor] = 1.0, dim: int = -1,
-                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                  out: Optional[torch.Tensor] = None, autotune: bool = False):
     """TV-l1 chain prox (tv_chain_prox_l1) of every chain along ``dim``:
     argmin sum w|x_{i+1} - x_i| + sum (x - y)^2/2 + sum c|x - d|.  ``w`` and
     ``c`` are floats or tensors shaped like ``y`` (w at node i is the weight of
-    edge (i, i+1))."""
+    edge (i, i+1)).  With ``autotune`` the call times the candidate plans and
+    returns (x, chosen plan)."""
     _require_gpu(y, d)
     lib = load()
     if y.numel() == 0:
@@ -338,14 +341,23 @@ def chain_prox_l1(y: torch.Tensor, d: torch.Tensor, w: Union[float, torch.Tensor
     code = _dtype_code(y)
     nbytes = lib.tv_chain_prox_l1_workspace(ctypes.byref(lay), code)
     ws = _workspace(nbytes, y.device)
-    st = lib.tv_chain_prox_l1(ctypes.byref(lay), code, _ptr(yv), _ptr(dv), _ptr(wv), ws_, _ptr(cv), cs_, _ptr(xv),
-                              _ptr(ws), nbytes, ctypes.c_void_p(_stream_ptr(y.device)))
-    _check(st, "tv_chain_prox_l1")
+    stream = ctypes.c_void_p(_stream_ptr(y.device))
+    chosen = None
+    if autotune:
+        r = TuningResult()
+        st = lib.tv_chain_prox_l1_autotune(ctypes.byref(lay), code, _ptr(yv), _ptr(dv), _ptr(wv), ws_, _ptr(cv), cs_,
+                                           _ptr(xv), _ptr(ws), nbytes, stream, ctypes.byref(r))
+        _check(st, "tv_chain_prox_l1_autotune")
+        chosen = r.as_dict()
+    else:
+        st = lib.tv_chain_prox_l1(ctypes.byref(lay), code, _ptr(yv), _ptr(dv), _ptr(wv), ws_, _ptr(cv), cs_,
+                                  _ptr(xv), _ptr(ws), nbytes, stream)
+        _check(st, "tv_chain_prox_l1")
     res = restore(xv)
     if out is not None:
         out.copy_(res)
-        return out
-    return res
+        res = out
+    return (res, chosen) if autotune else res
 
 
 MAX_CHAIN_BATCHES = 8

@@ -337,6 +337,58 @@ tv_status tv_chain_prox_l1(const tv_chain_layout *layout, tv_dtype dtype, const 
     return e == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
 
+tv_status tv_chain_prox_l1_autotune(const tv_chain_layout *layout, tv_dtype dtype, const void *y, const void *d,
+                                    const void *w, double w_scalar, const void *c, double c_scalar, void *x,
+                                    void *workspace, size_t workspace_bytes, hipStream_t stream,
+                                    tv_tuning_result *chosen) {
+    // argument checks and one launch with the current plan
+    tv_status st = tv_chain_prox_l1(layout, dtype, y, d, w, w_scalar, c, c_scalar, x, workspace, workspace_bytes,
+                                    stream);
+    if (st != TV_OK || layout->num_chains == 0) return st;
+    const int64_t C = layout->num_chains, n = layout->length;
+    const ChainBatch b = to_batch(layout);
+    SegPlan cand[64];
+    const int m = dtype == TV_F32 ? seg_candidates<float, TagJ<float>>(C, n, cand, 64)
+                                  : seg_candidates<double, TagJ<double>>(C, n, cand, 64);
+    int best = -1, tried = 0;
+    float best_ms = 0.0f;
+    for (int j = 0; j < m; ++j) {
+        const size_t need = dtype == TV_F32 ? seg_ws_bytes_plan<float, TagJ<float>>(C, n, cand[j])
+                                            : seg_ws_bytes_plan<double, TagJ<double>>(C, n, cand[j]);
+        if (need > workspace_bytes) continue;
+        seg_set_tuned(kPlanL1, C, n, cand[j]);
+        auto run = [&]() {
+            return dtype == TV_F32
+                       ? launch_chain_l1<float>(b, (const float *)y, (const float *)d, (const float *)w,
+                                                (float)w_scalar, (const float *)c, (float)c_scalar, (float *)x,
+                                                workspace, stream)
+                       : launch_chain_l1<double>(b, (const double *)y, (const double *)d, (const double *)w, w_scalar,
+                                                 (const double *)c, c_scalar, (double *)x, workspace, stream);
+        };
+        float ms = 0.0f;
+        if (time_calls(run, stream, 3, &ms) != hipSuccess) return TV_ERR_HIP;
+        ++tried;
+        if (best < 0 || ms < best_ms) {
+            best = j;
+            best_ms = ms;
+        }
+    }
+    if (best < 0) return TV_ERR_WORKSPACE;
+    seg_set_tuned(kPlanL1, C, n, cand[best]);
+    // x from the chosen plan (plans agree only to rounding for TV-l1)
+    st = tv_chain_prox_l1(layout, dtype, y, d, w, w_scalar, c, c_scalar, x, workspace, workspace_bytes, stream);
+    if (st != TV_OK) return st;
+    if (hipStreamSynchronize(stream) != hipSuccess) return TV_ERR_HIP;
+    if (chosen) {
+        chosen->segment_length = cand[best].L;
+        chosen->halo = cand[best].H;
+        chosen->ring_slots = cand[best].K;
+        chosen->candidates = tried;
+        chosen->ms = best_ms;
+    }
+    return TV_OK;
+}
+
 static_assert(kMaxChainBatches == TV_MAX_CHAIN_BATCHES, "batch limit of the ABI");
 
 static bool multi_ok(int nb, const tv_chain_layout *layouts, tv_dtype dtype, int64_t *C, int64_t *n) {

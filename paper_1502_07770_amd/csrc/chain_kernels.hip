@@ -571,7 +571,7 @@ size_t chain_prox_ws_bytes(const ChainBatch &b, const SegPlan &plan) {
     return seg_ws_bytes<T>(b.num_chains, b.n, plan);
 }
 
-// Autotuner candidates: segment lengths 32 .. 1024, halos 64 and 128, rings of
+// Autotuner candidates: segment lengths 32 .. 1024, halos 32, 64 and 128, rings of
 // 16 or 32 slots (32 only where segments are at least 4 times longer, to bound
 // the saved deques), keeping only plans whose workspace stays within twice the
 // default plan's (or the default's plus 64 MiB).  Segment lengths at or above
@@ -589,7 +589,7 @@ int seg_candidates(int64_t C, int64_t n, SegPlan *out, int max_out) {
         whole = L >= n;
         for (int K = 16; K <= 32; K *= 2) {
             if (K * 4 > Lr && K > 16) continue;
-            for (int64_t H = 64; H <= 128; H *= 2) {
+            for (int64_t H = 32; H <= 128; H *= 2) {
                 const SegPlan p{Lr, H, 16, K};
                 if (seg_ws_bytes<T, G>(C, n, p) > cap) continue;
                 bool dup = false;
@@ -629,6 +629,12 @@ template int seg_candidates<float, double>(int64_t, int64_t, SegPlan *, int);
 template size_t seg_bytes_max<float, float>(int64_t, int64_t, int);
 template size_t seg_bytes_max<double, double>(int64_t, int64_t, int);
 template size_t seg_bytes_max<float, double>(int64_t, int64_t, int);
+template size_t seg_ws_bytes_plan<float, TagJ<float>>(int64_t, int64_t, const SegPlan &);
+template size_t seg_ws_bytes_plan<double, TagJ<double>>(int64_t, int64_t, const SegPlan &);
+template int seg_candidates<float, TagJ<float>>(int64_t, int64_t, SegPlan *, int);
+template int seg_candidates<double, TagJ<double>>(int64_t, int64_t, SegPlan *, int);
+template size_t seg_bytes_max<float, TagJ<float>>(int64_t, int64_t, int);
+template size_t seg_bytes_max<double, TagJ<double>>(int64_t, int64_t, int);
 
 template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,

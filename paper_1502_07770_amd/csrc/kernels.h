@@ -42,7 +42,8 @@ enum PlanKind {
     kPlanBatchCol = 3,
     kPlanBatchRow = 4,
     kPlanDp = 5,
-    kPlanKinds = 6
+    kPlanL1 = 6,
+    kPlanKinds = 7
 };
 
 // Process-wide tuning: target lanes per launch, shortest segment, halo.
@@ -60,6 +61,9 @@ SegPlan seg_plan(int64_t num_chains, int64_t n, int kind = kPlanChain);
 SegPlan seg_default_plan(int64_t num_chains, int64_t n);
 void seg_set_tuned(int kind, int64_t num_chains, int64_t n, const SegPlan &p);
 void seg_clear_tuned();
+// Tag of a TV-l1 breakpoint (slope tag and jump; defined in l1_core.h).
+template <typename T> struct TagJ;
+
 // Candidate plans for the autotuner (the default plan first); every workspace
 // query reserves room for the largest of them, so a tuned plan always fits.
 // G is the tag type of the deque entries (T when a_i = 1, FP64 otherwise).

@@ -42,7 +42,10 @@
 // nodes ahead into registers (four per 16-byte load on unit-stride chains), so
 // each memory wait covers requests issued a tile earlier.
 #pragma once
+#include <type_traits>
+
 #include "chain_core.h"
+#include "l1_core.h"
 
 namespace tvc {
 
@@ -54,9 +57,13 @@ struct alignas(2 * sizeof(T)) LamPair {
 // A deque entry: breakpoint lambda and the tag k of the segment to its right.
 // With a_i = 1 the tag is the birth step, kept as a floating-point integer in
 // the working precision (exact below 2^24 for float) so the slope s - k is one
-// exact subtraction; with general a_i it is the FP64 prefix sum Abar_k.
+// exact subtraction; with general a_i it is the FP64 prefix sum Abar_k; for
+// TV-l1 sets it is the birth step and the jump of h at lambda (TagJ).  Every
+// step leaves the back entry's tag at 0, so saved states compare entry by
+// entry, tags included.
+constexpr size_t ent_align(size_t b) { return b <= 8 ? 8 : (b <= 16 ? 16 : 32); }
 template <typename T, typename G = T>
-struct alignas(2 * sizeof(G)) Ent {
+struct alignas(ent_align(sizeof(T) + sizeof(G))) Ent {
     T l;
     G k;
 };
@@ -132,6 +139,38 @@ __device__ __forceinline__ uint32_t bits32(double v) {
     return (uint32_t)b ^ (uint32_t)(b >> 32) * 0x9E3779B1u;
 }
 
+// State comparison of two deque entries, and the entry's share of the state
+// hash.  Exact for the Sec. 4.1 deques.  TV-l1 sets keep jump remainders that
+// are re-derived from the previous jump at every crossing, so their rounding
+// errors add up along the chain (a random walk, about 1e-5 of the data scale
+// after a few hundred FP32 steps) and two runs that reach the same set in exact
+// arithmetic stay apart by that much: there the slope tags must be equal and
+// positions and jumps agree to 3e-5 (FP32) or 1e-12 (FP64) of max(1, |value|);
+// the hash covers the tags only.  A segmented TV-l1 solve then agrees with a
+// sequential one to that level, not bit for bit.
+template <typename T> __device__ __forceinline__ T near_tol();
+template <> __device__ __forceinline__ float near_tol<float>() { return 3e-5f; }
+template <> __device__ __forceinline__ double near_tol<double>() { return 1e-12; }
+template <typename T> __device__ __forceinline__ bool near(T a, T b) {
+    const T m = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+    return fabs(a - b) <= near_tol<T>() * (m > (T)1 ? m : (T)1);
+}
+template <typename T, typename G> __device__ __forceinline__ bool ent_same(T la, const G &ka, T lb, const G &kb) {
+    return la == lb && ka == kb;
+}
+template <typename T>
+__device__ __forceinline__ bool ent_same(T la, const TagJ<T> &ka, T lb, const TagJ<T> &kb) {
+    return ka.k == kb.k && near(la, lb) && near(ka.j, kb.j);
+}
+template <typename T, typename G> __device__ __forceinline__ uint32_t ent_hash(uint32_t h, T l, const G &k, bool tag) {
+    h = (h ^ bits32(l)) * 0x01000193u;
+    return tag ? (h ^ bits32(k)) * 0x01000193u : h;
+}
+template <typename T>
+__device__ __forceinline__ uint32_t ent_hash(uint32_t h, T, const TagJ<T> &k, bool tag) {
+    return tag ? (h ^ bits32(k.k)) * 0x01000193u : h;
+}
+
 template <typename T, int K, typename G = T> struct CRing;
 
 // Entry-by-entry comparison of a ring with a saved state of the same size,
@@ -171,13 +210,13 @@ struct CRing {
     }
     __device__ __forceinline__ void set(int j, const E &e) const { put_slot((head + j) & (K - 1), e); }
     // Order-sensitive 32-bit hash of the breakpoints and tags (the back tag is
-    // excluded); a filter only: equality is always confirmed entry by entry.
+    // excluded; see ent_hash); a filter only: equality is always confirmed
+    // entry by entry.
     __device__ __forceinline__ uint32_t hash() const {
         uint32_t h = 0x811C9DC5u ^ (uint32_t)size;
         for (int j = 0; j < size; ++j) {
             const E e = ld(j);
-            h = (h ^ bits32(e.l)) * 0x01000193u;
-            if (j + 1 < size) h = (h ^ bits32(e.k)) * 0x01000193u;
+            h = ent_hash<T>(h, e.l, e.k, j + 1 < size);
         }
         return h;
     }
@@ -218,7 +257,7 @@ __device__ __forceinline__ bool saved_equal(const CRing<T, K, G> &R, const Ent<T
             const int jj = j0 + j;
             if (jj < n) {
                 const Ent<T, G> m = R.ld(jj);
-                eq = eq && (e[j].l == m.l) && (jj + 1 == n || e[j].k == m.k);
+                eq = eq && ent_same<T>(e[j].l, e[j].k, m.l, m.k);
             }
         }
     }
@@ -441,14 +480,86 @@ __device__ __forceinline__ StepIn<T, typename Prob::Tag> step_in(const typename 
     return in;
 }
 
+// TV-l1 problems (Prob::kL1): the set of the Sec. 4.2 message in the ring.
+template <class Prob, class = void> struct IsL1 : std::false_type {};
+template <class Prob> struct IsL1<Prob, std::void_t<decltype(Prob::kL1)>> : std::bool_constant<Prob::kL1> {};
+
+// The ring as a sorted TV-l1 store (l1_core.h); a push into a full ring sets
+// ovf and is dropped.
+template <typename T, int K>
+struct L1Ring {
+    CRing<T, K, TagJ<T>> &R;
+    bool ovf;
+    int size;
+    __device__ __forceinline__ L1Ring(CRing<T, K, TagJ<T>> &r) : R(r), ovf(false), size(r.size) {}
+    __device__ __forceinline__ L1E<T> get(int j) const {
+        const Ent<T, TagJ<T>> e = R.ld(j);
+        return L1E<T>{e.l, e.k.k, e.k.j};
+    }
+    __device__ __forceinline__ void put(int j, const L1E<T> &e) const {
+        R.set(j, mk_ent<T, TagJ<T>>(e.l, TagJ<T>{e.k, e.j}));
+    }
+    __device__ __forceinline__ void pop_front(int k) {
+        R.head = (R.head + k) & (K - 1);
+        size -= k;
+        R.size = size;
+    }
+    __device__ __forceinline__ void pop_back(int k) {
+        size -= k;
+        R.size = size;
+    }
+    __device__ __forceinline__ void push_front(const L1E<T> &e) {
+        if (size >= K) {
+            ovf = true;
+            return;
+        }
+        R.head = (R.head + K - 1) & (K - 1);
+        R.size = ++size;
+        put(0, e);
+    }
+    __device__ __forceinline__ void push_back(const L1E<T> &e) {
+        if (size >= K) {
+            ovf = true;
+            return;
+        }
+        R.size = ++size;
+        put(size - 1, e);
+    }
+    // insert at logical position q, shifting the shorter side
+    __device__ __forceinline__ void insert(int q, const L1E<T> &e) {
+        if (size >= K) {
+            ovf = true;
+            return;
+        }
+        if (q < size - q) {
+            R.head = (R.head + K - 1) & (K - 1);
+            for (int j = 0; j < q; ++j) put(j, get(j + 1));
+        } else {
+            for (int j = size; j > q; --j) put(j, get(j - 1));
+        }
+        R.size = ++size;
+        put(q, e);
+    }
+};
+
 template <typename T, class Prob, int K>
 __device__ __forceinline__ void node_step(CRing<T, K, typename Prob::Tag> &R, bool &ok, int64_t i, int64_t n,
                                           const typename Prob::Src &src, const typename Prob::Pre &pv,
                                           CarryOf<T, Prob> &cy, T &lm, T &lp) {
     const bool root = (i == n - 1);
-    const auto in = step_in<T, Prob>(src, pv, i, root, cy);
-    const bool fits = dp_step_win<T, typename Prob::Tag, K, kScanWindow, Prob::kGen>(R, in, lm, lp);
-    ok = ok & (fits | root);
+    if constexpr (IsL1<Prob>::value) {
+        const T wi = src.weight(pv);
+        const T w = root ? (T)0 : wi;
+        L1Ring<T, K> S(R);
+        l1_step<T>(S, (T)(int)(i + 1), src.data(pv), src.dval(pv), src.cval(pv), -cy.wprev, cy.wprev, -w, w, root,
+                   lm, lp);
+        cy.wprev = wi;
+        ok = ok & (!S.ovf | root);
+    } else {
+        const auto in = step_in<T, Prob>(src, pv, i, root, cy);
+        const bool fits = dp_step_win<T, typename Prob::Tag, K, kScanWindow, Prob::kGen>(R, in, lm, lp);
+        ok = ok & (fits | root);
+    }
     if (root) lp = lm;
 }
 
@@ -765,7 +876,7 @@ __global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Pr
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int jj = j0 + j;
-                if (jj < m) same = same && (ea[j].l == eb[j].l) && (jj + 1 == m || ea[j].k == eb[j].k);
+                if (jj < m) same = same && ent_same<T>(ea[j].l, ea[j].k, eb[j].l, eb[j].k);
             }
         }
     }
@@ -816,17 +927,35 @@ __device__ void seg_full_chain(const WsOf<T, Prob> &ws, const typename Prob::Par
                                int64_t c, int64_t slot) {
     using G = typename Prob::Tag;
     const auto src = Prob::src(pp, sp);
-    GlobalDeque<T, G> dq;
-    dq.init(ws.fb_lam + slot * ws.fb_cap, ws.fb_tag + slot * ws.fb_cap, ws.fb_cap);
     auto cy = carry_before<T, Prob>(src, 0);
-    for (int64_t i = 0; i < sp.n; ++i) {
-        const auto pr = src.load(i);
-        const bool root = (i == sp.n - 1);
-        T lm = (T)0, lp = (T)0;
-        const auto in = step_in<T, Prob>(src, pr, i, root, cy);
-        dp_step<T, G, Prob::kGen>(dq, in, root, lm, lp);
-        if (root) lp = lm;
-        put_lam<T>(ws.lam, i, ws.C, c, lm, lp);
+    if constexpr (IsL1<Prob>::value) {
+        // at most one front push per node: the set starts n + 4 slots in
+        L1ArrayStore<T> S;
+        S.init(ws.fb_lam + slot * ws.fb_cap, ws.fb_tag + slot * ws.fb_cap, ws.fb_cap, sp.n + 4);
+        for (int64_t i = 0; i < sp.n; ++i) {
+            const auto pr = src.load(i);
+            const bool root = (i == sp.n - 1);
+            const T wi = src.weight(pr);
+            const T w = root ? (T)0 : wi;
+            T lm = (T)0, lp = (T)0;
+            l1_step<T>(S, (T)(int)(i + 1), src.data(pr), src.dval(pr), src.cval(pr), -cy.wprev, cy.wprev, -w, w,
+                       root, lm, lp);
+            if (root) lp = lm;
+            put_lam<T>(ws.lam, i, ws.C, c, lm, lp);
+            cy.wprev = wi;
+        }
+    } else {
+        GlobalDeque<T, G> dq;
+        dq.init(ws.fb_lam + slot * ws.fb_cap, ws.fb_tag + slot * ws.fb_cap, ws.fb_cap);
+        for (int64_t i = 0; i < sp.n; ++i) {
+            const auto pr = src.load(i);
+            const bool root = (i == sp.n - 1);
+            T lm = (T)0, lp = (T)0;
+            const auto in = step_in<T, Prob>(src, pr, i, root, cy);
+            dp_step<T, G, Prob::kGen>(dq, in, root, lm, lp);
+            if (root) lp = lm;
+            put_lam<T>(ws.lam, i, ws.C, c, lm, lp);
+        }
     }
     full_backward<T, Prob>(ws, pp, sp, c);
 }
@@ -987,7 +1116,9 @@ template <typename T, int K, typename G = T>
 size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int64_t CK, SegWs<T, G> *out) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const int64_t S = (n + L - 1) / L;
-    const int64_t cap = 2 * n + 4;
+    // HBM deques: 2n + 4 entries; TV-l1 sets (one front push and at most two
+    // other insertions per node, starting n + 4 slots in): 4n + 8
+    const int64_t cap = std::is_same<G, TagJ<T>>::value ? 4 * n + 8 : 2 * n + 4;
     size_t off = 0;
     const size_t o_lam = off;  off += al(sizeof(LamPair<T>) * (size_t)(n * C));
     const size_t o_st = off;   off += al(sizeof(Ent<T, G>) * (size_t)(S * kSaves * K * C));

@@ -92,6 +92,72 @@ def test_large_sets_take_the_hbm_fallback(dtype):
     _check(y, y, xg, oracle.chain_prox_l1(y, y, w=w, c_scalar=1.0), TOL[dtype])
 
 
+@pytest.fixture
+def tuning():
+    saved = binding.get_tuning()
+    yield binding.set_tuning
+    binding.set_tuning(**saved)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("halo", [0, 16, 128])
+def test_segmented_matches_sequential(tuning, dtype, halo):
+    """One segment per chain against fine segmentation with short and long
+    halos (repairs, fix-ups and tails all run).  TV-l1 sets carry rounding
+    drift, so segment boundaries accept sets equal to rounding: the results
+    agree to 1e-4 (FP32) / 1e-10 (FP64) of the data scale, not bit for bit."""
+    f = _salt_pepper(60, 2500, 0.25, seed=21)
+    rng = np.random.default_rng(22)
+    yt = _dev(f + 0.05 * rng.normal(size=f.shape), dtype)
+    dt = _dev(f, dtype)
+    wt = _dev(rng.uniform(0.1, 1.2, f.shape), dtype)
+    tol = 1e-4 if dtype == torch.float32 else 1e-10
+    tuning(target_lanes=1, min_segment=1)
+    ref = binding.chain_prox_l1(yt, dt, wt, 0.8)
+    tuning(target_lanes=1 << 30, min_segment=32, halo=halo)
+    got = binding.chain_prox_l1(yt, dt, wt, 0.8)
+    assert (got - ref).abs().max().item() <= tol
+    tuning(target_lanes=1 << 30, min_segment=64, halo=halo)
+    got = binding.chain_prox_l1(yt, dt, wt, 0.8, dim=-1)
+    assert (got - ref).abs().max().item() <= tol
+    y = yt.double().cpu().numpy()
+    d = dt.double().cpu().numpy()
+    _check(y, d, got.double().cpu().numpy(),
+           oracle.chain_prox_l1(y, d, w=wt.double().cpu().numpy(), c_scalar=0.8), TOL[dtype])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_ring_sizes_agree(tuning, dtype):
+    """Sets of 20 .. 47 breakpoints: with 16 ring slots they go to the large
+    LDS ring or the HBM set, with 32 the smaller ones stay segmented; both
+    agree with the oracle and with each other to rounding."""
+    rng = np.random.default_rng(1)
+    C, n = 48, 1024
+    y = rng.normal(size=(C, n)) * 0.3 + np.repeat(rng.uniform(0, 1, (C, n // 64)), 64, axis=1)
+    w = np.repeat(np.array([0.5, 20.0, 50.0])[np.arange(C) % 3][:, None], n, axis=1)
+    yt, wt = _dev(y, dtype), _dev(w, dtype)
+    tuning(target_lanes=1 << 30, min_segment=128, ring_slots=16)
+    a = binding.chain_prox_l1(yt, yt, wt, 1.0)
+    tuning(target_lanes=1 << 30, min_segment=128, ring_slots=32)
+    b = binding.chain_prox_l1(yt, yt, wt, 1.0)
+    assert (a - b).abs().max().item() <= (1e-4 if dtype == torch.float32 else 1e-10)
+    yv = yt.double().cpu().numpy()
+    _check(yv, yv, b.double().cpu().numpy(), oracle.chain_prox_l1(yv, yv, w=wt.double().cpu().numpy(), c_scalar=1.0),
+           TOL[dtype])
+
+
+def test_autotune_picks_a_plan_and_keeps_the_result(tuning):
+    f = _salt_pepper(512, 2048, 0.25, seed=30)
+    t = _dev(f, torch.float32)
+    ref = binding.chain_prox_l1(t, t, 0.55, 1.0)
+    got, plan = binding.chain_prox_l1(t, t, 0.55, 1.0, autotune=True)
+    assert plan["candidates"] >= 2 and plan["halo"] in (32, 64, 128)
+    assert (got - ref).abs().max().item() <= 1e-4
+    again = binding.chain_prox_l1(t, t, 0.55, 1.0)
+    assert torch.equal(again, got)
+    binding.autotune_clear()
+
+
 def test_c_zero_is_the_tv_prox():
     """No data term: the TV-l2 prox (tv_chain_prox), to rounding."""
     y = synth.piecewise_constant(40, 2000, seed=9)
