@@ -82,6 +82,10 @@ def _load():
     lib.orc_pq_objective.restype = D
     lib.orc_chain_prox_l1.argtypes = [I64, I64, I64, I64, P, P, P, D, P, D, P, P, ctypes.c_int]
     lib.orc_chain_prox_l1.restype = ctypes.c_int
+    lib.orc_tvl1_2d_objective.argtypes = [I64, I64, P, D, P]
+    lib.orc_tvl1_2d_objective.restype = D
+    lib.orc_tv2d_l1.argtypes = [I64, I64, P, D, D, I64, P, P, ctypes.c_int]
+    lib.orc_tv2d_l1.restype = I64
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -280,3 +284,23 @@ def rof2d_objective(f, lam: float, x) -> float:
     f, x = _f64(f), _f64(x)
     H, W = f.shape
     return float(_load().orc_rof2d_objective(H, W, _ptr(f), float(lam), _ptr(x)))
+
+
+def tvl1_2d_objective(f, lam: float, x) -> float:
+    """TV-l1 objective lam (TV_h + TV_v)(x) + |x - f|_1."""
+    f, x = _f64(f), _f64(x)
+    H, W = f.shape
+    return float(_load().orc_tvl1_2d_objective(H, W, _ptr(f), float(lam), _ptr(x)))
+
+
+def tv2d_l1(f, lam: float, tau: float = 1.0, max_iter: int = 200, threads: int = 0):
+    """Sec. 5.2 TV-l1 by row/column decomposition, eq. (pd) with constant steps
+    tau, sigma = 1/tau, theta = 1.  Returns (x, energy history)."""
+    f = _f64(f)
+    H, W = f.shape
+    x = np.empty_like(f)
+    hist = np.empty(max(max_iter, 1))
+    k = _load().orc_tv2d_l1(H, W, _ptr(f), float(lam), float(tau), int(max_iter), _ptr(x), _ptr(hist), int(threads))
+    if k < 0:
+        raise ValueError("orc_tv2d_l1: invalid argument")
+    return x, hist[:k].copy()

@@ -31,6 +31,11 @@
  *                          the DP.
  *   orc_chain_prox_l1   -- the TV-l1 chain prox x = argmin sum w|dx| + sum
  *                          (x - y)^2/2 + sum c |x - d|, batched over chains.
+ *   orc_tv2d_l1         -- Sec. 5.2 TV-l1 by the same decomposition: the
+ *                          primal-dual iteration eq. (pd) with the dual prox of
+ *                          lambda TV_v on the columns (as for ROF) and the primal
+ *                          prox eq. (prox-pq) on the rows (orc_chain_prox_l1),
+ *                          constant steps tau sigma = 1, theta = 1.
  *
  * Conventions: node indices are 0-based here (the paper's node i is index i-1);
  * edge e joins nodes e and e+1, so a chain of n nodes has n-1 edge weights.
@@ -825,4 +830,60 @@ int orc_chain_prox_l1(int64_t num_chains, int64_t n, int64_t elem_stride, int64_
         }
     }
     return bad ? -1 : 0;
+}
+
+/* TV-l1 objective lambda (TV_h + TV_v)(x) + sum |x - f|. */
+double orc_tvl1_2d_objective(int64_t H, int64_t W, const double *f, double lambda, const double *x)
+{
+    double P = 0.0;
+    for (int64_t r = 0; r < H; ++r)
+        for (int64_t c = 0; c < W; ++c) {
+            const int64_t k = r * W + c;
+            P += fabs(x[k] - f[k]);
+            if (c + 1 < W) P += lambda * fabs(x[k + 1] - x[k]);
+            if (r + 1 < H) P += lambda * fabs(x[k + W] - x[k]);
+        }
+    return P;
+}
+
+/* Sec. 5.2: min_x lambda (TV_h + TV_v)(x) + |x - f|_1 through the saddle
+   problem min_x max_y <x, y> + lambda TV_h(x) + |x - f|_1 - (lambda TV_v)^*(y)
+   and eq. (pd) with constant steps (tau, sigma = 1 / tau, theta = 1):
+     column step: eta = y + sigma xbar, y' = eta - prox_{lambda TV_v}(eta)
+                  (the dual prox through the Moreau identity, as for ROF);
+     row step:    x' = prox_{tau (lambda TV_h + |. - f|_1)}(x - tau y'), i.e. per
+                  row argmin tau lambda TV + tau |x - f|_1 + |x - xi|^2 / 2
+                  (eq. (prox-pq) times tau), the Sec. 4.2 chain problem;
+     xbar' = 2 x' - x.
+   x^0 = xbar^0 = f, y^0 = 0.  energy_hist[k] = objective after iteration k+1.
+   Returns the iterations run, or -1 on a bad argument. */
+int64_t orc_tv2d_l1(int64_t H, int64_t W, const double *f, double lambda, double tau,
+                    int64_t max_iter, double *x, double *energy_hist, int threads)
+{
+    if (H < 1 || W < 1 || !(lambda >= 0.0) || !(tau > 0.0) || max_iter < 0) return -1;
+    const int64_t N = H * W;
+    double *y = (double *)calloc((size_t)N, sizeof(double));
+    double *xbar = (double *)malloc(sizeof(double) * (size_t)N);
+    double *eta = (double *)malloc(sizeof(double) * (size_t)N);
+    double *u = (double *)malloc(sizeof(double) * (size_t)N);
+    double *xi = (double *)malloc(sizeof(double) * (size_t)N);
+    double *xn = (double *)malloc(sizeof(double) * (size_t)N);
+    memcpy(x, f, sizeof(double) * (size_t)N);
+    memcpy(xbar, f, sizeof(double) * (size_t)N);
+    const double sigma = 1.0 / tau;
+    int64_t k;
+    for (k = 0; k < max_iter; ++k) {
+        for (int64_t i = 0; i < N; ++i) eta[i] = y[i] + sigma * xbar[i];
+        orc_chain_prox_tv(W, H, W, 1, eta, NULL, lambda, u, NULL, threads);
+        for (int64_t i = 0; i < N; ++i) y[i] = eta[i] - u[i];
+        for (int64_t i = 0; i < N; ++i) xi[i] = x[i] - tau * y[i];
+        orc_chain_prox_l1(H, W, 1, W, xi, f, NULL, tau * lambda, NULL, tau, xn, NULL, threads);
+        for (int64_t i = 0; i < N; ++i) {
+            xbar[i] = 2.0 * xn[i] - x[i];
+            x[i] = xn[i];
+        }
+        if (energy_hist) energy_hist[k] = orc_tvl1_2d_objective(H, W, f, lambda, x);
+    }
+    free(y); free(xbar); free(eta); free(u); free(xi); free(xn);
+    return k;
 }
