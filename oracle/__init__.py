@@ -86,6 +86,12 @@ def _load():
     lib.orc_tvl1_2d_objective.restype = D
     lib.orc_tv2d_l1.argtypes = [I64, I64, P, D, D, I64, P, P, ctypes.c_int]
     lib.orc_tv2d_l1.restype = I64
+    lib.orc_tree_pq.argtypes = [I64, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_tree_pq.restype = ctypes.c_int
+    lib.orc_tree_pq_brute.argtypes = [I64, P, P, P, P, P, P, P, P]
+    lib.orc_tree_pq_brute.restype = ctypes.c_int
+    lib.orc_tree_pq_objective.argtypes = [I64, P, P, P, P, P, P, P, P]
+    lib.orc_tree_pq_objective.restype = D
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -304,3 +310,38 @@ def tv2d_l1(f, lam: float, tau: float = 1.0, max_iter: int = 200, threads: int =
     if k < 0:
         raise ValueError("orc_tv2d_l1: invalid argument")
     return x, hist[:k].copy()
+
+
+def _tree_args(parent, a, b, c, d, wm, wp):
+    parent = np.ascontiguousarray(parent, dtype=np.int64)
+    n = parent.shape[0]
+    return n, parent, _f64(a), _f64(b), _f64(c), _f64(d), _f64(wm), _f64(wp)
+
+
+def tree_pq(parent, a, b, c, d, wm, wp):
+    """Algorithm 2 on a forest (parent[i] > i, -1 at roots) with unaries
+    a_i x^2/2 - b_i x + c_i |x - d_i| and edge slopes (wm[i], wp[i]) on the edge
+    from i to its parent (z = x_parent - x_i).  Returns (x, lam_lo, lam_hi)."""
+    n, parent, a, b, c, d, wm, wp = _tree_args(parent, a, b, c, d, wm, wp)
+    x, llo, lhi = np.empty(n), np.empty(n), np.empty(n)
+    rc = _load().orc_tree_pq(n, _ptr(parent), _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(wm), _ptr(wp), _ptr(x),
+                             _ptr(llo), _ptr(lhi))
+    if rc != 0:
+        raise ValueError("orc_tree_pq: parent[i] must exceed i (or be -1)")
+    return x, llo, lhi
+
+
+def tree_pq_brute(parent, a, b, c, d, wm, wp):
+    """Brute-force minimiser of the forest objective for n <= 6."""
+    n, parent, a, b, c, d, wm, wp = _tree_args(parent, a, b, c, d, wm, wp)
+    x = np.empty(n)
+    rc = _load().orc_tree_pq_brute(n, _ptr(parent), _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(wm), _ptr(wp), _ptr(x))
+    if rc != 0:
+        raise ValueError("orc_tree_pq_brute: n must be in [1, 6]")
+    return x
+
+
+def tree_pq_objective(parent, a, b, c, d, wm, wp, x) -> float:
+    n, parent, a, b, c, d, wm, wp = _tree_args(parent, a, b, c, d, wm, wp)
+    return float(_load().orc_tree_pq_objective(n, _ptr(parent), _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(wm),
+                                               _ptr(wp), _ptr(_f64(x))))

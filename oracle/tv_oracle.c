@@ -31,6 +31,12 @@
  *                          the DP.
  *   orc_chain_prox_l1   -- the TV-l1 chain prox x = argmin sum w|dx| + sum
  *                          (x - y)^2/2 + sum c |x - d|, batched over chains.
+ *   orc_tree_pq         -- Algorithm 2 on a forest (nodes numbered children
+ *                          before parents) with the Sec. 4.2 unaries: each
+ *                          node's message is the sum of its children's clipped
+ *                          messages (the union of their breakpoint sets, the
+ *                          "Extension to trees" of Sec. 4.2) plus its unary.
+ *   orc_tree_pq_brute   -- brute force over edge and node states, n <= 6.
  *   orc_tv2d_l1         -- Sec. 5.2 TV-l1 by the same decomposition: the
  *                          primal-dual iteration eq. (pd) with the dual prox of
  *                          lambda TV_v on the columns (as for ROF) and the primal
@@ -886,4 +892,196 @@ int64_t orc_tv2d_l1(int64_t H, int64_t W, const double *f, double lambda, double
     }
     free(y); free(xbar); free(eta); free(u); free(xi); free(xn);
     return k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 2 on a forest.  parent[i] > i for every non-root node (children  */
+/* numbered before their parents), parent[i] = -1 for roots.  Edge i joins    */
+/* node i to parent[i]: f_i(z) = w^-_i z (z < 0), w^+_i z (z >= 0) with       */
+/* z = x_parent - x_i (the chain convention with parent = i + 1).  Unaries as */
+/* in orc_chain_pq.  Each node accumulates the derivative of the sum of its   */
+/* children's clipped messages (ends added, breakpoint multisets merged in    */
+/* order), adds its unary, and is clipped (Algorithm 2, lines 2-4) or, at a   */
+/* root, solved for its zero; the backward pass clips each node to its        */
+/* parent's value.  Returns 0, or -1 on a bad argument or allocation failure. */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double al, bl, ar, br;
+    pq_set S;
+    int64_t cap;
+} pq_msg;
+
+static int pq_msg_reserve(pq_msg *m, int64_t need)
+{
+    if (need <= m->cap) return 0;
+    int64_t cap = m->cap > 0 ? m->cap : 8;
+    while (cap < need) cap *= 2;
+    double *buf = (double *)malloc(sizeof(double) * (size_t)(3 * cap));
+    if (!buf) return -1;
+    if (m->S.t > 0) {
+        memcpy(buf, m->S.lam, sizeof(double) * (size_t)m->S.t);
+        memcpy(buf + cap, m->S.da, sizeof(double) * (size_t)m->S.t);
+        memcpy(buf + 2 * cap, m->S.db, sizeof(double) * (size_t)m->S.t);
+    }
+    free(m->S.lam);
+    m->S.lam = buf;
+    m->S.da = buf + cap;
+    m->S.db = buf + 2 * cap;
+    m->cap = cap;
+    return 0;
+}
+
+int orc_tree_pq(int64_t n, const int64_t *parent, const double *a, const double *b, const double *c,
+                const double *d, const double *wm, const double *wp, double *x, double *lam_lo,
+                double *lam_hi)
+{
+    if (n < 1) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (parent[i] != -1 && (parent[i] <= i || parent[i] >= n)) return -1;
+    pq_msg *acc = (pq_msg *)calloc((size_t)n, sizeof(pq_msg));
+    if (!acc) return -1;
+    int rc = 0;
+    for (int64_t i = 0; i < n && rc == 0; ++i) {
+        pq_msg *m = &acc[i];
+        /* add g_i */
+        m->al += a[i];
+        m->bl += -b[i] - c[i];
+        m->ar += a[i];
+        m->br += -b[i] + c[i];
+        if (c[i] > 0.0) {
+            if (pq_msg_reserve(m, m->S.t + 1)) { rc = -1; break; }
+            int64_t lo_i = 0, hi_i = m->S.t;
+            while (lo_i < hi_i) {
+                const int64_t mid = (lo_i + hi_i) / 2;
+                if (m->S.lam[mid] <= d[i]) lo_i = mid + 1; else hi_i = mid;
+            }
+            pq_insert(&m->S, lo_i, d[i], 0.0, 2.0 * c[i]);
+        }
+        int64_t k;
+        double pa, pb;
+        int jump;
+        if (parent[i] < 0) {  /* root */
+            x[i] = pq_cross_left(&m->S, m->al, m->bl, 0.0, &k, &pa, &pb, &jump);
+            lam_lo[i] = lam_hi[i] = x[i];
+            free(m->S.lam);
+            continue;
+        }
+        /* clip to [w^-_i, w^+_i] as in orc_chain_pq */
+        const double lo = wm[i], hi = wp[i];
+        if (pq_msg_reserve(m, m->S.t + 2)) { rc = -1; break; }
+        const double lm = pq_cross_left(&m->S, m->al, m->bl, lo, &k, &pa, &pb, &jump);
+        double nda = pa, ndb = pb - lo;
+        if (jump) { nda += m->S.da[k]; ndb += m->S.db[k]; }
+        pq_erase_front(&m->S, k + jump);
+        pq_insert(&m->S, 0, lm, nda, ndb);
+        const double lp = pq_cross_right(&m->S, m->ar, m->br, hi, &k, &pa, &pb, &jump);
+        nda = -pa;
+        ndb = hi - pb;
+        if (jump) { nda += m->S.da[m->S.t - 1 - k]; ndb += m->S.db[m->S.t - 1 - k]; }
+        m->S.t -= k + jump;
+        pq_insert(&m->S, m->S.t, lp, nda, ndb);
+        lam_lo[i] = lm;
+        lam_hi[i] = lp < lm ? lm : lp;
+        /* merge the clipped message (ends (0, lo), (0, hi)) into the parent's sum */
+        pq_msg *q = &acc[parent[i]];
+        q->al += 0.0;
+        q->bl += lo;
+        q->ar += 0.0;
+        q->br += hi;
+        if (pq_msg_reserve(q, q->S.t + m->S.t)) { rc = -1; break; }
+        int64_t u = q->S.t - 1, v = m->S.t - 1, w = q->S.t + m->S.t - 1;
+        while (v >= 0) {  /* merge from the back, in place in q */
+            if (u >= 0 && q->S.lam[u] > m->S.lam[v]) {
+                q->S.lam[w] = q->S.lam[u]; q->S.da[w] = q->S.da[u]; q->S.db[w] = q->S.db[u]; --u;
+            } else {
+                q->S.lam[w] = m->S.lam[v]; q->S.da[w] = m->S.da[v]; q->S.db[w] = m->S.db[v]; --v;
+            }
+            --w;
+        }
+        q->S.t += m->S.t;
+        free(m->S.lam);
+        m->S.lam = NULL;
+    }
+    if (rc != 0) {
+        for (int64_t i = 0; i < n; ++i) free(acc[i].S.lam);
+    }
+    free(acc);
+    if (rc != 0) return rc;
+    /* backward pass: parents before children */
+    for (int64_t i = n - 1; i >= 0; --i) {
+        if (parent[i] < 0) continue;
+        double v = x[parent[i]];
+        if (v < lam_lo[i]) v = lam_lo[i];
+        if (v > lam_hi[i]) v = lam_hi[i];
+        x[i] = v;
+    }
+    return 0;
+}
+
+double orc_tree_pq_objective(int64_t n, const int64_t *parent, const double *a, const double *b, const double *c,
+                             const double *d, const double *wm, const double *wp, const double *x)
+{
+    double f = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        f += 0.5 * a[i] * x[i] * x[i] - b[i] * x[i] + c[i] * fabs(x[i] - d[i]);
+        if (parent[i] >= 0) {
+            const double z = x[parent[i]] - x[i];
+            f += (z < 0.0) ? wm[i] * z : wp[i] * z;
+        }
+    }
+    return f;
+}
+
+/* Brute force for n <= 6 as orc_chain_pq_brute, on the forest's edges: the
+   components of fused edges take d of their first "at d" node or their
+   stationary point sum(b - c s + q_in - q_out)... with q the slopes of the
+   edges leaving the component toward a parent (q_out) or entering it from a
+   child (q_in). */
+int orc_tree_pq_brute(int64_t n, const int64_t *parent, const double *a, const double *b, const double *c,
+                      const double *d, const double *wm, const double *wp, double *x_best)
+{
+    if (n < 1 || n > 6) return -1;
+    int64_t ne = 1, nn = 1;
+    for (int64_t i = 0; i < n; ++i) { ne *= 3; nn *= 3; }
+    double best = INFINITY, xc[6];
+    int es[6], ns[6], comp[6];
+    for (int64_t ce = 0; ce < ne; ++ce) {
+        int64_t t = ce;
+        int skip = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            es[i] = (int)(t % 3);
+            t /= 3;
+            if (parent[i] < 0 && es[i] != 0) skip = 1;  /* roots have no edge */
+        }
+        if (skip) continue;
+        /* components of fused edges: label by the topmost node (parents have larger indices) */
+        for (int64_t i = n - 1; i >= 0; --i) comp[i] = (parent[i] >= 0 && es[i] == 0) ? comp[parent[i]] : (int)i;
+        for (int64_t cn = 0; cn < nn; ++cn) {
+            int64_t u = cn;
+            for (int64_t i = 0; i < n; ++i) { ns[i] = (int)(u % 3); u /= 3; }
+            for (int64_t r = 0; r < n; ++r) {
+                if (comp[r] != r) continue;
+                double A = 0.0, B = 0.0, val = NAN;
+                for (int64_t i = 0; i < n; ++i) {
+                    if (comp[i] != r) continue;
+                    if (ns[i] == 1 && isnan(val)) val = d[i];
+                    A += a[i];
+                    B += b[i] - c[i] * (ns[i] == 0 ? -1.0 : 1.0);
+                    /* edge i (to its parent) leaves the component when not fused */
+                    if (parent[i] >= 0 && es[i] != 0) B += (es[i] == 1) ? wp[i] : wm[i];
+                }
+                for (int64_t i = 0; i < n; ++i)  /* edges from a child outside into the component */
+                    if (parent[i] >= 0 && es[i] != 0 && comp[parent[i]] == r) B -= (es[i] == 1) ? wp[i] : wm[i];
+                if (isnan(val)) val = B / A;
+                for (int64_t i = 0; i < n; ++i)
+                    if (comp[i] == r) xc[i] = val;
+            }
+            const double f = orc_tree_pq_objective(n, parent, a, b, c, d, wm, wp, xc);
+            if (f < best) {
+                best = f;
+                for (int64_t i = 0; i < n; ++i) x_best[i] = xc[i];
+            }
+        }
+    }
+    return 0;
 }

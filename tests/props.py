@@ -16,6 +16,10 @@ kernels: they restate what the problem statement fixes.
   subgradients q_e must satisfy q_e = q_{e-1} + a_i x_i - b_i + c_i u_i with
   u_i in the subdifferential of |x_i - d_i| and q_e in that of the edge term,
   and q_{n-1} = 0; the feasible q_e form an interval, propagated node by node.
+* ``kkt_tree``: the same certificate on a forest: the interval of the edge
+  subgradient from node i to its parent is a_i x_i - b_i + c_i U_i plus the sum
+  of its children's intervals, intersected with the edge's subdifferential;
+  a root's sum must contain 0.
 """
 from __future__ import annotations
 
@@ -128,4 +132,38 @@ def kkt_pq(a, b, c, d, wm, wp, x, tol: float):
         if lo > hi:  # empty: record the gap and continue from its midpoint
             worst = max(worst, lo - hi)
             lo = hi = 0.5 * (lo + hi)
+    return worst
+
+
+def kkt_tree(parent, a, b, c, d, wm, wp, x, tol: float):
+    """Largest violation of the optimality conditions on a forest (parent[i] > i,
+    -1 at roots); edge i joins i to parent[i] with z = x_parent - x_i."""
+    parent = np.asarray(parent)
+    a, b, c, d, x, wm, wp = (np.asarray(v, dtype=np.float64) for v in (a, b, c, d, x, wm, wp))
+    n = x.shape[0]
+    lo = np.zeros(n)
+    hi = np.zeros(n)  # sum of the children's intervals, accumulated as children finish
+    worst = 0.0
+    for i in range(n):
+        r = a[i] * x[i] - b[i]
+        ul, uh = (-1.0, 1.0) if abs(x[i] - d[i]) <= tol else (float(np.sign(x[i] - d[i])),) * 2
+        ql, qh = lo[i] + r + c[i] * ul, hi[i] + r + c[i] * uh
+        p = parent[i]
+        if p < 0:
+            el = eh = 0.0
+        else:
+            z = x[p] - x[i]
+            if z > tol:
+                el = eh = wp[i]
+            elif z < -tol:
+                el = eh = wm[i]
+            else:
+                el, eh = wm[i], wp[i]
+        l2, h2 = max(ql, el), min(qh, eh)
+        if l2 > h2:
+            worst = max(worst, l2 - h2)
+            l2 = h2 = 0.5 * (l2 + h2)
+        if p >= 0:
+            lo[p] += l2
+            hi[p] += h2
     return worst
