@@ -19,8 +19,9 @@ Also on the same JSON line:
                   200 iterations at 512^2, forward+backward of 65,536 chains of
                   1,024 with per-edge weights, the general chain DP (data weights,
                   asymmetric edge slopes) on the 4096^2 rows and columns, the
-                  TV-l1 chain prox of 65,536 salt & pepper chains, and a batch of
-                  256 uneven images.
+                  TV-l1 chain prox of 65,536 salt & pepper chains, 100 iterations
+                  of 2D TV-l1 at 4096^2, 65,536 trees of 256 nodes, and a batch
+                  of 256 uneven images.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras | --extras LIST]
        python bench.py --rocprof-summary DIR   (print a summary of rocprofv3 output)
@@ -301,6 +302,55 @@ def bench_l1(steps: int, autotune: bool = True):
     return out
 
 
+def bench_tv2d_l1():
+    """2D TV-l1 (Sec. 5.2) on a 4096 x 4096 shapes image with 25% salt & pepper
+    noise, lambda = 0.55, constant steps tau = sigma = 1, FP32: autotuned plans
+    (setup), then 100 iterations timed; FP64 energy at the end."""
+    import numpy as np
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    rng = np.random.default_rng(SEED)
+    f = synth.shapes_image(SIDE, SIDE, sigma=0.0, seed=SEED)
+    m = rng.random(f.shape) < 0.25
+    f[m] = rng.integers(0, 2, int(m.sum()))
+    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    _, info = binding.tv2d_l1(ft, 0.55, max_iter=1, autotune=True)  # setup, not timed
+    e0 = binding.tv2d_l1(ft, 0.55, max_iter=0)[1]["primal"]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, st = binding.tv2d_l1(ft, 0.55, max_iter=100, energy_every=100)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) * 1e3
+    return {"image": "4096x4096 shapes + 25% salt & pepper, lambda 0.55, tau = sigma = 1, FP32",
+            "plans": info.get("plans"), "ms_100_iters": round(dt, 2), "ms_per_iter": round(dt / 100, 3),
+            "energy_f": e0, "energy_100": st["primal"]}
+
+
+def bench_tree(steps: int):
+    """Algorithm 2 on 65,536 random post-order trees of 256 nodes (tv_tree_dp)
+    with a ~ U[0.3, 2], TV-l1 data terms on 70% of the nodes, asymmetric edge
+    slopes, FP32 inputs (FP64 inside).  Algorithmic bytes: parent (8 B), a, b, c,
+    d, w^-, w^+ read and x written (4 B each): 36 B/node."""
+    import numpy as np
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    par, off = synth.post_order_forest(65536, 256, seed=1)
+    g = synth.generator(2)
+    N = par.size
+    a = g.uniform(0.3, 2.0, N)
+    vals = [a, a * g.normal(size=N), g.uniform(0, 1, N) * (g.random(N) < 0.7), g.normal(size=N),
+            -g.uniform(0, 0.8, N), g.uniform(0, 0.8, N)]
+    a_t, b_t, c_t, d_t, wm_t, wp_t = (torch.tensor(v, dtype=torch.float32, device="cuda") for v in vals)
+    pt, ot = torch.tensor(par, device="cuda"), torch.tensor(off, device="cuda")
+    tm = Timer(torch, torch.cuda.current_stream())
+    run = lambda: binding.tree_dp(pt, ot, b_t, wm_t, wp_t, a=a_t, c=c_t, d=d_t)  # noqa: E731
+    run()
+    ms = tm(run, steps)
+    return {"workload": "65536 post-order trees x 256 nodes, a ~ U[0.3,2], l1 terms on 70% of nodes, FP32 in, FP64 DP",
+            "ms": round(ms, 3), "gelem_s": round(N / ms / 1e6, 2),
+            "hbm_frac": round(N * 36 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def bench_batched():
     import numpy as np
     import torch
@@ -432,7 +482,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,batched")
+                    help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -514,6 +564,8 @@ def main():
                 ("general_dp", "general chain DP 4096x4096 rows, cols",
                  lambda: bench_general_dp(10, autotune=not args.no_autotune)),
                 ("tv_l1", "TV-l1 chain prox 65536x1024", lambda: bench_l1(10, autotune=not args.no_autotune)),
+                ("tv2d_l1", "2D TV-l1 4096x4096", bench_tv2d_l1),
+                ("tree", "trees 65536x256", lambda: bench_tree(5)),
                 ("batched", "batched 256 images", bench_batched)]
         pick = None if args.extras == "all" else set(args.extras.split(","))
         try:

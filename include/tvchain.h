@@ -113,7 +113,7 @@ tv_status tv_chain_prox_multi(int num_batches, const tv_chain_layout *layouts, t
 typedef struct {
     int64_t segment_length; /* nodes per segment (lane) of a chain                 */
     int64_t halo;           /* nodes each segment's run starts before the segment  */
-    int ring_slots;         /* breakpoint slots of the on-chip deque (16 or 32)     */
+    int ring_slots;         /* breakpoint slots of the on-chip deque (16 .. 128)    */
     int candidates;         /* plans timed                                          */
     double ms;              /* time of one launch with the chosen plan              */
 } tv_tuning_result;
@@ -209,6 +209,34 @@ tv_status tv_chain_prox_l1_autotune(const tv_chain_layout *layout, tv_dtype dtyp
                                     const void *w, double w_scalar, const void *c, double c_scalar, void *x,
                                     void *workspace, size_t workspace_bytes, hipStream_t stream,
                                     tv_tuning_result *chosen);
+
+/* ---- Trees (Algorithm 2 on a tree, Sec. 4.2's extension to trees) ----
+ *
+ *     x = argmin_x  sum_i ( a_i x_i^2 / 2 - b_i x_i + c_i |x_i - d_i| )
+ *                 + sum_{i not a root} f_i(x_parent(i) - x_i),
+ *     f_i(z) = wm_i z (z < 0), wp_i z (z >= 0),  wm_i <= wp_i,
+ *
+ * on a batch of trees (a chain is the tree with parent(i) = i + 1).  The
+ * message derivative of each node is the sum of its children's clipped
+ * messages plus its unary; breakpoint sets are merged in order.  One tree per
+ * lane, computed in FP64 whatever the dtype.
+ *  offsets : DEVICE int64[num_trees + 1]: tree t is nodes offsets[t] ..
+ *            offsets[t+1]-1 of every per-node array.
+ *  parent  : DEVICE int64[num_nodes]: global index of each node's parent, -1 at
+ *            roots.  Every tree must be numbered in depth-first post-order
+ *            (each subtree a contiguous range ending at its root; a range may
+ *            hold several trees); otherwise TV_ERR_INVALID_ARG is returned
+ *            (detected on the device) and x is unspecified.
+ *  a       : a_i > 0 per node, or NULL for 1.   b : b_i per node.
+ *  c, d    : c_i >= 0 and d_i per node, or both NULL (no l1 term; d alone may be NULL).
+ *  wm, wp  : slopes of the edge from each node to its parent (roots' ignored).
+ *  x       : output per node; must not alias an input.
+ * Synchronous (it reads the post-order check back). */
+size_t tv_tree_dp_workspace(int64_t num_trees, int64_t num_nodes);
+tv_status tv_tree_dp(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const int64_t *offsets,
+                     const int64_t *parent, const void *a, const void *b, const void *c, const void *d,
+                     const void *wm, const void *wp, void *x, void *workspace, size_t workspace_bytes,
+                     hipStream_t stream);
 
 /* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
 size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);
@@ -308,6 +336,32 @@ tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, c
                              tv2d_stats *stats, void *workspace, size_t workspace_bytes,
                              hipStream_t stream);
 
+/* ---- 2D TV-l1 (Sec. 5.2) ----
+ * min_x lambda (TV_h + TV_v)(x) + sum |x - f| on the 4-connected grid, by the
+ * same decomposition: the primal-dual iteration eq. (pd) with constant steps
+ * tau = options->tau0, sigma = 1 / tau, theta = 1 (the data term is not
+ * strongly convex).  Column step: the ROF dual step (Moreau identity,
+ * eq. (prox-tv-conj)).  Row step: the primal prox eq. (prox-pq), per row the
+ * TV-l1 chain prox (tv_chain_prox_l1) of xi = x - tau y' with d = f, c = tau,
+ * w = tau lambda.  x^0 = xbar^0 = f, y^0 = 0.
+ *  options : max_iter iterations are run; every gap_every iterations (and after
+ *            the last) the FP64 energy P(x) = lambda (TV_h + TV_v)(x) + |x - f|_1
+ *            is evaluated, into gap_history[k - 1] if given (DEVICE).  gap_tol
+ *            must be <= 0 and resume 0 (no duality gap is formed for TV-l1);
+ *            use_graph is ignored.
+ *  stats   : iters, status, primal = P(x) of the returned x; dual and gap_norm
+ *            are NaN.
+ * Synchronous; returns TV_ERR_NONFINITE if the energy is not finite. */
+size_t tv2d_l1_workspace(int64_t H, int64_t W, tv_dtype dtype);
+tv_status tv2d_l1_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, void *x,
+                        const tv2d_options *options, tv2d_stats *stats, void *workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+/* Autotuner of the TV-l1 solver's column and row launches (after 8 warm-up
+ * iterations), as tv2d_autotune. */
+tv_status tv2d_l1_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda,
+                           double tau0, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                           tv_tuning_result *col, tv_tuning_result *row);
+
 /* [host] Process-wide tuning of the chain-prox launches.  Each chain of length
  * n is cut into S segments of L nodes that are solved in parallel and then
  * stitched exactly (the result does not depend on the tuning):
@@ -322,11 +376,13 @@ typedef struct {
     int64_t target_lanes;
     int64_t min_segment;
     int64_t halo;
-    int64_t ring_slots;  /* breakpoint slots of the on-chip deque: 16 or 32 */
+    int64_t ring_slots;  /* breakpoint slots of the on-chip deque: 16, 32, 64 or 128
+                          * (over 32 only where entries are 8 bytes, i.e. the FP32
+                          * TV-l2 chain prox and 2D steps; elsewhere it means 32) */
 } tv_tuning;
 
 /* Set the tuning (NULL restores the defaults); TV_ERR_INVALID_ARG on values < 1
- * or a ring size other than 16 or 32.
+ * or a ring size other than 16, 32, 64 or 128.
  * Not thread-safe with respect to concurrent prox calls: a workspace sized
  * before a change may be too small after it (TV_ERR_WORKSPACE). */
 tv_status tv_set_tuning(const tv_tuning *tuning);

@@ -98,6 +98,14 @@ _SIG = {
                                         _P, ctypes.c_size_t, _P]),
     "tv_chain_prox_l1_autotune": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P,
                                                  ctypes.c_double, _P, _P, ctypes.c_size_t, _P, _P]),
+    "tv2d_l1_workspace": (ctypes.c_size_t, [_I64, _I64, ctypes.c_int]),
+    "tv2d_l1_solve": (ctypes.c_int, [ctypes.c_int, _P, _I64, _I64, _I64, ctypes.c_double, _P, _P, _P, _P,
+                                     ctypes.c_size_t, _P]),
+    "tv2d_l1_autotune": (ctypes.c_int, [ctypes.c_int, _P, _I64, _I64, _I64, ctypes.c_double, ctypes.c_double, _P,
+                                        ctypes.c_size_t, _P, _P, _P]),
+    "tv_tree_dp_workspace": (ctypes.c_size_t, [_I64, _I64]),
+    "tv_tree_dp": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                  _P]),
     "tv_chain_dp_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "tv_chain_dp": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "tv_chain_dp_autotune": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
@@ -615,3 +623,61 @@ def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol
     infos = [{"iters": s.iters, "status": s.status, "gap_norm": s.gap_norm, "primal": s.primal, "dual": s.dual}
              for s in stats]
     return outs, infos
+
+
+def tv2d_l1(f: torch.Tensor, lam: float, max_iter: int = 200, energy_every: int = 10, tau0: float = 1.0,
+            energy_history: Optional[torch.Tensor] = None, autotune: bool = False):
+    """2D TV-l1, min_x lam (TV_h + TV_v)(x) + |x - f|_1, by the row/column
+    decomposition (tv2d_l1_solve, Sec. 5.2).  Returns (x, stats) with
+    stats["primal"] the FP64 energy of x; with ``autotune`` the launch plans are
+    tuned first and stats["plans"] holds them."""
+    _require_gpu(f)
+    lib = load()
+    H, W = f.shape
+    f = f.contiguous()
+    code = _dtype_code(f)
+    nbytes = lib.tv2d_l1_workspace(H, W, code)
+    ws = _workspace(nbytes, f.device)
+    stream = ctypes.c_void_p(_stream_ptr(f.device))
+    plans = None
+    if autotune:
+        col, row = TuningResult(), TuningResult()
+        _check(lib.tv2d_l1_autotune(code, _ptr(f), H, W, W, float(lam), float(tau0), _ptr(ws), nbytes, stream,
+                                    ctypes.byref(col), ctypes.byref(row)), "tv2d_l1_autotune")
+        plans = {"col": col.as_dict(), "row": row.as_dict()}
+    x = torch.empty_like(f)
+    opt = Tv2dOptions(int(max_iter), int(energy_every), 0.0, float(tau0), 0,
+                      ctypes.c_void_p(energy_history.data_ptr()) if energy_history is not None else None, 0)
+    st = Tv2dStats()
+    _check(lib.tv2d_l1_solve(code, _ptr(f), H, W, W, float(lam), _ptr(x), ctypes.byref(opt), ctypes.byref(st),
+                             _ptr(ws), nbytes, stream), "tv2d_l1_solve")
+    info = {"iters": st.iters, "status": st.status, "primal": st.primal}
+    if plans is not None:
+        info["plans"] = plans
+    return x, info
+
+
+def tree_dp(parent: torch.Tensor, offsets: torch.Tensor, b: torch.Tensor, wm: torch.Tensor, wp: torch.Tensor,
+            a: Optional[torch.Tensor] = None, c: Optional[torch.Tensor] = None,
+            d: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Algorithm 2 on a batch of trees (tv_tree_dp): parent (int64, -1 at roots,
+    each tree numbered in depth-first post-order), offsets (int64, num_trees + 1
+    node ranges), per-node b, wm, wp and optional a, c, d (1-D tensors of one
+    float dtype).  Returns x."""
+    _require_gpu(parent, offsets, b, wm, wp)
+    lib = load()
+    if parent.dtype != torch.int64 or offsets.dtype != torch.int64:
+        raise TvChainError(TV_ERR_INVALID_ARG, "parent and offsets must be int64")
+    ts = [t.contiguous() if t is not None else None for t in (a, b, c, d, wm, wp)]
+    for t in ts:
+        if t is not None and (t.dtype != b.dtype or t.shape != b.shape):
+            raise TvChainError(TV_ERR_INVALID_ARG, "per-node arrays must match b")
+    parent, offsets = parent.contiguous(), offsets.contiguous()
+    T, N = offsets.numel() - 1, b.numel()
+    x = torch.empty_like(ts[1])
+    nbytes = lib.tv_tree_dp_workspace(T, N)
+    ws = _workspace(nbytes, b.device)
+    st = lib.tv_tree_dp(_dtype_code(b), T, N, _ptr(offsets), _ptr(parent), *(_ptr(t) for t in ts), _ptr(x), _ptr(ws),
+                        nbytes, ctypes.c_void_p(_stream_ptr(b.device)))
+    _check(st, "tv_tree_dp")
+    return x

@@ -389,6 +389,39 @@ tv_status tv_chain_prox_l1_autotune(const tv_chain_layout *layout, tv_dtype dtyp
     return TV_OK;
 }
 
+// ---- trees ----
+
+size_t tv_tree_dp_workspace(int64_t num_trees, int64_t num_nodes) {
+    if (num_trees < 1 || num_nodes < 1) return 0;
+    return tree_dp_ws_bytes(num_trees, num_nodes);
+}
+
+tv_status tv_tree_dp(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const int64_t *offsets,
+                     const int64_t *parent, const void *a, const void *b, const void *c, const void *d,
+                     const void *wm, const void *wp, void *x, void *workspace, size_t workspace_bytes,
+                     hipStream_t stream) {
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (num_trees < 0 || num_nodes < 0) return TV_ERR_INVALID_ARG;
+    if (num_trees == 0 || num_nodes == 0) return TV_OK;
+    if (!offsets || !parent || !b || !wm || !wp || !x || (c && !d)) return TV_ERR_INVALID_ARG;
+    if (x == a || x == b || x == c || x == d || x == wm || x == wp) return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < tv_tree_dp_workspace(num_trees, num_nodes)) return TV_ERR_WORKSPACE;
+    tv_status st = device_check();
+    if (st != TV_OK) return st;
+    int bad = 0;
+    hipError_t e;
+    if (dtype == TV_F32)
+        e = launch_tree_dp<float>(num_trees, num_nodes, offsets, parent, (const float *)a, (const float *)b,
+                                  (const float *)c, (const float *)d, (const float *)wm, (const float *)wp,
+                                  (float *)x, workspace, &bad, stream);
+    else
+        e = launch_tree_dp<double>(num_trees, num_nodes, offsets, parent, (const double *)a, (const double *)b,
+                                   (const double *)c, (const double *)d, (const double *)wm, (const double *)wp,
+                                   (double *)x, workspace, &bad, stream);
+    if (e != hipSuccess) return TV_ERR_HIP;
+    return bad ? TV_ERR_INVALID_ARG : TV_OK;
+}
+
 static_assert(kMaxChainBatches == TV_MAX_CHAIN_BATCHES, "batch limit of the ABI");
 
 static bool multi_ok(int nb, const tv_chain_layout *layouts, tv_dtype dtype, int64_t *C, int64_t *n) {
@@ -505,7 +538,8 @@ tv_status tv_set_tuning(const tv_tuning *t) {
         return TV_OK;
     }
     if (t->target_lanes < 1 || t->min_segment < 1 || t->halo < 0) return TV_ERR_INVALID_ARG;
-    if (t->ring_slots != 16 && t->ring_slots != 32) return TV_ERR_INVALID_ARG;
+    if (t->ring_slots != 16 && t->ring_slots != 32 && t->ring_slots != 64 && t->ring_slots != 128)
+        return TV_ERR_INVALID_ARG;
     seg_tuning() = SegTuning{t->target_lanes, t->min_segment, t->halo, t->ring_slots};
     return TV_OK;
 }

@@ -572,8 +572,8 @@ size_t chain_prox_ws_bytes(const ChainBatch &b, const SegPlan &plan) {
 }
 
 // Autotuner candidates: segment lengths 32 .. 1024, halos 32, 64 and 128, rings of
-// 16 or 32 slots (32 only where segments are at least 4 times longer, to bound
-// the saved deques), keeping only plans whose workspace stays within twice the
+// 16, 32, 64 or 128 slots (more than 16 only where segments are at least 4
+// times longer, to bound the saved deques; over 32 only for 8-byte entries), keeping only plans whose workspace stays within twice the
 // default plan's (or the default's plus 64 MiB).  Segment lengths at or above
 // the chain length are all the same plan; only the shortest is kept.
 template <typename T, typename G>
@@ -587,8 +587,9 @@ int seg_candidates(int64_t C, int64_t n, SegPlan *out, int max_out) {
     for (int64_t L = 32; L <= 1024 && !whole; L *= 2) {
         const int64_t Lr = (L >= n) ? ((n + kTile - 1) / kTile) * kTile : L;
         whole = L >= n;
-        for (int K = 16; K <= 32; K *= 2) {
+        for (int K = 16; K <= 128; K *= 2) {
             if (K * 4 > Lr && K > 16) continue;
+            if (K > ring_max<T, G>()) continue;
             for (int64_t H = 32; H <= 128; H *= 2) {
                 const SegPlan p{Lr, H, 16, K};
                 if (seg_ws_bytes<T, G>(C, n, p) > cap) continue;

@@ -25,7 +25,7 @@ struct ChainBatch {
 
 // Segmentation of a launch: segment length L (S = ceil(n / L) segments per
 // chain), halo H run before each segment, checkpoint spacing CK, and the
-// number K of breakpoint slots of the LDS ring (16 or 32).
+// number K of breakpoint slots of the LDS ring (16, 32; 64 or 128 for 8-byte entries).
 struct SegPlan {
     int64_t L;
     int64_t H;
@@ -43,7 +43,8 @@ enum PlanKind {
     kPlanBatchRow = 4,
     kPlanDp = 5,
     kPlanL1 = 6,
-    kPlanKinds = 7
+    kPlan2dRowL1 = 7,
+    kPlanKinds = 8
 };
 
 // Process-wide tuning: target lanes per launch, shortest segment, halo.
@@ -103,6 +104,14 @@ size_t chain_l1_ws_bytes(int64_t num_chains, int64_t n);
 template <typename T>
 hipError_t launch_chain_l1(const ChainBatch &b, const T *y, const T *d, const T *w, T w_scalar, const T *c,
                            T c_scalar, T *x, void *workspace, hipStream_t stream);
+
+// Algorithm 2 on a batch of trees (see tv_tree_dp); the launch reads the
+// post-order check back into *bad_host and synchronizes the stream.
+size_t tree_dp_ws_bytes(int64_t num_trees, int64_t num_nodes);
+template <typename T>
+hipError_t launch_tree_dp(int64_t num_trees, int64_t num_nodes, const int64_t *offsets, const int64_t *parent,
+                          const T *a, const T *b, const T *c, const T *d, const T *wm, const T *wp, T *x,
+                          void *workspace, int *bad_host, hipStream_t stream);
 
 template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,

@@ -1049,13 +1049,14 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
 
 // ---------------------------------------------------------------------------
 // Overflowed chains, solved sequentially by a bounded pool of lanes: first with
-// a 64 KiB per-wave LDS ring (64 slots of 8-byte entries, 32 of 16-byte ones),
-// and only if the deque outgrows that too, with the deque in HBM (lane l owns
-// deque storage l).  Both paths compute the same bits as the segmented one.
+// the largest LDS ring a workgroup may hold (160 KiB on gfx950: 256 slots of
+// 8-byte entries, 128 of 16-byte ones, 64 of 32-byte ones), and only if the
+// deque outgrows that too, with the deque in HBM (lane l owns deque storage
+// l).  Both paths compute the same results as the segmented one.
 // ---------------------------------------------------------------------------
 template <class E> struct OvfRing {
-    static constexpr int fit(int k) { return (k + kScanWindow) * 64 * (int)sizeof(E) <= 65536 ? k : fit(k / 2); }
-    static constexpr int K = fit(256);
+    static constexpr int fit(int k) { return (k + kScanWindow) * 64 * (int)sizeof(E) <= 163840 ? k : fit(k / 2); }
+    static constexpr int K = fit(512);
 };
 
 template <typename T, class Prob>
@@ -1188,18 +1189,50 @@ hipError_t seg_launch(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, 
     return hipGetLastError();
 }
 
+// Ring sizes a launch may use: 16 and 32 slots, and 64 or 128 for 8-byte
+// entries (35 / 68 KiB rings per wave; gfx950 gives a workgroup up to 160 KiB).
+template <typename T, typename G>
+constexpr int ring_max() {
+    return sizeof(Ent<T, G>) <= 8 ? 128 : 32;
+}
+template <typename T, typename G>
+constexpr bool ring64_ok() {
+    return ring_max<T, G>() >= 64;
+}
+template <typename T, typename G>
+__host__ __device__ constexpr int ring_slots_for(int K) {
+    const int k = K >= 128 ? 128 : (K >= 64 ? 64 : (K >= 32 ? 32 : 16));
+    return k > ring_max<T, G>() ? ring_max<T, G>() : k;
+}
+
 // Workspace bytes and launch for a plan, dispatching on its ring size.
 template <typename T, typename G = T>
 size_t seg_ws_bytes(int64_t C, int64_t n, const SegPlan &p) {
-    return p.K == 32 ? seg_ws_layout<T, 32, G>(nullptr, C, n, p.L, p.H, p.CK, nullptr)
-                     : seg_ws_layout<T, 16, G>(nullptr, C, n, p.L, p.H, p.CK, nullptr);
+    switch (ring_slots_for<T, G>(p.K)) {
+    case 128: return seg_ws_layout<T, 128, G>(nullptr, C, n, p.L, p.H, p.CK, nullptr);
+    case 64: return seg_ws_layout<T, 64, G>(nullptr, C, n, p.L, p.H, p.CK, nullptr);
+    case 32: return seg_ws_layout<T, 32, G>(nullptr, C, n, p.L, p.H, p.CK, nullptr);
+    default: return seg_ws_layout<T, 16, G>(nullptr, C, n, p.L, p.H, p.CK, nullptr);
+    }
 }
 
 template <typename T, class Prob, int P>
 hipError_t seg_run(void *workspace, int64_t C, int64_t n, const SegPlan &p, const typename Prob::Params &pp,
                    hipStream_t stream) {
+    using G = typename Prob::Tag;
     WsOf<T, Prob> ws;
-    if (p.K == 32) {
+    const int K = ring_slots_for<T, G>(p.K);
+    if constexpr (ring_max<T, G>() >= 128) {
+        if (K == 128) {
+            seg_ws_layout<T, 128>(workspace, C, n, p.L, p.H, p.CK, &ws);
+            return seg_launch<T, Prob, 128, P>(ws, pp, stream);
+        }
+        if (K == 64) {
+            seg_ws_layout<T, 64>(workspace, C, n, p.L, p.H, p.CK, &ws);
+            return seg_launch<T, Prob, 64, P>(ws, pp, stream);
+        }
+    }
+    if (K == 32) {
         seg_ws_layout<T, 32>(workspace, C, n, p.L, p.H, p.CK, &ws);
         return seg_launch<T, Prob, 32, P>(ws, pp, stream);
     }

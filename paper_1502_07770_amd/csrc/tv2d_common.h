@@ -98,16 +98,17 @@ hipError_t time_calls(Fn fn, hipStream_t st, int reps, float *ms) {
     return e;
 }
 
-// Picks the fastest candidate plan of one launch; fills res.
-template <typename T, class Fn>
+// Picks the fastest candidate plan of one launch; fills res.  G is the tag
+// type of the launch's deque entries.
+template <typename T, typename G = T, class Fn>
 tv_status tune_launch(int64_t C, int64_t n, size_t seg_bytes, Fn launch, hipStream_t st, SegPlan *best_plan,
                              tv_tuning_result *res) {
     SegPlan cand[64];
-    const int m = seg_candidates<T>(C, n, cand, 64);
+    const int m = seg_candidates<T, G>(C, n, cand, 64);
     int best = -1, tried = 0;
     float best_ms = 0.0f;
     for (int j = 0; j < m; ++j) {
-        if (seg_ws_bytes_plan<T>(C, n, cand[j]) > seg_bytes) continue;
+        if (seg_ws_bytes_plan<T, G>(C, n, cand[j]) > seg_bytes) continue;
         float ms = 0.0f;
         if (time_calls([&]() { return launch(cand[j]); }, st, 3, &ms) != hipSuccess) return TV_ERR_HIP;
         ++tried;

@@ -371,11 +371,12 @@ struct Tv2dWs {
 };
 
 template <typename T>
-static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out) {
+static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out, bool l1 = false) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t N = (size_t)(H * W);
     // room for any plan the autotuner may choose for the row and column launches
-    const size_t sr = seg_bytes_max<T>(H, W, kPlan2dRow);
+    // (TV-l1 rows keep (lambda, tag, jump) sets)
+    const size_t sr = l1 ? seg_bytes_max<T, TagJ<T>>(H, W, kPlan2dRowL1) : seg_bytes_max<T>(H, W, kPlan2dRow);
     const size_t scol = seg_bytes_max<T>(W, H, kPlan2dCol);
     const size_t nparts = (size_t)H;
     const size_t ncol = (size_t)(((H + kGapRows - 1) / kGapRows) * W);
@@ -587,6 +588,194 @@ static tv_status tv2d_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld, d
     return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
 
+// ---------------------------------------------------------------------------
+// TV-l1 (Sec. 5.2): min_x lambda (TV_h + TV_v)(x) + |x - f|_1, eq. (pd) with
+// constant steps (tau, sigma = 1 / tau, theta = 1).  The column step is the
+// ROF one; the row step is the primal prox eq. (prox-pq) times tau, i.e. per
+// row the TV-l1 chain prox argmin tau lambda TV + tau |x - f|_1 + |x - xi|^2/2
+// with xi = x - tau y', formed in the loads; xbar in the stores.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RowL1Prob {
+    using Tag = TagJ<T>;
+    static constexpr bool kGen = false;
+    static constexpr bool kL1 = true;
+    using Params = typename RowProb<T>::Params;
+    using Pre = typename RowProb<T>::Pre;
+    using SinkPre = typename RowProb<T>::SinkPre;
+    using Sink = typename RowProb<T>::Sink;
+    struct Src : RowProb<T>::Src {
+        using Base = typename RowProb<T>::Src;
+        __device__ __forceinline__ Src(const Base &b) : Base(b) {}
+        __device__ __forceinline__ T data(const Pre &p) const { return p.x - this->tau * p.y; }
+        __device__ __forceinline__ T dval(const Pre &p) const { return p.f; }
+        __device__ __forceinline__ T cval(const Pre &) const { return this->tau; }
+        __device__ __forceinline__ T weight(const Pre &) const { return this->w; }
+    };
+    static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t r, int64_t nmax) {
+        return RowProb<T>::span(p, r, nmax);
+    }
+    static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) {
+        const IterSched sc = *p.sc;
+        // c = tau, w = tau lambda (inv1p slot unused)
+        return Src(typename RowProb<T>::Src{p.f, p.x_old, p.y, (T)sc.tau, (T)0, (T)(p.lam * sc.tau), sp.base, p.ldf,
+                                            p.W});
+    }
+    static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) {
+        return RowProb<T>::sink(p, sp);
+    }
+};
+
+template <typename T>
+static hipError_t tv2d_l1_row_step(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
+                                   int cur, const IterSched *sc, const SegPlan &pr, hipStream_t st) {
+    const int nxt = cur ^ 1;
+    typename RowL1Prob<T>::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, sc, lam, W};
+    return seg_run<T, RowL1Prob<T>, kTile>(ws.seg, H, W, pr, pp, st);
+}
+
+// TV-l1 energy lambda (TV_h + TV_v)(x) + |x - f|_1 in FP64: one wave per row
+// (lanes over columns, butterfly sum), then one block over the rows in a fixed
+// order.
+template <typename T>
+__global__ __launch_bounds__(kGapBlock) void k_l1_energy_rows(const T *__restrict__ x, const T *__restrict__ f,
+                                                              int64_t ldf, int64_t H, int64_t W, double lam,
+                                                              double *__restrict__ part) {
+    const int64_t r = (int64_t)blockIdx.x * (kGapBlock / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (r >= H) return;
+    double acc = 0.0;
+    for (int64_t c = lane; c < W; c += 64) {
+        const double v = (double)x[r * W + c];
+        acc += fabs(v - (double)f[r * ldf + c]);
+        if (c + 1 < W) acc += lam * fabs((double)x[r * W + c + 1] - v);
+        if (r + 1 < H) acc += lam * fabs((double)x[(r + 1) * W + c] - v);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) part[r] = acc;
+}
+
+__global__ __launch_bounds__(kGapBlock) void k_l1_energy_final(const double *__restrict__ part, int64_t H,
+                                                               double *__restrict__ out, double *__restrict__ hist,
+                                                               int64_t hist_at) {
+    __shared__ double s[kGapBlock];
+    double acc = 0.0;
+    for (int64_t r = threadIdx.x; r < H; r += kGapBlock) acc += part[r];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kGapBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out = s[0];
+        if (hist && hist_at >= 0) hist[hist_at] = s[0];
+    }
+}
+
+template <typename T>
+static hipError_t tv2d_l1_energy(const Tv2dWs<T> &ws, const T *x, const T *f, int64_t ldf, int64_t H, int64_t W,
+                                 double lam, double *hist, int64_t hist_at, hipStream_t st) {
+    const unsigned rb = (unsigned)((H + kGapBlock / 64 - 1) / (kGapBlock / 64));
+    hipLaunchKernelGGL((k_l1_energy_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, x, f, ldf, H, W, lam, ws.part);
+    hipLaunchKernelGGL(k_l1_energy_final, dim3(1), dim3(kGapBlock), 0, st, ws.part, H, &ws.hdr->gap[0], hist,
+                       hist_at);
+    return hipGetLastError();
+}
+
+// Constant-step schedule: tau, sigma = 1/tau, theta = 1.
+static IterSched l1_sched(double tau, int64_t k) {
+    IterSched s;
+    s.tau = tau;
+    s.sigma = 1.0 / tau;
+    s.theta = 1.0;
+    s.inv1p = 0.0;
+    s.pscale = 0.0;
+    s.iter_after = k + 1;
+    return s;
+}
+
+template <typename T>
+static tv_status tv2d_l1_init(const T *f, int64_t H, int64_t W, int64_t ld, double tau, const Tv2dWs<T> &ws,
+                              hipStream_t st) {
+    const unsigned nb = (unsigned)((H * W + 255) / 256);
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
+    hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
+    const IterSched sc = l1_sched(tau, 0);  // the same scalars every iteration
+    if (hipMemcpyAsync(ws.sched, &sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
+    return hipGetLastError() == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+template <typename T>
+static tv_status tv2d_l1_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, double lam, T *x,
+                                 const tv2d_options *opt, tv2d_stats *stats, void *workspace, hipStream_t st) {
+    Tv2dWs<T> ws;
+    tv2d_layout<T>(workspace, H, W, &ws, true);
+    tv_status s = tv2d_l1_init<T>(f, H, W, ld, opt->tau0, ws, st);
+    if (s != TV_OK) return s;
+    const SegPlan pc = seg_plan(W, H, kPlan2dCol), pr = seg_plan(H, W, kPlan2dRowL1);
+    if (seg_ws_bytes_plan<T>(W, H, pc) > ws.seg_bytes || seg_ws_bytes_plan<T, TagJ<T>>(H, W, pr) > ws.seg_bytes)
+        return TV_ERR_WORKSPACE;
+    const int every = opt->gap_every > 0 ? opt->gap_every : 1;
+    int cur = 0;
+    for (int k = 0; k < opt->max_iter; ++k) {
+        if (tv2d_col_step<T>(ws, H, W, lam, cur, ws.sched, pc, st) != hipSuccess) return TV_ERR_HIP;
+        if (tv2d_l1_row_step<T>(ws, f, ld, H, W, lam, cur, ws.sched, pr, st) != hipSuccess) return TV_ERR_HIP;
+        cur ^= 1;
+        if ((k + 1) % every == 0 || k + 1 == opt->max_iter) {
+            if (tv2d_l1_energy<T>(ws, ws.x[cur], f, ld, H, W, lam, opt->gap_history, k, st) != hipSuccess)
+                return TV_ERR_HIP;
+        }
+    }
+    double P = NAN;
+    if (opt->max_iter == 0 && tv2d_l1_energy<T>(ws, ws.x[0], f, ld, H, W, lam, nullptr, -1, st) != hipSuccess)
+        return TV_ERR_HIP;
+    if (hipMemcpyAsync(&P, &ws.hdr->gap[0], sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return TV_ERR_HIP;
+    const unsigned nb = (unsigned)((H * W + 255) / 256);
+    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, ws.x[cur], W, x, ld, H, W);
+    if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
+    const int status = isfinite(P) ? TV_OK : TV_ERR_NONFINITE;
+    if (stats) {
+        stats->iters = opt->max_iter;
+        stats->status = status;
+        stats->primal = P;
+        stats->dual = NAN;
+        stats->gap_norm = NAN;
+    }
+    return (tv_status)status;
+}
+
+template <typename T>
+static tv_status tv2d_l1_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld, double lam, double tau0,
+                                    void *workspace, hipStream_t st, tv_tuning_result *col, tv_tuning_result *row) {
+    Tv2dWs<T> ws;
+    tv2d_layout<T>(workspace, H, W, &ws, true);
+    tv_status s = tv2d_l1_init<T>(f, H, W, ld, tau0, ws, st);
+    if (s != TV_OK) return s;
+    // a few iterations first, so the plans are timed on later-iteration data
+    const SegPlan pc0 = seg_plan(W, H, kPlan2dCol), pr0 = seg_plan(H, W, kPlan2dRowL1);
+    for (int k = 0; k < kTuneWarm; ++k) {
+        if (tv2d_col_step<T>(ws, H, W, lam, k & 1, ws.sched, pc0, st) != hipSuccess) return TV_ERR_HIP;
+        if (tv2d_l1_row_step<T>(ws, f, ld, H, W, lam, k & 1, ws.sched, pr0, st) != hipSuccess) return TV_ERR_HIP;
+    }
+    SegPlan pc, pr;
+    s = tune_launch<T>(
+        W, H, ws.seg_bytes, [&](const SegPlan &p) { return tv2d_col_step<T>(ws, H, W, lam, 0, ws.sched, p, st); },
+        st, &pc, col);
+    if (s != TV_OK) return s;
+    if (tv2d_col_step<T>(ws, H, W, lam, 0, ws.sched, pc, st) != hipSuccess) return TV_ERR_HIP;
+    s = tune_launch<T, TagJ<T>>(
+        H, W, ws.seg_bytes,
+        [&](const SegPlan &p) { return tv2d_l1_row_step<T>(ws, f, ld, H, W, lam, 0, ws.sched, p, st); }, st, &pr,
+        row);
+    if (s != TV_OK) return s;
+    seg_set_tuned(kPlan2dCol, W, H, pc);
+    seg_set_tuned(kPlan2dRowL1, H, W, pr);
+    return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
 }  // namespace tvc
 
 using namespace tvc;
@@ -613,6 +802,49 @@ tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_
     if (dtype == TV_F32)
         return tv2d_solve_t<float>((const float *)f, H, W, ld, lambda, (float *)x, options, stats, workspace, stream);
     return tv2d_solve_t<double>((const double *)f, H, W, ld, lambda, (double *)x, options, stats, workspace, stream);
+}
+
+size_t tv2d_l1_workspace(int64_t H, int64_t W, tv_dtype dtype) {
+    if (H < 1 || W < 1 || (dtype != TV_F32 && dtype != TV_F64)) return 0;
+    return dtype == TV_F32 ? tv2d_layout<float>(nullptr, H, W, nullptr, true)
+                           : tv2d_layout<double>(nullptr, H, W, nullptr, true);
+}
+
+static tv_status l1_args(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, double tau0,
+                         void *workspace, size_t workspace_bytes) {
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (!f || H < 1 || W < 1 || ld < W) return TV_ERR_INVALID_ARG;
+    if (!(isfinite(lambda) && lambda >= 0.0) || !(tau0 > 0.0) || !isfinite(tau0)) return TV_ERR_INVALID_ARG;
+    const int64_t lim = (dtype == TV_F32) ? (int64_t(1) << 24) : (int64_t(1) << 31) - 8;
+    if (H >= lim || W >= lim) return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < tv2d_l1_workspace(H, W, dtype)) return TV_ERR_WORKSPACE;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
+    return TV_OK;
+}
+
+tv_status tv2d_l1_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, void *x,
+                        const tv2d_options *options, tv2d_stats *stats, void *workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+    if (!x || !options) return TV_ERR_INVALID_ARG;
+    if (options->max_iter < 0 || options->resume || options->gap_tol > 0.0) return TV_ERR_INVALID_ARG;
+    const tv_status s = l1_args(dtype, f, H, W, ld, lambda, options->tau0, workspace, workspace_bytes);
+    if (s != TV_OK) return s;
+    if (dtype == TV_F32)
+        return tv2d_l1_solve_t<float>((const float *)f, H, W, ld, lambda, (float *)x, options, stats, workspace,
+                                      stream);
+    return tv2d_l1_solve_t<double>((const double *)f, H, W, ld, lambda, (double *)x, options, stats, workspace,
+                                   stream);
+}
+
+tv_status tv2d_l1_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda,
+                           double tau0, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                           tv_tuning_result *col, tv_tuning_result *row) {
+    const tv_status s = l1_args(dtype, f, H, W, ld, lambda, tau0, workspace, workspace_bytes);
+    if (s != TV_OK) return s;
+    if (dtype == TV_F32)
+        return tv2d_l1_autotune_t<float>((const float *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
+    return tv2d_l1_autotune_t<double>((const double *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
 }
 
 tv_status tv2d_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, double tau0,

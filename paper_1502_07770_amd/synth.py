@@ -26,6 +26,11 @@ experiments, Figs. 5 and 6):
 * ``salt_pepper_chains``: piecewise-constant chains (levels U[0, 1], no
   Gaussian noise) with a fraction of the samples (25%) replaced by 0 or 1 with
   probability 1/2 each -- impulse noise, the TV-l1 model's setting (Sec. 5.2).
+* ``post_order_forest``: num_trees random trees of n nodes each, numbered in
+  depth-first post-order: node j adopts k of the pending subtree roots (the
+  most recent ones), k in {0, 1, 2, 3} with probabilities 0.4, 0.3, 0.2, 0.1
+  (at most the number pending), and the last node adopts all that remain.
+  Returns (parent with global indices and -1 at roots, offsets).
 * ``edge_weights`` (U[lo, hi]) and ``normal`` (N(0, 1)) helpers.
 """
 from __future__ import annotations
@@ -136,3 +141,28 @@ def salt_pepper_chains(num_chains: int, n: int, frac: float = 0.25, seed: int = 
     m = g.random(f.shape) < frac
     f[m] = g.integers(0, 2, int(m.sum())).astype(np.float64)
     return f
+
+
+def post_order_forest(num_trees: int, n: int, seed: int = 0):
+    """Random post-order trees (see the module docstring)."""
+    g = generator(seed)
+    T = int(num_trees)
+    parent = np.full((T, n), -1, dtype=np.int64)
+    stack = np.zeros((T, n), dtype=np.int64)
+    sp = np.zeros(T, dtype=np.int64)
+    rows = np.arange(T)
+    for j in range(n - 1):
+        k = np.minimum(g.choice(4, size=T, p=[0.4, 0.3, 0.2, 0.1]), sp)
+        for r in range(3):
+            m = k > r
+            parent[rows[m], stack[rows[m], sp[m] - 1]] = j
+            sp[m] -= 1
+        stack[rows, sp] = j
+        sp += 1
+    pending = np.arange(n)[None, :] < sp[:, None]
+    tt, cc = np.nonzero(pending)
+    parent[tt, stack[tt, cc]] = n - 1
+    base = (np.arange(T, dtype=np.int64) * n)[:, None]
+    glob = np.where(parent >= 0, parent + base, -1).reshape(-1)
+    offsets = np.arange(T + 1, dtype=np.int64) * n
+    return glob, offsets

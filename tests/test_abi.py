@@ -55,6 +55,11 @@ def test_tuning_round_trip_and_rejections(lib):
         assert lib.tv_set_tuning(ctypes.byref(bad)) == binding.TV_ERR_INVALID_ARG
         bad = binding.Tuning(4096, 1, 0, 24)
         assert lib.tv_set_tuning(ctypes.byref(bad)) == binding.TV_ERR_INVALID_ARG
+        bad = binding.Tuning(4096, 1, 0, 256)
+        assert lib.tv_set_tuning(ctypes.byref(bad)) == binding.TV_ERR_INVALID_ARG
+        for k in (16, 32, 64, 128):
+            binding.set_tuning(target_lanes=4096, min_segment=32, halo=40, ring_slots=k)
+            assert binding.get_tuning()["ring_slots"] == k
         assert lib.tv_get_tuning(None) == binding.TV_ERR_INVALID_ARG
     finally:
         binding.set_tuning(**saved)
@@ -162,6 +167,38 @@ def test_chain_prox_l1_argument_errors(lib):
         assert f(ctypes.byref(rows), 0, y, d, w, 0.1, c, 1.0, alias, ws, big, None) == binding.TV_ERR_INVALID_ARG
     assert f(ctypes.byref(rows), 0, y, d, w, 0.1, c, 1.0, x, None, 0, None) == binding.TV_ERR_WORKSPACE
     assert f(ctypes.byref(rows), 0, y, d, w, 0.1, c, 1.0, x, ws, 64, None) == binding.TV_ERR_WORKSPACE
+
+
+def test_tv2d_l1_argument_errors(lib):
+    P = ctypes.c_void_p
+    buf, ws = P(0x10000000), P(0x30000000)
+    assert lib.tv2d_l1_workspace(64, 48, binding.TV_F32) > lib.tv2d_workspace(64, 48, binding.TV_F32)
+    assert lib.tv2d_l1_workspace(0, 48, binding.TV_F32) == 0
+    ok = binding.Tv2dOptions(5, 1, 0.0, 1.0, 0, None, 0)
+    solve = lib.tv2d_l1_solve
+    big = 1 << 30
+    assert solve(0, buf, 64, 48, 40, 0.5, buf, ctypes.byref(ok), None, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    assert solve(0, buf, 64, 48, 48, -0.5, buf, ctypes.byref(ok), None, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    assert solve(0, buf, 64, 48, 48, 0.5, None, ctypes.byref(ok), None, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    for bad in (binding.Tv2dOptions(5, 1, 1e-3, 1.0, 0, None, 0), binding.Tv2dOptions(5, 1, 0.0, 1.0, 1, None, 0),
+                binding.Tv2dOptions(5, 1, 0.0, float("nan"), 0, None, 0)):
+        assert solve(0, buf, 64, 48, 48, 0.5, buf, ctypes.byref(bad), None, ws, big, None) == binding.TV_ERR_INVALID_ARG
+    assert solve(0, buf, 64, 48, 48, 0.5, buf, ctypes.byref(ok), None, ws, 16, None) == binding.TV_ERR_WORKSPACE
+    assert lib.tv2d_l1_autotune(0, buf, 64, 48, 48, 0.5, 0.0, ws, big, None, None, None) == binding.TV_ERR_INVALID_ARG
+
+
+def test_tree_dp_argument_errors(lib):
+    P = ctypes.c_void_p
+    buf, x = P(0x10000000), P(0x20000000)
+    assert lib.tv_tree_dp_workspace(10, 100) > 0
+    assert lib.tv_tree_dp_workspace(0, 100) == 0
+    f = lib.tv_tree_dp
+    assert f(0, 1, 4, None, buf, None, buf, None, None, buf, buf, x, buf, 1 << 20, None) == binding.TV_ERR_INVALID_ARG
+    assert f(0, 1, 4, buf, buf, None, buf, buf, None, buf, buf, x, buf, 1 << 20, None) == binding.TV_ERR_INVALID_ARG
+    assert f(0, 1, 4, buf, buf, None, buf, None, None, buf, buf, buf, buf, 1 << 20, None) == binding.TV_ERR_INVALID_ARG
+    assert f(7, 1, 4, buf, buf, None, buf, None, None, buf, buf, x, buf, 1 << 20, None) == binding.TV_ERR_INVALID_ARG
+    assert f(0, 1, 4, buf, buf, None, buf, None, None, buf, buf, x, None, 0, None) == binding.TV_ERR_WORKSPACE
+    assert f(0, 0, 0, None, None, None, None, None, None, None, None, None, None, 0, None) == binding.TV_OK
 
 
 def test_workspace_covers_every_autotune_candidate(lib):

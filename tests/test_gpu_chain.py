@@ -110,9 +110,9 @@ def test_deep_deque_takes_exact_fallback(dtype):
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_overflow_tiers_match_the_ring_path(tuning, dtype):
     """Deques of depth 17..112: with a 16-slot ring they overflow into the
-    large-ring sequential pass (up to 64 slots for float, 32 for double) or,
-    deeper still, into the HBM deque; with a 32-slot ring the shallower ones
-    stay on the segmented path.  Every route gives the same bits."""
+    large-ring sequential pass (up to 256 slots for float, 128 for double) or,
+    deeper still, into the HBM deque; with 32, 64 or 128-slot rings more of
+    them stay on the segmented path.  Every route gives the same bits."""
     n = 1024
     rows, ws = [], []
     for k, wv in enumerate((1.0, 3.0, 5.0, 10.0, 50.0)):
@@ -128,6 +128,12 @@ def test_overflow_tiers_match_the_ring_path(tuning, dtype):
     tuning(target_lanes=1 << 30, min_segment=128, ring_slots=32)
     b = _solve(y, w, dtype)
     assert np.array_equal(a, b)
+    # 64 slots (FP32: every depth here but the deepest stays segmented; FP64 uses 32)
+    tuning(target_lanes=1 << 30, min_segment=256, ring_slots=64)
+    assert np.array_equal(_solve(y, w, dtype), a)
+    # 128 slots (FP32: every depth here stays segmented; FP64 uses 32)
+    tuning(target_lanes=1 << 30, min_segment=512, ring_slots=128)
+    assert np.array_equal(_solve(y, w, dtype), a)
     yv = _dev(y, dtype).cpu().double().numpy()
     wv = _dev(w, dtype).cpu().double().numpy()
     _check_rows(yv, a.astype(np.float64), oracle.chain_prox(yv, w=wv), TOL[dtype])
