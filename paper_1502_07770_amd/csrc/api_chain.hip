@@ -31,7 +31,7 @@ SegPlan seg_default_plan(int64_t num_chains, int64_t n) {
     p.L = round_tile((n + S - 1) / S);
     if (p.L < kTile) p.L = kTile;
     p.H = round_tile(t.halo);
-    p.CK = 16;  // checkpoints at a + 16, 32, 48, 64 (tile multiples)
+    p.CK = 16;  // checkpoints at a + 16, 32, 64, 128 (tile multiples)
     p.K = (int)t.ring_slots;
     return p;
 }

@@ -571,11 +571,14 @@ size_t chain_prox_ws_bytes(const ChainBatch &b, const SegPlan &plan) {
     return seg_ws_bytes<T>(b.num_chains, b.n, plan);
 }
 
-// Autotuner candidates: segment lengths 32 .. 1024, halos 32, 64 and 128, rings of
-// 16, 32, 64 or 128 slots (more than 16 only where segments are at least 4
-// times longer, to bound the saved deques; over 32 only for 8-byte entries), keeping only plans whose workspace stays within twice the
-// default plan's (or the default's plus 64 MiB).  Segment lengths at or above
-// the chain length are all the same plan; only the shortest is kept.
+// Autotuner candidates: segment lengths 32 .. 1024 and the whole chain (one
+// segment per chain: no halo runs, for chains whose deques stay deeper than
+// any halo recovers), halos 32, 64 and 128, rings of 16, 32, 64 or 128 slots
+// (more than 16 only where segments are at least 4 times longer, to bound the
+// saved deques; over 32 only for 8-byte entries), keeping only plans whose
+// workspace stays within twice the default plan's (or the default's plus
+// 64 MiB).  Segment lengths at or above the chain length are all the same
+// plan, whose halo is never used; only one of them is kept.
 template <typename T, typename G>
 int seg_candidates(int64_t C, int64_t n, SegPlan *out, int max_out) {
     const SegPlan d = seg_default_plan(C, n);
@@ -584,13 +587,14 @@ int seg_candidates(int64_t C, int64_t n, SegPlan *out, int max_out) {
     int m = 0;
     if (m < max_out) out[m++] = d;
     bool whole = false;
-    for (int64_t L = 32; L <= 1024 && !whole; L *= 2) {
+    for (int64_t L = 32; !whole; L *= 2) {
+        if (L > 1024) L = n;  // after 1024: the whole chain
         const int64_t Lr = (L >= n) ? ((n + kTile - 1) / kTile) * kTile : L;
         whole = L >= n;
         for (int K = 16; K <= 128; K *= 2) {
             if (K * 4 > Lr && K > 16) continue;
             if (K > ring_max<T, G>()) continue;
-            for (int64_t H = 32; H <= 128; H *= 2) {
+            for (int64_t H = 32; H <= (whole ? 32 : 128); H *= 2) {
                 const SegPlan p{Lr, H, 16, K};
                 if (seg_ws_bytes<T, G>(C, n, p) > cap) continue;
                 bool dup = false;

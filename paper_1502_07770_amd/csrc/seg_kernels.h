@@ -14,17 +14,19 @@
 //  k_seg_main   runs its segment's DP from an empty deque starting H nodes
 //               early (the halo, which stores nothing), streams lambda^-/
 //               lambda^+ for its own nodes, and saves its deque after the halo
-//               (HS), at 4 checkpoints every CK nodes inside the segment and at
-//               its end (ES).  It then runs the backward clip pass of
+//               (HS), at checkpoints a + 16, 32, 64, 128 inside the segment and
+//               at its end (ES).  It then runs the backward clip pass of
 //               Algorithm 2 over its own nodes: composing x_i = clip(x_{i+1},
 //               lam^-_i, lam^+_i) from the right, the composed map is a clip onto
 //               an interval, and once that interval is a single point every node
-//               left of it is determined and written.
-//  k_seg_repair compares the saved end state of segment s-1 with the halo state
+//               left of it is determined and written; the sweep's state at
+//               the checkpoints is recorded for the repair.
+//  k_seg_check  compares the saved end state of segment s-1 with the halo state
 //               of segment s (hash, then exact comparison of breakpoints and
-//               tags); where they differ it reruns the segment from that end
+//               tags) and lists the boundaries where they differ;
+//  k_seg_repair one lane per listed boundary: reruns the segment from that end
 //               state until the deque meets a first-pass checkpoint (or the
-//               segment end) and redoes the backward pass.
+//               segment end) and redoes the backward pass left of it.
 //  k_seg_fix    one lane per chain: redoes, sequentially, the rare segments
 //               whose repair started from a state that was not yet the true one;
 //               then composes the value entering each segment from the root.
@@ -77,7 +79,7 @@ template <typename T, typename G> __device__ __forceinline__ Ent<T, G> mk_ent(T 
 
 // Segment geometry: halo H and checkpoint spacing CK (both multiples of the
 // tile) and the saved-state slots per segment.
-constexpr int kCheckpoints = 4;  // first-pass deques saved every CK nodes after a segment start
+constexpr int kCheckpoints = 4;  // first-pass deques saved at a + CK, 2 CK, 4 CK, 8 CK in a segment
 constexpr int kSaves = 3 + kCheckpoints;  // HS, CK..., ES, ES2
 // Breakpoints examined branch-free at each end of the deque per step.
 #ifndef TVC_SCAN_WINDOW
@@ -114,6 +116,9 @@ struct SegWs {
     T *seg_xb;          // [S][C] x at the first node after the segment
     int *ovf_count;     // chains appended to ovf_list (zeroed by k_seg_main)
     int *ovf_list;      // [C] chains whose deque outgrew the LDS ring
+    int *rep_count;     // boundaries appended to rep_list (zeroed by k_seg_main)
+    int *rep_list;      // [S][C] lanes (s - 1) C + c whose halo state mismatched
+    LamPair<T> *sw_cp;  // [kCheckpoints][S][C] first-pass backward-sweep state at the checkpoints
     T *fb_lam;          // [fb_lanes][2n+4] HBM deques of the overflow kernel
     G *fb_tag;
     int64_t fb_cap;
@@ -682,16 +687,60 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, c
 // the top, buffered, and stored with one 16-byte access per stream when the
 // whole group has collapsed (the group holding the collapse point falls back
 // to single stores).
-template <typename T, class Prob, int P, bool kVec>
+//
+// The sweep may start inside the segment: from node b - 1 with the state the
+// sweep had entering it from the right (the composed interval, or the value
+// and node of an earlier collapse).  With kRec the first pass records that
+// state at the checkpoint nodes (ck_offset) that fall on a tile edge counted
+// from b, so a repair that met checkpoint m redoes only
+// the nodes left of it.
+// Checkpoint m (1 .. kCheckpoints) of a segment starting at a sits at node
+// a + CK 2^(m-1): close together where the runs usually meet, and spread out
+// so that a late meeting still ends a rerun well before the segment end.
+__host__ __device__ __forceinline__ int64_t ck_offset(int m, int64_t CK) { return CK << (m - 1); }
+// m if node a + off is checkpoint m, else 0.
+__device__ __forceinline__ int ck_index(int64_t off, int64_t CK) {
+    int m = 0;
+#pragma unroll
+    for (int j = 1; j <= kCheckpoints; ++j) m = (off == ck_offset(j, CK)) ? j : m;
+    return m;
+}
+
+template <typename T>
+struct SweepIn {
+    T lo, hi;   // composed interval over [b, segment end), or the collapsed value twice
+    bool col;   // collapsed at node k >= b
+    int64_t k;
+};
+template <typename T>
+__device__ __forceinline__ SweepIn<T> sweep_from_end(int64_t a) {
+    return SweepIn<T>{-pos_inf<T>(), pos_inf<T>(), false, a - 1};
+}
+// Whether the first pass recorded the sweep state at checkpoint node e of the
+// segment [a, b) (both sides use this one rule).
+__device__ __forceinline__ bool sweep_cp_recorded(int64_t a, int64_t b, int64_t e, int64_t CK) {
+    return e < b && ck_index(e - a, CK) > 0 && (b - e) % kSweepTile == 0;
+}
+
+template <typename T, class Prob, int P, bool kVec, bool kRec>
 __device__ __forceinline__ void bwd_sweep_run(const WsOf<T, Prob> &ws, const typename Prob::Sink &sink, int64_t s,
-                                              int64_t c, int64_t a, int64_t b) {
+                                              int64_t c, int64_t a, int64_t b, const SweepIn<T> &in0) {
     static_assert(P % 4 == 0, "tiles hold whole groups of four nodes");
+    static_assert(!kRec || P == kSweepTile, "checkpoint records sit on sweep-tile edges");
     using SP = typename Prob::SinkPre;
     LamPair<T> *__restrict__ lam = ws.lam;
     const int64_t C = ws.C;
-    T glo = -pos_inf<T>(), ghi = pos_inf<T>(), x = (T)0;
-    bool col = false;
-    int64_t k = a - 1;
+    T glo = in0.lo, ghi = in0.hi, x = in0.lo;
+    bool col = in0.col;
+    int64_t k = in0.col ? in0.k : a - 1;
+    // next checkpoint to record (downwards); a tile edge or never reached
+    int mrec = 0;
+    int64_t erec = -1;
+    if (kRec) {
+        mrec = kCheckpoints;
+        while (mrec > 0 && a + ck_offset(mrec, ws.CK) >= b) --mrec;
+        erec = mrec > 0 ? a + ck_offset(mrec, ws.CK) : -1;
+    }
     LamPair<T> pre[P];
     SP spre[P];
     // slot j holds node i0 - j of the current tile (i0 = b - 1 - tile * P)
@@ -766,6 +815,16 @@ __device__ __forceinline__ void bwd_sweep_run(const WsOf<T, Prob> &ws, const typ
             else if ((j & 3) == 3) refill_sink(j, i - P);
             visit(i, j & 3, p, sv);
         }
+        if (kRec && i0 - (P - 1) == erec) {  // the state now covers [erec, b)
+            if (sweep_cp_recorded(a, b, erec, ws.CK)) {
+                LamPair<T> r;
+                r.lo = col ? x : glo;
+                r.hi = col ? x : ghi;
+                ws.sw_cp[(mrec - 1) * ws.S * C + s * C + c] = r;
+            }
+            --mrec;
+            erec = mrec > 0 ? a + ck_offset(mrec, ws.CK) : -1;
+        }
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -777,22 +836,22 @@ __device__ __forceinline__ void bwd_sweep_run(const WsOf<T, Prob> &ws, const typ
     ws.seg_hi[sc] = col ? x : ghi;
 }
 
-template <typename T, class Prob, int P>
+template <typename T, class Prob, int P, bool kRec = false>
 __device__ __forceinline__ void bwd_sweep(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, const ChainSpan &sp,
-                                          int64_t s, int64_t c, int64_t a, int64_t b) {
+                                          int64_t s, int64_t c, int64_t a, int64_t b, const SweepIn<T> &in0) {
     const auto sink = Prob::sink(pp, sp);
     if (sink.vec && (b & 3) == 0)
-        bwd_sweep_run<T, Prob, P, true>(ws, sink, s, c, a, b);
+        bwd_sweep_run<T, Prob, P, true, kRec>(ws, sink, s, c, a, b, in0);
     else
-        bwd_sweep_run<T, Prob, P, false>(ws, sink, s, c, a, b);
+        bwd_sweep_run<T, Prob, P, false, kRec>(ws, sink, s, c, a, b, in0);
 }
 
 // True if the deque after node e - 1 equals the first pass's checkpoint there.
 template <typename T, int K, typename G>
 __device__ __forceinline__ bool meets_checkpoint(const SegWs<T, G> &ws, const CRing<T, K, G> &R, int64_t s, int64_t c,
                                                  int64_t a, int64_t e) {
-    const int64_t m = (e - a) / ws.CK;
-    if (e <= a || m * ws.CK != e - a || m > kCheckpoints) return false;
+    const int m = ck_index(e - a, ws.CK);
+    if (m == 0) return false;
     return equals_state<T, K, G>(ws, R, s, kSaveCk + (int)m - 1, c);
 }
 
@@ -804,7 +863,10 @@ __global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob
     __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
-    if (g == 0) *ws.ovf_count = 0;  // consumed by k_seg_fix / k_seg_ovf after this kernel
+    if (g == 0) {  // consumed by the kernels after this one
+        *ws.ovf_count = 0;
+        *ws.rep_count = 0;
+    }
     if (g >= ws.S * ws.C) return;
     const int64_t c = g % ws.C, s = g / ws.C;
     const ChainSpan sp = Prob::span(pp, c, ws.n);
@@ -823,41 +885,35 @@ __global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob
     if (h0 < a)
         fwd_run<T, Prob, K, P, false>(R, src, ok, cy, h0, a, n, ws.lam, C, c, [](int64_t) { return false; });
     if (s > 0 && ok) save_state(ws, R, s, kSaveHalo, c);
-    // own nodes; tile edges align with a + m CK (multiples of P)
+    // own nodes; tile edges align with the checkpoints (multiples of P)
     auto saves = [&](int64_t e) {
         if (ok) {
-            const int64_t m = (e - a) / ws.CK;
-            if (m * ws.CK == e - a && m <= kCheckpoints) save_state(ws, R, s, kSaveCk + (int)m - 1, c);
+            const int m = ck_index(e - a, ws.CK);
+            if (m > 0) save_state(ws, R, s, kSaveCk + m - 1, c);
         }
         return false;
     };
     fwd_run<T, Prob, K, P, true>(R, src, ok, cy, a, b, n, ws.lam, C, c, saves);
     if (ok && b < n) save_state(ws, R, s, kSaveEnd, c);
     ws.ovf[c * ws.S + s] = ok ? 0 : 1;
-    if (ok) bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
+    if (ok) bwd_sweep<T, Prob, kSweepTile, true>(ws, pp, sp, s, c, a, b, sweep_from_end<T>(a));
 }
 
 // ---------------------------------------------------------------------------
-// Boundary check and repair, lane (s, c) for s >= 1.  If the first pass's
-// deque after the halo differs from the saved end state of segment s-1, the
-// segment is rerun from that end state (taken as the true incoming message;
-// k_seg_fix corrects the rare cases where it is not) until the deque matches a
-// first-pass checkpoint, then its backward pass is redone.
+// Boundary check, lane (s, c) for s >= 1: does the first pass's deque after the
+// halo equal the saved end state of segment s-1?  Mismatched boundaries are
+// appended to rep_list (one atomic per wave) so the repair runs on dense waves.
 // ---------------------------------------------------------------------------
-template <typename T, class Prob, int K, int P>
-__global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Prob::Params pp) {
-    __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
+template <typename T, class Prob, int K>
+__global__ __launch_bounds__(64) void k_seg_check(WsOf<T, Prob> ws, typename Prob::Params pp) {
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g >= (ws.S - 1) * ws.C) return;
     const int64_t c = g % ws.C, s = g / ws.C + 1;
     const ChainSpan sp = Prob::span(pp, c, ws.n);
-    const int64_t n = sp.n;
-    const int64_t a = s * ws.L;
-    if (a >= n) return;
-    const int64_t b = (a + ws.L < n) ? a + ws.L : n;
+    if (s * ws.L >= sp.n) return;
     const int64_t cs = c * ws.S + s;
-    if (ws.ovf[cs] || ws.ovf[cs - 1]) return;  // the chain goes to the HBM fallback
+    if (ws.ovf[cs] || ws.ovf[cs - 1]) return;  // the chain goes to the overflow kernel
     const int64_t C = ws.C;
     bool same = (*size_slot(ws, s - 1, kSaveEnd, c) == *size_slot(ws, s, kSaveHalo, c)) &&
                 (*hash_slot(ws, s - 1, kSaveEnd, c) == *hash_slot(ws, s, kSaveHalo, c));
@@ -881,7 +937,39 @@ __global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Pr
         }
     }
     ws.mis[cs] = same ? 0 : 1;
-    if (same) return;
+    const uint64_t want = __ballot(!same);
+    if (!same) {
+        const int leader = __ffsll((unsigned long long)want) - 1;
+        const int rank = __popcll(want & ((uint64_t(1) << lane) - 1));
+        int base = 0;
+        if (lane == leader) base = atomicAdd(ws.rep_count, __popcll(want));
+        base = __shfl(base, leader);
+        ws.rep_list[base + rank] = (int)g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Repair, one lane per listed boundary: the segment is rerun from the saved end
+// state of segment s-1 (taken as the true incoming message; k_seg_fix corrects
+// the rare cases where it is not) until the deque matches a first-pass
+// checkpoint.  The backward pass is then redone left of that checkpoint from
+// the first pass's recorded sweep state (the lambdas right of it are
+// unchanged), or over the whole segment.
+// ---------------------------------------------------------------------------
+template <typename T, class Prob, int K, int P>
+__global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Prob::Params pp) {
+    __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
+    const int lane = threadIdx.x;
+    const int64_t jl = (int64_t)blockIdx.x * 64 + lane;
+    if (jl >= *ws.rep_count) return;
+    const int64_t g = ws.rep_list[jl];
+    const int64_t c = g % ws.C, s = g / ws.C + 1;
+    const ChainSpan sp = Prob::span(pp, c, ws.n);
+    const int64_t n = sp.n;
+    const int64_t a = s * ws.L;
+    const int64_t b = (a + ws.L < n) ? a + ws.L : n;
+    const int64_t cs = c * ws.S + s;
+    const int64_t C = ws.C;
     const auto src = Prob::src(pp, sp);
     CRing<T, K, typename Prob::Tag> R;
     R.init(s_ent, lane);
@@ -900,7 +988,15 @@ __global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Pr
     ws.clean[cs] = clean ? 1 : 0;
     ws.rep_stop[s * C + c] = (int)stop;
     if (!clean && b < n) save_state(ws, R, s, kSaveEnd2, c);
-    bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
+    if (stop < b && sweep_cp_recorded(a, b, stop, ws.CK)) {
+        // nodes [stop, b) keep their first-pass lambdas and outputs
+        const LamPair<T> r = ws.sw_cp[(ck_index(stop - a, ws.CK) - 1) * ws.S * C + s * C + c];
+        const int64_t k1 = (int64_t)ws.seg_unc[s * C + c] - 1;  // the first pass's collapse node
+        const SweepIn<T> in0{r.lo, r.hi, k1 >= stop, k1};
+        bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, stop, in0);
+    } else {
+        bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b, sweep_from_end<T>(a));
+    }
 }
 
 // Backward clip of a whole chain from its lambda stream (after a sequential
@@ -1041,7 +1137,7 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
         if (!ok) break;
         if (stop == b && !met && b < n)
             met = equals_state(ws, R, s, kSaveEnd, c);
-        bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b);
+        bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b, sweep_from_end<T>(a));
         end_true = met;
     }
     return ok;
@@ -1136,6 +1232,9 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
     const int64_t fbl = (C < kOverflowLanes ? (C + 63) / 64 * 64 : kOverflowLanes);
     const size_t o_oc = off;   off += al(sizeof(int));
     const size_t o_ol = off;   off += al(sizeof(int) * (size_t)C);
+    const size_t o_rc = off;   off += al(sizeof(int));
+    const size_t o_rl = off;   off += al(sizeof(int) * (size_t)(S * C));
+    const size_t o_sw = off;   off += al(sizeof(LamPair<T>) * (size_t)(kCheckpoints * S * C));
     const size_t o_fl = off;   off += al(sizeof(T) * (size_t)(fbl * cap));
     const size_t o_ft = off;   off += al(sizeof(G) * (size_t)(fbl * cap));
     if (base && out) {
@@ -1161,6 +1260,9 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
         w.seg_xb = (T *)(p + o_xb);
         w.ovf_count = (int *)(p + o_oc);
         w.ovf_list = (int *)(p + o_ol);
+        w.rep_count = (int *)(p + o_rc);
+        w.rep_list = (int *)(p + o_rl);
+        w.sw_cp = (LamPair<T> *)(p + o_sw);
         w.fb_lam = (T *)(p + o_fl);
         w.fb_tag = (G *)(p + o_ft);
         w.fb_cap = cap;
@@ -1177,6 +1279,7 @@ hipError_t seg_launch(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, 
     hipLaunchKernelGGL((k_seg_main<T, Prob, K, P>), dim3(blocks), dim3(64), 0, stream, ws, pp);
     if (ws.S > 1) {
         const unsigned rb = (unsigned)(((ws.S - 1) * ws.C + 63) / 64);
+        hipLaunchKernelGGL((k_seg_check<T, Prob, K>), dim3(rb), dim3(64), 0, stream, ws, pp);
         hipLaunchKernelGGL((k_seg_repair<T, Prob, K, P>), dim3(rb), dim3(64), 0, stream, ws, pp);
     }
     const unsigned fb = (unsigned)((ws.C + 63) / 64);
