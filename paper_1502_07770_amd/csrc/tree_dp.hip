@@ -33,43 +33,91 @@ struct TreeBatch {
 
 struct TreeWs {
     double *lam, *da, *db;  // arena [6 N + 16 T] (entries of tree t from 6 off[t] + 16 t)
-    int64_t *hstart;        // pending-message stack [N]: start of its breakpoints in the arena
+    int64_t *hstart;        // pending-message stack [N]: first breakpoint in the arena
     int64_t *hcount;        //   number of breakpoints
+    int64_t *hreg;          //   start of the arena region the message owns (<= hstart)
     int64_t *hparent;       //   node the message is for
     double *hlo, *hhi;      //   clip levels (the message's flat ends)
     double *llo, *lhi;      // [N] lambda^-, lambda^+ of each node's edge (root: x_root twice)
     int *bad;               // set if a tree is not numbered in post-order
 };
 
+// A breakpoint in registers.
+struct TBp {
+    double l, a, b;
+};
+__device__ __forceinline__ TBp tb_get(const TreeWs &W, int64_t i) { return TBp{W.lam[i], W.da[i], W.db[i]}; }
+__device__ __forceinline__ void tb_put(const TreeWs &W, int64_t i, const TBp &e) {
+    W.lam[i] = e.l;
+    W.da[i] = e.a;
+    W.db[i] = e.b;
+}
+
+// Moves cnt breakpoints from src to dst (overlap allowed), eight at a time with
+// every load of a group issued before its stores, so a group costs one memory
+// latency rather than eight.
+constexpr int kMoveGroup = 8;
+__device__ __forceinline__ void arena_move_n(const TreeWs &W, int64_t dst, int64_t src, int64_t cnt) {
+    if (cnt <= 0 || dst == src) return;
+    TBp r[kMoveGroup];
+    if (dst > src) {  // from the top down
+        for (int64_t hi = cnt; hi > 0; hi -= kMoveGroup) {
+            const int64_t lo = hi > kMoveGroup ? hi - kMoveGroup : 0;
+#pragma unroll
+            for (int g = 0; g < kMoveGroup; ++g)
+                if (lo + g < hi) r[g] = tb_get(W, src + lo + g);
+#pragma unroll
+            for (int g = 0; g < kMoveGroup; ++g)
+                if (lo + g < hi) tb_put(W, dst + lo + g, r[g]);
+        }
+    } else {  // from the bottom up
+        for (int64_t lo = 0; lo < cnt; lo += kMoveGroup) {
+            const int64_t hi = lo + kMoveGroup < cnt ? lo + kMoveGroup : cnt;
+#pragma unroll
+            for (int g = 0; g < kMoveGroup; ++g)
+                if (lo + g < hi) r[g] = tb_get(W, src + lo + g);
+#pragma unroll
+            for (int g = 0; g < kMoveGroup; ++g)
+                if (lo + g < hi) tb_put(W, dst + lo + g, r[g]);
+        }
+    }
+}
+
 // h(z) <= v <= h(z+) scanning from the left over entries [s, s + t) of the
 // arena; returns z, the entries passed, the piece left of z and whether z is
-// the jump of entry s + passed.
+// the jump of entry s + passed.  The next entry is loaded one step ahead.
 __device__ double tree_cross_left(const TreeWs &W, int64_t s, int64_t t, double A, double B, double v,
                                   int64_t *passed, double *pa, double *pb, bool *jump) {
     int64_t j = 0;
     double z;
     *jump = false;
+    TBp e{0.0, 0.0, 0.0}, nx{0.0, 0.0, 0.0};
+    if (t > 0) e = tb_get(W, s);
+    double lprev = 0.0;
     for (;;) {
         if (j == t) {
             z = (v - B) / A;
             break;
         }
-        const double l = W.lam[s + j];
+        if (j + 1 < t) nx = tb_get(W, s + j + 1);
+        const double l = e.l;
         const double vl = A * l + B;
         if (vl >= v) {
             z = (v - B) / A;
             z = z > l ? l : z;
-            if (j > 0 && z < W.lam[s + j - 1]) z = W.lam[s + j - 1];
+            if (j > 0 && z < lprev) z = lprev;
             break;
         }
-        const double vr = vl + W.da[s + j] * l + W.db[s + j];
+        const double vr = vl + e.a * l + e.b;
         if (vr >= v) {
             z = l;
             *jump = true;
             break;
         }
-        A += W.da[s + j];
-        B += W.db[s + j];
+        A += e.a;
+        B += e.b;
+        lprev = l;
+        e = nx;
         ++j;
     }
     *passed = j;
@@ -83,27 +131,33 @@ __device__ double tree_cross_right(const TreeWs &W, int64_t s, int64_t t, double
     int64_t j = t - 1, k = 0;
     double z;
     *jump = false;
+    TBp e{0.0, 0.0, 0.0}, nx{0.0, 0.0, 0.0};
+    if (j >= 0) e = tb_get(W, s + j);
+    double lnext = 0.0;
     for (;;) {
         if (j < 0) {
             z = (v - B) / A;
             break;
         }
-        const double l = W.lam[s + j];
+        if (j > 0) nx = tb_get(W, s + j - 1);
+        const double l = e.l;
         const double vr = A * l + B;
         if (vr <= v) {
             z = (v - B) / A;
             z = z < l ? l : z;
-            if (j + 1 < t && z > W.lam[s + j + 1]) z = W.lam[s + j + 1];
+            if (j + 1 < t && z > lnext) z = lnext;
             break;
         }
-        const double vl = vr - (W.da[s + j] * l + W.db[s + j]);
+        const double vl = vr - (e.a * l + e.b);
         if (vl <= v) {
             z = l;
             *jump = true;
             break;
         }
-        A -= W.da[s + j];
-        B -= W.db[s + j];
+        A -= e.a;
+        B -= e.b;
+        lnext = l;
+        e = nx;
         --j;
         ++k;
     }
@@ -113,54 +167,77 @@ __device__ double tree_cross_right(const TreeWs &W, int64_t s, int64_t t, double
     return z;
 }
 
-__device__ __forceinline__ void arena_move(const TreeWs &W, int64_t to, int64_t from) {
-    W.lam[to] = W.lam[from];
-    W.da[to] = W.da[from];
-    W.db[to] = W.db[from];
-}
+// The working message of a node is the run [s, s + t) of its region [r, s + t)
+// (the front may float inside the region, so front pops and pushes move
+// nothing); the region ends at top = s + t, and the regions of pending
+// messages are stacked contiguously below it.
+// Lanes (trees) per 64-wide wave.  Each lane's work is a chain of dependent
+// memory accesses, so waves that are partly empty trade issue slots for more
+// waves per SIMD to hide that latency.
+constexpr int kTreeLanes = 64;
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T *__restrict__ a,
                                                 const T *__restrict__ b, const T *__restrict__ c,
                                                 const T *__restrict__ d, const T *__restrict__ wm,
-                                                const T *__restrict__ wp, T *__restrict__ x) {
-    const int64_t tr = (int64_t)blockIdx.x * 64 + threadIdx.x;
+                                                const T *__restrict__ wp, T *__restrict__ x, int lanes) {
+    if ((int)threadIdx.x >= lanes) return;
+    const int64_t tr = (int64_t)blockIdx.x * lanes + threadIdx.x;
     if (tr >= tb.num_trees) return;
     const int64_t n0 = tb.offsets[tr], n1 = tb.offsets[tr + 1];
     if (n1 <= n0) return;
     const int64_t abase = 6 * n0 + 16 * tr;     // this tree's arena
-    const int64_t acap = 6 * (n1 - n0) + 16;
-    int64_t top = abase;                          // arena end of the pending stack
+    const int64_t aend = abase + 6 * (n1 - n0) + 16;
+    int64_t top = abase;                          // end of the pending stack's regions
     int64_t sp = n0;                              // header stack pointer
     bool ok = true;
     for (int64_t i = n0; i < n1 && ok; ++i) {
-        // (a) the children's messages: the top headers whose node is i (contiguous
-        // in the arena); merge them pairwise from the top into one sorted run
+        // (a) the children's messages: the top headers whose node is i, their
+        // regions stacked right below the working one; the first is adopted in
+        // place, each further one merged with it via the buffer at top
         double al = 0.0, bl = 0.0, ar = 0.0, br = 0.0;
-        int64_t s = top, t = 0;
+        int64_t r = top, s = top, t = 0;
         while (sp > n0 && W.hparent[sp - 1] == i) {
             --sp;
-            const int64_t cs = W.hstart[sp], ct = W.hcount[sp];
-            // a child's run must lie right below the merged run, and the merge
-            // buffer above it must fit the arena
-            if (cs < abase || cs + ct != s || top + ct + t > abase + acap) {
+            const int64_t cs = W.hstart[sp], ct = W.hcount[sp], cr = W.hreg[sp];
+            if (cr < abase || cs < cr || cs + ct != r || top + ct + t > aend) {
                 ok = false;
                 break;
             }
             bl += W.hlo[sp];
             br += W.hhi[sp];
-            // merge run [cs, cs + ct) with run [s, s + t) (which follows it) via the buffer at top
-            int64_t u = cs, v = s, w = top;
-            while (u < cs + ct || v < s + t) {
-                if (v >= s + t || (u < cs + ct && W.lam[u] <= W.lam[v])) arena_move(W, w++, u++);
-                else arena_move(W, w++, v++);
+            if (t == 0) {
+                r = cr;
+                s = cs;
+                t = ct;
+                continue;
             }
-            for (int64_t q = 0; q < ct + t; ++q) arena_move(W, cs + q, top + q);
-            s = cs;
+            // merge run [cs, cs + ct) with run [s, s + t) into [top, top + ct + t)
+            int64_t u = cs, v = s, w = top;
+            const int64_t ue = cs + ct, ve = s + t;
+            TBp eu{0.0, 0.0, 0.0}, ev{0.0, 0.0, 0.0};
+            if (u < ue) eu = tb_get(W, u);
+            if (v < ve) ev = tb_get(W, v);
+            while (u < ue && v < ve) {
+                if (eu.l <= ev.l) {
+                    tb_put(W, w++, eu);
+                    if (++u < ue) eu = tb_get(W, u);
+                } else {
+                    tb_put(W, w++, ev);
+                    if (++v < ve) ev = tb_get(W, v);
+                }
+            }
+            arena_move_n(W, w, u, ue - u);
+            w += ue - u;
+            arena_move_n(W, w, v, ve - v);
+            arena_move_n(W, cr, top, ct + t);  // back to the bottom of the merged regions
+            r = cr;
+            s = cr;
             t += ct;
             top = s + t;
         }
         if (!ok) break;
+        top = s + t;
         // (b) add the unary
         const double ai = a ? (double)a[i] : 1.0;
         const double bi = (double)b[i];
@@ -171,18 +248,20 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
         ar += ai;
         br += -bi + ci;
         if (ci > 0.0) {
-            if (top + 2 - abase > acap) {
-                ok = false;
-                break;
-            }
+            // insertion point: after every breakpoint <= d_i; the shorter side moves
             int64_t q = t;
-            while (q > 0 && W.lam[s + q - 1] > di) {
-                arena_move(W, s + q, s + q - 1);
-                --q;
+            while (q > 0 && W.lam[s + q - 1] > di) --q;
+            if (s > r && q < t - q) {
+                arena_move_n(W, s - 1, s, q);
+                --s;
+            } else {
+                if (top + 1 > aend) {
+                    ok = false;
+                    break;
+                }
+                arena_move_n(W, s + q + 1, s + q, t - q);
             }
-            W.lam[s + q] = di;
-            W.da[s + q] = 0.0;
-            W.db[s + q] = 2.0 * ci;
+            tb_put(W, s + q, TBp{di, 0.0, 2.0 * ci});
             ++t;
             top = s + t;
         }
@@ -193,7 +272,7 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
         if (p < 0) {  // root: the zero of h
             const double xr = tree_cross_left(W, s, t, al, bl, 0.0, &k, &pa, &pb, &jump);
             W.llo[i] = W.lhi[i] = xr;
-            top = s;  // nothing stays pending for this root
+            top = r;  // nothing stays pending for this root
             continue;
         }
         if (p <= i || p >= n1) {
@@ -202,44 +281,40 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
         }
         // (c) clip to [wm_i, wp_i]
         const double lo = (double)wm[i], hi = (double)wp[i];
-        if (top + 2 - abase > acap) {
+        if (top + 2 > aend) {
             ok = false;
             break;
         }
         const double lm = tree_cross_left(W, s, t, al, bl, lo, &k, &pa, &pb, &jump);
         double nda = pa, ndb = pb - lo;
         if (jump) {
-            nda += W.da[s + k];
-            ndb += W.db[s + k];
+            const TBp e = tb_get(W, s + k);
+            nda += e.a;
+            ndb += e.b;
         }
         const int64_t drop = k + (jump ? 1 : 0);
-        // new front at s + drop - 1 (the dropped entries' last slot), shifting nothing
-        const int64_t f = s + drop - 1;
-        if (drop == 0) {  // room at the front: shift the run right by one
-            for (int64_t q = t; q > 0; --q) arena_move(W, s + q, s + q - 1);
-            W.lam[s] = lm;
-            W.da[s] = nda;
-            W.db[s] = ndb;
+        if (drop == 0) {  // a new front: room in the region, else shift right by one
+            if (s > r) {
+                --s;
+            } else {
+                arena_move_n(W, s + 1, s, t);
+            }
             ++t;
-        } else {
-            W.lam[f] = lm;
-            W.da[f] = nda;
-            W.db[f] = ndb;
+        } else {  // the new front takes the last dropped slot
+            s += drop - 1;
             t -= drop - 1;
-            // keep the run starting at s (the stack stays contiguous)
-            for (int64_t q = 0; q < t; ++q) arena_move(W, s + q, f + q);
         }
+        tb_put(W, s, TBp{lm, nda, ndb});
         const double lp = tree_cross_right(W, s, t, ar, br, hi, &k, &pa, &pb, &jump);
         nda = -pa;
         ndb = hi - pb;
         if (jump) {
-            nda += W.da[s + t - 1 - k];
-            ndb += W.db[s + t - 1 - k];
+            const TBp e = tb_get(W, s + t - 1 - k);
+            nda += e.a;
+            ndb += e.b;
         }
         t -= k + (jump ? 1 : 0);
-        W.lam[s + t] = lp;
-        W.da[s + t] = nda;
-        W.db[s + t] = ndb;
+        tb_put(W, s + t, TBp{lp, nda, ndb});
         ++t;
         top = s + t;
         W.llo[i] = lm;
@@ -247,6 +322,7 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
         // push the clipped message for the parent
         W.hstart[sp] = s;
         W.hcount[sp] = t;
+        W.hreg[sp] = r;
         W.hparent[sp] = p;
         W.hlo[sp] = lo;
         W.hhi[sp] = hi;
@@ -270,7 +346,7 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
     }
 }
 
-// Workspace: arena 3 x (6 N + 16 T) doubles, headers 3 x N int64 + 2 x N
+// Workspace: arena 3 x (6 N + 16 T) doubles, headers 4 x N int64 + 2 x N
 // doubles, lambdas 2 x N doubles, flag.
 static size_t tree_layout(void *p, int64_t T, int64_t N, TreeWs *out) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -281,6 +357,7 @@ static size_t tree_layout(void *p, int64_t T, int64_t N, TreeWs *out) {
     const size_t o_b = off;  off += al(sizeof(double) * A);
     const size_t o_hs = off; off += al(sizeof(int64_t) * (size_t)N);
     const size_t o_hc = off; off += al(sizeof(int64_t) * (size_t)N);
+    const size_t o_hr = off; off += al(sizeof(int64_t) * (size_t)N);
     const size_t o_hp = off; off += al(sizeof(int64_t) * (size_t)N);
     const size_t o_hl = off; off += al(sizeof(double) * (size_t)N);
     const size_t o_hh = off; off += al(sizeof(double) * (size_t)N);
@@ -294,6 +371,7 @@ static size_t tree_layout(void *p, int64_t T, int64_t N, TreeWs *out) {
         out->db = (double *)(c + o_b);
         out->hstart = (int64_t *)(c + o_hs);
         out->hcount = (int64_t *)(c + o_hc);
+        out->hreg = (int64_t *)(c + o_hr);
         out->hparent = (int64_t *)(c + o_hp);
         out->hlo = (double *)(c + o_hl);
         out->hhi = (double *)(c + o_hh);
@@ -309,21 +387,29 @@ size_t tree_dp_ws_bytes(int64_t num_trees, int64_t num_nodes) {
 }
 
 template <typename T>
-hipError_t launch_tree_dp(int64_t num_trees, int64_t num_nodes, const int64_t *offsets, const int64_t *parent,
-                          const T *a, const T *b, const T *c, const T *d, const T *wm, const T *wp, T *x,
-                          void *workspace, int *bad_host, hipStream_t stream) {
+hipError_t launch_tree_dp_lanes(int64_t num_trees, int64_t num_nodes, const int64_t *offsets, const int64_t *parent,
+                                const T *a, const T *b, const T *c, const T *d, const T *wm, const T *wp, T *x,
+                                void *workspace, int *bad_host, hipStream_t stream, int lanes) {
     TreeWs W;
     tree_layout(workspace, num_trees, num_nodes, &W);
     hipError_t e = hipMemsetAsync(W.bad, 0, sizeof(int), stream);
     if (e != hipSuccess) return e;
     const TreeBatch tb{num_trees, offsets, parent};
-    hipLaunchKernelGGL((k_tree_dp<T>), dim3((unsigned)((num_trees + 63) / 64)), dim3(64), 0, stream, tb, W, a, b, c,
-                       d, wm, wp, x);
+    hipLaunchKernelGGL((k_tree_dp<T>), dim3((unsigned)((num_trees + lanes - 1) / lanes)), dim3(64), 0, stream, tb, W,
+                       a, b, c, d, wm, wp, x, lanes);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(bad_host, W.bad, sizeof(int), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(stream);
+}
+
+template <typename T>
+hipError_t launch_tree_dp(int64_t num_trees, int64_t num_nodes, const int64_t *offsets, const int64_t *parent,
+                          const T *a, const T *b, const T *c, const T *d, const T *wm, const T *wp, T *x,
+                          void *workspace, int *bad_host, hipStream_t stream) {
+    return launch_tree_dp_lanes<T>(num_trees, num_nodes, offsets, parent, a, b, c, d, wm, wp, x, workspace, bad_host,
+                                   stream, kTreeLanes);
 }
 
 template hipError_t launch_tree_dp<float>(int64_t, int64_t, const int64_t *, const int64_t *, const float *,
