@@ -21,10 +21,9 @@
 //               an interval, and once that interval is a single point every node
 //               left of it is determined and written; the sweep's state at
 //               the checkpoints is recorded for the repair.
-//  k_seg_check  compares the saved end state of segment s-1 with the halo state
+//  k_seg_repair compares the saved end state of segment s-1 with the halo state
 //               of segment s (hash, then exact comparison of breakpoints and
-//               tags) and lists the boundaries where they differ;
-//  k_seg_repair one lane per listed boundary: reruns the segment from that end
+//               tags); where they differ it reruns the segment from that end
 //               state until the deque meets a first-pass checkpoint (or the
 //               segment end) and redoes the backward pass left of it.
 //  k_seg_fix    one lane per chain: redoes, sequentially, the rare segments
@@ -116,8 +115,6 @@ struct SegWs {
     T *seg_xb;          // [S][C] x at the first node after the segment
     int *ovf_count;     // chains appended to ovf_list (zeroed by k_seg_main)
     int *ovf_list;      // [C] chains whose deque outgrew the LDS ring
-    int *rep_count;     // boundaries appended to rep_list (zeroed by k_seg_main)
-    int *rep_list;      // [S][C] lanes (s - 1) C + c whose halo state mismatched
     LamPair<T> *sw_cp;  // [kCheckpoints][S][C] first-pass backward-sweep state at the checkpoints
     T *fb_lam;          // [fb_lanes][2n+4] HBM deques of the overflow kernel
     G *fb_tag;
@@ -863,10 +860,7 @@ __global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob
     __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
-    if (g == 0) {  // consumed by the kernels after this one
-        *ws.ovf_count = 0;
-        *ws.rep_count = 0;
-    }
+    if (g == 0) *ws.ovf_count = 0;  // consumed by k_seg_fix / k_seg_ovf after this kernel
     if (g >= ws.S * ws.C) return;
     const int64_t c = g % ws.C, s = g / ws.C;
     const ChainSpan sp = Prob::span(pp, c, ws.n);
@@ -900,18 +894,26 @@ __global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob
 }
 
 // ---------------------------------------------------------------------------
-// Boundary check, lane (s, c) for s >= 1: does the first pass's deque after the
-// halo equal the saved end state of segment s-1?  Mismatched boundaries are
-// appended to rep_list (one atomic per wave) so the repair runs on dense waves.
+// Boundary check and repair, lane (s, c) for s >= 1.  If the first pass's
+// deque after the halo differs from the saved end state of segment s-1, the
+// segment is rerun from that end state (taken as the true incoming message;
+// k_seg_fix corrects the rare cases where it is not) until the deque matches a
+// first-pass checkpoint.  The backward pass is then redone left of that
+// checkpoint from the first pass's recorded sweep state (the lambdas right of
+// it are unchanged), or over the whole segment.
 // ---------------------------------------------------------------------------
-template <typename T, class Prob, int K>
-__global__ __launch_bounds__(64) void k_seg_check(WsOf<T, Prob> ws, typename Prob::Params pp) {
+template <typename T, class Prob, int K, int P>
+__global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Prob::Params pp) {
+    __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g >= (ws.S - 1) * ws.C) return;
     const int64_t c = g % ws.C, s = g / ws.C + 1;
     const ChainSpan sp = Prob::span(pp, c, ws.n);
-    if (s * ws.L >= sp.n) return;
+    const int64_t n = sp.n;
+    const int64_t a = s * ws.L;
+    if (a >= n) return;
+    const int64_t b = (a + ws.L < n) ? a + ws.L : n;
     const int64_t cs = c * ws.S + s;
     if (ws.ovf[cs] || ws.ovf[cs - 1]) return;  // the chain goes to the overflow kernel
     const int64_t C = ws.C;
@@ -937,39 +939,7 @@ __global__ __launch_bounds__(64) void k_seg_check(WsOf<T, Prob> ws, typename Pro
         }
     }
     ws.mis[cs] = same ? 0 : 1;
-    const uint64_t want = __ballot(!same);
-    if (!same) {
-        const int leader = __ffsll((unsigned long long)want) - 1;
-        const int rank = __popcll(want & ((uint64_t(1) << lane) - 1));
-        int base = 0;
-        if (lane == leader) base = atomicAdd(ws.rep_count, __popcll(want));
-        base = __shfl(base, leader);
-        ws.rep_list[base + rank] = (int)g;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Repair, one lane per listed boundary: the segment is rerun from the saved end
-// state of segment s-1 (taken as the true incoming message; k_seg_fix corrects
-// the rare cases where it is not) until the deque matches a first-pass
-// checkpoint.  The backward pass is then redone left of that checkpoint from
-// the first pass's recorded sweep state (the lambdas right of it are
-// unchanged), or over the whole segment.
-// ---------------------------------------------------------------------------
-template <typename T, class Prob, int K, int P>
-__global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Prob::Params pp) {
-    __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
-    const int lane = threadIdx.x;
-    const int64_t jl = (int64_t)blockIdx.x * 64 + lane;
-    if (jl >= *ws.rep_count) return;
-    const int64_t g = ws.rep_list[jl];
-    const int64_t c = g % ws.C, s = g / ws.C + 1;
-    const ChainSpan sp = Prob::span(pp, c, ws.n);
-    const int64_t n = sp.n;
-    const int64_t a = s * ws.L;
-    const int64_t b = (a + ws.L < n) ? a + ws.L : n;
-    const int64_t cs = c * ws.S + s;
-    const int64_t C = ws.C;
+    if (same) return;
     const auto src = Prob::src(pp, sp);
     CRing<T, K, typename Prob::Tag> R;
     R.init(s_ent, lane);
@@ -1232,8 +1202,6 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
     const int64_t fbl = (C < kOverflowLanes ? (C + 63) / 64 * 64 : kOverflowLanes);
     const size_t o_oc = off;   off += al(sizeof(int));
     const size_t o_ol = off;   off += al(sizeof(int) * (size_t)C);
-    const size_t o_rc = off;   off += al(sizeof(int));
-    const size_t o_rl = off;   off += al(sizeof(int) * (size_t)(S * C));
     const size_t o_sw = off;   off += al(sizeof(LamPair<T>) * (size_t)(kCheckpoints * S * C));
     const size_t o_fl = off;   off += al(sizeof(T) * (size_t)(fbl * cap));
     const size_t o_ft = off;   off += al(sizeof(G) * (size_t)(fbl * cap));
@@ -1260,8 +1228,6 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
         w.seg_xb = (T *)(p + o_xb);
         w.ovf_count = (int *)(p + o_oc);
         w.ovf_list = (int *)(p + o_ol);
-        w.rep_count = (int *)(p + o_rc);
-        w.rep_list = (int *)(p + o_rl);
         w.sw_cp = (LamPair<T> *)(p + o_sw);
         w.fb_lam = (T *)(p + o_fl);
         w.fb_tag = (G *)(p + o_ft);
@@ -1279,7 +1245,6 @@ hipError_t seg_launch(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, 
     hipLaunchKernelGGL((k_seg_main<T, Prob, K, P>), dim3(blocks), dim3(64), 0, stream, ws, pp);
     if (ws.S > 1) {
         const unsigned rb = (unsigned)(((ws.S - 1) * ws.C + 63) / 64);
-        hipLaunchKernelGGL((k_seg_check<T, Prob, K>), dim3(rb), dim3(64), 0, stream, ws, pp);
         hipLaunchKernelGGL((k_seg_repair<T, Prob, K, P>), dim3(rb), dim3(64), 0, stream, ws, pp);
     }
     const unsigned fb = (unsigned)((ws.C + 63) / 64);
