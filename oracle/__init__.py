@@ -19,6 +19,10 @@ arrays.  Functions and the passages they follow:
 * ``tv2d``            -- Sec. 5.1 ROF via Lagrangian decomposition and the
                          accelerated primal-dual iteration eq. (pd), with an
                          FP64 duality gap.
+* ``nc_chain``        -- Sec. 3 (non-convex case) on a chain: piecewise-linear
+                         unaries, truncated TV, Lemma 1, Algorithm 1 and its
+                         reversal, the truncation, and the backward pass through
+                         the mappings pi; ``nc_brute`` is its independent pin.
 """
 from __future__ import annotations
 
@@ -92,6 +96,12 @@ def _load():
     lib.orc_tree_pq_brute.restype = ctypes.c_int
     lib.orc_tree_pq_objective.argtypes = [I64, P, P, P, P, P, P, P, P]
     lib.orc_tree_pq_objective.restype = D
+    lib.orc_nc_chain.argtypes = [I64, P, P, P, P, P, P, P]
+    lib.orc_nc_chain.restype = ctypes.c_int
+    lib.orc_nc_energy.argtypes = [I64, P, P, P, P, P, P]
+    lib.orc_nc_energy.restype = D
+    lib.orc_nc_brute.argtypes = [I64, P, P, P, P, P, P, P]
+    lib.orc_nc_brute.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -345,3 +355,46 @@ def tree_pq_objective(parent, a, b, c, d, wm, wp, x) -> float:
     n, parent, a, b, c, d, wm, wp = _tree_args(parent, a, b, c, d, wm, wp)
     return float(_load().orc_tree_pq_objective(n, _ptr(parent), _ptr(a), _ptr(b), _ptr(c), _ptr(d), _ptr(wm),
                                                _ptr(wp), _ptr(_f64(x))))
+
+
+def _nc_args(uoff, ulam, uslope, w, C):
+    uoff = np.ascontiguousarray(uoff, dtype=np.int64)
+    n = uoff.size - 1
+    ulam, uslope = _f64(ulam), _f64(uslope)
+    if ulam.size != uoff[-1] or uslope.size != uoff[-1] + n:
+        raise ValueError("unary arrays do not match the offsets")
+    w = _f64(np.broadcast_to(w, (max(n - 1, 0),)))
+    C = _f64(np.broadcast_to(C, (max(n - 1, 0),)))
+    return n, uoff, ulam, uslope, w, C
+
+
+def nc_chain(uoff, ulam, uslope, w, C):
+    """Sec. 3 on a chain: piecewise-linear unaries (node i: breakpoints
+    ulam[uoff[i]:uoff[i+1]], slopes uslope[uoff[i]+i : uoff[i+1]+i+1]) and
+    truncated TV min(w_e |x_{e+1} - x_e|, C_e) (C_e = inf: plain TV).
+    Returns (x, largest number of message breakpoints)."""
+    n, uoff, ulam, uslope, w, C = _nc_args(uoff, ulam, uslope, w, C)
+    x = np.empty(n)
+    mb = ctypes.c_int64(0)
+    rc = _load().orc_nc_chain(n, _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(w), _ptr(C), _ptr(x), ctypes.byref(mb))
+    if rc != 0:
+        raise ValueError("orc_nc_chain: invalid input (%d)" % rc)
+    return x, int(mb.value)
+
+
+def nc_energy(uoff, ulam, uslope, w, C, x) -> float:
+    """sum_i f_i(x_i) + sum_e min(w_e |x_{e+1} - x_e|, C_e), with f_i(first breakpoint) = 0."""
+    n, uoff, ulam, uslope, w, C = _nc_args(uoff, ulam, uslope, w, C)
+    x = _f64(x)
+    return float(_load().orc_nc_energy(n, _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(w), _ptr(C), _ptr(x)))
+
+
+def nc_brute(uoff, ulam, uslope, w, C):
+    """Exact minimum energy and a minimiser for n <= 5 (vertex candidates, Viterbi)."""
+    n, uoff, ulam, uslope, w, C = _nc_args(uoff, ulam, uslope, w, C)
+    x = np.empty(n)
+    e = ctypes.c_double(0.0)
+    rc = _load().orc_nc_brute(n, _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(w), _ptr(C), _ptr(x), ctypes.byref(e))
+    if rc != 0:
+        raise ValueError("orc_nc_brute: invalid input (%d)" % rc)
+    return float(e.value), x

@@ -37,6 +37,13 @@
  *                          messages (the union of their breakpoint sets, the
  *                          "Extension to trees" of Sec. 4.2) plus its unary.
  *   orc_tree_pq_brute   -- brute force over edge and node states, n <= 6.
+ *   orc_nc_chain        -- Sec. 3, non-convex case on a chain: piecewise-linear
+ *                          unaries and truncated TV min(w|z|, C), messages as
+ *                          slope/breakpoint sequences, Lemma 1 (sum), Lemma 2 via
+ *                          Prop. 2 (Algorithm 1, its reversal, the truncation)
+ *                          and the backward pass through the mappings pi.
+ *   orc_nc_brute        -- exact minimum of the same energy on tiny chains
+ *                          (n <= 5) by a Viterbi pass over vertex candidates.
  *   orc_tv2d_l1         -- Sec. 5.2 TV-l1 by the same decomposition: the
  *                          primal-dual iteration eq. (pd) with the dual prox of
  *                          lambda TV_v on the columns (as for ROF) and the primal
@@ -1083,5 +1090,497 @@ int orc_tree_pq_brute(int64_t n, const int64_t *parent, const double *a, const d
             }
         }
     }
+    return 0;
+}
+
+/* ======================================================================== *
+ * Sec. 3: non-convex case on a chain.  Unaries f_i are continuous
+ * piecewise-linear (breakpoints lam_{i,1..t_i}, slopes s_{i,0..t_i}, fixed by
+ * f_i(lam_{i,1}) = 0); pairwise terms are the truncated TV f_e(z) = min(w_e |z|,
+ * C_e) with w_e >= 0 and 0 < C_e <= +inf, z = x_{e+1} - x_e.
+ *
+ * Messages are kept as in Sec. 3: the sequence (s_0, lam_1, s_1, ..., lam_t,
+ * s_t), defined up to an additive constant.  Per edge:
+ *   hat M_i = f_i + M_{i-1}                       (Lemma 1: breakpoints merged,
+ *                                                  slopes added)
+ *   M_i = ((hat M_i (x) f^1) (x) f^2) (x) f^3     (Lemma 2 via the consecutive
+ *                                                  min-convolutions of Prop. 2)
+ * with f^1 = w z on z >= 0 (+inf below), f^2 = w|z| on z <= 0 (+inf above),
+ * f^3 = C off zero (0 at zero).  h (x) f^1 follows Algorithm 1 and records the
+ * intervals Pi^1 on which the minimiser is the interval's left end; h (x) f^2
+ * is the reversal of rev(h) (x) f^1; h (x) f^3 = min(h, min h + C) with Pi^3 the
+ * set where h >= min h + C (minimiser: the argmin breakpoint).  Backward: the
+ * last node takes an argmin of its hat M, then x_i = pi^1(pi^2(pi^3(x_{i+1}))).
+ * ======================================================================== */
+typedef struct {
+    int64_t t, cap;
+    double *l, *s; /* l[0..t-1], s[0..t]: s[k] is the slope left of l[k] */
+} nc_plf;
+
+typedef struct {
+    int64_t n, cap;
+    double *a, *b, *to; /* interval [a, b] maps to `to` */
+} nc_ivs;
+
+static int nc_reserve(nc_plf *h, int64_t t)
+{
+    if (t <= h->cap) return 0;
+    int64_t c = h->cap ? h->cap : 16;
+    while (c < t) c *= 2;
+    double *l = (double *)realloc(h->l, sizeof(double) * (size_t)c);
+    if (!l) return -2;
+    h->l = l;
+    double *s = (double *)realloc(h->s, sizeof(double) * (size_t)(c + 1));
+    if (!s) return -2;
+    h->s = s;
+    h->cap = c;
+    return 0;
+}
+
+static void nc_free(nc_plf *h)
+{
+    free(h->l);
+    free(h->s);
+    h->l = h->s = NULL;
+    h->t = h->cap = 0;
+}
+
+static int nc_iv_add(nc_ivs *v, double a, double b, double to)
+{
+    if (v->n == v->cap) {
+        int64_t c = v->cap ? 2 * v->cap : 64;
+        double *na = (double *)realloc(v->a, sizeof(double) * (size_t)c);
+        if (!na) return -2;
+        v->a = na;
+        double *nb = (double *)realloc(v->b, sizeof(double) * (size_t)c);
+        if (!nb) return -2;
+        v->b = nb;
+        double *nt = (double *)realloc(v->to, sizeof(double) * (size_t)c);
+        if (!nt) return -2;
+        v->to = nt;
+        v->cap = c;
+    }
+    v->a[v->n] = a;
+    v->b[v->n] = b;
+    v->to[v->n] = to;
+    v->n++;
+    return 0;
+}
+
+/* Append breakpoint lam with slope `right` to its right. */
+static int nc_push(nc_plf *h, double lam, double right)
+{
+    if (nc_reserve(h, h->t + 1)) return -2;
+    h->l[h->t] = lam;
+    h->s[h->t + 1] = right;
+    h->t++;
+    return 0;
+}
+
+/* Values v[p] = h(l[p]) relative to v[0] = 0, accumulated along the slopes. */
+static void nc_values(const nc_plf *h, double *v)
+{
+    if (h->t == 0) return;
+    v[0] = 0.0;
+    for (int64_t p = 1; p < h->t; ++p) v[p] = v[p - 1] + h->s[p] * (h->l[p] - h->l[p - 1]);
+}
+
+/* Lemma 1: out = a + b (breakpoint lists merged; equal positions become one). */
+static int nc_add(const nc_plf *a, const nc_plf *b, nc_plf *out)
+{
+    out->t = 0;
+    if (nc_reserve(out, a->t + b->t)) return -2;
+    int64_t i = 0, j = 0;
+    out->s[0] = a->s[0] + b->s[0];
+    while (i < a->t || j < b->t) {
+        double lam;
+        if (j >= b->t || (i < a->t && a->l[i] < b->l[j])) {
+            lam = a->l[i++];
+        } else if (i >= a->t || b->l[j] < a->l[i]) {
+            lam = b->l[j++];
+        } else {
+            lam = a->l[i];
+            ++i;
+            ++j;
+        }
+        /* slope right of lam: each function's slope after its breakpoints <= lam */
+        out->l[out->t] = lam;
+        out->s[out->t + 1] = a->s[i] + b->s[j];
+        out->t++;
+    }
+    return 0;
+}
+
+/* Algorithm 1: out = h (x) f^1 (f^1(z) = w z for z >= 0), Pi^1 appended to iv
+ * (each interval maps to its left end).  h must have s[0] <= 0. */
+static int nc_dt_f1(const nc_plf *h, double w, nc_plf *out, nc_ivs *iv)
+{
+    const int64_t t = h->t;
+    double *v = (double *)malloc(sizeof(double) * (size_t)(t > 0 ? t : 1));
+    if (!v) return -2;
+    nc_values(h, v);
+    out->t = 0;
+    if (nc_reserve(out, t)) {
+        free(v);
+        return -2;
+    }
+    out->s[0] = h->s[0];
+    int64_t p = 0;
+    int rc = 0;
+    while (p < t && rc == 0) {
+        const double right = h->s[p + 1];
+        rc = nc_push(out, h->l[p], right < w ? right : w);
+        if (rc) break;
+        if (right >= w) {
+            /* the line of slope w through (l[p], v[p]); first later breakpoint
+             * (skipping p + 1, which lies on or above it) where h is below it */
+            const double lp = h->l[p], vp = v[p];
+            int64_t q = p + 2 < t ? p + 2 : t;  /* q = t: the unbounded right piece */
+            while (q < t && !(v[q] < vp + w * (h->l[q] - lp))) ++q;
+            if (q == t && !(h->s[t] < w)) {  /* h never drops below the line */
+                rc = nc_iv_add(iv, lp, INFINITY, lp);
+                break;
+            }
+            /* crossing on the piece left of breakpoint q (slope s[q] < w) */
+            const double l0 = h->l[q - 1], v0 = v[q - 1];
+            double lam = l0 + (vp + w * (l0 - lp) - v0) / (h->s[q] - w);
+            if (lam < l0) lam = l0;
+            if (q < t && lam > h->l[q]) lam = h->l[q];
+            rc = nc_push(out, lam, h->s[q]);
+            if (rc == 0) rc = nc_iv_add(iv, lp, lam, lp);
+            p = q;
+        } else {
+            ++p;
+        }
+    }
+    free(v);
+    return rc;
+}
+
+/* phi^rev(z) = phi(-z): sequence reversed, every component negated. */
+static int nc_rev(const nc_plf *h, nc_plf *out)
+{
+    out->t = 0;
+    if (nc_reserve(out, h->t)) return -2;
+    out->t = h->t;
+    for (int64_t k = 0; k < h->t; ++k) out->l[k] = -h->l[h->t - 1 - k];
+    for (int64_t k = 0; k <= h->t; ++k) out->s[k] = -h->s[h->t - k];
+    return 0;
+}
+
+/* h (x) f^2 = (rev(h) (x) f^1)^rev; each interval maps to its right end. */
+static int nc_dt_f2(const nc_plf *h, double w, nc_plf *out, nc_ivs *iv, nc_plf *tmp1, nc_plf *tmp2)
+{
+    nc_ivs r = {0, 0, NULL, NULL, NULL};
+    int rc = nc_rev(h, tmp1);
+    if (rc == 0) rc = nc_dt_f1(tmp1, w, tmp2, &r);
+    if (rc == 0) rc = nc_rev(tmp2, out);
+    for (int64_t k = 0; rc == 0 && k < r.n; ++k) rc = nc_iv_add(iv, -r.b[k], -r.a[k], -r.to[k]);
+    free(r.a);
+    free(r.b);
+    free(r.to);
+    return rc;
+}
+
+/* h at z, from the values v at the breakpoints (t >= 1). */
+static double nc_eval(const nc_plf *h, const double *v, double z)
+{
+    const int64_t t = h->t;
+    if (z <= h->l[0]) return v[0] + h->s[0] * (z - h->l[0]);
+    for (int64_t k = 1; k < t; ++k)
+        if (z <= h->l[k]) return v[k - 1] + h->s[k] * (z - h->l[k - 1]);
+    return v[t - 1] + h->s[t] * (z - h->l[t - 1]);
+}
+
+/* slope of h at z (z inside a piece) */
+static double nc_slope_at(const nc_plf *h, double z)
+{
+    int64_t k = 0;
+    while (k < h->t && z > h->l[k]) ++k;
+    return h->s[k];
+}
+
+/* h (x) f^3 = min(h, C'), C' = min h + C.  The points where the result may
+ * kink are h's breakpoints and, in each piece, where h crosses C'; between
+ * consecutive points the result is h (below C') or flat (at or above C',
+ * decided at the segment's midpoint).  Pi^3 = the flat runs, each mapped to
+ * the first argmin breakpoint. */
+static int nc_trunc(const nc_plf *h, double C, nc_plf *out, nc_ivs *iv)
+{
+    const int64_t t = h->t;
+    out->t = 0;
+    if (nc_reserve(out, 2 * t + 2)) return -2;
+    if (t == 0) {  /* bounded below and linear: constant, never above C' */
+        out->s[0] = h->s[0];
+        return 0;
+    }
+    /* v: t values; pts: up to 2t + 1 points; sl: up to 2t + 2 segment slopes */
+    double *v = (double *)malloc(sizeof(double) * (size_t)(5 * t + 3));
+    if (!v) return -2;
+    double *pts = v + t, *sl = v + 3 * t + 1;
+    nc_values(h, v);
+    int64_t pm = 0;
+    for (int64_t p = 1; p < t; ++p)
+        if (v[p] < v[pm]) pm = p;
+    const double cp = v[pm] + C, xm = h->l[pm];
+    int64_t m = 0;
+    for (int64_t k = 0; k <= t; ++k) {
+        /* crossing of C' inside piece k (left of l[k]; piece 0 and t unbounded) */
+        if (k == 0) {
+            if (h->s[0] < 0.0 && v[0] < cp) pts[m++] = h->l[0] + (cp - v[0]) / h->s[0];
+        } else if (k == t) {
+            if (h->s[t] > 0.0 && v[t - 1] < cp) pts[m++] = h->l[t - 1] + (cp - v[t - 1]) / h->s[t];
+        } else if ((v[k - 1] < cp && v[k] > cp) || (v[k - 1] > cp && v[k] < cp)) {
+            pts[m++] = h->l[k - 1] + (cp - v[k - 1]) / h->s[k];
+        }
+        if (k < t) pts[m++] = h->l[k];
+    }
+    /* segment j in 0..m spans (pts[j-1], pts[j]) with pts[-1] = -inf, pts[m] = +inf */
+    int rc = 0;
+    double run = 0.0;
+    int in_run = 0;
+    for (int64_t j = 0; j <= m; ++j) {
+        const double mid = (j == 0) ? pts[0] - 1.0 : (j == m ? pts[m - 1] + 1.0 : 0.5 * (pts[j - 1] + pts[j]));
+        const int above = nc_eval(h, v, mid) >= cp;
+        sl[j] = above ? 0.0 : nc_slope_at(h, mid);
+        if (above && !in_run) {
+            run = (j == 0) ? -INFINITY : pts[j - 1];
+            in_run = 1;
+        } else if (!above && in_run) {
+            rc = nc_iv_add(iv, run, pts[j - 1], xm);
+            in_run = 0;
+        }
+        if (rc) break;
+    }
+    if (rc == 0 && in_run) rc = nc_iv_add(iv, run, INFINITY, xm);
+    if (rc == 0) {
+        out->s[0] = sl[0];
+        for (int64_t j = 0; j < m && rc == 0; ++j)
+            if (sl[j + 1] != out->s[out->t]) rc = nc_push(out, pts[j], sl[j + 1]);
+    }
+    free(v);
+    return rc;
+}
+
+/* pi(y) for a set of intervals: the first interval containing y, else y. */
+static double nc_apply(const nc_ivs *iv, int64_t lo, int64_t hi, double y)
+{
+    for (int64_t k = lo; k < hi; ++k)
+        if (y >= iv->a[k] && y <= iv->b[k]) return iv->to[k];
+    return y;
+}
+
+static int nc_unary(int64_t i, const int64_t *uoff, const double *ulam, const double *uslope, nc_plf *f)
+{
+    const int64_t t = uoff[i + 1] - uoff[i];
+    if (t < 1) return -1;
+    f->t = 0;
+    if (nc_reserve(f, t)) return -2;
+    f->t = t;
+    const double *l = ulam + uoff[i], *s = uslope + uoff[i] + i;
+    for (int64_t k = 0; k < t; ++k) {
+        if (k > 0 && !(l[k] >= l[k - 1])) return -1;
+        f->l[k] = l[k];
+    }
+    for (int64_t k = 0; k <= t; ++k) f->s[k] = s[k];
+    if (!(f->s[0] <= 0.0) || !(f->s[t] >= 0.0)) return -1;  /* bounded below */
+    return 0;
+}
+
+/* The chain: nodes 0..n-1; node i has t_i = uoff[i+1] - uoff[i] >= 1
+ * breakpoints ulam[uoff[i] ..] and t_i + 1 slopes uslope[uoff[i] + i ..];
+ * edge e (nodes e, e+1) has w[e] >= 0 and C[e] > 0 (INFINITY: plain TV).
+ * max_bp (optional) receives the largest number of breakpoints of any
+ * message.  Returns 0, -1 for invalid input, -2 if out of memory. */
+int orc_nc_chain(int64_t n, const int64_t *uoff, const double *ulam, const double *uslope, const double *w,
+                 const double *C, double *x, int64_t *max_bp)
+{
+    if (n < 1) return -1;
+    nc_plf hat = {0, 0, NULL, NULL}, f = {0, 0, NULL, NULL}, m1 = {0, 0, NULL, NULL}, m2 = {0, 0, NULL, NULL},
+           t1 = {0, 0, NULL, NULL}, t2 = {0, 0, NULL, NULL}, msg = {0, 0, NULL, NULL};
+    nc_ivs iv1 = {0, 0, NULL, NULL, NULL}, iv2 = {0, 0, NULL, NULL, NULL}, iv3 = {0, 0, NULL, NULL, NULL};
+    int64_t *o1 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(3 * n + 3));
+    int rc = o1 ? 0 : -2;
+    int64_t *o2 = o1 ? o1 + (n + 1) : NULL, *o3 = o1 ? o1 + 2 * (n + 1) : NULL;
+    int64_t mb = 0;
+    if (rc == 0) rc = nc_reserve(&msg, 1);
+    msg.t = 0;
+    if (rc == 0) msg.s[0] = 0.0;
+    for (int64_t i = 0; i < n && rc == 0; ++i) {
+        rc = nc_unary(i, uoff, ulam, uslope, &f);
+        if (rc == 0) rc = nc_add(&f, &msg, &hat);
+        if (rc) break;
+        mb = hat.t > mb ? hat.t : mb;
+        if (i == n - 1) break;
+        if (!(w[i] >= 0.0) || !(C[i] > 0.0)) {
+            rc = -1;
+            break;
+        }
+        o1[i] = iv1.n;
+        o2[i] = iv2.n;
+        o3[i] = iv3.n;
+        rc = nc_dt_f1(&hat, w[i], &m1, &iv1);
+        if (rc == 0) rc = nc_dt_f2(&m1, w[i], &m2, &iv2, &t1, &t2);
+        if (rc == 0 && isfinite(C[i])) {
+            rc = nc_trunc(&m2, C[i], &msg, &iv3);
+        } else if (rc == 0) {
+            rc = nc_reserve(&msg, m2.t);
+            if (rc == 0) {
+                msg.t = m2.t;
+                memcpy(msg.l, m2.l, sizeof(double) * (size_t)m2.t);
+                memcpy(msg.s, m2.s, sizeof(double) * (size_t)(m2.t + 1));
+            }
+        }
+        o1[i + 1] = iv1.n;
+        o2[i + 1] = iv2.n;
+        o3[i + 1] = iv3.n;
+        if (rc == 0) mb = msg.t > mb ? msg.t : mb;
+    }
+    if (rc == 0) {
+        /* the last node: an argmin of hat M (a breakpoint, the function being
+         * bounded below with slopes s_0 <= 0 <= s_t) */
+        double *v = (double *)malloc(sizeof(double) * (size_t)(hat.t > 0 ? hat.t : 1));
+        if (!v) {
+            rc = -2;
+        } else {
+            nc_values(&hat, v);
+            int64_t pm = 0;
+            for (int64_t p = 1; p < hat.t; ++p)
+                if (v[p] < v[pm]) pm = p;
+            double y = hat.t > 0 ? hat.l[pm] : 0.0;
+            x[n - 1] = y;
+            for (int64_t i = n - 2; i >= 0; --i) {
+                y = nc_apply(&iv3, o3[i], o3[i + 1], y);
+                y = nc_apply(&iv2, o2[i], o2[i + 1], y);
+                y = nc_apply(&iv1, o1[i], o1[i + 1], y);
+                x[i] = y;
+            }
+            free(v);
+        }
+    }
+    if (max_bp) *max_bp = mb;
+    nc_free(&hat);
+    nc_free(&f);
+    nc_free(&m1);
+    nc_free(&m2);
+    nc_free(&t1);
+    nc_free(&t2);
+    nc_free(&msg);
+    free(iv1.a); free(iv1.b); free(iv1.to);
+    free(iv2.a); free(iv2.b); free(iv2.to);
+    free(iv3.a); free(iv3.b); free(iv3.to);
+    free(o1);
+    return rc;
+}
+
+/* f_i(z) with f_i(lam_{i,1}) = 0. */
+static double nc_unary_val(int64_t i, const int64_t *uoff, const double *ulam, const double *uslope, double z)
+{
+    const int64_t t = uoff[i + 1] - uoff[i];
+    const double *l = ulam + uoff[i], *s = uslope + uoff[i] + i;
+    if (z <= l[0]) return s[0] * (z - l[0]);
+    double v = 0.0;
+    for (int64_t k = 1; k < t; ++k) {
+        if (z <= l[k]) return v + s[k] * (z - l[k - 1]);
+        v += s[k] * (l[k] - l[k - 1]);
+    }
+    return v + s[t] * (z - l[t - 1]);
+}
+
+double orc_nc_energy(int64_t n, const int64_t *uoff, const double *ulam, const double *uslope, const double *w,
+                     const double *C, const double *x)
+{
+    double e = 0.0;
+    for (int64_t i = 0; i < n; ++i) e += nc_unary_val(i, uoff, ulam, uslope, x[i]);
+    for (int64_t i = 0; i + 1 < n; ++i) {
+        const double d = w[i] * fabs(x[i + 1] - x[i]);
+        e += (isfinite(C[i]) && C[i] < d) ? C[i] : d;
+    }
+    return e;
+}
+
+/* Brute force for tiny chains (n <= 5), independent of the message passing: a
+ * minimiser of a coercive piecewise-linear energy lies at a vertex, where every
+ * x_i equals some unary breakpoint b plus a sum of offsets in {0, +-C_e/w_e}
+ * over the edges between i and b's node.  An exact Viterbi over those
+ * candidates gives the minimum energy (and a minimiser). */
+int orc_nc_brute(int64_t n, const int64_t *uoff, const double *ulam, const double *uslope, const double *w,
+                 const double *C, double *xbest, double *emin)
+{
+    if (n < 1 || n > 5) return -1;
+    int64_t nb = uoff[n] - uoff[0];
+    /* offsets reachable over up to n-1 consecutive edges */
+    enum { MAXC = 8192 };
+    static double cand[MAXC];
+    int64_t nc = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t k = uoff[j]; k < uoff[j + 1]; ++k) {
+            /* paths from node j to every node i: offsets of the edges between */
+            for (int64_t i = 0; i < n; ++i) {
+                const int64_t lo = i < j ? i : j, hi = i < j ? j : i;  /* edges lo .. hi-1 */
+                const int64_t m = hi - lo;
+                int64_t combos = 1;
+                for (int64_t q = 0; q < m; ++q) combos *= 3;
+                for (int64_t cmb = 0; cmb < combos; ++cmb) {
+                    double z = ulam[k];
+                    int64_t r = cmb;
+                    int ok = 1;
+                    for (int64_t q = 0; q < m; ++q) {
+                        const int d = (int)(r % 3) - 1;
+                        r /= 3;
+                        if (d != 0) {
+                            const double e = lo + q, c = C[(int64_t)e];
+                            if (!isfinite(c) || !(w[(int64_t)e] > 0.0)) {
+                                ok = 0;
+                                break;
+                            }
+                            z += d * c / w[(int64_t)e];
+                        }
+                    }
+                    if (ok && nc < MAXC) cand[nc++] = z;
+                }
+            }
+        }
+    }
+    (void)nb;
+    /* Viterbi over the candidate set (every node takes any candidate) */
+    double *cost = (double *)malloc(sizeof(double) * (size_t)(nc * n));
+    int64_t *arg = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc * n));
+    if (!cost || !arg) {
+        free(cost);
+        free(arg);
+        return -2;
+    }
+    for (int64_t a = 0; a < nc; ++a) {
+        cost[a] = nc_unary_val(0, uoff, ulam, uslope, cand[a]);
+        arg[a] = -1;
+    }
+    for (int64_t i = 1; i < n; ++i) {
+        for (int64_t b = 0; b < nc; ++b) {
+            double best = INFINITY;
+            int64_t ab = 0;
+            for (int64_t a = 0; a < nc; ++a) {
+                double d = w[i - 1] * fabs(cand[b] - cand[a]);
+                if (isfinite(C[i - 1]) && C[i - 1] < d) d = C[i - 1];
+                const double v = cost[(i - 1) * nc + a] + d;
+                if (v < best) {
+                    best = v;
+                    ab = a;
+                }
+            }
+            cost[i * nc + b] = best + nc_unary_val(i, uoff, ulam, uslope, cand[b]);
+            arg[i * nc + b] = ab;
+        }
+    }
+    int64_t bb = 0;
+    for (int64_t b = 1; b < nc; ++b)
+        if (cost[(n - 1) * nc + b] < cost[(n - 1) * nc + bb]) bb = b;
+    *emin = cost[(n - 1) * nc + bb];
+    for (int64_t i = n - 1; i >= 0; --i) {
+        xbest[i] = cand[bb];
+        bb = arg[i * nc + bb];
+    }
+    free(cost);
+    free(arg);
     return 0;
 }
