@@ -20,8 +20,9 @@ Also on the same JSON line:
                   1,024 with per-edge weights, the general chain DP (data weights,
                   asymmetric edge slopes) on the 4096^2 rows and columns, the
                   TV-l1 chain prox of 65,536 salt & pepper chains, 100 iterations
-                  of 2D TV-l1 at 4096^2, 65,536 trees of 256 nodes, and a batch
-                  of 256 uneven images.
+                  of 2D TV-l1 at 4096^2, 65,536 trees of 256 nodes, the 1000 rows
+                  of a 64-level synthetic cost volume as non-convex chains
+                  (truncated TV), and a batch of 256 uneven images.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras | --extras LIST]
        python bench.py --rocprof-summary DIR   (print a summary of rocprofv3 output)
@@ -326,6 +327,32 @@ def bench_tv2d_l1():
             "energy_f": e0, "energy_100": st["primal"]}
 
 
+def bench_nc(steps: int):
+    """Sec. 3 non-convex chains (tv_chain_nc): the 1000 rows (1482 nodes) of a
+    synthetic stereo-like cost volume with 64 levels (piecewise-linear unaries
+    through the level costs, 64 breakpoints each), truncated TV w = 0.6, C = 2,
+    FP32 in, FP64 inside.  Algorithmic bytes: the unary (64 breakpoints + 65
+    slopes) and w, C read and x written, 4 B each: 524 B/node."""
+    import numpy as np
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    H, W, D = 1000, 1482, 64
+    coff, uoff, ulam, usl, dt = synth.cost_volume_chains(H, W, D, seed=1)
+    N = uoff.size - 1
+    dev = lambda a, t=torch.float32: torch.tensor(a, dtype=t, device="cuda")  # noqa: E731
+    args = (dev(coff, torch.int64), dev(uoff, torch.int64), dev(ulam), dev(usl), dev(np.full(N, 0.6)),
+            dev(np.full(N, 2.0)))
+    del ulam, usl
+    run = lambda: binding.chain_nc(*args, msg_cap=256)  # noqa: E731
+    x = run()
+    tm = Timer(torch, torch.cuda.current_stream())
+    ms = tm(run, steps)
+    err = float(np.abs(x.cpu().numpy().reshape(H, W) - dt).mean())
+    return {"workload": "1000 rows x 1482 of a 64-level synthetic cost volume, truncated TV w 0.6, C 2, FP32 in, "
+                        "FP64 messages", "ms": round(ms, 2), "mnode_s": round(N / ms / 1e3, 2),
+            "hbm_frac": round(N * 524 / (ms * 1e-3) / 8e12, 5), "mean_abs_x_minus_true_disparity": round(err, 3)}
+
+
 def bench_tree(steps: int):
     """Algorithm 2 on 65,536 random post-order trees of 256 nodes (tv_tree_dp)
     with a ~ U[0.3, 2], TV-l1 data terms on 70% of the nodes, asymmetric edge
@@ -482,7 +509,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,batched")
+                    help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,nc,"
+                         "batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -566,6 +594,7 @@ def main():
                 ("tv_l1", "TV-l1 chain prox 65536x1024", lambda: bench_l1(10, autotune=not args.no_autotune)),
                 ("tv2d_l1", "2D TV-l1 4096x4096", bench_tv2d_l1),
                 ("tree", "trees 65536x256", lambda: bench_tree(5)),
+                ("nc", "non-convex chains 1000x1482, 64 levels", lambda: bench_nc(3)),
                 ("batched", "batched 256 images", bench_batched)]
         pick = None if args.extras == "all" else set(args.extras.split(","))
         try:

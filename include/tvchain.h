@@ -238,6 +238,35 @@ tv_status tv_tree_dp(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
                      const void *wm, const void *wp, void *x, void *workspace, size_t workspace_bytes,
                      hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Non-convex chains, Sec. 3: a batch of chains, each minimising
+ *     sum_i f_i(x_i) + sum_e min(w_e |x_{e+1} - x_e|, C_e)
+ * with f_i continuous piecewise-linear and the truncated TV of the pairwise
+ * terms (Lemma 1, Lemma 2 with Algorithm 1, its reversal and the truncation,
+ * and the backward pass through the mappings pi), exactly, one lane per chain.
+ *  chain_offsets : DEVICE int64 [num_chains + 1], node ranges (non-decreasing,
+ *                  last = num_nodes).
+ *  unary_offsets : DEVICE int64 [num_nodes + 1]; node i has t_i = unary_offsets[i+1]
+ *                  - unary_offsets[i] >= 1 breakpoints ulam[unary_offsets[i] ..]
+ *                  (non-decreasing) and t_i + 1 slopes uslope[unary_offsets[i] + i ..]
+ *                  (slope left of the first breakpoint first; s_0 <= 0 <= s_t,
+ *                  so that f_i is bounded below).
+ *  w, C          : DEVICE [num_nodes], the edge from node i to node i + 1 of the
+ *                  same chain (a chain's last entry is unused); w >= 0, C > 0;
+ *                  C NULL or +inf: plain TV.
+ *  x             : DEVICE [num_nodes] output.
+ *  msg_cap       : breakpoints a message may hold (1 .. 2^24).
+ *  map_cap       : intervals of the mappings pi kept per chain (1 .. 2^30).
+ * FP64 inside; dtype is that of ulam, uslope, w, C and x.  Synchronous.
+ * Returns TV_ERR_INVALID_ARG for an invalid unary, w < 0 or C <= 0 (found on
+ * the device), TV_ERR_WORKSPACE if the workspace is too small or a message or
+ * a chain's mappings outgrew msg_cap / map_cap (x is then incomplete). */
+size_t tv_chain_nc_workspace(int64_t num_chains, int64_t num_nodes, int64_t msg_cap, int64_t map_cap);
+tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, const int64_t *chain_offsets,
+                      const int64_t *unary_offsets, const void *ulam, const void *uslope, const void *w,
+                      const void *C, void *x, int64_t msg_cap, int64_t map_cap, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+
 /* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
 size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);
 

@@ -103,6 +103,9 @@ _SIG = {
                                      ctypes.c_size_t, _P]),
     "tv2d_l1_autotune": (ctypes.c_int, [ctypes.c_int, _P, _I64, _I64, _I64, ctypes.c_double, ctypes.c_double, _P,
                                         ctypes.c_size_t, _P, _P, _P]),
+    "tv_chain_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64]),
+    "tv_chain_nc": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _I64, _I64, _P,
+                                   ctypes.c_size_t, _P]),
     "tv_tree_dp_workspace": (ctypes.c_size_t, [_I64, _I64]),
     "tv_tree_dp": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                   _P]),
@@ -680,4 +683,43 @@ def tree_dp(parent: torch.Tensor, offsets: torch.Tensor, b: torch.Tensor, wm: to
     st = lib.tv_tree_dp(_dtype_code(b), T, N, _ptr(offsets), _ptr(parent), *(_ptr(t) for t in ts), _ptr(x), _ptr(ws),
                         nbytes, ctypes.c_void_p(_stream_ptr(b.device)))
     _check(st, "tv_tree_dp")
+    return x
+
+
+def chain_nc(chain_offsets: torch.Tensor, unary_offsets: torch.Tensor, ulam: torch.Tensor, uslope: torch.Tensor,
+             w: torch.Tensor, C: Optional[torch.Tensor] = None, msg_cap: int = 1024,
+             map_cap: Optional[int] = None) -> torch.Tensor:
+    """Sec. 3 non-convex chains (tv_chain_nc): chain_offsets (int64, chains + 1
+    node ranges), unary_offsets (int64, nodes + 1; node i has breakpoints
+    ulam[unary_offsets[i]:unary_offsets[i+1]] and slopes
+    uslope[unary_offsets[i]+i : unary_offsets[i+1]+i+1]), per-node w and C of the
+    edge to the next node (C None or inf: plain TV).  msg_cap bounds a
+    message's breakpoints, map_cap the intervals kept per chain (default: 32 per
+    node of the longest chain; cost-volume chains need about 8 to 12).  Returns x
+    (one value per node)."""
+    _require_gpu(chain_offsets, unary_offsets, ulam, uslope, w)
+    lib = load()
+    if chain_offsets.dtype != torch.int64 or unary_offsets.dtype != torch.int64:
+        raise TvChainError(TV_ERR_INVALID_ARG, "offsets must be int64")
+    N = unary_offsets.numel() - 1
+    ts = [t.contiguous() if t is not None else None for t in (ulam, uslope, w, C)]
+    for t in ts:
+        if t is not None and t.dtype != ulam.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "float arrays must share one dtype")
+    if ts[2].numel() != N or (ts[3] is not None and ts[3].numel() != N):
+        raise TvChainError(TV_ERR_INVALID_ARG, "w and C hold one value per node")
+    chain_offsets, unary_offsets = chain_offsets.contiguous(), unary_offsets.contiguous()
+    nchains = chain_offsets.numel() - 1
+    if map_cap is None:
+        longest = int((chain_offsets[1:] - chain_offsets[:-1]).max().item()) if nchains > 0 else 1
+        map_cap = max(64, 32 * longest)
+    x = torch.empty(N, dtype=ulam.dtype, device=ulam.device)
+    nbytes = lib.tv_chain_nc_workspace(nchains, N, msg_cap, map_cap)
+    if nbytes == 0:
+        raise TvChainError(TV_ERR_INVALID_ARG, "tv_chain_nc_workspace")
+    ws = _workspace(nbytes, ulam.device)
+    st = lib.tv_chain_nc(_dtype_code(ulam), nchains, N, _ptr(chain_offsets), _ptr(unary_offsets),
+                         *(_ptr(t) for t in ts), _ptr(x), msg_cap, map_cap, _ptr(ws), nbytes,
+                         ctypes.c_void_p(_stream_ptr(ulam.device)))
+    _check(st, "tv_chain_nc")
     return x

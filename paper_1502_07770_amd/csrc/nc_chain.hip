@@ -1,0 +1,472 @@
+// nc_chain.hip -- Sec. 3 (non-convex case) on a batch of chains:
+//
+//     x = argmin_x  sum_i f_i(x_i) + sum_e min(w_e |x_{e+1} - x_e|, C_e),
+//
+// f_i continuous piecewise-linear (breakpoints lambda_{i,1..t}, slopes
+// s_{i,0..t}, bounded below), 0 < C_e <= +inf (+inf: plain TV).  One lane per
+// chain runs the message passing of Sec. 3 exactly:
+//   hat M_i = f_i + M_{i-1}                    Lemma 1 (breakpoint lists merged)
+//   M_i = ((hat M_i (x) f^1) (x) f^2) (x) f^3  Lemma 2 via Prop. 2:
+//     f^1 (w z on z >= 0): Algorithm 1, intervals Pi^1 mapping to their left end;
+//     f^2 (w |z| on z <= 0): Algorithm 1 on the reversed function (Sec. 3's
+//       reversal), scanned from the right, intervals Pi^2 mapping to their right end;
+//     f^3 (C off zero): min(h, min h + C), Pi^3 = {h >= min h + C} mapping to the
+//       first argmin breakpoint,
+// then backward x_i = pi^1(pi^2(pi^3(x_{i+1}))) from an argmin of the last hat M.
+// Messages are sequences (s_0, lambda_1, s_1, ..., lambda_t, s_t) in FP64, held
+// in LDS (as many lanes per workgroup as fit in 160 KiB) or, for large
+// msg_cap, in the chain's slice of the workspace; the interval lists are in
+// the workspace.  A message
+// longer than msg_cap, or more than map_cap intervals on a chain, stops that
+// chain and the call returns TV_ERR_WORKSPACE; an invalid unary (no
+// breakpoint, unsorted, unbounded below) returns TV_ERR_INVALID_ARG.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "tvchain.h"
+
+namespace tvc {
+namespace {
+
+constexpr int kNcFlagCapacity = 1;
+constexpr int kNcFlagInvalid = 2;
+
+// A message buffer: breakpoints l[0..t), slopes s[0..t] (s[k] left of l[k]).
+struct NcBuf {
+    double *l, *s;
+    int64_t t, cap;
+    __device__ __forceinline__ bool push(double lam, double right) {
+        if (t >= cap) return false;
+        l[t] = lam;
+        s[t + 1] = right;
+        ++t;
+        return true;
+    }
+};
+
+// Read access to a buffer as stored, or as its reversal phi^rev(z) = phi(-z).
+struct NcFwd {
+    const NcBuf *b;
+    __device__ __forceinline__ int64_t t() const { return b->t; }
+    __device__ __forceinline__ double l(int64_t k) const { return b->l[k]; }
+    __device__ __forceinline__ double s(int64_t k) const { return b->s[k]; }
+};
+struct NcRev {
+    const NcBuf *b;
+    __device__ __forceinline__ int64_t t() const { return b->t; }
+    __device__ __forceinline__ double l(int64_t k) const { return -b->l[b->t - 1 - k]; }
+    __device__ __forceinline__ double s(int64_t k) const { return -b->s[b->t - k]; }
+};
+
+// The interval lists of one chain.
+struct NcMaps {
+    double *a, *b, *to;
+    int64_t n, cap;
+    __device__ __forceinline__ bool add(double lo, double hi, double target) {
+        if (n >= cap) return false;
+        a[n] = lo;
+        b[n] = hi;
+        to[n] = target;
+        ++n;
+        return true;
+    }
+};
+
+// Lemma 1: out = unary + msg (equal positions merged into one breakpoint).
+__device__ bool nc_sum(const double *ul, const double *us, int64_t tu, const NcBuf &m, NcBuf &out) {
+    out.t = 0;
+    out.s[0] = us[0] + m.s[0];
+    int64_t i = 0, j = 0;
+    while (i < tu || j < m.t) {
+        double lam;
+        if (j >= m.t || (i < tu && ul[i] < m.l[j])) {
+            lam = ul[i++];
+        } else if (i >= tu || m.l[j] < ul[i]) {
+            lam = m.l[j++];
+        } else {
+            lam = ul[i];
+            ++i;
+            ++j;
+        }
+        if (!out.push(lam, us[i] + m.s[j])) return false;
+    }
+    return true;
+}
+
+// Algorithm 1 on h (forward or reversed view): out = h (x) f^1.  Each interval
+// [lambda_p, lambda] found is reported through add(lo, hi) in h's coordinates.
+template <class View, class Add>
+__device__ bool nc_dt(const View &h, double w, NcBuf &out, Add add) {
+    const int64_t t = h.t();
+    out.t = 0;
+    out.s[0] = h.s(0);
+    int64_t p = 0;
+    double vp = 0.0;  // h(l(p)), with h(l(0)) = 0
+    while (p < t) {
+        const double right = h.s(p + 1);
+        if (!out.push(h.l(p), right < w ? right : w)) return false;
+        if (right >= w) {
+            // first breakpoint from p + 2 on where h lies below the line of slope
+            // w through (l(p), vp); q = t stands for the unbounded right piece
+            const double lp = h.l(p);
+            int64_t q = p + 1;
+            double vq = vp + h.s(p + 1) * (h.l(p + 1 < t ? p + 1 : p) - lp);  // h(l(p + 1))
+            double vq1 = vq;                                                 // h(l(q - 1)) below
+            bool found = false;
+            for (q = p + 2; q < t; ++q) {
+                vq1 = vq;
+                vq = vq1 + h.s(q) * (h.l(q) - h.l(q - 1));
+                if (vq < vp + w * (h.l(q) - lp)) {
+                    found = true;
+                    break;
+                }
+            }
+            if (!found) {
+                q = t;
+                vq1 = vq;  // h(l(t - 1))
+                if (p + 1 >= t) vq1 = vp;
+                if (!(h.s(t) < w)) {  // h never falls below the line
+                    if (!add(lp, HUGE_VAL)) return false;
+                    return true;
+                }
+            }
+            const double l0 = h.l(q - 1);
+            double lam = l0 + (vp + w * (l0 - lp) - vq1) / (h.s(q) - w);
+            if (lam < l0) lam = l0;
+            if (q < t && lam > h.l(q)) lam = h.l(q);
+            if (!out.push(lam, h.s(q))) return false;
+            if (!add(lp, lam)) return false;
+            p = q;
+            vp = (q < t) ? vq : 0.0;
+        } else {
+            if (p + 1 < t) vp += h.s(p + 1) * (h.l(p + 1) - h.l(p));
+            ++p;
+        }
+    }
+    return true;
+}
+
+// min(h, min h + C) with Pi^3; h given through a view.
+template <class View>
+__device__ bool nc_trunc(const View &h, double C, NcBuf &out, NcMaps &mp) {
+    const int64_t t = h.t();
+    out.t = 0;
+    if (t == 0) {
+        out.s[0] = h.s(0);
+        return true;
+    }
+    double v = 0.0, vmin = 0.0;
+    int64_t pm = 0;
+    for (int64_t k = 1; k < t; ++k) {
+        v += h.s(k) * (h.l(k) - h.l(k - 1));
+        if (v < vmin) {
+            vmin = v;
+            pm = k;
+        }
+    }
+    const double cp = vmin + C, xm = h.l(pm);
+    // Segments between consecutive kink candidates (breakpoints and crossings
+    // of cp), each inside one piece of h; classified at their midpoints.
+    // Emission lags one segment: a point is written once the slope right of it
+    // is known.
+    bool first = true, in_run = false;
+    double prev = 0.0, run = 0.0, pend = 0.0;  // last point; run start; point awaiting its right slope
+    bool has_pend = false;
+    auto segment = [&](double lo, double hi, double slope, double vlo_at, double lo_ref) -> bool {
+        // segment (lo, hi) of a piece with h(z) = vlo_at + slope (z - lo_ref)
+        const double mid = (lo == -HUGE_VAL) ? hi - 1.0 : (hi == HUGE_VAL ? lo + 1.0 : 0.5 * (lo + hi));
+        const bool above = vlo_at + slope * (mid - lo_ref) >= cp;
+        const double sl = above ? 0.0 : slope;
+        if (first) {
+            out.s[0] = sl;
+            first = false;
+        } else if (has_pend) {
+            if (sl != out.s[out.t] && !out.push(pend, sl)) return false;
+            has_pend = false;
+        }
+        if (above && !in_run) {
+            run = lo;
+            in_run = true;
+        } else if (!above && in_run) {
+            if (!mp.add(run, lo, xm)) return false;
+            in_run = false;
+        }
+        return true;
+    };
+    auto point = [&](double z) {
+        pend = z;
+        has_pend = true;
+        prev = z;
+    };
+    v = 0.0;  // h(l(k - 1)) while walking piece k
+    prev = -HUGE_VAL;
+    for (int64_t k = 0; k <= t; ++k) {
+        const double sk = h.s(k);
+        // piece k: (l(k-1), l(k)) with h = vref + sk (z - lref)
+        double lref, vref, hi;
+        if (k == 0) {
+            lref = h.l(0);
+            vref = 0.0;
+            hi = h.l(0);
+        } else {
+            lref = h.l(k - 1);
+            vref = v;
+            hi = (k < t) ? h.l(k) : HUGE_VAL;
+        }
+        const double vhi = (k < t) ? ((k == 0) ? 0.0 : v + sk * (h.l(k) - h.l(k - 1))) : 0.0;
+        // a crossing of cp inside the piece
+        bool cross = false;
+        double zc = 0.0;
+        if (k == 0) {
+            cross = sk < 0.0 && 0.0 < cp;
+            if (cross) zc = h.l(0) + cp / sk;
+        } else if (k == t) {
+            cross = sk > 0.0 && v < cp;
+            if (cross) zc = h.l(t - 1) + (cp - v) / sk;
+        } else {
+            cross = (v < cp && vhi > cp) || (v > cp && vhi < cp);
+            if (cross) zc = h.l(k - 1) + (cp - v) / sk;
+        }
+        if (cross) {
+            if (!segment(prev, zc, sk, vref, lref)) return false;
+            point(zc);
+        }
+        if (!segment(prev, hi, sk, vref, lref)) return false;
+        if (k < t) {
+            point(h.l(k));
+            v = vhi;
+        }
+    }
+    if (in_run && !mp.add(run, HUGE_VAL, xm)) return false;
+    return true;
+}
+
+// pi(y) over intervals [lo, hi) of a list: the first interval containing y.
+__device__ __forceinline__ double nc_apply(const NcMaps &mp, int64_t lo, int64_t hi, double y) {
+    for (int64_t k = lo; k < hi; ++k)
+        if (y >= mp.a[k] && y <= mp.b[k]) return mp.to[k];
+    return y;
+}
+
+struct NcArgs {
+    int64_t num_chains;
+    const int64_t *coff, *uoff;
+    int64_t msg_cap, map_cap;
+    double *bufs;     // per chain: 3 buffers of (msg_cap + msg_cap + 1) doubles
+    double *maps;     // per chain: 3 arrays of map_cap doubles
+    int64_t *eoff;    // per node: 3 offsets (Pi^1, Pi^2, Pi^3 of the edge leaving it)
+    int *flag;
+};
+
+// The three message buffers of a lane live in LDS when `lanes` lanes' worth
+// fit in one workgroup (kLds; the rest of the wave idles), else in HBM.
+template <typename T, bool kLds>
+__global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__ ulam, const T *__restrict__ uslope,
+                                                 const T *__restrict__ w, const T *__restrict__ C, T *__restrict__ x,
+                                                 int lanes) {
+    extern __shared__ double s_nc[];
+    if ((int)threadIdx.x >= lanes) return;
+    const int64_t c = (int64_t)blockIdx.x * lanes + threadIdx.x;
+    if (c >= A.num_chains) return;
+    const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
+    if (n1 <= n0) return;
+    const int64_t bstride = 2 * A.msg_cap + 1;
+    double *base = kLds ? s_nc + (int64_t)threadIdx.x * 3 * bstride : A.bufs + c * 3 * bstride;
+    NcBuf M{base, base + A.msg_cap, 0, A.msg_cap};
+    NcBuf H{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap};
+    NcBuf B{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};
+    double *mb = A.maps + c * 3 * A.map_cap;
+    NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    M.t = 0;
+    M.s[0] = 0.0;
+    // unary slopes are read in FP64; a small staging copy of one unary
+    bool ok = true;
+    int bad = 0;
+    for (int64_t i = n0; i < n1 && ok; ++i) {
+        const int64_t u0 = A.uoff[i], tu = A.uoff[i + 1] - u0;
+        if (tu < 1 || tu > A.msg_cap) {
+            bad = tu < 1 ? kNcFlagInvalid : kNcFlagCapacity;
+            break;
+        }
+        // hat M = f_i + M into H (the unary is staged in B, which is free here)
+        for (int64_t k = 0; k < tu; ++k) {
+            B.l[k] = (double)ulam[u0 + k];
+            if (k > 0 && !(B.l[k] >= B.l[k - 1])) bad = kNcFlagInvalid;
+        }
+        for (int64_t k = 0; k <= tu; ++k) B.s[k] = (double)uslope[u0 + i + k];
+        if (!(B.s[0] <= 0.0) || !(B.s[tu] >= 0.0)) bad = kNcFlagInvalid;
+        if (bad) break;
+        if (!nc_sum(B.l, B.s, tu, M, H)) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (i == n1 - 1) break;
+        const double wi = (double)w[i];
+        const double ci = C ? (double)C[i] : HUGE_VAL;
+        if (!(wi >= 0.0) || !(ci > 0.0)) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        int64_t *eo = A.eoff + 3 * i;
+        // f^1: H -> B
+        eo[0] = mp.n;
+        if (!nc_dt(NcFwd{&H}, wi, B, [&](double lo, double hi) { return mp.add(lo, hi, lo); })) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        // f^2: reversed scan of B -> H (H holds the result reversed)
+        eo[1] = mp.n;
+        if (!nc_dt(NcRev{&B}, wi, H, [&](double lo, double hi) { return mp.add(-hi, -lo, -lo); })) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        // f^3 on rev(H) -> M, or M = rev(H)
+        eo[2] = mp.n;
+        if (ci < HUGE_VAL) {
+            if (!nc_trunc(NcRev{&H}, ci, M, mp)) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+        } else {
+            const NcRev r{&H};
+            M.t = r.t();
+            for (int64_t k = 0; k < M.t; ++k) M.l[k] = r.l(k);
+            for (int64_t k = 0; k <= M.t; ++k) M.s[k] = r.s(k);
+        }
+    }
+    if (bad) {
+        atomicOr(A.flag, bad);
+        return;
+    }
+    // the last node: the first breakpoint attaining the minimum of hat M (in H)
+    double v = 0.0, vmin = 0.0, y = H.t > 0 ? H.l[0] : 0.0;
+    for (int64_t k = 1; k < H.t; ++k) {
+        v += H.s[k] * (H.l[k] - H.l[k - 1]);
+        if (v < vmin) {
+            vmin = v;
+            y = H.l[k];
+        }
+    }
+    x[n1 - 1] = (T)y;
+    for (int64_t i = n1 - 2; i >= n0; --i) {
+        const int64_t *eo = A.eoff + 3 * i;
+        const int64_t e3 = (i + 1 < n1 - 1) ? A.eoff[3 * (i + 1)] : mp.n;
+        y = nc_apply(mp, eo[2], e3, y);
+        y = nc_apply(mp, eo[1], eo[2], y);
+        y = nc_apply(mp, eo[0], eo[1], y);
+        x[i] = (T)y;
+    }
+}
+
+// Lanes per workgroup whose message buffers fit the LDS of one workgroup
+// (160 KiB on gfx950); 0 if not even one lane's do.
+constexpr size_t kNcLds = 160 * 1024;
+int nc_lds_lanes(int64_t msg_cap) {
+    const size_t per = sizeof(double) * 3 * (size_t)(2 * msg_cap + 1);
+    const size_t k = kNcLds / per;
+    return (int)(k > 64 ? 64 : k);
+}
+
+size_t nc_layout(int64_t num_chains, int64_t num_nodes, int64_t msg_cap, int64_t map_cap, void *p, NcArgs *A) {
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_b = off;
+    // HBM message buffers only where they do not fit in LDS
+    if (nc_lds_lanes(msg_cap) == 0) off += al(sizeof(double) * (size_t)(num_chains * 3 * (2 * msg_cap + 1)));
+    const size_t o_m = off;
+    off += al(sizeof(double) * (size_t)(num_chains * 3 * map_cap));
+    const size_t o_e = off;
+    off += al(sizeof(int64_t) * (size_t)(3 * num_nodes));
+    const size_t o_f = off;
+    off += al(sizeof(int));
+    if (p && A) {
+        char *c = (char *)p;
+        A->bufs = (double *)(c + o_b);
+        A->maps = (double *)(c + o_m);
+        A->eoff = (int64_t *)(c + o_e);
+        A->flag = (int *)(c + o_f);
+    }
+    return off;
+}
+
+}  // namespace
+}  // namespace tvc
+
+using namespace tvc;
+
+extern "C" {
+
+size_t tv_chain_nc_workspace(int64_t num_chains, int64_t num_nodes, int64_t msg_cap, int64_t map_cap) {
+    if (num_chains < 0 || num_nodes < 0 || msg_cap < 1 || map_cap < 1) return 0;
+    if (msg_cap > (int64_t(1) << 24) || map_cap > (int64_t(1) << 30)) return 0;
+    return nc_layout(num_chains, num_nodes, msg_cap, map_cap, nullptr, nullptr);
+}
+
+tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, const int64_t *chain_offsets,
+                      const int64_t *unary_offsets, const void *ulam, const void *uslope, const void *w,
+                      const void *C, void *x, int64_t msg_cap, int64_t map_cap, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream) {
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (num_chains < 0 || num_nodes < 0) return TV_ERR_INVALID_ARG;
+    if (num_chains == 0) return TV_OK;
+    if (!chain_offsets || !unary_offsets || !ulam || !uslope || !w || !x) return TV_ERR_INVALID_ARG;
+    const size_t need = tv_chain_nc_workspace(num_chains, num_nodes, msg_cap, map_cap);
+    if (need == 0) return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
+    NcArgs A;
+    A.num_chains = num_chains;
+    A.coff = chain_offsets;
+    A.uoff = unary_offsets;
+    A.msg_cap = msg_cap;
+    A.map_cap = map_cap;
+    nc_layout(num_chains, num_nodes, msg_cap, map_cap, workspace, &A);
+    if (hipMemsetAsync(A.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
+    int ll = nc_lds_lanes(msg_cap);
+    if (ll > 0) {  // allow the kernel more than the default 64 KiB of dynamic LDS
+        const int bytes = (int)(sizeof(double) * 3 * (size_t)(2 * msg_cap + 1) * (size_t)ll);
+        const hipError_t e = (dtype == TV_F32)
+                                 ? hipFuncSetAttribute((const void *)k_nc_chain<float, true>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes)
+                                 : hipFuncSetAttribute((const void *)k_nc_chain<double, true>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ll = 0;
+        }
+    }
+    if (ll == 0 && nc_lds_lanes(msg_cap) > 0) return TV_ERR_HIP;  // the workspace holds no HBM buffers
+    // Spread the chains over the 1024 SIMDs before packing them into waves: a
+    // lane's work is a serial, branchy walk, so lanes sharing a wave mostly wait
+    // for each other.
+    const int64_t spread = (num_chains + 1023) / 1024;
+    int lanes = ll > 0 ? ll : 64;
+    if (spread < lanes) lanes = (int)(spread < 1 ? 1 : spread);
+    const dim3 grid((unsigned)((num_chains + lanes - 1) / lanes));
+    const size_t lds = ll > 0 ? sizeof(double) * 3 * (size_t)(2 * msg_cap + 1) * (size_t)lanes : 0;
+    if (dtype == TV_F32) {
+        if (ll > 0)
+            hipLaunchKernelGGL((k_nc_chain<float, true>), grid, dim3(64), lds, stream, A, (const float *)ulam,
+                               (const float *)uslope, (const float *)w, (const float *)C, (float *)x, lanes);
+        else
+            hipLaunchKernelGGL((k_nc_chain<float, false>), grid, dim3(64), 0, stream, A, (const float *)ulam,
+                               (const float *)uslope, (const float *)w, (const float *)C, (float *)x, lanes);
+    } else {
+        if (ll > 0)
+            hipLaunchKernelGGL((k_nc_chain<double, true>), grid, dim3(64), lds, stream, A, (const double *)ulam,
+                               (const double *)uslope, (const double *)w, (const double *)C, (double *)x, lanes);
+        else
+            hipLaunchKernelGGL((k_nc_chain<double, false>), grid, dim3(64), 0, stream, A, (const double *)ulam,
+                               (const double *)uslope, (const double *)w, (const double *)C, (double *)x, lanes);
+    }
+    if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, A.flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return TV_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return TV_ERR_HIP;
+    if (flag & kNcFlagInvalid) return TV_ERR_INVALID_ARG;
+    if (flag & kNcFlagCapacity) return TV_ERR_WORKSPACE;
+    return TV_OK;
+}
+
+}  // extern "C"

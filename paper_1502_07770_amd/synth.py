@@ -166,3 +166,29 @@ def post_order_forest(num_trees: int, n: int, seed: int = 0):
     glob = np.where(parent >= 0, parent + base, -1).reshape(-1)
     offsets = np.arange(T + 1, dtype=np.int64) * n
     return glob, offsets
+
+
+def cost_volume_chains(H: int, W: int, D: int, seed: int = 0, outliers: float = 0.1, steep: float = 10.0):
+    """Rows of a synthetic stereo-like cost volume as non-convex chains: a
+    piecewise-smooth true disparity map (the shapes image scaled to [0, D-1]),
+    per pixel the matching cost min(|d - d_true|, 4) at the integer levels
+    d = 0..D-1 plus N(0, 0.1) noise (uniform [0, 4] costs on an `outliers`
+    fraction of pixels), joined linearly between levels, with slopes -steep /
+    +steep outside [0, D-1].  Returns chain_offsets (H + 1), unary_offsets
+    (H W + 1), ulam (H W D), uslope (H W (D + 1)) and the true disparities."""
+    g = generator(seed)
+    dt = shapes_image(H, W, sigma=0.0, seed=seed)
+    dt = (dt - dt.min()) / max(dt.max() - dt.min(), 1e-9) * (D - 1)
+    lev = np.arange(D, dtype=np.float64)
+    cost = np.minimum(np.abs(lev[None, None, :] - dt[:, :, None]), 4.0) + g.normal(0, 0.1, (H, W, D))
+    bad = g.random((H, W)) < outliers
+    cost[bad] = g.uniform(0, 4, (int(bad.sum()), D))
+    n = H * W
+    slopes = np.empty((n, D + 1))
+    slopes[:, 0] = -steep
+    slopes[:, D] = steep
+    slopes[:, 1:D] = np.diff(cost.reshape(n, D), axis=1)
+    chain_offsets = (np.arange(H + 1, dtype=np.int64) * W)
+    unary_offsets = (np.arange(n + 1, dtype=np.int64) * D)
+    ulam = np.tile(lev, n)
+    return chain_offsets, unary_offsets, ulam, slopes.reshape(-1), dt

@@ -214,3 +214,18 @@ def test_workspace_covers_every_autotune_candidate(lib):
         assert binding.segment_length(4096, 4096) == 4096
     finally:
         binding.set_tuning(**saved)
+
+
+def test_nc_chain_argument_errors(lib):
+    assert lib.tv_chain_nc_workspace(4, 100, 64, 256) > 0
+    assert lib.tv_chain_nc_workspace(-1, 100, 64, 256) == 0
+    assert lib.tv_chain_nc_workspace(4, 100, 0, 256) == 0
+    assert lib.tv_chain_nc_workspace(4, 100, 64, 0) == 0
+    # zero chains: nothing to do, no device call
+    assert lib.tv_chain_nc(binding.TV_F32, 0, 0, None, None, None, None, None, None, None, 8, 8, None, 0,
+                           None) == binding.TV_OK
+    # null arrays and a bad dtype are rejected on the host
+    assert lib.tv_chain_nc(binding.TV_F32, 1, 4, None, None, None, None, None, None, None, 8, 8, None, 0,
+                           None) == binding.TV_ERR_INVALID_ARG
+    assert lib.tv_chain_nc(7, 1, 4, None, None, None, None, None, None, None, 8, 8, None, 0,
+                           None) == binding.TV_ERR_INVALID_ARG
