@@ -398,3 +398,104 @@ def nc_brute(uoff, ulam, uslope, w, C):
     if rc != 0:
         raise ValueError("orc_nc_brute: invalid input (%d)" % rc)
     return float(e.value), x
+
+
+def grid_unaries(cost, d0: float, dd: float, steep: float):
+    """Piecewise-linear unaries through the costs of a cost volume cost[..., D]
+    at the levels d0 + k dd (k = 0..D-1), slopes -steep / +steep outside.
+    Returns (uoff, ulam, uslope) in the layout of nc_chain, pixels in C order."""
+    cost = np.asarray(cost, dtype=np.float64)
+    D = cost.shape[-1]
+    c2 = cost.reshape(-1, D)
+    n = c2.shape[0]
+    lev = d0 + dd * np.arange(D)
+    sl = np.empty((n, D + 1))
+    sl[:, 0] = -steep
+    sl[:, D] = steep
+    sl[:, 1:D] = np.diff(c2, axis=1) / dd
+    return (np.arange(n + 1, dtype=np.int64) * D), np.tile(lev, n), sl.reshape(-1)
+
+
+def nc2d_pd(cost, d0: float, dd: float, steep: float, w_h, w_v, C: float, tau0: float, iters: int):
+    """Sec. 5.3: TV^C_h + TV^C_v + sum f_i on an H x W grid (f_i piecewise-linear
+    through cost[i, j, :] at d0 + k dd), by the Lagrangian splitting
+    min_{x_h, x_v} max_y Psi_h(x_h) + Psi_v(x_v) + <x_h - x_v, y>,
+    Psi = TV^C + f / 2, with the primal-dual iteration
+      x_h <- prox_{tau Psi_h}(x_h - tau ybar),  x_v <- prox_{tau Psi_v}(x_v + tau ybar),
+      y <- y + sigma (x_h - x_v),  ybar <- 2 y_new - y_old,
+    tau_k = tau0 / k, sigma_k = 1 / (2 tau_k) (L^2 = 2), theta = 1.  Each prox
+    is the exact minimiser, over every row (or column) chain, of Psi plus the
+    piecewise-linear interpolant on the levels of |x - z|^2 / (2 tau) (Sec. 5.3),
+    solved by nc_chain.  w_h: H x (W-1) horizontal edge weights, w_v: (H-1) x W.
+    Starts from x_h = x_v = the per-pixel minimiser of f, y = 0.  Returns
+    (x_h, x_v, energies of x_h after each iteration)."""
+    cost = np.asarray(cost, dtype=np.float64)
+    H, W, D = cost.shape
+    lev = d0 + dd * np.arange(D)
+    uoff, ulam, usl = grid_unaries(cost, d0, dd, steep)
+    usl = usl.reshape(H, W, D + 1)
+    x0 = lev[np.argmin(cost, axis=2)]
+    xh, xv = x0.copy(), x0.copy()
+    y = np.zeros((H, W))
+    ybar = y.copy()
+    w_h = np.broadcast_to(np.asarray(w_h, dtype=np.float64), (H, W - 1))
+    w_v = np.broadcast_to(np.asarray(w_v, dtype=np.float64), (H - 1, W))
+
+    def prox(z, tau, horizontal):
+        # unary of pixel i: f_i / 2 + PL interpolant of (x - z_i)^2 / (2 tau) on the levels
+        q = (lev[None, None, :-1] + lev[None, None, 1:] - 2 * z[:, :, None]) / (2 * tau)  # quad slopes between levels
+        sl = 0.5 * usl.copy()
+        sl[:, :, 1:D] += q
+        sl[:, :, 0] += (lev[0] - z) / tau        # the quadratic's slope at the ends, added to the steep sides
+        sl[:, :, D] += (lev[-1] - z) / tau
+        sl[:, :, 0] = np.minimum(sl[:, :, 0], 0.0)
+        sl[:, :, D] = np.maximum(sl[:, :, D], 0.0)
+        out = np.empty((H, W))
+        if horizontal:
+            for r in range(H):
+                o = np.arange(W + 1, dtype=np.int64) * D
+                out[r], _ = nc_chain(o, np.tile(lev, W), sl[r].reshape(-1), w_h[r], np.full(W - 1, C))
+        else:
+            for c in range(W):
+                o = np.arange(H + 1, dtype=np.int64) * D
+                out[:, c], _ = nc_chain(o, np.tile(lev, H), sl[:, c].reshape(-1), w_v[:, c], np.full(H - 1, C))
+        return out
+
+    energies = []
+    for k in range(1, iters + 1):
+        tau = tau0 / k
+        sigma = 1.0 / (2.0 * tau)
+        xh = prox(xh - tau * ybar, tau, True)
+        xv = prox(xv + tau * ybar, tau, False)
+        y_new = y + sigma * (xh - xv)
+        ybar = 2 * y_new - y
+        y = y_new
+        energies.append(nc2d_energy(cost, d0, dd, steep, w_h, w_v, C, xh))
+    return xh, xv, np.array(energies)
+
+
+def nc2d_energy(cost, d0: float, dd: float, steep: float, w_h, w_v, C: float, x) -> float:
+    """TV^C_h + TV^C_v + sum f_i at x (f_i through the costs, as in nc2d_pd; the
+    absolute cost values are used, not nc_chain's f(first level) = 0)."""
+    cost = np.asarray(cost, dtype=np.float64)
+    H, W, D = cost.shape
+    lev = d0 + dd * np.arange(D)
+    x = np.asarray(x, dtype=np.float64)
+    e = 0.0
+    for i in range(H):
+        for j in range(W):
+            z = x[i, j]
+            c = cost[i, j]
+            if z <= lev[0]:
+                e += c[0] - steep * (z - lev[0])
+            elif z >= lev[-1]:
+                e += c[-1] + steep * (z - lev[-1])
+            else:
+                k = min(int((z - d0) // dd), D - 2)
+                t = (z - lev[k]) / dd
+                e += c[k] * (1 - t) + c[k + 1] * t
+    w_h = np.broadcast_to(np.asarray(w_h, dtype=np.float64), (H, W - 1))
+    w_v = np.broadcast_to(np.asarray(w_v, dtype=np.float64), (H - 1, W))
+    e += np.minimum(w_h * np.abs(np.diff(x, axis=1)), C).sum()
+    e += np.minimum(w_v * np.abs(np.diff(x, axis=0)), C).sum()
+    return float(e)
