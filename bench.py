@@ -22,7 +22,8 @@ Also on the same JSON line:
                   TV-l1 chain prox of 65,536 salt & pepper chains, 100 iterations
                   of 2D TV-l1 at 4096^2, 65,536 trees of 256 nodes, the 1000 rows
                   of a 64-level synthetic cost volume as non-convex chains
-                  (truncated TV), and a batch of 256 uneven images.
+                  (truncated TV), 5 iterations of the non-convex 2D solver on
+                  that volume, and a batch of 256 uneven images.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras | --extras LIST]
        python bench.py --rocprof-summary DIR   (print a summary of rocprofv3 output)
@@ -353,6 +354,37 @@ def bench_nc(steps: int):
             "hbm_frac": round(N * 524 / (ms * 1e-3) / 8e12, 5), "mean_abs_x_minus_true_disparity": round(err, 3)}
 
 
+def bench_nc2d(iters: int):
+    """Sec. 5.3 non-convex 2D (tv2d_nc_solve) on a 1000 x 1482 synthetic cost
+    volume with 64 levels (the stereo pair's size), truncated TV w = 0.6, C = 2,
+    tau0 = 100: `iters` primal-dual iterations (each one row and one column
+    non-convex chain solve), FP32 costs.  Reports the time per iteration and the
+    energy before and after."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1502_07770_amd import binding, synth
+    H, W, D = 1000, 1482, 64
+    cost, dt = synth.cost_volume(H, W, D, seed=1)
+    ct = torch.tensor(cost, dtype=torch.float32, device="cuda")
+    run = lambda k: binding.tv2d_nc(ct, 0.0, 1.0, 10.0, 0.6, 0.6, 2.0, 100.0, k)  # noqa: E731
+    run(1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x = run(iters)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3
+    x = x.double().cpu().numpy()
+    x0 = np.argmin(cost, axis=2).astype(np.float64)
+    e0 = oracle.nc2d_energy(cost[:64], 0.0, 1.0, 10.0, 0.6, 0.6, 2.0, x0[:64])
+    e1 = oracle.nc2d_energy(cost[:64], 0.0, 1.0, 10.0, 0.6, 0.6, 2.0, x[:64])
+    return {"workload": "1000 x 1482 x 64 synthetic cost volume, truncated TV w 0.6, C 2, tau0 100, FP32 costs",
+            "iters": iters, "ms": round(ms, 1), "ms_per_iter": round(ms / iters, 1),
+            "energy_first_64_rows_init": round(e0, 3), "energy_first_64_rows_after": round(e1, 3),
+            "mean_abs_x_minus_true_disparity": round(float(np.abs(x - dt).mean()), 3),
+            "mean_abs_init_minus_true_disparity": round(float(np.abs(x0 - dt).mean()), 3)}
+
+
 def bench_tree(steps: int):
     """Algorithm 2 on 65,536 random post-order trees of 256 nodes (tv_tree_dp)
     with a ~ U[0.3, 2], TV-l1 data terms on 70% of the nodes, asymmetric edge
@@ -510,7 +542,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
                     help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,nc,"
-                         "batched")
+                         "nc2d,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -595,6 +627,7 @@ def main():
                 ("tv2d_l1", "2D TV-l1 4096x4096", bench_tv2d_l1),
                 ("tree", "trees 65536x256", lambda: bench_tree(5)),
                 ("nc", "non-convex chains 1000x1482, 64 levels", lambda: bench_nc(3)),
+                ("nc2d", "non-convex 2D 1000x1482, 64 levels", lambda: bench_nc2d(5)),
                 ("batched", "batched 256 images", bench_batched)]
         pick = None if args.extras == "all" else set(args.extras.split(","))
         try:

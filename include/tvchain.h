@@ -267,6 +267,28 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
                       const void *C, void *x, int64_t msg_cap, int64_t map_cap, void *workspace,
                       size_t workspace_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Non-convex 2D, Sec. 5.3: on an H x W grid minimise
+ *     sum_horizontal min(w_h |x_i - x_j|, C) + sum_vertical min(w_v |x_i - x_j|, C)
+ *       + sum_i f_i(x_i),
+ * f_i piecewise-linear through cost[i][k] at the levels d0 + k dd (k < D) with
+ * slopes -steep / +steep outside, by the Lagrangian splitting into row and
+ * column problems and the primal-dual iteration of Sec. 5.3 (tau_k = tau0 / k,
+ * sigma_k = 1 / (2 tau_k), theta = 1), each prox an exact tv_chain_nc solve of
+ * the rows (columns) with the piecewise-linear interpolant of the quadratic
+ * proximity term on the levels.  Starts from each pixel's minimiser of f, y = 0.
+ *  cost : DEVICE [H][W][D] (dtype), D >= 2.
+ *  w_h  : DEVICE [H][W-1] or NULL (w_h_scalar >= 0); w_v: [H-1][W] or NULL.
+ *  C    : truncation (> 0; +inf: plain TV).  iters >= 0 iterations.
+ *  x    : DEVICE [H][W] output (x_h after the last iteration).
+ *  msg_cap (>= D), map_cap: as for tv_chain_nc (per row or column chain).
+ * Synchronous.  Errors as tv_chain_nc; TV_ERR_INVALID_ARG for bad sizes. */
+size_t tv2d_nc_workspace(int64_t H, int64_t W, int64_t D, int64_t msg_cap, int64_t map_cap);
+tv_status tv2d_nc_solve(tv_dtype dtype, const void *cost, int64_t H, int64_t W, int64_t D, double d0, double dd,
+                        double steep, const void *w_h, double w_h_scalar, const void *w_v, double w_v_scalar,
+                        double C, double tau0, int iters, void *x, int64_t msg_cap, int64_t map_cap,
+                        void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Bytes of device workspace tv_chain_prox_backward needs (may be 0). */
 size_t tv_chain_prox_backward_workspace(const tv_chain_layout *layout, tv_dtype dtype);
 

@@ -106,6 +106,10 @@ _SIG = {
     "tv_chain_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64]),
     "tv_chain_nc": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _I64, _I64, _P,
                                    ctypes.c_size_t, _P]),
+    "tv2d_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64, _I64]),
+    "tv2d_nc_solve": (ctypes.c_int, [ctypes.c_int, _P, _I64, _I64, _I64, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, _P, ctypes.c_double, _P, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int, _P, _I64, _I64, _P, ctypes.c_size_t, _P]),
     "tv_tree_dp_workspace": (ctypes.c_size_t, [_I64, _I64]),
     "tv_tree_dp": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
                                   _P]),
@@ -722,4 +726,37 @@ def chain_nc(chain_offsets: torch.Tensor, unary_offsets: torch.Tensor, ulam: tor
                          *(_ptr(t) for t in ts), _ptr(x), msg_cap, map_cap, _ptr(ws), nbytes,
                          ctypes.c_void_p(_stream_ptr(ulam.device)))
     _check(st, "tv_chain_nc")
+    return x
+
+
+def tv2d_nc(cost: torch.Tensor, d0: float, dd: float, steep: float, w_h, w_v, C: float, tau0: float, iters: int,
+            msg_cap: Optional[int] = None, map_cap: Optional[int] = None) -> torch.Tensor:
+    """Sec. 5.3 non-convex 2D (tv2d_nc_solve): cost is an H x W x D tensor of
+    unary costs at the levels d0 + k dd; w_h (H x (W-1)) and w_v ((H-1) x W)
+    are tensors or floats; C the truncation (inf: plain TV).  Returns x (H x W)."""
+    _require_gpu(cost)
+    lib = load()
+    if cost.dim() != 3:
+        raise TvChainError(TV_ERR_INVALID_ARG, "cost must be H x W x D")
+    H, W, D = cost.shape
+    cost = cost.contiguous()
+    wh = w_h.contiguous() if isinstance(w_h, torch.Tensor) else None
+    wv = w_v.contiguous() if isinstance(w_v, torch.Tensor) else None
+    for t in (wh, wv):
+        if t is not None and t.dtype != cost.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "weights must match the cost dtype")
+    if msg_cap is None:
+        msg_cap = max(256, 4 * D)
+    if map_cap is None:
+        map_cap = 32 * max(H, W)
+    x = torch.empty((H, W), dtype=cost.dtype, device=cost.device)
+    nbytes = lib.tv2d_nc_workspace(H, W, D, msg_cap, map_cap)
+    if nbytes == 0:
+        raise TvChainError(TV_ERR_INVALID_ARG, "tv2d_nc_workspace")
+    ws = _workspace(nbytes, cost.device)
+    st = lib.tv2d_nc_solve(_dtype_code(cost), _ptr(cost), H, W, D, float(d0), float(dd), float(steep), _ptr(wh),
+                           0.0 if wh is not None else float(w_h), _ptr(wv), 0.0 if wv is not None else float(w_v),
+                           float(C), float(tau0), int(iters), _ptr(x), msg_cap, map_cap, _ptr(ws), nbytes,
+                           ctypes.c_void_p(_stream_ptr(cost.device)))
+    _check(st, "tv2d_nc_solve")
     return x

@@ -168,14 +168,12 @@ def post_order_forest(num_trees: int, n: int, seed: int = 0):
     return glob, offsets
 
 
-def cost_volume_chains(H: int, W: int, D: int, seed: int = 0, outliers: float = 0.1, steep: float = 10.0):
-    """Rows of a synthetic stereo-like cost volume as non-convex chains: a
-    piecewise-smooth true disparity map (the shapes image scaled to [0, D-1]),
-    per pixel the matching cost min(|d - d_true|, 4) at the integer levels
-    d = 0..D-1 plus N(0, 0.1) noise (uniform [0, 4] costs on an `outliers`
-    fraction of pixels), joined linearly between levels, with slopes -steep /
-    +steep outside [0, D-1].  Returns chain_offsets (H + 1), unary_offsets
-    (H W + 1), ulam (H W D), uslope (H W (D + 1)) and the true disparities."""
+def cost_volume(H: int, W: int, D: int, seed: int = 0, outliers: float = 0.1):
+    """A synthetic stereo-like cost volume: a piecewise-smooth true disparity map
+    (the shapes image scaled to [0, D-1]) and per pixel the matching cost
+    min(|d - d_true|, 4) at the integer levels d = 0..D-1 plus N(0, 0.1) noise,
+    uniform [0, 4] costs on an `outliers` fraction of pixels.  Returns
+    (cost [H, W, D], true disparities [H, W])."""
     g = generator(seed)
     dt = shapes_image(H, W, sigma=0.0, seed=seed)
     dt = (dt - dt.min()) / max(dt.max() - dt.min(), 1e-9) * (D - 1)
@@ -183,6 +181,16 @@ def cost_volume_chains(H: int, W: int, D: int, seed: int = 0, outliers: float = 
     cost = np.minimum(np.abs(lev[None, None, :] - dt[:, :, None]), 4.0) + g.normal(0, 0.1, (H, W, D))
     bad = g.random((H, W)) < outliers
     cost[bad] = g.uniform(0, 4, (int(bad.sum()), D))
+    return cost, dt
+
+
+def cost_volume_chains(H: int, W: int, D: int, seed: int = 0, outliers: float = 0.1, steep: float = 10.0):
+    """Rows of the cost volume of cost_volume() as non-convex chains: the costs
+    joined linearly between the integer levels, slopes -steep / +steep outside
+    [0, D-1].  Returns chain_offsets (H + 1), unary_offsets (H W + 1), ulam
+    (H W D), uslope (H W (D + 1)) and the true disparities."""
+    cost, dt = cost_volume(H, W, D, seed=seed, outliers=outliers)
+    lev = np.arange(D, dtype=np.float64)
     n = H * W
     slopes = np.empty((n, D + 1))
     slopes[:, 0] = -steep

@@ -229,3 +229,15 @@ def test_nc_chain_argument_errors(lib):
                            None) == binding.TV_ERR_INVALID_ARG
     assert lib.tv_chain_nc(7, 1, 4, None, None, None, None, None, None, None, 8, 8, None, 0,
                            None) == binding.TV_ERR_INVALID_ARG
+
+
+def test_nc2d_argument_errors(lib):
+    assert lib.tv2d_nc_workspace(16, 20, 8, 64, 256) > 0
+    assert lib.tv2d_nc_workspace(0, 20, 8, 64, 256) == 0
+    assert lib.tv2d_nc_workspace(16, 20, 1, 64, 256) == 0   # D < 2
+    assert lib.tv2d_nc_workspace(16, 20, 8, 4, 256) == 0    # msg_cap < D
+    # null arrays, bad steps and bad dtype are rejected on the host
+    assert lib.tv2d_nc_solve(binding.TV_F32, None, 4, 4, 4, 0.0, 1.0, 10.0, None, 0.5, None, 0.5, 1.0, 10.0, 1,
+                             None, 64, 64, None, 0, None) == binding.TV_ERR_INVALID_ARG
+    assert lib.tv2d_nc_solve(7, None, 4, 4, 4, 0.0, 1.0, 10.0, None, 0.5, None, 0.5, 1.0, 10.0, 1,
+                             None, 64, 64, None, 0, None) == binding.TV_ERR_INVALID_ARG
