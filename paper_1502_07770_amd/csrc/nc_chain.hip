@@ -4,7 +4,8 @@
 //
 // f_i continuous piecewise-linear (breakpoints lambda_{i,1..t}, slopes
 // s_{i,0..t}, bounded below), 0 < C_e <= +inf (+inf: plain TV).  One lane per
-// chain runs the message passing of Sec. 3 exactly:
+// chain (or, for messages of at most 256 breakpoints, a wave per chain with
+// each pass spread over the lanes) runs the message passing of Sec. 3 exactly:
 //   hat M_i = f_i + M_{i-1}                    Lemma 1 (breakpoint lists merged)
 //   M_i = ((hat M_i (x) f^1) (x) f^2) (x) f^3  Lemma 2 via Prop. 2:
 //     f^1 (w z on z >= 0): Algorithm 1, intervals Pi^1 mapping to their left end;
@@ -360,6 +361,511 @@ __global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// A wave per chain.  The same message passing with each pass spread over the
+// 64 lanes (element k of a message on lane k mod 64, the message in LDS):
+//   Lemma 1: both sorted lists scattered by rank, equal positions merged, the
+//     slope right of each point read from the two lists' counts;
+//   f^1: h (x) f^1 (y) = w y + min_{x <= y} (h(x) - w x), so Algorithm 1 is a
+//     prefix minimum of g = h - w x over the breakpoints plus, per piece, the
+//     point where g comes back down to that minimum (the end of an interval of
+//     Pi^1, which starts at the minimum's breakpoint);
+//   f^2: the same on the reversed view; f^3: a wave minimum and per piece the
+//     crossing of min h + C;
+// each pass ends with a prefix count that places the points it emits.  The
+// backward pass is one lane's.  Used where msg_cap <= kWaveMsg.
+// ---------------------------------------------------------------------------
+constexpr int kWaveMsg = 256;
+
+__device__ __forceinline__ int wv_lane() { return (int)threadIdx.x; }
+
+__device__ __forceinline__ double wv_scan_add(double x) {
+    const int lane = wv_lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wv_scan_int(int x) {
+    const int lane = wv_lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Inclusive prefix minimum; ties keep the earlier index.
+__device__ __forceinline__ void wv_scan_min(double &v, int &i) {
+    const int lane = wv_lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double vo = __shfl_up(v, d, 64);
+        const int io = __shfl_up(i, d, 64);
+        if (lane >= d && (vo < v || (vo == v && io < i))) {
+            v = vo;
+            i = io;
+        }
+    }
+}
+
+// A message in LDS, read as stored or reversed (phi^rev(z) = phi(-z)).
+struct WView {
+    const double *L, *S;
+    int t;
+    bool rev;
+    __device__ __forceinline__ double l(int k) const { return rev ? -L[t - 1 - k] : L[k]; }
+    __device__ __forceinline__ double s(int k) const { return rev ? -S[t - k] : S[k]; }
+};
+
+// first index in a[0..n) with a[idx] >= v (strict = false: > v)
+__device__ __forceinline__ int wv_lower(const double *a, int n, double v, bool strict) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const bool go = strict ? (a[mid] <= v) : (a[mid] < v);
+        if (go) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Shared scratch of one wave.
+struct WScratch {
+    double *T;     // [2 kWaveMsg] merge staging
+    double *V;     // [kWaveMsg] values at breakpoints
+    double *PM;    // [kWaveMsg] prefix minimum
+    int *PA;       // [kWaveMsg] its index
+    double *PS, *PE;  // [kWaveMsg + 1] start / end slope of each piece
+    int *Q0, *Q1;     // [kWaveMsg + 1] start / end status of each piece
+};
+
+// V[k] = h(l(k)) - h(l(0)).
+__device__ void wv_values(const WView &h, double *V) {
+    double carry = 0.0;
+    for (int c = 0; c * 64 < h.t; ++c) {
+        const int k = c * 64 + wv_lane();
+        const double d = (k >= 1 && k < h.t) ? h.s(k) * (h.l(k) - h.l(k - 1)) : 0.0;
+        const double inc = wv_scan_add(d) + carry;
+        if (k < h.t) V[k] = inc;
+        carry = __shfl(inc, 63, 64);
+    }
+    __syncthreads();
+}
+
+// Lemma 1: out = unary + M.  Returns the number of breakpoints, or -1 if more
+// than cap.
+__device__ int wv_sum(const double *ul, const double *us, int tu, const double *ml, const double *ms, int tm,
+                      double *ol, double *os, int cap, const WScratch &W) {
+    for (int i = wv_lane(); i < tu; i += 64) W.T[i + wv_lower(ml, tm, ul[i], false)] = ul[i];
+    for (int j = wv_lane(); j < tm; j += 64) W.T[j + wv_lower(ul, tu, ml[j], true)] = ml[j];
+    __syncthreads();
+    const int tot = tu + tm;
+    int base = 0;
+    for (int c = 0; c * 64 < tot; ++c) {
+        const int k = c * 64 + wv_lane();
+        const bool keep = k < tot && (k == 0 || W.T[k] != W.T[k - 1]);
+        const int inc = wv_scan_int(keep ? 1 : 0);
+        const int pos = base + inc - 1;
+        if (keep && pos < cap) {
+            const double lam = W.T[k];
+            ol[pos] = lam;
+            os[pos + 1] = us[wv_lower(ul, tu, lam, true)] + ms[wv_lower(ml, tm, lam, true)];
+        }
+        base += __shfl(inc, 63, 64);
+    }
+    if (wv_lane() == 0) os[0] = us[0] + ms[0];
+    __syncthreads();
+    return base <= cap ? base : -1;
+}
+
+// h (x) f^1 (Algorithm 1 as a prefix minimum).  Intervals go to the chain's
+// list at *nmap (rev: reported in the original coordinates).  Returns the
+// number of breakpoints, -1 past cap, -2 past the interval capacity.
+__device__ int wv_dt(const WView &h, double w, double *ol, double *os, int cap, const NcMaps &mp, int64_t &nmap,
+                     const WScratch &W) {
+    const int t = h.t;
+    if (t == 0) {
+        if (wv_lane() == 0) os[0] = h.s(0);
+        __syncthreads();
+        return 0;
+    }
+    wv_values(h, W.V);
+    // prefix minimum of g_k = V_k - w l(k)
+    double cv = HUGE_VAL;
+    int ci = 0;
+    for (int c = 0; c * 64 < t; ++c) {
+        const int k = c * 64 + wv_lane();
+        double v = (k < t) ? W.V[k] - w * h.l(k) : HUGE_VAL;
+        int i = k;
+        wv_scan_min(v, i);
+        if (cv < v || (cv == v && ci < i)) {
+            v = cv;
+            i = ci;
+        }
+        if (k < t) {
+            W.PM[k] = v;
+            W.PA[k] = i;
+        }
+        cv = __shfl(v, 63, 64);
+        ci = __shfl(i, 63, 64);
+    }
+    __syncthreads();
+    // pieces k = 0..t: start / end slope of the result
+    for (int k = wv_lane(); k <= t; k += 64) {
+        double ps, pe;
+        if (k == 0) {
+            ps = pe = h.s(0);
+        } else {
+            const double sk = h.s(k), sig = sk - w;
+            const double gl = W.V[k - 1] - w * h.l(k - 1), m = W.PM[k - 1];
+            const bool on = gl <= m;
+            if (on) {
+                ps = pe = (sig < 0.0) ? sk : w;
+            } else {
+                const bool cross = (sig < 0.0) && (k == t || W.V[k] - w * h.l(k) <= m);
+                ps = w;
+                pe = cross ? sk : w;
+            }
+        }
+        W.PS[k] = ps;
+        W.PE[k] = pe;
+    }
+    __syncthreads();
+    // emit, unit k = 1..t: breakpoint l(k-1) if the slope changes there, then
+    // the crossing of piece k; close intervals at crossings (and an open end)
+    int base = 0, ibase = 0;
+    bool over = false;
+    for (int c = 0; c * 64 < t; ++c) {
+        const int k = 1 + c * 64 + wv_lane();
+        const bool in = k <= t;
+        bool e1 = false, e2 = false, close = false;
+        double y = 0.0, ilo = 0.0, ihi = 0.0;
+        if (in) {
+            e1 = W.PE[k - 1] != W.PS[k];
+            const double sk = h.s(k), sig = sk - w;
+            const double gl = W.V[k - 1] - w * h.l(k - 1), m = W.PM[k - 1];
+            const bool on = gl <= m;
+            const double la = h.l(W.PA[k - 1]);
+            if (!on && sig < 0.0 && (k == t || W.V[k] - w * h.l(k) <= m)) {
+                y = h.l(k - 1) + (m - gl) / sig;
+                if (y < h.l(k - 1)) y = h.l(k - 1);
+                if (k < t && y > h.l(k)) y = h.l(k);
+                e2 = true;
+                close = true;
+                ilo = la;
+                ihi = y;
+            } else if (k == t && sig >= 0.0) {  // flat to +inf
+                close = true;
+                ilo = on ? h.l(W.PA[k - 1]) : la;
+                ihi = HUGE_VAL;
+            }
+        }
+        const int cnt = (e1 ? 1 : 0) + (e2 ? 1 : 0);
+        const int inc = wv_scan_int(cnt);
+        int pos = base + inc - cnt;
+        if (e1) {
+            if (pos < cap) {
+                ol[pos] = h.l(k - 1);
+                os[pos + 1] = W.PS[k];
+            }
+            ++pos;
+        }
+        if (e2 && pos < cap) {
+            ol[pos] = y;
+            os[pos + 1] = W.PE[k];
+        }
+        base += __shfl(inc, 63, 64);
+        const int iinc = wv_scan_int(close ? 1 : 0);
+        const int64_t ipos = nmap + ibase + iinc - 1;
+        if (close) {
+            if (ipos < mp.cap) {
+                mp.a[ipos] = h.rev ? -ihi : ilo;
+                mp.b[ipos] = h.rev ? -ilo : ihi;
+                mp.to[ipos] = h.rev ? -ilo : ilo;
+            } else {
+                over = true;
+            }
+        }
+        ibase += __shfl(iinc, 63, 64);
+    }
+    if (wv_lane() == 0) os[0] = W.PS[0];
+    nmap += ibase;
+    const bool any_over = __ballot(over) != 0;
+    __syncthreads();
+    if (any_over) return -2;
+    return base <= cap ? base : -1;
+}
+
+// min(h, min h + C) with Pi^3 (h through a view).  Same returns as wv_dt.
+__device__ int wv_trunc(const WView &h, double C, double *ol, double *os, int cap, const NcMaps &mp,
+                        int64_t &nmap, const WScratch &W) {
+    const int t = h.t;
+    if (t == 0) {
+        if (wv_lane() == 0) os[0] = h.s(0);
+        __syncthreads();
+        return 0;
+    }
+    wv_values(h, W.V);
+    // minimum of V and its first index
+    double mv = HUGE_VAL;
+    int mi = 0;
+    for (int c = 0; c * 64 < t; ++c) {
+        const int k = c * 64 + wv_lane();
+        double v = (k < t) ? W.V[k] : HUGE_VAL;
+        int i = k;
+        wv_scan_min(v, i);
+        v = __shfl(v, 63, 64);
+        i = __shfl(i, 63, 64);
+        if (v < mv || (v == mv && i < mi)) {
+            mv = v;
+            mi = i;
+        }
+    }
+    const double cp = mv + C, xm = h.l(mi);
+    // per piece: crossing, and the status / slope of its first and last segment
+    // (status decided at each segment's midpoint)
+    auto hval = [&](int k, double z) { return (k == 0) ? W.V[0] + h.s(0) * (z - h.l(0)) : W.V[k - 1] + h.s(k) * (z - h.l(k - 1)); };
+    auto crossing = [&](int k, double &z) -> bool {
+        if (k == 0) {
+            if (h.s(0) < 0.0 && W.V[0] < cp) {
+                z = h.l(0) + (cp - W.V[0]) / h.s(0);
+                return true;
+            }
+            return false;
+        }
+        if (k == t) {
+            if (h.s(t) > 0.0 && W.V[t - 1] < cp) {
+                z = h.l(t - 1) + (cp - W.V[t - 1]) / h.s(t);
+                return true;
+            }
+            return false;
+        }
+        if ((W.V[k - 1] < cp && W.V[k] > cp) || (W.V[k - 1] > cp && W.V[k] < cp)) {
+            z = h.l(k - 1) + (cp - W.V[k - 1]) / h.s(k);
+            return true;
+        }
+        return false;
+    };
+    auto segstat = [&](int k, double lo, double hi) -> bool {
+        const double mid = (lo == -HUGE_VAL) ? hi - 1.0 : (hi == HUGE_VAL ? lo + 1.0 : 0.5 * (lo + hi));
+        return hval(k, mid) >= cp;
+    };
+    for (int k = wv_lane(); k <= t; k += 64) {
+        const double lo = (k == 0) ? -HUGE_VAL : h.l(k - 1), hi = (k == t) ? HUGE_VAL : h.l(k);
+        double z = 0.0;
+        const bool cr = crossing(k, z);
+        const bool s0 = segstat(k, lo, cr ? z : hi), s1 = cr ? segstat(k, z, hi) : s0;
+        W.Q0[k] = s0 ? 1 : 0;
+        W.Q1[k] = s1 ? 1 : 0;
+        W.PS[k] = s0 ? 0.0 : h.s(k);
+        W.PE[k] = s1 ? 0.0 : h.s(k);
+    }
+    __syncthreads();
+    // emit: unit u = 0..t: breakpoint l(u-1) (u >= 1), then piece u's crossing;
+    // status changes at those points start or end the runs of Pi^3
+    int base = 0, sb = 0, eb = 0;
+    bool over = false;
+    for (int c = 0; c * 64 <= t; ++c) {
+        const int u = c * 64 + wv_lane();
+        const bool in = u <= t;
+        bool e1 = false, e2 = false;
+        int st1 = 0, en1 = 0, st2 = 0, en2 = 0;  // run start / end at the breakpoint, at the crossing
+        double z = 0.0;
+        bool cr = false;
+        if (in) {
+            cr = crossing(u, z);
+            if (u >= 1) {
+                e1 = W.PE[u - 1] != W.PS[u];
+                st1 = (!W.Q1[u - 1] && W.Q0[u]) ? 1 : 0;
+                en1 = (W.Q1[u - 1] && !W.Q0[u]) ? 1 : 0;
+            } else {
+                st1 = W.Q0[0] ? 1 : 0;  // a run from -inf
+            }
+            if (cr) {
+                e2 = W.PS[u] != W.PE[u];
+                st2 = (!W.Q0[u] && W.Q1[u]) ? 1 : 0;
+                en2 = (W.Q0[u] && !W.Q1[u]) ? 1 : 0;
+            }
+        }
+        const int cnt = (e1 ? 1 : 0) + (e2 ? 1 : 0);
+        const int inc = wv_scan_int(cnt);
+        int pos = base + inc - cnt;
+        if (e1) {
+            if (pos < cap) {
+                ol[pos] = h.l(u - 1);
+                os[pos + 1] = W.PS[u];
+            }
+            ++pos;
+        }
+        if (e2 && pos < cap) {
+            ol[pos] = z;
+            os[pos + 1] = W.PE[u];
+        }
+        base += __shfl(inc, 63, 64);
+        // run starts and ends, in order; a run's interval is written at its
+        // end (start positions kept in the T scratch)
+        const double bpos = (u >= 1) ? h.l(u - 1) : -HUGE_VAL;
+        const int scount = st1 + st2, ecount = en1 + en2;
+        const int sinc = wv_scan_int(scount), einc = wv_scan_int(ecount);
+        int sp = sb + sinc - scount;
+        if (st1) {
+            if (sp < 2 * kWaveMsg) W.T[sp] = bpos;
+            ++sp;
+        }
+        if (st2 && sp < 2 * kWaveMsg) W.T[sp] = z;
+        sb += __shfl(sinc, 63, 64);
+        // ends are written after every start of this chunk is in T
+        __syncthreads();
+        int ep = eb + einc - ecount;
+        auto put_end = [&](double e) {
+            const int64_t ipos = nmap + ep;
+            if (ipos < mp.cap && ep < 2 * kWaveMsg) {
+                mp.a[ipos] = W.T[ep];
+                mp.b[ipos] = e;
+                mp.to[ipos] = xm;
+            } else {
+                over = true;
+            }
+            ++ep;
+        };
+        if (en1) put_end(bpos);
+        if (en2) put_end(z);
+        eb += __shfl(einc, 63, 64);
+        __syncthreads();
+    }
+    // a run still open at +inf
+    if (sb > eb) {
+        if (wv_lane() == 0) {
+            const int64_t ipos = nmap + eb;
+            if (ipos < mp.cap && eb < 2 * kWaveMsg) {
+                mp.a[ipos] = W.T[eb];
+                mp.b[ipos] = HUGE_VAL;
+                mp.to[ipos] = xm;
+            } else {
+                over = true;
+            }
+        }
+        ++eb;
+    }
+    if (wv_lane() == 0) os[0] = W.PS[0];
+    nmap += eb;
+    const bool any_over = __ballot(over) != 0;
+    __syncthreads();
+    if (any_over) return -2;
+    return base <= cap ? base : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ ulam, const T *__restrict__ uslope,
+                                                const T *__restrict__ w, const T *__restrict__ C,
+                                                T *__restrict__ x) {
+    __shared__ double sU_l[kWaveMsg], sU_s[kWaveMsg + 1];
+    __shared__ double sA_l[kWaveMsg], sA_s[kWaveMsg + 1];
+    __shared__ double sB_l[kWaveMsg], sB_s[kWaveMsg + 1];
+    __shared__ double sC_l[kWaveMsg], sC_s[kWaveMsg + 1];
+    __shared__ double sT[2 * kWaveMsg], sV[kWaveMsg], sPM[kWaveMsg], sPS[kWaveMsg + 1], sPE[kWaveMsg + 1];
+    __shared__ int sPA[kWaveMsg], sQ0[kWaveMsg + 1], sQ1[kWaveMsg + 1];
+    const WScratch W{sT, sV, sPM, sPA, sPS, sPE, sQ0, sQ1};
+    const int64_t c = blockIdx.x;
+    if (c >= A.num_chains) return;
+    const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
+    if (n1 <= n0) return;
+    const int lane = wv_lane();
+    const int cap = (int)(A.msg_cap < kWaveMsg ? A.msg_cap : kWaveMsg);
+    double *mb = A.maps + c * 3 * A.map_cap;
+    const NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    int64_t nmap = 0;
+    int tm = 0, th = 0, bad = 0;
+    if (lane == 0) sA_s[0] = 0.0;
+    __syncthreads();
+    for (int64_t i = n0; i < n1; ++i) {
+        const int64_t u0 = A.uoff[i], tu64 = A.uoff[i + 1] - u0;
+        if (tu64 < 1 || tu64 > cap) {
+            bad = tu64 < 1 ? kNcFlagInvalid : kNcFlagCapacity;
+            break;
+        }
+        const int tu = (int)tu64;
+        bool inval = false;
+        for (int k = lane; k < tu; k += 64) sU_l[k] = (double)ulam[u0 + k];
+        for (int k = lane; k <= tu; k += 64) sU_s[k] = (double)uslope[u0 + i + k];
+        __syncthreads();
+        for (int k = lane; k < tu; k += 64)
+            if (k > 0 && !(sU_l[k] >= sU_l[k - 1])) inval = true;
+        if (lane == 0 && (!(sU_s[0] <= 0.0) || !(sU_s[tu] >= 0.0))) inval = true;
+        if (__ballot(inval) != 0) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        th = wv_sum(sU_l, sU_s, tu, sA_l, sA_s, tm, sB_l, sB_s, cap, W);
+        if (th < 0) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (i == n1 - 1) break;
+        const double wi = (double)w[i];
+        const double ci = C ? (double)C[i] : HUGE_VAL;
+        if (!(wi >= 0.0) || !(ci > 0.0)) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        int64_t *eo = A.eoff + 3 * i;
+        if (lane == 0) eo[0] = nmap;
+        const int t1 = wv_dt(WView{sB_l, sB_s, th, false}, wi, sC_l, sC_s, cap, mp, nmap, W);
+        if (t1 < 0) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (lane == 0) eo[1] = nmap;
+        const int t2 = wv_dt(WView{sC_l, sC_s, t1, true}, wi, sB_l, sB_s, cap, mp, nmap, W);
+        if (t2 < 0) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (lane == 0) eo[2] = nmap;
+        const WView r{sB_l, sB_s, t2, true};
+        if (ci < HUGE_VAL) {
+            tm = wv_trunc(r, ci, sA_l, sA_s, cap, mp, nmap, W);
+            if (tm < 0) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+        } else {
+            for (int k = lane; k < t2; k += 64) sA_l[k] = r.l(k);
+            for (int k = lane; k <= t2; k += 64) sA_s[k] = r.s(k);
+            tm = t2;
+            __syncthreads();
+        }
+    }
+    if (bad) {
+        if (lane == 0) atomicOr(A.flag, bad);
+        return;
+    }
+    if (lane != 0) return;
+    // backward, one lane: the first minimum of the last hat M (in B), then pi
+    double v = 0.0, vmin = 0.0, y = th > 0 ? sB_l[0] : 0.0;
+    for (int k = 1; k < th; ++k) {
+        v += sB_s[k] * (sB_l[k] - sB_l[k - 1]);
+        if (v < vmin) {
+            vmin = v;
+            y = sB_l[k];
+        }
+    }
+    x[n1 - 1] = (T)y;
+    for (int64_t i = n1 - 2; i >= n0; --i) {
+        const int64_t *eo = A.eoff + 3 * i;
+        const int64_t e3 = (i + 1 < n1 - 1) ? A.eoff[3 * (i + 1)] : nmap;
+        y = nc_apply(mp, eo[2], e3, y);
+        y = nc_apply(mp, eo[1], eo[2], y);
+        y = nc_apply(mp, eo[0], eo[1], y);
+        x[i] = (T)y;
+    }
+}
+
 // Lanes per workgroup whose message buffers fit the LDS of one workgroup
 // (160 KiB on gfx950); 0 if not even one lane's do.
 constexpr size_t kNcLds = 160 * 1024;
@@ -389,6 +895,17 @@ size_t nc_layout(int64_t num_chains, int64_t num_nodes, int64_t msg_cap, int64_t
         A->flag = (int *)(c + o_f);
     }
     return off;
+}
+
+// Launch check, then the device flag read back (synchronous).
+tv_status nc_finish(int *dflag, hipStream_t stream) {
+    if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return TV_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return TV_ERR_HIP;
+    if (flag & kNcFlagInvalid) return TV_ERR_INVALID_ARG;
+    if (flag & kNcFlagCapacity) return TV_ERR_WORKSPACE;
+    return TV_OK;
 }
 
 }  // namespace
@@ -423,6 +940,16 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
     A.map_cap = map_cap;
     nc_layout(num_chains, num_nodes, msg_cap, map_cap, workspace, &A);
     if (hipMemsetAsync(A.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
+    if (msg_cap <= kWaveMsg) {  // a wave per chain
+        const dim3 gw((unsigned)num_chains);
+        if (dtype == TV_F32)
+            hipLaunchKernelGGL((k_nc_wave<float>), gw, dim3(64), 0, stream, A, (const float *)ulam,
+                               (const float *)uslope, (const float *)w, (const float *)C, (float *)x);
+        else
+            hipLaunchKernelGGL((k_nc_wave<double>), gw, dim3(64), 0, stream, A, (const double *)ulam,
+                               (const double *)uslope, (const double *)w, (const double *)C, (double *)x);
+        return nc_finish(A.flag, stream);
+    }
     int ll = nc_lds_lanes(msg_cap);
     if (ll > 0) {  // allow the kernel more than the default 64 KiB of dynamic LDS
         const int bytes = (int)(sizeof(double) * 3 * (size_t)(2 * msg_cap + 1) * (size_t)ll);
@@ -460,13 +987,7 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
             hipLaunchKernelGGL((k_nc_chain<double, false>), grid, dim3(64), 0, stream, A, (const double *)ulam,
                                (const double *)uslope, (const double *)w, (const double *)C, (double *)x, lanes);
     }
-    if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
-    int flag = 0;
-    if (hipMemcpyAsync(&flag, A.flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return TV_ERR_HIP;
-    if (hipStreamSynchronize(stream) != hipSuccess) return TV_ERR_HIP;
-    if (flag & kNcFlagInvalid) return TV_ERR_INVALID_ARG;
-    if (flag & kNcFlagCapacity) return TV_ERR_WORKSPACE;
-    return TV_OK;
+    return nc_finish(A.flag, stream);
 }
 
 }  // extern "C"

@@ -129,7 +129,47 @@ def test_hbm_message_buffers_match_lds_ones():
     coff, uoff, ulam, usl, w, C = _rand_batch(g, 70, 80)
     args = [_dev(coff, torch.int64), _dev(uoff, torch.int64), _dev(ulam, torch.float64), _dev(usl, torch.float64),
             _dev(w, torch.float64), _dev(C, torch.float64)]
-    a = binding.chain_nc(*args, msg_cap=256)
-    b = binding.chain_nc(*args, msg_cap=8192)
+    a = binding.chain_nc(*args, msg_cap=512)   # one lane per chain, buffers in LDS
+    b = binding.chain_nc(*args, msg_cap=8192)  # one lane per chain, buffers in HBM
     assert torch.equal(a, b)
     _check(coff, uoff, ulam, usl, w, C, b.cpu().numpy(), 1e-9)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_wave_kernel_matches_the_oracle(dtype):
+    """msg_cap <= 256 selects a wave per chain (prefix-minimum form of Algorithm 1):
+    the same minimum energies as the oracle and as the one-lane kernel."""
+    g = np.random.default_rng(21)
+    for trial in range(3):
+        coff, uoff, ulam, usl, w, C = _rand_batch(g, 120, 150, trunc_frac=(0.0, 0.5, 1.0)[trial])
+        if trial == 1:
+            w[g.random(w.size) < 0.2] = 0.0
+        if dtype == torch.float32:
+            ulam, usl, w = (a.astype(np.float32).astype(np.float64) for a in (ulam, usl, w))
+            C = C.astype(np.float32).astype(np.float64)
+        args = [_dev(coff, torch.int64), _dev(uoff, torch.int64), _dev(ulam, dtype), _dev(usl, dtype),
+                _dev(w, dtype), _dev(C, dtype)]
+        xw = binding.chain_nc(*args, msg_cap=256).double().cpu().numpy()
+        xl = binding.chain_nc(*args, msg_cap=1024).double().cpu().numpy()
+        if dtype == torch.float64:
+            _check(coff, uoff, ulam, usl, w, C, xw, 1e-9)
+        else:
+            _check(coff, uoff, ulam, usl, w, C, xw, 1e-6, 8 * 2.0 ** -23 * (np.abs(ulam).max() + 1) * 4)
+        del xl
+
+
+def test_wave_kernel_cost_volume_and_capacity():
+    coff, uoff, ulam, usl, _ = synth.cost_volume_chains(32, 300, 64, seed=8)
+    N = uoff.size - 1
+    w = np.full(N, 0.6)
+    C = np.full(N, 2.0)
+    args = [_dev(coff, torch.int64), _dev(uoff, torch.int64), _dev(ulam, torch.float64), _dev(usl, torch.float64),
+            _dev(w, torch.float64), _dev(C, torch.float64)]
+    x = binding.chain_nc(*args, msg_cap=256).cpu().numpy()
+    _check(coff, uoff, ulam, usl, w, C, x, 1e-9)
+    with pytest.raises(binding.TvChainError) as e:  # 64-breakpoint unaries do not fit 40
+        binding.chain_nc(*args, msg_cap=40)
+    assert e.value.status == binding.TV_ERR_WORKSPACE
+    with pytest.raises(binding.TvChainError) as e:
+        binding.chain_nc(*args, msg_cap=256, map_cap=100)
+    assert e.value.status == binding.TV_ERR_WORKSPACE
