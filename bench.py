@@ -462,7 +462,7 @@ def rocprof_summary(d):
         call_us = {}
         for name, calls, total, avg in con.execute(
                 "select name, total_calls, total_duration, average from top_kernels limit 25"):
-            short = name.split("(")[0].replace("void ", "")
+            short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
             print("  %-60s calls=%-6d total_us=%-10.1f avg_us=%.1f" % (short[:60], calls, total, avg))
             if short.startswith("tvc::k_seg_"):
                 prob = short.split(",")[1].strip().split("<")[0] if "," in short else short

@@ -61,7 +61,6 @@ __global__ __launch_bounds__(256) void k_nc2d_setup(Nc2dWs ws, const T *__restri
     ws.xv[c * H + r] = x0;
     ws.y[i] = 0.0;
     ws.ybar[i] = 0.0;
-    for (int64_t k = 0; k < D; ++k) ws.ulam[i * D + k] = d0 + (double)k * dd;
     ws.wr[i] = (c + 1 < W) ? (w_h ? (double)w_h[r * (W - 1) + c] : whs) : 0.0;
     ws.wc[c * H + r] = (r + 1 < H) ? (w_v ? (double)w_v[r * W + c] : wvs) : 0.0;
     ws.cc[i] = C;
@@ -69,31 +68,45 @@ __global__ __launch_bounds__(256) void k_nc2d_setup(Nc2dWs ws, const T *__restri
 
 // Unaries of the prox step: f / 2 plus the interpolant of |x - z|^2 / (2 tau)
 // on the levels, z = x_state + sgn tau ybar; row-major nodes for the rows,
-// column-major for the columns.
+// column-major for the columns.  One thread per slope (node, k), so the slope
+// array is written contiguously.
 template <typename T>
 __global__ __launch_bounds__(256) void k_nc2d_unary(Nc2dWs ws, const T *__restrict__ cost, int64_t H, int64_t W,
                                                     int64_t D, double d0, double dd, double steep, double tau,
                                                     double sgn, int horizontal) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= H * W) return;
-    const int64_t r = i / W, c = i % W;
-    const int64_t node = horizontal ? i : c * H + r;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= H * W * (D + 1)) return;
+    const int64_t node = j / (D + 1), k = j % (D + 1);
+    int64_t r, c;
+    if (horizontal) {
+        r = node / W;
+        c = node % W;
+    } else {
+        c = node / H;
+        r = node % H;
+    }
+    const int64_t i = r * W + c;
     const double xs = horizontal ? ws.xh[i] : ws.xv[node];
     const double z = xs + sgn * tau * ws.ybar[i];
-    const T *cr = cost + i * D;
-    double *s = ws.uslope + node * (D + 1);
-    const double lo = d0, hi = d0 + (double)(D - 1) * dd;
-    double s0 = -0.5 * steep + (lo - z) / tau;
-    double sD = 0.5 * steep + (hi - z) / tau;
-    s[0] = s0 < 0.0 ? s0 : 0.0;
-    s[D] = sD > 0.0 ? sD : 0.0;
-    double prev = (double)cr[0];
-    for (int64_t k = 1; k < D; ++k) {
-        const double cur = (double)cr[k];
+    double v;
+    if (k == 0) {
+        v = -0.5 * steep + (d0 - z) / tau;
+        v = v < 0.0 ? v : 0.0;
+    } else if (k == D) {
+        v = 0.5 * steep + (d0 + (double)(D - 1) * dd - z) / tau;
+        v = v > 0.0 ? v : 0.0;
+    } else {
+        const T *cr = cost + i * D;
         const double la = d0 + (double)(k - 1) * dd, lb = d0 + (double)k * dd;
-        s[k] = 0.5 * (cur - prev) / dd + (la + lb - 2.0 * z) / (2.0 * tau);
-        prev = cur;
+        v = 0.5 * ((double)cr[k] - (double)cr[k - 1]) / dd + (la + lb - 2.0 * z) / (2.0 * tau);
     }
+    ws.uslope[j] = v;
+}
+
+// The levels of every node (the same for rows and columns), one thread per entry.
+__global__ __launch_bounds__(256) void k_nc2d_levels(double *ulam, int64_t total, int64_t D, double d0, double dd) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < total) ulam[j] = d0 + (double)(j % D) * dd;
 }
 
 __global__ __launch_bounds__(256) void k_nc2d_update(Nc2dWs ws, int64_t H, int64_t W, double sigma) {
@@ -187,16 +200,20 @@ tv_status tv2d_nc_solve(tv_dtype dtype, const void *cost, int64_t H, int64_t W, 
         hipLaunchKernelGGL((k_nc2d_setup<double>), g1, blk, 0, stream, ws, (const double *)cost, H, W, D, d0, dd,
                            (const double *)w_h, w_h_scalar, (const double *)w_v, w_v_scalar, C);
     if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
+    hipLaunchKernelGGL(k_nc2d_levels, dim3((unsigned)((N * D + 255) / 256)), blk, 0, stream, ws.ulam, N * D, D, d0,
+                       dd);
+    if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
+    const dim3 gS((unsigned)((N * (D + 1) + 255) / 256));
     const double *cc = std::isfinite(C) ? ws.cc : nullptr;
     for (int k = 1; k <= iters; ++k) {
         const double tau = tau0 / k, sigma = 1.0 / (2.0 * tau);
         for (int pass = 0; pass < 2; ++pass) {
             const int horizontal = pass == 0;
             if (dtype == TV_F32)
-                hipLaunchKernelGGL((k_nc2d_unary<float>), gN, blk, 0, stream, ws, (const float *)cost, H, W, D, d0,
+                hipLaunchKernelGGL((k_nc2d_unary<float>), gS, blk, 0, stream, ws, (const float *)cost, H, W, D, d0,
                                    dd, steep, tau, horizontal ? -1.0 : 1.0, horizontal);
             else
-                hipLaunchKernelGGL((k_nc2d_unary<double>), gN, blk, 0, stream, ws, (const double *)cost, H, W, D,
+                hipLaunchKernelGGL((k_nc2d_unary<double>), gS, blk, 0, stream, ws, (const double *)cost, H, W, D,
                                    d0, dd, steep, tau, horizontal ? -1.0 : 1.0, horizontal);
             if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
             const tv_status st = tv_chain_nc(TV_F64, horizontal ? H : W, N, horizontal ? ws.coff_r : ws.coff_c,

@@ -173,3 +173,23 @@ def test_wave_kernel_cost_volume_and_capacity():
     with pytest.raises(binding.TvChainError) as e:
         binding.chain_nc(*args, msg_cap=256, map_cap=100)
     assert e.value.status == binding.TV_ERR_WORKSPACE
+
+
+def test_full_bench_size_sampled_rows():
+    """The bench's workload (1000 rows x 1482 of the 64-level cost volume, FP32,
+    w = 0.6, C = 2, msg_cap = 256: the wave kernel), checked on 8 sampled rows."""
+    coff, uoff, ulam, usl, _ = synth.cost_volume_chains(1000, 1482, 64, seed=1)
+    N = uoff.size - 1
+    w = np.full(N, 0.6)
+    C = np.full(N, 2.0)
+    x = binding.chain_nc(_dev(coff, torch.int64), _dev(uoff, torch.int64), _dev(ulam, torch.float32),
+                         _dev(usl, torch.float32), _dev(w, torch.float32), _dev(C, torch.float32),
+                         msg_cap=256).double().cpu().numpy()
+    l32, s32 = ulam.astype(np.float32).astype(np.float64), usl.astype(np.float32).astype(np.float64)
+    rows = np.random.default_rng(0).choice(1000, 8, replace=False)
+    sub = np.concatenate([[0], np.cumsum(np.full(8, 1482))]).astype(np.int64)
+    nodes = np.concatenate([np.arange(r * 1482, (r + 1) * 1482) for r in rows])
+    uo = np.arange(nodes.size + 1, dtype=np.int64) * 64
+    ll = np.concatenate([l32[i * 64:(i + 1) * 64] for i in nodes])
+    ss = np.concatenate([s32[i * 65 + 0:i * 65 + 65] for i in nodes])
+    _check(sub, uo, ll, ss, w[nodes], C[nodes], x[nodes], 1e-6, 1e-4)
