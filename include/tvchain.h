@@ -244,8 +244,8 @@ tv_status tv_tree_dp(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
  * with f_i continuous piecewise-linear and the truncated TV of the pairwise
  * terms (Lemma 1, Lemma 2 with Algorithm 1, its reversal and the truncation,
  * and the backward pass through the mappings pi), exactly, one lane per chain.
- *  chain_offsets : DEVICE int64 [num_chains + 1], node ranges (non-decreasing,
- *                  last = num_nodes).
+ *  chain_offsets : DEVICE int64 [num_chains + 1], node ranges within
+ *                  [0, num_nodes] (a range outside it: TV_ERR_INVALID_ARG).
  *  unary_offsets : DEVICE int64 [num_nodes + 1]; node i has t_i = unary_offsets[i+1]
  *                  - unary_offsets[i] >= 1 breakpoints ulam[unary_offsets[i] ..]
  *                  (non-decreasing) and t_i + 1 slopes uslope[unary_offsets[i] + i ..]

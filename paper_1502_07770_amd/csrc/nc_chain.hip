@@ -252,7 +252,7 @@ __device__ __forceinline__ double nc_apply(const NcMaps &mp, int64_t lo, int64_t
 }
 
 struct NcArgs {
-    int64_t num_chains;
+    int64_t num_chains, num_nodes;
     const int64_t *coff, *uoff;
     int64_t msg_cap, map_cap;
     double *bufs;     // per chain: 3 buffers of (msg_cap + msg_cap + 1) doubles
@@ -272,7 +272,11 @@ __global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__
     const int64_t c = (int64_t)blockIdx.x * lanes + threadIdx.x;
     if (c >= A.num_chains) return;
     const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
-    if (n1 <= n0) return;
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {  // a range outside the nodes
+        atomicOr(A.flag, kNcFlagInvalid);
+        return;
+    }
+    if (n1 == n0) return;
     const int64_t bstride = 2 * A.msg_cap + 1;
     double *base = kLds ? s_nc + (int64_t)threadIdx.x * 3 * bstride : A.bufs + c * 3 * bstride;
     NcBuf M{base, base + A.msg_cap, 0, A.msg_cap};
@@ -774,7 +778,11 @@ __global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ 
     const int64_t c = blockIdx.x;
     if (c >= A.num_chains) return;
     const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
-    if (n1 <= n0) return;
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {  // a range outside the nodes
+        if (threadIdx.x == 0) atomicOr(A.flag, kNcFlagInvalid);
+        return;
+    }
+    if (n1 == n0) return;
     const int lane = wv_lane();
     const int cap = (int)(A.msg_cap < kWaveMsg ? A.msg_cap : kWaveMsg);
     double *mb = A.maps + c * 3 * A.map_cap;
@@ -934,6 +942,7 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
     if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
     NcArgs A;
     A.num_chains = num_chains;
+    A.num_nodes = num_nodes;
     A.coff = chain_offsets;
     A.uoff = unary_offsets;
     A.msg_cap = msg_cap;

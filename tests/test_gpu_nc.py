@@ -193,3 +193,15 @@ def test_full_bench_size_sampled_rows():
     ll = np.concatenate([l32[i * 64:(i + 1) * 64] for i in nodes])
     ss = np.concatenate([s32[i * 65 + 0:i * 65 + 65] for i in nodes])
     _check(sub, uo, ll, ss, w[nodes], C[nodes], x[nodes], 1e-6, 1e-4)
+
+
+def test_chain_ranges_outside_the_nodes_are_rejected():
+    g = np.random.default_rng(30)
+    coff, uoff, ulam, usl, w, C = _rand_batch(g, 6, 20)
+    bad = coff.copy()
+    bad[-1] += 5  # past num_nodes
+    for cap in (256, 1024):  # wave and lane kernels
+        with pytest.raises(binding.TvChainError) as e:
+            binding.chain_nc(_dev(bad, torch.int64), _dev(uoff, torch.int64), _dev(ulam, torch.float64),
+                             _dev(usl, torch.float64), _dev(w, torch.float64), _dev(C, torch.float64), msg_cap=cap)
+        assert e.value.status == binding.TV_ERR_INVALID_ARG
