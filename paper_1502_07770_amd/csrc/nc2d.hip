@@ -12,9 +12,11 @@
 // tau_k = tau0 / k, sigma_k = 1 / (2 tau_k) (L^2 = 2), theta = 1.  Each prox is
 // the exact minimiser over every row (column) chain of Psi plus the
 // piecewise-linear interpolant of |x - z|^2 / (2 tau) on the cost levels: a
-// kernel forms those unaries (FP64) and tv_chain_nc solves the chains.  x_v and
-// the column unaries are kept column-major, so each column is a contiguous
-// chain.  Starts from the per-pixel minimiser of f with y = 0.
+// kernel forms those unaries (FP64) and one tv_chain_nc launch solves the H
+// row and W column chains together (both prox steps read only the previous
+// iterate).  Nodes 0..N-1 are the rows (row-major), N..2N-1 the columns
+// (column-major, x_v kept in that order), so every chain is contiguous.  Starts
+// from the per-pixel minimiser of f with y = 0.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,10 +28,10 @@ namespace tvc {
 namespace {
 
 struct Nc2dWs {
-    double *xh, *xv, *y, *ybar;  // [N]; xv column-major
-    double *ulam, *uslope;       // [N D], [N (D + 1)]
-    double *wr, *wc, *cc;        // [N] edge weights (row-major rows, column-major columns), C
-    int64_t *coff_r, *coff_c, *uoff;
+    double *xh, *xv, *y, *ybar;  // [N]; xv column-major, right after xh (the chains' output)
+    double *ulam, *uslope;       // [2N D], [2N (D + 1)]
+    double *wr, *wc, *cc;        // [N] row, [N] column edge weights (adjacent), [2N] C
+    int64_t *coff, *uoff;        // [H + W + 1] chain ranges, [2N + 1]
     void *chain_ws;
     size_t chain_bytes;
 };
@@ -40,11 +42,11 @@ __global__ __launch_bounds__(256) void k_nc2d_setup(Nc2dWs ws, const T *__restri
                                                     double whs, const T *__restrict__ w_v, double wvs, double C) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t N = H * W;
-    if (i <= H) ws.coff_r[i] = i * W;
-    if (i <= W) ws.coff_c[i] = i * H;
-    if (i > N) return;
+    if (i <= H) ws.coff[i] = i * W;
+    if (i >= 1 && i <= W) ws.coff[H + i] = N + i * H;
+    if (i > 2 * N) return;
     ws.uoff[i] = i * D;
-    if (i == N) return;
+    if (i >= N) return;
     const int64_t r = i / W, c = i % W;
     const T *cr = cost + i * D;
     int64_t kb = 0;
@@ -64,30 +66,33 @@ __global__ __launch_bounds__(256) void k_nc2d_setup(Nc2dWs ws, const T *__restri
     ws.wr[i] = (c + 1 < W) ? (w_h ? (double)w_h[r * (W - 1) + c] : whs) : 0.0;
     ws.wc[c * H + r] = (r + 1 < H) ? (w_v ? (double)w_v[r * W + c] : wvs) : 0.0;
     ws.cc[i] = C;
+    ws.cc[N + i] = C;
 }
 
-// Unaries of the prox step: f / 2 plus the interpolant of |x - z|^2 / (2 tau)
-// on the levels, z = x_state + sgn tau ybar; row-major nodes for the rows,
-// column-major for the columns.  One thread per slope (node, k), so the slope
-// array is written contiguously.
+// Unaries of the prox steps: f / 2 plus the interpolant of |x - z|^2 / (2 tau)
+// on the levels; z = x_h - tau ybar for the row nodes (0..N-1, row-major),
+// z = x_v + tau ybar for the column nodes (N..2N-1, column-major).  One thread
+// per slope (node, k), so the slope array is written contiguously.
 template <typename T>
 __global__ __launch_bounds__(256) void k_nc2d_unary(Nc2dWs ws, const T *__restrict__ cost, int64_t H, int64_t W,
-                                                    int64_t D, double d0, double dd, double steep, double tau,
-                                                    double sgn, int horizontal) {
+                                                    int64_t D, double d0, double dd, double steep, double tau) {
+    const int64_t N = H * W;
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= H * W * (D + 1)) return;
+    if (j >= 2 * N * (D + 1)) return;
     const int64_t node = j / (D + 1), k = j % (D + 1);
+    const bool horizontal = node < N;
+    const int64_t q = horizontal ? node : node - N;
     int64_t r, c;
     if (horizontal) {
-        r = node / W;
-        c = node % W;
+        r = q / W;
+        c = q % W;
     } else {
-        c = node / H;
-        r = node % H;
+        c = q / H;
+        r = q % H;
     }
     const int64_t i = r * W + c;
-    const double xs = horizontal ? ws.xh[i] : ws.xv[node];
-    const double z = xs + sgn * tau * ws.ybar[i];
+    const double xs = horizontal ? ws.xh[i] : ws.xv[q];
+    const double z = xs + (horizontal ? -tau : tau) * ws.ybar[i];
     double v;
     if (k == 0) {
         v = -0.5 * steep + (d0 - z) / tau;
@@ -128,14 +133,14 @@ __global__ __launch_bounds__(256) void k_nc2d_out(const double *__restrict__ xh,
 size_t nc2d_layout(int64_t H, int64_t W, int64_t D, int64_t msg_cap, int64_t map_cap, void *p, Nc2dWs *out) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const int64_t N = H * W;
-    const size_t cw = tv_chain_nc_workspace(H > W ? H : W, N, msg_cap, map_cap);
+    const size_t cw = tv_chain_nc_workspace(H + W, 2 * N, msg_cap, map_cap);
     if (cw == 0) return 0;
     size_t off = 0;
     const size_t o_x = off;   off += al(sizeof(double) * (size_t)(4 * N));
-    const size_t o_l = off;   off += al(sizeof(double) * (size_t)(N * D));
-    const size_t o_s = off;   off += al(sizeof(double) * (size_t)(N * (D + 1)));
-    const size_t o_w = off;   off += al(sizeof(double) * (size_t)(3 * N));
-    const size_t o_o = off;   off += al(sizeof(int64_t) * (size_t)(H + 1 + W + 1 + N + 1));
+    const size_t o_l = off;   off += al(sizeof(double) * (size_t)(2 * N * D));
+    const size_t o_s = off;   off += al(sizeof(double) * (size_t)(2 * N * (D + 1)));
+    const size_t o_w = off;   off += al(sizeof(double) * (size_t)(4 * N));
+    const size_t o_o = off;   off += al(sizeof(int64_t) * (size_t)(H + W + 1 + 2 * N + 1));
     const size_t o_c = off;   off += al(cw);
     if (p && out) {
         char *b = (char *)p;
@@ -151,9 +156,8 @@ size_t nc2d_layout(int64_t H, int64_t W, int64_t D, int64_t msg_cap, int64_t map
         out->wc = w + N;
         out->cc = w + 2 * N;
         int64_t *o = (int64_t *)(b + o_o);
-        out->coff_r = o;
-        out->coff_c = o + H + 1;
-        out->uoff = o + H + 1 + W + 1;
+        out->coff = o;
+        out->uoff = o + H + W + 1;
         out->chain_ws = b + o_c;
         out->chain_bytes = cw;
     }
@@ -191,7 +195,7 @@ tv_status tv2d_nc_solve(tv_dtype dtype, const void *cost, int64_t H, int64_t W, 
     nc2d_layout(H, W, D, msg_cap, map_cap, workspace, &ws);
     const int64_t N = H * W;
     const dim3 blk(256);
-    const dim3 g1((unsigned)((N + 1 + 255) / 256 + ((H > W ? H : W) + 256) / 256));
+    const dim3 g1((unsigned)((2 * N + 1 + 255) / 256 + ((H > W ? H : W) + 256) / 256));
     const dim3 gN((unsigned)((N + 255) / 256));
     if (dtype == TV_F32)
         hipLaunchKernelGGL((k_nc2d_setup<float>), g1, blk, 0, stream, ws, (const float *)cost, H, W, D, d0, dd,
@@ -200,28 +204,24 @@ tv_status tv2d_nc_solve(tv_dtype dtype, const void *cost, int64_t H, int64_t W, 
         hipLaunchKernelGGL((k_nc2d_setup<double>), g1, blk, 0, stream, ws, (const double *)cost, H, W, D, d0, dd,
                            (const double *)w_h, w_h_scalar, (const double *)w_v, w_v_scalar, C);
     if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
-    hipLaunchKernelGGL(k_nc2d_levels, dim3((unsigned)((N * D + 255) / 256)), blk, 0, stream, ws.ulam, N * D, D, d0,
-                       dd);
+    hipLaunchKernelGGL(k_nc2d_levels, dim3((unsigned)((2 * N * D + 255) / 256)), blk, 0, stream, ws.ulam,
+                       2 * N * D, D, d0, dd);
     if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
-    const dim3 gS((unsigned)((N * (D + 1) + 255) / 256));
+    const dim3 gS((unsigned)((2 * N * (D + 1) + 255) / 256));
     const double *cc = std::isfinite(C) ? ws.cc : nullptr;
     for (int k = 1; k <= iters; ++k) {
         const double tau = tau0 / k, sigma = 1.0 / (2.0 * tau);
-        for (int pass = 0; pass < 2; ++pass) {
-            const int horizontal = pass == 0;
-            if (dtype == TV_F32)
-                hipLaunchKernelGGL((k_nc2d_unary<float>), gS, blk, 0, stream, ws, (const float *)cost, H, W, D, d0,
-                                   dd, steep, tau, horizontal ? -1.0 : 1.0, horizontal);
-            else
-                hipLaunchKernelGGL((k_nc2d_unary<double>), gS, blk, 0, stream, ws, (const double *)cost, H, W, D,
-                                   d0, dd, steep, tau, horizontal ? -1.0 : 1.0, horizontal);
-            if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
-            const tv_status st = tv_chain_nc(TV_F64, horizontal ? H : W, N, horizontal ? ws.coff_r : ws.coff_c,
-                                             ws.uoff, ws.ulam, ws.uslope, horizontal ? ws.wr : ws.wc, cc,
-                                             horizontal ? ws.xh : ws.xv, msg_cap, map_cap, ws.chain_ws,
-                                             ws.chain_bytes, stream);
-            if (st != TV_OK) return st;
-        }
+        if (dtype == TV_F32)
+            hipLaunchKernelGGL((k_nc2d_unary<float>), gS, blk, 0, stream, ws, (const float *)cost, H, W, D, d0, dd,
+                               steep, tau);
+        else
+            hipLaunchKernelGGL((k_nc2d_unary<double>), gS, blk, 0, stream, ws, (const double *)cost, H, W, D, d0,
+                               dd, steep, tau);
+        if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
+        // rows and columns in one launch; x_h then x_v (column-major) are the output
+        const tv_status st = tv_chain_nc(TV_F64, H + W, 2 * N, ws.coff, ws.uoff, ws.ulam, ws.uslope, ws.wr, cc,
+                                         ws.xh, msg_cap, map_cap, ws.chain_ws, ws.chain_bytes, stream);
+        if (st != TV_OK) return st;
         hipLaunchKernelGGL(k_nc2d_update, gN, blk, 0, stream, ws, H, W, sigma);
         if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
     }
