@@ -441,6 +441,7 @@ __device__ __forceinline__ int wv_lower(const double *a, int n, double v, bool s
 // Shared scratch of one wave.
 struct WScratch {
     double *T;     // [2 kWaveMsg] merge staging
+    int *CU, *CM;  // [2 kWaveMsg] unary / message breakpoints at or before each merged one
     double *V;     // [kWaveMsg] values at breakpoints
     double *PM;    // [kWaveMsg] prefix minimum
     int *PA;       // [kWaveMsg] its index
@@ -465,8 +466,22 @@ __device__ void wv_values(const WView &h, double *V) {
 // than cap.
 __device__ int wv_sum(const double *ul, const double *us, int tu, const double *ml, const double *ms, int tm,
                       double *ol, double *os, int cap, const WScratch &W) {
-    for (int i = wv_lane(); i < tu; i += 64) W.T[i + wv_lower(ml, tm, ul[i], false)] = ul[i];
-    for (int j = wv_lane(); j < tm; j += 64) W.T[j + wv_lower(ul, tu, ml[j], true)] = ml[j];
+    // scatter by rank (a unary breakpoint goes before equal message ones) and
+    // record how many of each list lie at or before the element: for the last
+    // element of a group of equal positions those are the counts of both lists
+    // up to that position, which give the slope right of it
+    for (int i = wv_lane(); i < tu; i += 64) {
+        const int r = wv_lower(ml, tm, ul[i], false);
+        W.T[i + r] = ul[i];
+        W.CU[i + r] = i + 1;
+        W.CM[i + r] = r;
+    }
+    for (int j = wv_lane(); j < tm; j += 64) {
+        const int r = wv_lower(ul, tu, ml[j], true);
+        W.T[j + r] = ml[j];
+        W.CU[j + r] = r;
+        W.CM[j + r] = j + 1;
+    }
     __syncthreads();
     const int tot = tu + tm;
     int base = 0;
@@ -477,8 +492,10 @@ __device__ int wv_sum(const double *ul, const double *us, int tu, const double *
         const int pos = base + inc - 1;
         if (keep && pos < cap) {
             const double lam = W.T[k];
+            int last = k;
+            while (last + 1 < tot && W.T[last + 1] == lam) ++last;
             ol[pos] = lam;
-            os[pos + 1] = us[wv_lower(ul, tu, lam, true)] + ms[wv_lower(ml, tm, lam, true)];
+            os[pos + 1] = us[W.CU[last]] + ms[W.CM[last]];
         }
         base += __shfl(inc, 63, 64);
     }
@@ -774,7 +791,10 @@ __global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ 
     __shared__ double sC_l[kWaveMsg], sC_s[kWaveMsg + 1];
     __shared__ double sT[2 * kWaveMsg], sV[kWaveMsg], sPM[kWaveMsg], sPS[kWaveMsg + 1], sPE[kWaveMsg + 1];
     __shared__ int sPA[kWaveMsg], sQ0[kWaveMsg + 1], sQ1[kWaveMsg + 1];
-    const WScratch W{sT, sV, sPM, sPA, sPS, sPE, sQ0, sQ1};
+    // the merge's counts live only inside the sum, before V and PM are used:
+    // they share those arrays (2 kWaveMsg ints in kWaveMsg doubles each)
+    static_assert(2 * sizeof(int) == sizeof(double), "two counts per double");
+    const WScratch W{sT, (int *)sV, (int *)sPM, sV, sPM, sPA, sPS, sPE, sQ0, sQ1};
     const int64_t c = blockIdx.x;
     if (c >= A.num_chains) return;
     const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
@@ -790,6 +810,23 @@ __global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ 
     int64_t nmap = 0;
     int tm = 0, th = 0, bad = 0;
     if (lane == 0) sA_s[0] = 0.0;
+    // the next node's unary is loaded into registers while a node is processed
+    constexpr int kPer = kWaveMsg / 64;
+    double pl[kPer], ps[kPer + 1];
+    auto fetch = [&](int64_t i) {
+        const int64_t u0 = A.uoff[i], tu = A.uoff[i + 1] - u0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = lane + 64 * j;
+            pl[j] = (k < tu && tu <= cap) ? (double)ulam[u0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j <= kPer; ++j) {
+            const int k = lane + 64 * j;
+            ps[j] = (k <= tu && tu <= cap) ? (double)uslope[u0 + i + k] : 0.0;
+        }
+    };
+    fetch(n0);
     __syncthreads();
     for (int64_t i = n0; i < n1; ++i) {
         const int64_t u0 = A.uoff[i], tu64 = A.uoff[i + 1] - u0;
@@ -799,8 +836,17 @@ __global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ 
         }
         const int tu = (int)tu64;
         bool inval = false;
-        for (int k = lane; k < tu; k += 64) sU_l[k] = (double)ulam[u0 + k];
-        for (int k = lane; k <= tu; k += 64) sU_s[k] = (double)uslope[u0 + i + k];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = lane + 64 * j;
+            if (k < tu) sU_l[k] = pl[j];
+        }
+#pragma unroll
+        for (int j = 0; j <= kPer; ++j) {
+            const int k = lane + 64 * j;
+            if (k <= tu) sU_s[k] = ps[j];
+        }
+        if (i + 1 < n1) fetch(i + 1);
         __syncthreads();
         for (int k = lane; k < tu; k += 64)
             if (k > 0 && !(sU_l[k] >= sU_l[k - 1])) inval = true;
