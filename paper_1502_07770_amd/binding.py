@@ -691,14 +691,16 @@ def tree_dp(parent: torch.Tensor, offsets: torch.Tensor, b: torch.Tensor, wm: to
 
 
 def chain_nc(chain_offsets: torch.Tensor, unary_offsets: torch.Tensor, ulam: torch.Tensor, uslope: torch.Tensor,
-             w: torch.Tensor, C: Optional[torch.Tensor] = None, msg_cap: int = 1024,
+             w: torch.Tensor, C: Optional[torch.Tensor] = None, msg_cap: int = 256,
              map_cap: Optional[int] = None) -> torch.Tensor:
     """Sec. 3 non-convex chains (tv_chain_nc): chain_offsets (int64, chains + 1
     node ranges), unary_offsets (int64, nodes + 1; node i has breakpoints
     ulam[unary_offsets[i]:unary_offsets[i+1]] and slopes
     uslope[unary_offsets[i]+i : unary_offsets[i+1]+i+1]), per-node w and C of the
     edge to the next node (C None or inf: plain TV).  msg_cap bounds a
-    message's breakpoints, map_cap the intervals kept per chain (default: 32 per
+    message's breakpoints (up to 256: a wave per chain, 128 or less: smaller
+    LDS and more waves per CU; larger: a lane per chain), map_cap the intervals
+    kept per chain (default: 32 per
     node of the longest chain; cost-volume chains need about 8 to 12).  Returns x
     (one value per node)."""
     _require_gpu(chain_offsets, unary_offsets, ulam, uslope, w)
@@ -746,7 +748,7 @@ def tv2d_nc(cost: torch.Tensor, d0: float, dd: float, steep: float, w_h, w_v, C:
         if t is not None and t.dtype != cost.dtype:
             raise TvChainError(TV_ERR_INVALID_ARG, "weights must match the cost dtype")
     if msg_cap is None:
-        msg_cap = max(256, 4 * D)
+        msg_cap = max(256, 2 * D)
     if map_cap is None:
         map_cap = 32 * max(H, W)
     x = torch.empty((H, W), dtype=cost.dtype, device=cost.device)

@@ -218,9 +218,16 @@ tv_status tv2d_nc_solve(tv_dtype dtype, const void *cost, int64_t H, int64_t W, 
             hipLaunchKernelGGL((k_nc2d_unary<double>), gS, blk, 0, stream, ws, (const double *)cost, H, W, D, d0,
                                dd, steep, tau);
         if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
-        // rows and columns in one launch; x_h then x_v (column-major) are the output
-        const tv_status st = tv_chain_nc(TV_F64, H + W, 2 * N, ws.coff, ws.uoff, ws.ulam, ws.uslope, ws.wr, cc,
-                                         ws.xh, msg_cap, map_cap, ws.chain_ws, ws.chain_bytes, stream);
+        // rows and columns in one launch; x_h then x_v (column-major) are the
+        // output.  Messages of at most 128 breakpoints let twice as many waves
+        // share a CU: that capacity first, the caller's if a message outgrows it
+        // (the chain workspace does not depend on it for msg_cap <= 256).
+        const int64_t first = msg_cap > 128 && msg_cap <= 256 ? 128 : msg_cap;
+        tv_status st = tv_chain_nc(TV_F64, H + W, 2 * N, ws.coff, ws.uoff, ws.ulam, ws.uslope, ws.wr, cc, ws.xh,
+                                   first, map_cap, ws.chain_ws, ws.chain_bytes, stream);
+        if (st == TV_ERR_WORKSPACE && first < msg_cap)
+            st = tv_chain_nc(TV_F64, H + W, 2 * N, ws.coff, ws.uoff, ws.ulam, ws.uslope, ws.wr, cc, ws.xh, msg_cap,
+                             map_cap, ws.chain_ws, ws.chain_bytes, stream);
         if (st != TV_OK) return st;
         hipLaunchKernelGGL(k_nc2d_update, gN, blk, 0, stream, ws, H, W, sigma);
         if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;

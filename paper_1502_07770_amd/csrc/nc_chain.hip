@@ -377,7 +377,9 @@ __global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__
 //   f^2: the same on the reversed view; f^3: a wave minimum and per piece the
 //     crossing of min h + C;
 // each pass ends with a prefix count that places the points it emits.  The
-// backward pass is one lane's.  Used where msg_cap <= kWaveMsg.
+// backward pass is one lane's.  Instantiated for messages of up to 128 and up
+// to 256 breakpoints (16 and 32 KiB of LDS per wave), the smaller where
+// msg_cap allows, so that more waves fit on a CU.
 // ---------------------------------------------------------------------------
 constexpr int kWaveMsg = 256;
 
@@ -440,7 +442,8 @@ __device__ __forceinline__ int wv_lower(const double *a, int n, double v, bool s
 
 // Shared scratch of one wave.
 struct WScratch {
-    double *T;     // [2 kWaveMsg] merge staging
+    int tsize;     // entries of T
+    double *T;     // [2 cap] merge staging
     int *CU, *CM;  // [2 kWaveMsg] unary / message breakpoints at or before each merged one
     double *V;     // [kWaveMsg] values at breakpoints
     double *PM;    // [kWaveMsg] prefix minimum
@@ -735,17 +738,17 @@ __device__ int wv_trunc(const WView &h, double C, double *ol, double *os, int ca
         const int sinc = wv_scan_int(scount), einc = wv_scan_int(ecount);
         int sp = sb + sinc - scount;
         if (st1) {
-            if (sp < 2 * kWaveMsg) W.T[sp] = bpos;
+            if (sp < W.tsize) W.T[sp] = bpos;
             ++sp;
         }
-        if (st2 && sp < 2 * kWaveMsg) W.T[sp] = z;
+        if (st2 && sp < W.tsize) W.T[sp] = z;
         sb += __shfl(sinc, 63, 64);
         // ends are written after every start of this chunk is in T
         __syncthreads();
         int ep = eb + einc - ecount;
         auto put_end = [&](double e) {
             const int64_t ipos = nmap + ep;
-            if (ipos < mp.cap && ep < 2 * kWaveMsg) {
+            if (ipos < mp.cap && ep < W.tsize) {
                 mp.a[ipos] = W.T[ep];
                 mp.b[ipos] = e;
                 mp.to[ipos] = xm;
@@ -763,7 +766,7 @@ __device__ int wv_trunc(const WView &h, double C, double *ol, double *os, int ca
     if (sb > eb) {
         if (wv_lane() == 0) {
             const int64_t ipos = nmap + eb;
-            if (ipos < mp.cap && eb < 2 * kWaveMsg) {
+            if (ipos < mp.cap && eb < W.tsize) {
                 mp.a[ipos] = W.T[eb];
                 mp.b[ipos] = HUGE_VAL;
                 mp.to[ipos] = xm;
@@ -781,20 +784,21 @@ __device__ int wv_trunc(const WView &h, double C, double *ol, double *os, int ca
     return base <= cap ? base : -1;
 }
 
-template <typename T>
+template <typename T, int kCap>
 __global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ ulam, const T *__restrict__ uslope,
                                                 const T *__restrict__ w, const T *__restrict__ C,
                                                 T *__restrict__ x) {
-    __shared__ double sU_l[kWaveMsg], sU_s[kWaveMsg + 1];
-    __shared__ double sA_l[kWaveMsg], sA_s[kWaveMsg + 1];
-    __shared__ double sB_l[kWaveMsg], sB_s[kWaveMsg + 1];
-    __shared__ double sC_l[kWaveMsg], sC_s[kWaveMsg + 1];
-    __shared__ double sT[2 * kWaveMsg], sV[kWaveMsg], sPM[kWaveMsg], sPS[kWaveMsg + 1], sPE[kWaveMsg + 1];
-    __shared__ int sPA[kWaveMsg], sQ0[kWaveMsg + 1], sQ1[kWaveMsg + 1];
+    static_assert(kCap % 64 == 0 && kCap <= kWaveMsg, "wave message capacity");
+    __shared__ double sU_l[kCap], sU_s[kCap + 1];
+    __shared__ double sA_l[kCap], sA_s[kCap + 1];
+    __shared__ double sB_l[kCap], sB_s[kCap + 1];
+    __shared__ double sC_l[kCap], sC_s[kCap + 1];
+    __shared__ double sT[2 * kCap], sV[kCap], sPM[kCap], sPS[kCap + 1], sPE[kCap + 1];
+    __shared__ int sPA[kCap], sQ0[kCap + 1], sQ1[kCap + 1];
     // the merge's counts live only inside the sum, before V and PM are used:
-    // they share those arrays (2 kWaveMsg ints in kWaveMsg doubles each)
+    // they share those arrays (2 kCap ints in kCap doubles each)
     static_assert(2 * sizeof(int) == sizeof(double), "two counts per double");
-    const WScratch W{sT, (int *)sV, (int *)sPM, sV, sPM, sPA, sPS, sPE, sQ0, sQ1};
+    const WScratch W{2 * kCap, sT, (int *)sV, (int *)sPM, sV, sPM, sPA, sPS, sPE, sQ0, sQ1};
     const int64_t c = blockIdx.x;
     if (c >= A.num_chains) return;
     const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
@@ -804,14 +808,14 @@ __global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ 
     }
     if (n1 == n0) return;
     const int lane = wv_lane();
-    const int cap = (int)(A.msg_cap < kWaveMsg ? A.msg_cap : kWaveMsg);
+    const int cap = (int)(A.msg_cap < kCap ? A.msg_cap : kCap);
     double *mb = A.maps + c * 3 * A.map_cap;
     const NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
     int64_t nmap = 0;
     int tm = 0, th = 0, bad = 0;
     if (lane == 0) sA_s[0] = 0.0;
     // the next node's unary is loaded into registers while a node is processed
-    constexpr int kPer = kWaveMsg / 64;
+    constexpr int kPer = kCap / 64;
     double pl[kPer], ps[kPer + 1];
     auto fetch = [&](int64_t i) {
         const int64_t u0 = A.uoff[i], tu = A.uoff[i + 1] - u0;
@@ -997,12 +1001,21 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
     if (hipMemsetAsync(A.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
     if (msg_cap <= kWaveMsg) {  // a wave per chain
         const dim3 gw((unsigned)num_chains);
-        if (dtype == TV_F32)
-            hipLaunchKernelGGL((k_nc_wave<float>), gw, dim3(64), 0, stream, A, (const float *)ulam,
-                               (const float *)uslope, (const float *)w, (const float *)C, (float *)x);
-        else
-            hipLaunchKernelGGL((k_nc_wave<double>), gw, dim3(64), 0, stream, A, (const double *)ulam,
-                               (const double *)uslope, (const double *)w, (const double *)C, (double *)x);
+        if (dtype == TV_F32) {
+            if (msg_cap <= 128)
+                hipLaunchKernelGGL((k_nc_wave<float, 128>), gw, dim3(64), 0, stream, A, (const float *)ulam,
+                                   (const float *)uslope, (const float *)w, (const float *)C, (float *)x);
+            else
+                hipLaunchKernelGGL((k_nc_wave<float, kWaveMsg>), gw, dim3(64), 0, stream, A, (const float *)ulam,
+                                   (const float *)uslope, (const float *)w, (const float *)C, (float *)x);
+        } else {
+            if (msg_cap <= 128)
+                hipLaunchKernelGGL((k_nc_wave<double, 128>), gw, dim3(64), 0, stream, A, (const double *)ulam,
+                                   (const double *)uslope, (const double *)w, (const double *)C, (double *)x);
+            else
+                hipLaunchKernelGGL((k_nc_wave<double, kWaveMsg>), gw, dim3(64), 0, stream, A, (const double *)ulam,
+                                   (const double *)uslope, (const double *)w, (const double *)C, (double *)x);
+        }
         return nc_finish(A.flag, stream);
     }
     int ll = nc_lds_lanes(msg_cap);

@@ -167,6 +167,8 @@ def test_wave_kernel_cost_volume_and_capacity():
             _dev(w, torch.float64), _dev(C, torch.float64)]
     x = binding.chain_nc(*args, msg_cap=256).cpu().numpy()
     _check(coff, uoff, ulam, usl, w, C, x, 1e-9)
+    x = binding.chain_nc(*args, msg_cap=128).cpu().numpy()  # the 16 KiB wave variant
+    _check(coff, uoff, ulam, usl, w, C, x, 1e-9)
     with pytest.raises(binding.TvChainError) as e:  # 64-breakpoint unaries do not fit 40
         binding.chain_nc(*args, msg_cap=40)
     assert e.value.status == binding.TV_ERR_WORKSPACE

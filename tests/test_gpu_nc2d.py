@@ -62,3 +62,20 @@ def test_fp32_costs_and_plain_tv():
     e64 = oracle.nc2d_energy(cost, 0.0, 1.0, 20.0, 0.5, 0.5, np.inf, x64.cpu().numpy())
     e32 = oracle.nc2d_energy(cost, 0.0, 1.0, 20.0, 0.5, 0.5, np.inf, x32.double().cpu().numpy())
     assert abs(e32 - e64) <= 1e-5 * (1 + abs(e64))
+
+
+def test_messages_beyond_128_breakpoints_fall_back():
+    """150 levels with msg_cap = 256: the first solve with 128-breakpoint
+    messages runs out of room (each unary alone holds 150 breakpoints) and the
+    call repeats with the caller's capacity.  w = 0 keeps every pixel at its own
+    minimiser; with TV on, the energy equals the oracle's after 2 iterations.
+    Random uniform costs leave many intervals per node, hence the large map_cap."""
+    g = np.random.default_rng(12)
+    cost = g.uniform(0, 4, (6, 7, 150))
+    ct = torch.tensor(cost, device="cuda")
+    x = binding.tv2d_nc(ct, 0.0, 1.0, 20.0, 0.0, 0.0, 2.0, 50.0, 3, msg_cap=256, map_cap=8192).cpu().numpy()
+    assert np.array_equal(x, np.argmin(cost, axis=2).astype(np.float64))
+    xh, _, E = oracle.nc2d_pd(cost, 0.0, 1.0, 20.0, 0.5, 0.5, 1.5, 100.0, 2)
+    x = binding.tv2d_nc(ct, 0.0, 1.0, 20.0, 0.5, 0.5, 1.5, 100.0, 2, msg_cap=256, map_cap=8192).cpu().numpy()
+    e = oracle.nc2d_energy(cost, 0.0, 1.0, 20.0, 0.5, 0.5, 1.5, x)
+    assert abs(e - E[-1]) <= 1e-9 * (1 + abs(E[-1]))
