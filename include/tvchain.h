@@ -244,6 +244,7 @@ tv_status tv_tree_dp(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
  * with f_i continuous piecewise-linear and the truncated TV of the pairwise
  * terms (Lemma 1, Lemma 2 with Algorithm 1, its reversal and the truncation,
  * and the backward pass through the mappings pi), exactly, one lane per chain.
+ *  num_chains    : < 2^31.
  *  chain_offsets : DEVICE int64 [num_chains + 1], node ranges within
  *                  [0, num_nodes] (a range outside it: TV_ERR_INVALID_ARG).
  *  unary_offsets : DEVICE int64 [num_nodes + 1]; node i has t_i = unary_offsets[i+1]

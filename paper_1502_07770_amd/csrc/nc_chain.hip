@@ -985,6 +985,7 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
                       size_t workspace_bytes, hipStream_t stream) {
     if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
     if (num_chains < 0 || num_nodes < 0) return TV_ERR_INVALID_ARG;
+    if (num_chains >= (int64_t(1) << 31)) return TV_ERR_INVALID_ARG;  // one workgroup per chain at most
     if (num_chains == 0) return TV_OK;
     if (!chain_offsets || !unary_offsets || !ulam || !uslope || !w || !x) return TV_ERR_INVALID_ARG;
     const size_t need = tv_chain_nc_workspace(num_chains, num_nodes, msg_cap, map_cap);

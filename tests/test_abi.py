@@ -229,6 +229,8 @@ def test_nc_chain_argument_errors(lib):
                            None) == binding.TV_ERR_INVALID_ARG
     assert lib.tv_chain_nc(7, 1, 4, None, None, None, None, None, None, None, 8, 8, None, 0,
                            None) == binding.TV_ERR_INVALID_ARG
+    assert lib.tv_chain_nc(binding.TV_F64, 1 << 31, 4, None, None, None, None, None, None, None, 8, 8, None, 0,
+                           None) == binding.TV_ERR_INVALID_ARG
 
 
 def test_nc2d_argument_errors(lib):
