@@ -162,3 +162,16 @@ def test_rejects_invalid_unaries():
         oracle.nc_chain([0, 2], [1.0, 0.0], [-1, 0, 1], [], [])  # unsorted breakpoints
     with pytest.raises(ValueError):
         oracle.nc_chain([0, 0], [], [0.0], [], [])               # no breakpoint
+
+
+def test_lemma2_no_growth_without_truncation():
+    """Lemma 2: with C = inf a min-convolution adds no breakpoints, so no message
+    holds more than the unaries' breakpoints summed (hat M_i has at most
+    sum_{j <= i} t_j).  An Algorithm 1 that emitted extra points would exceed it."""
+    g = np.random.default_rng(18)
+    for _ in range(200):
+        n = int(g.integers(2, 80))
+        uoff, ulam, usl = _rand_unaries(g, n, tmax=4)
+        w = g.uniform(0, 2, n - 1)
+        _, mb = oracle.nc_chain(uoff, ulam, usl, w, np.full(n - 1, np.inf))
+        assert mb <= uoff[-1], (mb, uoff[-1])
