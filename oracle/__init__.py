@@ -22,7 +22,9 @@ arrays.  Functions and the passages they follow:
 * ``nc_chain``        -- Sec. 3 (non-convex case) on a chain: piecewise-linear
                          unaries, truncated TV, Lemma 1, Algorithm 1 and its
                          reversal, the truncation, and the backward pass through
-                         the mappings pi; ``nc_brute`` is its independent pin.
+                         the mappings pi; ``nc_brute`` is its independent pin;
+                         ``nc_tree`` the same on a forest (children's messages
+                         summed, Lemma 1), pinned by ``nc_tree_brute``.
 """
 from __future__ import annotations
 
@@ -102,6 +104,12 @@ def _load():
     lib.orc_nc_energy.restype = D
     lib.orc_nc_brute.argtypes = [I64, P, P, P, P, P, P, P]
     lib.orc_nc_brute.restype = ctypes.c_int
+    lib.orc_nc_tree.argtypes = [I64, P, P, P, P, P, P, P, P]
+    lib.orc_nc_tree.restype = ctypes.c_int
+    lib.orc_nc_tree_energy.argtypes = [I64, P, P, P, P, P, P, P]
+    lib.orc_nc_tree_energy.restype = D
+    lib.orc_nc_tree_brute.argtypes = [I64, P, P, P, P, P, P, P]
+    lib.orc_nc_tree_brute.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -499,3 +507,46 @@ def nc2d_energy(cost, d0: float, dd: float, steep: float, w_h, w_v, C: float, x)
     e += np.minimum(w_h * np.abs(np.diff(x, axis=1)), C).sum()
     e += np.minimum(w_v * np.abs(np.diff(x, axis=0)), C).sum()
     return float(e)
+
+
+def _nc_tree_args(parent, uoff, ulam, uslope, w, C):
+    parent = np.ascontiguousarray(parent, dtype=np.int64)
+    n = parent.size
+    uoff = np.ascontiguousarray(uoff, dtype=np.int64)
+    ulam, uslope = _f64(ulam), _f64(uslope)
+    if uoff.size != n + 1 or ulam.size != uoff[-1] or uslope.size != uoff[-1] + n:
+        raise ValueError("unary arrays do not match the offsets")
+    w = _f64(np.broadcast_to(w, (n,)))
+    C = _f64(np.broadcast_to(C, (n,)))
+    return n, parent, uoff, ulam, uslope, w, C
+
+
+def nc_tree(parent, uoff, ulam, uslope, w, C):
+    """Sec. 3 on a forest (parent[i] > i, -1 at roots; w[i], C[i] on the edge
+    from i to its parent): x and the largest number of message breakpoints."""
+    n, parent, uoff, ulam, uslope, w, C = _nc_tree_args(parent, uoff, ulam, uslope, w, C)
+    x = np.empty(n)
+    mb = ctypes.c_int64(0)
+    rc = _load().orc_nc_tree(n, _ptr(parent), _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(w), _ptr(C), _ptr(x),
+                             ctypes.byref(mb))
+    if rc != 0:
+        raise ValueError("orc_nc_tree: invalid input (%d)" % rc)
+    return x, int(mb.value)
+
+
+def nc_tree_energy(parent, uoff, ulam, uslope, w, C, x) -> float:
+    n, parent, uoff, ulam, uslope, w, C = _nc_tree_args(parent, uoff, ulam, uslope, w, C)
+    x = _f64(x)
+    return float(_load().orc_nc_tree_energy(n, _ptr(parent), _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(w),
+                                            _ptr(C), _ptr(x)))
+
+
+def nc_tree_brute(parent, uoff, ulam, uslope, w, C) -> float:
+    """Exact minimum energy of a forest of n <= 5 nodes (vertex candidates, min-sum)."""
+    n, parent, uoff, ulam, uslope, w, C = _nc_tree_args(parent, uoff, ulam, uslope, w, C)
+    e = ctypes.c_double(0.0)
+    rc = _load().orc_nc_tree_brute(n, _ptr(parent), _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(w), _ptr(C),
+                                   ctypes.byref(e))
+    if rc != 0:
+        raise ValueError("orc_nc_tree_brute: invalid input (%d)" % rc)
+    return float(e.value)

@@ -1584,3 +1584,222 @@ int orc_nc_brute(int64_t n, const int64_t *uoff, const double *ulam, const doubl
     free(arg);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ *
+ * Sec. 3 on a forest: nodes numbered children before parents (parent[i] > i,
+ * -1 at roots); edge i joins node i to parent[i] with w[i] >= 0 and C[i] > 0.
+ * A node's message hat M_i = f_i + sum over its children of M_c (Lemma 1, the
+ * children's lists merged one after another); a non-root then sends
+ * M_i = ((hat M_i (x) f^1) (x) f^2) (x) f^3 to its parent, recording the
+ * mappings pi of its edge; a root takes the first argmin of hat M_i.  Backward
+ * (parents before children): x_i = pi^1(pi^2(pi^3(x_parent))).
+ * ------------------------------------------------------------------------ */
+int orc_nc_tree(int64_t n, const int64_t *parent, const int64_t *uoff, const double *ulam, const double *uslope,
+                const double *w, const double *C, double *x, int64_t *max_bp)
+{
+    if (n < 1) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (parent[i] != -1 && (parent[i] <= i || parent[i] >= n)) return -1;
+    nc_plf *msg = (nc_plf *)calloc((size_t)n, sizeof(nc_plf));
+    /* per node: start and end of its intervals in each of the three lists */
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(6 * n));
+    /* children lists (CSR) */
+    int64_t *cnt = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *kid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    nc_plf hat = {0, 0, NULL, NULL}, tmp = {0, 0, NULL, NULL}, f = {0, 0, NULL, NULL}, m1 = {0, 0, NULL, NULL},
+           m2 = {0, 0, NULL, NULL}, t1 = {0, 0, NULL, NULL}, t2 = {0, 0, NULL, NULL};
+    nc_ivs iv1 = {0, 0, NULL, NULL, NULL}, iv2 = {0, 0, NULL, NULL, NULL}, iv3 = {0, 0, NULL, NULL, NULL};
+    int rc = (msg && off && cnt && kid) ? 0 : -2;
+    int64_t mb = 0;
+    if (rc == 0) {
+        for (int64_t i = 0; i < n; ++i)
+            if (parent[i] >= 0) cnt[parent[i] + 1]++;
+        for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+        int64_t *fill = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+        if (!fill) rc = -2;
+        for (int64_t i = 0; rc == 0 && i < n; ++i)
+            if (parent[i] >= 0) kid[cnt[parent[i]] + fill[parent[i]]++] = i;
+        free(fill);
+    }
+    for (int64_t i = 0; i < n && rc == 0; ++i) {
+        rc = nc_unary(i, uoff, ulam, uslope, &f);
+        if (rc) break;
+        /* hat = f + the children's messages */
+        rc = nc_reserve(&hat, f.t);
+        if (rc) break;
+        hat.t = f.t;
+        memcpy(hat.l, f.l, sizeof(double) * (size_t)f.t);
+        memcpy(hat.s, f.s, sizeof(double) * (size_t)(f.t + 1));
+        for (int64_t k = cnt[i]; k < cnt[i + 1] && rc == 0; ++k) {
+            const int64_t c = kid[k];
+            rc = nc_add(&hat, &msg[c], &tmp);
+            nc_free(&msg[c]);
+            if (rc == 0) {
+                nc_plf sw = hat;
+                hat = tmp;
+                tmp = sw;
+            }
+        }
+        if (rc) break;
+        mb = hat.t > mb ? hat.t : mb;
+        if (parent[i] < 0) {
+            double *v = (double *)malloc(sizeof(double) * (size_t)(hat.t > 0 ? hat.t : 1));
+            if (!v) {
+                rc = -2;
+                break;
+            }
+            nc_values(&hat, v);
+            int64_t pm = 0;
+            for (int64_t p = 1; p < hat.t; ++p)
+                if (v[p] < v[pm]) pm = p;
+            x[i] = hat.t > 0 ? hat.l[pm] : 0.0;
+            free(v);
+            continue;
+        }
+        if (!(w[i] >= 0.0) || !(C[i] > 0.0)) {
+            rc = -1;
+            break;
+        }
+        off[6 * i] = iv1.n;
+        rc = nc_dt_f1(&hat, w[i], &m1, &iv1);
+        off[6 * i + 1] = iv1.n;
+        off[6 * i + 2] = iv2.n;
+        if (rc == 0) rc = nc_dt_f2(&m1, w[i], &m2, &iv2, &t1, &t2);
+        off[6 * i + 3] = iv2.n;
+        off[6 * i + 4] = iv3.n;
+        if (rc == 0 && isfinite(C[i])) {
+            rc = nc_trunc(&m2, C[i], &msg[i], &iv3);
+        } else if (rc == 0) {
+            rc = nc_reserve(&msg[i], m2.t);
+            if (rc == 0) {
+                msg[i].t = m2.t;
+                memcpy(msg[i].l, m2.l, sizeof(double) * (size_t)m2.t);
+                memcpy(msg[i].s, m2.s, sizeof(double) * (size_t)(m2.t + 1));
+            }
+        }
+        off[6 * i + 5] = iv3.n;
+        if (rc == 0) mb = msg[i].t > mb ? msg[i].t : mb;
+    }
+    if (rc == 0) {
+        for (int64_t i = n - 1; i >= 0; --i) {
+            if (parent[i] < 0) continue;
+            double y = x[parent[i]];
+            y = nc_apply(&iv3, off[6 * i + 4], off[6 * i + 5], y);
+            y = nc_apply(&iv2, off[6 * i + 2], off[6 * i + 3], y);
+            y = nc_apply(&iv1, off[6 * i], off[6 * i + 1], y);
+            x[i] = y;
+        }
+    }
+    if (max_bp) *max_bp = mb;
+    for (int64_t i = 0; msg && i < n; ++i) nc_free(&msg[i]);
+    free(msg);
+    free(off);
+    free(cnt);
+    free(kid);
+    nc_free(&hat);
+    nc_free(&tmp);
+    nc_free(&f);
+    nc_free(&m1);
+    nc_free(&m2);
+    nc_free(&t1);
+    nc_free(&t2);
+    free(iv1.a); free(iv1.b); free(iv1.to);
+    free(iv2.a); free(iv2.b); free(iv2.to);
+    free(iv3.a); free(iv3.b); free(iv3.to);
+    return rc;
+}
+
+double orc_nc_tree_energy(int64_t n, const int64_t *parent, const int64_t *uoff, const double *ulam,
+                          const double *uslope, const double *w, const double *C, const double *x)
+{
+    double e = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        e += nc_unary_val(i, uoff, ulam, uslope, x[i]);
+        if (parent[i] >= 0) {
+            const double d = w[i] * fabs(x[parent[i]] - x[i]);
+            e += (isfinite(C[i]) && C[i] < d) ? C[i] : d;
+        }
+    }
+    return e;
+}
+
+/* Brute force for tiny forests (n <= 5), independent of the message passing:
+ * vertex candidates b + sum of offsets in {0, +-C_e/w_e} over the edges of the
+ * tree path between a breakpoint's node and each node, then an exact min-sum
+ * pass over the candidates, children before parents. */
+int orc_nc_tree_brute(int64_t n, const int64_t *parent, const int64_t *uoff, const double *ulam,
+                      const double *uslope, const double *w, const double *C, double *emin)
+{
+    if (n < 1 || n > 5) return -1;
+    enum { MAXC = 16384 };
+    static double cand[MAXC];
+    int64_t nc = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t k = uoff[j]; k < uoff[j + 1]; ++k) {
+            for (int64_t i = 0; i < n; ++i) {
+                /* edges on the path i .. j: climb both to the common ancestor */
+                int64_t path[8], m = 0, a = i, b = j;
+                int ok = 1;
+                while (a != b) {
+                    if (a < b) {  /* the lower index is deeper (children before parents) */
+                        if (parent[a] < 0) { ok = 0; break; }
+                        path[m++] = a;
+                        a = parent[a];
+                    } else {
+                        if (parent[b] < 0) { ok = 0; break; }
+                        path[m++] = b;
+                        b = parent[b];
+                    }
+                }
+                if (!ok) continue;  /* different trees */
+                int64_t combos = 1;
+                for (int64_t q = 0; q < m; ++q) combos *= 3;
+                for (int64_t cmb = 0; cmb < combos; ++cmb) {
+                    double z = ulam[k];
+                    int64_t r = cmb;
+                    int fine = 1;
+                    for (int64_t q = 0; q < m; ++q) {
+                        const int d = (int)(r % 3) - 1;
+                        r /= 3;
+                        if (d != 0) {
+                            const int64_t e = path[q];
+                            if (!isfinite(C[e]) || !(w[e] > 0.0)) {
+                                fine = 0;
+                                break;
+                            }
+                            z += d * C[e] / w[e];
+                        }
+                    }
+                    if (fine && nc < MAXC) cand[nc++] = z;
+                }
+            }
+        }
+    }
+    double *cost = (double *)malloc(sizeof(double) * (size_t)(nc * n));
+    if (!cost) return -2;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t a = 0; a < nc; ++a) cost[i * nc + a] = nc_unary_val(i, uoff, ulam, uslope, cand[a]);
+    double total = 0.0;
+    for (int64_t i = 0; i < n; ++i) {  /* children are complete before their parent */
+        if (parent[i] < 0) {
+            double best = INFINITY;
+            for (int64_t a = 0; a < nc; ++a) best = cost[i * nc + a] < best ? cost[i * nc + a] : best;
+            total += best;
+            continue;
+        }
+        const int64_t p = parent[i];
+        for (int64_t a = 0; a < nc; ++a) {
+            double best = INFINITY;
+            for (int64_t b = 0; b < nc; ++b) {
+                double d = w[i] * fabs(cand[a] - cand[b]);
+                if (isfinite(C[i]) && C[i] < d) d = C[i];
+                const double v = cost[i * nc + b] + d;
+                best = v < best ? v : best;
+            }
+            cost[p * nc + a] += best;
+        }
+    }
+    free(cost);
+    *emin = total;
+    return 0;
+}

@@ -175,3 +175,72 @@ def test_lemma2_no_growth_without_truncation():
         w = g.uniform(0, 2, n - 1)
         _, mb = oracle.nc_chain(uoff, ulam, usl, w, np.full(n - 1, np.inf))
         assert mb <= uoff[-1], (mb, uoff[-1])
+
+
+def _rand_forest(g, n):
+    """A random numbering with children before parents: node i's parent is a
+    random later node, or none (a root) with probability 0.15."""
+    par = np.full(n, -1, dtype=np.int64)
+    for i in range(n - 1):
+        if g.random() > 0.15:
+            par[i] = int(g.integers(i + 1, n))
+    return par
+
+
+@pytest.mark.parametrize("truncated", [False, True])
+def test_tree_reaches_the_exact_minimum(truncated):
+    g = np.random.default_rng(21 if truncated else 22)
+    for _ in range(600):
+        n = int(g.integers(1, 6))
+        par = _rand_forest(g, n)
+        uoff, ulam, usl = _rand_unaries(g, n)
+        w = g.uniform(0, 2, n)
+        C = g.uniform(0.1, 3, n) if truncated else np.full(n, np.inf)
+        x, _ = oracle.nc_tree(par, uoff, ulam, usl, w, C)
+        e = oracle.nc_tree_energy(par, uoff, ulam, usl, w, C, x)
+        eb = oracle.nc_tree_brute(par, uoff, ulam, usl, w, C)
+        assert abs(e - eb) <= 1e-9 * (1 + abs(eb)), (n, par, e, eb)
+
+
+def test_tree_chain_case_and_relabelling():
+    g = np.random.default_rng(23)
+    for _ in range(60):
+        n = int(g.integers(2, 60))
+        uoff, ulam, usl = _rand_unaries(g, n, tmax=4)
+        w = g.uniform(0, 2, n)
+        C = np.where(g.random(n) < 0.5, np.inf, g.uniform(0.2, 3, n))
+        # a chain as a tree (parent = i + 1): the chain solver's energy
+        par = np.arange(1, n + 1, dtype=np.int64)
+        par[-1] = -1
+        xt, _ = oracle.nc_tree(par, uoff, ulam, usl, w, C)
+        xc, _ = oracle.nc_chain(uoff, ulam, usl, w[:-1], C[:-1])
+        et = oracle.nc_tree_energy(par, uoff, ulam, usl, w, C, xt)
+        assert abs(et - oracle.nc_energy(uoff, ulam, usl, w[:-1], C[:-1], xc)) <= 1e-9 * (1 + abs(et))
+        # a random forest renumbered by another children-before-parents order
+        par = _rand_forest(g, n)
+        x1, _ = oracle.nc_tree(par, uoff, ulam, usl, w, C)
+        e1 = oracle.nc_tree_energy(par, uoff, ulam, usl, w, C, x1)
+        # new order: a topological order with random tie-breaks (children first)
+        remaining = {i: 0 for i in range(n)}
+        for i in range(n):
+            if par[i] >= 0:
+                remaining[int(par[i])] += 1
+        ready = [i for i in range(n) if remaining[i] == 0]
+        order = []
+        while ready:
+            k = ready.pop(int(g.integers(0, len(ready))))
+            order.append(k)
+            if par[k] >= 0:
+                remaining[int(par[k])] -= 1
+                if remaining[int(par[k])] == 0:
+                    ready.append(int(par[k]))
+        pos = np.empty(n, dtype=np.int64)
+        pos[order] = np.arange(n)
+        par2 = np.array([pos[par[k]] if par[k] >= 0 else -1 for k in order], dtype=np.int64)
+        ts = np.diff(uoff)[order]
+        uoff2 = np.concatenate([[0], np.cumsum(ts)]).astype(np.int64)
+        ul2 = np.concatenate([ulam[uoff[k]:uoff[k + 1]] for k in order])
+        us2 = np.concatenate([usl[uoff[k] + k:uoff[k + 1] + k + 1] for k in order])
+        x2, _ = oracle.nc_tree(par2, uoff2, ul2, us2, w[order], C[order])
+        e2 = oracle.nc_tree_energy(par2, uoff2, ul2, us2, w[order], C[order], x2)
+        assert abs(e1 - e2) <= 1e-9 * (1 + abs(e1))
