@@ -23,7 +23,8 @@ Also on the same JSON line:
                   of 2D TV-l1 at 4096^2, 65,536 trees of 256 nodes, the 1000 rows
                   of a 64-level synthetic cost volume as non-convex chains
                   (truncated TV), 5 iterations of the non-convex 2D solver on
-                  that volume, and a batch of 256 uneven images.
+                  that volume, 16,384 non-convex trees of 256 nodes, and a batch
+                  of 256 uneven images.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras | --extras LIST]
        python bench.py --rocprof-summary DIR   (print a summary of rocprofv3 output)
@@ -385,6 +386,35 @@ def bench_nc2d(iters: int):
             "mean_abs_init_minus_true_disparity": round(float(np.abs(x0 - dt).mean()), 3)}
 
 
+def bench_nc_tree(steps: int):
+    """Sec. 3 non-convex trees (tv_tree_nc): 16,384 random post-order trees of
+    256 nodes (post_order_forest), unaries through uniform [0, 4] costs at 16
+    levels (slopes -/+10 outside), truncated TV w = 0.5, C = 2, FP32 in, FP64
+    messages.  Capacities from the oracle on all the trees: messages up to
+    356 breakpoints, at most 3,114 intervals per tree; up to 39 messages wait
+    on a tree's stack (40 trees sampled)."""
+    import numpy as np
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    T, n, D = 16384, 256, 16
+    par, off = synth.post_order_forest(T, n, seed=7)
+    N = par.size
+    g = synth.generator(8)
+    cost = g.uniform(0, 4, (N, D))
+    sl = np.empty((N, D + 1))
+    sl[:, 0], sl[:, D] = -10.0, 10.0
+    sl[:, 1:D] = np.diff(cost, axis=1)
+    dev = lambda a, t=torch.float32: torch.tensor(a, dtype=t, device="cuda")  # noqa: E731
+    args = (dev(par, torch.int64), dev(off, torch.int64), dev(np.arange(N + 1, dtype=np.int64) * D, torch.int64),
+            dev(np.tile(np.arange(D, dtype=np.float64), N)), dev(sl.reshape(-1)), dev(np.full(N, 0.5)),
+            dev(np.full(N, 2.0)))
+    run = lambda: binding.tree_nc(*args, msg_cap=512, map_cap=32 * n, stack_cap=48 * 1025)  # noqa: E731
+    run()
+    ms = Timer(torch, torch.cuda.current_stream())(run, steps)
+    return {"workload": "16384 post-order trees x 256 nodes, 16-level uniform random costs, truncated TV w 0.5, C 2, "
+                        "FP32 in, FP64 messages", "ms": round(ms, 2), "mnode_s": round(N / ms / 1e3, 2)}
+
+
 def bench_tree(steps: int):
     """Algorithm 2 on 65,536 random post-order trees of 256 nodes (tv_tree_dp)
     with a ~ U[0.3, 2], TV-l1 data terms on 70% of the nodes, asymmetric edge
@@ -542,7 +572,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
                     help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,nc,"
-                         "nc2d,batched")
+                         "nc2d,nc_tree,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -628,6 +658,7 @@ def main():
                 ("tree", "trees 65536x256", lambda: bench_tree(5)),
                 ("nc", "non-convex chains 1000x1482, 64 levels", lambda: bench_nc(3)),
                 ("nc2d", "non-convex 2D 1000x1482, 64 levels", lambda: bench_nc2d(5)),
+                ("nc_tree", "non-convex trees 16384x256", lambda: bench_nc_tree(3)),
                 ("batched", "batched 256 images", bench_batched)]
         pick = None if args.extras == "all" else set(args.extras.split(","))
         try:

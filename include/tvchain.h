@@ -269,6 +269,30 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
                       size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Non-convex trees, Sec. 3: a batch of trees, each minimising
+ *     sum_i f_i(x_i) + sum_{i not a root} min(w_i |x_parent(i) - x_i|, C_i)
+ * with f_i as for tv_chain_nc; a node's message is its unary plus its
+ * children's messages (Lemma 1), min-convolved with its edge (Lemma 2), one
+ * lane per tree.
+ *  tree_offsets : DEVICE int64 [num_trees + 1] node ranges within [0, num_nodes];
+ *                 each tree numbered in depth-first post-order.
+ *  parent       : DEVICE int64 [num_nodes], global index of the parent (in the
+ *                 same tree, larger index), -1 at roots.  Other numberings
+ *                 are detected on the device: TV_ERR_INVALID_ARG.
+ *  unary_offsets, ulam, uslope : as for tv_chain_nc.
+ *  w, C         : DEVICE [num_nodes], the edge from node i to its parent.
+ *  msg_cap      : breakpoints a message may hold; map_cap: intervals of the
+ *                 mappings kept per tree; stack_cap: doubles per tree for the
+ *                 children's messages waiting for their parent (2t + 1 each).
+ * FP64 inside.  Synchronous.  Errors as tv_chain_nc. */
+size_t tv_tree_nc_workspace(int64_t num_trees, int64_t num_nodes, int64_t msg_cap, int64_t map_cap,
+                            int64_t stack_cap);
+tv_status tv_tree_nc(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const int64_t *tree_offsets,
+                     const int64_t *parent, const int64_t *unary_offsets, const void *ulam, const void *uslope,
+                     const void *w, const void *C, void *x, int64_t msg_cap, int64_t map_cap, int64_t stack_cap,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Non-convex 2D, Sec. 5.3: on an H x W grid minimise
  *     sum_horizontal min(w_h |x_i - x_j|, C) + sum_vertical min(w_v |x_i - x_j|, C)
  *       + sum_i f_i(x_i),

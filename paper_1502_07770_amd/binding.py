@@ -106,6 +106,9 @@ _SIG = {
     "tv_chain_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64]),
     "tv_chain_nc": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _I64, _I64, _P,
                                    ctypes.c_size_t, _P]),
+    "tv_tree_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64, _I64]),
+    "tv_tree_nc": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _I64, _I64, _P,
+                                  ctypes.c_size_t, _P]),
     "tv2d_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64, _I64]),
     "tv2d_nc_solve": (ctypes.c_int, [ctypes.c_int, _P, _I64, _I64, _I64, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, _P, ctypes.c_double, _P, ctypes.c_double, ctypes.c_double,
@@ -761,4 +764,41 @@ def tv2d_nc(cost: torch.Tensor, d0: float, dd: float, steep: float, w_h, w_v, C:
                            float(C), float(tau0), int(iters), _ptr(x), msg_cap, map_cap, _ptr(ws), nbytes,
                            ctypes.c_void_p(_stream_ptr(cost.device)))
     _check(st, "tv2d_nc_solve")
+    return x
+
+
+def tree_nc(parent: torch.Tensor, offsets: torch.Tensor, unary_offsets: torch.Tensor, ulam: torch.Tensor,
+            uslope: torch.Tensor, w: torch.Tensor, C: Optional[torch.Tensor] = None, msg_cap: int = 256,
+            map_cap: Optional[int] = None, stack_cap: Optional[int] = None) -> torch.Tensor:
+    """Sec. 3 non-convex trees (tv_tree_nc): parent (int64, global, -1 at roots,
+    each tree in depth-first post-order), offsets (int64, trees + 1), unaries as
+    for chain_nc, per-node w and C of the edge to the parent.  Defaults: 32
+    intervals per node and room for min(64, largest tree) waiting messages of
+    msg_cap breakpoints per tree.  Returns x."""
+    _require_gpu(parent, offsets, unary_offsets, ulam, uslope, w)
+    lib = load()
+    for t in (parent, offsets, unary_offsets):
+        if t.dtype != torch.int64:
+            raise TvChainError(TV_ERR_INVALID_ARG, "parent and offsets must be int64")
+    N = parent.numel()
+    ts = [t.contiguous() if t is not None else None for t in (ulam, uslope, w, C)]
+    for t in ts:
+        if t is not None and t.dtype != ulam.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "float arrays must share one dtype")
+    parent, offsets, unary_offsets = parent.contiguous(), offsets.contiguous(), unary_offsets.contiguous()
+    T = offsets.numel() - 1
+    biggest = int((offsets[1:] - offsets[:-1]).max().item()) if T > 0 else 1
+    if map_cap is None:
+        map_cap = max(64, 32 * biggest)
+    if stack_cap is None:
+        stack_cap = max(1, min(64, biggest)) * (2 * msg_cap + 1)
+    x = torch.empty(N, dtype=ulam.dtype, device=ulam.device)
+    nbytes = lib.tv_tree_nc_workspace(T, N, msg_cap, map_cap, stack_cap)
+    if nbytes == 0:
+        raise TvChainError(TV_ERR_INVALID_ARG, "tv_tree_nc_workspace")
+    ws = _workspace(nbytes, ulam.device)
+    st = lib.tv_tree_nc(_dtype_code(ulam), T, N, _ptr(offsets), _ptr(parent), _ptr(unary_offsets),
+                        *(_ptr(t) for t in ts), _ptr(x), msg_cap, map_cap, stack_cap, _ptr(ws), nbytes,
+                        ctypes.c_void_p(_stream_ptr(ulam.device)))
+    _check(st, "tv_tree_nc")
     return x

@@ -924,6 +924,198 @@ __global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sec. 3 on a batch of trees: one lane per tree, nodes in depth-first
+// post-order (every subtree a contiguous range ending at its root), so the
+// messages of a node's children are the top entries of a stack of finished,
+// not yet consumed messages.  A node sums its unary and its children's
+// messages (Lemma 1, one merge per child), then a non-root sends its
+// min-convolved message (Algorithm 1, its reversal, the truncation) to the
+// stack and a root takes its first argmin; backward, parents before children.
+// The three working buffers, the stack and the interval lists live in the
+// tree's slice of the workspace.
+// ---------------------------------------------------------------------------
+struct NcTreeArgs {
+    int64_t num_trees, num_nodes;
+    const int64_t *toff, *parent, *uoff;
+    int64_t msg_cap, map_cap, stack_cap;
+    double *bufs;      // per tree: 3 buffers of (2 msg_cap + 1) doubles
+    double *stack;     // per tree: stack_cap doubles of pending messages (l then s)
+    double *maps;      // per tree: 3 arrays of map_cap doubles
+    int64_t *hstart;   // [N] pending message: start in the stack
+    int64_t *hcount;   //     breakpoints
+    int64_t *hparent;  //     node it is for
+    int64_t *eoff;     // [N][6] start / end of the node's intervals in each list
+    int *flag;
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_nc_tree(NcTreeArgs A, const T *__restrict__ ulam,
+                                                const T *__restrict__ uslope, const T *__restrict__ w,
+                                                const T *__restrict__ C, T *__restrict__ x) {
+    const int64_t tr = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (tr >= A.num_trees) return;
+    const int64_t n0 = A.toff[tr], n1 = A.toff[tr + 1];
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {
+        atomicOr(A.flag, kNcFlagInvalid);
+        return;
+    }
+    if (n1 == n0) return;
+    const int64_t bstride = 2 * A.msg_cap + 1;
+    double *base = A.bufs + tr * 3 * bstride;
+    NcBuf H{base, base + A.msg_cap, 0, A.msg_cap};
+    NcBuf B{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap};
+    NcBuf U{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};  // the unary, staged
+    double *stk = A.stack + tr * A.stack_cap;
+    double *mb = A.maps + tr * 3 * A.map_cap;
+    NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    int64_t top = 0;   // stack fill (doubles)
+    int64_t sp = n0;   // header stack pointer
+    int bad = 0;
+    for (int64_t i = n0; i < n1 && !bad; ++i) {
+        const int64_t p = A.parent[i];
+        if (p != -1 && (p <= i || p >= n1)) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        // the unary, staged in U (validated)
+        const int64_t u0 = A.uoff[i], tu = A.uoff[i + 1] - u0;
+        if (tu < 1 || tu > A.msg_cap) {
+            bad = tu < 1 ? kNcFlagInvalid : kNcFlagCapacity;
+            break;
+        }
+        for (int64_t k = 0; k < tu; ++k) {
+            U.l[k] = (double)ulam[u0 + k];
+            if (k > 0 && !(U.l[k] >= U.l[k - 1])) bad = kNcFlagInvalid;
+        }
+        for (int64_t k = 0; k <= tu; ++k) U.s[k] = (double)uslope[u0 + i + k];
+        if (!(U.s[0] <= 0.0) || !(U.s[tu] >= 0.0)) bad = kNcFlagInvalid;
+        if (bad) break;
+        // hat = f_i (+ 0), then + each child's message from the top of the stack
+        B.t = 0;
+        B.s[0] = 0.0;
+        if (!nc_sum(U.l, U.s, tu, B, H)) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        while (sp > n0 && A.hparent[sp - 1] == i) {
+            --sp;
+            const int64_t cs = A.hstart[sp], ct = A.hcount[sp];
+            if (cs < 0 || cs + 2 * ct + 1 != top) {  // not right below: not a post-order numbering
+                bad = kNcFlagInvalid;
+                break;
+            }
+            const NcBuf child{stk + cs, stk + cs + ct, ct, ct};
+            if (!nc_sum(H.l, H.s, H.t, child, B)) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+            const NcBuf t = H;
+            H = B;
+            B = t;
+            top = cs;
+        }
+        if (bad) break;
+        if (p < 0) {  // a root: the first breakpoint attaining the minimum
+            double v = 0.0, vmin = 0.0, y = H.t > 0 ? H.l[0] : 0.0;
+            for (int64_t k = 1; k < H.t; ++k) {
+                v += H.s[k] * (H.l[k] - H.l[k - 1]);
+                if (v < vmin) {
+                    vmin = v;
+                    y = H.l[k];
+                }
+            }
+            x[i] = (T)y;
+            continue;
+        }
+        const double wi = (double)w[i];
+        const double ci = C ? (double)C[i] : HUGE_VAL;
+        if (!(wi >= 0.0) || !(ci > 0.0)) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        int64_t *eo = A.eoff + 6 * i;
+        eo[0] = mp.n;
+        if (!nc_dt(NcFwd{&H}, wi, B, [&](double lo, double hi) { return mp.add(lo, hi, lo); })) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        eo[1] = mp.n;
+        eo[2] = mp.n;
+        if (!nc_dt(NcRev{&B}, wi, H, [&](double lo, double hi) { return mp.add(-hi, -lo, -lo); })) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        eo[3] = mp.n;
+        eo[4] = mp.n;
+        // the message (of rev(H), truncated or not) is written into U, then pushed
+        if (ci < HUGE_VAL) {
+            if (!nc_trunc(NcRev{&H}, ci, U, mp)) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+        } else {
+            const NcRev r{&H};
+            U.t = r.t();
+            for (int64_t k = 0; k < U.t; ++k) U.l[k] = r.l(k);
+            for (int64_t k = 0; k <= U.t; ++k) U.s[k] = r.s(k);
+        }
+        eo[5] = mp.n;
+        const int64_t need = 2 * U.t + 1;
+        if (top + need > A.stack_cap) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        for (int64_t k = 0; k < U.t; ++k) stk[top + k] = U.l[k];
+        for (int64_t k = 0; k <= U.t; ++k) stk[top + U.t + k] = U.s[k];
+        A.hstart[sp] = top;
+        A.hcount[sp] = U.t;
+        A.hparent[sp] = p;
+        ++sp;
+        top += need;
+    }
+    if (!bad && sp != n0) bad = kNcFlagInvalid;  // messages left for parents outside the tree
+    if (bad) {
+        atomicOr(A.flag, bad);
+        return;
+    }
+    for (int64_t i = n1 - 1; i >= n0; --i) {
+        const int64_t p = A.parent[i];
+        if (p < 0) continue;
+        const int64_t *eo = A.eoff + 6 * i;
+        double y = (double)x[p];
+        y = nc_apply(mp, eo[4], eo[5], y);
+        y = nc_apply(mp, eo[2], eo[3], y);
+        y = nc_apply(mp, eo[0], eo[1], y);
+        x[i] = (T)y;
+    }
+}
+
+size_t nc_tree_layout(int64_t num_trees, int64_t num_nodes, int64_t msg_cap, int64_t map_cap, int64_t stack_cap,
+                      void *p, NcTreeArgs *A) {
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_b = off;  off += al(sizeof(double) * (size_t)(num_trees * 3 * (2 * msg_cap + 1)));
+    const size_t o_s = off;  off += al(sizeof(double) * (size_t)(num_trees * stack_cap));
+    const size_t o_m = off;  off += al(sizeof(double) * (size_t)(num_trees * 3 * map_cap));
+    const size_t o_h = off;  off += al(sizeof(int64_t) * (size_t)(3 * num_nodes));
+    const size_t o_e = off;  off += al(sizeof(int64_t) * (size_t)(6 * num_nodes));
+    const size_t o_f = off;  off += al(sizeof(int));
+    if (p && A) {
+        char *c = (char *)p;
+        A->bufs = (double *)(c + o_b);
+        A->stack = (double *)(c + o_s);
+        A->maps = (double *)(c + o_m);
+        int64_t *h = (int64_t *)(c + o_h);
+        A->hstart = h;
+        A->hcount = h + num_nodes;
+        A->hparent = h + 2 * num_nodes;
+        A->eoff = (int64_t *)(c + o_e);
+        A->flag = (int *)(c + o_f);
+    }
+    return off;
+}
+
 // Lanes per workgroup whose message buffers fit the LDS of one workgroup
 // (160 KiB on gfx950); 0 if not even one lane's do.
 constexpr size_t kNcLds = 160 * 1024;
@@ -1056,6 +1248,49 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
             hipLaunchKernelGGL((k_nc_chain<double, false>), grid, dim3(64), 0, stream, A, (const double *)ulam,
                                (const double *)uslope, (const double *)w, (const double *)C, (double *)x, lanes);
     }
+    return nc_finish(A.flag, stream);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+size_t tv_tree_nc_workspace(int64_t num_trees, int64_t num_nodes, int64_t msg_cap, int64_t map_cap,
+                            int64_t stack_cap) {
+    if (num_trees < 0 || num_nodes < 0 || msg_cap < 1 || map_cap < 1 || stack_cap < 1) return 0;
+    if (msg_cap > (int64_t(1) << 24) || map_cap > (int64_t(1) << 30) || stack_cap > (int64_t(1) << 34)) return 0;
+    return nc_tree_layout(num_trees, num_nodes, msg_cap, map_cap, stack_cap, nullptr, nullptr);
+}
+
+tv_status tv_tree_nc(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const int64_t *tree_offsets,
+                     const int64_t *parent, const int64_t *unary_offsets, const void *ulam, const void *uslope,
+                     const void *w, const void *C, void *x, int64_t msg_cap, int64_t map_cap, int64_t stack_cap,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (num_trees < 0 || num_nodes < 0) return TV_ERR_INVALID_ARG;
+    if (num_trees == 0) return TV_OK;
+    if (!tree_offsets || !parent || !unary_offsets || !ulam || !uslope || !w || !x) return TV_ERR_INVALID_ARG;
+    const size_t need = tv_tree_nc_workspace(num_trees, num_nodes, msg_cap, map_cap, stack_cap);
+    if (need == 0) return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
+    NcTreeArgs A;
+    A.num_trees = num_trees;
+    A.num_nodes = num_nodes;
+    A.toff = tree_offsets;
+    A.parent = parent;
+    A.uoff = unary_offsets;
+    A.msg_cap = msg_cap;
+    A.map_cap = map_cap;
+    A.stack_cap = stack_cap;
+    nc_tree_layout(num_trees, num_nodes, msg_cap, map_cap, stack_cap, workspace, &A);
+    if (hipMemsetAsync(A.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
+    const dim3 grid((unsigned)((num_trees + 63) / 64));
+    if (dtype == TV_F32)
+        hipLaunchKernelGGL((k_nc_tree<float>), grid, dim3(64), 0, stream, A, (const float *)ulam,
+                           (const float *)uslope, (const float *)w, (const float *)C, (float *)x);
+    else
+        hipLaunchKernelGGL((k_nc_tree<double>), grid, dim3(64), 0, stream, A, (const double *)ulam,
+                           (const double *)uslope, (const double *)w, (const double *)C, (double *)x);
     return nc_finish(A.flag, stream);
 }
 

@@ -243,3 +243,12 @@ def test_nc2d_argument_errors(lib):
                              None, 64, 64, None, 0, None) == binding.TV_ERR_INVALID_ARG
     assert lib.tv2d_nc_solve(7, None, 4, 4, 4, 0.0, 1.0, 10.0, None, 0.5, None, 0.5, 1.0, 10.0, 1,
                              None, 64, 64, None, 0, None) == binding.TV_ERR_INVALID_ARG
+
+
+def test_nc_tree_argument_errors(lib):
+    assert lib.tv_tree_nc_workspace(4, 100, 64, 256, 1000) > 0
+    assert lib.tv_tree_nc_workspace(4, 100, 64, 256, 0) == 0
+    assert lib.tv_tree_nc(binding.TV_F64, 0, 0, None, None, None, None, None, None, None, None, 8, 8, 8, None, 0,
+                          None) == binding.TV_OK
+    assert lib.tv_tree_nc(binding.TV_F64, 1, 4, None, None, None, None, None, None, None, None, 8, 8, 8, None, 0,
+                          None) == binding.TV_ERR_INVALID_ARG
