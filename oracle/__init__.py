@@ -110,6 +110,12 @@ def _load():
     lib.orc_nc_tree_energy.restype = D
     lib.orc_nc_tree_brute.argtypes = [I64, P, P, P, P, P, P, P]
     lib.orc_nc_tree_brute.restype = ctypes.c_int
+    lib.orc_ncg_chain.argtypes = [I64, P, P, P, P, P, P, P, P, P]
+    lib.orc_ncg_chain.restype = ctypes.c_int
+    lib.orc_ncg_energy.argtypes = [I64, P, P, P, P, P, P, P, P]
+    lib.orc_ncg_energy.restype = D
+    lib.orc_ncg_brute.argtypes = [I64, P, P, P, P, P, P, P, P, P]
+    lib.orc_ncg_brute.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -405,6 +411,55 @@ def nc_brute(uoff, ulam, uslope, w, C):
     rc = _load().orc_nc_brute(n, _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(w), _ptr(C), _ptr(x), ctypes.byref(e))
     if rc != 0:
         raise ValueError("orc_nc_brute: invalid input (%d)" % rc)
+    return float(e.value), x
+
+
+def _ncg_args(uoff, ulam, uslope, poff, alpha, C, side):
+    uoff = np.ascontiguousarray(uoff, dtype=np.int64)
+    n = uoff.size - 1
+    ulam, uslope = _f64(ulam), _f64(uslope)
+    if ulam.size != uoff[-1] or uslope.size != uoff[-1] + n:
+        raise ValueError("unary arrays do not match the offsets")
+    poff = np.ascontiguousarray(poff, dtype=np.int64)
+    alpha, C = _f64(alpha), _f64(C)
+    side = np.ascontiguousarray(side, dtype=np.int32)
+    if poff.size != n + 1 or not (alpha.size == C.size == side.size == poff[-1]):
+        raise ValueError("piece arrays do not match the offsets")
+    return n, uoff, ulam, uslope, poff, alpha, C, side
+
+
+def ncg_chain(uoff, ulam, uslope, poff, alpha, C, side):
+    """Sec. 3, Extensions (i), on a chain: unaries as for nc_chain; the
+    pairwise term of edge e is the minimum of its pieces k in
+    [poff[e], poff[e+1]), alpha[k] |z| + C[k] on the side side[k] (+1: z > 0,
+    -1: z < 0) of z = x_{e+1} - x_e, and 0 at z = 0.  Returns (x, largest
+    number of message breakpoints)."""
+    n, uoff, ulam, uslope, poff, alpha, C, side = _ncg_args(uoff, ulam, uslope, poff, alpha, C, side)
+    x = np.empty(n)
+    mb = ctypes.c_int64(0)
+    rc = _load().orc_ncg_chain(n, _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(poff), _ptr(alpha), _ptr(C),
+                               _ptr(side), _ptr(x), ctypes.byref(mb))
+    if rc != 0:
+        raise ValueError("orc_ncg_chain: invalid input (%d)" % rc)
+    return x, int(mb.value)
+
+
+def ncg_energy(uoff, ulam, uslope, poff, alpha, C, side, x) -> float:
+    n, uoff, ulam, uslope, poff, alpha, C, side = _ncg_args(uoff, ulam, uslope, poff, alpha, C, side)
+    x = _f64(x)
+    return float(_load().orc_ncg_energy(n, _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(poff), _ptr(alpha), _ptr(C),
+                                        _ptr(side), _ptr(x)))
+
+
+def ncg_brute(uoff, ulam, uslope, poff, alpha, C, side):
+    """Exact minimum energy and a minimiser for n <= 6 (unary breakpoints, Viterbi)."""
+    n, uoff, ulam, uslope, poff, alpha, C, side = _ncg_args(uoff, ulam, uslope, poff, alpha, C, side)
+    x = np.empty(n)
+    e = ctypes.c_double(0.0)
+    rc = _load().orc_ncg_brute(n, _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(poff), _ptr(alpha), _ptr(C),
+                               _ptr(side), _ptr(x), ctypes.byref(e))
+    if rc != 0:
+        raise ValueError("orc_ncg_brute: invalid input (%d)" % rc)
     return float(e.value), x
 
 

@@ -44,6 +44,14 @@
  *                          and the backward pass through the mappings pi.
  *   orc_nc_brute        -- exact minimum of the same energy on tiny chains
  *                          (n <= 5) by a Viterbi pass over vertex candidates.
+ *   orc_ncg_chain       -- Sec. 3, Extensions (i): the same chain with every
+ *                          pairwise term a minimum of one-sided linear pieces
+ *                          g(z) = alpha|z| + C on z > 0 or on z < 0 (concave,
+ *                          non-decreasing in |z| on each side, 0 at z = 0),
+ *                          applied one piece at a time by Prop. 2 with
+ *                          h (x) g = (h^alpha (x) g^alpha)^-alpha.
+ *   orc_ncg_brute       -- exact minimum of that energy on tiny chains (n <= 6)
+ *                          by a Viterbi pass over the unary breakpoints.
  *   orc_tv2d_l1         -- Sec. 5.2 TV-l1 by the same decomposition: the
  *                          primal-dual iteration eq. (pd) with the dual prox of
  *                          lambda TV_v on the columns (as for ROF) and the primal
@@ -1801,5 +1809,291 @@ int orc_nc_tree_brute(int64_t n, const int64_t *parent, const int64_t *uoff, con
     }
     free(cost);
     *emin = total;
+    return 0;
+}
+
+
+/* ========================================================================
+ * Sec. 3, Extensions (i): pairwise terms f_e(z) of z = x_{e+1} - x_e that are
+ * piecewise-linear, non-increasing and concave for z < 0, non-decreasing and
+ * concave for z > 0, with f_e(0) = 0.  Such an f_e is the minimum of pieces
+ * g(z) = alpha z + C on z > 0 (+inf on z < 0) and g(z) = alpha (-z) + C on
+ * z < 0 (+inf on z > 0), alpha >= 0, C >= 0, each with g(0) = 0 (truncated TV:
+ * (w, 0) and (0, C) on both sides; Potts: (0, C) on both sides).  f_e
+ * satisfies the triangle inequality, so by Prop. 2 the message is the
+ * consecutive min-convolution with the pieces in any order, and the mapping
+ * of the edge is the composition of the pieces' mappings.  A side without
+ * pieces makes f_e infinite there (a hard order constraint; no pieces at all:
+ * x_{e+1} = x_e).
+ *
+ * One right-side piece: with phi(x) = h(x) - alpha x (every slope minus
+ * alpha),
+ *   (h (x) g)(y) = alpha y + min( phi(y), min_{x <= y} phi(x) + C ),
+ * the minimiser being y where the first term is not larger and otherwise the
+ * first argmin of phi on (-inf, y] (min over x < y equals min over x <= y for
+ * continuous phi).  C = 0 gives Algorithm 1.  A left-side piece is the
+ * reversal of the right-side piece applied to the reversed function.
+ * ======================================================================== */
+
+/* One right-side piece (alpha, C) applied to h; its intervals go to iv.  At a
+ * point z of piece k (between l[k-1] and l[k], k >= 1) phi is linear, so the
+ * running minimum there is min(mn[k-1], phi(z)). */
+static int ncg_side(const nc_plf *h, double alpha, double C, nc_plf *out, nc_ivs *iv)
+{
+    const int64_t t = h->t;
+    out->t = 0;
+    if (nc_reserve(out, 2 * t + 2)) return -2;
+    out->s[0] = h->s[0];
+    if (t == 0) return 0; /* h constant (bounded below): phi non-increasing, no change */
+    double *ph = (double *)malloc(sizeof(double) * (size_t)t);
+    double *mn = (double *)malloc(sizeof(double) * (size_t)t);
+    double *am = (double *)malloc(sizeof(double) * (size_t)t);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)(2 * t + 1));
+    if (!ph || !mn || !am || !cp) {
+        free(ph); free(mn); free(am); free(cp);
+        return -2;
+    }
+    const double *l = h->l, *sl = h->s;
+    /* phi at the breakpoints (h(l[0]) = 0), running minimum and first argmin;
+     * on the left piece phi is non-increasing (s[0] <= 0 <= alpha), so the
+     * minimum up to l[0] is phi(l[0]) */
+    ph[0] = -alpha * l[0];
+    mn[0] = ph[0];
+    am[0] = l[0];
+    for (int64_t p = 1; p < t; ++p) {
+        ph[p] = ph[p - 1] + (sl[p] - alpha) * (l[p] - l[p - 1]);
+        mn[p] = mn[p - 1];
+        am[p] = am[p - 1];
+        if (ph[p] < mn[p]) {
+            mn[p] = ph[p];
+            am[p] = l[p];
+        }
+    }
+    /* kink candidates in order: the breakpoints, and in each piece k >= 1 the
+     * point where phi meets mn[k-1] + C */
+    int64_t nc = 0;
+    for (int64_t k = 1; k <= t; ++k) {
+        cp[nc++] = l[k - 1];
+        const double sg = sl[k] - alpha, L = l[k - 1];
+        const double R = k < t ? l[k] : INFINITY;
+        if (sg != 0.0) {
+            const double y1 = L + (mn[k - 1] + C - ph[k - 1]) / sg;
+            if (y1 > L && y1 < R) cp[nc++] = y1;
+        }
+    }
+    /* classify each segment between consecutive candidates at its midpoint
+     * (the last one, unbounded, one unit to the right of its start) */
+    double prev_slope = sl[0];
+    int in_run = 0;
+    double run_lo = 0.0, run_to = 0.0;
+    int rc = 0;
+    for (int64_t c = 0; c < nc && rc == 0; ++c) {
+        const double a = cp[c], b = c + 1 < nc ? cp[c + 1] : INFINITY;
+        if (!(b > a)) continue; /* empty segment */
+        const double z = isfinite(b) ? 0.5 * (a + b) : a + 1.0;
+        int64_t k = 1; /* the piece holding z */
+        while (k < t && z > l[k]) ++k;
+        const double sg = sl[k] - alpha;
+        const double phz = ph[k - 1] + sg * (z - l[k - 1]);
+        const double mz = phz < mn[k - 1] ? phz : mn[k - 1];
+        const int above = phz > mz + C;
+        const double slope = above ? alpha : sl[k];
+        if (slope != prev_slope) {
+            rc = nc_push(out, a, slope);
+            prev_slope = slope;
+        }
+        if (above && !in_run) {
+            in_run = 1;
+            run_lo = a;
+            run_to = am[k - 1];
+        } else if (!above && in_run) {
+            in_run = 0;
+            if (rc == 0) rc = nc_iv_add(iv, run_lo, a, run_to);
+        }
+    }
+    if (rc == 0 && in_run) rc = nc_iv_add(iv, run_lo, INFINITY, run_to);
+    free(ph); free(mn); free(am); free(cp);
+    return rc;
+}
+
+/* One piece on either side; a left-side piece through two reversals, its
+ * intervals mirrored back. */
+static int ncg_piece(const nc_plf *h, double alpha, double C, int side, nc_plf *out, nc_ivs *iv, nc_plf *t1,
+                     nc_plf *t2)
+{
+    if (side > 0) return ncg_side(h, alpha, C, out, iv);
+    const int64_t n0 = iv->n;
+    int rc = nc_rev(h, t1);
+    if (rc == 0) rc = ncg_side(t1, alpha, C, t2, iv);
+    if (rc == 0) rc = nc_rev(t2, out);
+    for (int64_t k = n0; rc == 0 && k < iv->n; ++k) {
+        const double a = iv->a[k];
+        iv->a[k] = -iv->b[k];
+        iv->b[k] = -a;
+        iv->to[k] = -iv->to[k];
+    }
+    return rc;
+}
+
+static int ncg_check_pieces(int64_t n, const int64_t *poff, const double *alpha, const double *C, const int32_t *side)
+{
+    if (poff[0] != 0) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (poff[i + 1] < poff[i]) return -1;
+    for (int64_t k = 0; k < poff[n]; ++k)
+        if (!(alpha[k] >= 0.0) || !isfinite(alpha[k]) || !(C[k] >= 0.0) || !isfinite(C[k]) ||
+            (side[k] != 1 && side[k] != -1))
+            return -1;
+    return 0;
+}
+
+/* The chain: unaries as for orc_nc_chain; the pieces of edge e (nodes e and
+ * e+1) are alpha, C, side [poff[e], poff[e+1]) (poff has n + 1 entries; the
+ * last node's pieces are ignored).  Returns 0, -1 for invalid input, -2 if out
+ * of memory; max_bp (optional) as for orc_nc_chain. */
+int orc_ncg_chain(int64_t n, const int64_t *uoff, const double *ulam, const double *uslope, const int64_t *poff,
+                  const double *alpha, const double *C, const int32_t *side, double *x, int64_t *max_bp)
+{
+    if (n < 1 || ncg_check_pieces(n, poff, alpha, C, side)) return -1;
+    nc_plf hat = {0, 0, NULL, NULL}, f = {0, 0, NULL, NULL}, a = {0, 0, NULL, NULL}, b = {0, 0, NULL, NULL},
+           t1 = {0, 0, NULL, NULL}, t2 = {0, 0, NULL, NULL};
+    nc_ivs iv = {0, 0, NULL, NULL, NULL};
+    const int64_t np = poff[n];
+    int64_t *pr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * np + 2)); /* per piece: its intervals */
+    int rc = pr ? 0 : -2;
+    int64_t mb = 0;
+    if (rc == 0) rc = nc_reserve(&a, 1);
+    a.t = 0;
+    if (rc == 0) a.s[0] = 0.0; /* the incoming message of node 0: zero */
+    for (int64_t i = 0; i < n && rc == 0; ++i) {
+        rc = nc_unary(i, uoff, ulam, uslope, &f);
+        if (rc == 0) rc = nc_add(&f, &a, &hat);
+        if (rc) break;
+        mb = hat.t > mb ? hat.t : mb;
+        if (i == n - 1) break;
+        /* the message: hat, then each piece in turn */
+        rc = nc_reserve(&a, hat.t);
+        if (rc) break;
+        a.t = hat.t;
+        memcpy(a.l, hat.l, sizeof(double) * (size_t)hat.t);
+        memcpy(a.s, hat.s, sizeof(double) * (size_t)(hat.t + 1));
+        for (int64_t k = poff[i]; k < poff[i + 1] && rc == 0; ++k) {
+            pr[2 * k] = iv.n;
+            rc = ncg_piece(&a, alpha[k], C[k], side[k], &b, &iv, &t1, &t2);
+            pr[2 * k + 1] = iv.n;
+            if (rc == 0) {
+                nc_plf sw = a;
+                a = b;
+                b = sw;
+                mb = a.t > mb ? a.t : mb;
+            }
+        }
+    }
+    if (rc == 0) {
+        double *v = (double *)malloc(sizeof(double) * (size_t)(hat.t > 0 ? hat.t : 1));
+        if (!v) {
+            rc = -2;
+        } else {
+            nc_values(&hat, v);
+            int64_t pm = 0;
+            for (int64_t p = 1; p < hat.t; ++p)
+                if (v[p] < v[pm]) pm = p;
+            double y = hat.t > 0 ? hat.l[pm] : 0.0;
+            x[n - 1] = y;
+            for (int64_t i = n - 2; i >= 0; --i) {
+                /* pi = pi^1 o ... o pi^m: the last piece's mapping first */
+                for (int64_t k = poff[i + 1] - 1; k >= poff[i]; --k) y = nc_apply(&iv, pr[2 * k], pr[2 * k + 1], y);
+                x[i] = y;
+            }
+            free(v);
+        }
+    }
+    if (max_bp) *max_bp = mb;
+    nc_free(&hat);
+    nc_free(&f);
+    nc_free(&a);
+    nc_free(&b);
+    nc_free(&t1);
+    nc_free(&t2);
+    free(iv.a); free(iv.b); free(iv.to);
+    free(pr);
+    return rc;
+}
+
+/* f_e(z): 0 at z = 0, else the least piece on z's side (+inf without one). */
+static double ncg_pair(const int64_t *poff, const double *alpha, const double *C, const int32_t *side, int64_t e,
+                       double z)
+{
+    if (z == 0.0) return 0.0;
+    const int sd = z > 0.0 ? 1 : -1;
+    double best = INFINITY;
+    for (int64_t k = poff[e]; k < poff[e + 1]; ++k)
+        if (side[k] == sd) {
+            const double v = alpha[k] * fabs(z) + C[k];
+            if (v < best) best = v;
+        }
+    return best;
+}
+
+double orc_ncg_energy(int64_t n, const int64_t *uoff, const double *ulam, const double *uslope, const int64_t *poff,
+                      const double *alpha, const double *C, const int32_t *side, const double *x)
+{
+    double e = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        e += nc_unary_val(i, uoff, ulam, uslope, x[i]);
+        if (i + 1 < n) e += ncg_pair(poff, alpha, C, side, i, x[i + 1] - x[i]);
+    }
+    return e;
+}
+
+/* Exact minimum for n <= 6.  Fixing, per edge, "equal", one right-side piece
+ * or one left-side piece (with its closed sign constraint), and per node one
+ * linear piece of its unary, leaves a linear program whose feasible set has
+ * vertices (every coordinate is bounded on at least one side); at a vertex
+ * each run of equal values holds a unary breakpoint.  The energy is the
+ * minimum over these choices and never exceeds any of them, so the minimum
+ * over x with every x_i a unary breakpoint is exact. */
+int orc_ncg_brute(int64_t n, const int64_t *uoff, const double *ulam, const double *uslope, const int64_t *poff,
+                  const double *alpha, const double *C, const int32_t *side, double *xbest, double *emin)
+{
+    if (n < 1 || n > 6 || ncg_check_pieces(n, poff, alpha, C, side)) return -1;
+    const int64_t nc = uoff[n] - uoff[0];
+    const double *cand = ulam + uoff[0];
+    double *cost = (double *)malloc(sizeof(double) * (size_t)(nc * n));
+    int64_t *arg = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc * n));
+    if (!cost || !arg) {
+        free(cost);
+        free(arg);
+        return -2;
+    }
+    for (int64_t a = 0; a < nc; ++a) {
+        cost[a] = nc_unary_val(0, uoff, ulam, uslope, cand[a]);
+        arg[a] = -1;
+    }
+    for (int64_t i = 1; i < n; ++i) {
+        for (int64_t b = 0; b < nc; ++b) {
+            double best = INFINITY;
+            int64_t ab = 0;
+            for (int64_t a = 0; a < nc; ++a) {
+                const double v = cost[(i - 1) * nc + a] + ncg_pair(poff, alpha, C, side, i - 1, cand[b] - cand[a]);
+                if (v < best) {
+                    best = v;
+                    ab = a;
+                }
+            }
+            cost[i * nc + b] = best + nc_unary_val(i, uoff, ulam, uslope, cand[b]);
+            arg[i * nc + b] = ab;
+        }
+    }
+    int64_t bb = 0;
+    for (int64_t b = 1; b < nc; ++b)
+        if (cost[(n - 1) * nc + b] < cost[(n - 1) * nc + bb]) bb = b;
+    *emin = cost[(n - 1) * nc + bb];
+    for (int64_t i = n - 1; i >= 0; --i) {
+        xbest[i] = cand[bb];
+        bb = arg[i * nc + bb];
+    }
+    free(cost);
+    free(arg);
     return 0;
 }

@@ -952,8 +952,9 @@ struct NcTreeArgs {
 template <typename T>
 __global__ __launch_bounds__(64) void k_nc_tree(NcTreeArgs A, const T *__restrict__ ulam,
                                                 const T *__restrict__ uslope, const T *__restrict__ w,
-                                                const T *__restrict__ C, T *__restrict__ x) {
-    const int64_t tr = (int64_t)blockIdx.x * 64 + threadIdx.x;
+                                                const T *__restrict__ C, T *__restrict__ x, int lanes) {
+    if ((int)threadIdx.x >= lanes) return;
+    const int64_t tr = (int64_t)blockIdx.x * lanes + threadIdx.x;
     if (tr >= A.num_trees) return;
     const int64_t n0 = A.toff[tr], n1 = A.toff[tr + 1];
     if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {
@@ -1267,7 +1268,7 @@ tv_status tv_tree_nc(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
                      const void *w, const void *C, void *x, int64_t msg_cap, int64_t map_cap, int64_t stack_cap,
                      void *workspace, size_t workspace_bytes, hipStream_t stream) {
     if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
-    if (num_trees < 0 || num_nodes < 0) return TV_ERR_INVALID_ARG;
+    if (num_trees < 0 || num_nodes < 0 || num_trees >= (int64_t(1) << 31)) return TV_ERR_INVALID_ARG;
     if (num_trees == 0) return TV_OK;
     if (!tree_offsets || !parent || !unary_offsets || !ulam || !uslope || !w || !x) return TV_ERR_INVALID_ARG;
     const size_t need = tv_tree_nc_workspace(num_trees, num_nodes, msg_cap, map_cap, stack_cap);
@@ -1284,13 +1285,17 @@ tv_status tv_tree_nc(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
     A.stack_cap = stack_cap;
     nc_tree_layout(num_trees, num_nodes, msg_cap, map_cap, stack_cap, workspace, &A);
     if (hipMemsetAsync(A.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
-    const dim3 grid((unsigned)((num_trees + 63) / 64));
+    // Each lane walks its tree serially, so spread the trees over at least
+    // 1024 waves (one per SIMD) before packing 64 into a wave.
+    const int64_t spread = (num_trees + 1023) / 1024;
+    const int lanes = spread < 64 ? (int)spread : 64;
+    const dim3 grid((unsigned)((num_trees + lanes - 1) / lanes));
     if (dtype == TV_F32)
         hipLaunchKernelGGL((k_nc_tree<float>), grid, dim3(64), 0, stream, A, (const float *)ulam,
-                           (const float *)uslope, (const float *)w, (const float *)C, (float *)x);
+                           (const float *)uslope, (const float *)w, (const float *)C, (float *)x, lanes);
     else
         hipLaunchKernelGGL((k_nc_tree<double>), grid, dim3(64), 0, stream, A, (const double *)ulam,
-                           (const double *)uslope, (const double *)w, (const double *)C, (double *)x);
+                           (const double *)uslope, (const double *)w, (const double *)C, (double *)x, lanes);
     return nc_finish(A.flag, stream);
 }
 
