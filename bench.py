@@ -386,6 +386,27 @@ def bench_nc2d(iters: int):
             "mean_abs_init_minus_true_disparity": round(float(np.abs(x0 - dt).mean()), 3)}
 
 
+def bench_nc_concave(steps: int):
+    """Sec. 3 Extensions (i) (tv_chain_nc_concave): 16,384 chains of 256 nodes
+    (concave_cost_chains), 16-level uniform [0, 4] costs, and on every edge
+    min(|z|, 0.25 |z| + 1, 2.5), three pieces per side, FP32 in, FP64
+    messages.  Capacities from the oracle on 256 of the chains: messages up to
+    37 breakpoints, up to 4,857 intervals per chain."""
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    coff, (uoff, ulam, usl), (poff, al, cc, sd) = synth.concave_cost_chains(16384, 256, 16, seed=9)
+    f32 = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")  # noqa: E731
+    i64 = lambda a: torch.tensor(a, dtype=torch.int64, device="cuda")  # noqa: E731
+    args = (i64(coff), i64(uoff), f32(ulam), f32(usl), i64(poff), f32(al), f32(cc),
+            torch.tensor(sd, dtype=torch.int32, device="cuda"))
+    run = lambda: binding.chain_nc_concave(*args, msg_cap=128, map_cap=8192)  # noqa: E731
+    run()
+    ms = Timer(torch, torch.cuda.current_stream())(run, steps)
+    N = int(coff[-1])
+    return {"workload": "16384 chains x 256 nodes, 16-level uniform random costs, pairwise min(|z|, 0.25|z| + 1, "
+                        "2.5), FP32 in, FP64 messages", "ms": round(ms, 2), "mnode_s": round(N / ms / 1e3, 2)}
+
+
 def bench_nc_tree(steps: int):
     """Sec. 3 non-convex trees (tv_tree_nc): 16,384 random post-order trees of
     256 nodes (post_order_forest), unaries through uniform [0, 4] costs at 16
@@ -572,7 +593,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
                     help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,nc,"
-                         "nc2d,nc_tree,batched")
+                         "nc2d,nc_tree,nc_concave,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -659,6 +680,7 @@ def main():
                 ("nc", "non-convex chains 1000x1482, 64 levels", lambda: bench_nc(3)),
                 ("nc2d", "non-convex 2D 1000x1482, 64 levels", lambda: bench_nc2d(5)),
                 ("nc_tree", "non-convex trees 16384x256", lambda: bench_nc_tree(3)),
+                ("nc_concave", "concave pairwise chains 16384x256", lambda: bench_nc_concave(3)),
                 ("batched", "batched 256 images", bench_batched)]
         pick = None if args.extras == "all" else set(args.extras.split(","))
         try:

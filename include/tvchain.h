@@ -269,6 +269,37 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
                       size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Non-convex chains with concave pairwise terms, Sec. 3, Extensions (i): as
+ * tv_chain_nc, but the term of the edge from node i to node i + 1 is
+ *     f_i(z) = 0 at z = 0, else min over its pieces k on z's side of
+ *              alpha_k |z| + C_k,   z = x_{i+1} - x_i,
+ * i.e. any piecewise-linear f_i that is non-increasing concave for z < 0 and
+ * non-decreasing concave for z > 0 (truncated TV: (w, 0) and (0, C) on both
+ * sides; Potts: (0, C) on both sides).  A side without pieces makes f_i
+ * infinite there (a hard order constraint).  The pieces are applied one at a
+ * time (Prop. 2) by h (x) g = (h^alpha (x) g^alpha)^-alpha, exactly; one lane
+ * per chain, FP64 messages in the workspace.
+ *  num_pieces    : total pieces (entries of piece_alpha, piece_C, piece_side).
+ *  chain_offsets, unary_offsets, ulam, uslope : as for tv_chain_nc.
+ *  piece_offsets : DEVICE int64 [num_nodes + 1]: node i's edge owns pieces
+ *                  [piece_offsets[i], piece_offsets[i+1]) (within
+ *                  [0, num_pieces], non-decreasing; a chain's last node's
+ *                  pieces are ignored).
+ *  piece_alpha, piece_C : DEVICE [num_pieces] (dtype), finite and >= 0.
+ *  piece_side    : DEVICE int32 [num_pieces], +1 (z > 0) or -1 (z < 0).
+ *  x             : DEVICE [num_nodes] output.
+ *  msg_cap, map_cap : as for tv_chain_nc (map_cap per chain).
+ * Synchronous.  Errors as tv_chain_nc (invalid pieces: TV_ERR_INVALID_ARG,
+ * found on the device). */
+size_t tv_chain_nc_concave_workspace(int64_t num_chains, int64_t num_nodes, int64_t num_pieces, int64_t msg_cap,
+                                     int64_t map_cap);
+tv_status tv_chain_nc_concave(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, int64_t num_pieces,
+                              const int64_t *chain_offsets, const int64_t *unary_offsets, const void *ulam,
+                              const void *uslope, const int64_t *piece_offsets, const void *piece_alpha,
+                              const void *piece_C, const int32_t *piece_side, void *x, int64_t msg_cap,
+                              int64_t map_cap, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Non-convex trees, Sec. 3: a batch of trees, each minimising
  *     sum_i f_i(x_i) + sum_{i not a root} min(w_i |x_parent(i) - x_i|, C_i)
  * with f_i as for tv_chain_nc; a node's message is its unary plus its

@@ -106,6 +106,9 @@ _SIG = {
     "tv_chain_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64]),
     "tv_chain_nc": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _I64, _I64, _P,
                                    ctypes.c_size_t, _P]),
+    "tv_chain_nc_concave_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64, _I64]),
+    "tv_chain_nc_concave": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                           _I64, _I64, _P, ctypes.c_size_t, _P]),
     "tv_tree_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64, _I64]),
     "tv_tree_nc": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _I64, _I64, _P,
                                   ctypes.c_size_t, _P]),
@@ -731,6 +734,53 @@ def chain_nc(chain_offsets: torch.Tensor, unary_offsets: torch.Tensor, ulam: tor
                          *(_ptr(t) for t in ts), _ptr(x), msg_cap, map_cap, _ptr(ws), nbytes,
                          ctypes.c_void_p(_stream_ptr(ulam.device)))
     _check(st, "tv_chain_nc")
+    return x
+
+
+def chain_nc_concave(chain_offsets: torch.Tensor, unary_offsets: torch.Tensor, ulam: torch.Tensor,
+                     uslope: torch.Tensor, piece_offsets: torch.Tensor, piece_alpha: torch.Tensor,
+                     piece_C: torch.Tensor, piece_side: torch.Tensor, msg_cap: int = 256,
+                     map_cap: Optional[int] = None) -> torch.Tensor:
+    """Sec. 3 Extensions (i) (tv_chain_nc_concave): chains as for chain_nc whose
+    pairwise term on the edge from node i to i + 1 is the minimum of the pieces
+    piece_offsets[i] .. piece_offsets[i+1] - 1, alpha |z| + C on the side
+    piece_side (+1: z = x_{i+1} - x_i > 0, -1: z < 0), and 0 at z = 0.
+    piece_offsets int64 (nodes + 1), piece_side int32.  map_cap defaults to 8
+    per piece of the chain with the most pieces (at least 64; about 3 per piece
+    on 16-level cost chains).  Returns x."""
+    _require_gpu(chain_offsets, unary_offsets, ulam, uslope, piece_offsets, piece_alpha, piece_C, piece_side)
+    lib = load()
+    if chain_offsets.dtype != torch.int64 or unary_offsets.dtype != torch.int64 or \
+            piece_offsets.dtype != torch.int64:
+        raise TvChainError(TV_ERR_INVALID_ARG, "offsets must be int64")
+    if piece_side.dtype != torch.int32:
+        raise TvChainError(TV_ERR_INVALID_ARG, "piece_side must be int32")
+    N = unary_offsets.numel() - 1
+    ts = [t.contiguous() for t in (ulam, uslope, piece_alpha, piece_C)]
+    for t in ts:
+        if t.dtype != ulam.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "float arrays must share one dtype")
+    P = ts[2].numel()
+    if piece_offsets.numel() != N + 1 or ts[3].numel() != P or piece_side.numel() != P:
+        raise TvChainError(TV_ERR_INVALID_ARG, "piece arrays do not match")
+    chain_offsets, unary_offsets = chain_offsets.contiguous(), unary_offsets.contiguous()
+    piece_offsets, piece_side = piece_offsets.contiguous(), piece_side.contiguous()
+    nchains = chain_offsets.numel() - 1
+    if map_cap is None:
+        co = chain_offsets.cpu()
+        po = piece_offsets.cpu()
+        most = int((po[co[1:]] - po[co[:-1]]).max().item()) if nchains > 0 else 1
+        map_cap = max(64, 8 * most)
+    x = torch.empty(N, dtype=ulam.dtype, device=ulam.device)
+    nbytes = lib.tv_chain_nc_concave_workspace(nchains, N, P, msg_cap, map_cap)
+    if nbytes == 0:
+        raise TvChainError(TV_ERR_INVALID_ARG, "tv_chain_nc_concave_workspace")
+    ws = _workspace(nbytes, ulam.device)
+    st = lib.tv_chain_nc_concave(_dtype_code(ulam), nchains, N, P, _ptr(chain_offsets), _ptr(unary_offsets),
+                                 _ptr(ts[0]), _ptr(ts[1]), _ptr(piece_offsets), _ptr(ts[2]), _ptr(ts[3]),
+                                 _ptr(piece_side), _ptr(x), msg_cap, map_cap, _ptr(ws), nbytes,
+                                 ctypes.c_void_p(_stream_ptr(ulam.device)))
+    _check(st, "tv_chain_nc_concave")
     return x
 
 

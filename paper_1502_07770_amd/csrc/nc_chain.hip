@@ -1149,6 +1149,217 @@ size_t nc_layout(int64_t num_chains, int64_t num_nodes, int64_t msg_cap, int64_t
 }
 
 // Launch check, then the device flag read back (synchronous).
+// ---------------------------------------------------------------------------
+// Sec. 3, Extensions (i): pairwise terms that are minima of one-sided linear
+// pieces g(z) = alpha |z| + C on z > 0 or on z < 0 (g(0) = 0), applied one
+// piece at a time (Prop. 2).  For a right-side piece and phi = h - alpha x,
+//   (h (x) g)(y) = alpha y + min(phi(y), min_{x <= y} phi(x) + C).
+// One sweep over the pieces of phi keeps its running minimum m and the first
+// point a attaining it: the output follows h while phi <= m + C and is flat in
+// phi's frame (slope alpha in h's) where phi rises above m + C; each such run
+// maps to a, reported through add(lo, hi, a).  A left-side piece is the same
+// sweep over the reversed view.
+// ---------------------------------------------------------------------------
+template <class View, class Add>
+__device__ bool nc_side(const View &h, double alpha, double C, NcBuf &out, Add add) {
+    const int64_t t = h.t();
+    out.t = 0;
+    out.s[0] = h.s(0);
+    if (t == 0) return true;  // h constant: phi never rises above its running minimum
+    double cur = h.s(0);      // the output's slope right of its last breakpoint
+    auto emit = [&](double lam, double sl) -> bool {
+        if (sl == cur) return true;
+        if (out.t > 0 && out.l[out.t - 1] == lam) {  // a second slope at the same point
+            out.s[out.t] = sl;
+            if (out.s[out.t] == out.s[out.t - 1]) --out.t;
+            cur = sl;
+            return true;
+        }
+        cur = sl;
+        return out.push(lam, sl);
+    };
+    // phi is non-increasing left of l(0) (s(0) <= 0 <= alpha): its minimum up to
+    // l(0) is there; values relative to h(l(0)) = 0
+    double phl = -alpha * h.l(0), m = phl, a = h.l(0), lo = 0.0;
+    bool above = false;
+    for (int64_t k = 1; k <= t; ++k) {
+        const double L = h.l(k - 1), sk = h.s(k), sg = sk - alpha;
+        const bool last = k == t;
+        const double R = last ? HUGE_VAL : h.l(k);
+        if (!above) {
+            if (!emit(L, sk)) return false;
+            if (sg > 0.0) {
+                double y = L + (m + C - phl) / sg;  // phi climbs to m + C
+                if (y < L) y = L;
+                if (y < R) {
+                    if (!emit(y, alpha)) return false;
+                    above = true;
+                    lo = y;
+                }
+            }
+        } else if (sg < 0.0) {
+            double y = L + (m + C - phl) / sg;  // phi comes back down to m + C
+            if (y < L) y = L;
+            if (y < R) {
+                if (!add(lo, y, a)) return false;
+                above = false;
+                if (!emit(y, sk)) return false;
+            }
+        }
+        if (last) break;
+        const double phr = phl + sg * (R - L);
+        if (!above && phr < m) {  // a new minimum (only where phi is not above m + C)
+            m = phr;
+            a = R;
+        }
+        phl = phr;
+    }
+    if (above && !add(lo, HUGE_VAL, a)) return false;
+    return true;
+}
+
+struct NcgArgs {
+    int64_t num_chains, num_nodes, num_pieces;
+    const int64_t *coff, *uoff, *poff;
+    int64_t msg_cap, map_cap;
+    double *bufs;   // per chain: 3 buffers of (2 msg_cap + 1) doubles
+    double *maps;   // per chain: 3 arrays of map_cap doubles
+    int64_t *pmap;  // per piece: its interval range [pmap[2k], pmap[2k + 1])
+    int *flag;
+};
+
+// One lane per chain (spread over at least 1024 waves), FP64 messages in the
+// workspace.  Per node: hat = unary + incoming message (Lemma 1), then every
+// piece of the edge to the next node in turn; backward, each node applies its
+// edge's mappings, the last piece's first.
+template <class T>
+__global__ __launch_bounds__(64) void k_nc_concave(NcgArgs A, const T *__restrict__ ulam,
+                                                   const T *__restrict__ uslope, const T *__restrict__ palpha,
+                                                   const T *__restrict__ pC, const int32_t *__restrict__ pside,
+                                                   T *__restrict__ x, int lanes) {
+    if ((int)threadIdx.x >= lanes) return;
+    const int64_t c = (int64_t)blockIdx.x * lanes + threadIdx.x;
+    if (c >= A.num_chains) return;
+    const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {
+        atomicOr(A.flag, kNcFlagInvalid);
+        return;
+    }
+    if (n1 == n0) return;
+    const int64_t bstride = 2 * A.msg_cap + 1;
+    double *base = A.bufs + c * 3 * bstride;
+    NcBuf X{base, base + A.msg_cap, 0, A.msg_cap};  // the incoming message
+    NcBuf Y{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap};
+    NcBuf U{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};
+    double *mb = A.maps + c * 3 * A.map_cap;
+    NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    X.s[0] = 0.0;
+    int bad = 0;
+    for (int64_t i = n0; i < n1 && !bad; ++i) {
+        const int64_t u0 = A.uoff[i], tu = A.uoff[i + 1] - u0;
+        if (tu < 1 || tu > A.msg_cap) {
+            bad = tu < 1 ? kNcFlagInvalid : kNcFlagCapacity;
+            break;
+        }
+        for (int64_t k = 0; k < tu; ++k) {
+            U.l[k] = (double)ulam[u0 + k];
+            if (k > 0 && !(U.l[k] >= U.l[k - 1])) bad = kNcFlagInvalid;
+        }
+        for (int64_t k = 0; k <= tu; ++k) U.s[k] = (double)uslope[u0 + i + k];
+        if (!(U.s[0] <= 0.0) || !(U.s[tu] >= 0.0)) bad = kNcFlagInvalid;
+        if (bad) break;
+        if (!nc_sum(U.l, U.s, tu, X, Y)) {  // hat in Y
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (i == n1 - 1) break;
+        const int64_t k0 = A.poff[i], k1 = A.poff[i + 1];
+        if (k0 < 0 || k1 < k0 || k1 > A.num_pieces) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        NcBuf *cur = &Y, *oth = &X;
+        bool rev = false;  // cur holds the reversal of the message
+        for (int64_t k = k0; k < k1; ++k) {
+            const double al = (double)palpha[k], cc = (double)pC[k];
+            const int sd = pside[k];
+            if (!(al >= 0.0) || !(al < HUGE_VAL) || !(cc >= 0.0) || !(cc < HUGE_VAL) || (sd != 1 && sd != -1)) {
+                bad = kNcFlagInvalid;
+                break;
+            }
+            A.pmap[2 * k] = mp.n;
+            bool ok;
+            auto fwd = [&](double lo, double hi, double to) { return mp.add(lo, hi, to); };
+            auto mir = [&](double lo, double hi, double to) { return mp.add(-hi, -lo, -to); };
+            if (sd > 0) {
+                ok = rev ? nc_side(NcRev{cur}, al, cc, *oth, fwd) : nc_side(NcFwd{cur}, al, cc, *oth, fwd);
+                rev = false;
+            } else {
+                ok = rev ? nc_side(NcFwd{cur}, al, cc, *oth, mir) : nc_side(NcRev{cur}, al, cc, *oth, mir);
+                rev = true;
+            }
+            A.pmap[2 * k + 1] = mp.n;
+            if (!ok) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+            NcBuf *sw = cur;
+            cur = oth;
+            oth = sw;
+        }
+        if (bad) break;
+        if (rev) {  // store the message forward
+            const NcRev r{cur};
+            oth->t = r.t();
+            for (int64_t k = 0; k < oth->t; ++k) oth->l[k] = r.l(k);
+            for (int64_t k = 0; k <= oth->t; ++k) oth->s[k] = r.s(k);
+            NcBuf *sw = cur;
+            cur = oth;
+            oth = sw;
+        }
+        if (cur != &X) {  // the message becomes X, the other buffer Y
+            const NcBuf sw = X;
+            X = Y;
+            Y = sw;
+        }
+    }
+    if (bad) {
+        atomicOr(A.flag, bad);
+        return;
+    }
+    // the last node: the first breakpoint attaining the minimum of its hat (Y)
+    double v = 0.0, vmin = 0.0, y = Y.t > 0 ? Y.l[0] : 0.0;
+    for (int64_t k = 1; k < Y.t; ++k) {
+        v += Y.s[k] * (Y.l[k] - Y.l[k - 1]);
+        if (v < vmin) {
+            vmin = v;
+            y = Y.l[k];
+        }
+    }
+    x[n1 - 1] = (T)y;
+    for (int64_t i = n1 - 2; i >= n0; --i) {
+        for (int64_t k = A.poff[i + 1] - 1; k >= A.poff[i]; --k) y = nc_apply(mp, A.pmap[2 * k], A.pmap[2 * k + 1], y);
+        x[i] = (T)y;
+    }
+}
+
+size_t ncg_layout(int64_t num_chains, int64_t num_pieces, int64_t msg_cap, int64_t map_cap, void *p, NcgArgs *A) {
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_b = off;  off += al(sizeof(double) * (size_t)(num_chains * 3 * (2 * msg_cap + 1)));
+    const size_t o_m = off;  off += al(sizeof(double) * (size_t)(num_chains * 3 * map_cap));
+    const size_t o_p = off;  off += al(sizeof(int64_t) * (size_t)(2 * num_pieces));
+    const size_t o_f = off;  off += al(sizeof(int));
+    if (p && A) {
+        char *c = (char *)p;
+        A->bufs = (double *)(c + o_b);
+        A->maps = (double *)(c + o_m);
+        A->pmap = (int64_t *)(c + o_p);
+        A->flag = (int *)(c + o_f);
+    }
+    return off;
+}
+
 tv_status nc_finish(int *dflag, hipStream_t stream) {
     if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
     int flag = 0;
@@ -1296,6 +1507,52 @@ tv_status tv_tree_nc(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
     else
         hipLaunchKernelGGL((k_nc_tree<double>), grid, dim3(64), 0, stream, A, (const double *)ulam,
                            (const double *)uslope, (const double *)w, (const double *)C, (double *)x, lanes);
+    return nc_finish(A.flag, stream);
+}
+
+size_t tv_chain_nc_concave_workspace(int64_t num_chains, int64_t num_nodes, int64_t num_pieces, int64_t msg_cap,
+                                     int64_t map_cap) {
+    if (num_chains < 0 || num_nodes < 0 || num_pieces < 0 || msg_cap < 1 || map_cap < 1) return 0;
+    if (msg_cap > (int64_t(1) << 24) || map_cap > (int64_t(1) << 30)) return 0;
+    return ncg_layout(num_chains, num_pieces, msg_cap, map_cap, nullptr, nullptr);
+}
+
+tv_status tv_chain_nc_concave(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, int64_t num_pieces,
+                              const int64_t *chain_offsets, const int64_t *unary_offsets, const void *ulam,
+                              const void *uslope, const int64_t *piece_offsets, const void *piece_alpha,
+                              const void *piece_C, const int32_t *piece_side, void *x, int64_t msg_cap,
+                              int64_t map_cap, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (num_chains < 0 || num_nodes < 0 || num_pieces < 0 || num_chains >= (int64_t(1) << 31))
+        return TV_ERR_INVALID_ARG;
+    if (num_chains == 0) return TV_OK;
+    if (!chain_offsets || !unary_offsets || !ulam || !uslope || !piece_offsets || !x) return TV_ERR_INVALID_ARG;
+    if (num_pieces > 0 && (!piece_alpha || !piece_C || !piece_side)) return TV_ERR_INVALID_ARG;
+    const size_t need = tv_chain_nc_concave_workspace(num_chains, num_nodes, num_pieces, msg_cap, map_cap);
+    if (need == 0) return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
+    NcgArgs A;
+    A.num_chains = num_chains;
+    A.num_nodes = num_nodes;
+    A.num_pieces = num_pieces;
+    A.coff = chain_offsets;
+    A.uoff = unary_offsets;
+    A.poff = piece_offsets;
+    A.msg_cap = msg_cap;
+    A.map_cap = map_cap;
+    ncg_layout(num_chains, num_pieces, msg_cap, map_cap, workspace, &A);
+    if (hipMemsetAsync(A.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
+    const int64_t spread = (num_chains + 1023) / 1024;
+    const int lanes = spread < 64 ? (int)spread : 64;
+    const dim3 grid((unsigned)((num_chains + lanes - 1) / lanes));
+    if (dtype == TV_F32)
+        hipLaunchKernelGGL((k_nc_concave<float>), grid, dim3(64), 0, stream, A, (const float *)ulam,
+                           (const float *)uslope, (const float *)piece_alpha, (const float *)piece_C, piece_side,
+                           (float *)x, lanes);
+    else
+        hipLaunchKernelGGL((k_nc_concave<double>), grid, dim3(64), 0, stream, A, (const double *)ulam,
+                           (const double *)uslope, (const double *)piece_alpha, (const double *)piece_C, piece_side,
+                           (double *)x, lanes);
     return nc_finish(A.flag, stream);
 }
 

@@ -200,3 +200,25 @@ def cost_volume_chains(H: int, W: int, D: int, seed: int = 0, outliers: float = 
     unary_offsets = (np.arange(n + 1, dtype=np.int64) * D)
     ulam = np.tile(lev, n)
     return chain_offsets, unary_offsets, ulam, slopes.reshape(-1), dt
+
+
+def concave_cost_chains(num_chains: int, n: int, D: int, seed: int = 0, steep: float = 10.0,
+                        pieces=((1.0, 0.0), (0.25, 1.0), (0.0, 2.5))):
+    """Chains of n nodes with uniform [0, 4] costs at the D integer levels
+    (joined linearly, slopes -steep / +steep outside) and, on every edge, the
+    pairwise term min over `pieces` (alpha, C) of alpha |z| + C on both sides
+    (default: min(|z|, 0.25 |z| + 1, 2.5)).  Returns chain_offsets, (unary
+    offsets, ulam, uslope) and (piece offsets, alpha, C, side int32)."""
+    g = generator(seed)
+    N = int(num_chains) * int(n)
+    cost = g.uniform(0, 4, (N, D))
+    sl = np.empty((N, D + 1))
+    sl[:, 0], sl[:, D] = -steep, steep
+    sl[:, 1:D] = np.diff(cost, axis=1)
+    k = 2 * len(pieces)
+    al = np.array([a for a, _ in pieces] * 2, dtype=np.float64)
+    cc = np.array([c for _, c in pieces] * 2, dtype=np.float64)
+    sd = np.array([1] * len(pieces) + [-1] * len(pieces), dtype=np.int32)
+    unaries = (np.arange(N + 1, dtype=np.int64) * D, np.tile(np.arange(D, dtype=np.float64), N), sl.reshape(-1))
+    pcs = (np.arange(N + 1, dtype=np.int64) * k, np.tile(al, N), np.tile(cc, N), np.tile(sd, N))
+    return np.arange(int(num_chains) + 1, dtype=np.int64) * int(n), unaries, pcs
