@@ -140,3 +140,15 @@ def test_full_size_sampled_chains():
     x = _run(coff, u, p, torch.float32, msg_cap=128, map_cap=8192)
     pick = np.sort(np.random.default_rng(53).choice(coff.size - 1, 300, replace=False))
     _check(coff, u, p, x, pick, 1e-6, 8 * 2.0 ** -23 * 20)
+
+
+def test_capacities_do_not_change_x():
+    """The same chains with 8192- and 256-breakpoint message buffers (other
+    strides in the workspace) give the same x."""
+    g = np.random.default_rng(54)
+    lengths = g.integers(1, 80, 120)
+    coff, u, p = _batch(g, lengths)
+    x_big = _run(coff, u, p, torch.float64, msg_cap=8192)
+    x_small = _run(coff, u, p, torch.float64, msg_cap=256)
+    np.testing.assert_array_equal(x_big, x_small)
+    _check(coff, u, p, x_big, range(lengths.size), 1e-9)
