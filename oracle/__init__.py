@@ -116,6 +116,12 @@ def _load():
     lib.orc_ncg_energy.restype = D
     lib.orc_ncg_brute.argtypes = [I64, P, P, P, P, P, P, P, P, P]
     lib.orc_ncg_brute.restype = ctypes.c_int
+    lib.orc_ncg_tree.argtypes = [I64, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_ncg_tree.restype = ctypes.c_int
+    lib.orc_ncg_tree_energy.argtypes = [I64, P, P, P, P, P, P, P, P, P]
+    lib.orc_ncg_tree_energy.restype = D
+    lib.orc_ncg_tree_brute.argtypes = [I64, P, P, P, P, P, P, P, P, P]
+    lib.orc_ncg_tree_brute.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -461,6 +467,43 @@ def ncg_brute(uoff, ulam, uslope, poff, alpha, C, side):
     if rc != 0:
         raise ValueError("orc_ncg_brute: invalid input (%d)" % rc)
     return float(e.value), x
+
+
+def ncg_tree(parent, uoff, ulam, uslope, poff, alpha, C, side):
+    """ncg_chain's pairwise terms on a forest (parent[i] > i, -1 at roots): the
+    pieces [poff[i], poff[i+1]) belong to the edge from i to its parent, with
+    z = x_parent - x_i.  Returns (x, largest number of message breakpoints)."""
+    parent = np.ascontiguousarray(parent, dtype=np.int64)
+    n, uoff, ulam, uslope, poff, alpha, C, side = _ncg_args(uoff, ulam, uslope, poff, alpha, C, side)
+    if parent.size != n:
+        raise ValueError("parent must hold one entry per node")
+    x = np.empty(n)
+    mb = ctypes.c_int64(0)
+    rc = _load().orc_ncg_tree(n, _ptr(parent), _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(poff), _ptr(alpha),
+                              _ptr(C), _ptr(side), _ptr(x), ctypes.byref(mb))
+    if rc != 0:
+        raise ValueError("orc_ncg_tree: invalid input (%d)" % rc)
+    return x, int(mb.value)
+
+
+def ncg_tree_energy(parent, uoff, ulam, uslope, poff, alpha, C, side, x) -> float:
+    parent = np.ascontiguousarray(parent, dtype=np.int64)
+    n, uoff, ulam, uslope, poff, alpha, C, side = _ncg_args(uoff, ulam, uslope, poff, alpha, C, side)
+    x = _f64(x)
+    return float(_load().orc_ncg_tree_energy(n, _ptr(parent), _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(poff),
+                                             _ptr(alpha), _ptr(C), _ptr(side), _ptr(x)))
+
+
+def ncg_tree_brute(parent, uoff, ulam, uslope, poff, alpha, C, side) -> float:
+    """Exact minimum energy of a forest of n <= 6 nodes (unary breakpoints, min-sum)."""
+    parent = np.ascontiguousarray(parent, dtype=np.int64)
+    n, uoff, ulam, uslope, poff, alpha, C, side = _ncg_args(uoff, ulam, uslope, poff, alpha, C, side)
+    e = ctypes.c_double(0.0)
+    rc = _load().orc_ncg_tree_brute(n, _ptr(parent), _ptr(uoff), _ptr(ulam), _ptr(uslope), _ptr(poff), _ptr(alpha),
+                                    _ptr(C), _ptr(side), ctypes.byref(e))
+    if rc != 0:
+        raise ValueError("orc_ncg_tree_brute: invalid input (%d)" % rc)
+    return float(e.value)
 
 
 def grid_unaries(cost, d0: float, dd: float, steep: float):

@@ -52,6 +52,9 @@
  *                          h (x) g = (h^alpha (x) g^alpha)^-alpha.
  *   orc_ncg_brute       -- exact minimum of that energy on tiny chains (n <= 6)
  *                          by a Viterbi pass over the unary breakpoints.
+ *   orc_ncg_tree        -- the same pairwise terms on a forest (Sec. 3 on trees:
+ *                          children's messages summed by Lemma 1), with
+ *                          orc_ncg_tree_brute its min-sum check on n <= 6.
  *   orc_tv2d_l1         -- Sec. 5.2 TV-l1 by the same decomposition: the
  *                          primal-dual iteration eq. (pd) with the dual prox of
  *                          lambda TV_v on the columns (as for ROF) and the primal
@@ -2095,5 +2098,170 @@ int orc_ncg_brute(int64_t n, const int64_t *uoff, const double *ulam, const doub
     }
     free(cost);
     free(arg);
+    return 0;
+}
+
+
+/* Forests (parent[i] > i, -1 at roots) with the pairwise terms above: the
+ * pieces [poff[i], poff[i+1]) belong to the edge from i to its parent, with
+ * z = x_parent - x_i (a chain numbered as a tree, parent = i + 1, is the chain
+ * case); a root's pieces are ignored.  hat M_i = f_i + the children's
+ * messages (Lemma 1), each message hat M_i through the pieces in turn, a root
+ * at the first breakpoint attaining the minimum of its hat M, and backward
+ * x_i = the composed mappings of its edge applied to x_parent. */
+int orc_ncg_tree(int64_t n, const int64_t *parent, const int64_t *uoff, const double *ulam, const double *uslope,
+                 const int64_t *poff, const double *alpha, const double *C, const int32_t *side, double *x,
+                 int64_t *max_bp)
+{
+    if (n < 1 || ncg_check_pieces(n, poff, alpha, C, side)) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (parent[i] != -1 && (parent[i] <= i || parent[i] >= n)) return -1;
+    nc_plf *msg = (nc_plf *)calloc((size_t)n, sizeof(nc_plf));
+    const int64_t np = poff[n];
+    int64_t *pr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * np + 2));
+    int64_t *cnt = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *kid = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    nc_plf hat = {0, 0, NULL, NULL}, tmp = {0, 0, NULL, NULL}, f = {0, 0, NULL, NULL}, a = {0, 0, NULL, NULL},
+           b = {0, 0, NULL, NULL}, t1 = {0, 0, NULL, NULL}, t2 = {0, 0, NULL, NULL};
+    nc_ivs iv = {0, 0, NULL, NULL, NULL};
+    int rc = (msg && pr && cnt && kid) ? 0 : -2;
+    int64_t mb = 0;
+    if (rc == 0) { /* children lists */
+        for (int64_t i = 0; i < n; ++i)
+            if (parent[i] >= 0) cnt[parent[i] + 1]++;
+        for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+        int64_t *fill = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+        if (!fill) rc = -2;
+        for (int64_t i = 0; rc == 0 && i < n; ++i)
+            if (parent[i] >= 0) kid[cnt[parent[i]] + fill[parent[i]]++] = i;
+        free(fill);
+    }
+    for (int64_t i = 0; i < n && rc == 0; ++i) {
+        rc = nc_unary(i, uoff, ulam, uslope, &f);
+        if (rc == 0) rc = nc_reserve(&hat, f.t);
+        if (rc) break;
+        hat.t = f.t;
+        memcpy(hat.l, f.l, sizeof(double) * (size_t)f.t);
+        memcpy(hat.s, f.s, sizeof(double) * (size_t)(f.t + 1));
+        for (int64_t k = cnt[i]; k < cnt[i + 1] && rc == 0; ++k) {
+            rc = nc_add(&hat, &msg[kid[k]], &tmp);
+            nc_free(&msg[kid[k]]);
+            if (rc == 0) {
+                nc_plf sw = hat;
+                hat = tmp;
+                tmp = sw;
+            }
+        }
+        if (rc) break;
+        mb = hat.t > mb ? hat.t : mb;
+        if (parent[i] < 0) {
+            double *v = (double *)malloc(sizeof(double) * (size_t)(hat.t > 0 ? hat.t : 1));
+            if (!v) {
+                rc = -2;
+                break;
+            }
+            nc_values(&hat, v);
+            int64_t pm = 0;
+            for (int64_t p = 1; p < hat.t; ++p)
+                if (v[p] < v[pm]) pm = p;
+            x[i] = hat.t > 0 ? hat.l[pm] : 0.0;
+            free(v);
+            continue;
+        }
+        rc = nc_reserve(&a, hat.t);
+        if (rc) break;
+        a.t = hat.t;
+        memcpy(a.l, hat.l, sizeof(double) * (size_t)hat.t);
+        memcpy(a.s, hat.s, sizeof(double) * (size_t)(hat.t + 1));
+        for (int64_t k = poff[i]; k < poff[i + 1] && rc == 0; ++k) {
+            pr[2 * k] = iv.n;
+            rc = ncg_piece(&a, alpha[k], C[k], side[k], &b, &iv, &t1, &t2);
+            pr[2 * k + 1] = iv.n;
+            if (rc == 0) {
+                nc_plf sw = a;
+                a = b;
+                b = sw;
+                mb = a.t > mb ? a.t : mb;
+            }
+        }
+        if (rc) break;
+        /* the message moves to msg[i]; a gets fresh storage */
+        msg[i] = a;
+        a.t = a.cap = 0;
+        a.l = a.s = NULL;
+    }
+    if (rc == 0) {
+        for (int64_t i = n - 1; i >= 0; --i) {
+            if (parent[i] < 0) continue;
+            double y = x[parent[i]];
+            for (int64_t k = poff[i + 1] - 1; k >= poff[i]; --k) y = nc_apply(&iv, pr[2 * k], pr[2 * k + 1], y);
+            x[i] = y;
+        }
+    }
+    if (max_bp) *max_bp = mb;
+    for (int64_t i = 0; msg && i < n; ++i) nc_free(&msg[i]);
+    free(msg);
+    free(pr);
+    free(cnt);
+    free(kid);
+    nc_free(&hat);
+    nc_free(&tmp);
+    nc_free(&f);
+    nc_free(&a);
+    nc_free(&b);
+    nc_free(&t1);
+    nc_free(&t2);
+    free(iv.a); free(iv.b); free(iv.to);
+    return rc;
+}
+
+double orc_ncg_tree_energy(int64_t n, const int64_t *parent, const int64_t *uoff, const double *ulam,
+                           const double *uslope, const int64_t *poff, const double *alpha, const double *C,
+                           const int32_t *side, const double *x)
+{
+    double e = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        e += nc_unary_val(i, uoff, ulam, uslope, x[i]);
+        if (parent[i] >= 0) e += ncg_pair(poff, alpha, C, side, i, x[parent[i]] - x[i]);
+    }
+    return e;
+}
+
+/* Exact minimum for n <= 6 by min-sum over the unary breakpoints (the same
+ * vertex argument as orc_ncg_brute: every run of equal values, here a
+ * connected set of nodes, holds a unary breakpoint at an optimal vertex). */
+int orc_ncg_tree_brute(int64_t n, const int64_t *parent, const int64_t *uoff, const double *ulam,
+                       const double *uslope, const int64_t *poff, const double *alpha, const double *C,
+                       const int32_t *side, double *emin)
+{
+    if (n < 1 || n > 6 || ncg_check_pieces(n, poff, alpha, C, side)) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (parent[i] != -1 && (parent[i] <= i || parent[i] >= n)) return -1;
+    const int64_t nc = uoff[n] - uoff[0];
+    const double *cand = ulam + uoff[0];
+    double *cost = (double *)malloc(sizeof(double) * (size_t)(nc * n));
+    if (!cost) return -2;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t a = 0; a < nc; ++a) cost[i * nc + a] = nc_unary_val(i, uoff, ulam, uslope, cand[a]);
+    double total = 0.0;
+    for (int64_t i = 0; i < n; ++i) { /* children are complete before their parent */
+        if (parent[i] < 0) {
+            double best = INFINITY;
+            for (int64_t a = 0; a < nc; ++a) best = cost[i * nc + a] < best ? cost[i * nc + a] : best;
+            total += best;
+            continue;
+        }
+        const int64_t p = parent[i];
+        for (int64_t a = 0; a < nc; ++a) {  /* x_parent = cand[a] */
+            double best = INFINITY;
+            for (int64_t b = 0; b < nc; ++b) {
+                const double v = cost[i * nc + b] + ncg_pair(poff, alpha, C, side, i, cand[a] - cand[b]);
+                best = v < best ? v : best;
+            }
+            cost[p * nc + a] += best;
+        }
+    }
+    free(cost);
+    *emin = total;
     return 0;
 }

@@ -152,3 +152,29 @@ def test_capacities_do_not_change_x():
     x_small = _run(coff, u, p, torch.float64, msg_cap=256)
     np.testing.assert_array_equal(x_big, x_small)
     _check(coff, u, p, x_big, range(lengths.size), 1e-9)
+
+
+@pytest.mark.parametrize("kind", ["potts", "monotone", "equal"])
+def test_special_piece_sets(kind):
+    """Potts (0, C) on both sides; one-sided pieces (x non-decreasing along the
+    chain); no pieces at all (every chain at one value)."""
+    g = np.random.default_rng(55)
+    lengths = g.integers(1, 70, 80)
+    N = int(lengths.sum())
+    coff = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    u = _rand_unaries(g, N)
+    if kind == "potts":
+        p = (np.arange(N + 1, dtype=np.int64) * 2, np.zeros(2 * N), g.uniform(0, 3, 2 * N),
+             np.tile(np.array([1, -1], dtype=np.int32), N))
+    elif kind == "monotone":
+        p = (np.arange(N + 1, dtype=np.int64), g.uniform(0, 1, N), g.uniform(0, 1, N), np.ones(N, dtype=np.int32))
+    else:
+        p = (np.zeros(N + 1, dtype=np.int64), np.zeros(0), np.zeros(0), np.zeros(0, dtype=np.int32))
+    x = _run(coff, u, p, torch.float64)
+    _check(coff, u, p, x, range(lengths.size), 1e-9)
+    for c in range(lengths.size):
+        seg = x[coff[c]:coff[c + 1]]
+        if kind == "monotone":
+            assert np.all(np.diff(seg) >= 0)
+        if kind == "equal":
+            assert np.all(seg == seg[0])

@@ -172,3 +172,49 @@ def test_invalid_pieces_are_rejected():
                        ([0.0, 0.0], [0.0, 0.0], [1, 0]), ([np.inf, 0.0], [0.0, 0.0], [1, 1])):
         with pytest.raises(ValueError):
             oracle.ncg_chain(*u, poff, np.array(al), np.array(cc), np.array(sd, dtype=np.int32))
+
+
+def _rand_forest(g, n):
+    par = np.full(n, -1, dtype=np.int64)
+    for i in range(n - 1):
+        if g.random() > 0.15:
+            par[i] = int(g.integers(i + 1, n))
+    return par
+
+
+def test_tree_reaches_the_exact_minimum():
+    g = np.random.default_rng(41)
+    for _ in range(1200):
+        n = int(g.integers(1, 7))
+        par = _rand_forest(g, n)
+        u = _rand_unaries(g, n)
+        p = _rand_pieces(g, n)
+        x, _ = oracle.ncg_tree(par, *u, *p)
+        e = oracle.ncg_tree_energy(par, *u, *p, x)
+        eb = oracle.ncg_tree_brute(par, *u, *p)
+        assert abs(e - eb) <= 1e-9 * (1 + abs(eb)), (n, par, e, eb)
+
+
+def test_tree_chain_case_and_truncated_tv():
+    g = np.random.default_rng(42)
+    for _ in range(60):
+        n = int(g.integers(2, 60))
+        u = _rand_unaries(g, n, tmax=4)
+        # a chain numbered as a tree: the chain solver's energy
+        par = np.arange(1, n + 1, dtype=np.int64)
+        par[-1] = -1
+        p = _rand_pieces(g, n)
+        xt, _ = oracle.ncg_tree(par, *u, *p)
+        xc, _ = oracle.ncg_chain(*u, *p)
+        ec = _energy(u, p, xc)
+        assert abs(oracle.ncg_tree_energy(par, *u, *p, xt) - ec) <= 1e-9 * (1 + abs(ec))
+        # truncated TV as pieces on a random forest: the truncated-TV tree solver's energy
+        par = _rand_forest(g, n)
+        w = g.uniform(0, 2, n)
+        C = np.where(g.random(n) < 0.3, np.inf, g.uniform(0.2, 3, n))
+        q = _tv_pieces(w, C)
+        q = (q[0][:n + 1] if q[0].size > n + 1 else q[0], q[1], q[2], q[3])
+        xg, _ = oracle.ncg_tree(par, *u, *q)
+        xr, _ = oracle.nc_tree(par, *u, w, C)
+        er = oracle.nc_tree_energy(par, *u, w, C, xr)
+        assert abs(oracle.nc_tree_energy(par, *u, w, C, xg) - er) <= 1e-9 * (1 + abs(er))
