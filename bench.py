@@ -407,6 +407,29 @@ def bench_nc_concave(steps: int):
                         "2.5), FP32 in, FP64 messages", "ms": round(ms, 2), "mnode_s": round(N / ms / 1e3, 2)}
 
 
+def bench_nc_tree_concave(steps: int):
+    """Sec. 3 Extensions (i) on trees (tv_tree_nc_concave): the 16,384 trees of
+    bench_nc_tree (post_order_forest, seed 7) with the unaries and pairwise
+    terms of bench_nc_concave (min(|z|, 0.25 |z| + 1, 2.5), three pieces per
+    side), FP32 in, FP64 messages.  Capacities from the oracle on all the
+    trees: messages up to 506 breakpoints, at most 4,875 intervals per tree."""
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    par, off = synth.post_order_forest(16384, 256, seed=7)
+    _, (uoff, ulam, usl), (poff, al, cc, sd) = synth.concave_cost_chains(16384, 256, 16, seed=9)
+    f32 = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")  # noqa: E731
+    i64 = lambda a: torch.tensor(a, dtype=torch.int64, device="cuda")  # noqa: E731
+    args = (i64(par), i64(off), i64(uoff), f32(ulam), f32(usl), i64(poff), f32(al), f32(cc),
+            torch.tensor(sd, dtype=torch.int32, device="cuda"))
+    run = lambda: binding.tree_nc_concave(*args, msg_cap=1024, map_cap=8192, stack_cap=64 * 1025)  # noqa: E731
+    run()
+    ms = Timer(torch, torch.cuda.current_stream())(run, steps)
+    N = int(off[-1])
+    return {"workload": "16384 post-order trees x 256 nodes, 16-level uniform random costs, pairwise min(|z|, "
+                        "0.25|z| + 1, 2.5), FP32 in, FP64 messages", "ms": round(ms, 2),
+            "mnode_s": round(N / ms / 1e3, 2)}
+
+
 def bench_nc_tree(steps: int):
     """Sec. 3 non-convex trees (tv_tree_nc): 16,384 random post-order trees of
     256 nodes (post_order_forest), unaries through uniform [0, 4] costs at 16
@@ -593,7 +616,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
                     help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,nc,"
-                         "nc2d,nc_tree,nc_concave,batched")
+                         "nc2d,nc_tree,nc_concave,nc_tree_concave,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -681,6 +704,7 @@ def main():
                 ("nc2d", "non-convex 2D 1000x1482, 64 levels", lambda: bench_nc2d(5)),
                 ("nc_tree", "non-convex trees 16384x256", lambda: bench_nc_tree(3)),
                 ("nc_concave", "concave pairwise chains 16384x256", lambda: bench_nc_concave(3)),
+                ("nc_tree_concave", "concave pairwise trees 16384x256", lambda: bench_nc_tree_concave(3)),
                 ("batched", "batched 256 images", bench_batched)]
         pick = None if args.extras == "all" else set(args.extras.split(","))
         try:

@@ -324,6 +324,27 @@ tv_status tv_tree_nc(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Concave pairwise terms on trees, Sec. 3 with Extensions (i): the trees of
+ * tv_tree_nc with the pairwise terms of tv_chain_nc_concave, z = x_parent(i)
+ * - x_i on the edge from node i to its parent (a chain numbered as a tree,
+ * parent(i) = i + 1, is the chain case).  One lane per tree.
+ *  tree_offsets, parent : as for tv_tree_nc (post-order, contiguous subtrees).
+ *  unary_offsets, ulam, uslope : as for tv_chain_nc.
+ *  piece_offsets, piece_alpha, piece_C, piece_side : as for
+ *                 tv_chain_nc_concave, node i's pieces being those of the edge
+ *                 to its parent (a root's pieces are ignored).
+ *  msg_cap, map_cap, stack_cap : as for tv_tree_nc.
+ * Synchronous.  Errors as tv_tree_nc. */
+size_t tv_tree_nc_concave_workspace(int64_t num_trees, int64_t num_nodes, int64_t num_pieces, int64_t msg_cap,
+                                    int64_t map_cap, int64_t stack_cap);
+tv_status tv_tree_nc_concave(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, int64_t num_pieces,
+                             const int64_t *tree_offsets, const int64_t *parent, const int64_t *unary_offsets,
+                             const void *ulam, const void *uslope, const int64_t *piece_offsets,
+                             const void *piece_alpha, const void *piece_C, const int32_t *piece_side, void *x,
+                             int64_t msg_cap, int64_t map_cap, int64_t stack_cap, void *workspace,
+                             size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Non-convex 2D, Sec. 5.3: on an H x W grid minimise
  *     sum_horizontal min(w_h |x_i - x_j|, C) + sum_vertical min(w_v |x_i - x_j|, C)
  *       + sum_i f_i(x_i),

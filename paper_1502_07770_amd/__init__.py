@@ -9,10 +9,10 @@ ABI; ``synth`` draws the seeded synthetic workloads.
 """
 from .binding import (Tv2dSolver, TvChainError, chain_dp, chain_prox, chain_prox_backward,  # noqa: F401
                       chain_prox_l1,
-                      chain_nc, chain_nc_concave, chain_prox_multi, load, prox, tree_dp, tree_nc, tv2d, tv2d_batched,
+                      chain_nc, chain_nc_concave, chain_prox_multi, load, prox, tree_dp, tree_nc,
+                      tree_nc_concave, tv2d, tv2d_batched,
                       tv2d_l1, tv2d_nc)
 
 __all__ = ["Tv2dSolver", "TvChainError", "chain_dp", "chain_prox", "chain_prox_l1", "chain_prox_backward",
-           "chain_nc", "chain_nc_concave", "chain_prox_multi", "load", "prox", "tree_dp", "tree_nc", "tv2d",
-           "tv2d_batched",
-           "tv2d_l1", "tv2d_nc"]
+           "chain_nc", "chain_nc_concave", "chain_prox_multi", "load", "prox", "tree_dp", "tree_nc",
+           "tree_nc_concave", "tv2d", "tv2d_batched", "tv2d_l1", "tv2d_nc"]

@@ -109,6 +109,9 @@ _SIG = {
     "tv_chain_nc_concave_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64, _I64]),
     "tv_chain_nc_concave": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                            _I64, _I64, _P, ctypes.c_size_t, _P]),
+    "tv_tree_nc_concave_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64, _I64, _I64]),
+    "tv_tree_nc_concave": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                          _I64, _I64, _I64, _P, ctypes.c_size_t, _P]),
     "tv_tree_nc_workspace": (ctypes.c_size_t, [_I64, _I64, _I64, _I64, _I64]),
     "tv_tree_nc": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _I64, _I64, _P,
                                   ctypes.c_size_t, _P]),
@@ -781,6 +784,57 @@ def chain_nc_concave(chain_offsets: torch.Tensor, unary_offsets: torch.Tensor, u
                                  _ptr(piece_side), _ptr(x), msg_cap, map_cap, _ptr(ws), nbytes,
                                  ctypes.c_void_p(_stream_ptr(ulam.device)))
     _check(st, "tv_chain_nc_concave")
+    return x
+
+
+def tree_nc_concave(parent: torch.Tensor, tree_offsets: torch.Tensor, unary_offsets: torch.Tensor,
+                    ulam: torch.Tensor, uslope: torch.Tensor, piece_offsets: torch.Tensor,
+                    piece_alpha: torch.Tensor, piece_C: torch.Tensor, piece_side: torch.Tensor,
+                    msg_cap: int = 256, map_cap: Optional[int] = None,
+                    stack_cap: Optional[int] = None) -> torch.Tensor:
+    """Sec. 3 Extensions (i) on trees (tv_tree_nc_concave): the trees of tree_nc
+    with the pieces of chain_nc_concave on the edge from each node to its parent
+    (z = x_parent - x_i).  Defaults: 8 intervals per piece of the tree with the
+    most pieces (at least 64), room for min(64, largest tree) waiting messages
+    of msg_cap breakpoints.  Returns x."""
+    _require_gpu(parent, tree_offsets, unary_offsets, ulam, uslope, piece_offsets, piece_alpha, piece_C, piece_side)
+    lib = load()
+    for t in (parent, tree_offsets, unary_offsets, piece_offsets):
+        if t.dtype != torch.int64:
+            raise TvChainError(TV_ERR_INVALID_ARG, "parent and offsets must be int64")
+    if piece_side.dtype != torch.int32:
+        raise TvChainError(TV_ERR_INVALID_ARG, "piece_side must be int32")
+    ts = [t.contiguous() for t in (ulam, uslope, piece_alpha, piece_C)]
+    for t in ts:
+        if t.dtype != ulam.dtype:
+            raise TvChainError(TV_ERR_INVALID_ARG, "float arrays must share one dtype")
+    N = parent.numel()
+    P = ts[2].numel()
+    if unary_offsets.numel() != N + 1 or piece_offsets.numel() != N + 1 or ts[3].numel() != P or \
+            piece_side.numel() != P:
+        raise TvChainError(TV_ERR_INVALID_ARG, "arrays do not match the nodes")
+    parent, tree_offsets = parent.contiguous(), tree_offsets.contiguous()
+    unary_offsets, piece_offsets, piece_side = (unary_offsets.contiguous(), piece_offsets.contiguous(),
+                                                piece_side.contiguous())
+    T = tree_offsets.numel() - 1
+    to = tree_offsets.cpu()
+    biggest = int((to[1:] - to[:-1]).max().item()) if T > 0 else 1
+    if map_cap is None:
+        po = piece_offsets.cpu()
+        most = int((po[to[1:]] - po[to[:-1]]).max().item()) if T > 0 else 1
+        map_cap = max(64, 8 * most)
+    if stack_cap is None:
+        stack_cap = max(1, min(64, biggest)) * (2 * msg_cap + 1)
+    x = torch.empty(N, dtype=ulam.dtype, device=ulam.device)
+    nbytes = lib.tv_tree_nc_concave_workspace(T, N, P, msg_cap, map_cap, stack_cap)
+    if nbytes == 0:
+        raise TvChainError(TV_ERR_INVALID_ARG, "tv_tree_nc_concave_workspace")
+    ws = _workspace(nbytes, ulam.device)
+    st = lib.tv_tree_nc_concave(_dtype_code(ulam), T, N, P, _ptr(tree_offsets), _ptr(parent), _ptr(unary_offsets),
+                                _ptr(ts[0]), _ptr(ts[1]), _ptr(piece_offsets), _ptr(ts[2]), _ptr(ts[3]),
+                                _ptr(piece_side), _ptr(x), msg_cap, map_cap, stack_cap, _ptr(ws), nbytes,
+                                ctypes.c_void_p(_stream_ptr(ulam.device)))
+    _check(st, "tv_tree_nc_concave")
     return x
 
 

@@ -1360,6 +1360,193 @@ size_t ncg_layout(int64_t num_chains, int64_t num_pieces, int64_t msg_cap, int64
     return off;
 }
 
+// The concave pairwise terms on a batch of trees: k_nc_tree's post-order walk
+// with its children's messages on a stack, each outgoing message taken through
+// the pieces of the edge to the parent (z = x_parent - x_i) by nc_side, and
+// pushed onto the stack from its forward or reversed view.
+struct NcgTreeArgs {
+    NcTreeArgs t;  // eoff unused
+    int64_t num_pieces;
+    const int64_t *poff;
+    int64_t *pmap;  // per piece: its interval range [pmap[2k], pmap[2k + 1])
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_nc_tree_concave(NcgTreeArgs G, const T *__restrict__ ulam,
+                                                        const T *__restrict__ uslope, const T *__restrict__ palpha,
+                                                        const T *__restrict__ pC,
+                                                        const int32_t *__restrict__ pside, T *__restrict__ x,
+                                                        int lanes) {
+    const NcTreeArgs &A = G.t;
+    if ((int)threadIdx.x >= lanes) return;
+    const int64_t tr = (int64_t)blockIdx.x * lanes + threadIdx.x;
+    if (tr >= A.num_trees) return;
+    const int64_t n0 = A.toff[tr], n1 = A.toff[tr + 1];
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {
+        atomicOr(A.flag, kNcFlagInvalid);
+        return;
+    }
+    if (n1 == n0) return;
+    const int64_t bstride = 2 * A.msg_cap + 1;
+    double *base = A.bufs + tr * 3 * bstride;
+    NcBuf H{base, base + A.msg_cap, 0, A.msg_cap};
+    NcBuf B{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap};
+    NcBuf U{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};  // the unary, staged
+    double *stk = A.stack + tr * A.stack_cap;
+    double *mb = A.maps + tr * 3 * A.map_cap;
+    NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    int64_t top = 0, sp = n0;
+    int bad = 0;
+    for (int64_t i = n0; i < n1 && !bad; ++i) {
+        const int64_t p = A.parent[i];
+        if (p != -1 && (p <= i || p >= n1)) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        const int64_t u0 = A.uoff[i], tu = A.uoff[i + 1] - u0;
+        if (tu < 1 || tu > A.msg_cap) {
+            bad = tu < 1 ? kNcFlagInvalid : kNcFlagCapacity;
+            break;
+        }
+        for (int64_t k = 0; k < tu; ++k) {
+            U.l[k] = (double)ulam[u0 + k];
+            if (k > 0 && !(U.l[k] >= U.l[k - 1])) bad = kNcFlagInvalid;
+        }
+        for (int64_t k = 0; k <= tu; ++k) U.s[k] = (double)uslope[u0 + i + k];
+        if (!(U.s[0] <= 0.0) || !(U.s[tu] >= 0.0)) bad = kNcFlagInvalid;
+        if (bad) break;
+        // hat = f_i (+ 0), then + each child's message from the top of the stack
+        B.t = 0;
+        B.s[0] = 0.0;
+        if (!nc_sum(U.l, U.s, tu, B, H)) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        while (sp > n0 && A.hparent[sp - 1] == i) {
+            --sp;
+            const int64_t cs = A.hstart[sp], ct = A.hcount[sp];
+            if (cs < 0 || cs + 2 * ct + 1 != top) {  // not right below: not a post-order numbering
+                bad = kNcFlagInvalid;
+                break;
+            }
+            const NcBuf child{stk + cs, stk + cs + ct, ct, ct};
+            if (!nc_sum(H.l, H.s, H.t, child, B)) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+            const NcBuf t = H;
+            H = B;
+            B = t;
+            top = cs;
+        }
+        if (bad) break;
+        if (p < 0) {  // a root: the first breakpoint attaining the minimum
+            double v = 0.0, vmin = 0.0, y = H.t > 0 ? H.l[0] : 0.0;
+            for (int64_t k = 1; k < H.t; ++k) {
+                v += H.s[k] * (H.l[k] - H.l[k - 1]);
+                if (v < vmin) {
+                    vmin = v;
+                    y = H.l[k];
+                }
+            }
+            x[i] = (T)y;
+            continue;
+        }
+        const int64_t k0 = G.poff[i], k1 = G.poff[i + 1];
+        if (k0 < 0 || k1 < k0 || k1 > G.num_pieces) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        NcBuf *cur = &H, *oth = &B;
+        bool rev = false;  // cur holds the reversal of the message
+        for (int64_t k = k0; k < k1; ++k) {
+            const double al = (double)palpha[k], cc = (double)pC[k];
+            const int sd = pside[k];
+            if (!(al >= 0.0) || !(al < HUGE_VAL) || !(cc >= 0.0) || !(cc < HUGE_VAL) || (sd != 1 && sd != -1)) {
+                bad = kNcFlagInvalid;
+                break;
+            }
+            G.pmap[2 * k] = mp.n;
+            bool ok;
+            auto fwd = [&](double lo, double hi, double to) { return mp.add(lo, hi, to); };
+            auto mir = [&](double lo, double hi, double to) { return mp.add(-hi, -lo, -to); };
+            if (sd > 0) {
+                ok = rev ? nc_side(NcRev{cur}, al, cc, *oth, fwd) : nc_side(NcFwd{cur}, al, cc, *oth, fwd);
+                rev = false;
+            } else {
+                ok = rev ? nc_side(NcFwd{cur}, al, cc, *oth, mir) : nc_side(NcRev{cur}, al, cc, *oth, mir);
+                rev = true;
+            }
+            G.pmap[2 * k + 1] = mp.n;
+            if (!ok) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+            NcBuf *sw = cur;
+            cur = oth;
+            oth = sw;
+        }
+        if (bad) break;
+        // push the message (forward) onto the stack: l then s, 2t + 1 doubles
+        const int64_t tm = cur->t, need = 2 * tm + 1;
+        if (top + need > A.stack_cap) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (rev) {
+            const NcRev r{cur};
+            for (int64_t k = 0; k < tm; ++k) stk[top + k] = r.l(k);
+            for (int64_t k = 0; k <= tm; ++k) stk[top + tm + k] = r.s(k);
+        } else {
+            for (int64_t k = 0; k < tm; ++k) stk[top + k] = cur->l[k];
+            for (int64_t k = 0; k <= tm; ++k) stk[top + tm + k] = cur->s[k];
+        }
+        A.hstart[sp] = top;
+        A.hcount[sp] = tm;
+        A.hparent[sp] = p;
+        ++sp;
+        top += need;
+    }
+    if (!bad && sp != n0) bad = kNcFlagInvalid;  // messages left for parents outside the tree
+    if (bad) {
+        atomicOr(A.flag, bad);
+        return;
+    }
+    for (int64_t i = n1 - 1; i >= n0; --i) {
+        const int64_t p = A.parent[i];
+        if (p < 0) continue;
+        double y = (double)x[p];
+        for (int64_t k = G.poff[i + 1] - 1; k >= G.poff[i]; --k) y = nc_apply(mp, G.pmap[2 * k], G.pmap[2 * k + 1], y);
+        x[i] = (T)y;
+    }
+}
+
+size_t ncg_tree_layout(int64_t num_trees, int64_t num_nodes, int64_t num_pieces, int64_t msg_cap, int64_t map_cap,
+                       int64_t stack_cap, void *p, NcgTreeArgs *G) {
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_b = off;  off += al(sizeof(double) * (size_t)(num_trees * 3 * (2 * msg_cap + 1)));
+    const size_t o_s = off;  off += al(sizeof(double) * (size_t)(num_trees * stack_cap));
+    const size_t o_m = off;  off += al(sizeof(double) * (size_t)(num_trees * 3 * map_cap));
+    const size_t o_h = off;  off += al(sizeof(int64_t) * (size_t)(3 * num_nodes));
+    const size_t o_p = off;  off += al(sizeof(int64_t) * (size_t)(2 * num_pieces));
+    const size_t o_f = off;  off += al(sizeof(int));
+    if (p && G) {
+        char *c = (char *)p;
+        G->t.bufs = (double *)(c + o_b);
+        G->t.stack = (double *)(c + o_s);
+        G->t.maps = (double *)(c + o_m);
+        int64_t *h = (int64_t *)(c + o_h);
+        G->t.hstart = h;
+        G->t.hcount = h + num_nodes;
+        G->t.hparent = h + 2 * num_nodes;
+        G->t.eoff = nullptr;
+        G->pmap = (int64_t *)(c + o_p);
+        G->t.flag = (int *)(c + o_f);
+    }
+    return off;
+}
+
 tv_status nc_finish(int *dflag, hipStream_t stream) {
     if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
     int flag = 0;
@@ -1554,6 +1741,56 @@ tv_status tv_chain_nc_concave(tv_dtype dtype, int64_t num_chains, int64_t num_no
                            (const double *)uslope, (const double *)piece_alpha, (const double *)piece_C, piece_side,
                            (double *)x, lanes);
     return nc_finish(A.flag, stream);
+}
+
+size_t tv_tree_nc_concave_workspace(int64_t num_trees, int64_t num_nodes, int64_t num_pieces, int64_t msg_cap,
+                                    int64_t map_cap, int64_t stack_cap) {
+    if (num_trees < 0 || num_nodes < 0 || num_pieces < 0 || msg_cap < 1 || map_cap < 1 || stack_cap < 1) return 0;
+    if (msg_cap > (int64_t(1) << 24) || map_cap > (int64_t(1) << 30) || stack_cap > (int64_t(1) << 34)) return 0;
+    return ncg_tree_layout(num_trees, num_nodes, num_pieces, msg_cap, map_cap, stack_cap, nullptr, nullptr);
+}
+
+tv_status tv_tree_nc_concave(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, int64_t num_pieces,
+                             const int64_t *tree_offsets, const int64_t *parent, const int64_t *unary_offsets,
+                             const void *ulam, const void *uslope, const int64_t *piece_offsets,
+                             const void *piece_alpha, const void *piece_C, const int32_t *piece_side, void *x,
+                             int64_t msg_cap, int64_t map_cap, int64_t stack_cap, void *workspace,
+                             size_t workspace_bytes, hipStream_t stream) {
+    if (dtype != TV_F32 && dtype != TV_F64) return TV_ERR_INVALID_ARG;
+    if (num_trees < 0 || num_nodes < 0 || num_pieces < 0 || num_trees >= (int64_t(1) << 31))
+        return TV_ERR_INVALID_ARG;
+    if (num_trees == 0) return TV_OK;
+    if (!tree_offsets || !parent || !unary_offsets || !ulam || !uslope || !piece_offsets || !x)
+        return TV_ERR_INVALID_ARG;
+    if (num_pieces > 0 && (!piece_alpha || !piece_C || !piece_side)) return TV_ERR_INVALID_ARG;
+    const size_t need = tv_tree_nc_concave_workspace(num_trees, num_nodes, num_pieces, msg_cap, map_cap, stack_cap);
+    if (need == 0) return TV_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < need) return TV_ERR_WORKSPACE;
+    NcgTreeArgs G;
+    G.t.num_trees = num_trees;
+    G.t.num_nodes = num_nodes;
+    G.t.toff = tree_offsets;
+    G.t.parent = parent;
+    G.t.uoff = unary_offsets;
+    G.t.msg_cap = msg_cap;
+    G.t.map_cap = map_cap;
+    G.t.stack_cap = stack_cap;
+    G.num_pieces = num_pieces;
+    G.poff = piece_offsets;
+    ncg_tree_layout(num_trees, num_nodes, num_pieces, msg_cap, map_cap, stack_cap, workspace, &G);
+    if (hipMemsetAsync(G.t.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
+    const int64_t spread = (num_trees + 1023) / 1024;
+    const int lanes = spread < 64 ? (int)spread : 64;
+    const dim3 grid((unsigned)((num_trees + lanes - 1) / lanes));
+    if (dtype == TV_F32)
+        hipLaunchKernelGGL((k_nc_tree_concave<float>), grid, dim3(64), 0, stream, G, (const float *)ulam,
+                           (const float *)uslope, (const float *)piece_alpha, (const float *)piece_C, piece_side,
+                           (float *)x, lanes);
+    else
+        hipLaunchKernelGGL((k_nc_tree_concave<double>), grid, dim3(64), 0, stream, G, (const double *)ulam,
+                           (const double *)uslope, (const double *)piece_alpha, (const double *)piece_C, piece_side,
+                           (double *)x, lanes);
+    return nc_finish(G.t.flag, stream);
 }
 
 }  // extern "C"

@@ -264,3 +264,12 @@ def test_nc_concave_argument_errors(lib):
                                    8, 8, None, 0, None) == binding.TV_ERR_INVALID_ARG
     assert lib.tv_chain_nc_concave(binding.TV_F64, 1 << 31, 4, 3, None, None, None, None, None, None, None, None,
                                    None, 8, 8, None, 0, None) == binding.TV_ERR_INVALID_ARG
+
+
+def test_nc_tree_concave_argument_errors(lib):
+    assert lib.tv_tree_nc_concave_workspace(4, 100, 300, 64, 256, 1000) > 0
+    assert lib.tv_tree_nc_concave_workspace(4, 100, 300, 64, 256, 0) == 0
+    assert lib.tv_tree_nc_concave(binding.TV_F64, 0, 0, 0, None, None, None, None, None, None, None, None, None,
+                                  None, 8, 8, 8, None, 0, None) == binding.TV_OK
+    assert lib.tv_tree_nc_concave(binding.TV_F64, 1, 4, 3, None, None, None, None, None, None, None, None, None,
+                                  None, 8, 8, 8, None, 0, None) == binding.TV_ERR_INVALID_ARG
