@@ -61,15 +61,20 @@ struct NcRev {
     __device__ __forceinline__ double s(int64_t k) const { return -b->s[b->t - k]; }
 };
 
-// The interval lists of one chain.
+// The interval list of one chain (tree): interval k is [p[3k], p[3k+1]] and
+// maps to p[3k+2], the three side by side so that a lane's appends and the
+// backward scan each walk one stream.
 struct NcMaps {
-    double *a, *b, *to;
+    double *p;
     int64_t n, cap;
+    __device__ __forceinline__ void put(int64_t k, double lo, double hi, double target) const {
+        p[3 * k] = lo;
+        p[3 * k + 1] = hi;
+        p[3 * k + 2] = target;
+    }
     __device__ __forceinline__ bool add(double lo, double hi, double target) {
         if (n >= cap) return false;
-        a[n] = lo;
-        b[n] = hi;
-        to[n] = target;
+        put(n, lo, hi, target);
         ++n;
         return true;
     }
@@ -247,7 +252,7 @@ __device__ bool nc_trunc(const View &h, double C, NcBuf &out, NcMaps &mp) {
 // pi(y) over intervals [lo, hi) of a list: the first interval containing y.
 __device__ __forceinline__ double nc_apply(const NcMaps &mp, int64_t lo, int64_t hi, double y) {
     for (int64_t k = lo; k < hi; ++k)
-        if (y >= mp.a[k] && y <= mp.b[k]) return mp.to[k];
+        if (y >= mp.p[3 * k] && y <= mp.p[3 * k + 1]) return mp.p[3 * k + 2];
     return y;
 }
 
@@ -256,7 +261,7 @@ struct NcArgs {
     const int64_t *coff, *uoff;
     int64_t msg_cap, map_cap;
     double *bufs;     // per chain: 3 buffers of (msg_cap + msg_cap + 1) doubles
-    double *maps;     // per chain: 3 arrays of map_cap doubles
+    double *maps;     // per chain: map_cap intervals of 3 doubles
     int64_t *eoff;    // per node: 3 offsets (Pi^1, Pi^2, Pi^3 of the edge leaving it)
     int *flag;
 };
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__
     NcBuf H{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap};
     NcBuf B{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};
     double *mb = A.maps + c * 3 * A.map_cap;
-    NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    NcMaps mp{mb, 0, A.map_cap};
     M.t = 0;
     M.s[0] = 0.0;
     // unary slopes are read in FP64; a small staging copy of one unary
@@ -608,9 +613,7 @@ __device__ int wv_dt(const WView &h, double w, double *ol, double *os, int cap, 
         const int64_t ipos = nmap + ibase + iinc - 1;
         if (close) {
             if (ipos < mp.cap) {
-                mp.a[ipos] = h.rev ? -ihi : ilo;
-                mp.b[ipos] = h.rev ? -ilo : ihi;
-                mp.to[ipos] = h.rev ? -ilo : ilo;
+                mp.put(ipos, h.rev ? -ihi : ilo, h.rev ? -ilo : ihi, h.rev ? -ilo : ilo);
             } else {
                 over = true;
             }
@@ -749,9 +752,7 @@ __device__ int wv_trunc(const WView &h, double C, double *ol, double *os, int ca
         auto put_end = [&](double e) {
             const int64_t ipos = nmap + ep;
             if (ipos < mp.cap && ep < W.tsize) {
-                mp.a[ipos] = W.T[ep];
-                mp.b[ipos] = e;
-                mp.to[ipos] = xm;
+                mp.put(ipos, W.T[ep], e, xm);
             } else {
                 over = true;
             }
@@ -767,9 +768,7 @@ __device__ int wv_trunc(const WView &h, double C, double *ol, double *os, int ca
         if (wv_lane() == 0) {
             const int64_t ipos = nmap + eb;
             if (ipos < mp.cap && eb < W.tsize) {
-                mp.a[ipos] = W.T[eb];
-                mp.b[ipos] = HUGE_VAL;
-                mp.to[ipos] = xm;
+                mp.put(ipos, W.T[eb], HUGE_VAL, xm);
             } else {
                 over = true;
             }
@@ -810,7 +809,7 @@ __global__ __launch_bounds__(64) void k_nc_wave(NcArgs A, const T *__restrict__ 
     const int lane = wv_lane();
     const int cap = (int)(A.msg_cap < kCap ? A.msg_cap : kCap);
     double *mb = A.maps + c * 3 * A.map_cap;
-    const NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    const NcMaps mp{mb, 0, A.map_cap};
     int64_t nmap = 0;
     int tm = 0, th = 0, bad = 0;
     if (lane == 0) sA_s[0] = 0.0;
@@ -941,7 +940,7 @@ struct NcTreeArgs {
     int64_t msg_cap, map_cap, stack_cap;
     double *bufs;      // per tree: 3 buffers of (2 msg_cap + 1) doubles
     double *stack;     // per tree: stack_cap doubles of pending messages (l then s)
-    double *maps;      // per tree: 3 arrays of map_cap doubles
+    double *maps;      // per tree: map_cap intervals of 3 doubles
     int64_t *hstart;   // [N] pending message: start in the stack
     int64_t *hcount;   //     breakpoints
     int64_t *hparent;  //     node it is for
@@ -969,7 +968,7 @@ __global__ __launch_bounds__(64) void k_nc_tree(NcTreeArgs A, const T *__restric
     NcBuf U{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};  // the unary, staged
     double *stk = A.stack + tr * A.stack_cap;
     double *mb = A.maps + tr * 3 * A.map_cap;
-    NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    NcMaps mp{mb, 0, A.map_cap};
     int64_t top = 0;   // stack fill (doubles)
     int64_t sp = n0;   // header stack pointer
     int bad = 0;
@@ -1223,7 +1222,7 @@ struct NcgArgs {
     const int64_t *coff, *uoff, *poff;
     int64_t msg_cap, map_cap;
     double *bufs;   // per chain: 3 buffers of (2 msg_cap + 1) doubles
-    double *maps;   // per chain: 3 arrays of map_cap doubles
+    double *maps;   // per chain: map_cap intervals of 3 doubles
     int64_t *pmap;  // per piece: its interval range [pmap[2k], pmap[2k + 1])
     int *flag;
 };
@@ -1252,7 +1251,7 @@ __global__ __launch_bounds__(64) void k_nc_concave(NcgArgs A, const T *__restric
     NcBuf Y{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap};
     NcBuf U{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};
     double *mb = A.maps + c * 3 * A.map_cap;
-    NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    NcMaps mp{mb, 0, A.map_cap};
     X.s[0] = 0.0;
     int bad = 0;
     for (int64_t i = n0; i < n1 && !bad; ++i) {
@@ -1394,7 +1393,7 @@ __global__ __launch_bounds__(64) void k_nc_tree_concave(NcgTreeArgs G, const T *
     NcBuf U{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};  // the unary, staged
     double *stk = A.stack + tr * A.stack_cap;
     double *mb = A.maps + tr * 3 * A.map_cap;
-    NcMaps mp{mb, mb + A.map_cap, mb + 2 * A.map_cap, 0, A.map_cap};
+    NcMaps mp{mb, 0, A.map_cap};
     int64_t top = 0, sp = n0;
     int bad = 0;
     for (int64_t i = n0; i < n1 && !bad; ++i) {
