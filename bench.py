@@ -390,7 +390,7 @@ def bench_nc_concave(steps: int):
     """Sec. 3 Extensions (i) (tv_chain_nc_concave): 16,384 chains of 256 nodes
     (concave_cost_chains), 16-level uniform [0, 4] costs, and on every edge
     min(|z|, 0.25 |z| + 1, 2.5), three pieces per side, FP32 in, FP64
-    messages.  Capacities from the oracle on 256 of the chains: messages up to
+    messages, msg_cap 128 (a wave per chain).  Capacities from the oracle on 256 of the chains: messages up to
     37 breakpoints, up to 4,857 intervals per chain."""
     import torch
     from paper_1502_07770_amd import binding, synth

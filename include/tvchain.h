@@ -277,8 +277,10 @@ tv_status tv_chain_nc(tv_dtype dtype, int64_t num_chains, int64_t num_nodes, con
  * non-decreasing concave for z > 0 (truncated TV: (w, 0) and (0, C) on both
  * sides; Potts: (0, C) on both sides).  A side without pieces makes f_i
  * infinite there (a hard order constraint).  The pieces are applied one at a
- * time (Prop. 2) by h (x) g = (h^alpha (x) g^alpha)^-alpha, exactly; one lane
- * per chain, FP64 messages in the workspace.
+ * time (Prop. 2) by h (x) g = (h^alpha (x) g^alpha)^-alpha, exactly, FP64:
+ * msg_cap <= 256 runs a wave per chain with the messages in LDS (<= 128: the
+ * smaller variant), larger msg_cap one lane per chain with the messages in
+ * the workspace.
  *  num_pieces    : total pieces (entries of piece_alpha, piece_C, piece_side).
  *  chain_offsets, unary_offsets, ulam, uslope : as for tv_chain_nc.
  *  piece_offsets : DEVICE int64 [num_nodes + 1]: node i's edge owns pieces

@@ -748,7 +748,9 @@ def chain_nc_concave(chain_offsets: torch.Tensor, unary_offsets: torch.Tensor, u
     pairwise term on the edge from node i to i + 1 is the minimum of the pieces
     piece_offsets[i] .. piece_offsets[i+1] - 1, alpha |z| + C on the side
     piece_side (+1: z = x_{i+1} - x_i > 0, -1: z < 0), and 0 at z = 0.
-    piece_offsets int64 (nodes + 1), piece_side int32.  map_cap defaults to 8
+    piece_offsets int64 (nodes + 1), piece_side int32.  msg_cap up to 256: a
+    wave per chain (128 or less: smaller LDS), larger: a lane per chain.
+    map_cap defaults to 8
     per piece of the chain with the most pieces (at least 64; about 3 per piece
     on 16-level cost chains).  Returns x."""
     _require_gpu(chain_offsets, unary_offsets, ulam, uslope, piece_offsets, piece_alpha, piece_C, piece_side)

@@ -1342,6 +1342,278 @@ __global__ __launch_bounds__(64) void k_nc_concave(NcgArgs A, const T *__restric
     }
 }
 
+// nc_side spread over a wave: with g = h - alpha x, the prefix minimum m of g
+// and its first argmin by a scan; per piece, whether g lies above m + C at its
+// two ends, which puts at most one crossing in it (g is linear there and m is
+// constant while g is above m + C); the output is flat in g's frame (slope
+// alpha) over the runs above m + C, each run mapping to the argmin.  A run is
+// closed at its down-crossing (or at +inf) and starts at the latest
+// up-crossing, found by a running maximum.  `mirror`: the view is the
+// reversal of the function, so intervals are reported mirrored.  Same
+// returns as wv_dt.
+__device__ int wv_side(const WView &h, double alpha, double C, bool mirror, double *ol, double *os, int cap,
+                       const NcMaps &mp, int64_t &nmap, const WScratch &W) {
+    const int t = h.t;
+    if (t == 0) {
+        if (wv_lane() == 0) os[0] = h.s(0);
+        __syncthreads();
+        return 0;
+    }
+    wv_values(h, W.V);
+    double cv = HUGE_VAL;
+    int ci = 0;
+    for (int c = 0; c * 64 < t; ++c) {
+        const int k = c * 64 + wv_lane();
+        double v = (k < t) ? W.V[k] - alpha * h.l(k) : HUGE_VAL;
+        int i = k;
+        wv_scan_min(v, i);
+        if (cv < v || (cv == v && ci < i)) {
+            v = cv;
+            i = ci;
+        }
+        if (k < t) {
+            W.PM[k] = v;
+            W.PA[k] = i;
+        }
+        cv = __shfl(v, 63, 64);
+        ci = __shfl(i, 63, 64);
+    }
+    __syncthreads();
+    // whether g lies above m + C at the start (end) of piece k >= 1
+    auto above_l = [&](int k) { return W.V[k - 1] - alpha * h.l(k - 1) > W.PM[k - 1] + C; };
+    auto above_r = [&](int k) {
+        if (k < t) return W.V[k] - alpha * h.l(k) > W.PM[k - 1] + C;
+        const double sg = h.s(t) - alpha;  // the unbounded right piece
+        return above_l(k) ? sg >= 0.0 : sg > 0.0;
+    };
+    for (int k = wv_lane(); k <= t; k += 64) {
+        double ps = h.s(0), pe = h.s(0);
+        if (k > 0) {
+            const double sk = h.s(k);
+            ps = above_l(k) ? alpha : sk;
+            pe = above_r(k) ? alpha : sk;
+        }
+        W.PS[k] = ps;
+        W.PE[k] = pe;
+    }
+    __syncthreads();
+    int base = 0, ibase = 0;
+    bool over = false;
+    double start = -HUGE_VAL;  // the latest up-crossing so far
+    for (int c = 0; c * 64 < t; ++c) {
+        const int k = 1 + c * 64 + wv_lane();
+        const bool in = k <= t;
+        bool e1 = false, e2 = false, up = false, close = false;
+        double y = 0.0, ihi = 0.0, ito = 0.0;
+        if (in) {
+            e1 = W.PE[k - 1] != W.PS[k];
+            const bool al = above_l(k), ar = above_r(k);
+            const double L = h.l(k - 1), sg = h.s(k) - alpha;
+            if (al != ar) {  // one crossing of m + C in the piece
+                y = L + (W.PM[k - 1] + C - (W.V[k - 1] - alpha * L)) / sg;
+                if (y < L) y = L;
+                if (k < t && y > h.l(k)) y = h.l(k);
+                e2 = true;
+                up = ar;
+                if (al) {
+                    close = true;
+                    ihi = y;
+                } else if (k == t) {  // up in the unbounded piece: above to +inf
+                    close = true;
+                    ihi = HUGE_VAL;
+                }
+            } else if (k == t && ar) {
+                close = true;  // above to +inf
+                ihi = HUGE_VAL;
+            }
+            if (close) ito = h.l(W.PA[k - 1]);
+        }
+        double nv = up ? -y : HUGE_VAL;  // running maximum of the up-crossings
+        int ni = k;
+        wv_scan_min(nv, ni);
+        double st = -nv;
+        if (start > st) st = start;
+        const int cnt = (e1 ? 1 : 0) + (e2 ? 1 : 0);
+        const int inc = wv_scan_int(cnt);
+        int pos = base + inc - cnt;
+        if (e1) {
+            if (pos < cap) {
+                ol[pos] = h.l(k - 1);
+                os[pos + 1] = W.PS[k];
+            }
+            ++pos;
+        }
+        if (e2 && pos < cap) {
+            ol[pos] = y;
+            os[pos + 1] = W.PE[k];
+        }
+        base += __shfl(inc, 63, 64);
+        start = __shfl(st, 63, 64);
+        const int iinc = wv_scan_int(close ? 1 : 0);
+        const int64_t ipos = nmap + ibase + iinc - 1;
+        if (close) {
+            if (ipos < mp.cap) {
+                if (mirror)
+                    mp.put(ipos, -ihi, -st, -ito);
+                else
+                    mp.put(ipos, st, ihi, ito);
+            } else {
+                over = true;
+            }
+        }
+        ibase += __shfl(iinc, 63, 64);
+    }
+    if (wv_lane() == 0) os[0] = W.PS[0];
+    nmap += ibase;
+    const bool any_over = __ballot(over) != 0;
+    __syncthreads();
+    if (any_over) return -2;
+    return base <= cap ? base : -1;
+}
+
+// A wave per chain: k_nc_wave's node loop (Lemma 1 by wv_sum, the next unary
+// prefetched into registers) with each edge's pieces applied by wv_side,
+// ping-ponging between two LDS buffers; the message is stored forward for the
+// next node.  Backward by one lane through every piece's mapping.
+template <typename T, int kCap>
+__global__ __launch_bounds__(64) void k_nc_wave_concave(NcgArgs A, const T *__restrict__ ulam,
+                                                        const T *__restrict__ uslope, const T *__restrict__ palpha,
+                                                        const T *__restrict__ pC,
+                                                        const int32_t *__restrict__ pside, T *__restrict__ x) {
+    static_assert(kCap % 64 == 0 && kCap <= kWaveMsg, "wave message capacity");
+    __shared__ double sU_l[kCap], sU_s[kCap + 1];
+    __shared__ double sA_l[kCap], sA_s[kCap + 1];
+    __shared__ double sB_l[kCap], sB_s[kCap + 1];
+    __shared__ double sC_l[kCap], sC_s[kCap + 1];
+    __shared__ double sT[2 * kCap], sV[kCap], sPM[kCap], sPS[kCap + 1], sPE[kCap + 1];
+    __shared__ int sPA[kCap], sQ0[kCap + 1], sQ1[kCap + 1];
+    static_assert(2 * sizeof(int) == sizeof(double), "two counts per double");
+    const WScratch W{2 * kCap, sT, (int *)sV, (int *)sPM, sV, sPM, sPA, sPS, sPE, sQ0, sQ1};
+    const int64_t c = blockIdx.x;
+    if (c >= A.num_chains) return;
+    const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {
+        if (threadIdx.x == 0) atomicOr(A.flag, kNcFlagInvalid);
+        return;
+    }
+    if (n1 == n0) return;
+    const int lane = wv_lane();
+    const int cap = (int)(A.msg_cap < kCap ? A.msg_cap : kCap);
+    double *mb = A.maps + c * 3 * A.map_cap;
+    const NcMaps mp{mb, 0, A.map_cap};
+    int64_t nmap = 0;
+    int tm = 0, th = 0, bad = 0;
+    if (lane == 0) sA_s[0] = 0.0;
+    constexpr int kPer = kCap / 64;
+    double pl[kPer], ps[kPer + 1];
+    auto fetch = [&](int64_t i) {
+        const int64_t u0 = A.uoff[i], tu = A.uoff[i + 1] - u0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = lane + 64 * j;
+            pl[j] = (k < tu && tu <= cap) ? (double)ulam[u0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j <= kPer; ++j) {
+            const int k = lane + 64 * j;
+            ps[j] = (k <= tu && tu <= cap) ? (double)uslope[u0 + i + k] : 0.0;
+        }
+    };
+    fetch(n0);
+    __syncthreads();
+    for (int64_t i = n0; i < n1; ++i) {
+        const int64_t u0 = A.uoff[i], tu64 = A.uoff[i + 1] - u0;
+        if (tu64 < 1 || tu64 > cap) {
+            bad = tu64 < 1 ? kNcFlagInvalid : kNcFlagCapacity;
+            break;
+        }
+        const int tu = (int)tu64;
+        bool inval = false;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = lane + 64 * j;
+            if (k < tu) sU_l[k] = pl[j];
+        }
+#pragma unroll
+        for (int j = 0; j <= kPer; ++j) {
+            const int k = lane + 64 * j;
+            if (k <= tu) sU_s[k] = ps[j];
+        }
+        if (i + 1 < n1) fetch(i + 1);
+        __syncthreads();
+        for (int k = lane; k < tu; k += 64)
+            if (k > 0 && !(sU_l[k] >= sU_l[k - 1])) inval = true;
+        if (lane == 0 && (!(sU_s[0] <= 0.0) || !(sU_s[tu] >= 0.0))) inval = true;
+        if (__ballot(inval) != 0) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        th = wv_sum(sU_l, sU_s, tu, sA_l, sA_s, tm, sB_l, sB_s, cap, W);
+        if (th < 0) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (i == n1 - 1) break;
+        const int64_t k0 = A.poff[i], k1 = A.poff[i + 1];
+        if (k0 < 0 || k1 < k0 || k1 > A.num_pieces) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        double *cl = sB_l, *cs = sB_s, *ol = sC_l, *os = sC_s;
+        int tc = th;
+        bool rev = false;  // the current buffer holds the reversal of the message
+        for (int64_t k = k0; k < k1 && !bad; ++k) {
+            const double al = (double)palpha[k], cc = (double)pC[k];
+            const int sd = pside[k];
+            if (!(al >= 0.0) || !(al < HUGE_VAL) || !(cc >= 0.0) || !(cc < HUGE_VAL) || (sd != 1 && sd != -1)) {
+                bad = kNcFlagInvalid;
+                break;
+            }
+            if (lane == 0) A.pmap[2 * k] = nmap;
+            // right side: the function itself; left side: its reversal
+            const bool want_rev = sd < 0;
+            const int to = wv_side(WView{cl, cs, tc, rev != want_rev}, al, cc, want_rev, ol, os, cap, mp, nmap, W);
+            if (lane == 0) A.pmap[2 * k + 1] = nmap;
+            if (to < 0) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+            rev = want_rev;
+            tc = to;
+            double *sw = cl;
+            cl = ol;
+            ol = sw;
+            sw = cs;
+            cs = os;
+            os = sw;
+        }
+        if (bad) break;
+        const WView fin{cl, cs, tc, rev};  // the message, stored forward in A
+        for (int k = lane; k < tc; k += 64) sA_l[k] = fin.l(k);
+        for (int k = lane; k <= tc; k += 64) sA_s[k] = fin.s(k);
+        tm = tc;
+        __syncthreads();
+    }
+    if (bad) {
+        if (lane == 0) atomicOr(A.flag, bad);
+        return;
+    }
+    if (lane != 0) return;
+    double v = 0.0, vmin = 0.0, y = th > 0 ? sB_l[0] : 0.0;
+    for (int k = 1; k < th; ++k) {
+        v += sB_s[k] * (sB_l[k] - sB_l[k - 1]);
+        if (v < vmin) {
+            vmin = v;
+            y = sB_l[k];
+        }
+    }
+    x[n1 - 1] = (T)y;
+    for (int64_t i = n1 - 2; i >= n0; --i) {
+        for (int64_t k = A.poff[i + 1] - 1; k >= A.poff[i]; --k) y = nc_apply(mp, A.pmap[2 * k], A.pmap[2 * k + 1], y);
+        x[i] = (T)y;
+    }
+}
+
 size_t ncg_layout(int64_t num_chains, int64_t num_pieces, int64_t msg_cap, int64_t map_cap, void *p, NcgArgs *A) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     size_t off = 0;
@@ -1728,6 +2000,29 @@ tv_status tv_chain_nc_concave(tv_dtype dtype, int64_t num_chains, int64_t num_no
     A.map_cap = map_cap;
     ncg_layout(num_chains, num_pieces, msg_cap, map_cap, workspace, &A);
     if (hipMemsetAsync(A.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
+    if (msg_cap <= kWaveMsg) {  // a wave per chain, messages in LDS
+        const dim3 gw((unsigned)num_chains);
+        if (dtype == TV_F32) {
+            if (msg_cap <= 128)
+                hipLaunchKernelGGL((k_nc_wave_concave<float, 128>), gw, dim3(64), 0, stream, A, (const float *)ulam,
+                                   (const float *)uslope, (const float *)piece_alpha, (const float *)piece_C,
+                                   piece_side, (float *)x);
+            else
+                hipLaunchKernelGGL((k_nc_wave_concave<float, kWaveMsg>), gw, dim3(64), 0, stream, A,
+                                   (const float *)ulam, (const float *)uslope, (const float *)piece_alpha,
+                                   (const float *)piece_C, piece_side, (float *)x);
+        } else {
+            if (msg_cap <= 128)
+                hipLaunchKernelGGL((k_nc_wave_concave<double, 128>), gw, dim3(64), 0, stream, A,
+                                   (const double *)ulam, (const double *)uslope, (const double *)piece_alpha,
+                                   (const double *)piece_C, piece_side, (double *)x);
+            else
+                hipLaunchKernelGGL((k_nc_wave_concave<double, kWaveMsg>), gw, dim3(64), 0, stream, A,
+                                   (const double *)ulam, (const double *)uslope, (const double *)piece_alpha,
+                                   (const double *)piece_C, piece_side, (double *)x);
+        }
+        return nc_finish(A.flag, stream);
+    }
     const int64_t spread = (num_chains + 1023) / 1024;
     const int lanes = spread < 64 ? (int)spread : 64;
     const dim3 grid((unsigned)((num_chains + lanes - 1) / lanes));
