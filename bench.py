@@ -407,6 +407,25 @@ def bench_nc_concave(steps: int):
                         "2.5), FP32 in, FP64 messages", "ms": round(ms, 2), "mnode_s": round(N / ms / 1e3, 2)}
 
 
+def bench_nc_concave_rows(steps: int):
+    """Sec. 3 Extensions (i) on the 1000 rows (1482 nodes, 64 levels) of the
+    synthetic cost volume (concave_cost_volume_rows) with min(0.6 |z|,
+    0.15 |z| + 1, 2) on every edge, FP32 in, msg_cap 256 (a wave per row)."""
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    coff, (uoff, ulam, usl), (poff, al, cc, sd) = synth.concave_cost_volume_rows(1000, 1482, 64, seed=1)
+    f32 = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")  # noqa: E731
+    i64 = lambda a: torch.tensor(a, dtype=torch.int64, device="cuda")  # noqa: E731
+    args = (i64(coff), i64(uoff), f32(ulam), f32(usl), i64(poff), f32(al), f32(cc),
+            torch.tensor(sd, dtype=torch.int32, device="cuda"))
+    run = lambda: binding.chain_nc_concave(*args, msg_cap=256, map_cap=64 * 1482)  # noqa: E731
+    run()
+    ms = Timer(torch, torch.cuda.current_stream())(run, steps)
+    N = int(coff[-1])
+    return {"workload": "1000 cost-volume rows x 1482 nodes, 64 levels, pairwise min(0.6|z|, 0.15|z| + 1, 2), "
+                        "FP32 in, FP64 messages", "ms": round(ms, 2), "mnode_s": round(N / ms / 1e3, 2)}
+
+
 def bench_nc_tree_concave(steps: int):
     """Sec. 3 Extensions (i) on trees (tv_tree_nc_concave): the 16,384 trees of
     bench_nc_tree (post_order_forest, seed 7) with the unaries and pairwise
@@ -616,7 +635,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
                     help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,nc,"
-                         "nc2d,nc_tree,nc_concave,nc_tree_concave,batched")
+                         "nc2d,nc_tree,nc_concave,nc_tree_concave,nc_concave_rows,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -705,6 +724,7 @@ def main():
                 ("nc_tree", "non-convex trees 16384x256", lambda: bench_nc_tree(3)),
                 ("nc_concave", "concave pairwise chains 16384x256", lambda: bench_nc_concave(3)),
                 ("nc_tree_concave", "concave pairwise trees 16384x256", lambda: bench_nc_tree_concave(3)),
+                ("nc_concave_rows", "concave pairwise cost-volume rows 1000x1482", lambda: bench_nc_concave_rows(3)),
                 ("batched", "batched 256 images", bench_batched)]
         pick = None if args.extras == "all" else set(args.extras.split(","))
         try:

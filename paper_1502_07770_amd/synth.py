@@ -222,3 +222,19 @@ def concave_cost_chains(num_chains: int, n: int, D: int, seed: int = 0, steep: f
     unaries = (np.arange(N + 1, dtype=np.int64) * D, np.tile(np.arange(D, dtype=np.float64), N), sl.reshape(-1))
     pcs = (np.arange(N + 1, dtype=np.int64) * k, np.tile(al, N), np.tile(cc, N), np.tile(sd, N))
     return np.arange(int(num_chains) + 1, dtype=np.int64) * int(n), unaries, pcs
+
+
+def concave_cost_volume_rows(H: int, W: int, D: int, seed: int = 0,
+                             pieces=((0.6, 0.0), (0.15, 1.0), (0.0, 2.0))):
+    """The rows of cost_volume_chains() with, on every edge, the pairwise term
+    min over `pieces` (alpha, C) of alpha |z| + C on both sides (default:
+    min(0.6 |z|, 0.15 |z| + 1, 2)).  Returns chain_offsets, (unary offsets,
+    ulam, uslope) and (piece offsets, alpha, C, side int32)."""
+    coff, uoff, ulam, usl, _ = cost_volume_chains(H, W, D, seed=seed)
+    N = uoff.size - 1
+    k = 2 * len(pieces)
+    al = np.array([a for a, _ in pieces] * 2, dtype=np.float64)
+    cc = np.array([c for _, c in pieces] * 2, dtype=np.float64)
+    sd = np.array([1] * len(pieces) + [-1] * len(pieces), dtype=np.int32)
+    pcs = (np.arange(N + 1, dtype=np.int64) * k, np.tile(al, N), np.tile(cc, N), np.tile(sd, N))
+    return coff, (uoff, ulam, usl), pcs

@@ -177,3 +177,14 @@ def test_special_piece_sets(kind):
             assert np.all(np.diff(seg) >= 0)
         if kind == "equal":
             assert np.all(seg == seg[0])
+
+
+def test_cost_volume_rows_sampled():
+    """The 1000 rows (1482 nodes, 64 levels) of the synthetic cost volume with
+    min(0.6 |z|, 0.15 |z| + 1, 2), FP32 in, in the benchmark's launch (a wave
+    per row); 24 sampled rows checked."""
+    coff, u, p = synth.concave_cost_volume_rows(1000, 1482, 64, seed=1)
+    u = (u[0], _f32(u[1]), _f32(u[2]))
+    x = _run(coff, u, p, torch.float32, msg_cap=256, map_cap=64 * 1482)
+    pick = np.sort(np.random.default_rng(56).choice(1000, 24, replace=False))
+    _check(coff, u, p, x, pick, 1e-6, 8 * 2.0 ** -23 * 70)
