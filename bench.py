@@ -449,6 +449,37 @@ def bench_nc_tree_concave(steps: int):
             "mnode_s": round(N / ms / 1e3, 2)}
 
 
+def bench_nc_tree_small(steps: int):
+    """Sec. 3 non-convex trees, a small batch: 512 post-order trees of 256 nodes
+    (fewer trees than SIMDs), 8-level uniform [0, 4] costs, truncated TV
+    w = 0.5, C = 2, FP32 in.  The oracle finds messages of at most 140
+    breakpoints, so msg_cap 256 runs a wave per tree; msg_cap 512 the lane
+    kernel on the same trees, for comparison."""
+    import numpy as np
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    T, n, D = 512, 256, 8
+    par, off = synth.post_order_forest(T, n, seed=7)
+    N = par.size
+    g = synth.generator(8)
+    cost = g.uniform(0, 4, (N, D))
+    sl = np.empty((N, D + 1))
+    sl[:, 0], sl[:, D] = -10.0, 10.0
+    sl[:, 1:D] = np.diff(cost, axis=1)
+    dev = lambda a, t=torch.float32: torch.tensor(a, dtype=t, device="cuda")  # noqa: E731
+    args = (dev(par, torch.int64), dev(off, torch.int64), dev(np.arange(N + 1, dtype=np.int64) * D, torch.int64),
+            dev(np.tile(np.arange(D, dtype=np.float64), N)), dev(sl.reshape(-1)), dev(np.full(N, 0.5)),
+            dev(np.full(N, 2.0)))
+    out = {"workload": "512 post-order trees x 256 nodes, 8-level uniform random costs, truncated TV w 0.5, C 2, "
+                       "FP32 in, FP64 messages"}
+    for name, cap in (("ms", 256), ("ms_lane", 512)):
+        run = lambda: binding.tree_nc(*args, msg_cap=cap, map_cap=32 * n)  # noqa: E731
+        run()
+        out[name] = round(Timer(torch, torch.cuda.current_stream())(run, steps), 2)
+    out["mnode_s"] = round(N / out["ms"] / 1e3, 2)
+    return out
+
+
 def bench_nc_tree(steps: int):
     """Sec. 3 non-convex trees (tv_tree_nc): 16,384 random post-order trees of
     256 nodes (post_order_forest), unaries through uniform [0, 4] costs at 16
@@ -635,7 +666,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
                     help="comma-separated subset of tv2d_512,tv2d_4096,adjoint,general_dp,tv_l1,tv2d_l1,tree,nc,"
-                         "nc2d,nc_tree,nc_concave,nc_tree_concave,nc_concave_rows,batched")
+                         "nc2d,nc_tree,nc_tree_small,nc_concave,nc_tree_concave,nc_concave_rows,batched")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -722,6 +753,7 @@ def main():
                 ("nc", "non-convex chains 1000x1482, 64 levels", lambda: bench_nc(3)),
                 ("nc2d", "non-convex 2D 1000x1482, 64 levels", lambda: bench_nc2d(5)),
                 ("nc_tree", "non-convex trees 16384x256", lambda: bench_nc_tree(3)),
+                ("nc_tree_small", "non-convex trees 512x256", lambda: bench_nc_tree_small(3)),
                 ("nc_concave", "concave pairwise chains 16384x256", lambda: bench_nc_concave(3)),
                 ("nc_tree_concave", "concave pairwise trees 16384x256", lambda: bench_nc_tree_concave(3)),
                 ("nc_concave_rows", "concave pairwise cost-volume rows 1000x1482", lambda: bench_nc_concave_rows(3)),

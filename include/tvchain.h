@@ -305,8 +305,9 @@ tv_status tv_chain_nc_concave(tv_dtype dtype, int64_t num_chains, int64_t num_no
  * Non-convex trees, Sec. 3: a batch of trees, each minimising
  *     sum_i f_i(x_i) + sum_{i not a root} min(w_i |x_parent(i) - x_i|, C_i)
  * with f_i as for tv_chain_nc; a node's message is its unary plus its
- * children's messages (Lemma 1), min-convolved with its edge (Lemma 2), one
- * lane per tree.
+ * children's messages (Lemma 1), min-convolved with its edge (Lemma 2): a
+ * wave per tree (messages in LDS) when there are fewer than 1024 trees and
+ * msg_cap <= 256, else one lane per tree.
  *  tree_offsets : DEVICE int64 [num_trees + 1] node ranges within [0, num_nodes];
  *                 each tree numbered in depth-first post-order.
  *  parent       : DEVICE int64 [num_nodes], global index of the parent (in the

@@ -1091,6 +1091,174 @@ __global__ __launch_bounds__(64) void k_nc_tree(NcTreeArgs A, const T *__restric
     }
 }
 
+// A wave per tree, for batches with fewer trees than SIMDs: k_nc_tree's
+// post-order walk with every pass spread over the wave (wv_sum for Lemma 1,
+// reading each child's message straight from the tree's stack; wv_dt twice
+// and wv_trunc for the edge), the working messages in LDS.  Every lane writes
+// the stack headers (the same values), so each reads back its own writes; the
+// pushed message itself is visible to the wave after the barrier.
+template <typename T, int kCap>
+__global__ __launch_bounds__(64) void k_nc_tree_wave(NcTreeArgs A, const T *__restrict__ ulam,
+                                                     const T *__restrict__ uslope, const T *__restrict__ w,
+                                                     const T *__restrict__ C, T *__restrict__ x) {
+    static_assert(kCap % 64 == 0 && kCap <= kWaveMsg, "wave message capacity");
+    __shared__ double sU_l[kCap], sU_s[kCap + 1];
+    __shared__ double sA_l[kCap], sA_s[kCap + 1];
+    __shared__ double sB_l[kCap], sB_s[kCap + 1];
+    __shared__ double sC_l[kCap], sC_s[kCap + 1];
+    __shared__ double sT[2 * kCap], sV[kCap], sPM[kCap], sPS[kCap + 1], sPE[kCap + 1];
+    __shared__ int sPA[kCap], sQ0[kCap + 1], sQ1[kCap + 1];
+    static_assert(2 * sizeof(int) == sizeof(double), "two counts per double");
+    const WScratch W{2 * kCap, sT, (int *)sV, (int *)sPM, sV, sPM, sPA, sPS, sPE, sQ0, sQ1};
+    const int64_t tr = blockIdx.x;
+    if (tr >= A.num_trees) return;
+    const int64_t n0 = A.toff[tr], n1 = A.toff[tr + 1];
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {
+        if (threadIdx.x == 0) atomicOr(A.flag, kNcFlagInvalid);
+        return;
+    }
+    if (n1 == n0) return;
+    const int lane = wv_lane();
+    const int cap = (int)(A.msg_cap < kCap ? A.msg_cap : kCap);
+    double *stk = A.stack + tr * A.stack_cap;
+    double *mb = A.maps + tr * 3 * A.map_cap;
+    const NcMaps mp{mb, 0, A.map_cap};
+    int64_t nmap = 0, top = 0, sp = n0;
+    int bad = 0;
+    for (int64_t i = n0; i < n1; ++i) {
+        const int64_t p = A.parent[i];
+        if (p != -1 && (p <= i || p >= n1)) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        const int64_t u0 = A.uoff[i], tu64 = A.uoff[i + 1] - u0;
+        if (tu64 < 1 || tu64 > cap) {
+            bad = tu64 < 1 ? kNcFlagInvalid : kNcFlagCapacity;
+            break;
+        }
+        const int tu = (int)tu64;
+        for (int k = lane; k < tu; k += 64) sU_l[k] = (double)ulam[u0 + k];
+        for (int k = lane; k <= tu; k += 64) sU_s[k] = (double)uslope[u0 + i + k];
+        if (lane == 0) sA_s[0] = 0.0;  // an empty message
+        __syncthreads();
+        bool inval = false;
+        for (int k = lane; k < tu; k += 64)
+            if (k > 0 && !(sU_l[k] >= sU_l[k - 1])) inval = true;
+        if (lane == 0 && (!(sU_s[0] <= 0.0) || !(sU_s[tu] >= 0.0))) inval = true;
+        if (__ballot(inval) != 0) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        int th = wv_sum(sU_l, sU_s, tu, sA_l, sA_s, 0, sB_l, sB_s, cap, W);
+        if (th < 0) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        double *hl = sB_l, *hs = sB_s, *ol = sC_l, *os = sC_s;
+        while (sp > n0 && A.hparent[sp - 1] == i) {
+            --sp;
+            const int64_t cs = A.hstart[sp], ct = A.hcount[sp];
+            if (cs < 0 || ct < 0 || ct > cap || cs + 2 * ct + 1 != top) {
+                bad = kNcFlagInvalid;
+                break;
+            }
+            const int tn = wv_sum(hl, hs, th, stk + cs, stk + cs + ct, (int)ct, ol, os, cap, W);
+            if (tn < 0) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+            double *sw = hl;
+            hl = ol;
+            ol = sw;
+            sw = hs;
+            hs = os;
+            os = sw;
+            th = tn;
+            top = cs;
+        }
+        if (bad) break;
+        if (p < 0) {  // a root: the first breakpoint attaining the minimum
+            if (lane == 0) {
+                double v = 0.0, vmin = 0.0, y = th > 0 ? hl[0] : 0.0;
+                for (int k = 1; k < th; ++k) {
+                    v += hs[k] * (hl[k] - hl[k - 1]);
+                    if (v < vmin) {
+                        vmin = v;
+                        y = hl[k];
+                    }
+                }
+                x[i] = (T)y;
+            }
+            __syncthreads();
+            continue;
+        }
+        const double wi = (double)w[i];
+        const double ci = C ? (double)C[i] : HUGE_VAL;
+        if (!(wi >= 0.0) || !(ci > 0.0)) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        int64_t *eo = A.eoff + 6 * i;
+        if (lane == 0) eo[0] = nmap;
+        const int t1 = wv_dt(WView{hl, hs, th, false}, wi, ol, os, cap, mp, nmap, W);
+        if (t1 < 0) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (lane == 0) eo[1] = eo[2] = nmap;
+        const int t2 = wv_dt(WView{ol, os, t1, true}, wi, hl, hs, cap, mp, nmap, W);
+        if (t2 < 0) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        if (lane == 0) eo[3] = eo[4] = nmap;
+        const WView r{hl, hs, t2, true};
+        int tm;
+        if (ci < HUGE_VAL) {
+            tm = wv_trunc(r, ci, sA_l, sA_s, cap, mp, nmap, W);
+            if (tm < 0) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+        } else {
+            for (int k = lane; k < t2; k += 64) sA_l[k] = r.l(k);
+            for (int k = lane; k <= t2; k += 64) sA_s[k] = r.s(k);
+            tm = t2;
+            __syncthreads();
+        }
+        if (lane == 0) eo[5] = nmap;
+        const int64_t need = 2 * (int64_t)tm + 1;
+        if (top + need > A.stack_cap) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        for (int k = lane; k < tm; k += 64) stk[top + k] = sA_l[k];
+        for (int k = lane; k <= tm; k += 64) stk[top + tm + k] = sA_s[k];
+        A.hstart[sp] = top;
+        A.hcount[sp] = tm;
+        A.hparent[sp] = p;
+        ++sp;
+        top += need;
+        __syncthreads();
+    }
+    if (!bad && sp != n0) bad = kNcFlagInvalid;
+    if (bad) {
+        if (lane == 0) atomicOr(A.flag, bad);
+        return;
+    }
+    if (lane != 0) return;
+    for (int64_t i = n1 - 1; i >= n0; --i) {
+        const int64_t p = A.parent[i];
+        if (p < 0) continue;
+        const int64_t *eo = A.eoff + 6 * i;
+        double y = (double)x[p];
+        y = nc_apply(mp, eo[4], eo[5], y);
+        y = nc_apply(mp, eo[2], eo[3], y);
+        y = nc_apply(mp, eo[0], eo[1], y);
+        x[i] = (T)y;
+    }
+}
+
 size_t nc_tree_layout(int64_t num_trees, int64_t num_nodes, int64_t msg_cap, int64_t map_cap, int64_t stack_cap,
                       void *p, NcTreeArgs *A) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -1954,6 +2122,28 @@ tv_status tv_tree_nc(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
     A.stack_cap = stack_cap;
     nc_tree_layout(num_trees, num_nodes, msg_cap, map_cap, stack_cap, workspace, &A);
     if (hipMemsetAsync(A.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
+    if (num_trees < 1024 && msg_cap <= kWaveMsg) {  // fewer trees than SIMDs: a wave per tree
+        const dim3 gw((unsigned)num_trees);
+        if (dtype == TV_F32) {
+            if (msg_cap <= 128)
+                hipLaunchKernelGGL((k_nc_tree_wave<float, 128>), gw, dim3(64), 0, stream, A, (const float *)ulam,
+                                   (const float *)uslope, (const float *)w, (const float *)C, (float *)x);
+            else
+                hipLaunchKernelGGL((k_nc_tree_wave<float, kWaveMsg>), gw, dim3(64), 0, stream, A,
+                                   (const float *)ulam, (const float *)uslope, (const float *)w, (const float *)C,
+                                   (float *)x);
+        } else {
+            if (msg_cap <= 128)
+                hipLaunchKernelGGL((k_nc_tree_wave<double, 128>), gw, dim3(64), 0, stream, A,
+                                   (const double *)ulam, (const double *)uslope, (const double *)w,
+                                   (const double *)C, (double *)x);
+            else
+                hipLaunchKernelGGL((k_nc_tree_wave<double, kWaveMsg>), gw, dim3(64), 0, stream, A,
+                                   (const double *)ulam, (const double *)uslope, (const double *)w,
+                                   (const double *)C, (double *)x);
+        }
+        return nc_finish(A.flag, stream);
+    }
     // Each lane walks its tree serially, so spread the trees over at least
     // 1024 waves (one per SIMD) before packing 64 into a wave.
     const int64_t spread = (num_trees + 1023) / 1024;

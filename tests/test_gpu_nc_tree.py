@@ -42,8 +42,11 @@ def _check_trees(par, off, uoff, ulam, usl, w, C, x, tol_rel, tol_node=0.0):
         assert abs(eg - eo) <= tol, (t, n1 - n0, eo, eg)
 
 
+@pytest.mark.parametrize("msg_cap", [512, 256, 128])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_random_forests_match_the_oracle(dtype):
+def test_random_forests_match_the_oracle(dtype, msg_cap):
+    """150 trees (fewer than 1024): msg_cap 512 runs a lane per tree, 256 and
+    128 a wave per tree."""
     g = np.random.default_rng(40)
     par, off = synth.post_order_forest(150, 60, seed=41)
     N = par.size
@@ -54,7 +57,7 @@ def test_random_forests_match_the_oracle(dtype):
         ulam, usl, w = (a.astype(np.float32).astype(np.float64) for a in (ulam, usl, w))
         C = C.astype(np.float32).astype(np.float64)
     x = binding.tree_nc(_dev(par, torch.int64), _dev(off, torch.int64), _dev(uoff, torch.int64), _dev(ulam, dtype),
-                        _dev(usl, dtype), _dev(w, dtype), _dev(C, dtype)).double().cpu().numpy()
+                        _dev(usl, dtype), _dev(w, dtype), _dev(C, dtype), msg_cap=msg_cap).double().cpu().numpy()
     if dtype == torch.float64:
         _check_trees(par, off, uoff, ulam, usl, w, C, x, 1e-9)
     else:
@@ -137,3 +140,24 @@ def test_full_batch_sampled_trees():
     sub_usl = usl.reshape(N, D + 1)[idx].reshape(-1)
     _check_trees(sub_par, np.array(sub_off, dtype=np.int64), sub_uoff, np.tile(np.arange(D, dtype=np.float64),
                  idx.size), sub_usl, w[idx], C[idx], x[idx], 1e-6, 8 * 2.0 ** -23 * 20)
+
+
+def test_small_batch_wave_per_tree():
+    """512 trees of 256 nodes (fewer than 1024: a wave per tree at msg_cap
+    256), 8-level uniform [0, 4] costs, w = 0.5, C = 2, FP32 in; all trees."""
+    T, n, D = 512, 256, 8
+    par, off = synth.post_order_forest(T, n, seed=7)
+    N = par.size
+    g = synth.generator(8)
+    cost = g.uniform(0, 4, (N, D))
+    sl = np.empty((N, D + 1))
+    sl[:, 0], sl[:, D] = -10.0, 10.0
+    sl[:, 1:D] = np.diff(cost, axis=1)
+    uoff = np.arange(N + 1, dtype=np.int64) * D
+    ulam = np.tile(np.arange(D, dtype=np.float64), N)
+    usl = sl.astype(np.float32).astype(np.float64).reshape(-1)
+    w, C = np.full(N, 0.5), np.full(N, 2.0)
+    x = binding.tree_nc(_dev(par, torch.int64), _dev(off, torch.int64), _dev(uoff, torch.int64),
+                        _dev(ulam, torch.float32), _dev(usl, torch.float32), _dev(w, torch.float32),
+                        _dev(C, torch.float32), msg_cap=256, map_cap=32 * n).double().cpu().numpy()
+    _check_trees(par, off, uoff, ulam, usl, w, C, x, 1e-6, 8 * 2.0 ** -23 * 20)
