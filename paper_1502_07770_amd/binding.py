@@ -878,7 +878,9 @@ def tree_nc(parent: torch.Tensor, offsets: torch.Tensor, unary_offsets: torch.Te
             map_cap: Optional[int] = None, stack_cap: Optional[int] = None) -> torch.Tensor:
     """Sec. 3 non-convex trees (tv_tree_nc): parent (int64, global, -1 at roots,
     each tree in depth-first post-order), offsets (int64, trees + 1), unaries as
-    for chain_nc, per-node w and C of the edge to the parent.  Defaults: 32
+    for chain_nc, per-node w and C of the edge to the parent.  Fewer than 1024
+    trees with msg_cap up to 256 run a wave per tree, otherwise a lane per
+    tree.  Defaults: 32
     intervals per node and room for min(64, largest tree) waiting messages of
     msg_cap breakpoints per tree.  Returns x."""
     _require_gpu(parent, offsets, unary_offsets, ulam, uslope, w)
