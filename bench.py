@@ -454,7 +454,8 @@ def bench_nc_tree_small(steps: int):
     (fewer trees than SIMDs), 8-level uniform [0, 4] costs, truncated TV
     w = 0.5, C = 2, FP32 in.  The oracle finds messages of at most 140
     breakpoints, so msg_cap 256 runs a wave per tree; msg_cap 512 the lane
-    kernel on the same trees, for comparison."""
+    kernel on the same trees, for comparison.  The same for concave pairwise
+    terms on these trees (tv_tree_nc_concave)."""
     import numpy as np
     import torch
     from paper_1502_07770_amd import binding, synth
@@ -477,6 +478,15 @@ def bench_nc_tree_small(steps: int):
         run()
         out[name] = round(Timer(torch, torch.cuda.current_stream())(run, steps), 2)
     out["mnode_s"] = round(N / out["ms"] / 1e3, 2)
+    # the same trees with 8-level concave_cost_chains unaries and min(|z|, 0.25 |z| + 1, 2.5)
+    # (messages up to 200 breakpoints)
+    _, (uoff, ulam, usl), (poff, al, cc, sd) = synth.concave_cost_chains(T, n, D, seed=9)
+    cargs = (args[0], args[1], dev(uoff, torch.int64), dev(ulam), dev(usl), dev(poff, torch.int64), dev(al), dev(cc),
+             dev(sd, torch.int32))
+    for name, cap in (("concave_ms", 256), ("concave_ms_lane", 512)):
+        run = lambda: binding.tree_nc_concave(*cargs, msg_cap=cap, map_cap=32 * n)  # noqa: E731
+        run()
+        out[name] = round(Timer(torch, torch.cuda.current_stream())(run, steps), 2)
     return out
 
 

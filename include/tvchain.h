@@ -330,7 +330,8 @@ tv_status tv_tree_nc(tv_dtype dtype, int64_t num_trees, int64_t num_nodes, const
  * Concave pairwise terms on trees, Sec. 3 with Extensions (i): the trees of
  * tv_tree_nc with the pairwise terms of tv_chain_nc_concave, z = x_parent(i)
  * - x_i on the edge from node i to its parent (a chain numbered as a tree,
- * parent(i) = i + 1, is the chain case).  One lane per tree.
+ * parent(i) = i + 1, is the chain case).  A wave per tree when there are
+ * fewer than 1024 trees and msg_cap <= 256, else one lane per tree.
  *  tree_offsets, parent : as for tv_tree_nc (post-order, contiguous subtrees).
  *  unary_offsets, ulam, uslope : as for tv_chain_nc.
  *  piece_offsets, piece_alpha, piece_C, piece_side : as for

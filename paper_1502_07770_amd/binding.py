@@ -796,7 +796,9 @@ def tree_nc_concave(parent: torch.Tensor, tree_offsets: torch.Tensor, unary_offs
                     stack_cap: Optional[int] = None) -> torch.Tensor:
     """Sec. 3 Extensions (i) on trees (tv_tree_nc_concave): the trees of tree_nc
     with the pieces of chain_nc_concave on the edge from each node to its parent
-    (z = x_parent - x_i).  Defaults: 8 intervals per piece of the tree with the
+    (z = x_parent - x_i).  Fewer than 1024 trees with msg_cap up to 256 run a
+    wave per tree, otherwise a lane per tree.  Defaults: 8 intervals per piece
+    of the tree with the
     most pieces (at least 64), room for min(64, largest tree) waiting messages
     of msg_cap breakpoints.  Returns x."""
     _require_gpu(parent, tree_offsets, unary_offsets, ulam, uslope, piece_offsets, piece_alpha, piece_C, piece_side)

@@ -1960,6 +1960,168 @@ __global__ __launch_bounds__(64) void k_nc_tree_concave(NcgTreeArgs G, const T *
     }
 }
 
+// A wave per tree for the concave pairwise terms (fewer trees than SIMDs):
+// k_nc_tree_wave's walk with each edge's pieces applied by wv_side, as in
+// k_nc_wave_concave, and the message pushed onto the stack forward.
+template <typename T, int kCap>
+__global__ __launch_bounds__(64) void k_nc_tree_wave_concave(NcgTreeArgs G, const T *__restrict__ ulam,
+                                                             const T *__restrict__ uslope,
+                                                             const T *__restrict__ palpha, const T *__restrict__ pC,
+                                                             const int32_t *__restrict__ pside, T *__restrict__ x) {
+    static_assert(kCap % 64 == 0 && kCap <= kWaveMsg, "wave message capacity");
+    __shared__ double sU_l[kCap], sU_s[kCap + 1];
+    __shared__ double sA_l[kCap], sA_s[kCap + 1];
+    __shared__ double sB_l[kCap], sB_s[kCap + 1];
+    __shared__ double sC_l[kCap], sC_s[kCap + 1];
+    __shared__ double sT[2 * kCap], sV[kCap], sPM[kCap], sPS[kCap + 1], sPE[kCap + 1];
+    __shared__ int sPA[kCap], sQ0[kCap + 1], sQ1[kCap + 1];
+    static_assert(2 * sizeof(int) == sizeof(double), "two counts per double");
+    const WScratch W{2 * kCap, sT, (int *)sV, (int *)sPM, sV, sPM, sPA, sPS, sPE, sQ0, sQ1};
+    const NcTreeArgs &A = G.t;
+    const int64_t tr = blockIdx.x;
+    if (tr >= A.num_trees) return;
+    const int64_t n0 = A.toff[tr], n1 = A.toff[tr + 1];
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {
+        if (threadIdx.x == 0) atomicOr(A.flag, kNcFlagInvalid);
+        return;
+    }
+    if (n1 == n0) return;
+    const int lane = wv_lane();
+    const int cap = (int)(A.msg_cap < kCap ? A.msg_cap : kCap);
+    double *stk = A.stack + tr * A.stack_cap;
+    double *mb = A.maps + tr * 3 * A.map_cap;
+    const NcMaps mp{mb, 0, A.map_cap};
+    int64_t nmap = 0, top = 0, sp = n0;
+    int bad = 0;
+    for (int64_t i = n0; i < n1; ++i) {
+        const int64_t p = A.parent[i];
+        if (p != -1 && (p <= i || p >= n1)) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        const int64_t u0 = A.uoff[i], tu64 = A.uoff[i + 1] - u0;
+        if (tu64 < 1 || tu64 > cap) {
+            bad = tu64 < 1 ? kNcFlagInvalid : kNcFlagCapacity;
+            break;
+        }
+        const int tu = (int)tu64;
+        for (int k = lane; k < tu; k += 64) sU_l[k] = (double)ulam[u0 + k];
+        for (int k = lane; k <= tu; k += 64) sU_s[k] = (double)uslope[u0 + i + k];
+        if (lane == 0) sA_s[0] = 0.0;  // an empty message
+        __syncthreads();
+        bool inval = false;
+        for (int k = lane; k < tu; k += 64)
+            if (k > 0 && !(sU_l[k] >= sU_l[k - 1])) inval = true;
+        if (lane == 0 && (!(sU_s[0] <= 0.0) || !(sU_s[tu] >= 0.0))) inval = true;
+        if (__ballot(inval) != 0) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        int th = wv_sum(sU_l, sU_s, tu, sA_l, sA_s, 0, sB_l, sB_s, cap, W);
+        if (th < 0) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        double *cl = sB_l, *cs = sB_s, *ol = sC_l, *os = sC_s;
+        while (sp > n0 && A.hparent[sp - 1] == i) {
+            --sp;
+            const int64_t hs0 = A.hstart[sp], ct = A.hcount[sp];
+            if (hs0 < 0 || ct < 0 || ct > cap || hs0 + 2 * ct + 1 != top) {
+                bad = kNcFlagInvalid;
+                break;
+            }
+            const int tn = wv_sum(cl, cs, th, stk + hs0, stk + hs0 + ct, (int)ct, ol, os, cap, W);
+            if (tn < 0) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+            double *sw = cl;
+            cl = ol;
+            ol = sw;
+            sw = cs;
+            cs = os;
+            os = sw;
+            th = tn;
+            top = hs0;
+        }
+        if (bad) break;
+        if (p < 0) {  // a root: the first breakpoint attaining the minimum
+            if (lane == 0) {
+                double v = 0.0, vmin = 0.0, y = th > 0 ? cl[0] : 0.0;
+                for (int k = 1; k < th; ++k) {
+                    v += cs[k] * (cl[k] - cl[k - 1]);
+                    if (v < vmin) {
+                        vmin = v;
+                        y = cl[k];
+                    }
+                }
+                x[i] = (T)y;
+            }
+            __syncthreads();
+            continue;
+        }
+        const int64_t k0 = G.poff[i], k1 = G.poff[i + 1];
+        if (k0 < 0 || k1 < k0 || k1 > G.num_pieces) {
+            bad = kNcFlagInvalid;
+            break;
+        }
+        int tc = th;
+        bool rev = false;  // the current buffer holds the reversal of the message
+        for (int64_t k = k0; k < k1 && !bad; ++k) {
+            const double al = (double)palpha[k], cc = (double)pC[k];
+            const int sd = pside[k];
+            if (!(al >= 0.0) || !(al < HUGE_VAL) || !(cc >= 0.0) || !(cc < HUGE_VAL) || (sd != 1 && sd != -1)) {
+                bad = kNcFlagInvalid;
+                break;
+            }
+            if (lane == 0) G.pmap[2 * k] = nmap;
+            const bool want_rev = sd < 0;
+            const int to = wv_side(WView{cl, cs, tc, rev != want_rev}, al, cc, want_rev, ol, os, cap, mp, nmap, W);
+            if (lane == 0) G.pmap[2 * k + 1] = nmap;
+            if (to < 0) {
+                bad = kNcFlagCapacity;
+                break;
+            }
+            rev = want_rev;
+            tc = to;
+            double *sw = cl;
+            cl = ol;
+            ol = sw;
+            sw = cs;
+            cs = os;
+            os = sw;
+        }
+        if (bad) break;
+        const int64_t need = 2 * (int64_t)tc + 1;
+        if (top + need > A.stack_cap) {
+            bad = kNcFlagCapacity;
+            break;
+        }
+        const WView fin{cl, cs, tc, rev};  // pushed forward
+        for (int k = lane; k < tc; k += 64) stk[top + k] = fin.l(k);
+        for (int k = lane; k <= tc; k += 64) stk[top + tc + k] = fin.s(k);
+        A.hstart[sp] = top;
+        A.hcount[sp] = tc;
+        A.hparent[sp] = p;
+        ++sp;
+        top += need;
+        __syncthreads();
+    }
+    if (!bad && sp != n0) bad = kNcFlagInvalid;
+    if (bad) {
+        if (lane == 0) atomicOr(A.flag, bad);
+        return;
+    }
+    if (lane != 0) return;
+    for (int64_t i = n1 - 1; i >= n0; --i) {
+        const int64_t p = A.parent[i];
+        if (p < 0) continue;
+        double y = (double)x[p];
+        for (int64_t k = G.poff[i + 1] - 1; k >= G.poff[i]; --k) y = nc_apply(mp, G.pmap[2 * k], G.pmap[2 * k + 1], y);
+        x[i] = (T)y;
+    }
+}
+
 size_t ncg_tree_layout(int64_t num_trees, int64_t num_nodes, int64_t num_pieces, int64_t msg_cap, int64_t map_cap,
                        int64_t stack_cap, void *p, NcgTreeArgs *G) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -2263,6 +2425,29 @@ tv_status tv_tree_nc_concave(tv_dtype dtype, int64_t num_trees, int64_t num_node
     G.poff = piece_offsets;
     ncg_tree_layout(num_trees, num_nodes, num_pieces, msg_cap, map_cap, stack_cap, workspace, &G);
     if (hipMemsetAsync(G.t.flag, 0, sizeof(int), stream) != hipSuccess) return TV_ERR_HIP;
+    if (num_trees < 1024 && msg_cap <= kWaveMsg) {  // fewer trees than SIMDs: a wave per tree
+        const dim3 gw((unsigned)num_trees);
+        if (dtype == TV_F32) {
+            if (msg_cap <= 128)
+                hipLaunchKernelGGL((k_nc_tree_wave_concave<float, 128>), gw, dim3(64), 0, stream, G,
+                                   (const float *)ulam, (const float *)uslope, (const float *)piece_alpha,
+                                   (const float *)piece_C, piece_side, (float *)x);
+            else
+                hipLaunchKernelGGL((k_nc_tree_wave_concave<float, kWaveMsg>), gw, dim3(64), 0, stream, G,
+                                   (const float *)ulam, (const float *)uslope, (const float *)piece_alpha,
+                                   (const float *)piece_C, piece_side, (float *)x);
+        } else {
+            if (msg_cap <= 128)
+                hipLaunchKernelGGL((k_nc_tree_wave_concave<double, 128>), gw, dim3(64), 0, stream, G,
+                                   (const double *)ulam, (const double *)uslope, (const double *)piece_alpha,
+                                   (const double *)piece_C, piece_side, (double *)x);
+            else
+                hipLaunchKernelGGL((k_nc_tree_wave_concave<double, kWaveMsg>), gw, dim3(64), 0, stream, G,
+                                   (const double *)ulam, (const double *)uslope, (const double *)piece_alpha,
+                                   (const double *)piece_C, piece_side, (double *)x);
+        }
+        return nc_finish(G.t.flag, stream);
+    }
     const int64_t spread = (num_trees + 1023) / 1024;
     const int lanes = spread < 64 ? (int)spread : 64;
     const dim3 grid((unsigned)((num_trees + lanes - 1) / lanes));

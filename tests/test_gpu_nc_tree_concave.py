@@ -43,8 +43,11 @@ def _f32(a):
     return a.astype(np.float32).astype(np.float64)
 
 
+@pytest.mark.parametrize("msg_cap", [512, 256, 128])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_random_forests_match_the_oracle(dtype):
+def test_random_forests_match_the_oracle(dtype, msg_cap):
+    """150 trees (fewer than 1024): msg_cap 512 runs a lane per tree, 256 and
+    128 a wave per tree."""
     g = np.random.default_rng(60)
     par, off = synth.post_order_forest(150, 60, seed=61)
     N = par.size
@@ -53,7 +56,7 @@ def test_random_forests_match_the_oracle(dtype):
     if dtype == torch.float32:
         u = (u[0], _f32(u[1]), _f32(u[2]))
         p = (p[0], _f32(p[1]), _f32(p[2]), p[3])
-    x = _run(par, off, u, p, dtype)
+    x = _run(par, off, u, p, dtype, msg_cap=msg_cap)
     if dtype == torch.float64:
         _check(par, off, u, p, x, range(off.size - 1), 1e-9)
     else:
