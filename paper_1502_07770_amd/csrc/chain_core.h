@@ -22,11 +22,7 @@
 // is one FP64 subtraction (rounded once to the working precision) and every
 // run over a node sees the same bits; the end segments have slope
 // Abar_s - Abar_{s-1} (= a_s).
-//
-// GlobalDeque is the exact fallback for chains whose deque outgrows the LDS
-// ring: a per-lane array of 2n + 4 entries in HBM, starting in its middle and
-// growing both ways (the 4n + O(1) array of Sec. 4.1, with two numbers per
-// breakpoint).
+
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -69,40 +65,6 @@ template <typename T> __device__ __forceinline__ bool elem_aligned(const T *p) {
 __device__ __forceinline__ float clampv(float v, float lo, float hi) { return __builtin_amdgcn_fmed3f(v, lo, hi); }
 __device__ __forceinline__ double clampv(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Per-lane array of cap entries in global memory (fallback path); tags of
-// type G (the working precision for a_i = 1, FP64 otherwise).
-template <typename T, typename G>
-struct GlobalDeque {
-    T *lam;
-    G *tag;
-    int64_t head, size, cap;
-    __device__ __forceinline__ void init(T *lam_base, G *tag_base, int64_t capacity) {
-        lam = lam_base;
-        tag = tag_base;
-        cap = capacity;
-        head = capacity / 2;
-        size = 0;
-    }
-    __device__ __forceinline__ bool full() const { return head <= 0 || head + size >= cap; }
-    __device__ __forceinline__ T front_lam() const { return lam[head]; }
-    __device__ __forceinline__ G front_tag() const { return tag[head]; }
-    __device__ __forceinline__ T back_lam() const { return lam[head + size - 1]; }
-    __device__ __forceinline__ G back_tag() const { return tag[head + size - 1]; }
-    __device__ __forceinline__ void pop_front() { ++head; --size; }
-    __device__ __forceinline__ void pop_back() { --size; }
-    __device__ __forceinline__ void push_front(T l, G k) {
-        --head;
-        ++size;
-        lam[head] = l;
-        tag[head] = k;
-    }
-    __device__ __forceinline__ void set_back_tag(G k) { tag[head + size - 1] = k; }
-    __device__ __forceinline__ void push_back(T l) {
-        lam[head + size] = l;
-        ++size;
-    }
-};
-
 // Inputs of one DP step at node i (1-based step s = i + 1).  sf / sprev are
 // the prefix sums Abar_s / Abar_{s-1} (s and s - 1 when a_i = 1); yi is b_i;
 // lop / hip are w^-, w^+ of the edge entering the node (0 at the first node);
@@ -143,111 +105,5 @@ struct EndSlope {
         else return v;
     }
 };
-
-// One forward step of the DP (transformations (a) and (b) of the message
-// update, Sec. 4.1 "Forward pass") with the deque in HBM.  On return lm / lp
-// are lambda^-_s / lambda^+_s, the points where the node's message derivative
-// equals w^- / w^+ of the leaving edge.  At the root only lm (the zero of the
-// derivative, i.e. x_n) is computed and the deque is left as is.  Returns
-// false if a push found the deque full.  The arithmetic is the LDS-ring step's
-// (dp_step_win), operation for operation.
-template <typename T, typename G, bool kGen, class DQ>
-__device__ __forceinline__ bool dp_step(DQ &dq, const StepIn<T, G> &in, bool root, T &lm, T &lp) {
-    const T lo = in.lo, hi = in.hi, yi = in.yi;
-    const G sf = in.sf;
-    const EndSlope<T, G, kGen> es(sf, in.sprev);
-    // the segment right of a new front breakpoint that was the flat left end
-    const G tend = kGen ? in.sprev : (G)(sf - (G)1);
-    if (dq.size == 0) {
-        // No incoming breakpoints (the first node of a chain, or the start of a
-        // run from an assumed zero message): the derivative is a_s z - b_s.
-        lm = es.div(yi + lo);
-        lp = es.div(yi + hi);
-        if (root) return true;
-        if (dq.full()) return false;
-        dq.push_front(lm, tend);
-        if (dq.full()) return false;
-        dq.push_back(lp);
-        return true;
-    }
-    // Left end: walk the breakpoints from the left while the derivative stays
-    // below w^-; values follow from the flat left end (w^- of the entering
-    // edge) plus slopes times breakpoint gaps.
-    G tnew;
-    T rl = (T)1;
-    bool end_seg;
-    {
-        T l1 = dq.front_lam();
-        T v = es.mul(l1) + in.lop - yi;
-        if (v >= lo) {
-            lm = l1 - es.div(v - lo);  // zero on the left end segment
-            tnew = tend;
-            end_seg = true;
-        } else {
-            for (;;) {
-                T lpv = dq.front_lam();
-                G kp = dq.front_tag();
-                dq.pop_front();
-                if (dq.size == 0) {  // right end segment
-                    lm = lpv + es.div(lo - v);
-                    tnew = tend;
-                    end_seg = true;
-                    break;
-                }
-                T lq = dq.front_lam();
-                T slope = slope_of<T, G>(sf, kp);
-                T vn = v + slope * (lq - lpv);
-                if (vn >= lo) {
-                    rl = recip(slope);
-                    lm = clampv(lpv + (lo - v) * rl, lpv, lq);
-                    tnew = kp;
-                    end_seg = false;
-                    break;
-                }
-                v = vn;
-            }
-        }
-    }
-    if (root) return true;
-    if (dq.full()) return false;
-    dq.push_front(lm, tnew);
-    // Right end, symmetric from the flat right end (w^+ of the entering edge),
-    // never popping the breakpoint lm pushed just now.
-    if (dq.size == 1) {
-        lp = lm + (hi - lo) * (end_seg ? es.ra : rl);  // tnew == tend: end slope
-        if (dq.full()) return false;
-        dq.push_back(lp);
-        return true;
-    }
-    {
-        T lt = dq.back_lam();
-        T v = es.mul(lt) + in.hip - yi;
-        if (v <= hi) {
-            lp = lt + es.div(hi - v);  // zero on the right end segment
-            dq.set_back_tag(tend);
-        } else {
-            for (;;) {
-                T lr = dq.back_lam();
-                dq.pop_back();
-                T lq = dq.back_lam();
-                if (dq.size == 1) {  // segment starting at lm
-                    lp = lm + (hi - lo) * (end_seg ? es.ra : rl);
-                    if (lp > lr) lp = lr;
-                    break;
-                }
-                T slope = slope_of<T, G>(sf, dq.back_tag());
-                T vp = v - slope * (lr - lq);
-                if (vp <= hi) {
-                    lp = clampv(lr - (v - hi) * recip(slope), lq, lr);
-                    break;
-                }
-                v = vp;
-            }
-        }
-    }
-    if (dq.full()) return false;
-    dq.push_back(lp);
-    return true;
-}
 
 }  // namespace tvc

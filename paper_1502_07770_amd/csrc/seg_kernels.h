@@ -36,12 +36,13 @@
 //               the segment's right end.
 // The output is bit-identical to running the DP sequentially per chain.
 //
-// The deque is a ring of packed (lambda, tag) entries in LDS whose first W
-// slots are also stored past its end, so the entries next to either end lie at
-// fixed offsets from one address, with the front and back entries cached in
-// registers.  Loads of node data run P
-// nodes ahead into registers (four per 16-byte load on unit-stride chains), so
-// each memory wait covers requests issued a tile earlier.
+// The deque is a ring of packed (lambda, tag) entries in LDS whose first
+// kRingCopies slots are also stored past its end, so the first kRingCopies
+// entries lie at fixed offsets from the head: a step reads them in one window
+// (the whole deque, almost always) and scans it branch-free (dp_step_ring).
+// Loads of node data run P nodes ahead into registers (four per 16-byte load
+// on unit-stride chains), so each memory wait covers requests issued a tile
+// earlier.
 #pragma once
 #include <type_traits>
 
@@ -80,11 +81,9 @@ template <typename T, typename G> __device__ __forceinline__ Ent<T, G> mk_ent(T 
 // tile) and the saved-state slots per segment.
 constexpr int kCheckpoints = 4;  // first-pass deques saved at a + CK, 2 CK, 4 CK, 8 CK in a segment
 constexpr int kSaves = 3 + kCheckpoints;  // HS, CK..., ES, ES2
-// Breakpoints examined branch-free at each end of the deque per step.
-#ifndef TVC_SCAN_WINDOW
-#define TVC_SCAN_WINDOW 5
-#endif
-constexpr int kScanWindow = TVC_SCAN_WINDOW;
+// Ring slots stored twice (slot m < kRingCopies also at m + K): the step reads
+// the first kRingCopies entries of a deque at fixed offsets from its head.
+constexpr int kRingCopies = 8;
 // Nodes the backward sweep loads ahead of their use.
 constexpr int kSweepTile = 16;
 // Lanes (each with a 2n + 4 entry HBM deque) for chains that overflow the ring.
@@ -181,34 +180,46 @@ template <typename T, int K, typename G>
 __device__ __forceinline__ bool saved_equal(const CRing<T, K, G> &R, const Ent<T, G> *src, int64_t stride);
 
 // ---------------------------------------------------------------------------
-// LDS ring of K entries per lane with register-cached ends.  The first W
-// slots are stored twice, at slot m and at slot m + K, so the first W and the
-// last W entries of the deque lie at fixed offsets from one base address each
-// (a window starting at slot m < K reads slots m .. m + W - 2 < K + W - 1): the
-// hot step needs no per-read index arithmetic and never wraps, and a lane
-// needs K + W slots rather than 2K.  Slots are lane-interleaved (slot m of lane
-// l at m * 64 + l), so the 64 lanes of a wave hit distinct banks.
+// LDS ring of K entries per lane.  The first kRingCopies slots are stored
+// twice, at slot m and at slot m + K, so the first kRingCopies entries of the
+// deque lie at fixed offsets from the head slot (logical j at physical
+// head + j < K + kRingCopies): the step's window needs no per-read index
+// arithmetic and never wraps, and a lane needs K + kRingCopies slots rather
+// than 2K.  Slots are lane-interleaved (slot m of lane l at m * 64 + l), so the
+// 64 lanes of a wave hit distinct banks.
 // ---------------------------------------------------------------------------
 template <typename T, int K, typename G>
 struct CRing {
     static_assert((K & (K - 1)) == 0, "ring size must be a power of two");
-    static_assert(kScanWindow <= K, "the copied slots are ring slots");
-    // slot rows of the per-wave LDS array (64 entries each)
-    static constexpr int kRows = K + kScanWindow;
+    static_assert(kRingCopies <= K, "the copied slots are ring slots");
     using E = Ent<T, G>;
-    E *col;  // this lane's column: slot m at col[m * 64], the copy of m < W at col[(m + K) * 64]
+    // Small rings of 8-byte entries copy every slot (2K rows: a copy is one
+    // more store at a fixed offset, no address select); others only the first
+    // kRingCopies.
+    static constexpr bool kAll = (K <= 16 && sizeof(E) <= 8);
+    // slot rows of the per-wave LDS array (64 entries each)
+    static constexpr int kRows = kAll ? 2 * K : K + kRingCopies;
+    E *col;  // this lane's column: slot m at col[m * 64], its copy at col[(m + K) * 64]
     int head, size;
-    E f, b;  // front / back copies (valid when size >= 1)
 
     __device__ __forceinline__ void init(E *base, int lane) {
         col = base + lane;
         head = 0;
         size = 0;
+        seal();
     }
     __device__ __forceinline__ E ld(int j) const { return col[((head + j) & (K - 1)) * 64]; }
     __device__ __forceinline__ void put_slot(int m, const E &e) const {
         col[m * 64] = e;
-        col[(m < kScanWindow ? m + K : m) * 64] = e;  // slots past W: the same slot again
+        if constexpr (kAll)
+            col[(m + K) * 64] = e;
+        else
+            col[(m < kRingCopies ? m + K : m) * 64] = e;  // other slots: the same slot again
+    }
+    // The slot after the back holds a +inf breakpoint (dp_step_ring's
+    // sentinel; the TV-l1 sets never read it).  A full ring has no such slot.
+    __device__ __forceinline__ void seal() const {
+        if (size < K) put_slot((head + size) & (K - 1), mk_ent<T, G>(pos_inf<T>(), G{}));
     }
     __device__ __forceinline__ void set(int j, const E &e) const { put_slot((head + j) & (K - 1), e); }
     // Order-sensitive 32-bit hash of the breakpoints and tags (the back tag is
@@ -231,10 +242,7 @@ struct CRing {
         head = 0;
         size = clamp_size<K>(*szsrc);
         for (int j = 0; j < size; ++j) put_slot(j, src[j * stride]);
-        if (size > 0) {
-            f = src[0];
-            b = src[(size - 1) * stride];
-        }
+        seal();
     }
     // Same breakpoints and tags (the back entry's tag is never read).  Size
     // and hash reject most unequal states with two loads; the exact check
@@ -266,144 +274,213 @@ __device__ __forceinline__ bool saved_equal(const CRing<T, K, G> &R, const Ent<T
     return eq;
 }
 
-// One DP step (Sec. 4.1) on a CRing, branch-free except for the rare long
-// scans.  With a_i = 1 (kGen false) sf = s = i + 1 is the number of unaries
-// added so far and the true slope of a segment with birth tag k is s - k; in
-// general it is Abar_s - Abar_k, and the segments beyond either end have slope
-// a_s (1 when a_i = 1).  The message values at the first W and the last W
-// breakpoints are formed up front; the pop count of each end is the number of
-// leading values beyond the threshold (non-decreasing, also in floating
-// point), and the bracketing segment is picked with selects.  An end needing
-// more than W pops falls back to a loop.  An empty deque (the first node of a
-// run) is handled by selects on the same path; its LDS reads are in bounds and
-// their values unused.  The root step is the same step with a zero leaving
-// edge (its deque update is never used).  Returns false if the deque would
-// outgrow the ring; the ring then keeps running on clamped sizes and the
-// caller discards it.
-template <typename T, typename G, int K, int W, bool kGen>
-__device__ __forceinline__ bool dp_step_win(CRing<T, K, G> &R, const StepIn<T, G> &in, T &lm, T &lp) {
-    static_assert(W >= 2 && W <= K, "scan window");
-    using E = Ent<T, G>;
-    const T lo = in.lo, hi = in.hi, yi = in.yi;
-    const G sf = in.sf;
-    const EndSlope<T, G, kGen> es(sf, in.sprev);
-    const G tend = kGen ? in.sprev : (G)(sf - (G)1);  // tag of a segment that was a flat end
+// ---------------------------------------------------------------------------
+// One Sec. 4.1 step on a deque of breakpoints (transformations (a) and (b)
+// of the message update): lambda^- and lambda^+ of node i, and the deque of
+// the message passed on.
+//
+// Entry j of the deque holds breakpoint lam_j and the tag k_j of the segment
+// to its right, whose true slope at step s is Abar_s - k_j (s - k_j when
+// a_i = 1).  Three conventions make every bracket the same formula:
+//  * the segment left of the front has the end slope a_s (the flat left end
+//    of the clipped message plus the node's unary);
+//  * the back entry's tag is Abar of the step that pushed it, so one step
+//    later its right segment (the flat right end plus a unary) has slope
+//    a_s too, and an old back that stays interior needs no new tag;
+//  * the slot after the back holds a +inf breakpoint (the sentinel).
+// The message derivative at the breakpoints, v_0 = a_s lam_0 + w^-_prev - b_i
+// and v_j = v_{j-1} + (Abar_s - k_{j-1}) (lam_j - lam_{j-1}), is
+// non-decreasing; it is +inf at the sentinel and NaN past it, so the number p
+// of breakpoints with v_j < w^- (popped at the left) and the number r with
+// v_j <= w^+ (the rest are popped at the right) need no masks: comparisons
+// with NaN are false.  lambda^- lies on the segment left of lam_p (the left
+// end when p = 0), lambda^+ on the segment left of lam_r, which is lambda^-'s
+// own when r = p.  The new deque (lambda^-, lam_p .. lam_{r-1}, lambda^+)
+// takes slot p - 1 for the front, slot r for the back and r + 1 for the
+// sentinel: the surviving breakpoints stay where they are.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T fmav(T a, T b, T c);
+template <> __device__ __forceinline__ float fmav<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fmav<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+struct DqScan {
+    int p, r;  // breakpoints with v < w^- / with v <= w^+
+    T vL, vR;  // v at breakpoint p - 1 / r - 1 (v_0 when p / r is 0)
+};
+
+// One breakpoint of the scan: v is the message derivative at breakpoint j.
+template <typename T>
+__device__ __forceinline__ void dq_count(DqScan<T> &sc, int j, T v, T lo, T hi) {
+    const bool cl = v < lo;
+    sc.p = cl ? j + 1 : sc.p;
+    sc.vL = cl ? v : sc.vL;
+    const bool ch = v <= hi;
+    sc.r = ch ? j + 1 : sc.r;
+    sc.vR = ch ? v : sc.vR;
+}
+
+// The solves.  E0 / E1 are entries max(p - 1, 0) and the one after it, G0 / G1
+// entries max(r - 1, 0) and the one after it.  Each root is clamped to its
+// segment (rounding guard), which also keeps lambda^- <= lambda^+.
+template <typename T, typename G, bool kGen>
+__device__ __forceinline__ void dq_solve(const DqScan<T> &sc, const StepIn<T, G> &in, const EndSlope<T, G, kGen> &es,
+                                         bool empty, const Ent<T, G> &E0, const Ent<T, G> &E1, const Ent<T, G> &G0,
+                                         const Ent<T, G> &G1, T &lm, T &lp, G &tnew) {
+    const T lo = in.lo, hi = in.hi;
+    const bool pl = sc.p > 0;
+    const T rL = pl ? recip(slope_of<T, G>(in.sf, E0.k)) : es.ra;
+    const T a = fmav(lo - sc.vL, rL, E0.l);
+    // an empty deque (a run's first node, from an assumed zero message): a_s z - b_s
+    lm = empty ? es.div(in.yi + lo) : clampv(a, pl ? E0.l : -pos_inf<T>(), pl ? E1.l : E0.l);
+    tnew = pl ? E0.k : (kGen ? in.sprev : (G)(in.sf - (G)1));
+    const bool rs = sc.r == sc.p;
+    const T rR = rs ? rL : recip(slope_of<T, G>(in.sf, G0.k));
+    const T base = rs ? lm : G0.l;
+    const T b = fmav(hi - (rs ? lo : sc.vR), rR, base);
+    lp = empty ? es.div(in.yi + hi) : clampv(b, base, sc.r > 0 ? G1.l : G0.l);
+}
+
+// The deque update through an accessor (put(j, e) writes logical entry j of
+// the current deque, j = -1 allowed; shift(d) moves the head by d).  Returns
+// the new number of breakpoints.
+template <typename T, typename G, class A>
+__device__ __forceinline__ int dq_update(A &R, const DqScan<T> &sc, G sf, T lm, T lp, G tnew) {
+    R.put(sc.p - 1, mk_ent<T, G>(lm, tnew));
+    R.put(sc.r, mk_ent<T, G>(lp, sf));
+    R.put(sc.r + 1, mk_ent<T, G>(pos_inf<T>(), G{}));
+    R.shift(sc.p - 1);
+    return sc.r - sc.p + 2;
+}
+
+// Sequential form of the scan (any depth): the same values in the same order,
+// stopping past the w^+ crossing (at the latest at the sentinel, entry t).
+template <typename T, typename G, class A>
+__device__ __forceinline__ DqScan<T> dq_scan_seq(const A &R, int t, G sf, T v0, T lo, T hi) {
+    Ent<T, G> prev = R.ld(0);
+    T v = v0;
+    DqScan<T> sc{0, 0, v, v};
+    for (int j = 0; j <= t; ++j) {
+        if (j > 0) {
+            const Ent<T, G> e = R.ld(j);
+            v = fmav(slope_of<T, G>(sf, prev.k), e.l - prev.l, v);
+            prev = e;
+        }
+        if (!(v <= hi)) break;
+        dq_count(sc, j, v, lo, hi);
+    }
+    return sc;
+}
+
+// Accessor of a CRing by logical entry.
+template <typename T, int K, typename G>
+struct RingAcc {
+    CRing<T, K, G> &R;
+    __device__ __forceinline__ Ent<T, G> ld(int j) const { return R.ld(j); }
+    __device__ __forceinline__ void put(int j, const Ent<T, G> &e) const { R.put_slot((R.head + j) & (K - 1), e); }
+    __device__ __forceinline__ void shift(int d) const { R.head = (R.head + d) & (K - 1); }
+};
+
+// The step in its general form: any depth (the sequential scan) and an empty
+// deque.  It serves a run's first node and the rare wave in which some deque
+// is deeper than the window.
+template <typename T, typename G, int K, bool kGen>
+__device__ __forceinline__ bool dp_step_ring_general(CRing<T, K, G> &R, const StepIn<T, G> &in, T &lm, T &lp) {
+    const EndSlope<T, G, kGen> es(in.sf, in.sprev);
     const int t = R.size;
-    const int h = R.head;
-    const E *fp = R.col + h * 64;                          // logical 0 .. W-1
-    const E *bp = R.col + ((h + t - W) & (K - 1)) * 64;    // logical t-W .. t-1
-    E F[W], B[W];
-    F[0] = R.f;
-    B[0] = R.b;
-#pragma unroll
-    for (int j = 1; j < W; ++j) {
-        F[j] = fp[j * 64];
-        B[j] = bp[(W - 1 - j) * 64];
-    }
-    // ---- left end: pops p = #{j < t : v_j < lo}, v_0 = message at lam_1 ----
-    T v[W];
-    v[0] = es.mul(F[0].l) + in.lop - yi;
-#pragma unroll
-    for (int j = 1; j < W; ++j) v[j] = v[j - 1] + slope_of<T, G>(sf, F[j - 1].k) * (F[j].l - F[j - 1].l);
-    int p = 0;
-    T vc = v[0];
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-        const bool c = (j < t) & (v[j] < lo);
-        p = c ? j + 1 : p;
-        vc = c ? v[j] : vc;
-    }
-    if (p == W && t > W) {  // rare: keep popping one breakpoint at a time
-        T cl = F[W - 1].l;
-        G ck = F[W - 1].k;
-        for (;;) {
-            if (p == t) break;
-            const E nx = R.ld(p);
-            const T vn = vc + slope_of<T, G>(sf, ck) * (nx.l - cl);
-            if (vn >= lo) break;
-            vc = vn;
-            cl = nx.l;
-            ck = nx.k;
-            ++p;
-        }
-    }
-    // the bracket [lam_p, lam_{p+1}] (logical p - 1 and p) is re-read from the
-    // ring rather than selected from the window: two loads instead of 3W selects
-    const E *pb = R.col + ((h + p - 1) & (K - 1)) * 64;
-    const E ea = pb[0], eb = pb[64];
-    const T cl = ea.l, nl = eb.l;
-    const G ck = ea.k;
-    const bool empty = (t == 0);
-    const T rl = recip(slope_of<T, G>(sf, ck));
+    RingAcc<T, K, G> A{R};
+    const DqScan<T> sc = dq_scan_seq<T, G>(A, t, in.sf, es.mul(A.ld(0).l) + (in.lop - in.yi), in.lo, in.hi);
+    const int i0 = sc.p > 0 ? sc.p - 1 : 0, i1 = sc.r > 0 ? sc.r - 1 : 0;
+    G tnew;
+    dq_solve<T, G, kGen>(sc, in, es, t == 0, A.ld(i0), A.ld(i0 + 1), A.ld(i1), A.ld(i1 + 1), lm, lp, tnew);
+    const int tn = dq_update<T, G>(A, sc, in.sf, lm, lp, tnew);
+    R.size = tn < K ? tn : K;
+    return tn < K;
+}
+
+// One step on the LDS ring.  Deques of fewer than kRingCopies breakpoints
+// (sentinel included, all in copied slots) are read in one window from the
+// head at fixed offsets and scanned branch-free; deeper ones take the
+// sequential scan.  The root step is the same step with a zero leaving edge
+// (its deque update is never used).  Returns false if the ring cannot hold
+// the new deque and its sentinel.
+template <typename T, typename G, int K, bool kGen>
+__device__ __forceinline__ bool dp_step_ring(CRing<T, K, G> &R, const StepIn<T, G> &in, T &lm, T &lp) {
+    using E = Ent<T, G>;
+    constexpr int M = kRingCopies;
+    const EndSlope<T, G, kGen> es(in.sf, in.sprev);
+    const T lo = in.lo, hi = in.hi;
+    const T c = in.lop - in.yi;
+    const int t = R.size;
+    DqScan<T> sc;
+    E E0, E1, G0, G1;
+    G tnew;
+    // Almost always every lane of the wave holds 1 .. M - 1 breakpoints: one
+    // window and no selects for an empty deque, decided once for the wave.
+    // Otherwise (a run's first node, or a deque deeper than the window in
+    // some lane) every lane takes the sequential scan.
+    if (__ballot((t == 0) | (t >= M))) return dp_step_ring_general<T, G, K, kGen>(R, in, lm, lp);
     {
-        const T lm_gen = clampv(cl + (lo - vc) * rl, cl, nl);
-        const T lm_all = cl + es.div(lo - vc);          // beyond every breakpoint (end slope)
-        const T lm_none = F[0].l - es.div(v[0] - lo);  // before the first breakpoint (end slope)
-        lm = (p == 0) ? lm_none : ((p == t) ? lm_all : lm_gen);
-        lm = empty ? es.div(yi + lo) : lm;
-    }
-    const bool end_seg = (p == 0 || p == t);
-    const G tnew = end_seg ? tend : ck;
-    // pop p, push lm at the front
-    const int h1 = (h + p - 1) & (K - 1);
-    const int t1 = t - p + 1;
-    const E fnew = mk_ent<T, G>(lm, tnew);
-    R.put_slot(h1, fnew);
-    // ---- right end over the qmax = t - p old breakpoints left (never pops lm) ----
-    const int qmax = t1 - 1;
-    T u[W];
-    u[0] = es.mul(B[0].l) + in.hip - yi;
+        const E *fp = R.col + R.head * 64;
+        E F[M];
 #pragma unroll
-    for (int j = 1; j < W; ++j) u[j] = u[j - 1] - slope_of<T, G>(sf, B[j].k) * (B[j - 1].l - B[j].l);
-    int q = 0;
-    T uc = u[0];
+        for (int j = 0; j < M; ++j) F[j] = fp[j * 64];
+        T v = es.mul(F[0].l) + c;
+        sc = DqScan<T>{0, 0, v, v};
+        dq_count(sc, 0, v, lo, hi);
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-        const bool c = (j < qmax) & (u[j] > hi);
-        q = c ? j + 1 : q;
-        uc = c ? u[j] : uc;
-    }
-    if (q == W && qmax > W) {  // rare: keep popping from the back
-        T rcl = B[W - 1].l;
-        for (;;) {
-            if (q == qmax) break;
-            const E nx = R.ld(t - 1 - q);
-            const T up = uc - slope_of<T, G>(sf, nx.k) * (rcl - nx.l);
-            if (up <= hi) break;
-            uc = up;
-            rcl = nx.l;
-            ++q;
+        for (int j = 1; j < M; ++j) {
+            v = fmav(slope_of<T, G>(in.sf, F[j - 1].k), F[j].l - F[j - 1].l, v);
+            dq_count(sc, j, v, lo, hi);
         }
+        const E *pb = fp + (sc.p > 0 ? sc.p - 1 : 0) * 64;
+        const E *qb = fp + (sc.r > 0 ? sc.r - 1 : 0) * 64;
+        E0 = pb[0];
+        E1 = pb[64];
+        G0 = qb[0];
+        G1 = qb[64];
+        dq_solve<T, G, kGen>(sc, in, es, false, E0, E1, G0, G1, lm, lp, tnew);
     }
-    // bracket: logical t - 1 - q (left end, its tag) and t - q (right end);
-    // only read where q < qmax, i.e. never the slot the front push just wrote
-    const E *qb = R.col + ((h + t - 1 - q) & (K - 1)) * 64;
-    const E ra = qb[0], rb = qb[64];
-    const T rnl = ra.l, rcl = rb.l;
-    const G rk = ra.k;
-    {
-        const T lp_gen = clampv(rcl - (uc - hi) * recip(slope_of<T, G>(sf, rk)), rnl, rcl);
-        // popped down to lm: lm's segment has the end slope when tnew = tend
-        T lp_lm = lm + (hi - lo) * (end_seg ? es.ra : rl);
-        lp_lm = (qmax > 0 && lp_lm > rcl) ? rcl : lp_lm;
-        const T lp_none = B[0].l + es.div(hi - u[0]);  // beyond the last breakpoint (end slope)
-        lp = (q == qmax) ? lp_lm : ((q == 0) ? lp_none : lp_gen);
-        lp = empty ? es.div(yi + hi) : lp;
+    RingAcc<T, K, G> A{R};
+    const int tn = dq_update<T, G>(A, sc, in.sf, lm, lp, tnew);
+    R.size = tn < K ? tn : K;
+    return tn < K;
+}
+
+// The same step with the deque in HBM (the exact fallback for deques that
+// outgrow every LDS ring): 2n + 4 entries per lane, the head starting at
+// n + 2.  The head moves down by at most one per step and the sentinel's slot
+// up by at most one, so n steps stay inside: the 4n + O(1) array of Sec. 4.1,
+// two numbers per breakpoint.
+template <typename T, typename G>
+struct HbmDeque {
+    T *lam;
+    G *tag;
+    int64_t head;
+    int size;
+    __device__ __forceinline__ void init(T *l, G *k, int64_t cap) {
+        lam = l;
+        tag = k;
+        head = cap / 2;
+        size = 0;
+        put(0, mk_ent<T, G>(pos_inf<T>(), G{}));
     }
-    // The old back (logical t1 - 1) stays as an interior breakpoint when q = 0:
-    // its right segment is the flat right end, tag tend.  Written
-    // unconditionally: when q > 0 that slot is dead or overwritten by the new
-    // back below, and when qmax = 0 it is the front slot, rewritten with its own
-    // value.
-    R.put_slot((h1 + t1 - 1) & (K - 1), qmax > 0 ? mk_ent<T, G>(B[0].l, tend) : fnew);
-    const int t2 = t1 - q + 1;
-    const E bnew = mk_ent<T, G>(lp, (G)0);
-    R.put_slot((h1 + t2 - 1) & (K - 1), bnew);
-    R.head = h1;
-    R.size = t2 < K ? t2 : K;
-    R.f = fnew;
-    R.b = bnew;
-    return (t1 <= K) & (t2 <= K);
+    __device__ __forceinline__ Ent<T, G> ld(int j) const { return mk_ent<T, G>(lam[head + j], tag[head + j]); }
+    __device__ __forceinline__ void put(int j, const Ent<T, G> &e) const {
+        lam[head + j] = e.l;
+        tag[head + j] = e.k;
+    }
+    __device__ __forceinline__ void shift(int d) { head += d; }
+};
+template <typename T, typename G, bool kGen>
+__device__ __forceinline__ void dp_step_hbm(HbmDeque<T, G> &D, const StepIn<T, G> &in, T &lm, T &lp) {
+    const EndSlope<T, G, kGen> es(in.sf, in.sprev);
+    const int t = D.size;
+    const DqScan<T> sc = dq_scan_seq<T, G>(D, t, in.sf, es.mul(D.ld(0).l) + (in.lop - in.yi), in.lo, in.hi);
+    const int i0 = sc.p > 0 ? sc.p - 1 : 0, i1 = sc.r > 0 ? sc.r - 1 : 0;
+    G tnew;
+    dq_solve<T, G, kGen>(sc, in, es, t == 0, D.ld(i0), D.ld(i0 + 1), D.ld(i1), D.ld(i1 + 1), lm, lp, tnew);
+    D.size = dq_update<T, G>(D, sc, in.sf, lm, lp, tnew);
 }
 
 // ---------------------------------------------------------------------------
@@ -559,7 +636,7 @@ __device__ __forceinline__ void node_step(CRing<T, K, typename Prob::Tag> &R, bo
         ok = ok & (!S.ovf | root);
     } else {
         const auto in = step_in<T, Prob>(src, pv, i, root, cy);
-        const bool fits = dp_step_win<T, typename Prob::Tag, K, kScanWindow, Prob::kGen>(R, in, lm, lp);
+        const bool fits = dp_step_ring<T, typename Prob::Tag, K, Prob::kGen>(R, in, lm, lp);
         ok = ok & (fits | root);
     }
     if (root) lp = lm;
@@ -607,10 +684,10 @@ __device__ __forceinline__ void load_state(const SegWs<T, G> &ws, CRing<T, K, G>
 // hook(e) is called with the next node index e (tile edges are multiples of P
 // from `from`); a true return stops the run, and fwd_run then returns e.
 // Otherwise it returns b.
-template <typename T, class Prob, int K, int P, bool kStore, class Hook>
-__device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, const typename Prob::Src &src,
-                                           bool &ok, CarryOf<T, Prob> &cy, int64_t from, int64_t b, int64_t n,
-                                           LamPair<T> *lam, int64_t C, int64_t c, Hook hook) {
+template <typename T, class Prob, int K, int P, bool kStore, bool kVec, class Hook>
+__device__ __forceinline__ int64_t fwd_run_t(CRing<T, K, typename Prob::Tag> &R, const typename Prob::Src &src,
+                                             bool &ok, CarryOf<T, Prob> &cy, int64_t from, int64_t b, int64_t n,
+                                             LamPair<T> *lam, int64_t C, int64_t c, Hook hook) {
     static_assert(P % 4 == 0, "tiles hold whole groups of four nodes");
     typename Prob::Pre pre[P];
 #pragma unroll
@@ -628,23 +705,29 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, c
         }
     };
     int64_t i0 = from;
-    // tiles whose prefetch stays inside [from, b): no clamping, running offsets
+    // tiles whose prefetch stays inside [from, b): double-buffered, the next
+    // tile's loads issued before this tile's nodes are processed (one wait per
+    // tile, for loads P nodes old); no clamping, running offsets
     for (; i0 + 2 * P <= b; i0 += P) {
-        int64_t o = src.off(i0 + P);
-        const int64_t st = src.step();
+        typename Prob::Pre nxt[P];
+        if constexpr (!kVec) {
+            int64_t o = src.off(i0 + P);
+            const int64_t st = src.step();
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const auto pv = pre[j];
-            if (!src.vec) {
-                pre[j] = src.load_off(o);
+            for (int j = 0; j < P; ++j) {
+                nxt[j] = src.load_off(o);
                 o += st;
-            } else if ((j & 3) == 3) {
-                // unit-stride chains (rows): refill the four slots just consumed
-                // with one 16-byte load per stream (node indices are multiples of 4)
-                src.load4(i0 + j + P - 3, &pre[j - 3]);
             }
-            node(i0 + j, pv);
+        } else {
+            // unit-stride chains (rows): one 16-byte load per stream for four
+            // nodes (node indices are multiples of 4)
+#pragma unroll
+            for (int j = 0; j < P; j += 4) src.load4(i0 + P + j, &nxt[j]);
         }
+#pragma unroll
+        for (int j = 0; j < P; ++j) node(i0 + j, pre[j]);
+#pragma unroll
+        for (int j = 0; j < P; ++j) pre[j] = nxt[j];
         if (hook(i0 + P)) return i0 + P;
     }
     // the last full tile (its prefetch is clamped to the run's last node)
@@ -652,8 +735,8 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, c
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             const int64_t i = i0 + j;
-            const auto pv = pre[j];
-            if (!src.vec) {
+            node(i, pre[j]);
+            if constexpr (!kVec) {
                 pre[j] = src.load((i + P < b) ? i + P : b - 1);
             } else if ((j & 3) == 3) {
                 const int64_t q = i + P - 3;
@@ -664,7 +747,6 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, c
                     for (int k = 0; k < 4; ++k) pre[j - 3 + k] = src.load((q + k < b) ? q + k : b - 1);
                 }
             }
-            node(i, pv);
         }
         if (hook(i0 + P)) return i0 + P;
     }
@@ -673,6 +755,19 @@ __device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, c
         if (i0 + j < b) node(i0 + j, pre[j]);
     }
     return b;
+}
+
+// The prefetch path is chosen once per wave: lanes whose chains all allow
+// 16-byte loads take them, any other wave loads node by node.  (A per-lane
+// choice would make every prefetch load conditional, and the compiler then
+// waits for each load a few nodes after issuing it.)
+template <typename T, class Prob, int K, int P, bool kStore, class Hook>
+__device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, const typename Prob::Src &src,
+                                           bool &ok, CarryOf<T, Prob> &cy, int64_t from, int64_t b, int64_t n,
+                                           LamPair<T> *lam, int64_t C, int64_t c, Hook hook) {
+    if (__ballot(!src.vec) == 0)
+        return fwd_run_t<T, Prob, K, P, kStore, true>(R, src, ok, cy, from, b, n, lam, C, c, hook);
+    return fwd_run_t<T, Prob, K, P, kStore, false>(R, src, ok, cy, from, b, n, lam, C, c, hook);
 }
 
 // Backward clip pass over [a, b) of one chain.  All lanes of a wave share a and
@@ -741,15 +836,15 @@ __device__ __forceinline__ void bwd_sweep_run(const WsOf<T, Prob> &ws, const typ
     LamPair<T> pre[P];
     SP spre[P];
     // slot j holds node i0 - j of the current tile (i0 = b - 1 - tile * P)
-    auto refill_sink = [&](int jhi, int64_t q) {  // nodes q .. q+3 into slots jhi, jhi-1, jhi-2, jhi-3
+    auto refill_sink = [&](SP *dst, int jhi, int64_t q) {  // nodes q .. q+3 into slots jhi, jhi-1, jhi-2, jhi-3
         if (q >= a) {
             SP t4[4];
             sink.load4(q, t4);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) spre[jhi - m] = t4[m];
+            for (int m = 0; m < 4; ++m) dst[jhi - m] = t4[m];
         } else {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) spre[jhi - m] = sink.load((q + m >= a) ? q + m : a);
+            for (int m = 0; m < 4; ++m) dst[jhi - m] = sink.load((q + m >= a) ? q + m : a);
         }
     };
 #pragma unroll
@@ -757,7 +852,7 @@ __device__ __forceinline__ void bwd_sweep_run(const WsOf<T, Prob> &ws, const typ
         const int64_t i = (b - 1 - j >= a) ? b - 1 - j : a;
         pre[j] = lam[i * C + c];
         if (!kVec) spre[j] = sink.load(i);
-        else if ((j & 3) == 3) refill_sink(j, b - 1 - j);
+        else if ((j & 3) == 3) refill_sink(spre, j, b - 1 - j);
     }
     T gx[4];
     SP gs[4];
@@ -801,16 +896,22 @@ __device__ __forceinline__ void bwd_sweep_run(const WsOf<T, Prob> &ws, const typ
     };
     int64_t i0 = b - 1;
     for (; i0 - (P - 1) >= a; i0 -= P) {
+        // double-buffered: the next tile's loads go out before this tile's nodes
+        LamPair<T> npre[P];
+        SP nspre[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            const int64_t i = i0 - j;
-            const LamPair<T> p = pre[j];
-            const SP sv = spre[j];
-            const int64_t ip = (i - P >= a) ? i - P : a;
-            pre[j] = lam[ip * C + c];
-            if (!kVec) spre[j] = sink.load(ip);
-            else if ((j & 3) == 3) refill_sink(j, i - P);
-            visit(i, j & 3, p, sv);
+            const int64_t ip = (i0 - j - P >= a) ? i0 - j - P : a;
+            npre[j] = lam[ip * C + c];
+            if (!kVec) nspre[j] = sink.load(ip);
+            else if ((j & 3) == 3) refill_sink(nspre, j, i0 - j - P);
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) visit(i0 - j, j & 3, pre[j], spre[j]);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            pre[j] = npre[j];
+            spre[j] = nspre[j];
         }
         if (kRec && i0 - (P - 1) == erec) {  // the state now covers [erec, b)
             if (sweep_cp_recorded(a, b, erec, ws.CK)) {
@@ -1011,14 +1112,14 @@ __device__ void seg_full_chain(const WsOf<T, Prob> &ws, const typename Prob::Par
             cy.wprev = wi;
         }
     } else {
-        GlobalDeque<T, G> dq;
+        HbmDeque<T, G> dq;
         dq.init(ws.fb_lam + slot * ws.fb_cap, ws.fb_tag + slot * ws.fb_cap, ws.fb_cap);
         for (int64_t i = 0; i < sp.n; ++i) {
             const auto pr = src.load(i);
             const bool root = (i == sp.n - 1);
             T lm = (T)0, lp = (T)0;
             const auto in = step_in<T, Prob>(src, pr, i, root, cy);
-            dp_step<T, G, Prob::kGen>(dq, in, root, lm, lp);
+            dp_step_hbm<T, G, Prob::kGen>(dq, in, lm, lp);
             if (root) lp = lm;
             put_lam<T>(ws.lam, i, ws.C, c, lm, lp);
         }
@@ -1121,7 +1222,7 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
 // l).  Both paths compute the same results as the segmented one.
 // ---------------------------------------------------------------------------
 template <class E> struct OvfRing {
-    static constexpr int fit(int k) { return (k + kScanWindow) * 64 * (int)sizeof(E) <= 163840 ? k : fit(k / 2); }
+    static constexpr int fit(int k) { return (k + kRingCopies) * 64 * (int)sizeof(E) <= 163840 ? k : fit(k / 2); }
     static constexpr int K = fit(512);
 };
 
