@@ -92,6 +92,27 @@ tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const voi
                         const void *w, double w_scalar, void *x,
                         void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* The chain prox of tv_chain_prox for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results (bit for bit, same launch
+ * plan), with the workspace taken from a fixed device array of
+ * TV_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  The call allocates and frees nothing.
+ *  Arguments as tv_chain_prox, without the workspace.
+ *  Returns TV_ERR_WORKSPACE, before any HIP call, if the launch needs more
+ *  scratch than that (a layout whose tv_chain_prox_workspace() is at most
+ *  TV_NOALLOC_SCRATCH_BYTES always fits; in FP32 the default launch plan
+ *  needs about 16 bytes per node, the 8-byte lambda pair of every node plus
+ *  the segments' saved deques: some 4 million nodes).
+ *  Every call on one GPU uses that GPU's one scratch array: calls that overlap
+ *  in time on the same GPU (other streams, other host threads) race and must
+ *  be serialised by the caller (one stream is enough).  Nothing in the
+ *  scratch needs to start at zero: each launch writes every value it reads.
+ *  Asynchronous on `stream`. */
+#define TV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+tv_status tv_chain_prox_noalloc(const tv_chain_layout *layout, tv_dtype dtype, const void *y,
+                                const void *w, double w_scalar, void *x, hipStream_t stream);
+
 /* Several uniform batches of chains solved in ONE launch (e.g. the row and
  * the column chains of an image, or chains of different lengths), each as by
  * tv_chain_prox: batch b is layouts[b] (offsets must be NULL) over y[b] with

@@ -84,6 +84,7 @@ _SIG = {
     "tv_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tv_chain_prox_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "tv_chain_prox": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, _P, _P, ctypes.c_size_t, _P]),
+    "tv_chain_prox_noalloc": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_double, _P, _P]),
     "tv_chain_prox_backward_workspace": (ctypes.c_size_t, [_P, ctypes.c_int]),
     "tv_chain_prox_backward": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, _P,
                                               ctypes.c_size_t, _P]),
@@ -285,6 +286,25 @@ def chain_prox(y: torch.Tensor, w: Union[float, torch.Tensor] = 0.0, dim: int = 
         out.copy_(res)
         return out
     return res
+
+
+def chain_prox_noalloc(y: torch.Tensor, x: torch.Tensor, w: Union[float, torch.Tensor] = 0.0) -> torch.Tensor:
+    """chain_prox of the rows of a contiguous 2D ``y`` into the preallocated ``x``
+    through tv_chain_prox_noalloc: the library call allocates nothing (its
+    workspace is the library's fixed per-GPU scratch), so it may run where
+    allocation is not allowed.  Raises TvChainError(TV_ERR_WORKSPACE) when the
+    problem needs more scratch than the library holds."""
+    _require_gpu(y, x)
+    if y.dim() != 2 or not y.is_contiguous() or x.shape != y.shape or x.dtype != y.dtype or not x.is_contiguous():
+        raise TvChainError(TV_ERR_INVALID_ARG, "y and x must be contiguous 2D tensors of one shape and dtype")
+    wv, w_scalar = (w, 0.0) if isinstance(w, torch.Tensor) else (None, float(w))
+    if wv is not None and (wv.shape != y.shape or wv.dtype != y.dtype or not wv.is_contiguous()):
+        raise TvChainError(TV_ERR_INVALID_ARG, "per-edge w must be contiguous and match y")
+    lay = ChainLayout(y.shape[0], y.shape[1], 1, y.shape[1], None)
+    st = load().tv_chain_prox_noalloc(ctypes.byref(lay), _dtype_code(y), _ptr(y), _ptr(wv), w_scalar, _ptr(x),
+                                      ctypes.c_void_p(_stream_ptr(y.device)))
+    _check(st, "tv_chain_prox_noalloc")
+    return x
 
 
 def chain_dp(b: torch.Tensor, wm: torch.Tensor, wp: torch.Tensor, a: Optional[torch.Tensor] = None,

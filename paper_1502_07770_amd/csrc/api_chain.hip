@@ -166,6 +166,34 @@ hipError_t time_multi(int nb, const ChainBatch *bs, const void *const *y, const 
     return e;
 }
 
+// Fixed device scratch of tv_chain_prox_noalloc: one copy per GPU the library
+// runs on, held until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in); it uses the device
+// address obtained once per device with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[TV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+// The current device's scratch address (looked up on the first call per
+// device, with that device current).
+static tv_status scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return TV_ERR_NO_DEVICE;
+    if (dev >= kMaxDevices) return TV_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TV_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TV_OK;
+}
+
 }  // namespace tvc
 
 using namespace tvc;
@@ -212,6 +240,32 @@ tv_status tv_chain_prox(const tv_chain_layout *layout, tv_dtype dtype, const voi
     else
         e = launch_chain_prox<double>(b, (const double *)y, (const double *)w, w_scalar, (double *)x,
                                       workspace, plan, stream);
+    return e == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+tv_status tv_chain_prox_noalloc(const tv_chain_layout *layout, tv_dtype dtype, const void *y, const void *w,
+                                double w_scalar, void *x, hipStream_t stream) {
+    if (!layout_ok(layout, dtype)) return TV_ERR_INVALID_ARG;
+    if (layout->num_chains == 0) return TV_OK;
+    if (!y || !x) return TV_ERR_INVALID_ARG;
+    if (!w && !(isfinite(w_scalar) && w_scalar >= 0.0)) return TV_ERR_INVALID_ARG;
+    if (overlaps(layout, x, layout, y, dtype) || overlaps(layout, x, layout, w, dtype)) return TV_ERR_INVALID_ARG;
+    const ChainBatch b = to_batch(layout);
+    const SegPlan plan = seg_plan(b.num_chains, b.n);
+    const size_t need = dtype == TV_F32 ? chain_prox_ws_bytes<float>(b, plan) : chain_prox_ws_bytes<double>(b, plan);
+    if (need > TV_NOALLOC_SCRATCH_BYTES) return TV_ERR_WORKSPACE;
+    tv_status st = device_check();
+    if (st != TV_OK) return st;
+    void *ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != TV_OK) return st;
+    hipError_t e;
+    if (dtype == TV_F32)
+        e = launch_chain_prox<float>(b, (const float *)y, (const float *)w, (float)w_scalar, (float *)x, ws, plan,
+                                     stream);
+    else
+        e = launch_chain_prox<double>(b, (const double *)y, (const double *)w, w_scalar, (double *)x, ws, plan,
+                                      stream);
     return e == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
 
