@@ -1,14 +1,15 @@
 """Build libtvchain.so (HIP, gfx950) in-tree with hipcc.
 
 Every ``*.hip`` file under ``csrc/`` is compiled for gfx950 with packed-FP32
-instruction selection disabled, then linked into one shared library next to
-this file.  ``python -m paper_1502_07770_amd.build_lib`` runs it.
+instruction selection disabled (the files listed in PARTS once per part),
+then linked into one shared library next to this file.  ``python -m paper_1502_07770_amd.build_lib`` runs it.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
 import os
+import re
 import subprocess
 import sys
 
@@ -27,20 +28,61 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+def _deps(src: str, seen=None) -> set:
+    """The file and every local header it includes, transitively."""
+    seen = set() if seen is None else seen
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    with open(src) as fh:
+        for line in fh:
+            m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+            if m:
+                for d in (os.path.dirname(src), CSRC, os.path.join(ROOT, "include")):
+                    h = os.path.join(d, m.group(1))
+                    if os.path.exists(h):
+                        _deps(h, seen)
+                        break
+    return seen
+
+
+# Sources compiled once per part (-DTVC_PART=k), each part instantiating a
+# subset of their kernels, so the longest single compilation is shorter.
+PARTS = {"chain_kernels.hip": 4, "tv2d_kernels.hip": 4, "tv2d_batched.hip": 2, "chain_l1.hip": 2}
+
+
+def _units(srcs):
+    """(source, part) pairs to compile; part 0 is a whole source."""
+    out = []
+    for f in srcs:
+        n = PARTS.get(os.path.basename(f), 0)
+        out += [(f, k) for k in range(1, n + 1)] if n else [(f, 0)]
+    return out
+
+
+def _compile(unit, incremental: bool = False) -> str:
+    src, part = unit
+    obj = os.path.join(BUILD, os.path.basename(src) + (".p%d" % part if part else "") + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if all(t > os.path.getmtime(d) for d in _deps(src)):
+            return obj
+    cmd = [HIPCC] + FLAGS + (["-DTVC_PART=%d" % part] if part else []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental, those older than their
+    object file or any header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    units = _units(sorted(glob.glob(os.path.join(CSRC, "*.hip"))))
+    # longest first: the split sources and the 2D ones dominate
+    units.sort(key=lambda u: -os.path.getsize(u[0]) * (2 if u[1] == 0 else 1))
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(units))) as ex:
+        objs = list(ex.map(lambda u: _compile(u, incremental), units))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,4 +95,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)

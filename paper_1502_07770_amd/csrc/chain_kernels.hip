@@ -625,6 +625,9 @@ template <typename T, typename G>
 size_t seg_ws_bytes_plan(int64_t C, int64_t n, const SegPlan &plan) {
     return seg_ws_bytes<T, G>(C, n, plan);
 }
+// Build parts: 1 the chain prox in FP32, 2 the multi-batch launch in FP32,
+// 3 both in FP64, 4 the adjoint and the plan arithmetic.
+#if TVC_IN_PART(4)
 template size_t seg_ws_bytes_plan<float, float>(int64_t, int64_t, const SegPlan &);
 template size_t seg_ws_bytes_plan<double, double>(int64_t, int64_t, const SegPlan &);
 template size_t seg_ws_bytes_plan<float, double>(int64_t, int64_t, const SegPlan &);
@@ -640,6 +643,7 @@ template int seg_candidates<float, TagJ<float>>(int64_t, int64_t, SegPlan *, int
 template int seg_candidates<double, TagJ<double>>(int64_t, int64_t, SegPlan *, int);
 template size_t seg_bytes_max<float, TagJ<float>>(int64_t, int64_t, int);
 template size_t seg_bytes_max<double, TagJ<double>>(int64_t, int64_t, int);
+#endif
 
 template <typename T>
 hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *gy, T *gw,
@@ -658,21 +662,31 @@ hipError_t launch_chain_adjoint(const ChainBatch &b, const T *x, const T *g, T *
     return hipGetLastError();
 }
 
+#if TVC_IN_PART(1)
 template hipError_t launch_chain_prox<float>(const ChainBatch &, const float *, const float *, float,
                                              float *, void *, const SegPlan &, hipStream_t);
+#endif
+#if TVC_IN_PART(3)
 template hipError_t launch_chain_prox<double>(const ChainBatch &, const double *, const double *, double,
                                               double *, void *, const SegPlan &, hipStream_t);
+#endif
+#if TVC_IN_PART(2)
 template hipError_t launch_chain_prox_multi<float>(int, const ChainBatch *, const float *const *,
                                                    const float *const *, const double *, float *const *, void *,
                                                    const SegPlan &, hipStream_t);
+#endif
+#if TVC_IN_PART(3)
 template hipError_t launch_chain_prox_multi<double>(int, const ChainBatch *, const double *const *,
                                                     const double *const *, const double *, double *const *, void *,
                                                     const SegPlan &, hipStream_t);
+#endif
+#if TVC_IN_PART(4)
 template size_t chain_prox_ws_bytes<float>(const ChainBatch &, const SegPlan &);
 template size_t chain_prox_ws_bytes<double>(const ChainBatch &, const SegPlan &);
 template hipError_t launch_chain_adjoint<float>(const ChainBatch &, const float *, const float *,
                                                 float *, float *, int, hipStream_t);
 template hipError_t launch_chain_adjoint<double>(const ChainBatch &, const double *, const double *,
                                                  double *, double *, int, hipStream_t);
+#endif
 
 }  // namespace tvc

@@ -124,11 +124,16 @@ hipError_t launch_chain_l1(const ChainBatch &bt, const T *y, const T *d, const T
     return seg_run<T, L1Prob<T>, kTile>(workspace, bt.num_chains, bt.n, plan, pp, stream);
 }
 
+// Build parts: 1 FP32, 2 FP64.
+#if TVC_IN_PART(1)
 template size_t chain_l1_ws_bytes<float>(int64_t, int64_t);
-template size_t chain_l1_ws_bytes<double>(int64_t, int64_t);
 template hipError_t launch_chain_l1<float>(const ChainBatch &, const float *, const float *, const float *, float,
                                            const float *, float, float *, void *, hipStream_t);
+#endif
+#if TVC_IN_PART(2)
+template size_t chain_l1_ws_bytes<double>(int64_t, int64_t);
 template hipError_t launch_chain_l1<double>(const ChainBatch &, const double *, const double *, const double *,
                                             double, const double *, double, double *, void *, hipStream_t);
+#endif
 
 }  // namespace tvc

@@ -4,6 +4,15 @@
 #include <stddef.h>
 #include <stdint.h>
 
+// A source that instantiates many kernel templates is compiled several times
+// by the build, once per part (TVC_PART = 1 .. n), each part instantiating
+// one subset; TVC_PART = 0 (the default, a single compilation) instantiates
+// everything.
+#ifndef TVC_PART
+#define TVC_PART 0
+#endif
+#define TVC_IN_PART(k) (TVC_PART == 0 || TVC_PART == (k))
+
 namespace tvc {
 
 // Breakpoint slots of the per-lane LDS ring.  The deepest deque seen on the
