@@ -426,13 +426,17 @@ typedef struct {
                             (same kernels and results; fewer launches from the host) */
 } tv2d_options;
 
-/* [host] Result of a 2D solve (written by the library before it returns). */
+/* [DEVICE] Result of a 2D solve, written by the solve's last kernel on the
+ * solve's stream (read it after that stream's work is done). */
 typedef struct {
     int iters;        /* total iterations in the state (including resumed ones)       */
     int status;       /* TV_OK, TV_ERR_NOT_CONVERGED or TV_ERR_NONFINITE              */
     double gap_norm;  /* (P - D) / (H W) at the last evaluation                       */
     double primal;    /* P(x) = lambda (TV_h + TV_v)(x) + |x - f|^2 / 2  (FP64)        */
     double dual;      /* D(p) = |f|^2/2 - |f - D_h^T p_h - D_v^T p_v|^2 / 2  (FP64)    */
+    double device_ms; /* device time from the first iteration to the stop (or to the
+                         last iteration): the solve's time to its tolerance; in a
+                         batched solve, to the image's own stop              */
 } tv2d_stats;
 
 /* Bytes of device workspace tv2d_solve needs for an H x W image. */
@@ -448,9 +452,17 @@ size_t tv2d_workspace(int64_t H, int64_t W, tv_dtype dtype);
  *  The duality gap uses dual edge variables recovered from the two chain
  *  solves, clipped to [-lambda, lambda], so P - D >= 0 always bounds the
  *  suboptimality of x.  Reductions are FP64 whatever dtype is.
- *  SYNCHRONOUS: returns after the solve ends (the host reads the gap every
- *  gap_every iterations to decide whether to continue); `stats` is host memory.
- *  Returns TV_OK, TV_ERR_NOT_CONVERGED (gap_tol > 0 not reached), or an error. */
+ *  ASYNCHRONOUS on `stream`: every iteration up to max_iter is enqueued at
+ *  once and the stopping test runs on the device: after each gap evaluation
+ *  (every gap_every iterations) a device flag, once the gap is at gap_tol or
+ *  not finite, makes every later kernel of the solve return at once (each
+ *  such skipped iteration still costs its launches, a few microseconds).  The
+ *  schedule is generated on the device, so nothing is copied from the host
+ *  and the host never waits, except once when resuming (to read which buffer
+ *  holds the iterate).  `stats` is DEVICE memory (or NULL), written by the
+ *  solve's last kernel; stats->status is TV_OK, TV_ERR_NOT_CONVERGED (gap_tol
+ *  > 0 not reached) or TV_ERR_NONFINITE.
+ *  Returns TV_OK once the solve is enqueued, or an argument / launch error. */
 tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld,
                      double lambda, void *x, const tv2d_options *options, tv2d_stats *stats,
                      void *workspace, size_t workspace_bytes, hipStream_t stream);
@@ -482,7 +494,15 @@ tv_status tv2d_batched_autotune(tv_dtype dtype, int num_images, const int64_t *H
  * image with its own lambda and its own stopping test.
  *  H, W, pixel_offsets, lambda: [host] arrays of num_images entries; image j
  *  occupies f[pixel_offsets[j] .. + H[j] W[j]) row-major (ld = W[j]), and x
- *  likewise.  stats: [host] array of num_images results.  SYNCHRONOUS. */
+ *  likewise.  stats: DEVICE array of num_images results (or NULL), written by
+ *  the solve's last kernel.  An image whose gap reaches gap_tol > 0, or is not
+ *  finite, is frozen on the device (its chains and gap terms are skipped from
+ *  then on); once every image is frozen the solve stops as tv2d_solve does.
+ *  ASYNCHRONOUS on `stream` except for one wait after the chain lists are
+ *  uploaded from host memory (before any iteration is enqueued), and, with
+ *  use_graph, a wait for the replays before returning.  resume must be 0.
+ *  Returns TV_OK once the solve is enqueued, or an argument / launch error;
+ *  each image's status is in its stats. */
 tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
                              const int64_t *pixel_offsets, const double *lambda,
                              const void *f, void *x, const tv2d_options *options,
@@ -502,9 +522,11 @@ tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, c
  *            is evaluated, into gap_history[k - 1] if given (DEVICE).  gap_tol
  *            must be <= 0 and resume 0 (no duality gap is formed for TV-l1);
  *            use_graph is ignored.
- *  stats   : iters, status, primal = P(x) of the returned x; dual and gap_norm
- *            are NaN.
- * Synchronous; returns TV_ERR_NONFINITE if the energy is not finite. */
+ *  stats   : DEVICE (or NULL): iters, status (TV_ERR_NONFINITE if the energy is
+ *            not finite), primal = P(x) of the returned x, device_ms; dual and
+ *            gap_norm are NaN.
+ * ASYNCHRONOUS on `stream`; returns TV_OK once the solve is enqueued, or an
+ * argument / launch error. */
 size_t tv2d_l1_workspace(int64_t H, int64_t W, tv_dtype dtype);
 tv_status tv2d_l1_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, void *x,
                         const tv2d_options *options, tv2d_stats *stats, void *workspace, size_t workspace_bytes,

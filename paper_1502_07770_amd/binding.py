@@ -72,7 +72,24 @@ class TuningResult(ctypes.Structure):
 
 class Tv2dStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("gap_norm", ctypes.c_double),
-                ("primal", ctypes.c_double), ("dual", ctypes.c_double)]
+                ("primal", ctypes.c_double), ("dual", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"iters": int(self.iters), "status": int(self.status), "gap_norm": float(self.gap_norm),
+                "primal": float(self.primal), "dual": float(self.dual), "device_ms": float(self.device_ms)}
+
+
+def _stats_buffer(n: int, device) -> torch.Tensor:
+    """Device memory for n tv2d_stats records (the 2D solves write them from
+    their last kernel)."""
+    return torch.empty(n * ctypes.sizeof(Tv2dStats), dtype=torch.uint8, device=device)
+
+
+def _read_stats(buf: torch.Tensor, n: int) -> list:
+    """The n records of a stats buffer, read after the work queued before on
+    the current stream (the copy to the host waits for it)."""
+    raw = buf.cpu().numpy().tobytes()
+    return [r.as_dict() for r in (Tv2dStats * n).from_buffer_copy(raw)]
 
 
 _lib = None
@@ -585,14 +602,11 @@ class Tv2dSolver:
             hist_ptr = gap_history.data_ptr()
         opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 1 if resume else 0, hist_ptr,
                           1 if use_graph else 0)
-        stats = Tv2dStats()
+        sbuf = _stats_buffer(1, f.device)
         st = load().tv2d_solve(self.code, _ptr(f), self.H, self.W, ld, float(lam), _ptr(x), ctypes.byref(opt),
-                               ctypes.byref(stats), _ptr(self.ws), self.nbytes,
-                               ctypes.c_void_p(_stream_ptr(f.device)))
-        if st not in (TV_OK, TV_ERR_NOT_CONVERGED):
-            raise TvChainError(st, "tv2d_solve")
-        info = {"iters": stats.iters, "status": stats.status, "gap_norm": stats.gap_norm,
-                "primal": stats.primal, "dual": stats.dual}
+                               _ptr(sbuf), _ptr(self.ws), self.nbytes, ctypes.c_void_p(_stream_ptr(f.device)))
+        _check(st, "tv2d_solve")
+        info = _read_stats(sbuf, 1)[0]
         if out is not None and x is not out:
             out.copy_(x)
             x = out
@@ -650,15 +664,12 @@ def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol
             tuned.update({"col": col.as_dict(), "row": row.as_dict()})
     x = torch.empty_like(packed)
     opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 0, None, 1 if use_graph else 0)
-    stats = (Tv2dStats * n)()
-    st = lib.tv2d_solve_batched(code, n, Hs, Ws, Os, Ls, _ptr(packed), _ptr(x), ctypes.byref(opt), stats, _ptr(ws),
-                                nbytes, ctypes.c_void_p(_stream_ptr(packed.device)))
-    if st not in (TV_OK, TV_ERR_NOT_CONVERGED):
-        raise TvChainError(st, "tv2d_solve_batched")
+    sbuf = _stats_buffer(n, packed.device)
+    st = lib.tv2d_solve_batched(code, n, Hs, Ws, Os, Ls, _ptr(packed), _ptr(x), ctypes.byref(opt), _ptr(sbuf),
+                                _ptr(ws), nbytes, ctypes.c_void_p(_stream_ptr(packed.device)))
+    _check(st, "tv2d_solve_batched")
     outs = [x[offs[j]:offs[j] + shapes[j][0] * shapes[j][1]].view(shapes[j]) for j in range(n)]
-    infos = [{"iters": s.iters, "status": s.status, "gap_norm": s.gap_norm, "primal": s.primal, "dual": s.dual}
-             for s in stats]
-    return outs, infos
+    return outs, _read_stats(sbuf, n)
 
 
 def tv2d_l1(f: torch.Tensor, lam: float, max_iter: int = 200, energy_every: int = 10, tau0: float = 1.0,
@@ -684,10 +695,11 @@ def tv2d_l1(f: torch.Tensor, lam: float, max_iter: int = 200, energy_every: int 
     x = torch.empty_like(f)
     opt = Tv2dOptions(int(max_iter), int(energy_every), 0.0, float(tau0), 0,
                       ctypes.c_void_p(energy_history.data_ptr()) if energy_history is not None else None, 0)
-    st = Tv2dStats()
-    _check(lib.tv2d_l1_solve(code, _ptr(f), H, W, W, float(lam), _ptr(x), ctypes.byref(opt), ctypes.byref(st),
+    sbuf = _stats_buffer(1, f.device)
+    _check(lib.tv2d_l1_solve(code, _ptr(f), H, W, W, float(lam), _ptr(x), ctypes.byref(opt), _ptr(sbuf),
                              _ptr(ws), nbytes, stream), "tv2d_l1_solve")
-    info = {"iters": st.iters, "status": st.status, "primal": st.primal}
+    r = _read_stats(sbuf, 1)[0]
+    info = {"iters": r["iters"], "status": r["status"], "primal": r["primal"], "device_ms": r["device_ms"]}
     if plans is not None:
         info["plans"] = plans
     return x, info

@@ -119,7 +119,14 @@ struct SegWs {
     G *fb_tag;
     int64_t fb_cap;
     int64_t fb_lanes;
+    const int *stop;    // device flag (or null): when set, every kernel of the launch returns at once
 };
+
+// The launch's stop flag is set (a 2D solve that already met its stopping test).
+template <typename T, typename G>
+__device__ __forceinline__ bool seg_stopped(const SegWs<T, G> &ws) {
+    return ws.stop && *(volatile const int *)ws.stop;
+}
 
 struct ChainSpan {
     int64_t base;  // element of node 0
@@ -757,6 +764,10 @@ __device__ __forceinline__ int64_t fwd_run_t(CRing<T, K, typename Prob::Tag> &R,
     return b;
 }
 
+// A source whose vec is a compile-time false never takes the 16-byte path.
+template <class S, class = void> struct NeverVec : std::false_type {};
+template <class S> struct NeverVec<S, std::enable_if_t<!S::vec>> : std::true_type {};
+
 // The prefetch path is chosen once per wave: lanes whose chains all allow
 // 16-byte loads take them, any other wave loads node by node.  (A per-lane
 // choice would make every prefetch load conditional, and the compiler then
@@ -765,8 +776,10 @@ template <typename T, class Prob, int K, int P, bool kStore, class Hook>
 __device__ __forceinline__ int64_t fwd_run(CRing<T, K, typename Prob::Tag> &R, const typename Prob::Src &src,
                                            bool &ok, CarryOf<T, Prob> &cy, int64_t from, int64_t b, int64_t n,
                                            LamPair<T> *lam, int64_t C, int64_t c, Hook hook) {
-    if (__ballot(!src.vec) == 0)
-        return fwd_run_t<T, Prob, K, P, kStore, true>(R, src, ok, cy, from, b, n, lam, C, c, hook);
+    if constexpr (!NeverVec<typename Prob::Src>::value) {
+        if (__ballot(!src.vec) == 0)
+            return fwd_run_t<T, Prob, K, P, kStore, true>(R, src, ok, cy, from, b, n, lam, C, c, hook);
+    }
     return fwd_run_t<T, Prob, K, P, kStore, false>(R, src, ok, cy, from, b, n, lam, C, c, hook);
 }
 
@@ -959,6 +972,7 @@ __device__ __forceinline__ bool meets_checkpoint(const SegWs<T, G> &ws, const CR
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob::Params pp) {
     __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
+    if (seg_stopped(ws)) return;
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g == 0) *ws.ovf_count = 0;  // consumed by k_seg_fix / k_seg_ovf after this kernel
@@ -1006,6 +1020,7 @@ __global__ __launch_bounds__(64) void k_seg_main(WsOf<T, Prob> ws, typename Prob
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_repair(WsOf<T, Prob> ws, typename Prob::Params pp) {
     __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
+    if (seg_stopped(ws)) return;
     const int lane = threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     if (g >= (ws.S - 1) * ws.C) return;
@@ -1141,6 +1156,7 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
 template <typename T, class Prob, int K, int P>
 __global__ __launch_bounds__(64) void k_seg_fix(WsOf<T, Prob> ws, typename Prob::Params pp) {
     __shared__ EntOf<T, Prob> s_ent[CRing<T, K, typename Prob::Tag>::kRows * 64];
+    if (seg_stopped(ws)) return;
     const int lane = threadIdx.x;
     const int64_t c = (int64_t)blockIdx.x * 64 + lane;
     if (c >= ws.C) return;
@@ -1230,6 +1246,7 @@ template <typename T, class Prob>
 __global__ __launch_bounds__(64) void k_seg_ovf(WsOf<T, Prob> ws, typename Prob::Params pp) {
     constexpr int KB = OvfRing<EntOf<T, Prob>>::K;
     __shared__ EntOf<T, Prob> s_big[CRing<T, KB, typename Prob::Tag>::kRows * 64];
+    if (seg_stopped(ws)) return;
     const int lane = threadIdx.x;
     const int64_t l = (int64_t)blockIdx.x * 64 + lane;
     const int64_t cnt = *ws.ovf_count;
@@ -1256,6 +1273,7 @@ __global__ __launch_bounds__(64) void k_seg_ovf(WsOf<T, Prob> ws, typename Prob:
 // ---------------------------------------------------------------------------
 template <typename T, class Prob>
 __global__ __launch_bounds__(64) void k_seg_tail(WsOf<T, Prob> ws, typename Prob::Params pp) {
+    if (seg_stopped(ws)) return;
     const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (g >= (ws.S - 1) * ws.C) return;
     const int64_t c = g % ws.C, s = g / ws.C;
@@ -1334,6 +1352,7 @@ size_t seg_ws_layout(void *base, int64_t C, int64_t n, int64_t L, int64_t H, int
         w.fb_tag = (G *)(p + o_ft);
         w.fb_cap = cap;
         w.fb_lanes = fbl;
+        w.stop = nullptr;
         *out = w;
     }
     return off;
@@ -1385,27 +1404,33 @@ size_t seg_ws_bytes(int64_t C, int64_t n, const SegPlan &p) {
     }
 }
 
+// One segmented launch (five kernels) of plan p.  stop (device, optional):
+// when it is set by the time a kernel starts, that kernel does nothing.
 template <typename T, class Prob, int P>
 hipError_t seg_run(void *workspace, int64_t C, int64_t n, const SegPlan &p, const typename Prob::Params &pp,
-                   hipStream_t stream) {
+                   hipStream_t stream, const int *stop = nullptr) {
     using G = typename Prob::Tag;
     WsOf<T, Prob> ws;
     const int K = ring_slots_for<T, G>(p.K);
     if constexpr (ring_max<T, G>() >= 128) {
         if (K == 128) {
             seg_ws_layout<T, 128>(workspace, C, n, p.L, p.H, p.CK, &ws);
+            ws.stop = stop;
             return seg_launch<T, Prob, 128, P>(ws, pp, stream);
         }
         if (K == 64) {
             seg_ws_layout<T, 64>(workspace, C, n, p.L, p.H, p.CK, &ws);
+            ws.stop = stop;
             return seg_launch<T, Prob, 64, P>(ws, pp, stream);
         }
     }
     if (K == 32) {
         seg_ws_layout<T, 32>(workspace, C, n, p.L, p.H, p.CK, &ws);
+        ws.stop = stop;
         return seg_launch<T, Prob, 32, P>(ws, pp, stream);
     }
     seg_ws_layout<T, 16>(workspace, C, n, p.L, p.H, p.CK, &ws);
+    ws.stop = stop;
     return seg_launch<T, Prob, 16, P>(ws, pp, stream);
 }
 

@@ -8,7 +8,9 @@
 // counter and step schedule (tau_k, sigma_k = 1/tau_k, theta_k); each has its
 // own lambda and its own FP64 duality gap, and an image whose gap reaches the
 // tolerance is frozen on the device: its chains and gap terms are skipped from
-// then on and its iterate stays in the buffer it was in.
+// then on and its iterate stays in the buffer it was in.  Once every image is
+// frozen the solve stops on the device (every later kernel returns at once),
+// so the host enqueues all iterations without reading anything back.
 #include <math.h>
 
 #include <algorithm>
@@ -212,7 +214,9 @@ struct BImg {
 template <typename T>
 __global__ __launch_bounds__(64) void k_bgap_pv(const BChain *__restrict__ cols, int64_t ncols,
                                                 const T *__restrict__ y, T *__restrict__ pv,
-                                                const double *__restrict__ lam, const int *__restrict__ active) {
+                                                const double *__restrict__ lam, const int *__restrict__ active,
+                                                const int *__restrict__ stop) {
+    if (*stop) return;
     const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (c >= ncols) return;
     const BChain d = cols[c];
@@ -244,7 +248,9 @@ __global__ __launch_bounds__(kGapBlock) void k_bgap_rows(const BImg *__restrict_
                                                          const T *__restrict__ xn, const T *__restrict__ xo,
                                                          const T *__restrict__ y, const T *__restrict__ pv,
                                                          const double *__restrict__ lamv, const int *__restrict__ active,
-                                                         const IterSched *__restrict__ sc, double *__restrict__ part) {
+                                                         const IterSched *__restrict__ sc, double *__restrict__ part,
+                                                         const int *__restrict__ stop) {
+    if (*stop) return;
     const T tau = (T)sc->tau, inv1p = (T)sc->inv1p;
     const double pscale = sc->pscale;
     const int lane = threadIdx.x & 63;
@@ -309,15 +315,26 @@ __global__ __launch_bounds__(kGapBlock) void k_bgap_rows(const BImg *__restrict_
     }
 }
 
-// One block per image: reduce the image's rows, record the gap, freeze the
-// image once it is at the tolerance (its iterate is in buffer `nxt`).
-__global__ __launch_bounds__(kGapBlock) void k_bgap_final(const BImg *__restrict__ imgs, const double *__restrict__ part,
-                                                          int *__restrict__ active, int *__restrict__ buf,
-                                                          int *__restrict__ iters, double *__restrict__ gap3,
-                                                          double tol, int nxt, const IterSched *__restrict__ sc) {
-    const int iter_after = (int)sc->iter_after;
+// Per-image solver state on the device.
+struct BState {
+    int buf;        // buffer holding a frozen image's iterate
+    int iters;      // iterations done at the image's last gap evaluation
+    int status;     // a frozen image's status (TV_OK or TV_ERR_NONFINITE)
+    double gap[3];  // P, D, gap_norm of the last evaluation
+    uint64_t t1;    // device wall clock when the image froze
+};
+
+// One block per image: reduce the image's rows and record the gap.  An image
+// whose gap is at tol > 0, or is not finite, is frozen (its iterate is in
+// buffer `nxt`); the image that freezes last stops the solve.
+static __global__ __launch_bounds__(kGapBlock) void k_bgap_final(const BImg *__restrict__ imgs, const double *__restrict__ part,
+                                                          BState *__restrict__ bs, int *__restrict__ active,
+                                                          SolveCtl *__restrict__ ctl, double tol, int nxt,
+                                                          const IterSched *__restrict__ sc) {
+    if (*(volatile const int *)&ctl->stop) return;
     const int j = blockIdx.x;
     if (!active[j]) return;  // uniform per block
+    const int iter_after = (int)sc->iter_after;
     const BImg im = imgs[j];
     __shared__ double sP[kGapBlock], sD[kGapBlock];
     double P = 0.0, D = 0.0;
@@ -337,21 +354,68 @@ __global__ __launch_bounds__(kGapBlock) void k_bgap_final(const BImg *__restrict
     }
     if (threadIdx.x == 0) {
         const double g = (sP[0] - sD[0]) / (double)(im.H * im.W);
-        gap3[3 * j] = sP[0];
-        gap3[3 * j + 1] = sD[0];
-        gap3[3 * j + 2] = g;
-        iters[j] = iter_after;
-        if (tol > 0.0 && g <= tol) {
+        BState &b = bs[j];
+        b.gap[0] = sP[0];
+        b.gap[1] = sD[0];
+        b.gap[2] = g;
+        b.iters = iter_after;
+        const bool bad = !isfinite(g);
+        if (bad || (tol > 0.0 && g <= tol)) {
+            b.status = bad ? TV_ERR_NONFINITE : TV_OK;
+            b.buf = nxt;
+            b.t1 = wall_clock64();
             active[j] = 0;
-            buf[j] = nxt;
+            // the image that freezes last stops the solve
+            if (atomicSub(&ctl->n_active, 1) == 1) ctl_stop(ctl, TV_OK);
         }
     }
+}
+
+// Fresh per-image state: active, iterate in buffer 0, no gap yet.
+static __global__ void k_binit(BState *__restrict__ bs, int *__restrict__ active, int nimg) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nimg) return;
+    BState b;
+    b.buf = 0;
+    b.iters = 0;
+    b.status = TV_OK;
+    b.gap[0] = b.gap[1] = b.gap[2] = __builtin_nan("");
+    b.t1 = 0;
+    bs[j] = b;
+    active[j] = 1;
+}
+
+// Stats of every image (one thread each).  An image still active after the
+// last iteration has not reached tol > 0.
+static __global__ void k_bstats(const BState *__restrict__ bs, const int *__restrict__ active,
+                                const SolveCtl *__restrict__ ctl, int nimg, double tol, double clk_khz,
+                                tv2d_stats *__restrict__ stats) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nimg) return;
+    const BState b = bs[j];
+    const bool live = active[j] != 0;
+    int st = TV_OK;
+    if (!live) st = b.status;
+    else if (tol > 0.0) st = TV_ERR_NOT_CONVERGED;
+    double ms = 0.0;
+    if (ctl->t0 != 0 && clk_khz > 0.0) {
+        const uint64_t t1 = live ? (ctl->stop ? ctl->t1 : wall_clock64()) : b.t1;
+        ms = (double)(t1 - ctl->t0) / clk_khz;
+    }
+    tv2d_stats o;
+    o.iters = b.iters;
+    o.status = st;
+    o.gap_norm = b.gap[2];
+    o.primal = b.gap[0];
+    o.dual = b.gap[1];
+    o.device_ms = ms;
+    stats[j] = o;
 }
 
 // Copy each image's iterate (buffer buf[j], or `cur` if still active) out.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bcopy_out(const BImg *__restrict__ imgs, int nimg, const int *__restrict__ active,
-                                                   const int *__restrict__ buf, int cur, const T *__restrict__ x0,
+                                                   const BState *__restrict__ bs, int cur, const T *__restrict__ x0,
                                                    const T *__restrict__ x1, T *__restrict__ out, int64_t total) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= total) return;
@@ -361,7 +425,7 @@ __global__ __launch_bounds__(256) void k_bcopy_out(const BImg *__restrict__ imgs
         if (imgs[mid].off <= i) lo = mid;
         else hi = mid - 1;
     }
-    const int b = active[lo] ? cur : buf[lo];
+    const int b = active[lo] ? cur : bs[lo].buf;
     out[i] = b ? x1[i] : x0[i];
 }
 
@@ -392,8 +456,10 @@ template <typename T>
 struct BWs {
     BImg *imgs;
     BChain *rows, *cols;
-    int *rowimg, *active, *buf, *iters;
-    double *lam, *gap3, *part;
+    int *rowimg, *active;  // active: 1 while an image iterates (read by the chain launches)
+    BState *bs;
+    SolveCtl *ctl;
+    double *lam, *part;
     T *x[2], *y[2], *xbar, *pv;
     IterSched *sched;  // [kSchedCap] per-iteration scalars of the current chunk
     void *seg;
@@ -413,10 +479,9 @@ static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
     const size_t o_cl = off;  off += al(sizeof(BChain) * (size_t)g.ncols);
     const size_t o_ri = off;  off += al(sizeof(int) * (size_t)g.nrows);
     const size_t o_ac = off;  off += al(sizeof(int) * g.nimg);
-    const size_t o_bf = off;  off += al(sizeof(int) * g.nimg);
-    const size_t o_it = off;  off += al(sizeof(int) * g.nimg);
+    const size_t o_bs = off;  off += al(sizeof(BState) * g.nimg);
+    const size_t o_ct = off;  off += al(sizeof(SolveCtl));
     const size_t o_lm = off;  off += al(sizeof(double) * g.nimg);
-    const size_t o_g3 = off;  off += al(sizeof(double) * 3 * g.nimg);
     const size_t o_pt = off;  off += al(sizeof(double) * 2 * (size_t)g.nrows);
     const size_t o_x0 = off;  off += al(sizeof(T) * N);
     const size_t o_x1 = off;  off += al(sizeof(T) * N);
@@ -433,10 +498,9 @@ static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
         out->cols = (BChain *)(p + o_cl);
         out->rowimg = (int *)(p + o_ri);
         out->active = (int *)(p + o_ac);
-        out->buf = (int *)(p + o_bf);
-        out->iters = (int *)(p + o_it);
+        out->bs = (BState *)(p + o_bs);
+        out->ctl = (SolveCtl *)(p + o_ct);
         out->lam = (double *)(p + o_lm);
-        out->gap3 = (double *)(p + o_g3);
         out->part = (double *)(p + o_pt);
         out->x[0] = (T *)(p + o_x0);
         out->x[1] = (T *)(p + o_x1);
@@ -452,10 +516,12 @@ static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
 }
 
 // Uploads the geometry and chain lists (longest chains first; stable, so an
-// image's chains stay adjacent and in order) and sets x^0 = xbar^0 = f, y^0 = 0.
+// image's chains stay adjacent and in order), sets x^0 = xbar^0 = f, y^0 = 0,
+// and starts the device control at tau0 with every image active.  Waits once,
+// for the uploads from host memory.
 template <typename T>
 static tv_status batched_setup(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
-                               const double *lam, const T *f, const BWs<T> &ws, hipStream_t st) {
+                               const double *lam, const T *f, double tau0, const BWs<T> &ws, hipStream_t st) {
     std::vector<BImg> imgs(g.nimg);
     std::vector<int> rowimg((size_t)g.nrows);
     std::vector<BChain> rows, cols;
@@ -474,17 +540,15 @@ static tv_status batched_setup(const BGeom &g, const int64_t *H, const int64_t *
     auto longer = [](const BChain &a, const BChain &b) { return a.n > b.n; };
     std::stable_sort(rows.begin(), rows.end(), longer);
     std::stable_sort(cols.begin(), cols.end(), longer);
-    std::vector<int> ones(g.nimg, 1), zeros(g.nimg, 0);
     hipError_t e = hipSuccess;
     e = e ? e : hipMemcpyAsync(ws.imgs, imgs.data(), sizeof(BImg) * g.nimg, hipMemcpyHostToDevice, st);
     e = e ? e : hipMemcpyAsync(ws.rows, rows.data(), sizeof(BChain) * rows.size(), hipMemcpyHostToDevice, st);
     e = e ? e : hipMemcpyAsync(ws.cols, cols.data(), sizeof(BChain) * cols.size(), hipMemcpyHostToDevice, st);
     e = e ? e : hipMemcpyAsync(ws.rowimg, rowimg.data(), sizeof(int) * rowimg.size(), hipMemcpyHostToDevice, st);
     e = e ? e : hipMemcpyAsync(ws.lam, lam, sizeof(double) * g.nimg, hipMemcpyHostToDevice, st);
-    e = e ? e : hipMemcpyAsync(ws.active, ones.data(), sizeof(int) * g.nimg, hipMemcpyHostToDevice, st);
-    e = e ? e : hipMemcpyAsync(ws.buf, zeros.data(), sizeof(int) * g.nimg, hipMemcpyHostToDevice, st);
-    e = e ? e : hipMemcpyAsync(ws.iters, zeros.data(), sizeof(int) * g.nimg, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return TV_ERR_HIP;
+    hipLaunchKernelGGL(k_binit, dim3((unsigned)((g.nimg + 255) / 256)), dim3(256), 0, st, ws.bs, ws.active, g.nimg);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, ws.ctl, tau0, g.nimg);
     const unsigned nb = (unsigned)((g.total + 255) / 256);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, g.total, ws.x[0], g.total, (int64_t)1, g.total);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, g.total, ws.xbar, g.total, (int64_t)1, g.total);
@@ -495,42 +559,45 @@ static tv_status batched_setup(const BGeom &g, const int64_t *H, const int64_t *
 
 template <typename T>
 static hipError_t batched_col_step(const BGeom &g, const BWs<T> &ws, int cur, const IterSched *sc, const SegPlan &pc,
-                                   hipStream_t st) {
+                                   hipStream_t st, const int *stop = nullptr) {
     typename BColProb<T>::Params cp{ws.cols, ws.y[cur], ws.xbar, ws.y[cur ^ 1], sc, ws.lam, ws.active};
-    return seg_run<T, BColProb<T>, kTile>(ws.seg, g.ncols, g.maxH, pc, cp, st);
+    return seg_run<T, BColProb<T>, kTile>(ws.seg, g.ncols, g.maxH, pc, cp, st, stop);
 }
 
 template <typename T>
 static hipError_t batched_row_step(const BGeom &g, const BWs<T> &ws, const T *f, int cur, const IterSched *sc,
-                                   const SegPlan &pr, hipStream_t st) {
+                                   const SegPlan &pr, hipStream_t st, const int *stop = nullptr) {
     typename BRowProb<T>::Params rp{ws.rows, f, ws.x[cur], ws.y[cur ^ 1], ws.x[cur ^ 1], ws.xbar, sc, ws.lam,
                                     ws.active};
-    return seg_run<T, BRowProb<T>, kTile>(ws.seg, g.nrows, g.maxW, pr, rp, st);
+    return seg_run<T, BRowProb<T>, kTile>(ws.seg, g.nrows, g.maxW, pr, rp, st, stop);
 }
 
-// Issues `count` iterations starting at parity cur0; iteration j reads its
-// scalars from ws.sched[j]; the last one is followed by the gap evaluation and
-// the per-image stopping test.  The same sequence is launched directly or
-// captured into a HIP graph and replayed.
+// Issues `count` iterations starting at parity cur0, iteration j reading
+// ws.sched[j] (generated on the device first); with `gap`, the gap evaluation
+// and the per-image stopping test follow the last one.  Nothing here reads host
+// memory, so the same sequence is launched directly or captured into a HIP
+// graph and replayed.  Every kernel returns at once once the solve has stopped.
 template <typename T>
-static hipError_t batched_iters(const BGeom &g, const BWs<T> &ws, const T *f, int cur0, int count, double gap_tol,
-                                const SegPlan &pc, const SegPlan &pr, hipStream_t st) {
+static hipError_t batched_iters(const BGeom &g, const BWs<T> &ws, const T *f, int cur0, int count, bool gap,
+                                double gap_tol, const SegPlan &pc, const SegPlan &pr, hipStream_t st) {
+    const int *stop = &ws.ctl->stop;
+    hipLaunchKernelGGL(k_ctl_sched, dim3(1), dim3(64), 0, st, ws.ctl, ws.sched, count);
     int cur = cur0;
     for (int j = 0; j < count; ++j) {
         const int nxt = cur ^ 1;
         const IterSched *sc = ws.sched + j;
-        hipError_t e = batched_col_step<T>(g, ws, cur, sc, pc, st);
-        if (e == hipSuccess) e = batched_row_step<T>(g, ws, f, cur, sc, pr, st);
+        hipError_t e = batched_col_step<T>(g, ws, cur, sc, pc, st, stop);
+        if (e == hipSuccess) e = batched_row_step<T>(g, ws, f, cur, sc, pr, st, stop);
         if (e != hipSuccess) return e;
-        if (j == count - 1) {
+        if (gap && j == count - 1) {
             const unsigned cb = (unsigned)((g.ncols + 63) / 64);
             hipLaunchKernelGGL((k_bgap_pv<T>), dim3(cb), dim3(64), 0, st, ws.cols, g.ncols, ws.y[nxt], ws.pv, ws.lam,
-                               ws.active);
+                               ws.active, stop);
             const unsigned rb = (unsigned)((g.nrows + kGapBlock / 64 - 1) / (kGapBlock / 64));
             hipLaunchKernelGGL((k_bgap_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, ws.imgs, ws.rowimg, g.nrows, f,
-                               ws.x[nxt], ws.x[cur], ws.y[nxt], ws.pv, ws.lam, ws.active, sc, ws.part);
-            hipLaunchKernelGGL(k_bgap_final, dim3(g.nimg), dim3(kGapBlock), 0, st, ws.imgs, ws.part, ws.active,
-                               ws.buf, ws.iters, ws.gap3, gap_tol, nxt, sc);
+                               ws.x[nxt], ws.x[cur], ws.y[nxt], ws.pv, ws.lam, ws.active, sc, ws.part, stop);
+            hipLaunchKernelGGL(k_bgap_final, dim3(g.nimg), dim3(kGapBlock), 0, st, ws.imgs, ws.part, ws.bs,
+                               ws.active, ws.ctl, gap_tol, nxt, sc);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -539,93 +606,56 @@ static hipError_t batched_iters(const BGeom &g, const BWs<T> &ws, const T *f, in
     return hipSuccess;
 }
 
-
+// The iterations are enqueued on st without waiting (the stopping test runs
+// on the device, see batched_iters); the setup waits once for its uploads, and
+// a solve that replays captured graphs waits for them before returning.
 template <typename T>
 static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
                                  const double *lam, const T *f, T *x, const tv2d_options *opt, tv2d_stats *stats,
                                  void *workspace, hipStream_t st) {
     BWs<T> ws;
     batched_layout<T>(workspace, g, &ws);
-    const tv_status s0 = batched_setup<T>(g, H, W, pix, lam, f, ws, st);
+    const tv_status s0 = batched_setup<T>(g, H, W, pix, lam, f, opt->tau0, ws, st);
     if (s0 != TV_OK) return s0;
     const unsigned nb = (unsigned)((g.total + 255) / 256);
-    std::vector<double> gap3(3 * (size_t)g.nimg, NAN);
-    std::vector<int> active(g.nimg, 1), iters(g.nimg, 0);
     const int every = opt->gap_every > 0 ? opt->gap_every : 1;
-    double tau = opt->tau0;
-    int cur = 0, k = 0;
-    int n_active = g.nimg;
     const SegPlan pr = seg_plan(g.nrows, g.maxW, kPlanBatchRow), pc = seg_plan(g.ncols, g.maxH, kPlanBatchCol);
     if (seg_ws_bytes_plan<T>(g.nrows, g.maxW, pr) > ws.seg_bytes ||
         seg_ws_bytes_plan<T>(g.ncols, g.maxH, pc) > ws.seg_bytes)
         return TV_ERR_WORKSPACE;
     ChunkGraphs graphs;
-    std::vector<IterSched> sched(kSchedCap);
-    while (k < opt->max_iter && n_active > 0) {
-        const int chunk = (opt->max_iter - k < every) ? opt->max_iter - k : every;
-        // upload the chunk's schedule in pieces of at most kSchedCap iterations;
-        // the gap follows the chunk's last iteration
-        for (int done = 0; done < chunk;) {
-            const int piece = (chunk - done < kSchedCap) ? chunk - done : kSchedCap;
-            for (int j = 0; j < piece; ++j) {
-                sched[j] = make_sched(tau, k + j);
-                tau *= sched[j].theta;
-            }
-            if (hipMemcpyAsync(ws.sched, sched.data(), sizeof(IterSched) * piece, hipMemcpyHostToDevice, st) !=
-                hipSuccess)
-                return TV_ERR_HIP;
-            const bool last = done + piece == chunk;
-            const double tol = opt->gap_tol;
-            auto issue = [&](hipStream_t s2) { return batched_iters<T>(g, ws, f, cur, piece, tol, pc, pr, s2); };
+    int cur = 0;
+    for (int done = 0; done < opt->max_iter;) {
+        const int chunk = (opt->max_iter - done < every) ? opt->max_iter - done : every;
+        // pieces of at most kSchedCap iterations; the gap follows the chunk's last
+        for (int part = 0; part < chunk;) {
+            const int piece = (chunk - part < kSchedCap) ? chunk - part : kSchedCap;
+            const bool last = part + piece == chunk;
+            const int c0 = cur;
+            auto issue = [&](hipStream_t s2) {
+                return batched_iters<T>(g, ws, f, c0, piece, last, opt->gap_tol, pc, pr, s2);
+            };
             hipGraphExec_t ge = nullptr;
-            if (opt->use_graph && last && piece == every && done == 0) ge = graphs.get(cur, issue);
+            if (opt->use_graph && last && piece == every && part == 0) ge = graphs.get(cur, issue);
             if (ge) {
                 if (hipGraphLaunch(ge, st) != hipSuccess) return TV_ERR_HIP;
-            } else if (last) {
-                if (batched_iters<T>(g, ws, f, cur, piece, tol, pc, pr, st) != hipSuccess) return TV_ERR_HIP;
-            } else {
-                // a piece without the gap: iterations only
-                for (int j = 0; j < piece; ++j) {
-                    if (batched_col_step<T>(g, ws, (cur + j) & 1, ws.sched + j, pc, st) != hipSuccess ||
-                        batched_row_step<T>(g, ws, f, (cur + j) & 1, ws.sched + j, pr, st) != hipSuccess)
-                        return TV_ERR_HIP;
-                }
+            } else if (issue(st) != hipSuccess) {
+                return TV_ERR_HIP;
             }
-            // the host schedule buffer is reused by the next piece: wait for the upload
-            if (!last && hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
             cur = (cur + piece) & 1;
-            k += piece;
-            done += piece;
+            part += piece;
         }
-        if (hipMemcpyAsync(active.data(), ws.active, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st) != hipSuccess)
-            return TV_ERR_HIP;
-        if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
-        n_active = 0;
-        for (int j = 0; j < g.nimg; ++j) n_active += active[j];
+        done += chunk;
     }
-    hipLaunchKernelGGL((k_bcopy_out<T>), dim3(nb), dim3(256), 0, st, ws.imgs, g.nimg, ws.active, ws.buf, cur, ws.x[0],
+    hipLaunchKernelGGL((k_bcopy_out<T>), dim3(nb), dim3(256), 0, st, ws.imgs, g.nimg, ws.active, ws.bs, cur, ws.x[0],
                        ws.x[1], x, g.total);
-    hipError_t e = hipMemcpyAsync(gap3.data(), ws.gap3, sizeof(double) * 3 * g.nimg, hipMemcpyDeviceToHost, st);
-    e = e ? e : hipMemcpyAsync(iters.data(), ws.iters, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st);
-    e = e ? e : hipMemcpyAsync(active.data(), ws.active, sizeof(int) * g.nimg, hipMemcpyDeviceToHost, st);
-    e = e ? e : hipStreamSynchronize(st);
-    if (e != hipSuccess) return TV_ERR_HIP;
-    tv_status worst = TV_OK;
-    for (int j = 0; j < g.nimg; ++j) {
-        int s = TV_OK;
-        if (!isfinite(gap3[3 * j + 2])) s = TV_ERR_NONFINITE;
-        else if (opt->gap_tol > 0.0 && active[j]) s = TV_ERR_NOT_CONVERGED;
-        if (stats) {
-            stats[j].iters = iters[j];
-            stats[j].status = s;
-            stats[j].primal = gap3[3 * j];
-            stats[j].dual = gap3[3 * j + 1];
-            stats[j].gap_norm = gap3[3 * j + 2];
-        }
-        if (s == TV_ERR_NONFINITE) worst = TV_ERR_NONFINITE;
-        else if (s == TV_ERR_NOT_CONVERGED && worst == TV_OK) worst = TV_ERR_NOT_CONVERGED;
-    }
-    return worst;
+    if (stats)
+        hipLaunchKernelGGL(k_bstats, dim3((unsigned)((g.nimg + 255) / 256)), dim3(256), 0, st, ws.bs, ws.active,
+                           ws.ctl, g.nimg, opt->gap_tol, wall_clock_khz(), stats);
+    if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
+    // captured graphs live for this call only: wait for their replays
+    if (graphs.exec[0] || graphs.exec[1]) return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
+    return TV_OK;
 }
 
 // Autotune of the batched column and row launches on the first iteration's data.
@@ -635,22 +665,15 @@ static tv_status batched_autotune_t(const BGeom &g, const int64_t *H, const int6
                                     tv_tuning_result *col, tv_tuning_result *row) {
     BWs<T> ws;
     batched_layout<T>(workspace, g, &ws);
-    tv_status s = batched_setup<T>(g, H, W, pix, lam, f, ws, st);
+    tv_status s = batched_setup<T>(g, H, W, pix, lam, f, tau0, ws, st);
     if (s != TV_OK) return s;
     // a few iterations first, so the plans are timed on deques as deep as the
-    // solve's later iterations build (no image converges: tolerance 0)
-    IterSched sc[kTuneWarm + 1];
-    double tau = tau0;
-    for (int j = 0; j <= kTuneWarm; ++j) {
-        sc[j] = make_sched(tau, j);
-        tau *= sc[j].theta;
-    }
-    if (hipMemcpyAsync(ws.sched, sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
-    if (batched_iters<T>(g, ws, f, 0, kTuneWarm, 0.0, seg_plan(g.ncols, g.maxH, kPlanBatchCol),
+    // solve's later iterations build (no gap evaluation: nothing stops)
+    if (batched_iters<T>(g, ws, f, 0, kTuneWarm, false, 0.0, seg_plan(g.ncols, g.maxH, kPlanBatchCol),
                          seg_plan(g.nrows, g.maxW, kPlanBatchRow), st) != hipSuccess)
         return TV_ERR_HIP;
-    if (hipMemcpyAsync(ws.sched, &sc[kTuneWarm], sizeof(IterSched), hipMemcpyHostToDevice, st) != hipSuccess)
-        return TV_ERR_HIP;
+    // the timed steps read iteration kTuneWarm's scalars from the first slot
+    hipLaunchKernelGGL(k_ctl_sched, dim3(1), dim3(64), 0, st, ws.ctl, ws.sched, 1);
     SegPlan pc, pr;
     s = tune_launch<T>(
         g.ncols, g.maxH, ws.seg_bytes,
@@ -666,8 +689,44 @@ static tv_status batched_autotune_t(const BGeom &g, const int64_t *H, const int6
     return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
 
+// Entry points per precision.  The build compiles this file in two parts (1:
+// FP32, 2: FP64 and the C ABI), each defining its group; the ABI calls them
+// through these declarations.
+tv_status batched_solve_f32(const BGeom &, const int64_t *, const int64_t *, const int64_t *, const double *,
+                            const float *, float *, const tv2d_options *, tv2d_stats *, void *, hipStream_t);
+tv_status batched_solve_f64(const BGeom &, const int64_t *, const int64_t *, const int64_t *, const double *,
+                            const double *, double *, const tv2d_options *, tv2d_stats *, void *, hipStream_t);
+tv_status batched_autotune_f32(const BGeom &, const int64_t *, const int64_t *, const int64_t *, const double *,
+                               const float *, double, void *, hipStream_t, tv_tuning_result *, tv_tuning_result *);
+tv_status batched_autotune_f64(const BGeom &, const int64_t *, const int64_t *, const int64_t *, const double *,
+                               const double *, double, void *, hipStream_t, tv_tuning_result *, tv_tuning_result *);
+#if TVC_IN_PART(1)
+tv_status batched_solve_f32(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix, const double *lam,
+                            const float *f, float *x, const tv2d_options *o, tv2d_stats *st, void *ws, hipStream_t s) {
+    return batched_solve_t<float>(g, H, W, pix, lam, f, x, o, st, ws, s);
+}
+tv_status batched_autotune_f32(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
+                               const double *lam, const float *f, double tau0, void *ws, hipStream_t s,
+                               tv_tuning_result *col, tv_tuning_result *row) {
+    return batched_autotune_t<float>(g, H, W, pix, lam, f, tau0, ws, s, col, row);
+}
+#endif
+#if TVC_IN_PART(2)
+tv_status batched_solve_f64(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix, const double *lam,
+                            const double *f, double *x, const tv2d_options *o, tv2d_stats *st, void *ws,
+                            hipStream_t s) {
+    return batched_solve_t<double>(g, H, W, pix, lam, f, x, o, st, ws, s);
+}
+tv_status batched_autotune_f64(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
+                               const double *lam, const double *f, double tau0, void *ws, hipStream_t s,
+                               tv_tuning_result *col, tv_tuning_result *row) {
+    return batched_autotune_t<double>(g, H, W, pix, lam, f, tau0, ws, s, col, row);
+}
+#endif
+
 }  // namespace tvc
 
+#if TVC_IN_PART(2)
 using namespace tvc;
 
 extern "C" {
@@ -709,10 +768,10 @@ tv_status tv2d_batched_autotune(tv_dtype dtype, int num_images, const int64_t *H
     tv_status s = batched_args(dtype, num_images, H, W, pixel_offsets, lambda, f, tau0, workspace, workspace_bytes, &g);
     if (s != TV_OK) return s;
     if (dtype == TV_F32)
-        return batched_autotune_t<float>(g, H, W, pixel_offsets, lambda, (const float *)f, tau0, workspace, stream,
-                                         col, row);
-    return batched_autotune_t<double>(g, H, W, pixel_offsets, lambda, (const double *)f, tau0, workspace, stream,
-                                      col, row);
+        return batched_autotune_f32(g, H, W, pixel_offsets, lambda, (const float *)f, tau0, workspace, stream, col,
+                                    row);
+    return batched_autotune_f64(g, H, W, pixel_offsets, lambda, (const double *)f, tau0, workspace, stream, col,
+                                row);
 }
 
 tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,
@@ -726,10 +785,11 @@ tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, c
                                workspace_bytes, &g);
     if (s != TV_OK) return s;
     if (dtype == TV_F32)
-        return batched_solve_t<float>(g, H, W, pixel_offsets, lambda, (const float *)f, (float *)x, options, stats,
-                                      workspace, stream);
-    return batched_solve_t<double>(g, H, W, pixel_offsets, lambda, (const double *)f, (double *)x, options, stats,
-                                   workspace, stream);
+        return batched_solve_f32(g, H, W, pixel_offsets, lambda, (const float *)f, (float *)x, options, stats,
+                                 workspace, stream);
+    return batched_solve_f64(g, H, W, pixel_offsets, lambda, (const double *)f, (double *)x, options, stats,
+                             workspace, stream);
 }
 
 }  // extern "C"
+#endif

@@ -33,7 +33,7 @@ constexpr int kSchedCap = 64;
 // state is back in the buffers of parity 0).
 constexpr int kTuneWarm = 8;
 
-__host__ __forceinline__ IterSched make_sched(double tau, int64_t k) {
+__host__ __device__ __forceinline__ IterSched make_sched(double tau, int64_t k) {
     IterSched s;
     s.tau = tau;
     s.sigma = 1.0 / tau;
@@ -42,6 +42,76 @@ __host__ __forceinline__ IterSched make_sched(double tau, int64_t k) {
     s.pscale = (1.0 + tau) / tau;
     s.iter_after = k + 1;
     return s;
+}
+
+// Device-resident control of a 2D solve.  The host enqueues every iteration
+// up to max_iter without waiting; the schedule is generated on the device, and
+// once the stopping test passes (or the gap is not finite) `stop` is set and
+// every later kernel of the solve returns at once.
+struct SolveCtl {
+    double tau;        // tau of the next iteration to schedule
+    int64_t knext;     // index of the next iteration to schedule
+    int32_t stop;      // 1: stopped; later launches do nothing
+    int32_t status;    // the solve's status once stopped (TV_OK or TV_ERR_NONFINITE)
+    int32_t n_active;  // batched solves: images still iterating
+    int32_t pad;
+    uint64_t t0, t1;   // device wall clock at the first scheduled iteration and at the stop
+};
+
+static __global__ void k_ctl_init(SolveCtl *c, double tau0, int n_active) {
+    if (threadIdx.x != 0) return;
+    c->tau = tau0;
+    c->knext = 0;
+    c->stop = 0;
+    c->status = TV_OK;
+    c->n_active = n_active;
+    c->pad = 0;
+    c->t0 = c->t1 = 0;
+}
+
+// A resumed solve continues from the saved schedule position.
+static __global__ void k_ctl_resume(SolveCtl *c) {
+    if (threadIdx.x != 0) return;
+    c->stop = 0;
+    c->status = TV_OK;
+    c->t0 = c->t1 = 0;
+}
+
+// The accelerated schedule of the next `count` iterations (FP64, one thread;
+// the same arithmetic as make_sched on the host).
+static __global__ void k_ctl_sched(SolveCtl *c, IterSched *sc, int count) {
+    if (threadIdx.x != 0 || c->stop) return;
+    if (c->t0 == 0) c->t0 = wall_clock64();
+    double tau = c->tau;
+    for (int j = 0; j < count; ++j) {
+        sc[j] = make_sched(tau, c->knext + j);
+        tau *= sc[j].theta;
+    }
+    c->tau = tau;
+    c->knext += count;
+}
+
+// Marks the solve stopped with `status` (one thread).
+__device__ __forceinline__ void ctl_stop(SolveCtl *c, int status) {
+    c->stop = 1;
+    c->status = status;
+    c->t1 = wall_clock64();
+}
+
+// Milliseconds of device time since the first scheduled iteration, up to the
+// stop (or now); clk_khz is the device wall clock's rate.
+__device__ __forceinline__ double ctl_ms(const SolveCtl *c, double clk_khz) {
+    if (c->t0 == 0 || clk_khz <= 0.0) return 0.0;
+    const uint64_t t1 = c->stop ? c->t1 : wall_clock64();
+    return (double)(t1 - c->t0) / clk_khz;
+}
+
+// Rate of the device wall clock in kHz (0 if unknown).
+static inline double wall_clock_khz() {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0.0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0.0;
+    return (double)khz;
 }
 
 // b_i of the row step; shared by the row chain source and the gap kernel so

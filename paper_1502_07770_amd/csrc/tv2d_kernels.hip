@@ -219,7 +219,8 @@ struct RowProb {
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_gap_colsum(const T *__restrict__ y, double *__restrict__ colpart, int64_t H,
-                                                   int64_t W) {
+                                                   int64_t W, const int *__restrict__ stop) {
+    if (*stop) return;
     const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t nseg = (H + kGapRows - 1) / kGapRows;
     if (g >= nseg * W) return;
@@ -233,7 +234,9 @@ __global__ __launch_bounds__(64) void k_gap_colsum(const T *__restrict__ y, doub
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_gap_pv(const T *__restrict__ y, const double *__restrict__ colpart,
-                                               T *__restrict__ pv, int64_t H, int64_t W, double lam) {
+                                               T *__restrict__ pv, int64_t H, int64_t W, double lam,
+                                               const int *__restrict__ stop) {
+    if (*stop) return;
     const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t nseg = (H + kGapRows - 1) / kGapRows;
     if (g >= nseg * W) return;
@@ -257,7 +260,9 @@ template <typename T>
 __global__ __launch_bounds__(kGapBlock) void k_gap_rows(const T *__restrict__ f, int64_t ldf, const T *__restrict__ xn,
                                                         const T *__restrict__ xo, const T *__restrict__ y,
                                                         const T *__restrict__ pv, int64_t H, int64_t W, double lam,
-                                                        const IterSched *__restrict__ sc, double *__restrict__ part) {
+                                                        const IterSched *__restrict__ sc, double *__restrict__ part,
+                                                        const int *__restrict__ stop) {
+    if (*stop) return;
     const T tau = (T)sc->tau, inv1p = (T)sc->inv1p;
     const double pscale = sc->pscale;
     const int lane = threadIdx.x & 63;
@@ -317,11 +322,21 @@ __global__ __launch_bounds__(kGapBlock) void k_gap_rows(const T *__restrict__ f,
     }
 }
 
-// Final reduction (one block): out = {P, D, (P - D) / (H W)}; also the gap
-// history slot of this iteration.
-__global__ __launch_bounds__(kGapBlock) void k_gap_final(const double *__restrict__ part, int nparts, double HW,
-                                                         double *__restrict__ out, double *__restrict__ hist,
-                                                         const IterSched *__restrict__ sc) {
+struct Tv2dHeader {  // device-resident solver state header
+    int64_t iters;   // iterations done (at the last gap evaluation)
+    int64_t cur;     // which x / y buffer holds the current iterate
+    double gap[3];   // P, D, gap_norm of the last evaluation
+    SolveCtl ctl;    // schedule position and stop flag
+};
+
+// Final reduction (one block): the header gets {P, D, (P - D) / (H W)}, the
+// iteration count and the buffer of the iterate (nxt); the gap history slot of
+// this iteration is written; and the solve stops once the gap is at tol > 0,
+// or is not finite.
+static __global__ __launch_bounds__(kGapBlock) void k_gap_final(const double *__restrict__ part, int nparts, double HW,
+                                                                Tv2dHeader *__restrict__ h, double *__restrict__ hist,
+                                                                const IterSched *__restrict__ sc, double tol, int nxt) {
+    if (*(volatile const int *)&h->ctl.stop) return;
     const int64_t hist_idx = sc->iter_after - 1;
     __shared__ double sP[kGapBlock], sD[kGapBlock];
     double P = 0.0, D = 0.0;
@@ -341,24 +356,53 @@ __global__ __launch_bounds__(kGapBlock) void k_gap_final(const double *__restric
     }
     if (threadIdx.x == 0) {
         const double g = (sP[0] - sD[0]) / HW;
-        out[0] = sP[0];
-        out[1] = sD[0];
-        out[2] = g;
+        h->gap[0] = sP[0];
+        h->gap[1] = sD[0];
+        h->gap[2] = g;
+        h->iters = sc->iter_after;
+        h->cur = nxt;
         if (hist) hist[hist_idx] = g;
+        if (!isfinite(g)) ctl_stop(&h->ctl, TV_ERR_NONFINITE);
+        else if (tol > 0.0 && g <= tol) ctl_stop(&h->ctl, TV_OK);
     }
+}
+
+// Copy of the iterate into the caller's x (ld >= W) and, from one thread, the
+// stats of the solve.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tv2d_finish(const Tv2dHeader *__restrict__ h, const T *__restrict__ x0,
+                                                     const T *__restrict__ x1, T *__restrict__ out, int64_t ld,
+                                                     int64_t H, int64_t W, tv2d_stats *__restrict__ stats, double tol,
+                                                     double clk_khz) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const T *src = h->cur ? x1 : x0;
+    if (i < H * W) out[(i / W) * ld + i % W] = src[i];
+    if (i == 0 && stats) {
+        const double g = h->gap[2];
+        int st = TV_OK;
+        if (h->ctl.stop) st = h->ctl.status;
+        else if (h->iters > 0 && !isfinite(g)) st = TV_ERR_NONFINITE;
+        else if (tol > 0.0) st = TV_ERR_NOT_CONVERGED;
+        stats->iters = (int)h->iters;
+        stats->status = st;
+        stats->gap_norm = g;
+        stats->primal = h->gap[0];
+        stats->dual = h->gap[1];
+        stats->device_ms = ctl_ms(&h->ctl, clk_khz);
+    }
+}
+
+// Fresh header: no iteration yet, tau0, the iterate in buffer 0.
+static __global__ void k_tv2d_init_hdr(Tv2dHeader *h) {
+    if (threadIdx.x != 0) return;
+    h->iters = 0;
+    h->cur = 0;
+    h->gap[0] = h->gap[1] = h->gap[2] = __builtin_nan("");
 }
 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-struct Tv2dHeader {  // device-resident solver state header
-    int64_t iters;
-    int64_t cur;     // which x / y buffer holds the current iterate
-    double tau;
-    double pad;
-    double gap[3];   // P, D, gap_norm of the last evaluation
-};
-
 template <typename T>
 struct Tv2dWs {
     Tv2dHeader *hdr;
@@ -413,44 +457,51 @@ static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out, bool
 // Column step: y[nxt] = eta - prox(eta), eta = y[cur] + sigma xbar.
 template <typename T>
 static hipError_t tv2d_col_step(const Tv2dWs<T> &ws, int64_t H, int64_t W, double lam, int cur, const IterSched *sc,
-                                const SegPlan &pc, hipStream_t st) {
+                                const SegPlan &pc, hipStream_t st, const int *stop = nullptr) {
     const int nxt = cur ^ 1;
     typename ColProb<T>::Params pp{ws.y[cur], ws.xbar, ws.y[nxt], sc, (T)lam, W};
-    return seg_run<T, ColProb<T>, kTile>(ws.seg, W, H, pc, pp, st);
+    return seg_run<T, ColProb<T>, kTile>(ws.seg, W, H, pc, pp, st, stop);
 }
 
 // Row step: x[nxt] = prox(b), xbar = x[nxt] + theta (x[nxt] - x[cur]).
 template <typename T>
 static hipError_t tv2d_row_step(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
-                                int cur, const IterSched *sc, const SegPlan &pr, hipStream_t st) {
+                                int cur, const IterSched *sc, const SegPlan &pr, hipStream_t st,
+                                const int *stop = nullptr) {
     const int nxt = cur ^ 1;
     typename RowProb<T>::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, sc, lam, W};
-    return seg_run<T, RowProb<T>, kTile>(ws.seg, H, W, pr, pp, st);
+    return seg_run<T, RowProb<T>, kTile>(ws.seg, H, W, pr, pp, st, stop);
 }
 
-// `count` iterations from parity cur0, iteration j reading ws.sched[j]; the gap
-// after the last one.  Launched directly or captured into a HIP graph.
+// `count` iterations from parity cur0, iteration j reading ws.sched[j]
+// (generated on the device first); with `gap`, the gap evaluation and the
+// stopping test follow the last one.  Launched directly or captured into a
+// HIP graph: nothing here reads host memory.  Every kernel returns at once if
+// the solve has stopped.
 template <typename T>
 static hipError_t tv2d_iters(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
-                             int cur0, int count, bool gap, double *hist, const SegPlan &pc, const SegPlan &pr,
-                             hipStream_t st) {
+                             int cur0, int count, bool gap, double tol, double *hist, const SegPlan &pc,
+                             const SegPlan &pr, hipStream_t st) {
+    const int *stop = &ws.hdr->ctl.stop;
+    hipLaunchKernelGGL(k_ctl_sched, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, ws.sched, count);
     int cur = cur0;
     for (int j = 0; j < count; ++j) {
         const int nxt = cur ^ 1;
         const IterSched *sc = ws.sched + j;
-        hipError_t e = tv2d_col_step<T>(ws, H, W, lam, cur, sc, pc, st);
-        if (e == hipSuccess) e = tv2d_row_step<T>(ws, f, ldf, H, W, lam, cur, sc, pr, st);
+        hipError_t e = tv2d_col_step<T>(ws, H, W, lam, cur, sc, pc, st, stop);
+        if (e == hipSuccess) e = tv2d_row_step<T>(ws, f, ldf, H, W, lam, cur, sc, pr, st, stop);
         if (e != hipSuccess) return e;
         if (gap && j == count - 1) {
             const int64_t nseg = (H + kGapRows - 1) / kGapRows;
             const unsigned cb = (unsigned)((nseg * W + 63) / 64);
-            hipLaunchKernelGGL((k_gap_colsum<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, H, W);
-            hipLaunchKernelGGL((k_gap_pv<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, ws.pv, H, W, lam);
+            hipLaunchKernelGGL((k_gap_colsum<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, H, W, stop);
+            hipLaunchKernelGGL((k_gap_pv<T>), dim3(cb), dim3(64), 0, st, ws.y[nxt], ws.colpart, ws.pv, H, W, lam,
+                               stop);
             const unsigned rb = (unsigned)((H + kGapBlock / 64 - 1) / (kGapBlock / 64));
             hipLaunchKernelGGL((k_gap_rows<T>), dim3(rb), dim3(kGapBlock), 0, st, f, ldf, ws.x[nxt], ws.x[cur],
-                               ws.y[nxt], ws.pv, H, W, lam, sc, ws.part);
-            hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(kGapBlock), 0, st, ws.part, (int)H, (double)(H * W),
-                               &ws.hdr->gap[0], hist, sc);
+                               ws.y[nxt], ws.pv, H, W, lam, sc, ws.part, stop);
+            hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(kGapBlock), 0, st, ws.part, (int)H, (double)(H * W), ws.hdr,
+                               hist, sc, tol, nxt);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -459,92 +510,63 @@ static hipError_t tv2d_iters(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64
     return hipSuccess;
 }
 
+// The whole solve is enqueued on st without waiting (the stopping test runs
+// on the device, see tv2d_iters); a resume reads the header once to learn
+// which buffer holds the iterate.
 template <typename T>
 static tv_status tv2d_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, double lam, T *x,
                               const tv2d_options *opt, tv2d_stats *stats, void *workspace, hipStream_t st) {
     Tv2dWs<T> ws;
     tv2d_layout<T>(workspace, H, W, &ws);
-    Tv2dHeader h{};
+    const unsigned nb = (unsigned)((H * W + 255) / 256);
+    int cur = 0;
     if (opt->resume) {
-        if (hipMemcpyAsync(&h, ws.hdr, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return TV_ERR_HIP;
+        int64_t c = 0;
+        if (hipMemcpyAsync(&c, &ws.hdr->cur, sizeof(c), hipMemcpyDeviceToHost, st) != hipSuccess) return TV_ERR_HIP;
         if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
+        cur = (int)(c & 1);
+        hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, st, &ws.hdr->ctl);
     } else {
         // x^0 = xbar^0 = f, y^0 = 0
-        const unsigned nb = (unsigned)((H * W + 255) / 256);
         hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
         hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
         hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
-        h.iters = 0;
-        h.cur = 0;
-        h.tau = opt->tau0;
-        h.gap[0] = h.gap[1] = h.gap[2] = NAN;
+        hipLaunchKernelGGL(k_tv2d_init_hdr, dim3(1), dim3(64), 0, st, ws.hdr);
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, opt->tau0, 1);
     }
     const int every = opt->gap_every > 0 ? opt->gap_every : 1;
-    int status = TV_OK;
-    int done = 0;
-    double g3[3] = {h.gap[0], h.gap[1], h.gap[2]};
-    bool have_gap = !opt->resume ? false : !isnan(h.gap[2]);
     const SegPlan pc = seg_plan(W, H, kPlan2dCol), pr = seg_plan(H, W, kPlan2dRow);
     if (seg_ws_bytes_plan<T>(W, H, pc) > ws.seg_bytes || seg_ws_bytes_plan<T>(H, W, pr) > ws.seg_bytes)
         return TV_ERR_WORKSPACE;
     ChunkGraphs graphs;
-    std::vector<IterSched> sched(kSchedCap);
-    while (done < opt->max_iter) {
+    for (int done = 0; done < opt->max_iter;) {
         const int chunk = (opt->max_iter - done < every) ? opt->max_iter - done : every;
         for (int part = 0; part < chunk;) {
             const int piece = (chunk - part < kSchedCap) ? chunk - part : kSchedCap;
-            for (int j = 0; j < piece; ++j) {
-                sched[j] = make_sched(h.tau, h.iters + j);
-                h.tau *= sched[j].theta;
-            }
-            if (hipMemcpyAsync(ws.sched, sched.data(), sizeof(IterSched) * piece, hipMemcpyHostToDevice, st) !=
-                hipSuccess)
-                return TV_ERR_HIP;
             const bool last = part + piece == chunk;
-            const int cur = (int)h.cur;
+            const int c0 = cur;
             auto issue = [&](hipStream_t s2) {
-                return tv2d_iters<T>(ws, f, ld, H, W, lam, cur, piece, true, opt->gap_history, pc, pr, s2);
+                return tv2d_iters<T>(ws, f, ld, H, W, lam, c0, piece, last, opt->gap_tol, opt->gap_history, pc,
+                                     pr, s2);
             };
             hipGraphExec_t ge = nullptr;
             if (opt->use_graph && last && piece == every && part == 0) ge = graphs.get(cur, issue);
             if (ge) {
                 if (hipGraphLaunch(ge, st) != hipSuccess) return TV_ERR_HIP;
-            } else if (tv2d_iters<T>(ws, f, ld, H, W, lam, cur, piece, last, opt->gap_history, pc, pr, st) !=
-                       hipSuccess) {
+            } else if (issue(st) != hipSuccess) {
                 return TV_ERR_HIP;
             }
-            // the host schedule buffer is reused by the next piece: wait for the upload
-            if (!last && hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
-            h.cur = (h.cur + piece) & 1;
-            h.iters += piece;
+            cur = (cur + piece) & 1;
             part += piece;
         }
         done += chunk;
-        if (hipMemcpyAsync(g3, ws.hdr->gap, sizeof(g3), hipMemcpyDeviceToHost, st) != hipSuccess) return TV_ERR_HIP;
-        if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
-        have_gap = true;
-        if (!isfinite(g3[2])) {
-            status = TV_ERR_NONFINITE;
-            break;
-        }
-        if (opt->gap_tol > 0.0 && g3[2] <= opt->gap_tol) break;
     }
-    if (status == TV_OK && opt->gap_tol > 0.0 && !(have_gap && g3[2] <= opt->gap_tol)) status = TV_ERR_NOT_CONVERGED;
-    h.gap[0] = g3[0];
-    h.gap[1] = g3[1];
-    h.gap[2] = g3[2];
-    if (hipMemcpyAsync(ws.hdr, &h, sizeof(h), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
-    const unsigned nb = (unsigned)((H * W + 255) / 256);
-    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, ws.x[h.cur], W, x, ld, H, W);
-    if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
-    if (stats) {
-        stats->iters = (int)h.iters;
-        stats->status = status;
-        stats->primal = g3[0];
-        stats->dual = g3[1];
-        stats->gap_norm = g3[2];
-    }
-    return (tv_status)status;
+    hipLaunchKernelGGL((k_tv2d_finish<T>), dim3(nb), dim3(256), 0, st, ws.hdr, ws.x[0], ws.x[1], x, ld, H, W, stats,
+                       opt->gap_tol, wall_clock_khz());
+    if (hipGetLastError() != hipSuccess) return TV_ERR_HIP;
+    // captured graphs live for this call only: wait for their replays
+    if (graphs.exec[0] || graphs.exec[1]) return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
+    return TV_OK;
 }
 
 // Autotune of the column and the row launch on the first iteration's data.
@@ -557,22 +579,16 @@ static tv_status tv2d_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld, d
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
     hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
+    hipLaunchKernelGGL(k_tv2d_init_hdr, dim3(1), dim3(64), 0, st, ws.hdr);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, tau0, 1);
     // Run a few iterations first: the deques of the column and row chains
     // deepen as the dual variable builds up, and a plan timed on the first
     // iteration's data alone would pick a ring that overflows later on.
-    IterSched sc[kTuneWarm + 1];
-    double tau = tau0;
-    for (int j = 0; j <= kTuneWarm; ++j) {
-        sc[j] = make_sched(tau, j);
-        tau *= sc[j].theta;
-    }
-    if (hipMemcpyAsync(ws.sched, sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
-    if (tv2d_iters<T>(ws, f, ld, H, W, lam, 0, kTuneWarm, false, nullptr, seg_plan(W, H, kPlan2dCol),
+    if (tv2d_iters<T>(ws, f, ld, H, W, lam, 0, kTuneWarm, false, 0.0, nullptr, seg_plan(W, H, kPlan2dCol),
                       seg_plan(H, W, kPlan2dRow), st) != hipSuccess)
         return TV_ERR_HIP;
     // the timed steps read iteration kTuneWarm's scalars from the first slot
-    if (hipMemcpyAsync(ws.sched, &sc[kTuneWarm], sizeof(IterSched), hipMemcpyHostToDevice, st) != hipSuccess)
-        return TV_ERR_HIP;
+    hipLaunchKernelGGL(k_ctl_sched, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, ws.sched, 1);
     SegPlan pc, pr;
     tv_status s = tune_launch<T>(
         W, H, ws.seg_bytes, [&](const SegPlan &p) { return tv2d_col_step<T>(ws, H, W, lam, 0, ws.sched, p, st); },
@@ -655,7 +671,7 @@ __global__ __launch_bounds__(kGapBlock) void k_l1_energy_rows(const T *__restric
     if (lane == 0) part[r] = acc;
 }
 
-__global__ __launch_bounds__(kGapBlock) void k_l1_energy_final(const double *__restrict__ part, int64_t H,
+static __global__ __launch_bounds__(kGapBlock) void k_l1_energy_final(const double *__restrict__ part, int64_t H,
                                                                double *__restrict__ out, double *__restrict__ hist,
                                                                int64_t hist_at) {
     __shared__ double s[kGapBlock];
@@ -684,7 +700,7 @@ static hipError_t tv2d_l1_energy(const Tv2dWs<T> &ws, const T *x, const T *f, in
 }
 
 // Constant-step schedule: tau, sigma = 1/tau, theta = 1.
-static IterSched l1_sched(double tau, int64_t k) {
+static __host__ __device__ IterSched l1_sched(double tau, int64_t k) {
     IterSched s;
     s.tau = tau;
     s.sigma = 1.0 / tau;
@@ -695,6 +711,10 @@ static IterSched l1_sched(double tau, int64_t k) {
     return s;
 }
 
+static __global__ void k_l1_sched_set(IterSched *sc, double tau) {
+    if (threadIdx.x == 0) sc[0] = l1_sched(tau, 0);
+}
+
 template <typename T>
 static tv_status tv2d_l1_init(const T *f, int64_t H, int64_t W, int64_t ld, double tau, const Tv2dWs<T> &ws,
                               hipStream_t st) {
@@ -702,9 +722,31 @@ static tv_status tv2d_l1_init(const T *f, int64_t H, int64_t W, int64_t ld, doub
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
     hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
-    const IterSched sc = l1_sched(tau, 0);  // the same scalars every iteration
-    if (hipMemcpyAsync(ws.sched, &sc, sizeof(sc), hipMemcpyHostToDevice, st) != hipSuccess) return TV_ERR_HIP;
+    // the same scalars every iteration
+    hipLaunchKernelGGL(k_l1_sched_set, dim3(1), dim3(64), 0, st, ws.sched, tau);
+    // the device clock starts here (no schedule: the count is 0)
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, tau, 1);
+    hipLaunchKernelGGL(k_ctl_sched, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, ws.sched, 0);
     return hipGetLastError() == hipSuccess ? TV_OK : TV_ERR_HIP;
+}
+
+// Copy of the iterate into the caller's x and the stats of a TV-l1 solve (its
+// energy in gap[0]; no duality gap).
+template <typename T>
+__global__ __launch_bounds__(256) void k_tv2d_l1_finish(const Tv2dHeader *__restrict__ h, const T *__restrict__ xc,
+                                                        T *__restrict__ out, int64_t ld, int64_t H, int64_t W,
+                                                        tv2d_stats *__restrict__ stats, int iters, double clk_khz) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < H * W) out[(i / W) * ld + i % W] = xc[i];
+    if (i == 0 && stats) {
+        const double P = h->gap[0];
+        stats->iters = iters;
+        stats->status = isfinite(P) ? TV_OK : TV_ERR_NONFINITE;
+        stats->primal = P;
+        stats->dual = __builtin_nan("");
+        stats->gap_norm = __builtin_nan("");
+        stats->device_ms = ctl_ms(&h->ctl, clk_khz);
+    }
 }
 
 template <typename T>
@@ -728,23 +770,12 @@ static tv_status tv2d_l1_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, d
                 return TV_ERR_HIP;
         }
     }
-    double P = NAN;
     if (opt->max_iter == 0 && tv2d_l1_energy<T>(ws, ws.x[0], f, ld, H, W, lam, nullptr, -1, st) != hipSuccess)
         return TV_ERR_HIP;
-    if (hipMemcpyAsync(&P, &ws.hdr->gap[0], sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
-        return TV_ERR_HIP;
     const unsigned nb = (unsigned)((H * W + 255) / 256);
-    hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, ws.x[cur], W, x, ld, H, W);
-    if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
-    const int status = isfinite(P) ? TV_OK : TV_ERR_NONFINITE;
-    if (stats) {
-        stats->iters = opt->max_iter;
-        stats->status = status;
-        stats->primal = P;
-        stats->dual = NAN;
-        stats->gap_norm = NAN;
-    }
-    return (tv_status)status;
+    hipLaunchKernelGGL((k_tv2d_l1_finish<T>), dim3(nb), dim3(256), 0, st, ws.hdr, ws.x[cur], x, ld, H, W, stats,
+                       opt->max_iter, wall_clock_khz());
+    return hipGetLastError() == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
 
 template <typename T>
@@ -776,8 +807,71 @@ static tv_status tv2d_l1_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld
     return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
 
+// Entry points per solver and precision.  The build compiles this file in
+// parts (1: ROF FP32, 2: ROF FP64, 3: TV-l1 FP32, 4: TV-l1 FP64 and the C
+// ABI); each part defines its group and the ABI calls them through these
+// declarations.
+tv_status rof_solve_f32(const float *, int64_t, int64_t, int64_t, double, float *, const tv2d_options *,
+                        tv2d_stats *, void *, hipStream_t);
+tv_status rof_solve_f64(const double *, int64_t, int64_t, int64_t, double, double *, const tv2d_options *,
+                        tv2d_stats *, void *, hipStream_t);
+tv_status rof_autotune_f32(const float *, int64_t, int64_t, int64_t, double, double, void *, hipStream_t,
+                           tv_tuning_result *, tv_tuning_result *);
+tv_status rof_autotune_f64(const double *, int64_t, int64_t, int64_t, double, double, void *, hipStream_t,
+                           tv_tuning_result *, tv_tuning_result *);
+tv_status l1_solve_f32(const float *, int64_t, int64_t, int64_t, double, float *, const tv2d_options *,
+                       tv2d_stats *, void *, hipStream_t);
+tv_status l1_solve_f64(const double *, int64_t, int64_t, int64_t, double, double *, const tv2d_options *,
+                       tv2d_stats *, void *, hipStream_t);
+tv_status l1_autotune_f32(const float *, int64_t, int64_t, int64_t, double, double, void *, hipStream_t,
+                          tv_tuning_result *, tv_tuning_result *);
+tv_status l1_autotune_f64(const double *, int64_t, int64_t, int64_t, double, double, void *, hipStream_t,
+                          tv_tuning_result *, tv_tuning_result *);
+
+#if TVC_IN_PART(1)
+tv_status rof_solve_f32(const float *f, int64_t H, int64_t W, int64_t ld, double lam, float *x,
+                        const tv2d_options *o, tv2d_stats *st, void *ws, hipStream_t s) {
+    return tv2d_solve_t<float>(f, H, W, ld, lam, x, o, st, ws, s);
+}
+tv_status rof_autotune_f32(const float *f, int64_t H, int64_t W, int64_t ld, double lam, double tau0, void *ws,
+                           hipStream_t s, tv_tuning_result *col, tv_tuning_result *row) {
+    return tv2d_autotune_t<float>(f, H, W, ld, lam, tau0, ws, s, col, row);
+}
+#endif
+#if TVC_IN_PART(2)
+tv_status rof_solve_f64(const double *f, int64_t H, int64_t W, int64_t ld, double lam, double *x,
+                        const tv2d_options *o, tv2d_stats *st, void *ws, hipStream_t s) {
+    return tv2d_solve_t<double>(f, H, W, ld, lam, x, o, st, ws, s);
+}
+tv_status rof_autotune_f64(const double *f, int64_t H, int64_t W, int64_t ld, double lam, double tau0, void *ws,
+                           hipStream_t s, tv_tuning_result *col, tv_tuning_result *row) {
+    return tv2d_autotune_t<double>(f, H, W, ld, lam, tau0, ws, s, col, row);
+}
+#endif
+#if TVC_IN_PART(3)
+tv_status l1_solve_f32(const float *f, int64_t H, int64_t W, int64_t ld, double lam, float *x,
+                       const tv2d_options *o, tv2d_stats *st, void *ws, hipStream_t s) {
+    return tv2d_l1_solve_t<float>(f, H, W, ld, lam, x, o, st, ws, s);
+}
+tv_status l1_autotune_f32(const float *f, int64_t H, int64_t W, int64_t ld, double lam, double tau0, void *ws,
+                          hipStream_t s, tv_tuning_result *col, tv_tuning_result *row) {
+    return tv2d_l1_autotune_t<float>(f, H, W, ld, lam, tau0, ws, s, col, row);
+}
+#endif
+#if TVC_IN_PART(4)
+tv_status l1_solve_f64(const double *f, int64_t H, int64_t W, int64_t ld, double lam, double *x,
+                       const tv2d_options *o, tv2d_stats *st, void *ws, hipStream_t s) {
+    return tv2d_l1_solve_t<double>(f, H, W, ld, lam, x, o, st, ws, s);
+}
+tv_status l1_autotune_f64(const double *f, int64_t H, int64_t W, int64_t ld, double lam, double tau0, void *ws,
+                          hipStream_t s, tv_tuning_result *col, tv_tuning_result *row) {
+    return tv2d_l1_autotune_t<double>(f, H, W, ld, lam, tau0, ws, s, col, row);
+}
+#endif
+
 }  // namespace tvc
 
+#if TVC_IN_PART(4)
 using namespace tvc;
 
 extern "C" {
@@ -800,8 +894,8 @@ tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
     if (dtype == TV_F32)
-        return tv2d_solve_t<float>((const float *)f, H, W, ld, lambda, (float *)x, options, stats, workspace, stream);
-    return tv2d_solve_t<double>((const double *)f, H, W, ld, lambda, (double *)x, options, stats, workspace, stream);
+        return rof_solve_f32((const float *)f, H, W, ld, lambda, (float *)x, options, stats, workspace, stream);
+    return rof_solve_f64((const double *)f, H, W, ld, lambda, (double *)x, options, stats, workspace, stream);
 }
 
 size_t tv2d_l1_workspace(int64_t H, int64_t W, tv_dtype dtype) {
@@ -831,10 +925,8 @@ tv_status tv2d_l1_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int
     const tv_status s = l1_args(dtype, f, H, W, ld, lambda, options->tau0, workspace, workspace_bytes);
     if (s != TV_OK) return s;
     if (dtype == TV_F32)
-        return tv2d_l1_solve_t<float>((const float *)f, H, W, ld, lambda, (float *)x, options, stats, workspace,
-                                      stream);
-    return tv2d_l1_solve_t<double>((const double *)f, H, W, ld, lambda, (double *)x, options, stats, workspace,
-                                   stream);
+        return l1_solve_f32((const float *)f, H, W, ld, lambda, (float *)x, options, stats, workspace, stream);
+    return l1_solve_f64((const double *)f, H, W, ld, lambda, (double *)x, options, stats, workspace, stream);
 }
 
 tv_status tv2d_l1_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda,
@@ -843,8 +935,8 @@ tv_status tv2d_l1_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, 
     const tv_status s = l1_args(dtype, f, H, W, ld, lambda, tau0, workspace, workspace_bytes);
     if (s != TV_OK) return s;
     if (dtype == TV_F32)
-        return tv2d_l1_autotune_t<float>((const float *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
-    return tv2d_l1_autotune_t<double>((const double *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
+        return l1_autotune_f32((const float *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
+    return l1_autotune_f64((const double *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
 }
 
 tv_status tv2d_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, double tau0,
@@ -859,8 +951,9 @@ tv_status tv2d_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return TV_ERR_NO_DEVICE;
     if (dtype == TV_F32)
-        return tv2d_autotune_t<float>((const float *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
-    return tv2d_autotune_t<double>((const double *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
+        return rof_autotune_f32((const float *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
+    return rof_autotune_f64((const double *)f, H, W, ld, lambda, tau0, workspace, stream, col, row);
 }
 
 }  // extern "C"
+#endif

@@ -83,9 +83,11 @@ def test_batched_autotune_is_bitwise_identical():
 
 def test_full_size_batch_of_256_against_oracle():
     """The bench's batch (256 images, sides U{64..2048}, per-image lambda and
-    noise) solved to gap 1e-4 per image in FP32 with autotuned launches; the
-    smallest, the largest and a middle image are checked against the FP64
-    oracle run for the same number of iterations (1e-4 x range)."""
+    noise) solved to gap 1e-4 per image in FP32 with autotuned launches; every
+    image is checked against the FP64 oracle run for the same number of
+    iterations: x to 1e-4 x range, and the gap to 2e-6 + 10% of the oracle's
+    (the FP32 gap is formed from dual variables rounded toward zero to stay
+    feasible, which puts a floor of about 1e-6 per pixel under it)."""
     specs = synth.uneven_batch_specs(256, seed=11)
     imgs = [synth.shapes_image(s["H"], s["W"], sigma=s["sigma"], seed=s["seed"]) for s in specs]
     packed = torch.tensor(np.concatenate([im.ravel() for im in imgs]), dtype=torch.float32, device="cuda")
@@ -97,13 +99,15 @@ def test_full_size_batch_of_256_against_oracle():
     finally:
         binding.autotune_clear()
     assert all(i["status"] == binding.TV_OK and i["gap_norm"] <= 1e-4 for i in infos)
-    sizes = [h * w for h, w in shapes]
-    order = np.argsort(sizes)
-    for j in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+    worst = 0.0
+    for j in range(len(imgs)):
         fv = np.float32(imgs[j]).astype(np.float64)
         xo, _, (_, _, go), k = oracle.tv2d(fv, lams[j], max_iter=infos[j]["iters"])
-        assert np.abs(xs[j].double().cpu().numpy() - xo).max() <= 1e-4 * np.ptp(fv), j
-        assert abs(infos[j]["gap_norm"] - go) <= 1e-6
+        err = np.abs(xs[j].double().cpu().numpy() - xo).max() / np.ptp(fv)
+        worst = max(worst, err)
+        assert err <= 1e-4, (j, err)
+        assert abs(infos[j]["gap_norm"] - go) <= 2e-6 + 0.1 * go, (j, infos[j]["gap_norm"], go)
+    print("worst max error / range over the 256 images: %.3g" % worst)
 
 
 def test_batched_graph_replays_match_direct_launches():
