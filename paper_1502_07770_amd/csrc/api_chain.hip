@@ -402,13 +402,12 @@ tv_status tv_chain_prox_l1_autotune(const tv_chain_layout *layout, tv_dtype dtyp
     const int64_t C = layout->num_chains, n = layout->length;
     const ChainBatch b = to_batch(layout);
     SegPlan cand[64];
-    const int m = dtype == TV_F32 ? seg_candidates<float, TagJ<float>>(C, n, cand, 64)
-                                  : seg_candidates<double, TagJ<double>>(C, n, cand, 64);
+    // the TV-l1 set is FP64 for either data precision
+    const int m = seg_candidates<double, TagJ<double>>(C, n, cand, 64);
     int best = -1, tried = 0;
     float best_ms = 0.0f;
     for (int j = 0; j < m; ++j) {
-        const size_t need = dtype == TV_F32 ? seg_ws_bytes_plan<float, TagJ<float>>(C, n, cand[j])
-                                            : seg_ws_bytes_plan<double, TagJ<double>>(C, n, cand[j]);
+        const size_t need = seg_ws_bytes_plan<double, TagJ<double>>(C, n, cand[j]);
         if (need > workspace_bytes) continue;
         seg_set_tuned(kPlanL1, C, n, cand[j]);
         auto run = [&]() {
@@ -429,7 +428,7 @@ tv_status tv_chain_prox_l1_autotune(const tv_chain_layout *layout, tv_dtype dtyp
     }
     if (best < 0) return TV_ERR_WORKSPACE;
     seg_set_tuned(kPlanL1, C, n, cand[best]);
-    // x from the chosen plan (plans agree only to rounding for TV-l1)
+    // x from the chosen plan (every plan gives the same bits)
     st = tv_chain_prox_l1(layout, dtype, y, d, w, w_scalar, c, c_scalar, x, workspace, workspace_bytes, stream);
     if (st != TV_OK) return st;
     if (hipStreamSynchronize(stream) != hipSuccess) return TV_ERR_HIP;

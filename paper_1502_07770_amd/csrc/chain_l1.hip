@@ -7,9 +7,10 @@
 // the quadratic weight normalised to 1).  The message step is l1_step
 // (l1_core.h) on the LDS ring, whose entries hold (lambda, slope tag, jump);
 // segments, halos, repair, fix-up, overflow fallbacks and the backward pass are
-// the ones of the chain prox.  Segment boundaries accept TV-l1 sets that agree
-// to rounding (see ent_same), so the output agrees with a sequential run to
-// about 3e-5 of the data scale in FP32 (1e-12 in FP64) for every plan.
+// the ones of the chain prox, and segment boundaries compare sets bit for bit,
+// so the output is the sequential run's for every plan.  The set is FP64 for
+// FP32 data too (WideL1: its jumps carry running sums).  The data, d, c and w
+// are read in the caller's precision and x written in it.
 #include "kernels.h"
 #include "seg_kernels.h"
 
@@ -112,7 +113,7 @@ struct L1Prob {
 
 template <typename T>
 size_t chain_l1_ws_bytes(int64_t C, int64_t n) {
-    return seg_bytes_max<T, TagJ<T>>(C, n, kPlanL1);
+    return seg_bytes_max<double, TagJ<double>>(C, n, kPlanL1);
 }
 
 template <typename T>
@@ -120,8 +121,9 @@ hipError_t launch_chain_l1(const ChainBatch &bt, const T *y, const T *d, const T
                            T c_scalar, T *x, void *workspace, hipStream_t stream) {
     if (bt.num_chains <= 0) return hipSuccess;
     const SegPlan plan = seg_plan(bt.num_chains, bt.n, kPlanL1);
-    typename L1Prob<T>::Params pp{y, d, w, c, w_scalar, c_scalar, x, bt.es, bt.cs, bt.offsets};
-    return seg_run<T, L1Prob<T>, kTile>(workspace, bt.num_chains, bt.n, plan, pp, stream);
+    using R = typename L1Run<L1Prob, T>::Prob;
+    typename R::Params pp{y, d, w, c, w_scalar, c_scalar, x, bt.es, bt.cs, bt.offsets};
+    return seg_run<double, R, kTile>(workspace, bt.num_chains, bt.n, plan, pp, stream);
 }
 
 // Build parts: 1 FP32, 2 FP64.

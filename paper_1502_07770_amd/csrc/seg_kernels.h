@@ -61,8 +61,9 @@ struct alignas(2 * sizeof(T)) LamPair {
 // the working precision (exact below 2^24 for float) so the slope s - k is one
 // exact subtraction; with general a_i it is the FP64 prefix sum Abar_k; for
 // TV-l1 sets it is the birth step and the jump of h at lambda (TagJ).  Every
-// step leaves the back entry's tag at 0, so saved states compare entry by
-// entry, tags included.
+// step leaves the back entry's tag at a value fixed by the node (the step's
+// own index in the Sec. 4.1 deque, 0 in a TV-l1 set), so saved states compare
+// entry by entry, tags included.
 constexpr size_t ent_align(size_t b) { return b <= 8 ? 8 : (b <= 16 ? 16 : 32); }
 template <typename T, typename G = T>
 struct alignas(ent_align(sizeof(T) + sizeof(G))) Ent {
@@ -147,35 +148,28 @@ __device__ __forceinline__ uint32_t bits32(double v) {
     return (uint32_t)b ^ (uint32_t)(b >> 32) * 0x9E3779B1u;
 }
 
-// State comparison of two deque entries, and the entry's share of the state
-// hash.  Exact for the Sec. 4.1 deques.  TV-l1 sets keep jump remainders that
-// are re-derived from the previous jump at every crossing, so their rounding
-// errors add up along the chain (a random walk, about 1e-5 of the data scale
-// after a few hundred FP32 steps) and two runs that reach the same set in exact
-// arithmetic stay apart by that much: there the slope tags must be equal and
-// positions and jumps agree to 3e-5 (FP32) or 1e-12 (FP64) of max(1, |value|);
-// the hash covers the tags only.  A segmented TV-l1 solve then agrees with a
-// sequential one to that level, not bit for bit.
-template <typename T> __device__ __forceinline__ T near_tol();
-template <> __device__ __forceinline__ float near_tol<float>() { return 3e-5f; }
-template <> __device__ __forceinline__ double near_tol<double>() { return 1e-12; }
-template <typename T> __device__ __forceinline__ bool near(T a, T b) {
-    const T m = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
-    return fabs(a - b) <= near_tol<T>() * (m > (T)1 ? m : (T)1);
+// State comparison of two deque entries (bit for bit: two runs whose states
+// hold the same bits compute the same values from then on; == would also take
+// -0 for +0), and the entry's share of the state hash.
+__device__ __forceinline__ bool same_bits(float a, float b) { return __float_as_uint(a) == __float_as_uint(b); }
+__device__ __forceinline__ bool same_bits(double a, double b) {
+    return __double_as_longlong(a) == __double_as_longlong(b);
 }
 template <typename T, typename G> __device__ __forceinline__ bool ent_same(T la, const G &ka, T lb, const G &kb) {
-    return la == lb && ka == kb;
+    return same_bits(la, lb) && same_bits(ka, kb);
 }
 template <typename T>
 __device__ __forceinline__ bool ent_same(T la, const TagJ<T> &ka, T lb, const TagJ<T> &kb) {
-    return ka.k == kb.k && near(la, lb) && near(ka.j, kb.j);
+    return same_bits(la, lb) && same_bits(ka.k, kb.k) && same_bits(ka.j, kb.j);
 }
 template <typename T, typename G> __device__ __forceinline__ uint32_t ent_hash(uint32_t h, T l, const G &k, bool tag) {
     h = (h ^ bits32(l)) * 0x01000193u;
     return tag ? (h ^ bits32(k)) * 0x01000193u : h;
 }
 template <typename T>
-__device__ __forceinline__ uint32_t ent_hash(uint32_t h, T, const TagJ<T> &k, bool tag) {
+__device__ __forceinline__ uint32_t ent_hash(uint32_t h, T l, const TagJ<T> &k, bool tag) {
+    h = (h ^ bits32(l)) * 0x01000193u;
+    h = (h ^ bits32(k.j)) * 0x01000193u;
     return tag ? (h ^ bits32(k.k)) * 0x01000193u : h;
 }
 
@@ -360,21 +354,55 @@ __device__ __forceinline__ int dq_update(A &R, const DqScan<T> &sc, G sf, T lm, 
     return sc.r - sc.p + 2;
 }
 
-// Sequential form of the scan (any depth): the same values in the same order,
-// stopping past the w^+ crossing (at the latest at the sentinel, entry t).
-template <typename T, typename G, class A>
-__device__ __forceinline__ DqScan<T> dq_scan_seq(const A &R, int t, G sf, T v0, T lo, T hi) {
+// Deques of at least this many breakpoints take the two-ended scan.
+constexpr int kTwoEnded = 16;
+
+// The scan of a deque of t breakpoints.  Below kTwoEnded breakpoints it is a
+// front walk with the window's values in the window's order, stopping past
+// the w^+ crossing (at the latest at the sentinel, entry t); it reads r + 1
+// breakpoints, which on shallow deques is no more than a walk from the back.
+// From kTwoEnded on it is two-ended: the front walk stops at the w^- crossing,
+// and the w^+ crossing is found walking from the back, with values from the
+// right end piece (h(z) = w^+_prev + a_s z - b_s beyond the back breakpoint),
+// so a step reads the breakpoints it pops and one more at each end: the O(1)
+// amortised step of Sec. 4.1 however deep the deque.  Values near the back
+// differ in rounding from a front walk's; since the form follows the deque's
+// own depth, in the ring and in the HBM deque alike, a state always takes the
+// same arithmetic and segmented runs stay bit-identical.  Rounding cannot make
+// the w^+ count fall below the w^- count: it is raised to it.
+// kDeep false: the store never holds kTwoEnded breakpoints (a 16-slot ring).
+template <typename T, typename G, bool kGen, bool kDeep, class A>
+__device__ __forceinline__ DqScan<T> dq_scan(const A &R, int t, const StepIn<T, G> &in,
+                                             const EndSlope<T, G, kGen> &es) {
+    const bool deep = kDeep && t >= kTwoEnded;
     Ent<T, G> prev = R.ld(0);
-    T v = v0;
+    T v = es.mul(prev.l) + (in.lop - in.yi);
     DqScan<T> sc{0, 0, v, v};
     for (int j = 0; j <= t; ++j) {
         if (j > 0) {
             const Ent<T, G> e = R.ld(j);
-            v = fmav(slope_of<T, G>(sf, prev.k), e.l - prev.l, v);
+            v = fmav(slope_of<T, G>(in.sf, prev.k), e.l - prev.l, v);
             prev = e;
         }
-        if (!(v <= hi)) break;
-        dq_count(sc, j, v, lo, hi);
+        if (deep ? !(v < in.lo) : !(v <= in.hi)) break;
+        dq_count(sc, j, v, in.lo, in.hi);
+    }
+    if (deep) {
+        int j = t - 1;
+        Ent<T, G> b = R.ld(j);
+        T u = es.mul(b.l) + (in.hip - in.yi);  // h at breakpoint j
+        while (!(u <= in.hi) && j > 0) {
+            const Ent<T, G> pv = R.ld(j - 1);
+            u = fmav(slope_of<T, G>(in.sf, pv.k), pv.l - b.l, u);
+            b = pv;
+            --j;
+        }
+        sc.r = (u <= in.hi) ? j + 1 : 0;
+        sc.vR = u;
+        if (sc.r < sc.p) {
+            sc.r = sc.p;
+            sc.vR = sc.vL;
+        }
     }
     return sc;
 }
@@ -388,15 +416,15 @@ struct RingAcc {
     __device__ __forceinline__ void shift(int d) const { R.head = (R.head + d) & (K - 1); }
 };
 
-// The step in its general form: any depth (the sequential scan) and an empty
-// deque.  It serves a run's first node and the rare wave in which some deque
-// is deeper than the window.
+// The step in its general form: any depth (dq_scan) and an empty deque.  It
+// serves a run's first node and the rare wave in which some deque is deeper
+// than the window.
 template <typename T, typename G, int K, bool kGen>
 __device__ __forceinline__ bool dp_step_ring_general(CRing<T, K, G> &R, const StepIn<T, G> &in, T &lm, T &lp) {
     const EndSlope<T, G, kGen> es(in.sf, in.sprev);
     const int t = R.size;
     RingAcc<T, K, G> A{R};
-    const DqScan<T> sc = dq_scan_seq<T, G>(A, t, in.sf, es.mul(A.ld(0).l) + (in.lop - in.yi), in.lo, in.hi);
+    const DqScan<T> sc = dq_scan<T, G, kGen, (K > kTwoEnded)>(A, t, in, es);
     const int i0 = sc.p > 0 ? sc.p - 1 : 0, i1 = sc.r > 0 ? sc.r - 1 : 0;
     G tnew;
     dq_solve<T, G, kGen>(sc, in, es, t == 0, A.ld(i0), A.ld(i0 + 1), A.ld(i1), A.ld(i1 + 1), lm, lp, tnew);
@@ -408,7 +436,7 @@ __device__ __forceinline__ bool dp_step_ring_general(CRing<T, K, G> &R, const St
 // One step on the LDS ring.  Deques of fewer than kRingCopies breakpoints
 // (sentinel included, all in copied slots) are read in one window from the
 // head at fixed offsets and scanned branch-free; deeper ones take the
-// sequential scan.  The root step is the same step with a zero leaving edge
+// two-ended scan.  The root step is the same step with a zero leaving edge
 // (its deque update is never used).  Returns false if the ring cannot hold
 // the new deque and its sentinel.
 template <typename T, typename G, int K, bool kGen>
@@ -425,7 +453,8 @@ __device__ __forceinline__ bool dp_step_ring(CRing<T, K, G> &R, const StepIn<T, 
     // Almost always every lane of the wave holds 1 .. M - 1 breakpoints: one
     // window and no selects for an empty deque, decided once for the wave.
     // Otherwise (a run's first node, or a deque deeper than the window in
-    // some lane) every lane takes the sequential scan.
+    // some lane) every lane takes the general step, whose front walk for the
+    // shallow lanes gives the window's bits.
     if (__ballot((t == 0) | (t >= M))) return dp_step_ring_general<T, G, K, kGen>(R, in, lm, lp);
     {
         const E *fp = R.col + R.head * 64;
@@ -483,7 +512,7 @@ template <typename T, typename G, bool kGen>
 __device__ __forceinline__ void dp_step_hbm(HbmDeque<T, G> &D, const StepIn<T, G> &in, T &lm, T &lp) {
     const EndSlope<T, G, kGen> es(in.sf, in.sprev);
     const int t = D.size;
-    const DqScan<T> sc = dq_scan_seq<T, G>(D, t, in.sf, es.mul(D.ld(0).l) + (in.lop - in.yi), in.lo, in.hi);
+    const DqScan<T> sc = dq_scan<T, G, kGen, true>(D, t, in, es);
     const int i0 = sc.p > 0 ? sc.p - 1 : 0, i1 = sc.r > 0 ? sc.r - 1 : 0;
     G tnew;
     dq_solve<T, G, kGen>(sc, in, es, t == 0, D.ld(i0), D.ld(i0 + 1), D.ld(i1), D.ld(i1 + 1), lm, lp, tnew);
@@ -569,6 +598,64 @@ __device__ __forceinline__ StepIn<T, typename Prob::Tag> step_in(const typename 
 // TV-l1 problems (Prob::kL1): the set of the Sec. 4.2 message in the ring.
 template <class Prob, class = void> struct IsL1 : std::false_type {};
 template <class Prob> struct IsL1<Prob, std::void_t<decltype(Prob::kL1)>> : std::bool_constant<Prob::kL1> {};
+
+// A TV-l1 problem on FP32 data solved with its set in FP64.  A crossing at a
+// breakpoint's jump keeps the part of the jump beyond the clip level, so a
+// breakpoint that is crossed on many consecutive nodes carries a running sum
+// of data terms in its jump.  In FP32 that sum drifts by rounding (about 1e-5
+// of the data scale after a few hundred nodes), which moves the minimiser
+// across a kink of the l1 term wherever two candidates are close, and it
+// keeps a run started from an empty set apart from the true run bit for bit,
+// so the segments would rarely meet.  In FP64 both effects vanish at FP32
+// output precision.  Data are read and x written in FP32; lambda^-/lambda^+
+// and the backward clip are FP64.
+template <class P>
+struct WideL1 {
+    using Tag = TagJ<double>;
+    static constexpr bool kGen = false;
+    static constexpr bool kL1 = true;
+    using Params = typename P::Params;
+    using Pre = typename P::Pre;
+    using SinkPre = typename P::SinkPre;
+    struct Src {
+        typename P::Src in;
+        bool vec;
+        __device__ __forceinline__ Src(const typename P::Src &s) : in(s), vec(s.vec) {}
+        __device__ __forceinline__ Pre load(int64_t i) const { return in.load(i); }
+        __device__ __forceinline__ int64_t off(int64_t i) const { return in.off(i); }
+        __device__ __forceinline__ int64_t step() const { return in.step(); }
+        __device__ __forceinline__ Pre load_off(int64_t o) const { return in.load_off(o); }
+        __device__ __forceinline__ void load4(int64_t i, Pre *o) const { in.load4(i, o); }
+        __device__ __forceinline__ double data(const Pre &p) const { return (double)in.data(p); }
+        __device__ __forceinline__ double dval(const Pre &p) const { return (double)in.dval(p); }
+        __device__ __forceinline__ double cval(const Pre &p) const { return (double)in.cval(p); }
+        __device__ __forceinline__ double weight(const Pre &p) const { return (double)in.weight(p); }
+    };
+    struct Sink {
+        typename P::Sink in;
+        bool vec;
+        __device__ __forceinline__ Sink(const typename P::Sink &s) : in(s), vec(s.vec) {}
+        __device__ __forceinline__ SinkPre load(int64_t i) const { return in.load(i); }
+        __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const { in.load4(i, o); }
+        __device__ __forceinline__ void store(int64_t i, double u, const SinkPre &p) const { in.store(i, (float)u, p); }
+        __device__ __forceinline__ void store4(int64_t i, const double (&u)[4], const SinkPre (&p)[4]) const {
+            const float v[4] = {(float)u[0], (float)u[1], (float)u[2], (float)u[3]};
+            in.store4(i, v, p);
+        }
+    };
+    static __device__ __forceinline__ ChainSpan span(const Params &p, int64_t c, int64_t nmax) {
+        return P::span(p, c, nmax);
+    }
+    static __device__ __forceinline__ Src src(const Params &p, const ChainSpan &sp) { return Src(P::src(p, sp)); }
+    static __device__ __forceinline__ Sink sink(const Params &p, const ChainSpan &sp) { return Sink(P::sink(p, sp)); }
+};
+// The problem type and working precision a TV-l1 problem Pb<T> runs with.
+template <template <typename> class Pb, typename T> struct L1Run {
+    using Prob = Pb<double>;
+};
+template <template <typename> class Pb> struct L1Run<Pb, float> {
+    using Prob = WideL1<Pb<float>>;
+};
 
 // The ring as a sorted TV-l1 store (l1_core.h); a push into a full ring sets
 // ovf and is dropped.
@@ -1200,19 +1287,25 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
     R.init(s_ent, lane);
     const int64_t C = ws.C;
     bool end_true = true, ok = true;
-    for (int64_t s = 1; s < Sc && ok; ++s) {
-        const int64_t a = s * ws.L;
-        const int64_t b = (a + ws.L < n) ? a + ws.L : n;
-        if (end_true) {
+    // Each lane walks its own chain: a pass of the outer loop skips the
+    // segments whose results stand and redoes at most one, so the lanes of a
+    // wave redo their segments side by side whatever their positions, and the
+    // wave costs as many segment runs as its lane with the most redos.
+    int64_t s = 1;
+    while (ok) {
+        while (s < Sc && end_true) {
             // the pass that wrote segment s started from the true state
             if (mis[s] && !cln[s]) {
                 end_true = false;
-                if (b < n) load_state(ws, R, s, kSaveEnd2, c);
+                if ((s + 1) * ws.L < n) load_state(ws, R, s, kSaveEnd2, c);
             }
-            continue;
+            ++s;
         }
+        if (s >= Sc) break;
         // R holds the true deque entering segment s: redo it until it meets the
         // first pass and is past whatever the repair kernel rewrote.
+        const int64_t a = s * ws.L;
+        const int64_t b = (a + ws.L < n) ? a + ws.L : n;
         const int64_t redo_to = mis[s] ? (int64_t)ws.rep_stop[s * C + c] : a;
         auto cy = carry_before<T, Prob>(src, a);
         bool met = false;
@@ -1226,6 +1319,7 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
             met = equals_state(ws, R, s, kSaveEnd, c);
         bwd_sweep<T, Prob, kSweepTile>(ws, pp, sp, s, c, a, b, sweep_from_end<T>(a));
         end_true = met;
+        ++s;
     }
     return ok;
 }

@@ -420,7 +420,8 @@ static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out, bool
     const size_t N = (size_t)(H * W);
     // room for any plan the autotuner may choose for the row and column launches
     // (TV-l1 rows keep (lambda, tag, jump) sets)
-    const size_t sr = l1 ? seg_bytes_max<T, TagJ<T>>(H, W, kPlan2dRowL1) : seg_bytes_max<T>(H, W, kPlan2dRow);
+    const size_t sr = l1 ? seg_bytes_max<double, TagJ<double>>(H, W, kPlan2dRowL1)  // FP64 set (WideL1)
+                         : seg_bytes_max<T>(H, W, kPlan2dRow);
     const size_t scol = seg_bytes_max<T>(W, H, kPlan2dCol);
     const size_t nparts = (size_t)H;
     const size_t ncol = (size_t)(((H + kGapRows - 1) / kGapRows) * W);
@@ -646,8 +647,9 @@ template <typename T>
 static hipError_t tv2d_l1_row_step(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64_t H, int64_t W, double lam,
                                    int cur, const IterSched *sc, const SegPlan &pr, hipStream_t st) {
     const int nxt = cur ^ 1;
-    typename RowL1Prob<T>::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, sc, lam, W};
-    return seg_run<T, RowL1Prob<T>, kTile>(ws.seg, H, W, pr, pp, st);
+    using R = typename L1Run<RowL1Prob, T>::Prob;  // the set in FP64 (see WideL1)
+    typename R::Params pp{f, ldf, ws.x[cur], ws.y[nxt], ws.x[nxt], ws.xbar, sc, lam, W};
+    return seg_run<double, R, kTile>(ws.seg, H, W, pr, pp, st);
 }
 
 // TV-l1 energy lambda (TV_h + TV_v)(x) + |x - f|_1 in FP64: one wave per row
@@ -757,7 +759,7 @@ static tv_status tv2d_l1_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, d
     tv_status s = tv2d_l1_init<T>(f, H, W, ld, opt->tau0, ws, st);
     if (s != TV_OK) return s;
     const SegPlan pc = seg_plan(W, H, kPlan2dCol), pr = seg_plan(H, W, kPlan2dRowL1);
-    if (seg_ws_bytes_plan<T>(W, H, pc) > ws.seg_bytes || seg_ws_bytes_plan<T, TagJ<T>>(H, W, pr) > ws.seg_bytes)
+    if (seg_ws_bytes_plan<T>(W, H, pc) > ws.seg_bytes || seg_ws_bytes_plan<double, TagJ<double>>(H, W, pr) > ws.seg_bytes)
         return TV_ERR_WORKSPACE;
     const int every = opt->gap_every > 0 ? opt->gap_every : 1;
     int cur = 0;
@@ -797,7 +799,7 @@ static tv_status tv2d_l1_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld
         st, &pc, col);
     if (s != TV_OK) return s;
     if (tv2d_col_step<T>(ws, H, W, lam, 0, ws.sched, pc, st) != hipSuccess) return TV_ERR_HIP;
-    s = tune_launch<T, TagJ<T>>(
+    s = tune_launch<double, TagJ<double>>(
         H, W, ws.seg_bytes,
         [&](const SegPlan &p) { return tv2d_l1_row_step<T>(ws, f, ld, H, W, lam, 0, ws.sched, p, st); }, st, &pr,
         row);

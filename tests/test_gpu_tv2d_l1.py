@@ -1,9 +1,10 @@
 """GPU parity of the 2D TV-l1 solver (tv2d_l1_solve, Sec. 5.2) with the
 oracle's (pinned to the LP optimum in tests/test_oracle_tv2d_l1.py): the same
 iteration with the same constant steps, compared iterate and energy after k
-iterations.  The chain proxes inside are exact up to rounding (the TV-l1 row
-sets match across segments to rounding), and the iteration is non-expansive,
-so FP64 iterates agree to 1e-9 and FP32 ones to 2e-3 (of a [0, 1] image)."""
+iterations.  The row proxes keep their TV-l1 sets in FP64 for FP32 data too
+and are bitwise sequential for every plan, and the iteration is
+non-expansive, so FP64 iterates agree to 1e-9 and FP32 ones to 1e-4 (of a
+[0, 1] image), also at 2048 x 2048 after 30 iterations."""
 import ctypes
 
 import numpy as np
@@ -24,7 +25,7 @@ def _impulse(H, W, seed, frac=0.25):
     return f
 
 
-@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 2e-3)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-9), (torch.float32, 1e-4)])
 @pytest.mark.parametrize("shape", [(64, 80), (130, 47)])
 def test_iterates_and_energy_match_oracle(dtype, tol, shape):
     H, W = shape
@@ -37,7 +38,7 @@ def test_iterates_and_energy_match_oracle(dtype, tol, shape):
     xo, ho = oracle.tv2d_l1(fv, 0.55, tau=1.0, max_iter=k)
     assert np.abs(x.double().cpu().numpy() - xo).max() <= tol
     h = hist.cpu().numpy()
-    assert np.abs(h - ho).max() <= (1e-9 if dtype == torch.float64 else 1e-3) * ho.max()
+    assert np.abs(h - ho).max() <= (1e-9 if dtype == torch.float64 else 1e-6) * ho.max()
     assert info["primal"] == pytest.approx(oracle.tvl1_2d_objective(fv, 0.55, x.double().cpu().numpy()), rel=1e-12)
 
 
@@ -69,12 +70,31 @@ def test_autotune_and_other_steps():
 
 
 def test_full_size_fp32():
-    """2048 x 2048 impulse-noise image, 6 iterations, against the oracle."""
+    """2048 x 2048 impulse-noise image, 30 iterations, against the oracle."""
     f = _impulse(2048, 2048, seed=3)
     ft = torch.tensor(f, dtype=torch.float32, device="cuda")
-    x, _ = binding.tv2d_l1(ft, 0.55, max_iter=6, energy_every=6)
-    xo, _ = oracle.tv2d_l1(ft.double().cpu().numpy(), 0.55, tau=1.0, max_iter=6)
-    assert np.abs(x.double().cpu().numpy() - xo).max() <= 2e-3
+    x, info = binding.tv2d_l1(ft, 0.55, max_iter=30, energy_every=30)
+    xo, ho = oracle.tv2d_l1(ft.double().cpu().numpy(), 0.55, tau=1.0, max_iter=30)
+    assert np.abs(x.double().cpu().numpy() - xo).max() <= 1e-4
+    assert info["primal"] == pytest.approx(ho[-1], rel=1e-6)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_segmented_rows_match_sequential(dtype):
+    """The same solve with one segment per row and with the default plan:
+    bit for bit (segment boundaries compare the TV-l1 sets exactly)."""
+    f = _impulse(300, 1100, seed=5)
+    ft = torch.tensor(f, dtype=dtype, device="cuda")
+    saved = binding.get_tuning()
+    try:
+        binding.set_tuning(target_lanes=1, min_segment=1)
+        ref, _ = binding.tv2d_l1(ft, 0.55, max_iter=12, energy_every=12)
+        binding.set_tuning(**saved)
+        binding.set_tuning(target_lanes=1 << 30, min_segment=32, halo=16)
+        got, _ = binding.tv2d_l1(ft, 0.55, max_iter=12, energy_every=12)
+    finally:
+        binding.set_tuning(**saved)
+    assert torch.equal(got, ref)
 
 
 def test_rejects_bad_options():
