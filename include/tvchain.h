@@ -468,8 +468,9 @@ tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_
                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Autotuner of tv2d_solve's two chain launches (the column and the row step):
- * sets up the first iteration from f in the workspace, times every candidate
- * plan of each launch that fits the workspace and makes the fastest the plan
+ * runs 32 iterations from f in the workspace (the chains' deques deepen as the
+ * dual variable builds up), then times every candidate plan of each launch on
+ * the next iteration's data that fits the workspace and makes the fastest the plan
  * of every later tv2d_solve of an H x W image in this process.  Overwrites
  * the solver state held in the workspace (run a fresh solve after it, not a
  * resume).  Synchronous.  The solve's results do not depend on the plans. */
@@ -531,8 +532,7 @@ size_t tv2d_l1_workspace(int64_t H, int64_t W, tv_dtype dtype);
 tv_status tv2d_l1_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda, void *x,
                         const tv2d_options *options, tv2d_stats *stats, void *workspace, size_t workspace_bytes,
                         hipStream_t stream);
-/* Autotuner of the TV-l1 solver's column and row launches (after 8 warm-up
- * iterations), as tv2d_autotune. */
+/* Autotuner of the TV-l1 solver's column and row launches, as tv2d_autotune. */
 tv_status tv2d_l1_autotune(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_t ld, double lambda,
                            double tau0, void *workspace, size_t workspace_bytes, hipStream_t stream,
                            tv_tuning_result *col, tv_tuning_result *row);

@@ -30,8 +30,11 @@ struct IterSched {
 // Iterations whose schedule one upload holds (and the longest captured chunk).
 constexpr int kSchedCap = 64;
 // Iterations the autotuners run before timing candidate plans (even, so the
-// state is back in the buffers of parity 0).
-constexpr int kTuneWarm = 8;
+// state is back in the buffers of parity 0).  The chains' deques deepen as the
+// dual variable builds up: timed after 8 iterations, the plans of a 4096^2
+// ROF solve used 16-slot rings that later iterations outgrew (the overflowed
+// chains then run sequentially), 3x slower to a gap of 1e-6 than 32 slots.
+constexpr int kTuneWarm = 32;
 
 __host__ __device__ __forceinline__ IterSched make_sched(double tau, int64_t k) {
     IterSched s;
