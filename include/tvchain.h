@@ -42,10 +42,19 @@ typedef enum {
     TV_ERR_NO_DEVICE = 3,     /* no HIP device visible                                 */
     TV_ERR_HIP = 4,           /* a HIP runtime call failed (launch, copy, sync)        */
     TV_ERR_NOT_CONVERGED = 5, /* tv2d: max_iter reached before gap_tol; stats filled   */
-    TV_ERR_NONFINITE = 6      /* tv2d: the duality gap became NaN or infinite          */
+    TV_ERR_NONFINITE = 6,     /* tv2d: the duality gap became NaN or infinite          */
+    /* range markers, not codes: they make every int a valid value of the type, so
+     * an unknown code passed in from C or Python is reported, not undefined */
+    TV_STATUS_MIN_ = -2147483647 - 1,
+    TV_STATUS_MAX_ = 2147483647
 } tv_status;
 
-typedef enum { TV_F32 = 0, TV_F64 = 1 } tv_dtype;
+typedef enum {
+    TV_F32 = 0,
+    TV_F64 = 1,
+    TV_DTYPE_MIN_ = -2147483647 - 1, /* range markers, as for tv_status */
+    TV_DTYPE_MAX_ = 2147483647
+} tv_dtype;
 
 /* [host] A batch of chains inside one buffer.
  *  Uniform batch (offsets == NULL): chain c, node i is element

@@ -45,15 +45,28 @@ class _Counts(ctypes.Structure):
                 ("max_breakpoints", ctypes.c_int64)]
 
 
-def build(force: bool = True) -> str:
-    """Compile tv_oracle.c into liboracle.so (gcc, -O2, OpenMP, IEEE FP64)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
-               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
+# A sanitized build (AddressSanitizer + UndefinedBehaviorSanitizer), for
+# running the oracle's own tests under the sanitizers; ORACLE_LIBRARY makes
+# this module load it (or any other build) instead of liboracle.so.
+SAN_LIB_PATH = os.path.join(_HERE, "liboracle_san.so")
+if os.environ.get("ORACLE_LIBRARY"):
+    _LIB_PATH = os.environ["ORACLE_LIBRARY"]
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile tv_oracle.c into liboracle.so (gcc, -O2, OpenMP, IEEE FP64), or
+    with sanitize into liboracle_san.so (-O1, ASan + UBSan, aborting on the
+    first error; load it into a process that preloads libasan)."""
+    out = SAN_LIB_PATH if sanitize else _LIB_PATH
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp%d" % os.getpid()
+        opt = (["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                "-fno-omit-frame-pointer"] if sanitize else ["-O2"])
+        cmd = ["gcc"] + opt + ["-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+                               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, out)
+    return out
 
 
 def _load():

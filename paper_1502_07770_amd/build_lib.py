@@ -94,5 +94,74 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     return LIB
 
 
+# Host-only build with AddressSanitizer and UndefinedBehaviorSanitizer on the
+# host code, for checking the C ABI's host side on a CPU.  Its device code is a
+# one-kernel stub fatbinary, so none of the library's kernels can launch from it.
+SAN = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN, "libtvchain_san.so")
+SAN_HOST_FLAGS = ["-O1", "-g", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"),
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+# the link names only host objects (clang++, not hipcc)
+SAN_LINK = [os.environ.get("CLANGXX", "/opt/rocm/llvm/bin/clang++"), "-shared", "-shared-libsan",
+            "-fsanitize=address,undefined"]
+
+
+def build_host_sanitized() -> str:
+    """Build SAN_LIB (see above) and return its path."""
+    os.makedirs(SAN, exist_ok=True)
+    stub_src = os.path.join(SAN, "stub.hip")
+    stub_fb = os.path.join(SAN, "stub.hipfb")
+    with open(stub_src, "w") as fh:
+        fh.write("#include <hip/hip_runtime.h>\n__global__ void tvc_host_check_stub(int *p) { if (p) p[0] = 0; }\n")
+    r = subprocess.run([HIPCC, "--cuda-device-only", "--offload-arch=gfx950", "-O1", stub_src, "-o", stub_fb],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("stub fatbinary failed:\n%s" % r.stderr)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+    def host_obj(src):
+        obj = os.path.join(SAN, os.path.basename(src) + ".o")
+        cmd = [HIPCC, "--cuda-host-only", "-Xclang", "-fcuda-include-gpubinary", "-Xclang", stub_fb] + \
+            SAN_HOST_FLAGS + ["-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("host compile failed for %s:\n%s" % (src, r.stderr))
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(host_obj, srcs))
+    cmd = SAN_LINK + objs + ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", SAN_LIB]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n%s" % r.stderr)
+    return SAN_LIB
+
+
+def build_host_check(src: str) -> str:
+    """Compile a host-only sanitized program from a HIP source (kernels become
+    stubs over the stub fatbinary of build_host_sanitized) and return its path."""
+    if not os.path.exists(os.path.join(SAN, "stub.hipfb")):
+        build_host_sanitized()
+    obj = os.path.join(SAN, os.path.basename(src) + ".o")
+    exe = os.path.join(SAN, os.path.splitext(os.path.basename(src))[0])
+    cmd = [HIPCC, "--cuda-host-only", "-Xclang", "-fcuda-include-gpubinary", "-Xclang",
+           os.path.join(SAN, "stub.hipfb")] + SAN_HOST_FLAGS + ["-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("host compile failed for %s:\n%s" % (src, r.stderr))
+    rt = subprocess.run([SAN_LINK[0], "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                        text=True).stdout.strip()
+    cmd = SAN_LINK[:1] + SAN_LINK[2:] + ["-shared-libsan", obj, "-L/opt/rocm/lib", "-lamdhip64",
+                                         "-Wl,-rpath,/opt/rocm/lib", "-Wl,-rpath," + os.path.dirname(rt), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n%s" % r.stderr)
+    return exe
+
+
 if __name__ == "__main__":
-    build(verbose=True, incremental="--incremental" in sys.argv)
+    if "--host-sanitized" in sys.argv:
+        print("built", build_host_sanitized(), file=sys.stderr)
+    else:
+        build(verbose=True, incremental="--incremental" in sys.argv)

@@ -201,6 +201,7 @@ using namespace tvc;
 extern "C" {
 
 const char *tv_status_string(tv_status s) {
+    static_assert(sizeof(tv_status) == sizeof(int) && sizeof(tv_dtype) == sizeof(int), "int-sized enums");
     switch (s) {
     case TV_OK: return "ok";
     case TV_ERR_INVALID_ARG: return "invalid argument";
