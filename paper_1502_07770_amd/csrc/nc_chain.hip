@@ -38,7 +38,7 @@ constexpr int kNcFlagInvalid = 2;
 struct NcBuf {
     double *l, *s;
     int64_t t, cap;
-    __device__ __forceinline__ bool push(double lam, double right) {
+    __host__ __device__ __forceinline__ bool push(double lam, double right) {
         if (t >= cap) return false;
         l[t] = lam;
         s[t + 1] = right;
@@ -50,15 +50,15 @@ struct NcBuf {
 // Read access to a buffer as stored, or as its reversal phi^rev(z) = phi(-z).
 struct NcFwd {
     const NcBuf *b;
-    __device__ __forceinline__ int64_t t() const { return b->t; }
-    __device__ __forceinline__ double l(int64_t k) const { return b->l[k]; }
-    __device__ __forceinline__ double s(int64_t k) const { return b->s[k]; }
+    __host__ __device__ __forceinline__ int64_t t() const { return b->t; }
+    __host__ __device__ __forceinline__ double l(int64_t k) const { return b->l[k]; }
+    __host__ __device__ __forceinline__ double s(int64_t k) const { return b->s[k]; }
 };
 struct NcRev {
     const NcBuf *b;
-    __device__ __forceinline__ int64_t t() const { return b->t; }
-    __device__ __forceinline__ double l(int64_t k) const { return -b->l[b->t - 1 - k]; }
-    __device__ __forceinline__ double s(int64_t k) const { return -b->s[b->t - k]; }
+    __host__ __device__ __forceinline__ int64_t t() const { return b->t; }
+    __host__ __device__ __forceinline__ double l(int64_t k) const { return -b->l[b->t - 1 - k]; }
+    __host__ __device__ __forceinline__ double s(int64_t k) const { return -b->s[b->t - k]; }
 };
 
 // The interval list of one chain (tree): interval k is [p[3k], p[3k+1]] and
@@ -67,12 +67,12 @@ struct NcRev {
 struct NcMaps {
     double *p;
     int64_t n, cap;
-    __device__ __forceinline__ void put(int64_t k, double lo, double hi, double target) const {
+    __host__ __device__ __forceinline__ void put(int64_t k, double lo, double hi, double target) const {
         p[3 * k] = lo;
         p[3 * k + 1] = hi;
         p[3 * k + 2] = target;
     }
-    __device__ __forceinline__ bool add(double lo, double hi, double target) {
+    __host__ __device__ __forceinline__ bool add(double lo, double hi, double target) {
         if (n >= cap) return false;
         put(n, lo, hi, target);
         ++n;
@@ -81,7 +81,7 @@ struct NcMaps {
 };
 
 // Lemma 1: out = unary + msg (equal positions merged into one breakpoint).
-__device__ bool nc_sum(const double *ul, const double *us, int64_t tu, const NcBuf &m, NcBuf &out) {
+__host__ __device__ bool nc_sum(const double *ul, const double *us, int64_t tu, const NcBuf &m, NcBuf &out) {
     out.t = 0;
     out.s[0] = us[0] + m.s[0];
     int64_t i = 0, j = 0;
@@ -104,7 +104,7 @@ __device__ bool nc_sum(const double *ul, const double *us, int64_t tu, const NcB
 // Algorithm 1 on h (forward or reversed view): out = h (x) f^1.  Each interval
 // [lambda_p, lambda] found is reported through add(lo, hi) in h's coordinates.
 template <class View, class Add>
-__device__ bool nc_dt(const View &h, double w, NcBuf &out, Add add) {
+__host__ __device__ bool nc_dt(const View &h, double w, NcBuf &out, Add add) {
     const int64_t t = h.t();
     out.t = 0;
     out.s[0] = h.s(0);
@@ -156,7 +156,7 @@ __device__ bool nc_dt(const View &h, double w, NcBuf &out, Add add) {
 
 // min(h, min h + C) with Pi^3; h given through a view.
 template <class View>
-__device__ bool nc_trunc(const View &h, double C, NcBuf &out, NcMaps &mp) {
+__host__ __device__ bool nc_trunc(const View &h, double C, NcBuf &out, NcMaps &mp) {
     const int64_t t = h.t();
     out.t = 0;
     if (t == 0) {
@@ -250,7 +250,7 @@ __device__ bool nc_trunc(const View &h, double C, NcBuf &out, NcMaps &mp) {
 }
 
 // pi(y) over intervals [lo, hi) of a list: the first interval containing y.
-__device__ __forceinline__ double nc_apply(const NcMaps &mp, int64_t lo, int64_t hi, double y) {
+__host__ __device__ __forceinline__ double nc_apply(const NcMaps &mp, int64_t lo, int64_t hi, double y) {
     for (int64_t k = lo; k < hi; ++k)
         if (y >= mp.p[3 * k] && y <= mp.p[3 * k + 1]) return mp.p[3 * k + 2];
     return y;
@@ -266,35 +266,24 @@ struct NcArgs {
     int *flag;
 };
 
-// The three message buffers of a lane live in LDS when `lanes` lanes' worth
-// fit in one workgroup (kLds; the rest of the wave idles), else in HBM.
-template <typename T, bool kLds>
-__global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__ ulam, const T *__restrict__ uslope,
-                                                 const T *__restrict__ w, const T *__restrict__ C, T *__restrict__ x,
-                                                 int lanes) {
-    extern __shared__ double s_nc[];
-    if ((int)threadIdx.x >= lanes) return;
-    const int64_t c = (int64_t)blockIdx.x * lanes + threadIdx.x;
-    if (c >= A.num_chains) return;
+// One lane's chain c: the message passing and the backward pass with the
+// three message buffers M, H, B given (each of msg_cap breakpoints); returns
+// the flag bits to raise (0: x written).  Host-callable, so that its indexing
+// can be run against exactly-sized buffers on a CPU.
+template <typename T>
+__host__ __device__ int nc_chain_lane(const NcArgs &A, const T *__restrict__ ulam, const T *__restrict__ uslope,
+                                      const T *__restrict__ w, const T *__restrict__ C, T *__restrict__ x, int64_t c,
+                                      NcBuf M, NcBuf H, NcBuf B) {
     const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
-    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {  // a range outside the nodes
-        atomicOr(A.flag, kNcFlagInvalid);
-        return;
-    }
-    if (n1 == n0) return;
-    const int64_t bstride = 2 * A.msg_cap + 1;
-    double *base = kLds ? s_nc + (int64_t)threadIdx.x * 3 * bstride : A.bufs + c * 3 * bstride;
-    NcBuf M{base, base + A.msg_cap, 0, A.msg_cap};
-    NcBuf H{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap};
-    NcBuf B{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) return kNcFlagInvalid;  // a range outside the nodes
+    if (n1 == n0) return 0;
     double *mb = A.maps + c * 3 * A.map_cap;
     NcMaps mp{mb, 0, A.map_cap};
     M.t = 0;
     M.s[0] = 0.0;
     // unary slopes are read in FP64; a small staging copy of one unary
-    bool ok = true;
     int bad = 0;
-    for (int64_t i = n0; i < n1 && ok; ++i) {
+    for (int64_t i = n0; i < n1; ++i) {
         const int64_t u0 = A.uoff[i], tu = A.uoff[i + 1] - u0;
         if (tu < 1 || tu > A.msg_cap) {
             bad = tu < 1 ? kNcFlagInvalid : kNcFlagCapacity;
@@ -346,10 +335,7 @@ __global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__
             for (int64_t k = 0; k <= M.t; ++k) M.s[k] = r.s(k);
         }
     }
-    if (bad) {
-        atomicOr(A.flag, bad);
-        return;
-    }
+    if (bad) return bad;
     // the last node: the first breakpoint attaining the minimum of hat M (in H)
     double v = 0.0, vmin = 0.0, y = H.t > 0 ? H.l[0] : 0.0;
     for (int64_t k = 1; k < H.t; ++k) {
@@ -368,6 +354,25 @@ __global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__
         y = nc_apply(mp, eo[0], eo[1], y);
         x[i] = (T)y;
     }
+    return 0;
+}
+
+// The three message buffers of a lane live in LDS when `lanes` lanes' worth
+// fit in one workgroup (kLds; the rest of the wave idles), else in HBM.
+template <typename T, bool kLds>
+__global__ __launch_bounds__(64) void k_nc_chain(NcArgs A, const T *__restrict__ ulam, const T *__restrict__ uslope,
+                                                 const T *__restrict__ w, const T *__restrict__ C, T *__restrict__ x,
+                                                 int lanes) {
+    extern __shared__ double s_nc[];
+    if ((int)threadIdx.x >= lanes) return;
+    const int64_t c = (int64_t)blockIdx.x * lanes + threadIdx.x;
+    if (c >= A.num_chains) return;
+    const int64_t bstride = 2 * A.msg_cap + 1;
+    double *base = kLds ? s_nc + (int64_t)threadIdx.x * 3 * bstride : A.bufs + c * 3 * bstride;
+    const int bad = nc_chain_lane<T>(A, ulam, uslope, w, C, x, c, NcBuf{base, base + A.msg_cap, 0, A.msg_cap},
+                                     NcBuf{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap},
+                                     NcBuf{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap});
+    if (bad) atomicOr(A.flag, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -1328,7 +1333,7 @@ size_t nc_layout(int64_t num_chains, int64_t num_nodes, int64_t msg_cap, int64_t
 // sweep over the reversed view.
 // ---------------------------------------------------------------------------
 template <class View, class Add>
-__device__ bool nc_side(const View &h, double alpha, double C, NcBuf &out, Add add) {
+__host__ __device__ bool nc_side(const View &h, double alpha, double C, NcBuf &out, Add add) {
     const int64_t t = h.t();
     out.t = 0;
     out.s[0] = h.s(0);
@@ -1399,25 +1404,18 @@ struct NcgArgs {
 // workspace.  Per node: hat = unary + incoming message (Lemma 1), then every
 // piece of the edge to the next node in turn; backward, each node applies its
 // edge's mappings, the last piece's first.
+// One lane's chain c with its three message buffers given: X the incoming
+// message, Y the other, U the staged unary (each of msg_cap breakpoints);
+// returns the flag bits to raise (0: x written).  Host-callable, so that its
+// indexing can be run against exactly-sized buffers on a CPU.
 template <class T>
-__global__ __launch_bounds__(64) void k_nc_concave(NcgArgs A, const T *__restrict__ ulam,
-                                                   const T *__restrict__ uslope, const T *__restrict__ palpha,
-                                                   const T *__restrict__ pC, const int32_t *__restrict__ pside,
-                                                   T *__restrict__ x, int lanes) {
-    if ((int)threadIdx.x >= lanes) return;
-    const int64_t c = (int64_t)blockIdx.x * lanes + threadIdx.x;
-    if (c >= A.num_chains) return;
+__host__ __device__ int ncg_chain_lane(const NcgArgs &A, const T *__restrict__ ulam, const T *__restrict__ uslope,
+                                       const T *__restrict__ palpha, const T *__restrict__ pC,
+                                       const int32_t *__restrict__ pside, T *__restrict__ x, int64_t c, NcBuf X,
+                                       NcBuf Y, NcBuf U) {
     const int64_t n0 = A.coff[c], n1 = A.coff[c + 1];
-    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) {
-        atomicOr(A.flag, kNcFlagInvalid);
-        return;
-    }
-    if (n1 == n0) return;
-    const int64_t bstride = 2 * A.msg_cap + 1;
-    double *base = A.bufs + c * 3 * bstride;
-    NcBuf X{base, base + A.msg_cap, 0, A.msg_cap};  // the incoming message
-    NcBuf Y{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap};
-    NcBuf U{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap};
+    if (n0 < 0 || n1 > A.num_nodes || n1 < n0) return kNcFlagInvalid;
+    if (n1 == n0) return 0;
     double *mb = A.maps + c * 3 * A.map_cap;
     NcMaps mp{mb, 0, A.map_cap};
     X.s[0] = 0.0;
@@ -1490,10 +1488,7 @@ __global__ __launch_bounds__(64) void k_nc_concave(NcgArgs A, const T *__restric
             Y = sw;
         }
     }
-    if (bad) {
-        atomicOr(A.flag, bad);
-        return;
-    }
+    if (bad) return bad;
     // the last node: the first breakpoint attaining the minimum of its hat (Y)
     double v = 0.0, vmin = 0.0, y = Y.t > 0 ? Y.l[0] : 0.0;
     for (int64_t k = 1; k < Y.t; ++k) {
@@ -1508,6 +1503,24 @@ __global__ __launch_bounds__(64) void k_nc_concave(NcgArgs A, const T *__restric
         for (int64_t k = A.poff[i + 1] - 1; k >= A.poff[i]; --k) y = nc_apply(mp, A.pmap[2 * k], A.pmap[2 * k + 1], y);
         x[i] = (T)y;
     }
+    return 0;
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_nc_concave(NcgArgs A, const T *__restrict__ ulam,
+                                                   const T *__restrict__ uslope, const T *__restrict__ palpha,
+                                                   const T *__restrict__ pC, const int32_t *__restrict__ pside,
+                                                   T *__restrict__ x, int lanes) {
+    if ((int)threadIdx.x >= lanes) return;
+    const int64_t c = (int64_t)blockIdx.x * lanes + threadIdx.x;
+    if (c >= A.num_chains) return;
+    const int64_t bstride = 2 * A.msg_cap + 1;
+    double *base = A.bufs + c * 3 * bstride;
+    const int bad = ncg_chain_lane<T>(A, ulam, uslope, palpha, pC, pside, x, c,
+                                      NcBuf{base, base + A.msg_cap, 0, A.msg_cap},
+                                      NcBuf{base + bstride, base + bstride + A.msg_cap, 0, A.msg_cap},
+                                      NcBuf{base + 2 * bstride, base + 2 * bstride + A.msg_cap, 0, A.msg_cap});
+    if (bad) atomicOr(A.flag, bad);
 }
 
 // nc_side spread over a wave: with g = h - alpha x, the prefix minimum m of g
