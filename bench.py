@@ -145,7 +145,7 @@ def bench_chain(steps: int, warmup: int, autotune: bool = True):
     else:
         plan = {"segment_length": int(lib.tv_chain_prox_segment_length(ctypes.byref(
             binding.ChainLayout(2 * SIDE, SIDE, 1, SIDE, None)))), "halo": binding.get_tuning()["halo"],
-                "ring_slots": 16, "candidates": 0, "ms": None}
+                "ring_slots": binding.get_tuning()["ring_slots"], "candidates": 0, "ms": None}
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -752,6 +752,9 @@ def main():
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--plan", metavar="L,H,K",
+                    help="fixed plan for the headline launch (segment length, halo, ring slots) instead of the "
+                         "autotuner's: for profiling runs that must launch exactly the plan the default run picks")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="rocprofv3 --pmc output folders; writes the traffic record read by the roofline")
     args = ap.parse_args()
@@ -778,7 +781,11 @@ def main():
         return
 
     log("bench: chain prox 4096x4096 rows+cols, steps=%d warmup=%d" % (args.steps, args.warmup))
-    r = bench_chain(args.steps, args.warmup, autotune=not args.no_autotune)
+    if args.plan:
+        from paper_1502_07770_amd import binding
+        L, H, K = (int(v) for v in args.plan.split(","))
+        binding.set_tuning(target_lanes=1 << 30, min_segment=L, halo=H, ring_slots=K)
+    r = bench_chain(args.steps, args.warmup, autotune=not (args.no_autotune or args.plan))
     log("bench: %.3f ms/step, %.1f Gelem/s (one launch %.3f ms; separate row / column calls %.3f / %.3f ms)" % (
         r["ms_per_step"], r["gelem"], r["launch_ms"], r["separate_ms"][0], r["separate_ms"][1]))
     alg_bytes = 8.0 * r["nodes"]
