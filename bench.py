@@ -646,6 +646,27 @@ def bench_batched():
     return out
 
 
+def c4_iters(iters: int):
+    """The C4 batch for profiling runs: its two launches autotuned (setup), then
+    `iters` iterations with one gap evaluation."""
+    import numpy as np
+    import torch
+    from paper_1502_07770_amd import binding, synth
+    specs = synth.uneven_batch_specs(256, seed=11)
+    packed = np.concatenate([synth.shapes_image(s["H"], s["W"], sigma=s["sigma"], seed=s["seed"]).ravel()
+                             .astype(np.float32) for s in specs])
+    f = torch.from_numpy(packed).cuda()
+    shapes = [(s["H"], s["W"]) for s in specs]
+    lams = [s["lam"] for s in specs]
+    tuned = {}
+    binding.tv2d_batched(shapes, lams, max_iter=1, gap_every=1, packed=f, autotune=True, tuned=tuned)
+    torch.cuda.synchronize()
+    log("plans", tuned)
+    binding.tv2d_batched(shapes, lams, max_iter=iters, gap_every=iters, gap_tol=0.0, packed=f)
+    torch.cuda.synchronize()
+    log("c4: %d iterations done" % iters)
+
+
 def rocprof_summary(d):
     """Print per-kernel call counts and average durations from rocprofv3 output
     (kernel_stats CSV or the results database) and, if counter CSVs are present,
@@ -752,6 +773,8 @@ def main():
                     help="use the default plan (profiling runs: no candidate dispatches in the trace)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--c4-iters", type=int, metavar="N",
+                    help="run the C4 batch's autotune and N iterations only (for profiling runs)")
     ap.add_argument("--plan", metavar="L,H,K",
                     help="fixed plan for the headline launch (segment length, halo, ring slots) instead of the "
                          "autotuner's: for profiling runs that must launch exactly the plan the default run picks")
@@ -769,8 +792,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X and the chains of the "
-              "workload are independent (run with --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU: the workload's chains are independent and one MI355X holds "
+              "all of them (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
     from paper_1502_07770_amd import binding
     if not os.path.exists(binding.LIB_PATH):
@@ -781,6 +804,9 @@ def main():
         return
 
     log("bench: chain prox 4096x4096 rows+cols, steps=%d warmup=%d" % (args.steps, args.warmup))
+    if args.c4_iters:
+        c4_iters(args.c4_iters)
+        return
     if args.plan:
         from paper_1502_07770_amd import binding
         L, H, K = (int(v) for v in args.plan.split(","))

@@ -234,9 +234,10 @@ __global__ __launch_bounds__(64) void k_chain_adjoint(ChainBatch b, const T *__r
 // A run still open at the end of a chunk carries its sum, count and start
 // into the next chunk; when it closes, its nodes in earlier chunks and the
 // boundary edge before it are written then.  Every output element is
-// written once.
+// written once.  Eight nodes per lane keep the kernel at 152 VGPRs, three
+// waves per SIMD (sixteen took 240 VGPRs, two waves, and 10% longer).
 // ---------------------------------------------------------------------------
-constexpr int kAdjV = 16;
+constexpr int kAdjV = 8;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_chain_adjoint_rows(ChainBatch b, const T *__restrict__ x,
