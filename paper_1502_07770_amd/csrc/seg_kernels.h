@@ -1264,12 +1264,23 @@ __global__ __launch_bounds__(64) void k_seg_fix(WsOf<T, Prob> ws, typename Prob:
         return;
     }
     // x entering each segment from the right: compose the segment maps from the
-    // root's segment leftwards (seg_lo/hi are final here)
+    // root's segment leftwards (seg_lo/hi are final here).  Eight segments'
+    // maps are loaded before their stores, so a group costs one memory latency.
     T x = ws.seg_lo[(Sc - 1) * ws.C + c];
-#pragma unroll 4
-    for (int64_t j = Sc - 2; j >= 0; --j) {
-        ws.seg_xb[j * ws.C + c] = x;
-        x = clampv(x, ws.seg_lo[j * ws.C + c], ws.seg_hi[j * ws.C + c]);
+    for (int64_t j1 = Sc - 2; j1 >= 0; j1 -= 8) {
+        T lo[8], hi[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t j = j1 - k >= 0 ? j1 - k : 0;
+            lo[k] = ws.seg_lo[j * ws.C + c];
+            hi[k] = ws.seg_hi[j * ws.C + c];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (j1 - k < 0) break;
+            ws.seg_xb[(j1 - k) * ws.C + c] = x;
+            x = clampv(x, lo[k], hi[k]);
+        }
     }
 }
 
@@ -1381,11 +1392,19 @@ __global__ __launch_bounds__(64) void k_seg_tail(WsOf<T, Prob> ws, typename Prob
     if (u >= b) return;
     const T x = ws.seg_xb[s * C + c];
     const auto sink = Prob::sink(pp, sp);
-#pragma unroll 4
-    for (int64_t i = b - 1; i >= u; --i) {
-        const LamPair<T> p = ws.lam[i * C + c];
-        const auto sv = sink.load(i);
-        sink.store(i, clampv(x, p.lo, p.hi), sv);
+    // eight nodes' intervals (and sink inputs) loaded before their stores
+    for (int64_t i1 = b - 1; i1 >= u; i1 -= 8) {
+        LamPair<T> p[8];
+        typename Prob::SinkPre sv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = i1 - k >= u ? i1 - k : u;
+            p[k] = ws.lam[i * C + c];
+            sv[k] = sink.load(i);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (i1 - k >= u) sink.store(i1 - k, clampv(x, p[k].lo, p[k].hi), sv[k]);
     }
 }
 
