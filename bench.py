@@ -14,7 +14,9 @@ Also on the same JSON line:
                   8 TB/s HBM peak; traffic from the committed rocprofv3
                   FETCH_SIZE/WRITE_SIZE summary when it was taken on the current
                   kernel sources, else null.
-  cpu_baseline -- the FP64 C oracle on the host cores, same workload.
+  cpu_baseline -- the FP64 C oracle on the host cores, same workload; with
+                  the extras, "parity" holds each extra's max error against
+                  the oracle on the inputs that extra times (sampled).
   extras       -- 2D ROF time-to-gap 1e-4 in FP32 vs FP64 (512^2 and 4096^2),
                   200 iterations at 512^2, forward+backward of 65,536 chains of
                   1,024 with per-edge weights, the general chain DP (data weights,
@@ -239,6 +241,252 @@ def cpu_baseline(img, x_rows, x_cols):
                             "against the FP64 oracle (bar 1e-4)"}
 
 
+def oracle_parity(pick=None):
+    """Max error of each extra's result against the FP64 oracle, on the inputs
+    that line times (a seeded sample of its chains, trees or images where the
+    oracle on all of them would take minutes; 2D solves at a fixed iteration
+    count, the same on both sides).  Each entry holds max_err, the bar the GPU
+    tests hold that result to, ok, what the error measures and the sample.
+    FP32 results are compared with the oracle run on the FP32-rounded inputs."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1502_07770_amd import binding, synth
+    out = {}
+    f64 = lambda t: t.double().cpu().numpy()  # noqa: E731
+    dev = lambda a, t=torch.float32: torch.tensor(np.asarray(a), dtype=t, device="cuda")  # noqa: E731
+    pick_rng = np.random.default_rng(2024)
+
+    def want(key):
+        return pick is None or key in pick
+
+    def rec(key, err, bar, measure, sample, **extra):
+        out[key] = dict(max_err=float(err), bar=bar, ok=bool(err <= bar), measure=measure, sample=sample, **extra)
+        log("parity %s: %.3g (bar %g)" % (key, err, bar))
+
+    rel_img = "max |x - x_oracle| / (max f - min f)"
+    for key, side, seed, iters in (("tv2d_512", 512, 11, 200), ("tv2d_4096", SIDE, SEED, 5)):
+        if not want(key):
+            continue
+        img = synth.shapes_image(side, side, seed=seed)
+        for name, dt, bar in (("fp32", torch.float32, 1e-4), ("fp64", torch.float64, 1e-9)):
+            f = dev(img, dt)
+            x, info = binding.tv2d(f, 0.1, max_iter=iters, gap_every=iters)
+            fv = f64(f)
+            xo, _, (_, _, go), _ = oracle.tv2d(fv, 0.1, max_iter=iters)
+            rec("%s_%s" % (key, name), np.abs(f64(x) - xo).max() / np.ptp(fv), bar, rel_img,
+                "whole image, %d iterations" % iters, gap=info["gap_norm"], gap_oracle=float(go))
+            del f, x
+
+    if want("adjoint"):
+        C, n, S = 65536, 1024, 2048
+        y = dev(synth.piecewise_constant(C, n, seed=5))
+        w = dev(synth.edge_weights((C, n), seed=6))
+        g = dev(synth.normal((C, n), seed=7))
+        x = binding.chain_prox(y, w, dim=-1)
+        dy, dw = binding.chain_prox_backward(x, g, dim=-1, per_edge_w=True)
+        rows = np.sort(pick_rng.choice(C, S, replace=False))
+        ri = torch.tensor(rows, device="cuda")
+        yv, wv, gv, xg, dyg, dwg = (f64(t.index_select(0, ri)) for t in (y, w, g, x, dy, dw))
+        del y, w, g, x, dy, dw
+        wv[:, -1] = 0.0  # the last slot is no edge
+        xo = oracle.chain_prox(yv, w=wv)
+        dyo, dwo = oracle.chain_adjoint(xo, gv)
+        same = ((xg[:, 1:] == xg[:, :-1]) == (xo[:, 1:] == xo[:, :-1])).all(axis=1)
+        sample = "%d of the 65,536 chains (seeded choice)" % S
+        rec("adjoint_fwd", (np.abs(xg - xo) / np.ptp(yv, axis=1, keepdims=True)).max(), 1e-4,
+            "max over chains of |x - x_oracle| / (max y - min y)", sample)
+        rec("adjoint_dy", np.abs(dyg - dyo)[same].max(initial=0.0) / max(1.0, np.abs(dyo).max()), 1e-4,
+            "max |dy - dy_oracle| / max(1, max |dy_oracle|) over chains whose run structure matches the oracle's",
+            sample, run_structure_mismatch=round(1.0 - float(same.mean()), 5), run_structure_mismatch_bar=0.02)
+        rec("adjoint_dw", np.abs(dwg - dwo)[same].max(initial=0.0) / max(1.0, np.abs(dwo).max()), 1e-4,
+            "max |dw - dw_oracle| / max(1, max |dw_oracle|) over the same chains", sample)
+
+    if want("general_dp"):
+        a, b, wm, wp = (dev(v) for v in synth.general_chain_problem(SIDE, SIDE, seed=SEED))
+        S = 128
+        worst = 0.0
+        for dim in (-1, 0):
+            xg = binding.chain_dp(b, wm, wp, a=a, dim=dim)
+            idx = np.sort(pick_rng.choice(SIDE, S, replace=False))
+            for c in idx:
+                sl = (int(c), slice(None)) if dim == -1 else (slice(None), int(c))
+                av, bv, wmv, wpv, xv = (f64(t[sl]) for t in (a, b, wm, wp, xg))
+                xo = oracle.chain_dp(av, bv, wmv[:-1], wpv[:-1])[0]
+                scale = max(np.ptp(xo), np.ptp(bv / av), 1e-30)
+                worst = max(worst, np.abs(xv - xo).max() / scale)
+            del xg
+        rec("general_dp", worst, 1e-4, "max over chains of |x - x_oracle| / max(range x_oracle, range b/a)",
+            "%d row and %d column chains (seeded choice)" % (S, S))
+        del a, b, wm, wp
+
+    if want("tv_l1"):
+        S = 4096
+        f = dev(synth.salt_pepper_chains(65536, 1024, seed=12))
+        ft = f.t().contiguous()
+        rows = torch.tensor(np.sort(pick_rng.choice(65536, S, replace=False)), device="cuda")
+        xr = f64(binding.chain_prox_l1(f, f, 0.55, 1.0, dim=-1).index_select(0, rows))
+        xc = f64(binding.chain_prox_l1(ft, ft, 0.55, 1.0, dim=0).index_select(1, rows).t())
+        yv = f64(f.index_select(0, rows))
+        del f, ft
+        xo = oracle.chain_prox_l1(yv, yv, w_scalar=0.55, c_scalar=1.0)
+        s = np.maximum(np.ptp(yv, axis=1), 1.0)
+        err = max((np.abs(xr - xo).max(axis=1) / s).max(), (np.abs(xc - xo).max(axis=1) / s).max())
+        rec("tv_l1", err, 1e-4, "max over chains of |x - x_oracle| / max(range y, 1), row and column layouts",
+            "%d of the 65,536 chains (seeded choice)" % S)
+
+    if want("tv2d_l1"):
+        iters = 10
+        f = dev(tv2d_l1_image())
+        x, info = binding.tv2d_l1(f, 0.55, max_iter=iters, energy_every=iters)
+        fv = f64(f)
+        xo, ho = oracle.tv2d_l1(fv, 0.55, tau=1.0, max_iter=iters)
+        rec("tv2d_l1", np.abs(f64(x) - xo).max(), 1e-4, "max |x - x_oracle| (f in [0, 1])",
+            "whole 4096 x 4096 image, %d iterations" % iters, energy=info["primal"], energy_oracle=float(ho[-1]))
+        del f, x
+
+    if want("tree"):
+        par, off, vals = tree_inputs()
+        ts = [dev(v) for v in vals]
+        xg = f64(binding.tree_dp(torch.tensor(par, device="cuda"), torch.tensor(off, device="cuda"), ts[1], ts[4],
+                                 ts[5], a=ts[0], c=ts[2], d=ts[3]))
+        a, b, c, d, wm, wp = (f64(t) for t in ts)
+        del ts
+        worst = 0.0
+        for t in pick_rng.choice(65536, 300, replace=False):
+            lo, hi = off[t], off[t + 1]
+            p = par[lo:hi].copy()
+            p[p >= 0] -= lo
+            xo = oracle.tree_pq(p, *(v[lo:hi] for v in (a, b, c, d, wm, wp)))[0]
+            worst = max(worst, np.abs(xg[lo:hi] - xo).max() / max(np.ptp(xo), np.ptp(b[lo:hi] / a[lo:hi]), 1.0))
+        rec("tree", worst, 1e-5, "max over trees of |x - x_oracle| / max(range x_oracle, range b/a, 1)",
+            "300 of the 65,536 trees (seeded choice)")
+
+    def energy_rec(key, diffs, sample):
+        d = np.array(diffs)  # (|E_gpu - E_oracle|, 1 + |E_oracle|, nodes) per chain or tree
+        rec(key, float((d[:, 0] / d[:, 1]).max()), 1e-5,
+            "max |E(x) - E(x_oracle)| / (1 + |E(x_oracle)|) (minimisers need not be unique)", sample,
+            within_test_tolerance=bool((d[:, 0] <= 1e-5 * d[:, 1] + 1e-4 * d[:, 2]).all()))
+
+    if want("nc"):
+        coff, uoff, ulam, usl, _ = synth.cost_volume_chains(1000, 1482, 64, seed=1)
+        N = uoff.size - 1
+        ulam, usl = (v.astype(np.float32).astype(np.float64) for v in (ulam, usl))
+        w, Cc = np.full(N, np.float32(0.6), dtype=np.float64), np.full(N, 2.0)  # the FP32 weights
+        x = f64(binding.chain_nc(dev(coff, torch.int64), dev(uoff, torch.int64), dev(ulam), dev(usl), dev(w),
+                                 dev(Cc), msg_cap=256))
+        diffs = []
+        for c in pick_rng.choice(coff.size - 1, 64, replace=False):
+            n0, n1 = int(coff[c]), int(coff[c + 1])
+            uo = uoff[n0:n1 + 1] - uoff[n0]
+            lc, sc = ulam[uoff[n0]:uoff[n1]], usl[uoff[n0] + n0:uoff[n1] + n1]
+            xo, _ = oracle.nc_chain(uo, lc, sc, w[n0:n1 - 1], Cc[n0:n1 - 1])
+            eo = oracle.nc_energy(uo, lc, sc, w[n0:n1 - 1], Cc[n0:n1 - 1], xo)
+            eg = oracle.nc_energy(uo, lc, sc, w[n0:n1 - 1], Cc[n0:n1 - 1], x[n0:n1])
+            diffs.append((abs(eg - eo), 1.0 + abs(eo), n1 - n0))
+        energy_rec("nc", diffs, "64 of the 1000 rows (seeded choice)")
+
+    if want("nc2d"):
+        cost, _ = synth.cost_volume(1000, 1482, 64, seed=1)
+        crop = np.ascontiguousarray(cost[:128, :160].astype(np.float32).astype(np.float64))
+        del cost
+        iters = 5
+        x = f64(binding.tv2d_nc(dev(crop), 0.0, 1.0, 10.0, 0.6, 0.6, 2.0, 100.0, iters))
+        _, _, E = oracle.nc2d_pd(crop, 0.0, 1.0, 10.0, 0.6, 0.6, 2.0, 100.0, iters)
+        e = oracle.nc2d_energy(crop, 0.0, 1.0, 10.0, 0.6, 0.6, 2.0, x)
+        rec("nc2d", abs(e - E[-1]) / (1 + abs(E[-1])), 1e-5,
+            "|E(x) - E(x_oracle)| / (1 + |E(x_oracle)|) after the same iterations",
+            "the top-left 128 x 160 crop of the 64-level cost volume, %d iterations" % iters)
+
+    if want("nc_tree"):
+        par, off, uoff, ulam, usl, w, Cc = nc_tree_inputs()
+        x = f64(binding.tree_nc(dev(par, torch.int64), dev(off, torch.int64), dev(uoff, torch.int64), dev(ulam),
+                                dev(usl), dev(w), dev(Cc), msg_cap=512, map_cap=32 * 256, stack_cap=48 * 1025))
+        ulam, usl = (v.astype(np.float32).astype(np.float64) for v in (ulam, usl))
+        diffs = []
+        for t in pick_rng.choice(off.size - 1, 32, replace=False):
+            n0, n1 = int(off[t]), int(off[t + 1])
+            p = par[n0:n1].copy()
+            p[p >= 0] -= n0
+            uo = uoff[n0:n1 + 1] - uoff[n0]
+            lc, sc = ulam[uoff[n0]:uoff[n1]], usl[uoff[n0] + n0:uoff[n1] + n1]
+            xo, _ = oracle.nc_tree(p, uo, lc, sc, w[n0:n1], Cc[n0:n1])
+            eo = oracle.nc_tree_energy(p, uo, lc, sc, w[n0:n1], Cc[n0:n1], xo)
+            eg = oracle.nc_tree_energy(p, uo, lc, sc, w[n0:n1], Cc[n0:n1], x[n0:n1])
+            diffs.append((abs(eg - eo), 1.0 + abs(eo), n1 - n0))
+        energy_rec("nc_tree", diffs, "32 of the 16,384 trees (seeded choice)")
+
+    if want("batched"):
+        packed, shapes, lams = batched_inputs()
+        iters = 20
+        xs, _ = binding.tv2d_batched(shapes, lams, max_iter=iters, gap_every=iters, packed=dev(packed))
+        worst, offs = 0.0, np.concatenate([[0], np.cumsum([h * w_ for h, w_ in shapes])])
+        picked = pick_rng.choice(len(shapes), 8, replace=False)
+        for j in picked:
+            fv = packed[offs[j]:offs[j + 1]].astype(np.float64).reshape(shapes[j])
+            xo = oracle.tv2d(fv, lams[j], max_iter=iters)[0]
+            worst = max(worst, np.abs(f64(xs[j]) - xo).max() / max(np.ptp(fv), 1e-12))
+        del xs
+        rec("batched", worst, 1e-4, rel_img, "8 of the 256 images (seeded choice), %d iterations" % iters)
+    torch.cuda.empty_cache()
+    return out
+
+
+def tv2d_l1_image():
+    """The 2D TV-l1 input: the 4096 x 4096 shapes image (no Gaussian noise) with
+    25% of the pixels replaced by 0 or 1."""
+    import numpy as np
+    from paper_1502_07770_amd import synth
+    rng = np.random.default_rng(SEED)
+    f = synth.shapes_image(SIDE, SIDE, sigma=0.0, seed=SEED)
+    m = rng.random(f.shape) < 0.25
+    f[m] = rng.integers(0, 2, int(m.sum()))
+    return f
+
+
+def tree_inputs():
+    """The tree line's forest and data: 65,536 post-order trees of 256 nodes,
+    a ~ U[0.3, 2], b = a N(0, 1), c ~ U[0, 1] on 70% of the nodes (0 elsewhere),
+    d ~ N(0, 1), w^- ~ -U[0, 0.8], w^+ ~ U[0, 0.8]."""
+    from paper_1502_07770_amd import synth
+    par, off = synth.post_order_forest(65536, 256, seed=1)
+    g = synth.generator(2)
+    N = par.size
+    a = g.uniform(0.3, 2.0, N)
+    vals = [a, a * g.normal(size=N), g.uniform(0, 1, N) * (g.random(N) < 0.7), g.normal(size=N),
+            -g.uniform(0, 0.8, N), g.uniform(0, 0.8, N)]
+    return par, off, vals
+
+
+def nc_tree_inputs():
+    """The non-convex tree line's input: 16,384 post-order trees of 256 nodes,
+    unaries through uniform [0, 4] costs at 16 levels (slopes -/+10 outside),
+    w = 0.5, C = 2 on every edge.  Returns (par, off, uoff, ulam, uslope, w, C)."""
+    import numpy as np
+    from paper_1502_07770_amd import synth
+    T, n, D = 16384, 256, 16
+    par, off = synth.post_order_forest(T, n, seed=7)
+    N = par.size
+    g = synth.generator(8)
+    cost = g.uniform(0, 4, (N, D))
+    sl = np.empty((N, D + 1))
+    sl[:, 0], sl[:, D] = -10.0, 10.0
+    sl[:, 1:D] = np.diff(cost, axis=1)
+    return (par, off, np.arange(N + 1, dtype=np.int64) * D, np.tile(np.arange(D, dtype=np.float64), N),
+            sl.reshape(-1), np.full(N, 0.5), np.full(N, 2.0))
+
+
+def batched_inputs():
+    """The batched line's 256 uneven images, packed FP32, with their shapes and
+    lambdas."""
+    import numpy as np
+    from paper_1502_07770_amd import synth
+    specs = synth.uneven_batch_specs(256, seed=11)
+    packed = np.concatenate([synth.shapes_image(s["H"], s["W"], sigma=s["sigma"], seed=s["seed"]).ravel()
+                             .astype(np.float32) for s in specs])
+    return packed, [(s["H"], s["W"]) for s in specs], [s["lam"] for s in specs]
+
+
 def bench_tv2d(side: int, seed: int, iters_fixed: int | None, hist_iters: int, max_iter: int):
     """2D ROF (Sec. 5.1) on a side x side shapes image, FP32 and FP64 iterates
     (FP64 gaps).  The gap after every iteration (gap_every = 1) over hist_iters
@@ -383,11 +631,7 @@ def bench_tv2d_l1():
     import numpy as np
     import torch
     from paper_1502_07770_amd import binding, synth
-    rng = np.random.default_rng(SEED)
-    f = synth.shapes_image(SIDE, SIDE, sigma=0.0, seed=SEED)
-    m = rng.random(f.shape) < 0.25
-    f[m] = rng.integers(0, 2, int(m.sum()))
-    ft = torch.tensor(f, dtype=torch.float32, device="cuda")
+    ft = torch.tensor(tv2d_l1_image(), dtype=torch.float32, device="cuda")
     _, info = binding.tv2d_l1(ft, 0.55, max_iter=1, autotune=True)  # setup, not timed
     e0 = binding.tv2d_l1(ft, 0.55, max_iter=0)[1]["primal"]
     torch.cuda.synchronize()
@@ -567,18 +811,11 @@ def bench_nc_tree(steps: int):
     import numpy as np
     import torch
     from paper_1502_07770_amd import binding, synth
-    T, n, D = 16384, 256, 16
-    par, off = synth.post_order_forest(T, n, seed=7)
-    N = par.size
-    g = synth.generator(8)
-    cost = g.uniform(0, 4, (N, D))
-    sl = np.empty((N, D + 1))
-    sl[:, 0], sl[:, D] = -10.0, 10.0
-    sl[:, 1:D] = np.diff(cost, axis=1)
+    par, off, uoff, ulam, usl, w, C = nc_tree_inputs()
+    N, n = par.size, 256
     dev = lambda a, t=torch.float32: torch.tensor(a, dtype=t, device="cuda")  # noqa: E731
-    args = (dev(par, torch.int64), dev(off, torch.int64), dev(np.arange(N + 1, dtype=np.int64) * D, torch.int64),
-            dev(np.tile(np.arange(D, dtype=np.float64), N)), dev(sl.reshape(-1)), dev(np.full(N, 0.5)),
-            dev(np.full(N, 2.0)))
+    args = (dev(par, torch.int64), dev(off, torch.int64), dev(uoff, torch.int64), dev(ulam), dev(usl), dev(w),
+            dev(C))
     run = lambda: binding.tree_nc(*args, msg_cap=512, map_cap=32 * n, stack_cap=48 * 1025)  # noqa: E731
     run()
     ms = Timer(torch, torch.cuda.current_stream())(run, steps)
@@ -594,12 +831,8 @@ def bench_tree(steps: int):
     import numpy as np
     import torch
     from paper_1502_07770_amd import binding, synth
-    par, off = synth.post_order_forest(65536, 256, seed=1)
-    g = synth.generator(2)
+    par, off, vals = tree_inputs()
     N = par.size
-    a = g.uniform(0.3, 2.0, N)
-    vals = [a, a * g.normal(size=N), g.uniform(0, 1, N) * (g.random(N) < 0.7), g.normal(size=N),
-            -g.uniform(0, 0.8, N), g.uniform(0, 0.8, N)]
     a_t, b_t, c_t, d_t, wm_t, wp_t = (torch.tensor(v, dtype=torch.float32, device="cuda") for v in vals)
     pt, ot = torch.tensor(par, device="cuda"), torch.tensor(off, device="cuda")
     tm = Timer(torch, torch.cuda.current_stream())
@@ -619,13 +852,9 @@ def bench_batched():
     import torch
     from paper_1502_07770_amd import binding, synth
     t = time.perf_counter()
-    specs = synth.uneven_batch_specs(256, seed=11)
-    packed = np.concatenate([synth.shapes_image(s["H"], s["W"], sigma=s["sigma"], seed=s["seed"]).ravel()
-                             .astype(np.float32) for s in specs])
+    packed, shapes, lams = batched_inputs()
     gen_s = time.perf_counter() - t
     f = torch.from_numpy(packed).cuda()
-    shapes = [(s["H"], s["W"]) for s in specs]
-    lams = [s["lam"] for s in specs]
     tuned = {}
     binding.tv2d_batched(shapes, lams, max_iter=1, gap_every=1, packed=f, autotune=True, tuned=tuned)  # setup
     tm = Timer(torch, torch.cuda.current_stream())
@@ -647,17 +876,12 @@ def bench_batched():
 
 
 def c4_iters(iters: int):
-    """The C4 batch for profiling runs: its two launches autotuned (setup), then
-    `iters` iterations with one gap evaluation."""
-    import numpy as np
+    """The batched line's 256 images for profiling runs: its two launches
+    autotuned (setup), then `iters` iterations with one gap evaluation."""
     import torch
-    from paper_1502_07770_amd import binding, synth
-    specs = synth.uneven_batch_specs(256, seed=11)
-    packed = np.concatenate([synth.shapes_image(s["H"], s["W"], sigma=s["sigma"], seed=s["seed"]).ravel()
-                             .astype(np.float32) for s in specs])
+    from paper_1502_07770_amd import binding
+    packed, shapes, lams = batched_inputs()
     f = torch.from_numpy(packed).cuda()
-    shapes = [(s["H"], s["W"]) for s in specs]
-    lams = [s["lam"] for s in specs]
     tuned = {}
     binding.tv2d_batched(shapes, lams, max_iter=1, gap_every=1, packed=f, autotune=True, tuned=tuned)
     torch.cuda.synchronize()
@@ -883,6 +1107,13 @@ def main():
         except Exception as e:  # report what finished
             extras["error"] = repr(e)
         out["extras"] = extras
+    if not (args.no_cpu or args.no_extras):
+        log("bench: oracle parity of the extras")
+        try:
+            out["cpu_baseline"]["parity"] = oracle_parity(None if args.extras == "all"
+                                                          else set(args.extras.split(",")))
+        except Exception as e:  # report what finished
+            out["cpu_baseline"]["parity_error"] = repr(e)
     print(json.dumps(out), flush=True)
 
 
