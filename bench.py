@@ -493,9 +493,11 @@ def bench_tv2d(side: int, seed: int, iters_fixed: int | None, hist_iters: int, m
     iterations gives the iterations each per-pixel tolerance takes and the
     relative gap (P - D) / P.  Time to gap: solves with gap_every = 1 that stop
     on the device at the tolerance (gap checks included), timed with HIP events
-    around the whole call ("ms", which also holds the launches enqueued after
-    the stop, each returning at once) and by the device clock from the first
-    iteration to the stop ("device_ms").  At 1e-7 the FP32 iterate's gap floor
+    around the whole call ("ms": the binding's default lookahead of 4 chunks,
+    so at most 4 iterations of launches follow the stop), by the device clock
+    from the first iteration to the stop ("device_ms"), and with HIP events
+    around the fully asynchronous call ("ms_lookahead_0": every iteration up to
+    max_iter enqueued, those after the stop returning at once).  At 1e-7 the FP32 iterate's gap floor
     (about 1e-6 to 1e-7 per pixel) separates it from FP64."""
     import numpy as np
     import torch
@@ -531,8 +533,10 @@ def bench_tv2d(side: int, seed: int, iters_fixed: int | None, hist_iters: int, m
         for tol in (1e-4, 1e-5, 1e-6, 1e-7):
             res = {}
             ms = tm(lambda: res.update(info=s.solve(f, 0.1, max_iter=max_iter, gap_every=1, gap_tol=tol)[1]), 1)
+            ms0 = tm(lambda: s.solve(f, 0.1, max_iter=max_iter, gap_every=1, gap_tol=tol, lookahead=0), 1)
             info = res["info"]
-            ttg["%g" % tol] = {"ms": round(ms, 3), "device_ms": round(info["device_ms"], 3), "iters": info["iters"],
+            ttg["%g" % tol] = {"ms": round(ms, 3), "device_ms": round(info["device_ms"], 3),
+                               "ms_lookahead_0": round(ms0, 3), "iters": info["iters"],
                                "reached": info["status"] == binding.TV_OK,
                                "rel_gap": float(info["gap_norm"] * hw / info["primal"])}
         r["time_to_gap"] = ttg

@@ -433,6 +433,17 @@ typedef struct {
     int use_graph;       /* nonzero: capture a chunk of gap_every (<= 64) iterations
                             in a HIP graph once and replay it for every full chunk
                             (same kernels and results; fewer launches from the host) */
+    int lookahead;       /* 0: enqueue every iteration up to max_iter at once (the
+                            call never waits on the device).  1 .. 64: the host
+                            enqueues at most this many chunks of gap_every
+                            iterations beyond the last one it has seen finished
+                            (waiting on an event when ahead) and stops enqueuing
+                            once the device has stopped, so a solve that stops early
+                            costs at most this many chunks of launches that return
+                            at once; the call then returns when the device is within
+                            this many chunks of the end of what it enqueued.
+                            Results are the same either way.  Ignored by
+                            tv2d_l1_solve, which has no stopping test. */
 } tv2d_options;
 
 /* [DEVICE] Result of a 2D solve, written by the solve's last kernel on the
@@ -461,14 +472,18 @@ size_t tv2d_workspace(int64_t H, int64_t W, tv_dtype dtype);
  *  The duality gap uses dual edge variables recovered from the two chain
  *  solves, clipped to [-lambda, lambda], so P - D >= 0 always bounds the
  *  suboptimality of x.  Reductions are FP64 whatever dtype is.
- *  ASYNCHRONOUS on `stream`: every iteration up to max_iter is enqueued at
- *  once and the stopping test runs on the device: after each gap evaluation
- *  (every gap_every iterations) a device flag, once the gap is at gap_tol or
- *  not finite, makes every later kernel of the solve return at once (each
- *  such skipped iteration still costs its launches, a few microseconds).  The
- *  schedule is generated on the device, so nothing is copied from the host
- *  and the host never waits, except once when resuming (to read which buffer
- *  holds the iterate).  `stats` is DEVICE memory (or NULL), written by the
+ *  ASYNCHRONOUS on `stream` with lookahead 0: every iteration up to max_iter
+ *  is enqueued at once and the stopping test runs on the device: after each
+ *  gap evaluation (every gap_every iterations) a device flag, once the gap is
+ *  at gap_tol or not finite, makes every later kernel of the solve return at
+ *  once (each such skipped iteration still costs its launches, a few
+ *  microseconds each).  The schedule is generated on the device, so nothing
+ *  is copied from the host and the host never waits, except once when
+ *  resuming (to read which buffer holds the iterate).  With lookahead > 0 the
+ *  host also mirrors the device's stop through a pinned host word (one per
+ *  host thread and device, allocated on first use and kept) and stops
+ *  enqueuing after it: see tv2d_options.lookahead (outside 0 .. 64:
+ *  TV_ERR_INVALID_ARG).  `stats` is DEVICE memory (or NULL), written by the
  *  solve's last kernel; stats->status is TV_OK, TV_ERR_NOT_CONVERGED (gap_tol
  *  > 0 not reached) or TV_ERR_NONFINITE.
  *  Returns TV_OK once the solve is enqueued, or an argument / launch error. */
@@ -509,8 +524,10 @@ tv_status tv2d_batched_autotune(tv_dtype dtype, int num_images, const int64_t *H
  *  finite, is frozen on the device (its chains and gap terms are skipped from
  *  then on); once every image is frozen the solve stops as tv2d_solve does.
  *  ASYNCHRONOUS on `stream` except for one wait after the chain lists are
- *  uploaded from host memory (before any iteration is enqueued), and, with
- *  use_graph, a wait for the replays before returning.  resume must be 0.
+ *  uploaded from host memory (before any iteration is enqueued), the waits of
+ *  a lookahead > 0 (as for tv2d_solve; the stop comes once every image is
+ *  frozen), and, with use_graph, a wait for the replays before returning.
+ *  resume must be 0; lookahead outside 0 .. 64 is TV_ERR_INVALID_ARG.
  *  Returns TV_OK once the solve is enqueued, or an argument / launch error;
  *  each image's status is in its stats. */
 tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, const int64_t *W,

@@ -53,7 +53,19 @@ class ChainLayout(ctypes.Structure):
 class Tv2dOptions(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("gap_every", ctypes.c_int), ("gap_tol", ctypes.c_double),
                 ("tau0", ctypes.c_double), ("resume", ctypes.c_int), ("gap_history", ctypes.c_void_p),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("lookahead", ctypes.c_int)]
+
+
+# Chunks of gap_every iterations the host may enqueue ahead of the device in a
+# solve that can stop early (tv2d_options.lookahead); these calls read their
+# stats back at once, so the host waits for the device anyway.
+DEFAULT_LOOKAHEAD = 4
+
+
+def _lookahead(lookahead: Optional[int], gap_tol: float) -> int:
+    if lookahead is None:
+        return DEFAULT_LOOKAHEAD if gap_tol > 0.0 else 0
+    return int(lookahead)
 
 
 class Tuning(ctypes.Structure):
@@ -582,10 +594,12 @@ class Tv2dSolver:
     def solve(self, f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10,
               gap_tol: float = 0.0, tau0: float = 1.0, resume: bool = False,
               gap_history: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
-              use_graph: bool = False):
+              use_graph: bool = False, lookahead: Optional[int] = None):
         """Run the Sec. 5.1 decomposition.  Returns (x, stats dict).  With
         gap_tol > 0 a solve that stops at max_iter above the tolerance raises
-        nothing: stats['status'] says TV_ERR_NOT_CONVERGED."""
+        nothing: stats['status'] says TV_ERR_NOT_CONVERGED.  ``lookahead``:
+        tv2d_options.lookahead (default DEFAULT_LOOKAHEAD with gap_tol > 0,
+        else 0)."""
         _require_gpu(f)
         if f.shape != (self.H, self.W) or f.dtype != self.dtype:
             raise TvChainError(TV_ERR_INVALID_ARG, "f must be (%d, %d) %s" % (self.H, self.W, self.dtype))
@@ -601,7 +615,7 @@ class Tv2dSolver:
                 raise TvChainError(TV_ERR_INVALID_ARG, "gap_history must be a float64 GPU tensor")
             hist_ptr = gap_history.data_ptr()
         opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 1 if resume else 0, hist_ptr,
-                          1 if use_graph else 0)
+                          1 if use_graph else 0, _lookahead(lookahead, gap_tol))
         sbuf = _stats_buffer(1, f.device)
         st = load().tv2d_solve(self.code, _ptr(f), self.H, self.W, ld, float(lam), _ptr(x), ctypes.byref(opt),
                                _ptr(sbuf), _ptr(self.ws), self.nbytes, ctypes.c_void_p(_stream_ptr(f.device)))
@@ -614,21 +628,23 @@ class Tv2dSolver:
 
 
 def tv2d(f: torch.Tensor, lam: float, max_iter: int = 200, gap_every: int = 10, gap_tol: float = 0.0,
-         tau0: float = 1.0, gap_history: Optional[torch.Tensor] = None, use_graph: bool = False):
+         tau0: float = 1.0, gap_history: Optional[torch.Tensor] = None, use_graph: bool = False,
+         lookahead: Optional[int] = None):
     """2D ROF min_x lam (TV_h + TV_v)(x) + |x - f|^2 / 2 by the row/column chain
     decomposition (Sec. 5.1).  Returns (x, stats)."""
     s = Tv2dSolver(f.shape[0], f.shape[1], f.dtype, f.device)
     return s.solve(f, lam, max_iter=max_iter, gap_every=gap_every, gap_tol=gap_tol, tau0=tau0,
-                   gap_history=gap_history, use_graph=use_graph)
+                   gap_history=gap_history, use_graph=use_graph, lookahead=lookahead)
 
 
 def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol: float = 0.0,
                  tau0: float = 1.0, packed: Optional[torch.Tensor] = None, autotune: bool = False,
-                 tuned: Optional[dict] = None, use_graph: bool = False):
+                 tuned: Optional[dict] = None, use_graph: bool = False, lookahead: Optional[int] = None):
     """Solve many 2D ROF problems of different sizes in one call
     (tv2d_solve_batched).  ``images`` is a list of (H_j, W_j) GPU tensors of one
     dtype (or a list of shapes when ``packed`` holds them back to back);
     ``lams`` the per-image weights.  Each image stops at its own gap_tol.
+    ``lookahead`` as for Tv2dSolver.solve.
     Returns (list of x_j views into one packed output, list of stats dicts)."""
     if packed is None:
         _require_gpu(*images)
@@ -663,7 +679,8 @@ def tv2d_batched(images, lams, max_iter: int = 200, gap_every: int = 10, gap_tol
         if tuned is not None:
             tuned.update({"col": col.as_dict(), "row": row.as_dict()})
     x = torch.empty_like(packed)
-    opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 0, None, 1 if use_graph else 0)
+    opt = Tv2dOptions(int(max_iter), int(gap_every), float(gap_tol), float(tau0), 0, None, 1 if use_graph else 0,
+                      _lookahead(lookahead, gap_tol))
     sbuf = _stats_buffer(n, packed.device)
     st = lib.tv2d_solve_batched(code, n, Hs, Ws, Os, Ls, _ptr(packed), _ptr(x), ctypes.byref(opt), _ptr(sbuf),
                                 _ptr(ws), nbytes, ctypes.c_void_p(_stream_ptr(packed.device)))
@@ -694,7 +711,7 @@ def tv2d_l1(f: torch.Tensor, lam: float, max_iter: int = 200, energy_every: int 
         plans = {"col": col.as_dict(), "row": row.as_dict()}
     x = torch.empty_like(f)
     opt = Tv2dOptions(int(max_iter), int(energy_every), 0.0, float(tau0), 0,
-                      ctypes.c_void_p(energy_history.data_ptr()) if energy_history is not None else None, 0)
+                      ctypes.c_void_p(energy_history.data_ptr()) if energy_history is not None else None, 0, 0)
     sbuf = _stats_buffer(1, f.device)
     _check(lib.tv2d_l1_solve(code, _ptr(f), H, W, W, float(lam), _ptr(x), ctypes.byref(opt), _ptr(sbuf),
                              _ptr(ws), nbytes, stream), "tv2d_l1_solve")

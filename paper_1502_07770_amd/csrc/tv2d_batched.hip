@@ -521,7 +521,8 @@ static size_t batched_layout(void *base, const BGeom &g, BWs<T> *out) {
 // for the uploads from host memory.
 template <typename T>
 static tv_status batched_setup(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
-                               const double *lam, const T *f, double tau0, const BWs<T> &ws, hipStream_t st) {
+                               const double *lam, const T *f, double tau0, const BWs<T> &ws, hipStream_t st,
+                               uint32_t *host_stop = nullptr, uint32_t seq = 0) {
     std::vector<BImg> imgs(g.nimg);
     std::vector<int> rowimg((size_t)g.nrows);
     std::vector<BChain> rows, cols;
@@ -548,7 +549,7 @@ static tv_status batched_setup(const BGeom &g, const int64_t *H, const int64_t *
     e = e ? e : hipMemcpyAsync(ws.lam, lam, sizeof(double) * g.nimg, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return TV_ERR_HIP;
     hipLaunchKernelGGL(k_binit, dim3((unsigned)((g.nimg + 255) / 256)), dim3(256), 0, st, ws.bs, ws.active, g.nimg);
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, ws.ctl, tau0, g.nimg);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, ws.ctl, tau0, g.nimg, host_stop, seq);
     const unsigned nb = (unsigned)((g.total + 255) / 256);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, g.total, ws.x[0], g.total, (int64_t)1, g.total);
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, g.total, ws.xbar, g.total, (int64_t)1, g.total);
@@ -606,16 +607,20 @@ static hipError_t batched_iters(const BGeom &g, const BWs<T> &ws, const T *f, in
     return hipSuccess;
 }
 
-// The iterations are enqueued on st without waiting (the stopping test runs
-// on the device, see batched_iters); the setup waits once for its uploads, and
-// a solve that replays captured graphs waits for them before returning.
+// The iterations are enqueued on st without waiting on the device (the
+// stopping test runs on the device, see batched_iters), all of them, or with a
+// lookahead at most that many gap evaluations ahead of the device (see
+// Lookahead); the setup waits once for its uploads, and a solve that replays
+// captured graphs waits for them before returning.
 template <typename T>
 static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t *W, const int64_t *pix,
                                  const double *lam, const T *f, T *x, const tv2d_options *opt, tv2d_stats *stats,
                                  void *workspace, hipStream_t st) {
     BWs<T> ws;
     batched_layout<T>(workspace, g, &ws);
-    const tv_status s0 = batched_setup<T>(g, H, W, pix, lam, f, opt->tau0, ws, st);
+    Lookahead la;
+    if (!la.begin(opt->lookahead)) return TV_ERR_HIP;
+    const tv_status s0 = batched_setup<T>(g, H, W, pix, lam, f, opt->tau0, ws, st, la.dev_word(), la.seq);
     if (s0 != TV_OK) return s0;
     const unsigned nb = (unsigned)((g.total + 255) / 256);
     const int every = opt->gap_every > 0 ? opt->gap_every : 1;
@@ -626,6 +631,9 @@ static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t
     ChunkGraphs graphs;
     int cur = 0;
     for (int done = 0; done < opt->max_iter;) {
+        hipError_t le;
+        if (la.stopped(&le)) break;  // every image frozen: the copy-out reads each image's own buffer
+        if (le != hipSuccess) return TV_ERR_HIP;
         const int chunk = (opt->max_iter - done < every) ? opt->max_iter - done : every;
         // pieces of at most kSchedCap iterations; the gap follows the chunk's last
         for (int part = 0; part < chunk;) {
@@ -645,6 +653,7 @@ static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t
             cur = (cur + piece) & 1;
             part += piece;
         }
+        if (la.chunk_done(st) != hipSuccess) return TV_ERR_HIP;
         done += chunk;
     }
     hipLaunchKernelGGL((k_bcopy_out<T>), dim3(nb), dim3(256), 0, st, ws.imgs, g.nimg, ws.active, ws.bs, cur, ws.x[0],
@@ -781,6 +790,7 @@ tv_status tv2d_solve_batched(tv_dtype dtype, int num_images, const int64_t *H, c
     BGeom g;
     if (!options || !x) return TV_ERR_INVALID_ARG;
     if (options->max_iter < 0 || options->resume) return TV_ERR_INVALID_ARG;
+    if (options->lookahead < 0 || options->lookahead > kMaxLookahead) return TV_ERR_INVALID_ARG;
     tv_status s = batched_args(dtype, num_images, H, W, pixel_offsets, lambda, f, options->tau0, workspace,
                                workspace_bytes, &g);
     if (s != TV_OK) return s;

@@ -47,37 +47,42 @@ __host__ __device__ __forceinline__ IterSched make_sched(double tau, int64_t k) 
     return s;
 }
 
-// Device-resident control of a 2D solve.  The host enqueues every iteration
-// up to max_iter without waiting; the schedule is generated on the device, and
-// once the stopping test passes (or the gap is not finite) `stop` is set and
-// every later kernel of the solve returns at once.
+// Device-resident control of a 2D solve.  The host enqueues iterations
+// without waiting on the device (up to max_iter, or a bounded lookahead of gap
+// evaluations, see Lookahead below); the schedule is generated on the device,
+// and once the stopping test passes (or the gap is not finite) `stop` is set
+// and every later kernel of the solve returns at once.
 struct SolveCtl {
     double tau;        // tau of the next iteration to schedule
     int64_t knext;     // index of the next iteration to schedule
     int32_t stop;      // 1: stopped; later launches do nothing
     int32_t status;    // the solve's status once stopped (TV_OK or TV_ERR_NONFINITE)
     int32_t n_active;  // batched solves: images still iterating
-    int32_t pad;
+    uint32_t seq;      // the call's number, written to *host_stop at the stop
     uint64_t t0, t1;   // device wall clock at the first scheduled iteration and at the stop
+    uint32_t *host_stop;  // pinned host word that mirrors the stop for the host (or null)
 };
 
-static __global__ void k_ctl_init(SolveCtl *c, double tau0, int n_active) {
+static __global__ void k_ctl_init(SolveCtl *c, double tau0, int n_active, uint32_t *host_stop, uint32_t seq) {
     if (threadIdx.x != 0) return;
     c->tau = tau0;
     c->knext = 0;
     c->stop = 0;
     c->status = TV_OK;
     c->n_active = n_active;
-    c->pad = 0;
+    c->seq = seq;
     c->t0 = c->t1 = 0;
+    c->host_stop = host_stop;
 }
 
 // A resumed solve continues from the saved schedule position.
-static __global__ void k_ctl_resume(SolveCtl *c) {
+static __global__ void k_ctl_resume(SolveCtl *c, uint32_t *host_stop, uint32_t seq) {
     if (threadIdx.x != 0) return;
     c->stop = 0;
     c->status = TV_OK;
+    c->seq = seq;
     c->t0 = c->t1 = 0;
+    c->host_stop = host_stop;
 }
 
 // The accelerated schedule of the next `count` iterations (FP64, one thread;
@@ -99,6 +104,10 @@ __device__ __forceinline__ void ctl_stop(SolveCtl *c, int status) {
     c->stop = 1;
     c->status = status;
     c->t1 = wall_clock64();
+    if (c->host_stop) {
+        *(volatile uint32_t *)c->host_stop = c->seq;
+        __threadfence_system();
+    }
 }
 
 // Milliseconds of device time since the first scheduled iteration, up to the
@@ -201,6 +210,75 @@ tv_status tune_launch(int64_t C, int64_t n, size_t seg_bytes, Fn launch, hipStre
     }
     return TV_OK;
 }
+
+// Bounded lookahead of a solve's host loop (tv2d_options::lookahead = A > 0):
+// after each chunk of iterations (one gap evaluation) the host records an
+// event; before enqueuing chunk n it waits for the event of chunk n - A and
+// reads the pinned host word that the device's stop writes this call's number
+// to, and stops enqueuing once it is there.  The device keeps A - 1 chunks
+// queued meanwhile, and a solve that stops early costs at most A chunks of
+// launches that return at once.  The word and the events belong to the host
+// thread and the device (one set per pair, kept until the process ends), so
+// calls from one thread run their loops one after another; a call's number
+// tells its stop from a late stop of an earlier call of the thread.
+constexpr int kMaxLookahead = 64;
+constexpr int kLookaheadDevices = 64;
+
+struct StopMirror {
+    uint32_t *host = nullptr;  // pinned host word
+    uint32_t *dev = nullptr;   // its address on the device
+    uint32_t seq = 0;
+    hipEvent_t ev[kMaxLookahead] = {};
+};
+
+inline StopMirror *stop_mirror() {
+    static thread_local StopMirror m[kLookaheadDevices];
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kLookaheadDevices) return nullptr;
+    StopMirror &s = m[d];
+    if (!s.host) {
+        void *p = nullptr, *dp = nullptr;
+        if (hipHostMalloc(&p, 256, hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent) !=
+            hipSuccess)
+            return nullptr;
+        if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess) return nullptr;
+        for (auto &e : s.ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        *(volatile uint32_t *)p = 0;
+        s.host = (uint32_t *)p;
+        s.dev = (uint32_t *)dp;
+    }
+    return &s;
+}
+
+struct Lookahead {
+    StopMirror *m = nullptr;
+    int depth = 0;
+    uint32_t seq = 0;
+    int n = 0;  // chunks enqueued
+    // Returns false if the host resources cannot be set up.
+    bool begin(int lookahead) {
+        depth = lookahead;
+        if (depth <= 0) return true;
+        m = stop_mirror();
+        if (!m) return false;
+        seq = ++m->seq;
+        if (seq == 0) seq = ++m->seq;  // 0 is never a call's number
+        return true;
+    }
+    uint32_t *dev_word() const { return m ? m->dev : nullptr; }
+    // Before enqueuing the next chunk: true once the device has stopped.
+    bool stopped(hipError_t *err) {
+        *err = hipSuccess;
+        if (depth <= 0 || n < depth) return false;
+        *err = hipEventSynchronize(m->ev[(n - depth) % depth]);
+        return *err == hipSuccess && *(volatile uint32_t *)m->host == seq;
+    }
+    hipError_t chunk_done(hipStream_t st) {
+        if (depth <= 0) return hipSuccess;
+        return hipEventRecord(m->ev[n++ % depth], st);
+    }
+};
 
 // Graphs of full chunks, one per starting parity, captured on a private
 // stream on first use and replayed on the caller's stream.

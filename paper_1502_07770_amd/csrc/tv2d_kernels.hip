@@ -511,29 +511,34 @@ static hipError_t tv2d_iters(const Tv2dWs<T> &ws, const T *f, int64_t ldf, int64
     return hipSuccess;
 }
 
-// The whole solve is enqueued on st without waiting (the stopping test runs
-// on the device, see tv2d_iters); a resume reads the header once to learn
-// which buffer holds the iterate.
+// The solve is enqueued on st without waiting on the device (the stopping
+// test runs on the device, see tv2d_iters), all of it, or with a lookahead
+// the host keeps at most that many gap evaluations ahead and stops enqueuing
+// once the device has stopped; a resume reads the header once to learn which
+// buffer holds the iterate.
 template <typename T>
 static tv_status tv2d_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, double lam, T *x,
                               const tv2d_options *opt, tv2d_stats *stats, void *workspace, hipStream_t st) {
     Tv2dWs<T> ws;
     tv2d_layout<T>(workspace, H, W, &ws);
     const unsigned nb = (unsigned)((H * W + 255) / 256);
+    Lookahead la;
+    if (!la.begin(opt->lookahead)) return TV_ERR_HIP;
     int cur = 0;
     if (opt->resume) {
         int64_t c = 0;
         if (hipMemcpyAsync(&c, &ws.hdr->cur, sizeof(c), hipMemcpyDeviceToHost, st) != hipSuccess) return TV_ERR_HIP;
         if (hipStreamSynchronize(st) != hipSuccess) return TV_ERR_HIP;
         cur = (int)(c & 1);
-        hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, st, &ws.hdr->ctl);
+        hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, la.dev_word(), la.seq);
     } else {
         // x^0 = xbar^0 = f, y^0 = 0
         hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.x[0], W, H, W);
         hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
         hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
         hipLaunchKernelGGL(k_tv2d_init_hdr, dim3(1), dim3(64), 0, st, ws.hdr);
-        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, opt->tau0, 1);
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, opt->tau0, 1, la.dev_word(),
+                           la.seq);
     }
     const int every = opt->gap_every > 0 ? opt->gap_every : 1;
     const SegPlan pc = seg_plan(W, H, kPlan2dCol), pr = seg_plan(H, W, kPlan2dRow);
@@ -541,6 +546,9 @@ static tv_status tv2d_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, doub
         return TV_ERR_WORKSPACE;
     ChunkGraphs graphs;
     for (int done = 0; done < opt->max_iter;) {
+        hipError_t le;
+        if (la.stopped(&le)) break;
+        if (le != hipSuccess) return TV_ERR_HIP;
         const int chunk = (opt->max_iter - done < every) ? opt->max_iter - done : every;
         for (int part = 0; part < chunk;) {
             const int piece = (chunk - part < kSchedCap) ? chunk - part : kSchedCap;
@@ -560,6 +568,7 @@ static tv_status tv2d_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, doub
             cur = (cur + piece) & 1;
             part += piece;
         }
+        if (la.chunk_done(st) != hipSuccess) return TV_ERR_HIP;
         done += chunk;
     }
     hipLaunchKernelGGL((k_tv2d_finish<T>), dim3(nb), dim3(256), 0, st, ws.hdr, ws.x[0], ws.x[1], x, ld, H, W, stats,
@@ -581,7 +590,7 @@ static tv_status tv2d_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld, d
     hipLaunchKernelGGL((k_copy2d<T>), dim3(nb), dim3(256), 0, st, f, ld, ws.xbar, W, H, W);
     hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(256), 0, st, ws.y[0], H * W, (T)0);
     hipLaunchKernelGGL(k_tv2d_init_hdr, dim3(1), dim3(64), 0, st, ws.hdr);
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, tau0, 1);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, tau0, 1, nullptr, 0u);
     // Run a few iterations first: the deques of the column and row chains
     // deepen as the dual variable builds up, and a plan timed on the first
     // iteration's data alone would pick a ring that overflows later on.
@@ -727,7 +736,7 @@ static tv_status tv2d_l1_init(const T *f, int64_t H, int64_t W, int64_t ld, doub
     // the same scalars every iteration
     hipLaunchKernelGGL(k_l1_sched_set, dim3(1), dim3(64), 0, st, ws.sched, tau);
     // the device clock starts here (no schedule: the count is 0)
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, tau, 1);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, tau, 1, nullptr, 0u);
     hipLaunchKernelGGL(k_ctl_sched, dim3(1), dim3(64), 0, st, &ws.hdr->ctl, ws.sched, 0);
     return hipGetLastError() == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
@@ -890,6 +899,7 @@ tv_status tv2d_solve(tv_dtype dtype, const void *f, int64_t H, int64_t W, int64_
     if (!f || !x || !options || H < 1 || W < 1 || ld < W) return TV_ERR_INVALID_ARG;
     if (!(isfinite(lambda) && lambda >= 0.0)) return TV_ERR_INVALID_ARG;
     if (options->max_iter < 0 || !(options->tau0 > 0.0) || !isfinite(options->tau0)) return TV_ERR_INVALID_ARG;
+    if (options->lookahead < 0 || options->lookahead > kMaxLookahead) return TV_ERR_INVALID_ARG;
     const int64_t lim = (dtype == TV_F32) ? (int64_t(1) << 24) : (int64_t(1) << 31) - 8;
     if (H >= lim || W >= lim) return TV_ERR_INVALID_ARG;
     if (!workspace || workspace_bytes < tv2d_workspace(H, W, dtype)) return TV_ERR_WORKSPACE;

@@ -134,6 +134,13 @@ int main(void) {
     expect_status("tv2d small ws", tv2d_solve(TV_F32, p, 8, 8, 8, 0.1, q, &opt, NULL, p, 8, NULL),
                   TV_ERR_WORKSPACE);
     bad = opt;
+    bad.lookahead = 65;
+    expect_status("tv2d lookahead", tv2d_solve(TV_F32, p, 8, 8, 8, 0.1, q, &bad, NULL, p, 1 << 30, NULL),
+                  TV_ERR_INVALID_ARG);
+    bad.lookahead = -1;
+    expect_status("tv2d lookahead < 0", tv2d_solve(TV_F64, p, 8, 8, 8, 0.1, q, &bad, NULL, p, 1 << 30, NULL),
+                  TV_ERR_INVALID_ARG);
+    bad = opt;
     bad.gap_tol = 1e-3;
     expect_status("tv2d l1 gap_tol", tv2d_l1_solve(TV_F32, p, 8, 8, 8, 0.5, p, &bad, NULL, p, 1 << 30, NULL),
                   TV_ERR_INVALID_ARG);
@@ -165,6 +172,10 @@ int main(void) {
     expect_status("batched resume",
                   tv2d_solve_batched(TV_F32, NI, H, W, off, lam, p, p, &opt, NULL, p, bws, NULL), TV_ERR_INVALID_ARG);
     opt.resume = 0;
+    opt.lookahead = 99;
+    expect_status("batched lookahead",
+                  tv2d_solve_batched(TV_F32, NI, H, W, off, lam, p, q, &opt, NULL, p, bws, NULL), TV_ERR_INVALID_ARG);
+    opt.lookahead = 0;
     expect_status("batched small ws",
                   tv2d_solve_batched(TV_F32, NI, H, W, off, lam, p, q, &opt, NULL, p, bws - 1, NULL), TV_ERR_WORKSPACE);
 

@@ -187,6 +187,24 @@ def test_tv2d_l1_argument_errors(lib):
     assert lib.tv2d_l1_autotune(0, buf, 64, 48, 48, 0.5, 0.0, ws, big, None, None, None) == binding.TV_ERR_INVALID_ARG
 
 
+def test_tv2d_lookahead_out_of_range_is_rejected(lib):
+    """tv2d_options.lookahead outside 0 .. 64 is an argument error of the ROF
+    and the batched solve, found on the host before any device call."""
+    P = ctypes.c_void_p
+    buf, out, ws = P(0x10000000), P(0x20000000), P(0x30000000)
+    big = 1 << 30
+    H = (ctypes.c_int64 * 1)(16)
+    W = (ctypes.c_int64 * 1)(16)
+    off = (ctypes.c_int64 * 1)(0)
+    lam = (ctypes.c_double * 1)(0.1)
+    for la in (-1, 65):
+        bad = binding.Tv2dOptions(5, 1, 1e-4, 1.0, 0, None, 0, la)
+        assert lib.tv2d_solve(0, buf, 16, 16, 16, 0.1, out, ctypes.byref(bad), None, ws, big,
+                              None) == binding.TV_ERR_INVALID_ARG
+        assert lib.tv2d_solve_batched(0, 1, H, W, off, lam, buf, out, ctypes.byref(bad), None, ws, big,
+                                      None) == binding.TV_ERR_INVALID_ARG
+
+
 def test_tree_dp_argument_errors(lib):
     P = ctypes.c_void_p
     buf, x = P(0x10000000), P(0x20000000)

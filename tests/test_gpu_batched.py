@@ -119,3 +119,31 @@ def test_batched_graph_replays_match_direct_launches():
     assert len({i["iters"] for i in inf0}) > 1          # images stop in different replays
     for a, b, ia, ib in zip(xs0, xs1, inf0, inf1):
         assert torch.equal(a, b) and ia["iters"] == ib["iters"] and ia["gap_norm"] == ib["gap_norm"]
+
+
+def test_batched_lookahead_gives_the_async_result():
+    """tv2d_options.lookahead in the batched solve: the host stops enqueuing
+    once every image is frozen; same per-image results as enqueuing every
+    iteration up to max_iter (lookahead 0), in less wall time."""
+    import time
+    specs, imgs = _batch(10, 24, 180, seed=9)
+    ts = [torch.tensor(im, dtype=torch.float32, device="cuda") for im in imgs]
+    lams = [s["lam"] for s in specs]
+    run = lambda la: binding.tv2d_batched(ts, lams, max_iter=1500, gap_every=1, gap_tol=1e-4,  # noqa: E731
+                                          lookahead=la)
+    run(0), run(4)
+    res = {}
+    for la in (0, 1, 4):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res[la] = run(la)
+        torch.cuda.synchronize()
+        res[la] += (time.perf_counter() - t,)
+    xs0, inf0, t0 = res[0]
+    assert len({i["iters"] for i in inf0}) > 1 and max(i["iters"] for i in inf0) < 100
+    for la in (1, 4):
+        xs1, inf1, t1 = res[la]
+        for a, b, ia, ib in zip(xs0, xs1, inf0, inf1):
+            assert torch.equal(a, b) and (ia["iters"], ia["gap_norm"], ia["status"]) == (ib["iters"], ib["gap_norm"],
+                                                                                      ib["status"])
+        assert t1 < 0.5 * t0, (la, t1, t0)

@@ -4,6 +4,8 @@ The oracle runs the same iteration (same schedule, x^0 = f, y^0 = 0); the GPU
 FP64 path must match it to rounding, the FP32 path to 1e-4 x (max f - min f).
 Gap values are rigorous bounds on both sides and are compared too.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -172,3 +174,61 @@ def test_graph_replays_match_direct_launches(every, iters):
     x2, i2 = binding.tv2d(f, 0.12, max_iter=500, gap_every=every, gap_tol=2e-4, use_graph=True)
     x3, i3 = binding.tv2d(f, 0.12, max_iter=500, gap_every=every, gap_tol=2e-4)
     assert i2["iters"] == i3["iters"] and torch.equal(x2, x3)
+
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("every,graph", [(1, False), (5, False), (5, True)])
+def test_lookahead_gives_the_async_result_without_the_stopped_launches(dtype, every, graph):
+    """tv2d_options.lookahead: the host stops enqueuing once the device has
+    stopped.  Same iterate, iterations and gap as the fully asynchronous solve
+    (lookahead 0, every iteration up to max_iter enqueued), and far less wall
+    time when the stop comes long before max_iter."""
+    f = torch.tensor(_img(96, 80, seed=21), dtype=dtype, device="cuda")
+    s = binding.Tv2dSolver(96, 80, dtype)
+    run = lambda la: s.solve(f, 0.1, max_iter=1500, gap_every=every, gap_tol=1e-4, use_graph=graph,  # noqa: E731
+                             lookahead=la)
+    run(0), run(4)  # warm-up (graph capture, first launches)
+    (x0, i0), t0 = _timed(lambda: run(0))
+    assert i0["status"] == binding.TV_OK and i0["iters"] < 100
+    for la in (1, 4, 64):
+        (x1, i1), t1 = _timed(lambda: run(la))  # noqa: B023
+        assert torch.equal(x0, x1)
+        assert (i1["iters"], i1["gap_norm"], i1["status"]) == (i0["iters"], i0["gap_norm"], i0["status"])
+        assert t1 < 0.5 * t0, (la, t1, t0)
+
+
+def test_lookahead_ignores_a_late_stop_of_the_previous_call():
+    """A call that returns before its device stop (the stop lands within its
+    last lookahead chunks) writes the host word while the next call of the same
+    thread is running; the next call must not take that write for its own stop.
+    The first call goes through the C ABI without stats, so nothing waits for
+    it before the second begins (same stream)."""
+    import ctypes
+    f = torch.tensor(_img(64, 64, seed=22), dtype=torch.float32, device="cuda")
+    s1 = binding.Tv2dSolver(64, 64, torch.float32)
+    s2 = binding.Tv2dSolver(64, 64, torch.float32)
+    _, ref = s1.solve(f, 0.1, max_iter=500, gap_every=1, gap_tol=1e-4, lookahead=0)
+    k = ref["iters"]
+    assert ref["status"] == binding.TV_OK and k > 4
+    x_ref, _ = s2.solve(f, 0.1, max_iter=40, gap_every=1, lookahead=0)
+    xa = torch.empty_like(f)
+    lib = binding.load()
+    stream = ctypes.c_void_p(binding._stream_ptr(f.device))
+    for _ in range(3):
+        # stops at iteration k of k + 1: within the last 8 chunks, after the host loop has ended
+        opt = binding.Tv2dOptions(k + 1, 1, 1e-4, 1.0, 0, None, 0, 8)
+        assert lib.tv2d_solve(s1.code, binding._ptr(f), 64, 64, 64, 0.1, binding._ptr(xa), ctypes.byref(opt), None,
+                              binding._ptr(s1.ws), s1.nbytes, stream) == binding.TV_OK
+        xb, ib = s2.solve(f, 0.1, max_iter=40, gap_every=1, gap_tol=1e-12, lookahead=8)
+        assert ib["iters"] == 40 and ib["status"] == binding.TV_ERR_NOT_CONVERGED
+        assert torch.equal(xb, x_ref)
+        _, ia = s1.solve(f, 0.1, max_iter=0, resume=True)  # the first call's state: stopped at k
+        assert ia["iters"] == k
