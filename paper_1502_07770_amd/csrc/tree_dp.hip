@@ -31,27 +31,32 @@ struct TreeBatch {
     const int64_t *parent;   // [N] global parent index, -1 at each tree's root
 };
 
-struct TreeWs {
-    double *lam, *da, *db;  // arena [6 N + 16 T] (entries of tree t from 6 off[t] + 16 t)
-    int64_t *hstart;        // pending-message stack [N]: first breakpoint in the arena
-    int64_t *hcount;        //   number of breakpoints
-    int64_t *hreg;          //   start of the arena region the message owns (<= hstart)
-    int64_t *hparent;       //   node the message is for
-    double *hlo, *hhi;      //   clip levels (the message's flat ends)
-    double *llo, *lhi;      // [N] lambda^-, lambda^+ of each node's edge (root: x_root twice)
-    int *bad;               // set if a tree is not numbered in post-order
+// A breakpoint: lambda and the changes (da, db) of the linear piece to its
+// right.  Each record is one 32-byte block, so a lane's access to it is one
+// pair of 16-byte loads from a single cache line.
+struct alignas(32) TBp {
+    double l, a, b, pad;
+};
+// A pending message: its run [start, start + count) inside the region that
+// starts at reg, the node it is for, and its clip levels (flat ends).
+struct alignas(16) THdr {
+    int64_t start, count, reg, parent;
+    double lo, hi;
+};
+// lambda^-, lambda^+ of a node's edge (root: x_root twice).
+struct alignas(16) TLam {
+    double lo, hi;
 };
 
-// A breakpoint in registers.
-struct TBp {
-    double l, a, b;
+struct TreeWs {
+    TBp *ent;   // arena [6 N + 16 T] (entries of tree t from 6 off[t] + 16 t)
+    THdr *hdr;  // pending-message stack [N]
+    TLam *lam;  // [N]
+    int *bad;   // set if a tree is not numbered in post-order
 };
-__device__ __forceinline__ TBp tb_get(const TreeWs &W, int64_t i) { return TBp{W.lam[i], W.da[i], W.db[i]}; }
-__device__ __forceinline__ void tb_put(const TreeWs &W, int64_t i, const TBp &e) {
-    W.lam[i] = e.l;
-    W.da[i] = e.a;
-    W.db[i] = e.b;
-}
+
+__device__ __forceinline__ TBp tb_get(const TreeWs &W, int64_t i) { return W.ent[i]; }
+__device__ __forceinline__ void tb_put(const TreeWs &W, int64_t i, const TBp &e) { W.ent[i] = e; }
 
 // Moves cnt breakpoints from src to dst (overlap allowed), eight at a time with
 // every load of a group issued before its stores, so a group costs one memory
@@ -167,6 +172,56 @@ __device__ double tree_cross_right(const TreeWs &W, int64_t s, int64_t t, double
     return z;
 }
 
+// A node's inputs in FP64 and its parent.
+struct TIn {
+    double a, b, c, d, lo, hi;
+    int64_t p;
+};
+
+// Runs of at most this many breakpoints are merged by rank: both are loaded
+// at once and every entry goes straight to its place (an entry of the first
+// run after the second run's entries with a smaller lambda, one of the second
+// run after the first run's entries with a lambda at most its own, as the
+// sequential merge orders them), so a merge costs one memory latency rather
+// than one per entry.  The same bound selects the unary's insertion point
+// from parallel loads.
+constexpr int kRankMerge = 8;
+
+// Merge runs [cs, cs + ct) and [s, s + t) (1 <= ct, t <= kRankMerge) into
+// [dst, dst + ct + t); every load precedes every store, so dst may overlap
+// both runs.
+__device__ __forceinline__ void tree_rank_merge(const TreeWs &W, int64_t cs, int64_t ct, int64_t s, int64_t t,
+                                                int64_t dst) {
+    TBp U[kRankMerge], V[kRankMerge];
+#pragma unroll
+    for (int k = 0; k < kRankMerge; ++k)
+        if (k < ct) U[k] = tb_get(W, cs + k);
+#pragma unroll
+    for (int m = 0; m < kRankMerge; ++m)
+        if (m < t) V[m] = tb_get(W, s + m);
+    int64_t pu[kRankMerge], pv[kRankMerge];
+#pragma unroll
+    for (int k = 0; k < kRankMerge; ++k) {
+        int64_t pos = k;
+#pragma unroll
+        for (int m = 0; m < kRankMerge; ++m) pos += (k < ct && m < t && V[m].l < U[k].l) ? 1 : 0;
+        pu[k] = pos;
+    }
+#pragma unroll
+    for (int m = 0; m < kRankMerge; ++m) {
+        int64_t pos = m;
+#pragma unroll
+        for (int k = 0; k < kRankMerge; ++k) pos += (k < ct && m < t && U[k].l <= V[m].l) ? 1 : 0;
+        pv[m] = pos;
+    }
+#pragma unroll
+    for (int k = 0; k < kRankMerge; ++k)
+        if (k < ct) tb_put(W, dst + pu[k], U[k]);
+#pragma unroll
+    for (int m = 0; m < kRankMerge; ++m)
+        if (m < t) tb_put(W, dst + pv[m], V[m]);
+}
+
 // The working message of a node is the run [s, s + t) of its region [r, s + t)
 // (the front may float inside the region, so front pops and pushes move
 // nothing); the region ends at top = s + t, and the regions of pending
@@ -191,25 +246,50 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
     int64_t top = abase;                          // end of the pending stack's regions
     int64_t sp = n0;                              // header stack pointer
     bool ok = true;
+    // a node's inputs are loaded while the node before it is processed
+    auto load_in = [&](int64_t i) {
+        TIn q;
+        q.a = a ? (double)a[i] : 1.0;
+        q.b = (double)b[i];
+        q.c = c ? (double)c[i] : 0.0;
+        q.d = d ? (double)d[i] : 0.0;
+        q.lo = (double)wm[i];
+        q.hi = (double)wp[i];
+        q.p = tb.parent[i];
+        return q;
+    };
+    TIn nx = load_in(n0);
     for (int64_t i = n0; i < n1 && ok; ++i) {
+        const TIn in = nx;
+        if (i + 1 < n1) nx = load_in(i + 1);
         // (a) the children's messages: the top headers whose node is i, their
         // regions stacked right below the working one; the first is adopted in
         // place, each further one merged with it via the buffer at top
         double al = 0.0, bl = 0.0, ar = 0.0, br = 0.0;
         int64_t r = top, s = top, t = 0;
-        while (sp > n0 && W.hparent[sp - 1] == i) {
+        while (sp > n0) {
+            const THdr hd = W.hdr[sp - 1];
+            if (hd.parent != i) break;
             --sp;
-            const int64_t cs = W.hstart[sp], ct = W.hcount[sp], cr = W.hreg[sp];
+            const int64_t cs = hd.start, ct = hd.count, cr = hd.reg;
             if (cr < abase || cs < cr || cs + ct != r || top + ct + t > aend) {
                 ok = false;
                 break;
             }
-            bl += W.hlo[sp];
-            br += W.hhi[sp];
+            bl += hd.lo;
+            br += hd.hi;
             if (t == 0) {
                 r = cr;
                 s = cs;
                 t = ct;
+                continue;
+            }
+            if (ct <= kRankMerge && t <= kRankMerge) {
+                tree_rank_merge(W, cs, ct, s, t, cr);
+                r = cr;
+                s = cr;
+                t += ct;
+                top = s + t;
                 continue;
             }
             // merge run [cs, cs + ct) with run [s, s + t) into [top, top + ct + t)
@@ -239,10 +319,7 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
         if (!ok) break;
         top = s + t;
         // (b) add the unary
-        const double ai = a ? (double)a[i] : 1.0;
-        const double bi = (double)b[i];
-        const double ci = c ? (double)c[i] : 0.0;
-        const double di = d ? (double)d[i] : 0.0;
+        const double ai = in.a, bi = in.b, ci = in.c, di = in.d;
         al += ai;
         bl += -bi - ci;
         ar += ai;
@@ -250,7 +327,16 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
         if (ci > 0.0) {
             // insertion point: after every breakpoint <= d_i; the shorter side moves
             int64_t q = t;
-            while (q > 0 && W.lam[s + q - 1] > di) --q;
+            if (t <= kRankMerge) {
+                double l[kRankMerge];
+#pragma unroll
+                for (int j = 0; j < kRankMerge; ++j) l[j] = j < t ? W.ent[s + j].l : 0.0;
+                q = 0;
+#pragma unroll
+                for (int j = 0; j < kRankMerge; ++j) q += (j < t && l[j] <= di) ? 1 : 0;
+            } else {
+                while (q > 0 && W.ent[s + q - 1].l > di) --q;
+            }
             if (s > r && q < t - q) {
                 arena_move_n(W, s - 1, s, q);
                 --s;
@@ -261,17 +347,17 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
                 }
                 arena_move_n(W, s + q + 1, s + q, t - q);
             }
-            tb_put(W, s + q, TBp{di, 0.0, 2.0 * ci});
+            tb_put(W, s + q, TBp{di, 0.0, 2.0 * ci, 0.0});
             ++t;
             top = s + t;
         }
-        const int64_t p = tb.parent[i];
+        const int64_t p = in.p;
         int64_t k;
         double pa, pb;
         bool jump;
         if (p < 0) {  // root: the zero of h
             const double xr = tree_cross_left(W, s, t, al, bl, 0.0, &k, &pa, &pb, &jump);
-            W.llo[i] = W.lhi[i] = xr;
+            W.lam[i] = TLam{xr, xr};
             top = r;  // nothing stays pending for this root
             continue;
         }
@@ -280,7 +366,7 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
             break;
         }
         // (c) clip to [wm_i, wp_i]
-        const double lo = (double)wm[i], hi = (double)wp[i];
+        const double lo = in.lo, hi = in.hi;
         if (top + 2 > aend) {
             ok = false;
             break;
@@ -317,15 +403,9 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
         tb_put(W, s + t, TBp{lp, nda, ndb});
         ++t;
         top = s + t;
-        W.llo[i] = lm;
-        W.lhi[i] = lp < lm ? lm : lp;
+        W.lam[i] = TLam{lm, lp < lm ? lm : lp};
         // push the clipped message for the parent
-        W.hstart[sp] = s;
-        W.hcount[sp] = t;
-        W.hreg[sp] = r;
-        W.hparent[sp] = p;
-        W.hlo[sp] = lo;
-        W.hhi[sp] = hi;
+        W.hdr[sp] = THdr{s, t, r, p, lo, hi};
         ++sp;
     }
     if (!ok || sp != n0) {  // not a post-order numbering (or a tree left children pending)
@@ -336,47 +416,32 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
     for (int64_t i = n1 - 1; i >= n0; --i) {
         const int64_t p = tb.parent[i];
         double v;
+        const TLam L = W.lam[i];
         if (p < 0) {
-            v = W.llo[i];
+            v = L.lo;
         } else {
             v = (double)x[p];
-            v = v < W.llo[i] ? W.llo[i] : (v > W.lhi[i] ? W.lhi[i] : v);
+            v = v < L.lo ? L.lo : (v > L.hi ? L.hi : v);
         }
         x[i] = (T)v;
     }
 }
 
-// Workspace: arena 3 x (6 N + 16 T) doubles, headers 4 x N int64 + 2 x N
-// doubles, lambdas 2 x N doubles, flag.
+// Workspace: arena of 6 N + 16 T breakpoint records, the header stack and the
+// lambda pairs (one record per node each), flag.
 static size_t tree_layout(void *p, int64_t T, int64_t N, TreeWs *out) {
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t A = (size_t)(6 * N + 16 * T);
     size_t off = 0;
-    const size_t o_l = off;  off += al(sizeof(double) * A);
-    const size_t o_a = off;  off += al(sizeof(double) * A);
-    const size_t o_b = off;  off += al(sizeof(double) * A);
-    const size_t o_hs = off; off += al(sizeof(int64_t) * (size_t)N);
-    const size_t o_hc = off; off += al(sizeof(int64_t) * (size_t)N);
-    const size_t o_hr = off; off += al(sizeof(int64_t) * (size_t)N);
-    const size_t o_hp = off; off += al(sizeof(int64_t) * (size_t)N);
-    const size_t o_hl = off; off += al(sizeof(double) * (size_t)N);
-    const size_t o_hh = off; off += al(sizeof(double) * (size_t)N);
-    const size_t o_ll = off; off += al(sizeof(double) * (size_t)N);
-    const size_t o_lh = off; off += al(sizeof(double) * (size_t)N);
+    const size_t o_e = off;  off += al(sizeof(TBp) * A);
+    const size_t o_h = off;  off += al(sizeof(THdr) * (size_t)N);
+    const size_t o_l = off;  off += al(sizeof(TLam) * (size_t)N);
     const size_t o_bd = off; off += al(sizeof(int));
     if (p && out) {
         char *c = (char *)p;
-        out->lam = (double *)(c + o_l);
-        out->da = (double *)(c + o_a);
-        out->db = (double *)(c + o_b);
-        out->hstart = (int64_t *)(c + o_hs);
-        out->hcount = (int64_t *)(c + o_hc);
-        out->hreg = (int64_t *)(c + o_hr);
-        out->hparent = (int64_t *)(c + o_hp);
-        out->hlo = (double *)(c + o_hl);
-        out->hhi = (double *)(c + o_hh);
-        out->llo = (double *)(c + o_ll);
-        out->lhi = (double *)(c + o_lh);
+        out->ent = (TBp *)(c + o_e);
+        out->hdr = (THdr *)(c + o_h);
+        out->lam = (TLam *)(c + o_l);
         out->bad = (int *)(c + o_bd);
     }
     return off;
