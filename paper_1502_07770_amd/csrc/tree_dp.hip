@@ -172,6 +172,108 @@ __device__ double tree_cross_right(const TreeWs &W, int64_t s, int64_t t, double
     return z;
 }
 
+// tree_cross_left / tree_cross_right on a run of at most kRankMerge entries:
+// the run is loaded at once and scanned in registers with the same
+// arithmetic, in the same order, so the results are the same bits; the
+// crossed entry's increments come back in ja, jb when z is its jump.
+template <int N>
+__device__ __forceinline__ double tree_cross_left_short(const TreeWs &W, int64_t s, int64_t t, double A, double B,
+                                                        double v, int64_t *passed, double *pa, double *pb,
+                                                        bool *jump, double *ja, double *jb) {
+    TBp E[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (j < t) E[j] = tb_get(W, s + j);
+    bool done = false;
+    double z = 0.0, lprev = 0.0;
+    int64_t k = t;
+    *jump = false;
+    *ja = 0.0;
+    *jb = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (!done && j < t) {
+            const double l = E[j].l;
+            const double vl = A * l + B;
+            if (vl >= v) {
+                z = (v - B) / A;
+                z = z > l ? l : z;
+                if (j > 0 && z < lprev) z = lprev;
+                k = j;
+                done = true;
+            } else {
+                const double vr = vl + E[j].a * l + E[j].b;
+                if (vr >= v) {
+                    z = l;
+                    *jump = true;
+                    *ja = E[j].a;
+                    *jb = E[j].b;
+                    k = j;
+                    done = true;
+                } else {
+                    A += E[j].a;
+                    B += E[j].b;
+                    lprev = l;
+                }
+            }
+        }
+    }
+    if (!done) z = (v - B) / A;
+    *passed = k;
+    *pa = A;
+    *pb = B;
+    return z;
+}
+
+template <int N>
+__device__ __forceinline__ double tree_cross_right_short(const TreeWs &W, int64_t s, int64_t t, double A, double B,
+                                                         double v, int64_t *passed, double *pa, double *pb,
+                                                         bool *jump, double *ja, double *jb) {
+    TBp E[N];  // E[m]: entry t - 1 - m of the run
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+        if (m < t) E[m] = tb_get(W, s + t - 1 - m);
+    bool done = false;
+    double z = 0.0, lnext = 0.0;
+    int64_t k = t;
+    *jump = false;
+    *ja = 0.0;
+    *jb = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        if (!done && m < t) {
+            const double l = E[m].l;
+            const double vr = A * l + B;
+            if (vr <= v) {
+                z = (v - B) / A;
+                z = z < l ? l : z;
+                if (m > 0 && z > lnext) z = lnext;
+                k = m;
+                done = true;
+            } else {
+                const double vl = vr - (E[m].a * l + E[m].b);
+                if (vl <= v) {
+                    z = l;
+                    *jump = true;
+                    *ja = E[m].a;
+                    *jb = E[m].b;
+                    k = m;
+                    done = true;
+                } else {
+                    A -= E[m].a;
+                    B -= E[m].b;
+                    lnext = l;
+                }
+            }
+        }
+    }
+    if (!done) z = (v - B) / A;
+    *passed = k;
+    *pa = A;
+    *pb = B;
+    return z;
+}
+
 // A node's inputs in FP64 and its parent.
 struct TIn {
     double a, b, c, d, lo, hi;
@@ -371,12 +473,22 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
             ok = false;
             break;
         }
-        const double lm = tree_cross_left(W, s, t, al, bl, lo, &k, &pa, &pb, &jump);
+        double ja, jb;
+        double lm;
+        if (t <= kRankMerge) {
+            lm = tree_cross_left_short<kRankMerge>(W, s, t, al, bl, lo, &k, &pa, &pb, &jump, &ja, &jb);
+        } else {
+            lm = tree_cross_left(W, s, t, al, bl, lo, &k, &pa, &pb, &jump);
+            if (jump) {
+                const TBp e = tb_get(W, s + k);
+                ja = e.a;
+                jb = e.b;
+            }
+        }
         double nda = pa, ndb = pb - lo;
         if (jump) {
-            const TBp e = tb_get(W, s + k);
-            nda += e.a;
-            ndb += e.b;
+            nda += ja;
+            ndb += jb;
         }
         const int64_t drop = k + (jump ? 1 : 0);
         if (drop == 0) {  // a new front: room in the region, else shift right by one
@@ -391,13 +503,22 @@ __global__ __launch_bounds__(64) void k_tree_dp(TreeBatch tb, TreeWs W, const T 
             t -= drop - 1;
         }
         tb_put(W, s, TBp{lm, nda, ndb});
-        const double lp = tree_cross_right(W, s, t, ar, br, hi, &k, &pa, &pb, &jump);
+        double lp;
+        if (t <= kRankMerge) {
+            lp = tree_cross_right_short<kRankMerge>(W, s, t, ar, br, hi, &k, &pa, &pb, &jump, &ja, &jb);
+        } else {
+            lp = tree_cross_right(W, s, t, ar, br, hi, &k, &pa, &pb, &jump);
+            if (jump) {
+                const TBp e = tb_get(W, s + t - 1 - k);
+                ja = e.a;
+                jb = e.b;
+            }
+        }
         nda = -pa;
         ndb = hi - pb;
         if (jump) {
-            const TBp e = tb_get(W, s + t - 1 - k);
-            nda += e.a;
-            ndb += e.b;
+            nda += ja;
+            ndb += jb;
         }
         t -= k + (jump ? 1 : 0);
         tb_put(W, s + t, TBp{lp, nda, ndb});
