@@ -53,7 +53,8 @@ enum PlanKind {
     kPlanDp = 5,
     kPlanL1 = 6,
     kPlan2dRowL1 = 7,
-    kPlanKinds = 8
+    kPlan2dColL1 = 8,  // the TV-l1 solve's column (ROF dual) launch: deeper deques than ROF's
+    kPlanKinds = 9
 };
 
 // Process-wide tuning: target lanes per launch, shortest segment, halo.

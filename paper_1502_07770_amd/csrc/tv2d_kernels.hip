@@ -422,7 +422,7 @@ static size_t tv2d_layout(void *base, int64_t H, int64_t W, Tv2dWs<T> *out, bool
     // (TV-l1 rows keep (lambda, tag, jump) sets)
     const size_t sr = l1 ? seg_bytes_max<double, TagJ<double>>(H, W, kPlan2dRowL1)  // FP64 set (WideL1)
                          : seg_bytes_max<T>(H, W, kPlan2dRow);
-    const size_t scol = seg_bytes_max<T>(W, H, kPlan2dCol);
+    const size_t scol = seg_bytes_max<T>(W, H, l1 ? kPlan2dColL1 : kPlan2dCol);
     const size_t nparts = (size_t)H;
     const size_t ncol = (size_t)(((H + kGapRows - 1) / kGapRows) * W);
     size_t off = 0;
@@ -767,7 +767,7 @@ static tv_status tv2d_l1_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, d
     tv2d_layout<T>(workspace, H, W, &ws, true);
     tv_status s = tv2d_l1_init<T>(f, H, W, ld, opt->tau0, ws, st);
     if (s != TV_OK) return s;
-    const SegPlan pc = seg_plan(W, H, kPlan2dCol), pr = seg_plan(H, W, kPlan2dRowL1);
+    const SegPlan pc = seg_plan(W, H, kPlan2dColL1), pr = seg_plan(H, W, kPlan2dRowL1);
     if (seg_ws_bytes_plan<T>(W, H, pc) > ws.seg_bytes || seg_ws_bytes_plan<double, TagJ<double>>(H, W, pr) > ws.seg_bytes)
         return TV_ERR_WORKSPACE;
     const int every = opt->gap_every > 0 ? opt->gap_every : 1;
@@ -797,7 +797,7 @@ static tv_status tv2d_l1_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld
     tv_status s = tv2d_l1_init<T>(f, H, W, ld, tau0, ws, st);
     if (s != TV_OK) return s;
     // a few iterations first, so the plans are timed on later-iteration data
-    const SegPlan pc0 = seg_plan(W, H, kPlan2dCol), pr0 = seg_plan(H, W, kPlan2dRowL1);
+    const SegPlan pc0 = seg_plan(W, H, kPlan2dColL1), pr0 = seg_plan(H, W, kPlan2dRowL1);
     for (int k = 0; k < kTuneWarm; ++k) {
         if (tv2d_col_step<T>(ws, H, W, lam, k & 1, ws.sched, pc0, st) != hipSuccess) return TV_ERR_HIP;
         if (tv2d_l1_row_step<T>(ws, f, ld, H, W, lam, k & 1, ws.sched, pr0, st) != hipSuccess) return TV_ERR_HIP;
@@ -813,7 +813,7 @@ static tv_status tv2d_l1_autotune_t(const T *f, int64_t H, int64_t W, int64_t ld
         [&](const SegPlan &p) { return tv2d_l1_row_step<T>(ws, f, ld, H, W, lam, 0, ws.sched, p, st); }, st, &pr,
         row);
     if (s != TV_OK) return s;
-    seg_set_tuned(kPlan2dCol, W, H, pc);
+    seg_set_tuned(kPlan2dColL1, W, H, pc);
     seg_set_tuned(kPlan2dRowL1, H, W, pr);
     return hipStreamSynchronize(st) == hipSuccess ? TV_OK : TV_ERR_HIP;
 }
