@@ -433,39 +433,28 @@ __device__ __forceinline__ bool dp_step_ring_general(CRing<T, K, G> &R, const St
     return tn < K;
 }
 
-// One step on the LDS ring.  Deques of fewer than kRingCopies breakpoints
-// (sentinel included, all in copied slots) are read in one window from the
-// head at fixed offsets and scanned branch-free; deeper ones take the
-// two-ended scan.  The root step is the same step with a zero leaving edge
-// (its deque update is never used).  Returns false if the ring cannot hold
-// the new deque and its sentinel.
-template <typename T, typename G, int K, bool kGen>
-__device__ __forceinline__ bool dp_step_ring(CRing<T, K, G> &R, const StepIn<T, G> &in, T &lm, T &lp) {
+// The windowed step: every lane's deque has 1 .. WN - 1 breakpoints, all of
+// them and the sentinel in copied slots, read in one window from the head at
+// fixed offsets and scanned branch-free.
+template <typename T, typename G, int K, bool kGen, int WN>
+__device__ __forceinline__ bool dp_step_window(CRing<T, K, G> &R, const StepIn<T, G> &in, T &lm, T &lp) {
     using E = Ent<T, G>;
-    constexpr int M = kRingCopies;
     const EndSlope<T, G, kGen> es(in.sf, in.sprev);
     const T lo = in.lo, hi = in.hi;
     const T c = in.lop - in.yi;
-    const int t = R.size;
     DqScan<T> sc;
     E E0, E1, G0, G1;
     G tnew;
-    // Almost always every lane of the wave holds 1 .. M - 1 breakpoints: one
-    // window and no selects for an empty deque, decided once for the wave.
-    // Otherwise (a run's first node, or a deque deeper than the window in
-    // some lane) every lane takes the general step, whose front walk for the
-    // shallow lanes gives the window's bits.
-    if (__ballot((t == 0) | (t >= M))) return dp_step_ring_general<T, G, K, kGen>(R, in, lm, lp);
     {
         const E *fp = R.col + R.head * 64;
-        E F[M];
+        E F[WN];
 #pragma unroll
-        for (int j = 0; j < M; ++j) F[j] = fp[j * 64];
+        for (int j = 0; j < WN; ++j) F[j] = fp[j * 64];
         T v = es.mul(F[0].l) + c;
         sc = DqScan<T>{0, 0, v, v};
         dq_count(sc, 0, v, lo, hi);
 #pragma unroll
-        for (int j = 1; j < M; ++j) {
+        for (int j = 1; j < WN; ++j) {
             v = fmav(slope_of<T, G>(in.sf, F[j - 1].k), F[j].l - F[j - 1].l, v);
             dq_count(sc, j, v, lo, hi);
         }
@@ -481,6 +470,33 @@ __device__ __forceinline__ bool dp_step_ring(CRing<T, K, G> &R, const StepIn<T, 
     const int tn = dq_update<T, G>(A, sc, in.sf, lm, lp, tnew);
     R.size = tn < K ? tn : K;
     return tn < K;
+}
+
+// One step on the LDS ring.  Deques of fewer than kRingCopies breakpoints
+// (sentinel included, all in copied slots) are read in one window from the
+// head at fixed offsets and scanned branch-free; in a ring whose every slot is
+// copied (kAll), deques of up to 2 kRingCopies - 1 breakpoints take a window
+// twice as wide, the same front walk without its branches.  Deeper ones take
+// the two-ended scan.  The root step is the same step with a zero leaving
+// edge (its deque update is never used).  Returns false if the ring cannot
+// hold the new deque and its sentinel.
+template <typename T, typename G, int K, bool kGen>
+__device__ __forceinline__ bool dp_step_ring(CRing<T, K, G> &R, const StepIn<T, G> &in, T &lm, T &lp) {
+    constexpr int M = kRingCopies;
+    const int t = R.size;
+    // Almost always every lane of the wave holds 1 .. M - 1 breakpoints: one
+    // window and no selects for an empty deque, decided once for the wave.
+    // Otherwise (a run's first node, or a deque deeper than the window in
+    // some lane) the wider window if it holds every lane's deque, else every
+    // lane takes the general step, whose front walk for the shallow lanes
+    // gives the window's bits.
+    if (__ballot((t == 0) | (t >= M))) {
+        if constexpr (CRing<T, K, G>::kAll && K >= 2 * M) {
+            if (!__ballot((t == 0) | (t >= 2 * M))) return dp_step_window<T, G, K, kGen, 2 * M>(R, in, lm, lp);
+        }
+        return dp_step_ring_general<T, G, K, kGen>(R, in, lm, lp);
+    }
+    return dp_step_window<T, G, K, kGen, M>(R, in, lm, lp);
 }
 
 // The same step with the deque in HBM (the exact fallback for deques that

@@ -65,7 +65,7 @@ struct BColProb {
             p.xb = xb[o];
             return p;
         }
-        __device__ __forceinline__ T data(const Pre &p) const { return p.y + sigma * p.xb; }
+        __device__ __forceinline__ T data(const Pre &p) const { return col_eta<T>(p.y, sigma, p.xb); }
         __device__ __forceinline__ T weight(const Pre &) const { return lam; }
         static constexpr bool vec = false;  // lanes of a wave already read consecutive columns
         __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
@@ -85,7 +85,7 @@ struct BColProb {
             return p;
         }
         __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
-            yn[base + i * es] = (p.y + sigma * p.xb) - u;
+            yn[base + i * es] = col_dual<T>(p.y, sigma, p.xb, u);
         }
         static constexpr bool vec = false;
         __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const {
@@ -181,11 +181,11 @@ struct BRowProb {
         }
         __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
             xn[base + i] = u;
-            xb[base + i] = u + theta * (u - p.x);
+            xb[base + i] = row_xbar<T>(u, theta, p.x);
         }
         __device__ __forceinline__ void store4(int64_t i, const T (&u)[4], const SinkPre (&p)[4]) const {
             T b[4];
-            for (int k = 0; k < 4; ++k) b[k] = u[k] + theta * (u[k] - p[k].x);
+            for (int k = 0; k < 4; ++k) b[k] = row_xbar<T>(u[k], theta, p[k].x);
             vstore4(xn + base + i, u);
             vstore4(xb + base + i, b);
         }

@@ -126,11 +126,40 @@ static inline double wall_clock_khz() {
     return (double)khz;
 }
 
-// b_i of the row step; shared by the row chain source and the gap kernel so
-// both see bit-identical values.
+// The elementwise updates of the iteration, each rounded operation by
+// operation as written (no multiply-add contraction, whichever kernel inlines
+// them): the chain kernels' sources and sinks and the gap kernels then see the
+// same bits for the same inputs in every build.
+//
+// b_i of the row step; shared by the row chain source and the gap kernel.
 template <typename T>
 __device__ __forceinline__ T row_data(T f, T x, T y, T tau, T inv1p) {
+#pragma clang fp contract(off)
     return (tau * f + x - tau * y) * inv1p;
+}
+// eta_i = y_i + sigma xbar_i of the column step (its source and its sink).
+template <typename T>
+__device__ __forceinline__ T col_eta(T y, T sigma, T xb) {
+#pragma clang fp contract(off)
+    return y + sigma * xb;
+}
+// y'_i = eta_i - u_i (Moreau identity) of the column step's sink.
+template <typename T>
+__device__ __forceinline__ T col_dual(T y, T sigma, T xb, T u) {
+#pragma clang fp contract(off)
+    return col_eta<T>(y, sigma, xb) - u;
+}
+// xbar'_i = x'_i + theta (x'_i - x_i) of the row step's sink.
+template <typename T>
+__device__ __forceinline__ T row_xbar(T u, T theta, T x) {
+#pragma clang fp contract(off)
+    return u + theta * (u - x);
+}
+// The TV-l1 row step's chain data x_i - tau y_i.
+template <typename T>
+__device__ __forceinline__ T l1_row_data(T x, T tau, T y) {
+#pragma clang fp contract(off)
+    return x - tau * y;
 }
 
 // Store a clipped dual value in precision T, rounded toward zero so that the

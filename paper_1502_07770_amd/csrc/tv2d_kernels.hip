@@ -72,7 +72,7 @@ struct ColProb {
             p.xb = xb[o];
             return p;
         }
-        __device__ __forceinline__ T data(const Pre &p) const { return p.y + sigma * p.xb; }
+        __device__ __forceinline__ T data(const Pre &p) const { return col_eta<T>(p.y, sigma, p.xb); }
         __device__ __forceinline__ T weight(const Pre &) const { return lam; }
         static constexpr bool vec = false;  // lanes of a wave already read consecutive columns
         __device__ __forceinline__ void load4(int64_t i, Pre *o) const {
@@ -92,7 +92,7 @@ struct ColProb {
             return p;
         }
         __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
-            yn[i * W + c] = (p.y + sigma * p.xb) - u;
+            yn[i * W + c] = col_dual<T>(p.y, sigma, p.xb, u);
         }
         static constexpr bool vec = false;
         __device__ __forceinline__ void load4(int64_t i, SinkPre *o) const {
@@ -189,11 +189,11 @@ struct RowProb {
         }
         __device__ __forceinline__ void store(int64_t i, T u, const SinkPre &p) const {
             xn[r * W + i] = u;
-            xb[r * W + i] = u + theta * (u - p.x);
+            xb[r * W + i] = row_xbar<T>(u, theta, p.x);
         }
         __device__ __forceinline__ void store4(int64_t i, const T (&u)[4], const SinkPre (&p)[4]) const {
             T b[4];
-            for (int k = 0; k < 4; ++k) b[k] = u[k] + theta * (u[k] - p[k].x);
+            for (int k = 0; k < 4; ++k) b[k] = row_xbar<T>(u[k], theta, p[k].x);
             vstore4(xn + r * W + i, u);
             vstore4(xb + r * W + i, b);
         }
@@ -633,7 +633,7 @@ struct RowL1Prob {
     struct Src : RowProb<T>::Src {
         using Base = typename RowProb<T>::Src;
         __device__ __forceinline__ Src(const Base &b) : Base(b) {}
-        __device__ __forceinline__ T data(const Pre &p) const { return p.x - this->tau * p.y; }
+        __device__ __forceinline__ T data(const Pre &p) const { return l1_row_data<T>(p.x, this->tau, p.y); }
         __device__ __forceinline__ T dval(const Pre &p) const { return p.f; }
         __device__ __forceinline__ T cval(const Pre &) const { return this->tau; }
         __device__ __forceinline__ T weight(const Pre &) const { return this->w; }
