@@ -84,7 +84,10 @@ constexpr int kCheckpoints = 4;  // first-pass deques saved at a + CK, 2 CK, 4 C
 constexpr int kSaves = 3 + kCheckpoints;  // HS, CK..., ES, ES2
 // Ring slots stored twice (slot m < kRingCopies also at m + K): the step reads
 // the first kRingCopies entries of a deque at fixed offsets from its head.
+// Rings of 8-byte entries copy twice as many (or every slot), so that a
+// window twice as wide needs no wrap either.
 constexpr int kRingCopies = 8;
+template <class E> constexpr int ring_copies() { return sizeof(E) <= 8 ? 2 * kRingCopies : kRingCopies; }
 // Nodes the backward sweep loads ahead of their use.
 constexpr int kSweepTile = 16;
 // Lanes (each with a 2n + 4 entry HBM deque) for chains that overflow the ring.
@@ -192,14 +195,15 @@ __device__ __forceinline__ bool saved_equal(const CRing<T, K, G> &R, const Ent<T
 template <typename T, int K, typename G>
 struct CRing {
     static_assert((K & (K - 1)) == 0, "ring size must be a power of two");
-    static_assert(kRingCopies <= K, "the copied slots are ring slots");
     using E = Ent<T, G>;
     // Small rings of 8-byte entries copy every slot (2K rows: a copy is one
     // more store at a fixed offset, no address select); others only the first
-    // kRingCopies.
+    // kCopies.
     static constexpr bool kAll = (K <= 16 && sizeof(E) <= 8);
+    static constexpr int kCopies = kAll ? K : ring_copies<E>();
+    static_assert(kCopies <= K, "the copied slots are ring slots");
     // slot rows of the per-wave LDS array (64 entries each)
-    static constexpr int kRows = kAll ? 2 * K : K + kRingCopies;
+    static constexpr int kRows = kAll ? 2 * K : K + kCopies;
     E *col;  // this lane's column: slot m at col[m * 64], its copy at col[(m + K) * 64]
     int head, size;
 
@@ -215,7 +219,7 @@ struct CRing {
         if constexpr (kAll)
             col[(m + K) * 64] = e;
         else
-            col[(m < kRingCopies ? m + K : m) * 64] = e;  // other slots: the same slot again
+            col[(m < kCopies ? m + K : m) * 64] = e;  // other slots: the same slot again
     }
     // The slot after the back holds a +inf breakpoint (dp_step_ring's
     // sentinel; the TV-l1 sets never read it).  A full ring has no such slot.
@@ -474,9 +478,9 @@ __device__ __forceinline__ bool dp_step_window(CRing<T, K, G> &R, const StepIn<T
 
 // One step on the LDS ring.  Deques of fewer than kRingCopies breakpoints
 // (sentinel included, all in copied slots) are read in one window from the
-// head at fixed offsets and scanned branch-free; in a ring whose every slot is
-// copied (kAll), deques of up to 2 kRingCopies - 1 breakpoints take a window
-// twice as wide, the same front walk without its branches.  Deeper ones take
+// head at fixed offsets and scanned branch-free; in a ring with twice as many
+// copied slots (8-byte entries), deques of up to 2 kRingCopies - 1 breakpoints
+// take a window twice as wide, the same front walk without its branches.  Deeper ones take
 // the two-ended scan.  The root step is the same step with a zero leaving
 // edge (its deque update is never used).  Returns false if the ring cannot
 // hold the new deque and its sentinel.
@@ -491,7 +495,7 @@ __device__ __forceinline__ bool dp_step_ring(CRing<T, K, G> &R, const StepIn<T, 
     // lane takes the general step, whose front walk for the shallow lanes
     // gives the window's bits.
     if (__ballot((t == 0) | (t >= M))) {
-        if constexpr (CRing<T, K, G>::kAll && K >= 2 * M) {
+        if constexpr (CRing<T, K, G>::kCopies >= 2 * M) {
             if (!__ballot((t == 0) | (t >= 2 * M))) return dp_step_window<T, G, K, kGen, 2 * M>(R, in, lm, lp);
         }
         return dp_step_ring_general<T, G, K, kGen>(R, in, lm, lp);
@@ -1359,7 +1363,9 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
 // l).  Both paths compute the same results as the segmented one.
 // ---------------------------------------------------------------------------
 template <class E> struct OvfRing {
-    static constexpr int fit(int k) { return (k + kRingCopies) * 64 * (int)sizeof(E) <= 163840 ? k : fit(k / 2); }
+    static constexpr int fit(int k) {
+        return (k + ring_copies<E>()) * 64 * (int)sizeof(E) <= 163840 ? k : fit(k / 2);
+    }
     static constexpr int K = fit(512);
 };
 
@@ -1507,7 +1513,7 @@ hipError_t seg_launch(const WsOf<T, Prob> &ws, const typename Prob::Params &pp, 
 }
 
 // Ring sizes a launch may use: 16 and 32 slots, and 64 or 128 for 8-byte
-// entries (35 / 68 KiB rings per wave; gfx950 gives a workgroup up to 160 KiB).
+// entries (40 / 72 KiB rings per wave; gfx950 gives a workgroup up to 160 KiB).
 template <typename T, typename G>
 constexpr int ring_max() {
     return sizeof(Ent<T, G>) <= 8 ? 128 : 32;
