@@ -238,6 +238,40 @@ def test_segmented_is_bitwise_sequential(tuning, dtype, wval):
     _check_rows(yv, ref.astype(np.float64), oracle.chain_prox(yv, w_scalar=wval), TOL[dtype])
 
 
+@pytest.mark.parametrize("ring", [16, 32])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_window_widths_give_the_same_bits(tuning, ring, dtype):
+    """Square-root ramps with w in [0.2, 0.8] keep 8 to 15 breakpoints alive,
+    next to shallow piecewise-constant chains in the same waves: in FP32 those
+    waves take the 16-entry window (rings of 8-byte entries), FP64 the general
+    step.  Segmented runs equal the one-segment-per-chain run bit for bit, for
+    16- and 32-slot rings, and the oracle within the bar."""
+    n = 1024
+    rows, ws = [], []
+    pc = synth.piecewise_constant(96, n, seed=33)
+    for k in range(96):
+        if k % 3 == 0:
+            rows.append(pc[k])
+            ws.append(0.1)
+        else:
+            rows.append(np.sqrt(np.arange(n) + 5 * k))
+            ws.append((0.2, 0.3, 0.5, 0.8)[k % 4])
+    y = np.array(rows)
+    w = np.repeat(np.array(ws)[:, None], n, axis=1)
+    _, st = oracle.chain_prox(y, w=w, counts=True)
+    deep = st[:, 2]
+    assert ((deep >= 8) & (deep <= 15)).sum() >= 48 and deep.min() < 8
+    tuning(target_lanes=1, min_segment=1, ring_slots=ring)
+    ref = _solve(y, w, dtype)
+    for min_seg in (32, 128):
+        tuning(target_lanes=1 << 30, min_segment=min_seg, ring_slots=ring)
+        got = _solve(y, w, dtype)
+        assert np.array_equal(got, ref), (min_seg, np.abs(got - ref).max())
+    yv = _dev(y, dtype).cpu().double().numpy()
+    wv = _dev(w, dtype).cpu().double().numpy()
+    _check_rows(yv, ref.astype(np.float64), oracle.chain_prox(yv, w=wv), TOL[dtype])
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_segmented_columns_edge_weights_and_overflow(tuning, dtype):
     """Column layout, per-edge weights, and chains whose deques overflow the
