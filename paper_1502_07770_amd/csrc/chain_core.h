@@ -29,6 +29,13 @@
 
 namespace tvc {
 
+// Every rounded operation of the DP is the one written: no multiply-add
+// contraction (FMAs are explicit), so each step rounds the same in every
+// kernel that inlines it and in every build, which the bit-for-bit comparison
+// of segment states and the segmented = sequential results rely on.
+#pragma clang fp contract(off)
+
+
 template <typename T> __device__ __forceinline__ T recip(T v);
 template <> __device__ __forceinline__ float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double recip<double>(double v) { return 1.0 / v; }
@@ -106,4 +113,5 @@ struct EndSlope {
     }
 };
 
+#pragma clang fp contract(fast)
 }  // namespace tvc

@@ -28,6 +28,13 @@
 
 namespace tvc {
 
+// Every rounded operation of the DP is the one written: no multiply-add
+// contraction (FMAs are explicit), so each step rounds the same in every
+// kernel that inlines it and in every build, which the bit-for-bit comparison
+// of segment states and the segmented = sequential results rely on.
+#pragma clang fp contract(off)
+
+
 // Slope tag and value jump of a TV-l1 breakpoint.
 template <typename T>
 struct TagJ {
@@ -247,4 +254,5 @@ __device__ __forceinline__ void l1_step(St &S, T s, T yi, T di, T ci, T lop, T h
     lp = lp < lm ? lm : lp;
 }
 
+#pragma clang fp contract(fast)
 }  // namespace tvc

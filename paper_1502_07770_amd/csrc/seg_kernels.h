@@ -51,6 +51,13 @@
 
 namespace tvc {
 
+// Every rounded operation of the DP is the one written: no multiply-add
+// contraction (FMAs are explicit), so each step rounds the same in every
+// kernel that inlines it and in every build, which the bit-for-bit comparison
+// of segment states and the segmented = sequential results rely on.
+#pragma clang fp contract(off)
+
+
 template <typename T>
 struct alignas(2 * sizeof(T)) LamPair {
     T lo, hi;
@@ -1569,4 +1576,5 @@ hipError_t seg_run(void *workspace, int64_t C, int64_t n, const SegPlan &p, cons
     return seg_launch<T, Prob, 16, P>(ws, pp, stream);
 }
 
+#pragma clang fp contract(fast)
 }  // namespace tvc
