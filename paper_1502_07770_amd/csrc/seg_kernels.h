@@ -91,10 +91,15 @@ constexpr int kCheckpoints = 4;  // first-pass deques saved at a + CK, 2 CK, 4 C
 constexpr int kSaves = 3 + kCheckpoints;  // HS, CK..., ES, ES2
 // Ring slots stored twice (slot m < kRingCopies also at m + K): the step reads
 // the first kRingCopies entries of a deque at fixed offsets from its head.
-// Rings of 8-byte entries copy twice as many (or every slot), so that a
-// window twice as wide needs no wrap either.
+// The rings of the TV deque (tags in the working precision) copy twice as
+// many, so that a window twice as wide needs no wrap either: the 2D
+// iterations' deques often hold 8 to 15 breakpoints.  The general DP's FP32
+// rings (FP64 prefix-sum tags, 16-byte entries, shallow deques) and the TV-l1
+// sets (TagJ entries, which no window reads) keep kRingCopies.
 constexpr int kRingCopies = 8;
-template <class E> constexpr int ring_copies() { return sizeof(E) <= 8 ? 2 * kRingCopies : kRingCopies; }
+template <typename T, typename G> constexpr int ring_copies() {
+    return std::is_same<T, G>::value ? 2 * kRingCopies : kRingCopies;
+}
 // Nodes the backward sweep loads ahead of their use.
 constexpr int kSweepTile = 16;
 // Lanes (each with a 2n + 4 entry HBM deque) for chains that overflow the ring.
@@ -207,7 +212,7 @@ struct CRing {
     // more store at a fixed offset, no address select); others only the first
     // kCopies.
     static constexpr bool kAll = (K <= 16 && sizeof(E) <= 8);
-    static constexpr int kCopies = kAll ? K : ring_copies<E>();
+    static constexpr int kCopies = kAll ? K : ring_copies<T, G>();
     static_assert(kCopies <= K, "the copied slots are ring slots");
     // slot rows of the per-wave LDS array (64 entries each)
     static constexpr int kRows = kAll ? 2 * K : K + kCopies;
@@ -486,8 +491,9 @@ __device__ __forceinline__ bool dp_step_window(CRing<T, K, G> &R, const StepIn<T
 // One step on the LDS ring.  Deques of fewer than kRingCopies breakpoints
 // (sentinel included, all in copied slots) are read in one window from the
 // head at fixed offsets and scanned branch-free; in a ring with twice as many
-// copied slots (8-byte entries), deques of up to 2 kRingCopies - 1 breakpoints
-// take a window twice as wide, the same front walk without its branches.  Deeper ones take
+// copied slots (every deque ring), deques of up to 2 kRingCopies - 1
+// breakpoints take a window twice as wide, the same front walk without its
+// branches.  Deeper ones take
 // the two-ended scan.  The root step is the same step with a zero leaving
 // edge (its deque update is never used).  Returns false if the ring cannot
 // hold the new deque and its sentinel.
@@ -1369,16 +1375,17 @@ __device__ bool fix_chain(const WsOf<T, Prob> &ws, const typename Prob::Params &
 // deque outgrows that too, with the deque in HBM (lane l owns deque storage
 // l).  Both paths compute the same results as the segmented one.
 // ---------------------------------------------------------------------------
-template <class E> struct OvfRing {
+template <typename T, typename G> struct OvfRing {
+    using E = Ent<T, G>;
     static constexpr int fit(int k) {
-        return (k + ring_copies<E>()) * 64 * (int)sizeof(E) <= 163840 ? k : fit(k / 2);
+        return (k + ring_copies<T, G>()) * 64 * (int)sizeof(E) <= 163840 ? k : fit(k / 2);
     }
     static constexpr int K = fit(512);
 };
 
 template <typename T, class Prob>
 __global__ __launch_bounds__(64) void k_seg_ovf(WsOf<T, Prob> ws, typename Prob::Params pp) {
-    constexpr int KB = OvfRing<EntOf<T, Prob>>::K;
+    constexpr int KB = OvfRing<T, typename Prob::Tag>::K;
     __shared__ EntOf<T, Prob> s_big[CRing<T, KB, typename Prob::Tag>::kRows * 64];
     if (seg_stopped(ws)) return;
     const int lane = threadIdx.x;
