@@ -1002,7 +1002,7 @@ def main():
     ap.add_argument("--rocprof-summary", metavar="DIR")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--c4-iters", type=int, metavar="N",
-                    help="run the C4 batch's autotune and N iterations only (for profiling runs)")
+                    help="run the batched line's autotune and N iterations only (for profiling runs)")
     ap.add_argument("--plan", metavar="L,H,K",
                     help="fixed plan for the headline launch (segment length, halo, ring slots) instead of the "
                          "autotuner's: for profiling runs that must launch exactly the plan the default run picks")
