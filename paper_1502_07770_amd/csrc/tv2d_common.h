@@ -270,9 +270,17 @@ inline StopMirror *stop_mirror() {
         if (hipHostMalloc(&p, 256, hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent) !=
             hipSuccess)
             return nullptr;
-        if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess) return nullptr;
-        for (auto &e : s.ev)
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        int made = 0;
+        bool ok = hipHostGetDevicePointer(&dp, p, 0) == hipSuccess;
+        while (ok && made < kMaxLookahead) {
+            ok = hipEventCreateWithFlags(&s.ev[made], hipEventDisableTiming) == hipSuccess;
+            if (ok) ++made;
+        }
+        if (!ok) {  // leave nothing half set up: a later call starts afresh
+            for (int j = 0; j < made; ++j) (void)hipEventDestroy(s.ev[j]);
+            (void)hipHostFree(p);
+            return nullptr;
+        }
         *(volatile uint32_t *)p = 0;
         s.host = (uint32_t *)p;
         s.dev = (uint32_t *)dp;
