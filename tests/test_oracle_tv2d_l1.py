@@ -71,3 +71,44 @@ def test_shift_invariance():
     x, _ = oracle.tv2d_l1(f, 0.5, max_iter=50)
     xs, _ = oracle.tv2d_l1(f + 0.375, 0.5, max_iter=50)
     assert np.abs(xs - (x + 0.375)).max() <= 1e-12
+
+
+def test_single_row_iterates_are_tv_l1_chain_proxes(orc):
+    """One row: every column chain is one node (prox = identity), so the dual
+    iterate stays 0 and each iteration is the TV-l1 chain prox of the row,
+    x^{k+1} = prox of (1/2)|x - x^k|^2 + tau lam TV(x) + tau |x - f|, i.e.
+    orc.chain_prox_l1 with y = x^k, d = f, w = tau lam, c = tau (pinned by
+    brute force in its own tests)."""
+    rng = np.random.default_rng(41)
+    f = np.repeat(rng.uniform(0, 1, 16), 10)[None, :]
+    m = rng.random(f.shape) < 0.25
+    f[m] = rng.integers(0, 2, int(m.sum()))
+    lam, tau = 0.55, 0.7
+    x = f[0].copy()
+    for k in range(4):
+        x = orc.chain_prox_l1(x, f[0], w_scalar=tau * lam, c_scalar=tau)
+        xo, _ = orc.tv2d_l1(f, lam, tau=tau, max_iter=k + 1)
+        assert np.abs(xo[0] - x).max() <= 1e-12, k
+
+
+def test_single_column_iterates_soft_threshold_toward_f(orc):
+    """One column: every row chain is one node, whose TV-l1 prox is the
+    soft-threshold of xi toward f by tau; the dual step is the Moreau identity
+    of the column's TV prox with sigma = 1/tau and xbar' = 2 x' - x."""
+    rng = np.random.default_rng(42)
+    col = np.repeat(rng.uniform(0, 1, 15), 10)
+    m = rng.random(col.shape) < 0.25
+    col[m] = rng.integers(0, 2, int(m.sum()))
+    f = col[:, None].copy()
+    lam, tau = 0.4, 0.8
+    sigma = 1.0 / tau
+    x, xbar, y = col.copy(), col.copy(), np.zeros_like(col)
+    for k in range(4):
+        eta = y + sigma * xbar
+        y = eta - orc.chain_prox(eta, w_scalar=lam)
+        xi = x - tau * y
+        xn = col + np.sign(xi - col) * np.maximum(np.abs(xi - col) - tau, 0.0)
+        xbar = 2.0 * xn - x
+        x = xn
+        xo, _ = orc.tv2d_l1(f, lam, tau=tau, max_iter=k + 1)
+        assert np.abs(xo[:, 0] - x).max() <= 1e-12, k
