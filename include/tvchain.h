@@ -442,8 +442,10 @@ typedef struct {
                             costs at most this many chunks of launches that return
                             at once; the call then returns when the device is within
                             this many chunks of the end of what it enqueued.
-                            Results are the same either way.  Ignored by
-                            tv2d_l1_solve, which has no stopping test. */
+                            Results are the same either way.  A stream being
+                            captured into a graph takes 0 only (otherwise
+                            TV_ERR_INVALID_ARG).  Ignored by tv2d_l1_solve,
+                            which has no stopping test. */
 } tv2d_options;
 
 /* [DEVICE] Result of a 2D solve, written by the solve's last kernel on the

@@ -619,7 +619,8 @@ static tv_status batched_solve_t(const BGeom &g, const int64_t *H, const int64_t
     BWs<T> ws;
     batched_layout<T>(workspace, g, &ws);
     Lookahead la;
-    if (!la.begin(opt->lookahead)) return TV_ERR_HIP;
+    const tv_status ls = la.begin(opt->lookahead, st);
+    if (ls != TV_OK) return ls;
     const tv_status s0 = batched_setup<T>(g, H, W, pix, lam, f, opt->tau0, ws, st, la.dev_word(), la.seq);
     if (s0 != TV_OK) return s0;
     const unsigned nb = (unsigned)((g.total + 255) / 256);

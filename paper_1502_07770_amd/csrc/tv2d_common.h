@@ -293,15 +293,19 @@ struct Lookahead {
     int depth = 0;
     uint32_t seq = 0;
     int n = 0;  // chunks enqueued
-    // Returns false if the host resources cannot be set up.
-    bool begin(int lookahead) {
+    // TV_OK, TV_ERR_INVALID_ARG when `st` is being captured into a graph (the
+    // host cannot wait on work that does not run yet), or TV_ERR_HIP.
+    tv_status begin(int lookahead, hipStream_t st) {
         depth = lookahead;
-        if (depth <= 0) return true;
+        if (depth <= 0) return TV_OK;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess) return TV_ERR_HIP;
+        if (cs != hipStreamCaptureStatusNone) return TV_ERR_INVALID_ARG;
         m = stop_mirror();
-        if (!m) return false;
+        if (!m) return TV_ERR_HIP;
         seq = ++m->seq;
         if (seq == 0) seq = ++m->seq;  // 0 is never a call's number
-        return true;
+        return TV_OK;
     }
     uint32_t *dev_word() const { return m ? m->dev : nullptr; }
     // Before enqueuing the next chunk: true once the device has stopped.

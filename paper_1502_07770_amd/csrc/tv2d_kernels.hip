@@ -523,7 +523,8 @@ static tv_status tv2d_solve_t(const T *f, int64_t H, int64_t W, int64_t ld, doub
     tv2d_layout<T>(workspace, H, W, &ws);
     const unsigned nb = (unsigned)((H * W + 255) / 256);
     Lookahead la;
-    if (!la.begin(opt->lookahead)) return TV_ERR_HIP;
+    const tv_status ls = la.begin(opt->lookahead, st);
+    if (ls != TV_OK) return ls;
     int cur = 0;
     if (opt->resume) {
         int64_t c = 0;

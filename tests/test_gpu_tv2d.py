@@ -232,3 +232,25 @@ def test_lookahead_ignores_a_late_stop_of_the_previous_call():
         assert torch.equal(xb, x_ref)
         _, ia = s1.solve(f, 0.1, max_iter=0, resume=True)  # the first call's state: stopped at k
         assert ia["iters"] == k
+
+
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
+def test_lookahead_is_rejected_on_a_capturing_stream():
+    """The host cannot wait on work that a graph capture has not run yet: with
+    lookahead > 0 on a stream being captured the call returns an argument
+    error before enqueuing anything."""
+    import ctypes
+    f = torch.tensor(_img(32, 32, seed=23), dtype=torch.float32, device="cuda")
+    s = binding.Tv2dSolver(32, 32, torch.float32)
+    xa = torch.empty_like(f)
+    lib = binding.load()
+    opt = binding.Tv2dOptions(20, 1, 1e-4, 1.0, 0, None, 0, 4)
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=side):
+        st = lib.tv2d_solve(s.code, binding._ptr(f), 32, 32, 32, 0.1, binding._ptr(xa), ctypes.byref(opt), None,
+                            binding._ptr(s.ws), s.nbytes, ctypes.c_void_p(side.cuda_stream))
+    assert st == binding.TV_ERR_INVALID_ARG
+    x, info = s.solve(f, 0.1, max_iter=20, gap_every=1, gap_tol=1e-4, lookahead=4)  # outside a capture
+    assert info["status"] in (binding.TV_OK, binding.TV_ERR_NOT_CONVERGED)
